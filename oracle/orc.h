@@ -1,0 +1,111 @@
+/*
+ * FP64 CPU oracle for the total-Lagrangian vectorial lattice Boltzmann method
+ * (Feng & Chu, "Total-Lagrangian vectorial lattice Boltzmann method for
+ * finite-strain hyperelasticity with curved boundaries").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that
+ * the GPU path is checked against.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header or constant with the GPU library.
+ *
+ * Conventions (all arrays are caller-owned, host memory, double precision):
+ *   D      spatial dimension (2 or 3); Q = 2D lattice directions; M = D + D*D.
+ *   state  U = (v_1..v_D, F_11, F_12, .., F_DD), F row-major (Sec. 2.2, Eq. 11).
+ *   dirs   q = 0..Q-1 ordered (+e1, -e1, +e2, -e2, +e3, -e3); opp(q) = q ^ 1.
+ *   nodes  X_i = origin + (i + 1/2) dx, linear index x + nx*(y + ny*z).
+ *   planar field arrays are [component][node] over ALL grid nodes.
+ *
+ * Parity notes: functions whose result has no independent pin are marked
+ * "parity unpinned" in orc.c; every other function is pinned by tests that
+ * do not re-type its formula.
+ */
+#ifndef ORC_H
+#define ORC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes (same numeric meaning as the product library, defined here
+ * independently) */
+enum { ORC_OK = 0, ORC_ERR_ARG = 1, ORC_ERR_MEM = 2, ORC_ERR_J = 4,
+       ORC_ERR_NEWTON = 5, ORC_ERR_NONFINITE = 6, ORC_ERR_ORDER = 7 };
+
+enum { ORC_BC_NONE = 0, ORC_BC_DIRICHLET = 1, ORC_BC_NEUMANN = 2 };
+enum { ORC_RAMP_CONST = 0, ORC_RAMP_SIN2 = 1, ORC_RAMP_HALFCOS = 2,
+       ORC_RAMP_LINEAR = 3 };
+
+/* ---- point maps (Sec. 2.1, Eq. 4; Sec. 4.1, Eq. 62) ---------------------- */
+int  orc_piola(int D, double mu, double lam, const double *F, double *P);
+int  orc_piola_jvp(int D, double mu, double lam, const double *F,
+                   const double *dF, double *dP);
+int  orc_cauchy(int D, double mu, double lam, const double *F, double *sigma);
+double orc_energy(int D, double mu, double lam, const double *F);
+/* fluxes Phi[A][M] (Eq. 13) and equilibria feq[q][M] (Eq. 24) */
+void orc_flux(int D, double mu, double lam, double rho0, const double *U,
+              double *Phi);
+void orc_feq(int D, double c, double mu, double lam, double rho0,
+             const double *U, double *feq);
+void orc_feq_jvp(int D, double c, double mu, double lam, double rho0,
+                 const double *U, const double *Z, double *dfeq);
+
+/* ---- cut-link local solves (Sec. 3.4) ------------------------------------ */
+/* weighted LSQ tangent-derivative weights (Eqs. 49-52).  xi[npts][D] are
+ * normalised offsets (X_m - X_b)/dx, tang[(D-1)][D] unit tangents.  Writes
+ * w[(D-1)][npts].  Returns 2 (quadratic basis), 1 (linear fallback) or 0. */
+int orc_lsq_weights(int D, int npts, const double *xi, const double *tang,
+                    double dx, double *w);
+/* Newton solve of R(h) = P(h (x) N + G_t) N - T = 0 (Eqs. 53-56).
+ * Gt = sum_alpha g_alpha (x) t_alpha (DxD row-major).  Returns 1 on
+ * convergence, 0 on failure; h holds the last admissible iterate. */
+int orc_newton(int D, double mu, double lam, const double *N, const double *Gt,
+               const double *T, const double *h0, double tol, double *h,
+               int *iters);
+
+/* ---- the simulation ------------------------------------------------------ */
+typedef struct orc_sim orc_sim;
+
+orc_sim *orc_create(int D, const int *n, double dx, const double *origin,
+                    int periodic_mask, double mu, double lam, double rho0,
+                    double dt, double omega, double gamma, double theta_F,
+                    int proj_every);
+void orc_destroy(orc_sim *s);
+/* phi[N] node samples (phi <= 0 inside, Eq. 36); bid[N] boundary ids. */
+int  orc_set_levelset(orc_sim *s, const double *phi, const uint8_t *bid);
+/* boundary value s(t) (a + G (X - X0) + p_radial e_R + p_normal N_b) */
+int  orc_set_bc(orc_sim *s, int bid, int type, int ramp, double T_r,
+                int given_as_displacement, const double *a, const double *G,
+                double p_radial, double p_normal, const double *X0);
+/* U0[M][N]; u0[D][N] or NULL; dU0[D][M][N] (d/dX_A of U0) or NULL */
+int  orc_set_state(orc_sim *s, const double *U0, const double *u0,
+                   const double *dU0);
+int  orc_step(orc_sim *s, int64_t nsteps);
+/* U[M][N] (recovered, Eq. 28), u[D][N] (Eq. 34), J[N]; any may be NULL */
+int  orc_moments(orc_sim *s, double *U, double *u, double *J);
+/* pre-collision populations f^n as [Q][M][N] */
+int  orc_get_f(orc_sim *s, double *f);
+int  orc_put_f(orc_sim *s, const double *f, const double *ustar, int64_t step);
+/* post-collision populations f* of the last completed step, [Q][M][N] */
+int  orc_get_fs(orc_sim *s, double *f);
+int64_t orc_num_active(orc_sim *s);
+int64_t orc_num_links(orc_sim *s);
+/* link records in (bid, node, q) order: node[L], q[L], eta[L], Nb[L][3],
+ * bid[L]; any pointer may be NULL */
+int  orc_get_links(orc_sim *s, int64_t *node, int32_t *q, double *eta,
+                   double *Nb, int32_t *bid);
+/* stats[0]=newton iterations, [1]=newton failures, [2]=cg iterations,
+ *      [3]=projections, [4]=step, [5]=status */
+void orc_stats(orc_sim *s, int64_t *stats);
+/* projection-only entry for pins: given F[D*D][N] (planar) and a warm start
+ * u[D][N], solve the edge least-squares problem of Eq. 57 in place. */
+int  orc_project(orc_sim *s, const double *F, double *u, double rtol,
+                 int64_t *iters);
+/* compatible gradient of Eq. 59 (planar in/out) */
+int  orc_compatible_F(orc_sim *s, const double *u, const double *F,
+                      double *Fc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,344 @@
+"""Pins of the oracle's embedded-boundary machinery (Sec. 3).
+
+- geometry: active-node / cut-link counts printed for six lattices;
+  cut fractions against the closed-form circle intersection and normals
+  against the exact radial direction (Sec. 3.1);
+- LSQ tangent derivatives exact on quadratic fields (Sec. 3.4, Eqs. 49-52);
+- Newton normal image: the closed-form root h = F N of a compatible state
+  (Eqs. 53-56);
+- embedded patch tests: uniform Dirichlet data and compatible uniform
+  Neumann data keep the equilibrium fixed for every cut fraction (Eqs. 40-47);
+- the grid-aligned half-way formulas of the appendix (Eqs. A.1-A.7) as the
+  eta = 1/2 limit of the curved reconstruction;
+- compatibility projection: dense least squares with the mean gauge, exact
+  reproduction of compatible (affine) fields (Sec. 3.5, Eqs. 57-61);
+- physics: the mixed annulus relaxes to the radial BVP (Sec. 4.3, Eq. 75).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from refsol import radial_bvp
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _counts():
+    rows = {}
+    for line in open(os.path.join(GOLD, "geometry_counts.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            name, a, c, exact, *_ = line.split()
+            rows[name] = (float(a), float(c), int(exact))
+    return rows
+
+
+def _geom_sim(orc, g, D):
+    s = orc.Sim(D, g["n"], g["dx"], g["dx"] / 10, 1.0, 2.0 / 3.0, origin=g["origin"],
+                periodic_mask=g.get("periodic_mask", 0))
+    s.set_levelset(g["phi"], g["bid"])
+    return s
+
+
+@pytest.mark.parametrize("name,fn,D", [("affine_annulus", W.geom_affine_annulus, 2),
+                                       ("radial_annulus", W.geom_radial_annulus, 2),
+                                       ("superellipse", W.geom_superellipse, 2),
+                                       ("tube", W.geom_tube, 3),
+                                       ("spherical_shell", W.geom_spherical_shell, 3),
+                                       pytest.param("ellipsoid", W.geom_ellipsoid, 3,
+                                                    marks=pytest.mark.slow)])
+def test_printed_geometry_counts(orc, name, fn, D):
+    act, cut, exact = _counts()[name]
+    s = _geom_sim(orc, fn(), D)
+    if exact:
+        assert (s.num_active(), s.num_links()) == (int(act), int(cut))
+    else:  # printed to three significant digits
+        assert abs(s.num_active() / act - 1) < 0.005 and abs(s.num_links() / cut - 1) < 0.005
+
+
+def test_cut_fraction_and_normal_on_circles(orc):
+    g = W.geom_affine_annulus(128)
+    s = _geom_sim(orc, g, 2)
+    L = s.links()
+    X = g["X"][:, L["node"]]
+    e = np.zeros((2, len(L["q"])))
+    e[L["q"] // 2, np.arange(len(L["q"]))] = np.where(L["q"] & 1, -1.0, 1.0)
+    d = X - 0.5
+    R = np.where(g["bid"][L["node"] + 0] >= 0, 0, 0)  # placeholder shape
+    # exact intersection of X + t dx e with the circle the link crosses
+    rad = np.where(L["bid"] == 1, 0.18, 0.42)
+    b = (d * e).sum(0)
+    cc = (d * d).sum(0) - rad ** 2
+    disc = np.sqrt(b * b - cc)
+    roots = np.stack([-b - disc, -b + disc]) / g["dx"]
+    roots = np.where((roots >= -1e-12) & (roots <= 1 + 1e-12), roots, np.inf)
+    t_ex = roots.min(0)
+    assert np.abs(L["eta"] - t_ex).max() < 2e-5
+    Xb = X + L["eta"] * g["dx"] * e
+    nr = (Xb - 0.5) / np.linalg.norm(Xb - 0.5, axis=0)
+    N_ex = np.where(L["bid"] == 1, -1.0, 1.0) * nr  # outward from the material
+    assert np.abs(L["N"].T - N_ex).max() < 2e-3
+    assert R.shape[0] == len(L["q"])
+    # both interpolation branches occur
+    assert (L["eta"] < 0.5).any() and (L["eta"] >= 0.5).any()
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_lsq_tangent_derivative_exact_on_quadratics(orc, D):
+    rng = np.random.default_rng(21)
+    dx = 0.037
+    for trial in range(20):
+        xb = rng.uniform(-0.5, 0.5, D)
+        offs = np.array(np.meshgrid(*[np.arange(-3, 4)] * D, indexing="ij")).reshape(D, -1).T
+        xi = offs - xb
+        keep = (np.linalg.norm(xi, axis=1) <= 2.5) & (rng.uniform(size=len(xi)) < 0.7)
+        xi = xi[keep]
+        N = rng.standard_normal(D)
+        N /= np.linalg.norm(N)
+        if D == 2:
+            t = np.array([[-N[1], N[0]]])
+        else:
+            a = np.eye(3)[np.argmin(np.abs(N))]
+            t1 = a - (a @ N) * N
+            t1 /= np.linalg.norm(t1)
+            t = np.stack([t1, np.cross(N, t1)])
+        basis, w = orc.lsq_weights(xi, t, dx)
+        # a random quadratic in physical coordinates X = X_b + dx xi
+        c0, g = rng.standard_normal(), rng.standard_normal(D)
+        H = rng.standard_normal((D, D))
+        H = H + H.T
+        Xr = dx * xi
+        vals = c0 + Xr @ g + 0.5 * np.einsum("ma,ab,mb->m", Xr, H, Xr)
+        if basis == 2:
+            assert np.allclose(w @ vals, t @ g, rtol=1e-10, atol=1e-10)
+        else:
+            lin = c0 + Xr @ g
+            assert basis == 1 and np.allclose(w @ lin, t @ g, rtol=1e-10, atol=1e-10)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_newton_recovers_compatible_normal_image(orc, D):
+    rng = np.random.default_rng(22)
+    for _ in range(30):
+        F = np.eye(D) + 0.35 * rng.standard_normal((D, D))
+        if np.linalg.det(F) < 0.3:
+            continue
+        mu, lam = rng.uniform(0.5, 2.0), rng.uniform(0.5, 40.0)
+        N = rng.standard_normal(D)
+        N /= np.linalg.norm(N)
+        T = orc.piola(F, mu, lam) @ N
+        Gt = F @ (np.eye(D) - np.outer(N, N))  # sum_a (F t_a) (x) t_a
+        ok, h, its = orc.newton(N, Gt, T, N, mu, lam)
+        assert ok and np.allclose(h, F @ N, atol=1e-10)
+
+
+def _annulus_sim(orc, N, omega=1.8, mu=1.0, lam=2.0, gamma=0.0):
+    g = W.geom_affine_annulus(N)
+    dt = g["dx"] / 10
+    s = orc.Sim(2, g["n"], g["dx"], dt, mu, lam, omega=omega, gamma=gamma, origin=g["origin"],
+                periodic_mask=0)
+    s.set_levelset(g["phi"], g["bid"])
+    return s, g
+
+
+def test_dirichlet_patch_uniform_state(orc):
+    s, g = _annulus_sim(orc, 48)
+    v = np.array([0.03, -0.02])
+    F = np.array([[1.1, 0.05], [-0.04, 0.95]])
+    for bid in (1, 2):
+        s.set_bc(bid, orc.DIRICHLET, a=v)
+    U0 = np.zeros((6, s.N))
+    U0[:2] = v[:, None]
+    U0[2:] = F.reshape(-1)[:, None]
+    s.set_state(U0)
+    f0 = s.get_f()
+    s.step(30)
+    assert np.abs(s.get_f() - f0).max() < 1e-13
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_neumann_patch_isotropic_stretch(orc, D):
+    """F = a I is stress-isotropic: P = p I, so T = P N_b is the normal pressure
+    p N_b on every cut link.  With u0 = (F - I)(X - X_c) the LSQ derivatives
+    are exact, the Newton root is h = F N_b, the projection reproduces u and F,
+    and the state is a fixed point."""
+    mu, lam, a = 1.0, 2.0, 1.04
+    if D == 2:
+        g = W.geom_affine_annulus(40)
+    else:
+        g = W.framed_box(16, 3)
+        X = W.node_coords(g["n"], g["dx"], g["origin"])
+        d = np.sqrt(((X - 0.5) ** 2).sum(0))
+        g = dict(g, phi=np.maximum(0.15 - d, d - 0.4), bid=np.where(d < 0.3, 1, 2).astype(np.uint8), X=X)
+    s = orc.Sim(D, g["n"], g["dx"], g["dx"] / 10, mu, lam, omega=1.8, origin=g["origin"], periodic_mask=0,
+                proj_every=5)
+    s.set_levelset(g["phi"], g["bid"])
+    p = mu * (a - 1 / a) + 0.5 * lam * (a ** (2 * D) - 1) / a
+    for bid in (1, 2):
+        s.set_bc(bid, orc.NEUMANN, p_normal=p)
+    N = s.N
+    U0 = np.zeros((D + D * D, N))
+    U0[D:] = (a * np.eye(D)).reshape(-1)[:, None]
+    u0 = (a - 1) * (g["X"] - 0.5)
+    s.set_state(U0, u0=u0)
+    f0 = s.get_f()
+    s.step(12)
+    assert np.abs(s.get_f() - f0).max() < 1e-12
+    st = s.stats()
+    assert st["projections"] == 3 and st["newton_fail"] == 0
+    _, u, _ = s.moments()
+    act = g["phi"] <= 0
+    assert np.abs(u[:, act] - u0[:, act]).max() < 1e-12
+
+
+def test_appendix_halfway_rules_3d_box(orc):
+    """On a box with cell-centred nodes every cut fraction is exactly 1/2 and
+    the curved reconstruction must reduce to the grid-aligned rules
+    (Eqs. A.2-A.7): Dirichlet faces give f_d = diag(-I3, I9) f*_-d + S_D with
+    S_D = (v/3, N_B v_i / c); Neumann faces give velocity rows
+    f_d^v = f*_-d^v + T/c and F rows whose boundary gradient F^b satisfies
+    P(F^b) N = T."""
+    Nc = 8
+    g = W.framed_box(Nc, 3)
+    X = W.node_coords(g["n"], g["dx"], g["origin"])
+    phi = np.maximum.reduce([-X[0], X[0] - 1, -X[1], X[1] - 1, -X[2], X[2] - 1])
+    bid = np.full(X.shape[1], 2, np.uint8)
+    bid[X[0] < 0] = 1
+    bid[X[0] > 1] = 1
+    mu, lam, dt = 1.0, 2.0, g["dx"] / 10
+    c = g["dx"] / dt
+    s = orc.Sim(3, g["n"], g["dx"], dt, mu, lam, omega=1.8, origin=g["origin"], periodic_mask=0, proj_every=0)
+    s.set_levelset(phi, bid)
+    vD = np.array([0.01, -0.02, 0.015])
+    T = np.array([0.02, 0.01, -0.03])
+    s.set_bc(1, orc.DIRICHLET, a=vD)
+    s.set_bc(2, orc.NEUMANN, a=T)
+    rng = np.random.default_rng(23)
+    U0 = np.zeros((12, s.N))
+    U0[:3] = 0.01 * rng.standard_normal((3, s.N))
+    U0[3:] = (np.eye(3) + 0.02 * rng.standard_normal((3, 3))).reshape(-1)[:, None] \
+        + 0.005 * rng.standard_normal((9, s.N))
+    s.set_state(U0, u0=0.001 * rng.standard_normal((3, s.N)))
+    s.step(1)
+    L = s.links()
+    assert np.allclose(L["eta"], 0.5, atol=1e-15)
+    fs, f = s.get_fs(), s.get_f()
+    nface = 0
+    for k in range(len(L["q"])):
+        m, qo = L["node"][k], L["q"][k]
+        qi = qo ^ 1
+        Nn = np.zeros(3)
+        Nn[qo // 2] = -1.0 if qo & 1 else 1.0  # outward face normal = e_{q_out}
+        if np.abs(L["N"][k] - Nn).max() > 0:
+            continue  # edge/corner links: the level-set normal mixes two faces
+        nface += 1
+        fo, fn = fs[qo, :, m], f[qi, :, m]
+        if L["bid"][k] == 1:
+            S = np.concatenate([vD / 3, np.outer(vD, Nn).reshape(-1) / c])
+            Dg = np.concatenate([-np.ones(3), np.ones(9)])
+            assert np.allclose(fn, Dg * fo + S, atol=1e-15)
+        else:
+            assert np.allclose(fn[:3], fo[:3] + T / c, atol=1e-12)
+            Fb = (3.0 * (fn[3:] + fo[3:])).reshape(3, 3)
+            assert np.allclose(orc.piola(Fb, mu, lam) @ Nn, T, atol=1e-11)
+    assert nface == 6 * (Nc - 2) ** 2
+
+
+def _small_domain(orc, rng):
+    g = W.framed_box(10, 2)
+    X = W.node_coords(g["n"], g["dx"], g["origin"])
+    d = np.sqrt(((X - [[0.45], [0.55]]) ** 2).sum(0))
+    phi = np.maximum.reduce([-X[0], X[0] - 1, -X[1], X[1] - 1, 0.22 - d])
+    s = orc.Sim(2, g["n"], g["dx"], g["dx"] / 10, 1.0, 2.0, origin=g["origin"], periodic_mask=0)
+    s.set_levelset(phi, np.ones(X.shape[1], np.uint8))
+    return s, g, X, phi <= 0
+
+
+def test_projection_is_gauged_least_squares(orc):
+    rng = np.random.default_rng(24)
+    s, g, X, act = _small_domain(orc, rng)
+    D, N = 2, s.N
+    F = np.eye(2).reshape(-1)[:, None] + 0.1 * rng.standard_normal((4, N))
+    u0 = 0.05 * rng.standard_normal((2, N))
+    uc, its = s.project(F, u0)
+    # dense reference: incidence system over active axis edges, plus the gauge
+    ids = np.flatnonzero(act)
+    pos = {int(n): k for k, n in enumerate(ids)}
+    nx = g["n"][0]
+    for i in range(D):
+        rows, rhs = [], []
+        for nd in ids:
+            for A, off in ((0, 1), (1, nx)):
+                nb = nd + off
+                if nb in pos:
+                    r = np.zeros(len(ids))
+                    r[pos[nb]], r[pos[nd]] = 1.0, -1.0
+                    rows.append(r)
+                    rhs.append(0.5 * g["dx"] * (F[i * 2 + A, nb] + F[i * 2 + A, nd] - 2.0 * (i == A)))
+        A_ = np.array(rows)
+        x, *_ = np.linalg.lstsq(A_, np.array(rhs), rcond=None)
+        x += (u0[i, ids] - x).mean()  # mean-preserving gauge (one component)
+        assert np.abs(uc[i, ids] - x).max() < 1e-12
+
+
+def test_projection_reproduces_compatible_affine_field(orc):
+    rng = np.random.default_rng(25)
+    s, g, X, act = _small_domain(orc, rng)
+    G = 0.1 * rng.standard_normal((2, 2))
+    u = G @ X + rng.standard_normal((2, 1))
+    F = (np.eye(2) + G).reshape(-1)[:, None] * np.ones((1, s.N))
+    uc, _ = s.project(F, u)
+    assert np.abs((uc - u)[:, act]).max() < 1e-13
+    Fc = s.compatible_F(uc, F)
+    assert np.abs((Fc - F)[:, act]).max() < 1e-11
+
+
+def test_reference_bvp_reproduces_printed_shell_solution():
+    gold = {}
+    for line in open(os.path.join(GOLD, "spherical_shell_bvp.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split()
+            gold[k] = float(v)
+    s = radial_bvp(3, 1.0, 2.0 / 3.0, 0.20, 0.38, r_inner=0.28)
+    R = np.linspace(0.20, 0.38, 2001)
+    lr, lt = s["lr"](R), s["lt"](R)
+    assert abs(s["r"](0.38) - gold["r_Ro"]) < 5e-6
+    assert abs(s["Pr"](0.20) - gold["Pr_Ri"]) < 5e-6
+    assert abs(lr.min() - gold["lambda_r_min"]) < 5e-5 and abs(lr.max() - gold["lambda_r_max"]) < 5e-5
+    assert abs(lt.min() - gold["lambda_t_min"]) < 5e-4 and abs(lt.max() - gold["lambda_t_max"]) < 5e-4
+    J = lr * lt ** 2
+    assert abs(J.min() - gold["J_min"]) < 5e-4 and abs(J.max() - gold["J_max"]) < 5e-4
+
+
+@pytest.mark.slow
+def test_mixed_annulus_relaxes_to_radial_bvp(orc):
+    """The annulus 0.25 <= R <= 0.5 with the inner surface displaced radially
+    by 0.05 (sine-squared ramp, Eq. 71) and a traction-free outer surface,
+    damped (gamma = 10) and projected every 20 steps with the clamp as
+    projection anchor, must relax to the radial BVP of Eq. 75 (mu = 1,
+    lambda = 10), with the error falling under refinement."""
+    errs, vrms = [], []
+    ref = radial_bvp(2, 1.0, 10.0, 0.25, 0.5, r_inner=0.30)
+    for Nc in (48, 96):
+        c = W.config_c2(Nc)
+        s = orc.Sim(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
+                    origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"])
+        s.set_levelset(c["phi"], c["bid"])
+        s.set_bc(1, orc.DIRICHLET, ramp=orc.RAMP_SIN2, T_r=2.0, given_as_displacement=True, p_radial=0.05,
+                 X0=(0.5, 0.5))
+        s.set_bc(2, orc.NEUMANN)
+        s.set_state(c["U0"])
+        s.step(int(round(3.5 / c["dt"])))
+        U, u, J = s.moments()
+        act = c["phi"] <= 0
+        d = c["X"][:, act] - 0.5
+        R = np.linalg.norm(d, axis=0)
+        u_ex = (ref["r"](R) - R) * d / R
+        errs.append(np.linalg.norm(u[:, act] - u_ex) / np.linalg.norm(u_ex))
+        vrms.append(np.sqrt((U[:2, act] ** 2).sum(0).mean()))
+        assert s.stats()["newton_fail"] == 0
+    assert errs[-1] < 2e-3 and errs[-1] < errs[0], errs
+    assert vrms[-1] < vrms[0], vrms

@@ -1,0 +1,211 @@
+/*
+ * tlvlbm.h -- C ABI of the MI355X (gfx950) implementation of the
+ * total-Lagrangian vectorial lattice Boltzmann method for finite-strain
+ * hyperelasticity with curved boundaries (J. Feng, X. Chu).
+ *
+ * One context owns one lattice (D2Q4x6 or D3Q6x12) on one GPU: the
+ * vector populations, the displacement history, the cut-link tables of an
+ * embedded level-set geometry, and the scratch of the compatibility
+ * projection.  All compute runs in HIP kernels on the context's stream.
+ *
+ * Common conventions
+ *  - State ordering U = (v_1..v_D, F_11, F_12, .., F_DD), F row-major
+ *    (Sec. 2.2, Eq. 11); M = D + D^2 components.
+ *  - Lattice directions q = 0..2D-1 ordered (+e1, -e1, +e2, -e2, +e3, -e3);
+ *    the opposite direction is q ^ 1 (Sec. 2.3, Eq. 20).
+ *  - Grid nodes sit at origin + (i + 1/2) dx; the linear node index is
+ *    x + nx*(y + ny*z).  Field arrays crossing the ABI are planar,
+ *    [component][node] over ALL grid nodes, in double precision; values at
+ *    inactive nodes are ignored on input and written as 0 on output.
+ *  - Pointers: every array argument may be host memory or device memory
+ *    (detected with hipPointerGetAttributes).  Inputs are borrowed for the
+ *    duration of the call; the library copies what it keeps.  Outputs are
+ *    caller-owned; calls that write outputs return after the data is in
+ *    place (they synchronise the context stream).
+ *  - Errors: status codes only; nothing throws across the ABI.  Device
+ *    failures detected during stepping (J <= 0, non-finite state, Newton
+ *    failure) are sticky: every later call returns the same code until
+ *    tlvlbm_set_state or tlvlbm_put_state.  tlvlbm_last_error() gives text.
+ *  - Call order: create -> [set_levelset] -> [set_boundary]* -> set_state ->
+ *    step / moments / get_state.  Out-of-order calls return
+ *    TLVLBM_ERR_CALL_ORDER.
+ */
+#ifndef TLVLBM_H
+#define TLVLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tlvlbm_ctx tlvlbm_ctx;
+
+typedef enum {
+  TLVLBM_OK = 0,
+  TLVLBM_ERR_INVALID_ARG = 1,
+  TLVLBM_ERR_OUT_OF_MEMORY = 2,
+  TLVLBM_ERR_DEVICE = 3,
+  TLVLBM_ERR_NONPOSITIVE_J = 4, /* admissibility J = det F > 0 violated (Sec. 2.1, Eq. 3) */
+  TLVLBM_ERR_NEWTON = 5,        /* Neumann normal-image solve failed (Sec. 3.4) */
+  TLVLBM_ERR_NONFINITE = 6,
+  TLVLBM_ERR_CALL_ORDER = 7
+} tlvlbm_status;
+
+typedef enum { TLVLBM_D2Q4x6 = 2, TLVLBM_D3Q6x12 = 3 } tlvlbm_lattice;
+typedef enum { TLVLBM_FP32 = 0, TLVLBM_FP64 = 1 } tlvlbm_precision;
+typedef enum { TLVLBM_BC_DIRICHLET_VELOCITY = 1, TLVLBM_BC_NEUMANN_TRACTION = 2 } tlvlbm_bc_type;
+typedef enum {
+  TLVLBM_RAMP_CONST = 0,   /* s(t) = 1 */
+  TLVLBM_RAMP_SIN2 = 1,    /* s(t) = sin^2(pi t / (2 T_r)) for t < T_r, else 1 (Sec. 4.3, Eq. 71) */
+  TLVLBM_RAMP_HALFCOS = 2, /* s(t) = (1 - cos(pi t / T_r)) / 2 for t < T_r, else 1 (Sec. 5.3, Eq. 88) */
+  TLVLBM_RAMP_LINEAR = 3   /* s(t) = t / T_r for t < T_r, else 1 */
+} tlvlbm_ramp;
+
+/* Cartesian grid.  Nodes at origin + (i + 1/2) dx.  Bit A of periodic_mask
+ * makes axis A periodic.  A non-periodic axis needs a level set whose outer
+ * node layers are inactive (every lattice neighbour of an active node must
+ * exist). */
+typedef struct {
+  int32_t n[3];
+  double dx;
+  double origin[3];
+  uint32_t periodic_mask;
+} tlvlbm_grid;
+
+/* Material law.  law 0: compressible neo-Hookean,
+ * W = mu/2 (|F|^2 - D) - (mu + lambda/2) ln J + lambda/4 (J^2 - 1)
+ * (Sec. 4.1, Eq. 62); P = dW/dF (Sec. 2.1, Eq. 4). */
+typedef struct {
+  int32_t law;
+  double mu, lambda;
+} tlvlbm_material;
+
+/* Run options (tlvlbm_default_options fills the paper's settings of
+ * Sec. 4.1: omega = 1.8, gamma = 0, theta_F = 1, projection every 20 steps). */
+typedef struct {
+  double omega;       /* BGK relaxation, 0 < omega <= 2 (Sec. 2.4, Eq. 29) */
+  double gamma;       /* velocity damping source B = (-gamma v, 0) (Sec. 4.1) */
+  double theta_F;     /* repair weight, 0 < theta_F <= 1 (Sec. 3.5, Eq. 60) */
+  double cg_rtol;     /* projection CG tolerance ||r|| <= rtol max(||b||, ||r0||); <= 0: default */
+  int32_t proj_every; /* projection cadence in steps when Neumann links exist; 0 disables */
+  int32_t cg_maxit;   /* projection CG iteration cap; <= 0: 10 * active nodes */
+  int32_t precision;  /* tlvlbm_precision of the populations and bulk arithmetic */
+  int32_t track_u;    /* 1: carry the displacement quadrature (Eq. 34); 0: not; -1: auto
+                         (on whenever a level set is set) */
+  void *stream;       /* hipStream_t for all work; NULL = default stream */
+} tlvlbm_options;
+
+/* Boundary condition attached to a boundary identifier (Sec. 3.1).
+ * Value at boundary point X_b and time t:
+ *   s(t) * ( a + G (X_b - X0) + p_radial e_R + p_normal N_b ),
+ * e_R = (X_b - X0)/|X_b - X0|, N_b the outward unit normal (Eq. 38),
+ * G row-major 3x3 (the leading D x D block is used).
+ * DIRICHLET_VELOCITY imposes v_D at t^n + dt/2 (Sec. 3.3, Eqs. 44-45); with
+ * given_as_displacement the value is u_D and v_D = d u_D/dt (Sec. 2.1, Eq. 9).
+ * NEUMANN_TRACTION imposes the nominal traction P N = T at t^n + dt/2
+ * (Sec. 3.4, Eqs. 46-56). */
+typedef struct {
+  int32_t type;  /* tlvlbm_bc_type */
+  int32_t ramp;  /* tlvlbm_ramp */
+  double T_r;
+  int32_t given_as_displacement;
+  double a[3];
+  double G[9];
+  double p_radial;
+  double p_normal;
+  double X0[3];
+} tlvlbm_bc;
+
+typedef struct {
+  int64_t active_nodes;
+  int64_t cut_links;
+  int64_t dirichlet_links;
+  int64_t neumann_links;
+  int64_t cg_iterations;   /* cumulative */
+  int64_t newton_failures; /* cumulative */
+  int64_t projections;     /* cumulative */
+  int64_t step;            /* time level n of the stored state */
+  int64_t lsq_linear_fallbacks;
+} tlvlbm_stats_t;
+
+/* Fill options with the defaults listed above. */
+void tlvlbm_default_options(tlvlbm_options *opt);
+
+/* Create a context.  lattice selects D; rho0 > 0 divides the stress flux
+ * (Phi_A^{v_i} = -P_iA / rho0, Sec. 2.2, Eq. 13 with the density restored);
+ * dt > 0 sets the lattice speed c = dx / dt (Sec. 2.3).  opt may be NULL
+ * (defaults).  On success *out owns all device memory of the context. */
+tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, const tlvlbm_material *mat,
+                            double rho0, double dt, const tlvlbm_options *opt, tlvlbm_ctx **out);
+tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *ctx);
+
+/* Embed a body by node samples of a level set, phi <= 0 inside (Sec. 3.1,
+ * Eq. 36).  phi[N] (double), bid[N] (uint8, may be NULL = 0) boundary
+ * identifiers, read at the outside node of each cut link.  Builds, on the GPU:
+ * the active mask, the compacted cut-link table (prefix scan over sign changes,
+ * ordered by (bid, node, q)), cut fractions by FP64 bisection of the cubic
+ * along-link interpolant of phi (Eq. 37), normals from central-difference
+ * gradients of phi interpolated to X_b (Eq. 38), and the static weighted
+ * least-squares tangent-derivative weights of every link (Eqs. 49-52).
+ * Returns INVALID_ARG if an active node lacks a lattice neighbour. */
+tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *ctx, const double *phi, const uint8_t *bid);
+
+/* Attach a boundary condition to identifier bid (copied). */
+tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *ctx, uint8_t bid, const tlvlbm_bc *bc);
+
+/* Replace the material (e.g. for finite-difference sweeps).  The stored
+ * populations are kept. */
+tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *ctx, const tlvlbm_material *mat);
+
+/* Initial state (Sec. 2.1, Eq. 6).  U0[M][N]; u0[D][N] or NULL (zero);
+ * dU0[D][M][N] = d U0 / d X_A or NULL (zero gradients).  Populations are
+ * initialised to second order, f_q = feq(U0) - dt/2 (d_t + c e_qA d_A)
+ * feq(U0) with d_t U0 = B0 - Phi'_A(U0) d_A U0 (Sec. 2.4, Eqs. 32-33), and
+ * the history so that u^0 = u0 (Eq. 34).  Resets the step counter to 0 and
+ * clears sticky errors.  Returns NONPOSITIVE_J if det F0 <= 0 at an active
+ * node. */
+tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *ctx, const double *U0, const double *u0, const double *dU0);
+
+/* Advance n time steps of Algorithm 1 (Sec. 3.6): state recovery (Eq. 28),
+ * compatibility projection and population repair when Neumann links exist
+ * and step % proj_every == 0 (Sec. 3.5, Eqs. 57-61), local BGK collision
+ * with source (Eqs. 29-30), displacement quadrature (Eq. 34), streaming
+ * (Eq. 31) and cut-link reconstruction (Eqs. 41-56).  Returns after one
+ * status read at the end of the n steps; device failures are reported as
+ * NONPOSITIVE_J / NONFINITE / NEWTON. */
+tlvlbm_status tlvlbm_step(tlvlbm_ctx *ctx, int64_t n);
+
+/* Recovered state of the current time level: U_out[M][N] (Eq. 28),
+ * u_out[D][N] displacement (Eq. 34; zero when not tracked), J_out[N]
+ * (det F).  Any output may be NULL. */
+tlvlbm_status tlvlbm_moments(tlvlbm_ctx *ctx, double *U_out, double *u_out, double *J_out);
+
+/* Raw state for checkpoint/resume: pre-collision populations f^n as
+ * [2D][M][N] and the displacement history u*^n as [D][N] (either may be
+ * NULL), plus the step index. */
+tlvlbm_status tlvlbm_get_state(tlvlbm_ctx *ctx, double *f, double *ustar, int64_t *step);
+tlvlbm_status tlvlbm_put_state(tlvlbm_ctx *ctx, const double *f, const double *ustar, int64_t step);
+
+/* Cut-link table (host or device outputs, length = stats.cut_links): node,
+ * outgoing direction q, cut fraction eta, normal N_b [L][3], boundary id.
+ * Any output may be NULL. */
+tlvlbm_status tlvlbm_get_links(tlvlbm_ctx *ctx, int64_t *node, int32_t *q, double *eta, double *Nb,
+                               int32_t *bid);
+
+tlvlbm_status tlvlbm_stats(tlvlbm_ctx *ctx, tlvlbm_stats_t *out);
+
+/* Block until all work of the context's stream is done. */
+tlvlbm_status tlvlbm_synchronize(tlvlbm_ctx *ctx);
+
+/* Text of the last error on this context (never NULL). */
+const char *tlvlbm_last_error(const tlvlbm_ctx *ctx);
+
+/* Size in bytes of one population buffer (for bandwidth accounting). */
+size_t tlvlbm_population_bytes(const tlvlbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

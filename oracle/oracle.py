@@ -72,6 +72,7 @@ def lib():
         L.orc_stats.argtypes = [C.c_void_p, i64p]
         L.orc_project.argtypes = [C.c_void_p, dp, dp, C.c_double, i64p]
         L.orc_compatible_F.argtypes = [C.c_void_p, dp, dp, dp]
+        L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -88,6 +89,10 @@ class OracleError(RuntimeError):
     def __init__(self, code, what):
         super().__init__(f"oracle {what} failed with status {code}")
         self.code = code
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 # ---- point maps -----------------------------------------------------------

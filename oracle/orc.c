@@ -23,6 +23,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAXD 3
 #define MAXQ 6
@@ -1356,4 +1359,13 @@ int orc_get_fs(orc_sim *s, double *fo) {
       for (int r = 0; r < M; ++r)
         fo[((size_t)q * M + r) * s->N + i] = s->act[i] ? s->fs[(size_t)i * Q * M + q * M + r] : 0.0;
   return ORC_OK;
+}
+
+/* number of OpenMP threads the oracle runs with */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -101,6 +101,8 @@ void orc_stats(orc_sim *s, int64_t *stats);
  * u[D][N], solve the edge least-squares problem of Eq. 57 in place. */
 int  orc_project(orc_sim *s, const double *F, double *u, double rtol,
                  int64_t *iters);
+/* OpenMP threads used by the oracle */
+int  orc_num_threads(void);
 /* compatible gradient of Eq. 59 (planar in/out) */
 int  orc_compatible_F(orc_sim *s, const double *u, const double *F,
                       double *Fc);

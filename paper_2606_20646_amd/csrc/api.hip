@@ -1,0 +1,471 @@
+// C ABI of the tlvlbm runtime: context lifetime, host/device argument
+// marshalling, call-order checks and the step loop of Algorithm 1.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <utility>
+
+#include "tl_internal.hpp"
+
+using namespace tl;
+
+namespace {
+
+bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// device view of a borrowed input array (copied when it lives on the host)
+struct DevIn {
+  const void *ptr = nullptr;
+  void *owned = nullptr;
+  ~DevIn() {
+    if (owned) (void)hipFree(owned);
+  }
+  hipError_t take(const void *src, size_t bytes, hipStream_t st) {
+    if (!src) return hipSuccess;
+    if (is_device_ptr(src)) {
+      ptr = src;
+      return hipSuccess;
+    }
+    hipError_t e = hipMalloc(&owned, bytes);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(owned, src, bytes, hipMemcpyHostToDevice, st);
+    ptr = owned;
+    return e;
+  }
+};
+
+// device target for a caller output (staged when it lives on the host)
+struct DevOut {
+  void *user = nullptr, *ptr = nullptr, *owned = nullptr;
+  size_t bytes = 0;
+  ~DevOut() {
+    if (owned) (void)hipFree(owned);
+  }
+  hipError_t take(void *dst, size_t b) {
+    user = dst;
+    bytes = b;
+    if (!dst) return hipSuccess;
+    if (is_device_ptr(dst)) {
+      ptr = dst;
+      return hipSuccess;
+    }
+    hipError_t e = hipMalloc(&owned, b);
+    ptr = owned;
+    return e;
+  }
+  hipError_t finish(hipStream_t st) {
+    if (owned && user) return hipMemcpyAsync(user, owned, bytes, hipMemcpyDeviceToHost, st);
+    return hipSuccess;
+  }
+};
+
+tlvlbm_status fail(tlvlbm_ctx *c, tlvlbm_status s, const char *msg) {
+  if (c) {
+    try {
+      c->err = msg;
+    } catch (...) {
+    }
+  }
+  return s;
+}
+
+tlvlbm_status dev_fail(tlvlbm_ctx *c, hipError_t e, const char *where) {
+  if (c) {
+    try {
+      c->err = std::string(where) + ": " + hipGetErrorString(e);
+    } catch (...) {
+    }
+  }
+  return e == hipErrorOutOfMemory ? TLVLBM_ERR_OUT_OF_MEMORY : TLVLBM_ERR_DEVICE;
+}
+
+#define CHK(expr, where)                   \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return dev_fail(c, e_, where); \
+  } while (0)
+
+__global__ void k_count_active(const uint8_t *act, int64_t n, unsigned long long *out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool a = i < n && act[i];
+  const unsigned long long b = __ballot(a);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
+}
+
+tlvlbm_status read_flag(tlvlbm_ctx *c) {
+  int flag = 0;
+  CHK(hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->st), "flag read");
+  CHK(hipStreamSynchronize(c->st), "synchronize");
+  flag = *c->h_flag;
+  if (flag & FLAG_NONFINITE) return fail(c, TLVLBM_ERR_NONFINITE, "non-finite state");
+  if (flag & FLAG_J) return fail(c, TLVLBM_ERR_NONPOSITIVE_J, "det F <= 0 at an active node");
+  if (flag & FLAG_NEWTON) return fail(c, TLVLBM_ERR_NEWTON, "Neumann normal-image solve left det F_b <= 0");
+  return TLVLBM_OK;
+}
+
+bool has_neumann(const tlvlbm_ctx *c) {
+  for (int b = 0; b < 256; ++b)
+    if (c->bid_end[b] > c->bid_begin[b] && c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION) return true;
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tlvlbm_default_options(tlvlbm_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->omega = 1.8;
+  o->gamma = 0.0;
+  o->theta_F = 1.0;
+  o->cg_rtol = 0.0;
+  o->proj_every = 20;
+  o->cg_maxit = 0;
+  o->precision = TLVLBM_FP32;
+  o->track_u = -1;
+  o->stream = nullptr;
+}
+
+tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, const tlvlbm_material *mat, double rho0,
+                            double dt, const tlvlbm_options *opt, tlvlbm_ctx **out) {
+  if (!out) return TLVLBM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!grid || !mat || (lattice != TLVLBM_D2Q4x6 && lattice != TLVLBM_D3Q6x12)) return TLVLBM_ERR_INVALID_ARG;
+  if (!(rho0 > 0) || !(dt > 0) || !(grid->dx > 0) || mat->law != 0) return TLVLBM_ERR_INVALID_ARG;
+  tlvlbm_options o;
+  tlvlbm_default_options(&o);
+  if (opt) o = *opt;
+  if (!(o.omega > 0 && o.omega <= 2) || !(o.theta_F > 0 && o.theta_F <= 1)) return TLVLBM_ERR_INVALID_ARG;
+  if (o.precision != TLVLBM_FP32 && o.precision != TLVLBM_FP64) return TLVLBM_ERR_INVALID_ARG;
+  const int D = (int)lattice;
+  int64_t N = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int na = a < D ? grid->n[a] : 1;
+    if (na < 1) return TLVLBM_ERR_INVALID_ARG;
+    N *= na;
+  }
+  if (N >= (int64_t(1) << 31)) return TLVLBM_ERR_INVALID_ARG;
+  tlvlbm_ctx *c = new (std::nothrow) tlvlbm_ctx();
+  if (!c) return TLVLBM_ERR_OUT_OF_MEMORY;
+  c->D = D;
+  c->Q = 2 * D;
+  c->M = D + D * D;
+  c->prec = o.precision;
+  c->esz = o.precision ? 8 : 4;
+  c->geo.nx = grid->n[0];
+  c->geo.ny = grid->n[1];
+  c->geo.nz = D == 3 ? grid->n[2] : 1;
+  c->geo.per = (int)(grid->periodic_mask & ((1u << D) - 1)) | (D == 2 ? 4 : 0);
+  c->geo.N = N;
+  // plane stride: whole 256-element rows plus a small odd offset so that
+  // planes of large power-of-two grids do not start on the same channel
+  int64_t S = (N + 255) / 256 * 256;
+  if (S >= (int64_t(1) << 20)) S += 256 * 3;
+  c->geo.S = S;
+  c->geo.dx = grid->dx;
+  c->geo.ox = grid->origin[0];
+  c->geo.oy = grid->origin[1];
+  c->geo.oz = D == 3 ? grid->origin[2] : 0.0;
+  c->par.mu = mat->mu;
+  c->par.lam = mat->lambda;
+  c->par.inv_rho0 = 1.0 / rho0;
+  c->par.dt = dt;
+  c->par.c = grid->dx / dt;
+  c->par.omega = o.omega;
+  c->par.gamma = o.gamma;
+  c->theta = o.theta_F;
+  c->cg_rtol = o.cg_rtol;
+  c->proj_every = o.proj_every;
+  c->cg_maxit = o.cg_maxit;
+  c->track_opt = o.track_u;
+  c->track_u = o.track_u == 1;
+  c->st = (hipStream_t)o.stream;
+  const size_t fb = (size_t)c->Q * c->M * (size_t)S * c->esz;
+  if (hipMalloc(&c->fA, fb) != hipSuccess || hipMalloc(&c->fB, fb) != hipSuccess ||
+      hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess ||
+      hipMalloc(&c->d_newton_fail, sizeof(int64_t)) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_flag, sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void **)&c->hscal, 64 * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    tlvlbm_destroy(c);
+    return TLVLBM_ERR_OUT_OF_MEMORY;
+  }
+  if (hipMemsetAsync(c->d_flag, 0, sizeof(int), c->st) != hipSuccess ||
+      hipMemsetAsync(c->d_newton_fail, 0, sizeof(int64_t), c->st) != hipSuccess) {
+    tlvlbm_destroy(c);
+    return TLVLBM_ERR_DEVICE;
+  }
+  c->nactive = N;
+  *out = c;
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  else (void)hipDeviceSynchronize();
+  void *ptrs[] = {c->fA, c->fB, c->ustar, c->ubuf, c->act, c->d_flag, c->d_newton_fail, c->L.node, c->L.out,
+                  c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
+                  c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
+                  c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.counter};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  delete c;
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *c, const double *phi, const uint8_t *bid) {
+  if (!c || !phi) return TLVLBM_ERR_INVALID_ARG;
+  try {
+    if (c->has_ls) return fail(c, TLVLBM_ERR_CALL_ORDER, "level set already set");
+    const int64_t N = c->geo.N;
+    DevIn dphi, dbid;
+    CHK(dphi.take(phi, N * sizeof(double), c->st), "phi upload");
+    CHK(dbid.take(bid, N, c->st), "bid upload");
+    CHK(hipMalloc(&c->act, N), "mask alloc");
+    std::string err;
+    int s = build_links(c, (const double *)dphi.ptr, (const uint8_t *)dbid.ptr, err);
+    if (s) return fail(c, (tlvlbm_status)s, err.c_str());
+    unsigned long long *cnt = nullptr;
+    CHK(hipMalloc(&cnt, sizeof(unsigned long long)), "count alloc");
+    CHK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->st), "count clear");
+    hipLaunchKernelGGL(k_count_active, (unsigned)((N + 255) / 256), 256, 0, c->st, c->act, N, cnt);
+    unsigned long long na = 0;
+    CHK(hipMemcpyAsync(&na, cnt, sizeof(na), hipMemcpyDeviceToHost, c->st), "count read");
+    CHK(hipStreamSynchronize(c->st), "synchronize");
+    (void)hipFree(cnt);
+    c->nactive = (int64_t)na;
+    c->has_ls = true;
+    c->have_state = false;
+    if (c->track_opt == -1) c->track_u = true;
+    return TLVLBM_OK;
+  } catch (...) {
+    return fail(c, TLVLBM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *c, uint8_t bid, const tlvlbm_bc *bc) {
+  if (!c || !bc) return TLVLBM_ERR_INVALID_ARG;
+  if (bc->type != TLVLBM_BC_DIRICHLET_VELOCITY && bc->type != TLVLBM_BC_NEUMANN_TRACTION)
+    return fail(c, TLVLBM_ERR_INVALID_ARG, "unknown boundary type");
+  if (bc->ramp < 0 || bc->ramp > 3 || (bc->ramp != TLVLBM_RAMP_CONST && !(bc->T_r > 0)))
+    return fail(c, TLVLBM_ERR_INVALID_ARG, "bad ramp");
+  BC &b = c->bcs[bid];
+  b.type = bc->type;
+  b.ramp = bc->ramp;
+  b.disp = bc->given_as_displacement ? 1 : 0;
+  b.Tr = bc->T_r;
+  for (int k = 0; k < 3; ++k) {
+    b.a[k] = bc->a[k];
+    b.X0[k] = bc->X0[k];
+  }
+  for (int k = 0; k < 9; ++k) b.G[k] = bc->G[k];
+  b.pr = bc->p_radial;
+  b.pn = bc->p_normal;
+  c->bc_set[bid] = true;
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *c, const tlvlbm_material *m) {
+  if (!c || !m || m->law != 0) return TLVLBM_ERR_INVALID_ARG;
+  c->par.mu = m->mu;
+  c->par.lam = m->lambda;
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0) {
+  if (!c || !U0) return TLVLBM_ERR_INVALID_ARG;
+  try {
+    if (!c->has_ls)
+      for (int a = 0; a < c->D; ++a)
+        if (!((c->geo.per >> a) & 1))
+          return fail(c, TLVLBM_ERR_INVALID_ARG, "without a level set every axis must be periodic");
+    for (int b = 0; b < 256; ++b)
+      if (c->bid_end[b] > c->bid_begin[b] && !c->bc_set[b])
+        return fail(c, TLVLBM_ERR_CALL_ORDER, "a boundary identifier with cut links has no condition");
+    if (has_neumann(c) && !c->track_u)
+      return fail(c, TLVLBM_ERR_INVALID_ARG, "Neumann links need the displacement quadrature (track_u)");
+    const int64_t N = c->geo.N, S = c->geo.S;
+    const int D = c->D, M = c->M;
+    if (c->track_u && !c->ustar) {
+      CHK(hipMalloc(&c->ustar, (size_t)D * S * c->esz), "u* alloc");
+      CHK(hipMalloc(&c->ubuf, (size_t)D * S * c->esz), "u alloc");
+      CHK(hipMemsetAsync(c->ubuf, 0, (size_t)D * S * c->esz, c->st), "u clear");
+    }
+    DevIn dU, du, ddU;
+    CHK(dU.take(U0, (size_t)M * N * sizeof(double), c->st), "U0 upload");
+    CHK(du.take(u0, (size_t)D * N * sizeof(double), c->st), "u0 upload");
+    CHK(ddU.take(dU0, (size_t)D * M * N * sizeof(double), c->st), "dU0 upload");
+    const size_t fb = (size_t)c->Q * M * (size_t)S * c->esz;
+    CHK(hipMemsetAsync(c->fB, 0, fb, c->st), "population clear");
+    CHK(hipMemsetAsync(c->fA, 0, fb, c->st), "population clear");
+    CHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->st), "flag clear");
+    launch_init(c, (const double *)dU.ptr, (const double *)du.ptr, (const double *)ddU.ptr);
+    CHK(hipGetLastError(), "init launch");
+    tlvlbm_status s = read_flag(c);
+    if (s) return s;
+    c->step = 0;
+    c->status = TLVLBM_OK;
+    c->have_state = true;
+    return TLVLBM_OK;
+  } catch (...) {
+    return fail(c, TLVLBM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+tlvlbm_status tlvlbm_step(tlvlbm_ctx *c, int64_t n) {
+  if (!c || n < 0) return TLVLBM_ERR_INVALID_ARG;
+  if (!c->have_state) return fail(c, TLVLBM_ERR_CALL_ORDER, "step before set_state");
+  if (c->status) return (tlvlbm_status)c->status;
+  const bool neu = has_neumann(c);
+  for (int64_t k = 0; k < n; ++k) {
+    const double tn = c->step * c->par.dt;
+    const bool proj = neu && c->proj_every > 0 && (c->step % c->proj_every == 0);
+    if (proj) {
+      int s = run_projection(c, true, tn);
+      if (s) return (tlvlbm_status)(c->status = s);
+      launch_bulk(c, true);
+      s = run_projection(c, false, tn);
+      if (s) return (tlvlbm_status)(c->status = s);
+      ++c->st_proj;
+    } else {
+      launch_bulk(c, false);
+    }
+    if (c->L.n) launch_cutlinks(c, tn);
+    std::swap(c->fA, c->fB);
+    ++c->step;
+  }
+  CHK(hipGetLastError(), "step launch");
+  tlvlbm_status s = read_flag(c);
+  c->status = s;
+  return s;
+}
+
+tlvlbm_status tlvlbm_moments(tlvlbm_ctx *c, double *U_out, double *u_out, double *J_out) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  if (!c->have_state) return fail(c, TLVLBM_ERR_CALL_ORDER, "moments before set_state");
+  const int64_t N = c->geo.N;
+  DevOut U, u, J;
+  CHK(U.take(U_out, (size_t)c->M * N * sizeof(double)), "U alloc");
+  CHK(u.take(u_out, (size_t)c->D * N * sizeof(double)), "u alloc");
+  CHK(J.take(J_out, (size_t)N * sizeof(double)), "J alloc");
+  if (u.ptr && !c->track_u) CHK(hipMemsetAsync(u.ptr, 0, (size_t)c->D * N * sizeof(double), c->st), "u clear");
+  launch_pull_moments(c, (double *)U.ptr, c->track_u ? (double *)u.ptr : nullptr, (double *)J.ptr, false);
+  CHK(hipGetLastError(), "moments launch");
+  CHK(U.finish(c->st), "U copy");
+  CHK(u.finish(c->st), "u copy");
+  CHK(J.finish(c->st), "J copy");
+  CHK(hipStreamSynchronize(c->st), "synchronize");
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_get_state(tlvlbm_ctx *c, double *f, double *ustar, int64_t *step) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  if (!c->have_state) return fail(c, TLVLBM_ERR_CALL_ORDER, "get_state before set_state");
+  const int64_t N = c->geo.N;
+  DevOut F, U;
+  CHK(F.take(f, (size_t)c->Q * c->M * N * sizeof(double)), "f alloc");
+  CHK(U.take(ustar, (size_t)c->D * N * sizeof(double)), "u* alloc");
+  launch_get_f(c, (double *)F.ptr, (double *)U.ptr);
+  CHK(hipGetLastError(), "get_state launch");
+  CHK(F.finish(c->st), "f copy");
+  CHK(U.finish(c->st), "u* copy");
+  CHK(hipStreamSynchronize(c->st), "synchronize");
+  if (step) *step = c->step;
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_put_state(tlvlbm_ctx *c, const double *f, const double *ustar, int64_t step) {
+  if (!c || !f || step < 0) return TLVLBM_ERR_INVALID_ARG;
+  {
+    const int64_t N = c->geo.N;
+    if (c->track_u && !c->ustar) {
+      CHK(hipMalloc(&c->ustar, (size_t)c->D * c->geo.S * c->esz), "u* alloc");
+      CHK(hipMalloc(&c->ubuf, (size_t)c->D * c->geo.S * c->esz), "u alloc");
+      CHK(hipMemsetAsync(c->ubuf, 0, (size_t)c->D * c->geo.S * c->esz, c->st), "u clear");
+    }
+    DevIn F, U;
+    CHK(F.take(f, (size_t)c->Q * c->M * N * sizeof(double), c->st), "f upload");
+    CHK(U.take(ustar, (size_t)c->D * N * sizeof(double), c->st), "u* upload");
+    launch_put_f(c, (const double *)F.ptr, (const double *)U.ptr);
+    CHK(hipGetLastError(), "put_state launch");
+    CHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->st), "flag clear");
+    CHK(hipStreamSynchronize(c->st), "synchronize");
+  }
+  c->step = step;
+  c->status = TLVLBM_OK;
+  c->have_state = true;
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_get_links(tlvlbm_ctx *c, int64_t *node, int32_t *q, double *eta, double *Nb, int32_t *bid) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  const size_t n = (size_t)c->L.n;
+  if (!n) return TLVLBM_OK;
+  struct Item {
+    void *dst;
+    const void *src;
+    size_t bytes;
+  } items[] = {{node, c->L.node, n * 8}, {q, c->L.q, n * 4}, {eta, c->L.eta, n * 8}, {Nb, c->L.Nb, n * 24},
+               {bid, c->L.bid, n * 4}};
+  for (auto &it : items)
+    if (it.dst) CHK(hipMemcpyAsync(it.dst, it.src, it.bytes, hipMemcpyDefault, c->st), "link copy");
+  CHK(hipStreamSynchronize(c->st), "synchronize");
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_stats(tlvlbm_ctx *c, tlvlbm_stats_t *o) {
+  if (!c || !o) return TLVLBM_ERR_INVALID_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->active_nodes = c->nactive;
+  o->cut_links = c->L.n;
+  for (int b = 0; b < 256; ++b) {
+    const int64_t k = c->bid_end[b] - c->bid_begin[b];
+    if (k <= 0) continue;
+    if (c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION) o->neumann_links += k;
+    else if (c->bcs[b].type == TLVLBM_BC_DIRICHLET_VELOCITY) o->dirichlet_links += k;
+  }
+  o->cg_iterations = c->st_cg;
+  o->projections = c->st_proj;
+  o->step = c->step;
+  int64_t nf = 0;
+  if (hipMemcpy(&nf, c->d_newton_fail, sizeof(nf), hipMemcpyDeviceToHost) != hipSuccess)
+    return TLVLBM_ERR_DEVICE;
+  o->newton_failures = nf;
+  if (c->L.n) {
+    std::vector<int32_t> basis(c->L.n);
+    if (hipMemcpy(basis.data(), c->L.basis, c->L.n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return TLVLBM_ERR_DEVICE;
+    for (int32_t b : basis) o->lsq_linear_fallbacks += (b == 1);
+  }
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_synchronize(tlvlbm_ctx *c) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  CHK(hipStreamSynchronize(c->st), "synchronize");
+  return TLVLBM_OK;
+}
+
+const char *tlvlbm_last_error(const tlvlbm_ctx *c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+size_t tlvlbm_population_bytes(const tlvlbm_ctx *c) {
+  if (!c) return 0;
+  return (size_t)c->Q * c->M * (size_t)c->geo.N * c->esz;
+}
+
+}  // extern "C"

@@ -1,0 +1,505 @@
+// Bulk kernels of the TL-VLBM update on gfx950.
+//
+// Storage.  Populations live in structure-of-arrays planes, plane (q, r) at
+// offset (q*M + r) * S, node x fastest.  The stored field between steps is the
+// post-collision, pre-streaming population f*, so one fused kernel pulls
+// f*_q(X - e_q) (streaming, Sec. 2.4, Eq. 31), recovers the state (Eq. 28),
+// collides (Eq. 29) and writes f*(X) for the next step: one read and one write
+// of every population per step.  A population that would have to come from
+// outside the body (missing direction of a cut link) is deposited by the
+// cut-link kernel into the pull slot of the outside (inactive) node, so the
+// bulk kernel never branches on geometry.
+//
+// Precision.  Populations are stored shifted by the equilibrium of the
+// reference state, df = f - feq(v = 0, F = I); that equilibrium is U_I/(2D)
+// with U_I = (0, I) because P(I) = 0.  In FP32 this keeps the diagonal
+// deformation-gradient rows at O(|F - I|) magnitude instead of O(1/(2D)).
+#include "tl_internal.hpp"
+#include "tl_math.hpp"
+
+namespace tl {
+
+__device__ __forceinline__ int wrap_m(int v, int n) { return v < 0 ? v + n : v; }
+__device__ __forceinline__ int wrap_p(int v, int n) { return v >= n ? v - n : v; }
+
+// node index of X - e_q (periodic wrap; for active nodes of an embedded body
+// the neighbour always exists, see set_levelset)
+template <int q>
+__device__ __forceinline__ int64_t pull_src(const Geo &g, int x, int y, int z) {
+  int xs = x, ys = y, zs = z;
+  if constexpr (q == 0) xs = wrap_m(x - 1, g.nx);
+  if constexpr (q == 1) xs = wrap_p(x + 1, g.nx);
+  if constexpr (q == 2) ys = wrap_m(y - 1, g.ny);
+  if constexpr (q == 3) ys = wrap_p(y + 1, g.ny);
+  if constexpr (q == 4) zs = wrap_m(z - 1, g.nz);
+  if constexpr (q == 5) zs = wrap_p(z + 1, g.nz);
+  return xs + (int64_t)g.nx * (ys + (int64_t)g.ny * zs);
+}
+
+template <int D, typename T, int q, int M>
+__device__ __forceinline__ void load_dir(const T *__restrict__ fin, const Geo &g, int x, int y, int z,
+                                         T (&f)[2 * D][M]) {
+  const int64_t s = pull_src<q>(g, x, y, z);
+#pragma unroll
+  for (int r = 0; r < M; ++r) f[q][r] = fin[(size_t)(q * M + r) * g.S + s];
+}
+
+template <int D, typename T, int M>
+__device__ __forceinline__ void pull_all(const T *__restrict__ fin, const Geo &g, int x, int y, int z,
+                                         T (&f)[2 * D][M]) {
+  load_dir<D, T, 0>(fin, g, x, y, z, f);
+  load_dir<D, T, 1>(fin, g, x, y, z, f);
+  load_dir<D, T, 2>(fin, g, x, y, z, f);
+  load_dir<D, T, 3>(fin, g, x, y, z, f);
+  if constexpr (D == 3) {
+    load_dir<D, T, 4>(fin, g, x, y, z, f);
+    load_dir<D, T, 5>(fin, g, x, y, z, f);
+  }
+}
+
+template <typename T> __device__ __forceinline__ bool finite_(T v) { return __builtin_isfinite(v); }
+
+// Fused pull-stream + state recovery + (optional projection repair) + BGK
+// collision with source + displacement quadrature (Algorithm 1, bulk loops).
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR>
+__global__ __launch_bounds__(256) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
+                                               const uint8_t *__restrict__ act, T *__restrict__ ustar,
+                                               T *__restrict__ ubuf, const T *__restrict__ Frp,
+                                               int *__restrict__ flag) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int row = blockIdx.y;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = x + (int64_t)g.nx * row;
+  if constexpr (MASK) {
+    if (!act[node]) return;
+  }
+  T f[Q][M];
+  pull_all<D, T, M>(fin, g, x, y, z, f);
+
+  // state recovery with the half-step damping source (Eq. 28): the velocity
+  // is implicit in B = (-gamma v, 0), v = sum_q f^v / (1 + gamma dt / 2)
+  T dU[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    T s = f[0][r];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) s += f[q][r];
+    dU[r] = s;
+  }
+  const T dt = T(p.dt), mu = T(p.mu), lam = T(p.lam), irho = T(p.inv_rho0);
+  const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
+  T v[D], F[D * D], P[D * D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) v[i] = dU[i] * inv_damp;
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
+  T J = piola<D>(F, mu, lam, P);
+  bool bad = !(J > T(0));
+  const T inv2c = T(0.5) / T(p.c);
+  const T inv2D = T(1) / T(2 * D);
+
+  if constexpr (REPAIR) {
+    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61)
+    T Fr[D * D], P1[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Fr[k] = Frp[(size_t)k * g.S + node];
+    const T J1 = piola<D>(Fr, mu, lam, P1);
+    bad |= !(J1 > T(0));
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int A = q / 2;
+      const T sg = (q & 1) ? T(-1) : T(1);
+#pragma unroll
+      for (int i = 0; i < D; ++i) f[q][i] += sg * inv2c * (-(P1[i * D + A] - P[i * D + A]) * irho);
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) f[q][D + k] += (Fr[k] - F[k]) * inv2D;
+    }
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+      F[k] = Fr[k];
+      P[k] = P1[k];
+      dU[D + k] = Fr[k] - ((k % (D + 1) == 0) ? T(1) : T(0));
+    }
+    J = J1;
+  }
+
+  // BGK collision with source weights 1/(4D) (Eqs. 29-30).  Shifted
+  // equilibrium: feq_q - U_I/(2D) = (U - U_I)/(2D) + e_qA Phi_A(U) / (2c).
+  const T om = T(p.omega);
+  const T srcw = dt * (T(2) - om) / T(4 * D);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int A = q / 2;
+    const T sg = (q & 1) ? T(-1) : T(1);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      T phi;
+      T base;
+      if (r < D) {
+        phi = -P[r * D + A] * irho;
+        base = v[r];
+      } else {
+        const int i = (r - D) / D, B = (r - D) % D;
+        phi = (A == B) ? -v[i] : T(0);
+        base = dU[r];
+      }
+      const T feq = base * inv2D + sg * inv2c * phi;
+      T out = f[q][r] + om * (feq - f[q][r]);
+      if (r < D) out += srcw * (-T(p.gamma) * v[r]);
+      fout[(size_t)(q * M + r) * g.S + node] = out;
+    }
+  }
+
+  if constexpr (TRACK) {
+    // trapezoidal displacement quadrature (Eq. 34)
+    const T hdt = T(0.5) * dt;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T uu;
+      if constexpr (REPAIR) {
+        uu = ubuf[(size_t)i * g.S + node];
+      } else {
+        uu = ustar[(size_t)i * g.S + node] + hdt * v[i];
+        ubuf[(size_t)i * g.S + node] = uu;
+      }
+      ustar[(size_t)i * g.S + node] = uu + hdt * v[i];
+    }
+  }
+  T chk = J;
+#pragma unroll
+  for (int i = 0; i < D; ++i) chk += v[i];
+  if (bad || !finite_(chk)) atomicOr(flag, finite_(chk) ? FLAG_J : FLAG_NONFINITE);
+}
+
+// Pull f^n and write moments: v (damping-corrected), F, u = u* + dt/2 v, J.
+// Output planes have stride ostride; any output may be null.
+template <int D, typename T, typename O, bool MASK>
+__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ fin, Geo g, Par p,
+                                                  const uint8_t *__restrict__ act,
+                                                  const T *__restrict__ ustar, O *__restrict__ Vo,
+                                                  O *__restrict__ Fo, O *__restrict__ uo, O *__restrict__ Jo,
+                                                  int64_t ostride) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int row = blockIdx.y;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = x + (int64_t)g.nx * row;
+  if (MASK && !act[node]) {
+    for (int i = 0; i < D; ++i) {
+      if (Vo) Vo[(size_t)i * ostride + node] = O(0);
+      if (uo) uo[(size_t)i * ostride + node] = O(0);
+    }
+    if (Fo)
+      for (int k = 0; k < D * D; ++k) Fo[(size_t)k * ostride + node] = O(0);
+    if (Jo) Jo[node] = O(0);
+    return;
+  }
+  T f[Q][M];
+  pull_all<D, T, M>(fin, g, x, y, z, f);
+  T dU[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    T s = f[0][r];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) s += f[q][r];
+    dU[r] = s;
+  }
+  const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * T(p.dt));
+  T v[D], F[D * D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) v[i] = dU[i] * inv_damp;
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
+  if (Vo)
+    for (int i = 0; i < D; ++i) Vo[(size_t)i * ostride + node] = O(v[i]);
+  if (Fo)
+    for (int k = 0; k < D * D; ++k) Fo[(size_t)k * ostride + node] = O(F[k]);
+  if (uo)
+    for (int i = 0; i < D; ++i)
+      uo[(size_t)i * ostride + node] = ustar ? O(ustar[(size_t)i * g.S + node] + T(0.5) * T(p.dt) * v[i]) : O(0);
+  if (Jo) Jo[node] = O(det<D>(F));
+}
+
+// Second-order initialisation (Sec. 2.4, Eqs. 32-33) in FP64, stored
+// reverse-streamed: the value for direction q of node X goes to the pull slot
+// X - e_q, so that the first bulk pull reads f^0_q(X).
+template <int D, typename T, bool MASK>
+__global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p, const uint8_t *__restrict__ act,
+                                               const double *__restrict__ U0, const double *__restrict__ u0,
+                                               const double *__restrict__ dU0, T *__restrict__ ustar,
+                                               int *__restrict__ flag) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int row = blockIdx.y;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = x + (int64_t)g.nx * row;
+  if (MASK && !act[node]) return;
+  double U[M], dA[D][M], Ut[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) U[r] = U0[(size_t)r * g.N + node];
+#pragma unroll
+  for (int A = 0; A < D; ++A)
+#pragma unroll
+    for (int r = 0; r < M; ++r) dA[A][r] = dU0 ? dU0[((size_t)A * M + r) * g.N + node] : 0.0;
+  const double *F = U + D;
+  double P[D * D];
+  const double J = piola<D>(F, p.mu, p.lam, P);
+  if (!(J > 0.0)) {
+    atomicOr(flag, FLAG_J);
+    return;
+  }
+  // d_t U0 = B0 - Phi'_A(U0) d_A U0, B0 = (-gamma v0, 0)
+#pragma unroll
+  for (int r = 0; r < M; ++r) Ut[r] = (r < D) ? -p.gamma * U[r] : 0.0;
+#pragma unroll
+  for (int A = 0; A < D; ++A) {
+    double dP[D * D];
+    piola_tangent<D>(F, dA[A] + D, p.mu, p.lam, dP);
+#pragma unroll
+    for (int i = 0; i < D; ++i) Ut[i] += dP[i * D + A] * p.inv_rho0;  // -(-dP)
+#pragma unroll
+    for (int i = 0; i < D; ++i) Ut[D + i * D + A] += dA[A][i];        // -(-dv_i)
+  }
+  const double c = p.c, inv2D = 1.0 / (2 * D);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int A = q / 2;
+    const double sg = (q & 1) ? -1.0 : 1.0;
+    double Z[M], dP[D * D];
+#pragma unroll
+    for (int r = 0; r < M; ++r) Z[r] = Ut[r] + c * sg * dA[A][r];
+    piola_tangent<D>(F, Z + D, p.mu, p.lam, dP);
+    int xs = x, ys = y, zs = z;  // X - e_q
+    if (A == 0) xs = (x - (int)sg + g.nx) % g.nx;
+    if (A == 1) ys = (y - (int)sg + g.ny) % g.ny;
+    if (A == 2) zs = (z - (int)sg + g.nz) % g.nz;
+    const int64_t dst = xs + (int64_t)g.nx * (ys + (int64_t)g.ny * zs);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      double phi, dphi;
+      if (r < D) {
+        phi = -P[r * D + A] * p.inv_rho0;
+        dphi = -dP[r * D + A] * p.inv_rho0;
+      } else {
+        const int i = (r - D) / D, B = (r - D) % D;
+        phi = (A == B) ? -U[i] : 0.0;
+        dphi = (A == B) ? -Z[i] : 0.0;
+      }
+      const double feq = U[r] * inv2D + sg * phi / (2.0 * c);
+      const double dfeq = Z[r] * inv2D + sg * dphi / (2.0 * c);
+      double fv = feq - 0.5 * p.dt * dfeq;
+      if (r >= D && ((r - D) % (D + 1) == 0)) fv -= inv2D;  // shifted storage
+      fout[(size_t)(q * M + r) * g.S + dst] = T(fv);
+    }
+  }
+  if (ustar)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      ustar[(size_t)i * g.S + node] = T((u0 ? u0[(size_t)i * g.N + node] : 0.0) - 0.5 * p.dt * U[i]);
+}
+
+// raw pre-collision populations f^n (unshifted) [Q][M][N] and u*^n [D][N]
+template <int D, typename T, bool MASK>
+__global__ __launch_bounds__(256) void k_get_f(const T *__restrict__ fin, Geo g, const uint8_t *__restrict__ act,
+                                                const T *__restrict__ ustar, double *__restrict__ fo,
+                                                double *__restrict__ uso) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int row = blockIdx.y;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = x + (int64_t)g.nx * row;
+  const bool on = !MASK || act[node];
+  if (fo) {
+    T f[Q][M];
+    if (on) pull_all<D, T, M>(fin, g, x, y, z, f);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        double sh = (r >= D && ((r - D) % (D + 1) == 0)) ? 1.0 / (2 * D) : 0.0;
+        fo[((size_t)q * M + r) * g.N + node] = on ? double(f[q][r]) + sh : 0.0;
+      }
+  }
+  if (uso)
+    for (int i = 0; i < D; ++i) uso[(size_t)i * g.N + node] = (on && ustar) ? double(ustar[(size_t)i * g.S + node]) : 0.0;
+}
+
+template <int D, typename T, bool MASK>
+__global__ __launch_bounds__(256) void k_put_f(T *__restrict__ fout, Geo g, const uint8_t *__restrict__ act,
+                                                const double *__restrict__ fi, const double *__restrict__ usi,
+                                                T *__restrict__ ustar) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int row = blockIdx.y;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = x + (int64_t)g.nx * row;
+  if (MASK && !act[node]) return;
+  if (fi) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int A = q / 2, sg = (q & 1) ? -1 : 1;
+      int xs = x, ys = y, zs = z;
+      if (A == 0) xs = (x - sg + g.nx) % g.nx;
+      if (A == 1) ys = (y - sg + g.ny) % g.ny;
+      if (A == 2) zs = (z - sg + g.nz) % g.nz;
+      const int64_t dst = xs + (int64_t)g.nx * (ys + (int64_t)g.ny * zs);
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        double sh = (r >= D && ((r - D) % (D + 1) == 0)) ? 1.0 / (2 * D) : 0.0;
+        fout[(size_t)(q * M + r) * g.S + dst] = T(fi[((size_t)q * M + r) * g.N + node] - sh);
+      }
+    }
+  }
+  if (ustar)
+    for (int i = 0; i < D; ++i) ustar[(size_t)i * g.S + node] = usi ? T(usi[(size_t)i * g.N + node]) : T(0);
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline void grid_of(const Geo &g, dim3 &grid, dim3 &block) {
+  int bx = g.nx >= 256 ? 256 : ((g.nx + 63) / 64) * 64;
+  block = dim3(bx, 1, 1);
+  grid = dim3((g.nx + bx - 1) / bx, g.ny * g.nz, 1);
+}
+
+template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair) {
+  dim3 grid, block;
+  grid_of(c->geo, grid, block);
+  const T *fin = (const T *)c->fB;
+  T *fout = (T *)c->fA;
+  T *us = (T *)c->ustar, *ub = (T *)c->ubuf;
+  const T *Fr = (const T *)c->cg.Fr;
+  if (repair) {
+    hipLaunchKernelGGL((k_bulk<D, T, true, true, true>), grid, block, 0, c->st, fin, fout, c->geo, c->par, c->act,
+                       us, ub, Fr, c->d_flag);
+  } else if (c->act) {
+    if (c->track_u)
+      hipLaunchKernelGGL((k_bulk<D, T, true, true, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag);
+    else
+      hipLaunchKernelGGL((k_bulk<D, T, true, false, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag);
+  } else {
+    if (c->track_u)
+      hipLaunchKernelGGL((k_bulk<D, T, false, true, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag);
+    else
+      hipLaunchKernelGGL((k_bulk<D, T, false, false, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag);
+  }
+}
+
+void launch_bulk(tlvlbm_ctx *c, bool repair) {
+  if (c->D == 2) {
+    if (c->prec) bulk_t<2, double>(c, repair);
+    else bulk_t<2, float>(c, repair);
+  } else {
+    if (c->prec) bulk_t<3, double>(c, repair);
+    else bulk_t<3, float>(c, repair);
+  }
+}
+
+template <int D, typename T>
+static void moments_t(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch) {
+  dim3 grid, block;
+  grid_of(c->geo, grid, block);
+  const T *us = c->track_u ? (const T *)c->ustar : nullptr;
+  if (to_scratch) {
+    // projection inputs: v, F into the CG workspace, u into the u buffer
+    if (c->act)
+      hipLaunchKernelGGL((k_moments<D, T, T, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act,
+                         us, (T *)c->cg.V, (T *)c->cg.Fm, (T *)c->ubuf, (T *)nullptr, (int64_t)c->geo.S);
+    else
+      hipLaunchKernelGGL((k_moments<D, T, T, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par,
+                         c->act, us, (T *)c->cg.V, (T *)c->cg.Fm, (T *)c->ubuf, (T *)nullptr, (int64_t)c->geo.S);
+    return;
+  }
+  double *Vo = U, *Fo = U ? U + (size_t)D * c->geo.N : nullptr;
+  if (c->act)
+    hipLaunchKernelGGL((k_moments<D, T, double, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par,
+                       c->act, us, Vo, Fo, u, J, (int64_t)c->geo.N);
+  else
+    hipLaunchKernelGGL((k_moments<D, T, double, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par,
+                       c->act, us, Vo, Fo, u, J, (int64_t)c->geo.N);
+}
+
+void launch_pull_moments(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch) {
+  if (c->D == 2) {
+    if (c->prec) moments_t<2, double>(c, U, u, J, to_scratch);
+    else moments_t<2, float>(c, U, u, J, to_scratch);
+  } else {
+    if (c->prec) moments_t<3, double>(c, U, u, J, to_scratch);
+    else moments_t<3, float>(c, U, u, J, to_scratch);
+  }
+}
+
+template <int D, typename T>
+static void init_t(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0) {
+  dim3 grid, block;
+  grid_of(c->geo, grid, block);
+  T *us = c->track_u ? (T *)c->ustar : nullptr;
+  if (c->act)
+    hipLaunchKernelGGL((k_init<D, T, true>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->par, c->act, U0, u0, dU0,
+                       us, c->d_flag);
+  else
+    hipLaunchKernelGGL((k_init<D, T, false>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->par, c->act, U0, u0,
+                       dU0, us, c->d_flag);
+}
+
+void launch_init(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0) {
+  if (c->D == 2) {
+    if (c->prec) init_t<2, double>(c, U0, u0, dU0);
+    else init_t<2, float>(c, U0, u0, dU0);
+  } else {
+    if (c->prec) init_t<3, double>(c, U0, u0, dU0);
+    else init_t<3, float>(c, U0, u0, dU0);
+  }
+}
+
+template <int D, typename T> static void getf_t(tlvlbm_ctx *c, double *f, double *us) {
+  dim3 grid, block;
+  grid_of(c->geo, grid, block);
+  const T *ust = c->track_u ? (const T *)c->ustar : nullptr;
+  if (c->act)
+    hipLaunchKernelGGL((k_get_f<D, T, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->act, ust, f, us);
+  else
+    hipLaunchKernelGGL((k_get_f<D, T, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->act, ust, f, us);
+}
+
+void launch_get_f(tlvlbm_ctx *c, double *f, double *ustar) {
+  if (c->D == 2) {
+    if (c->prec) getf_t<2, double>(c, f, ustar);
+    else getf_t<2, float>(c, f, ustar);
+  } else {
+    if (c->prec) getf_t<3, double>(c, f, ustar);
+    else getf_t<3, float>(c, f, ustar);
+  }
+}
+
+template <int D, typename T> static void putf_t(tlvlbm_ctx *c, const double *f, const double *us) {
+  dim3 grid, block;
+  grid_of(c->geo, grid, block);
+  T *ust = c->track_u ? (T *)c->ustar : nullptr;
+  if (c->act)
+    hipLaunchKernelGGL((k_put_f<D, T, true>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->act, f, us, ust);
+  else
+    hipLaunchKernelGGL((k_put_f<D, T, false>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->act, f, us, ust);
+}
+
+void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar) {
+  if (c->D == 2) {
+    if (c->prec) putf_t<2, double>(c, f, ustar);
+    else putf_t<2, float>(c, f, ustar);
+  } else {
+    if (c->prec) putf_t<3, double>(c, f, ustar);
+    else putf_t<3, float>(c, f, ustar);
+  }
+}
+
+}  // namespace tl

@@ -1,0 +1,1239 @@
+// Embedded-boundary kernels of the TL-VLBM update on gfx950:
+//  - cut-link construction from level-set samples (Sec. 3.1),
+//  - cut-link reconstruction, velocity Dirichlet and nominal-traction Neumann
+//    (Secs. 3.2-3.4),
+//  - compatibility projection by conjugate gradients (Sec. 3.5).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "tl_internal.hpp"
+#include "tl_math.hpp"
+
+namespace tl {
+
+#define HIP_OK(x)                                   \
+  do {                                              \
+    if ((x) != hipSuccess) return TLVLBM_ERR_DEVICE; \
+  } while (0)
+
+// ------------------------------------------------------------ grid helpers
+
+struct C3 {
+  int x, y, z;
+};
+
+__device__ __forceinline__ C3 coords_of(const Geo &g, int64_t i) {
+  C3 c;
+  c.x = (int)(i % g.nx);
+  c.y = (int)((i / g.nx) % g.ny);
+  c.z = (int)(i / ((int64_t)g.nx * g.ny));
+  return c;
+}
+
+// node at integer offset (ox, oy, oz): periodic wrap, -1 outside a non-periodic box
+__device__ __forceinline__ int64_t node_at(const Geo &g, C3 c, int ox, int oy, int oz) {
+  int v[3] = {c.x + ox, c.y + oy, c.z + oz};
+  const int n[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    if (v[A] < 0 || v[A] >= n[A]) {
+      if (!((g.per >> A) & 1)) return -1;
+      v[A] = ((v[A] % n[A]) + n[A]) % n[A];
+    }
+  }
+  return v[0] + (int64_t)g.nx * (v[1] + (int64_t)g.ny * v[2]);
+}
+
+__device__ __forceinline__ int64_t node_dir(const Geo &g, C3 c, int q, int mult) {
+  const int A = q / 2, sg = (q & 1) ? -1 : 1;
+  return node_at(g, c, A == 0 ? sg * mult : 0, A == 1 ? sg * mult : 0, A == 2 ? sg * mult : 0);
+}
+
+// ----------------------------------------------------------- active mask
+
+template <int D>
+__global__ void k_active(const double *__restrict__ phi, Geo g, uint8_t *__restrict__ act, int *flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  act[i] = phi[i] <= 0.0;
+}
+
+// every lattice neighbour of an active node must exist; count cut links per bid
+template <int D>
+__global__ void k_check_hist(Geo g, const uint8_t *__restrict__ act, const uint8_t *__restrict__ bid, int *flag,
+                             unsigned *hist) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N || !act[i]) return;
+  const C3 c = coords_of(g, i);
+  for (int q = 0; q < 2 * D; ++q) {
+    const int64_t o = node_dir(g, c, q, 1);
+    if (o < 0) {
+      atomicOr(flag, FLAG_ARG);
+      return;
+    }
+    if (!act[o]) atomicAdd(&hist[bid ? bid[o] : 0], 1u);
+  }
+}
+
+// number of cut links of node i whose outside node carries identifier b
+template <int D>
+__global__ void k_count(Geo g, const uint8_t *__restrict__ act, const uint8_t *__restrict__ bid, int b,
+                        int *__restrict__ cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  int k = 0;
+  if (act[i]) {
+    const C3 c = coords_of(g, i);
+    for (int q = 0; q < 2 * D; ++q) {
+      const int64_t o = node_dir(g, c, q, 1);
+      if (o >= 0 && !act[o] && (bid ? bid[o] : 0) == b) ++k;
+    }
+  }
+  cnt[i] = k;
+}
+
+// ------------------------------------------------ exclusive prefix scan
+// three phases: per-block totals, scan of totals (one block), local rescan
+
+constexpr int SCAN_T = 256, SCAN_V = 8, SCAN_CH = SCAN_T * SCAN_V;
+
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *sh, int64_t &total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < SCAN_T; off <<= 1) {
+    int64_t a = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  total = sh[SCAN_T - 1];
+  int64_t ex = sh[t] - v;
+  __syncthreads();
+  return ex;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_tot(const int *__restrict__ cnt, int64_t n, int64_t *__restrict__ tot) {
+  __shared__ int64_t sh[SCAN_T];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CH + threadIdx.x * SCAN_V;
+  int64_t s = 0;
+  for (int k = 0; k < SCAN_V; ++k)
+    if (base + k < n) s += cnt[base + k];
+  int64_t total;
+  block_excl_scan(s, sh, total);
+  if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_tot2(int64_t *__restrict__ tot, int64_t nb, int64_t *__restrict__ grand) {
+  __shared__ int64_t sh[SCAN_T];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += SCAN_T) {
+    const int64_t i = b0 + threadIdx.x;
+    int64_t v = (i < nb) ? tot[i] : 0;
+    int64_t total;
+    int64_t ex = block_excl_scan(v, sh, total);
+    if (i < nb) tot[i] = carry + ex;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_apply(const int *__restrict__ cnt, int64_t n,
+                                                       const int64_t *__restrict__ tot, int64_t *__restrict__ off) {
+  __shared__ int64_t sh[SCAN_T];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CH + threadIdx.x * SCAN_V;
+  int64_t s = 0;
+  for (int k = 0; k < SCAN_V; ++k)
+    if (base + k < n) s += cnt[base + k];
+  int64_t total;
+  int64_t ex = block_excl_scan(s, sh, total) + tot[blockIdx.x];
+  for (int k = 0; k < SCAN_V; ++k)
+    if (base + k < n) {
+      off[base + k] = ex;
+      ex += cnt[base + k];
+    }
+}
+
+// compacted link records of identifier b, in (node, q) order
+template <int D>
+__global__ void k_scatter(Geo g, const uint8_t *__restrict__ act, const uint8_t *__restrict__ bid, int b,
+                          const int *__restrict__ cnt, const int64_t *__restrict__ off, int64_t base, Links L) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N || cnt[i] == 0) return;
+  const C3 c = coords_of(g, i);
+  int64_t k = base + off[i];
+  for (int q = 0; q < 2 * D; ++q) {
+    const int64_t o = node_dir(g, c, q, 1);
+    if (o >= 0 && !act[o] && (bid ? bid[o] : 0) == b) {
+      L.node[k] = i;
+      L.out[k] = o;
+      L.q[k] = q;
+      L.bid[k] = b;
+      ++k;
+    }
+  }
+}
+
+// ---------------------------------------------- link geometry (FP64)
+
+__device__ double phi_grad_axis(const Geo &g, const double *phi, C3 c, int64_t i, int A) {
+  const int64_t ip = node_at(g, c, A == 0, A == 1, A == 2);
+  const int64_t im = node_at(g, c, -(A == 0), -(A == 1), -(A == 2));
+  if (ip >= 0 && im >= 0) return (phi[ip] - phi[im]) / (2.0 * g.dx);
+  if (ip >= 0) return (phi[ip] - phi[i]) / g.dx;
+  if (im >= 0) return (phi[i] - phi[im]) / g.dx;
+  return 0.0;
+}
+
+// Cut fraction eta: bisection of the cubic interpolant of phi through the
+// link parameters -1, 0, 1, 2 (linear when an outer sample is missing)
+// (Sec. 3.1, Eq. 37); normal N_b from the level-set gradient (Eq. 38),
+// tangent frame, upstream node m^- of the eta < 1/2 branch (Eq. 43).
+template <int D>
+__global__ void k_link_geom(Geo g, const double *__restrict__ phi, const uint8_t *__restrict__ act, Links L) {
+  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= L.n) return;
+  const int64_t m = L.node[l], o = L.out[l];
+  const int q = L.q[l], A = q / 2, sg = (q & 1) ? -1 : 1;
+  const C3 cm = coords_of(g, m), co = coords_of(g, o);
+  const int64_t mb = node_dir(g, cm, q, -1), o2 = node_dir(g, co, q, 1);
+  const double p0 = phi[m], p1 = phi[o];
+  const bool cubic = (mb >= 0 && o2 >= 0);
+  const double pm = cubic ? phi[mb] : 0.0, p2 = cubic ? phi[o2] : 0.0;
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 80; ++it) {
+    const double s = 0.5 * (lo + hi);
+    double val;
+    if (cubic) {
+      // Lagrange basis on the nodes -1, 0, 1, 2
+      const double lm = -s * (s - 1.0) * (s - 2.0) / 6.0;
+      const double l0 = (s + 1.0) * (s - 1.0) * (s - 2.0) / 2.0;
+      const double l1 = -(s + 1.0) * s * (s - 2.0) / 2.0;
+      const double l2 = (s + 1.0) * s * (s - 1.0) / 6.0;
+      val = pm * lm + p0 * l0 + p1 * l1 + p2 * l2;
+    } else {
+      val = p0 + s * (p1 - p0);
+    }
+    if (val <= 0.0) lo = s;
+    else hi = s;
+  }
+  double eta = 0.5 * (lo + hi);
+  eta = eta < 0.0 ? 0.0 : (eta > 1.0 ? 1.0 : eta);
+  L.eta[l] = eta;
+  const double X[3] = {g.ox + (cm.x + 0.5) * g.dx, g.oy + (cm.y + 0.5) * g.dx, g.oz + (cm.z + 0.5) * g.dx};
+  double N[3] = {0, 0, 0}, nrm = 0.0;
+  for (int a = 0; a < D; ++a) {
+    const double gm = phi_grad_axis(g, phi, cm, m, a), go = phi_grad_axis(g, phi, co, o, a);
+    N[a] = (1.0 - eta) * gm + eta * go;
+    nrm += N[a] * N[a];
+  }
+  nrm = sqrt(nrm);
+  if (nrm > 0.0) {
+    for (int a = 0; a < D; ++a) N[a] /= nrm;
+  } else {
+    for (int a = 0; a < D; ++a) N[a] = (a == A) ? sg : 0.0;
+  }
+  for (int a = 0; a < 3; ++a) {
+    L.Nb[l * 3 + a] = N[a];
+    L.Xb[l * 3 + a] = X[a] + ((a == A) ? sg * eta * g.dx : 0.0);
+  }
+  double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
+  if (D == 2) {
+    t1[0] = -N[1];
+    t1[1] = N[0];
+  } else {
+    int k0 = 0;
+    for (int a = 1; a < 3; ++a)
+      if (fabs(N[a]) < fabs(N[k0])) k0 = a;
+    const double dd = N[k0];
+    double n1 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      t1[a] = ((a == k0) ? 1.0 : 0.0) - dd * N[a];
+      n1 += t1[a] * t1[a];
+    }
+    n1 = sqrt(n1);
+    for (int a = 0; a < 3; ++a) t1[a] /= n1;
+    t2[0] = N[1] * t1[2] - N[2] * t1[1];
+    t2[1] = N[2] * t1[0] - N[0] * t1[2];
+    t2[2] = N[0] * t1[1] - N[1] * t1[0];
+  }
+  for (int a = 0; a < 3; ++a) {
+    L.tang[l * 6 + a] = t1[a];
+    L.tang[l * 6 + 3 + a] = t2[a];
+  }
+  L.mminus[l] = (mb >= 0 && act[mb]) ? mb : m;
+}
+
+// quadratic (or linear) LSQ basis row in normalised coordinates (Eq. 50)
+template <int D> __device__ __forceinline__ int lsq_row(const double *xi, bool quad, double *a) {
+  int k = 0;
+  a[k++] = 1.0;
+  for (int d = 0; d < D; ++d) a[k++] = xi[d];
+  if (quad) {
+    if (D == 2) {
+      a[k++] = 0.5 * xi[0] * xi[0];
+      a[k++] = xi[0] * xi[1];
+      a[k++] = 0.5 * xi[1] * xi[1];
+    } else {
+      a[k++] = 0.5 * xi[0] * xi[0];
+      a[k++] = 0.5 * xi[1] * xi[1];
+      a[k++] = 0.5 * xi[2] * xi[2];
+      a[k++] = xi[0] * xi[1];
+      a[k++] = xi[0] * xi[2];
+      a[k++] = xi[1] * xi[2];
+    }
+  }
+  return k;
+}
+
+// Static weighted-LSQ tangent-derivative weights per link (Eqs. 49-52):
+// stencil = active nodes within 2.5 dx of X_b, weights 1/(1 + |xi|^2),
+// quadratic basis, linear fallback when there are fewer than twice as many
+// points as terms or a Jacobi-scaled Cholesky pivot drops below 1e-10.
+template <int D>
+__global__ void k_link_lsq(Geo g, const uint8_t *__restrict__ act, Links L, int *flag) {
+  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= L.n) return;
+  const int64_t m = L.node[l];
+  const int q = L.q[l], A = q / 2, sg = (q & 1) ? -1 : 1;
+  const double eta = L.eta[l];
+  const C3 cm = coords_of(g, m);
+  int32_t *idx = L.sidx + l * L.kmax;
+  double *w = L.sw + l * 2 * L.kmax;
+  int np = 0;
+  const int R = 4;
+  for (int oz = (D == 3 ? -R : 0); oz <= (D == 3 ? R : 0); ++oz)
+    for (int oy = -R; oy <= R; ++oy)
+      for (int ox = -R; ox <= R; ++ox) {
+        const int o[3] = {ox, oy, oz};
+        double r2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+          const double xr = o[a] - ((a == A) ? sg * eta : 0.0);
+          r2 += xr * xr;
+        }
+        if (r2 > LSQ_RADIUS * LSQ_RADIUS) continue;
+        const int64_t j = node_at(g, cm, ox, oy, oz);
+        if (j < 0 || !act[j]) continue;
+        if (np >= L.kmax) {
+          atomicOr(flag, FLAG_STENCIL);
+          L.npts[l] = 0;
+          L.basis[l] = 0;
+          return;
+        }
+        idx[np] = (int32_t)j;
+        ++np;
+      }
+  L.npts[l] = np;
+  // normalised coordinates of the stencil, in stencil order
+  double xs[KMAX3 * 3];
+  {
+    int cnt = 0;
+    for (int oz = (D == 3 ? -R : 0); oz <= (D == 3 ? R : 0); ++oz)
+      for (int oy = -R; oy <= R; ++oy)
+        for (int ox = -R; ox <= R; ++ox) {
+          const int o[3] = {ox, oy, oz};
+          double r2 = 0.0, xr[3];
+          for (int a = 0; a < D; ++a) {
+            xr[a] = o[a] - ((a == A) ? sg * eta : 0.0);
+            r2 += xr[a] * xr[a];
+          }
+          if (r2 > LSQ_RADIUS * LSQ_RADIUS) continue;
+          const int64_t j = node_at(g, cm, ox, oy, oz);
+          if (j < 0 || !act[j]) continue;
+          for (int a = 0; a < D; ++a) xs[cnt * D + a] = xr[a];
+          ++cnt;
+        }
+  }
+  const double *tg = L.tang + l * 6;
+  for (int quad = 1; quad >= 0; --quad) {
+    const int nb = quad ? (D == 2 ? 6 : 10) : D + 1;
+    if (np < (quad ? 2 * nb : nb)) continue;
+    double Nm[100];
+    for (int k = 0; k < nb * nb; ++k) Nm[k] = 0.0;
+    for (int k = 0; k < np; ++k) {
+      double a[10], r2 = 0.0;
+      lsq_row<D>(xs + k * D, quad, a);
+      for (int d = 0; d < D; ++d) r2 += xs[k * D + d] * xs[k * D + d];
+      const double W = 1.0 / (1.0 + r2);
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j) Nm[i * nb + j] += a[i] * W * a[j];
+    }
+    // Jacobi-scaled Cholesky pivot test
+    double Ls[100], sc[10];
+    for (int i = 0; i < nb; ++i) sc[i] = 1.0 / sqrt(Nm[i * nb + i]);
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j) Ls[i * nb + j] = Nm[i * nb + j] * sc[i] * sc[j];
+    bool ok = true;
+    for (int k = 0; k < nb && ok; ++k) {
+      double d = Ls[k * nb + k];
+      for (int p = 0; p < k; ++p) d -= Ls[k * nb + p] * Ls[k * nb + p];
+      if (!(d >= 1e-10)) {
+        ok = false;
+        break;
+      }
+      Ls[k * nb + k] = sqrt(d);
+      for (int i = k + 1; i < nb; ++i) {
+        double s = Ls[i * nb + k];
+        for (int p = 0; p < k; ++p) s -= Ls[i * nb + p] * Ls[k * nb + p];
+        Ls[i * nb + k] = s / Ls[k * nb + k];
+      }
+    }
+    if (!ok) continue;
+    // z = Nm^{-1} e_t through the scaled factor: Nm = S^-1 Ls Ls^T S^-1
+    for (int al = 0; al < D - 1; ++al) {
+      double y[10], z[10];
+      for (int i = 0; i < nb; ++i) y[i] = 0.0;
+      for (int d = 0; d < D; ++d) y[1 + d] = tg[al * 3 + d] / g.dx;
+      for (int i = 0; i < nb; ++i) y[i] *= sc[i];
+      for (int i = 0; i < nb; ++i) {  // forward
+        double s = y[i];
+        for (int p = 0; p < i; ++p) s -= Ls[i * nb + p] * z[p];
+        z[i] = s / Ls[i * nb + i];
+      }
+      for (int i = nb - 1; i >= 0; --i) {  // backward
+        double s = z[i];
+        for (int p = i + 1; p < nb; ++p) s -= Ls[p * nb + i] * y[p];
+        y[i] = s / Ls[i * nb + i];
+      }
+      for (int i = 0; i < nb; ++i) y[i] *= sc[i];
+      for (int k = 0; k < np; ++k) {
+        double a[10], r2 = 0.0, s = 0.0;
+        lsq_row<D>(xs + k * D, quad, a);
+        for (int d = 0; d < D; ++d) r2 += xs[k * D + d] * xs[k * D + d];
+        for (int j = 0; j < nb; ++j) s += a[j] * y[j];
+        w[al * L.kmax + k] = s / (1.0 + r2);
+      }
+    }
+    L.basis[l] = quad ? 2 : 1;
+    return;
+  }
+  L.basis[l] = 0;
+  for (int al = 0; al < D - 1; ++al)
+    for (int k = 0; k < np; ++k) w[al * L.kmax + k] = 0.0;
+}
+
+// ------------------------------------------------- boundary data (FP64)
+
+__device__ __forceinline__ void ramp_eval(int kind, double Tr, double t, double &s, double &ds) {
+  s = 1.0;
+  ds = 0.0;
+  if (t < Tr) {
+    if (kind == TLVLBM_RAMP_SIN2) {
+      const double a = M_PI * t / (2.0 * Tr);
+      s = sin(a) * sin(a);
+      ds = M_PI / (2.0 * Tr) * sin(M_PI * t / Tr);
+    } else if (kind == TLVLBM_RAMP_HALFCOS) {
+      s = 0.5 * (1.0 - cos(M_PI * t / Tr));
+      ds = 0.5 * M_PI / Tr * sin(M_PI * t / Tr);
+    } else if (kind == TLVLBM_RAMP_LINEAR) {
+      s = t / Tr;
+      ds = 1.0 / Tr;
+    }
+  }
+}
+
+// integral of the loading factor from 0 to t
+__device__ __forceinline__ double ramp_int(int kind, double Tr, double t) {
+  if (kind == TLVLBM_RAMP_CONST) return t;
+  const double tc = t < Tr ? t : Tr;
+  double S;
+  if (kind == TLVLBM_RAMP_LINEAR) S = 0.5 * tc * tc / Tr;
+  else S = 0.5 * tc - Tr / (2.0 * M_PI) * sin(M_PI * tc / Tr);  // sin^2 and half-cosine
+  return S + (t - tc);
+}
+
+template <int D> __device__ __forceinline__ void bc_base(const BC &b, const double *X, const double *N, double *val) {
+  double d[3], r = 0.0;
+  for (int a = 0; a < D; ++a) {
+    d[a] = X[a] - b.X0[a];
+    r += d[a] * d[a];
+  }
+  r = sqrt(r);
+  for (int i = 0; i < D; ++i) {
+    double s = b.a[i];
+    for (int A = 0; A < D; ++A) s += b.G[i * 3 + A] * d[A];
+    if (b.pr != 0.0 && r > 0.0) s += b.pr * d[i] / r;
+    s += b.pn * N[i];
+    val[i] = s;
+  }
+}
+
+// ----------------------------------------------------- cut-link closure
+
+// Velocity Dirichlet (Sec. 3.3, Eqs. 44-45) with cut-link interpolation
+// (Sec. 3.2, Eqs. 42-43).  f holds post-collision populations (shifted); the
+// reconstructed incoming population is written to the pull slot of the
+// outside node.  One thread per link.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cut_dirichlet(T *__restrict__ f, Links L, int64_t b0, int64_t b1, BC bc,
+                                                        Geo g, Par p, double th) {
+  constexpr int M = D + D * D;
+  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= b1) return;
+  const int64_t m = L.node[l], mm = L.mminus[l], o = L.out[l];
+  const int qo = L.q[l], qi = qo ^ 1, A = qo / 2;
+  const double sg = (qo & 1) ? -1.0 : 1.0;
+  const double eta = L.eta[l];
+  double Xb[3], N[3], vb[3];
+  for (int a = 0; a < 3; ++a) {
+    Xb[a] = L.Xb[l * 3 + a];
+    N[a] = L.Nb[l * 3 + a];
+  }
+  double s, ds;
+  ramp_eval(bc.ramp, bc.Tr, th, s, ds);
+  bc_base<D>(bc, Xb, N, vb);
+  const double fac = bc.disp ? ds : s;
+  for (int i = 0; i < D; ++i) vb[i] *= fac;
+  const T ie = T(1.0 / (2.0 * eta));
+  const T e2 = T(2.0 * eta);
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    T Dg, S;
+    if (r < D) {
+      Dg = T(-1);
+      S = T(vb[r] / D);
+    } else {
+      const int i = (r - D) / D, B = (r - D) % D;
+      Dg = T(1);
+      // -d_B v_i / c with d = -e_{q_out}; the shift cancels for these rows
+      S = (B == A) ? T(sg * vb[i] / p.c) : T(0);
+    }
+    const T fo = f[(size_t)(qo * M + r) * g.S + m];
+    T out;
+    if (eta >= 0.5) {
+      const T fi = f[(size_t)(qi * M + r) * g.S + m];
+      out = (Dg * fo + S) * ie + (T(1) - ie) * fi;
+    } else {
+      const T fm = f[(size_t)(qo * M + r) * g.S + mm];
+      out = Dg * (e2 * fo + (T(1) - e2) * fm) + S;
+    }
+    f[(size_t)(qi * M + r) * g.S + o] = out;
+  }
+}
+
+// small dense solve (n <= 3) by Gaussian elimination with partial pivoting
+__device__ bool solve_small(int n, double *A, double *b, double *x) {
+  for (int k = 0; k < n; ++k) {
+    int pv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(A[i * n + k]) > fabs(A[pv * n + k])) pv = i;
+    if (A[pv * n + k] == 0.0) return false;
+    if (pv != k) {
+      for (int j = 0; j < n; ++j) {
+        double t = A[k * n + j];
+        A[k * n + j] = A[pv * n + j];
+        A[pv * n + j] = t;
+      }
+      double t = b[k];
+      b[k] = b[pv];
+      b[pv] = t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double lf = A[i * n + k] / A[k * n + k];
+      for (int j = k; j < n; ++j) A[i * n + j] -= lf * A[k * n + j];
+      b[i] -= lf * b[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
+    x[i] = s / A[i * n + i];
+  }
+  return true;
+}
+
+// R(h) = P(h (x) N + Gt) N - T (Eqs. 54, 56); false if det F_b <= 0
+template <int D>
+__device__ bool nm_residual(const double *h, const double *N, const double *Gt, const double *Tb, double mu,
+                            double lam, double *R) {
+  double F[D * D], P[D * D];
+  for (int i = 0; i < D; ++i)
+    for (int a = 0; a < D; ++a) F[i * D + a] = h[i] * N[a] + Gt[i * D + a];
+  if (!(det<D>(F) > 0.0)) return false;
+  piola<D>(F, mu, lam, P);
+  for (int i = 0; i < D; ++i) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) s += P[i * D + a] * N[a];
+    R[i] = s - Tb[i];
+    if (!__builtin_isfinite(R[i])) return false;
+  }
+  return true;
+}
+
+// Local Newton for the normal image h (Eqs. 53-56) in FP64, Jacobian
+// dR/dh = Q(N; F_b) (acoustic tensor, Eq. 19) from the tangent action;
+// accepts only det F_b > 0 with a decreasing residual (<= 10 halvings).
+template <int D>
+__device__ bool newton_h(const double *N, const double *Gt, const double *Tb, double mu, double lam, double tol,
+                         double *h) {
+  double R[D], Rt[D], ht[D];
+  if (!nm_residual<D>(h, N, Gt, Tb, mu, lam, R)) return false;
+  const double thr = tol * (mu > 1.0 ? mu : 1.0);
+  for (int it = 0; it <= 30; ++it) {
+    double rinf = 0.0, r2 = 0.0;
+    for (int i = 0; i < D; ++i) {
+      rinf = fmax(rinf, fabs(R[i]));
+      r2 += R[i] * R[i];
+    }
+    if (rinf <= thr) return true;
+    if (it == 30) break;
+    double F[D * D], Qm[D * D], dh[D], mR[D];
+    for (int i = 0; i < D; ++i)
+      for (int a = 0; a < D; ++a) F[i * D + a] = h[i] * N[a] + Gt[i * D + a];
+    for (int k = 0; k < D; ++k) {
+      double dF[D * D], dP[D * D];
+      for (int i = 0; i < D; ++i)
+        for (int a = 0; a < D; ++a) dF[i * D + a] = (i == k) ? N[a] : 0.0;
+      piola_tangent<D>(F, dF, mu, lam, dP);
+      for (int i = 0; i < D; ++i) {
+        double s = 0.0;
+        for (int a = 0; a < D; ++a) s += dP[i * D + a] * N[a];
+        Qm[i * D + k] = s;
+      }
+    }
+    for (int i = 0; i < D; ++i) mR[i] = -R[i];
+    if (!solve_small(D, Qm, mR, dh)) return false;
+    double step = 1.0;
+    bool acc = false;
+    for (int ls = 0; ls <= 10; ++ls) {
+      for (int i = 0; i < D; ++i) ht[i] = h[i] + step * dh[i];
+      if (nm_residual<D>(ht, N, Gt, Tb, mu, lam, Rt)) {
+        double rt2 = 0.0, rtinf = 0.0;
+        for (int i = 0; i < D; ++i) {
+          rt2 += Rt[i] * Rt[i];
+          rtinf = fmax(rtinf, fabs(Rt[i]));
+        }
+        if (rt2 < r2 || rtinf <= thr) {
+          acc = true;
+          break;
+        }
+      }
+      step *= 0.5;
+    }
+    if (!acc) return false;
+    for (int i = 0; i < D; ++i) {
+      h[i] = ht[i];
+      R[i] = Rt[i];
+    }
+  }
+  return false;
+}
+
+// Nominal-traction Neumann (Sec. 3.4, Eqs. 46-56) with cut-link
+// interpolation.  Tangent images from the static LSQ weights applied to the
+// displacement u (Eqs. 48-52); normal image by the local Newton; the
+// boundary state enters the deformation-gradient rows, the Piola flux the
+// velocity rows.
+template <int D, typename T>
+__global__ __launch_bounds__(128) void k_cut_neumann(T *__restrict__ f, Links L, int64_t b0, int64_t b1, BC bc,
+                                                      Geo g, Par p, double th, const T *__restrict__ u,
+                                                      int *__restrict__ flag,
+                                                      unsigned long long *__restrict__ nfail) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= b1) return;
+  const int64_t m = L.node[l], mm = L.mminus[l], o = L.out[l];
+  const int qo = L.q[l], qi = qo ^ 1, A = qo / 2;
+  const double sg = (qo & 1) ? -1.0 : 1.0;
+  const double eta = L.eta[l];
+  double Xb[3], N[3], Tb[3];
+  for (int a = 0; a < 3; ++a) {
+    Xb[a] = L.Xb[l * 3 + a];
+    N[a] = L.Nb[l * 3 + a];
+  }
+  // sum_alpha g_alpha (x) t_alpha with g_alpha = t_alpha + sum_k w_alpha,k u_k
+  double Gt[D * D];
+  for (int k = 0; k < D * D; ++k) Gt[k] = 0.0;
+  const int np = L.npts[l];
+  const int32_t *idx = L.sidx + l * L.kmax;
+  const double *w = L.sw + l * 2 * L.kmax;
+  for (int al = 0; al < D - 1; ++al) {
+    double gv[D];
+    for (int i = 0; i < D; ++i) gv[i] = L.tang[l * 6 + al * 3 + i];
+    for (int k = 0; k < np; ++k) {
+      const double wk = w[al * L.kmax + k];
+      const int64_t j = idx[k];
+      for (int i = 0; i < D; ++i) gv[i] += wk * double(u[(size_t)i * g.S + j]);
+    }
+    for (int i = 0; i < D; ++i)
+      for (int B = 0; B < D; ++B) Gt[i * D + B] += gv[i] * L.tang[l * 6 + al * 3 + B];
+  }
+  double s, ds;
+  ramp_eval(bc.ramp, bc.Tr, th, s, ds);
+  bc_base<D>(bc, Xb, N, Tb);
+  for (int i = 0; i < D; ++i) Tb[i] *= s;
+  // initial guess h0 = F_m N with F_m = sum_q f*_q^F(m) (collision keeps the
+  // F moment since the source has no F rows)
+  double h[D];
+  {
+    double Fm[D * D];
+    for (int k = 0; k < D * D; ++k) {
+      double acc = (k % (D + 1) == 0) ? 1.0 : 0.0;
+      for (int qq = 0; qq < Q; ++qq) acc += double(f[(size_t)(qq * M + D + k) * g.S + m]);
+      Fm[k] = acc;
+    }
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int B = 0; B < D; ++B) acc += Fm[i * D + B] * N[B];
+      h[i] = acc;
+    }
+  }
+  const bool conv = newton_h<D>(N, Gt, Tb, p.mu, p.lam, 1e-12, h);
+  if (!conv) atomicAdd(nfail, 1ull);
+  double Fb[D * D], Pb[D * D];
+  for (int i = 0; i < D; ++i)
+    for (int a = 0; a < D; ++a) Fb[i * D + a] = h[i] * N[a] + Gt[i * D + a];
+  if (!(det<D>(Fb) > 0.0)) {
+    atomicOr(flag, FLAG_NEWTON);
+    for (int k = 0; k < D * D; ++k) Fb[k] = (k % (D + 1) == 0) ? 1.0 : 0.0;
+  }
+  piola<D>(Fb, p.mu, p.lam, Pb);
+  const T ie = T(1.0 / (2.0 * eta));
+  const T e2 = T(2.0 * eta);
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    T Dg, S;
+    if (r < D) {
+      Dg = T(1);
+      S = T(sg * Pb[r * D + A] * p.inv_rho0 / p.c);  // -d_A P_b,iA / (rho0 c)
+    } else {
+      const int k = r - D;
+      Dg = T(-1);
+      // F_b/D in shifted variables: (F_b - I)/D
+      S = T((Fb[k] - ((k % (D + 1) == 0) ? 1.0 : 0.0)) / D);
+    }
+    const T fo = f[(size_t)(qo * M + r) * g.S + m];
+    T out;
+    if (eta >= 0.5) {
+      const T fi = f[(size_t)(qi * M + r) * g.S + m];
+      out = (Dg * fo + S) * ie + (T(1) - ie) * fi;
+    } else {
+      const T fm = f[(size_t)(qo * M + r) * g.S + mm];
+      out = Dg * (e2 * fo + (T(1) - e2) * fm) + S;
+    }
+    f[(size_t)(qi * M + r) * g.S + o] = out;
+  }
+}
+
+// --------------------------------------------------------- projection
+
+// anchors of the projection null mode: each Dirichlet cut link adds
+// u_m = u_D(X_b, t) - (F_m - I)(X_b - X_m) with unit weight
+template <int D, typename T>
+__global__ void k_anchor(Links L, int64_t b0, int64_t b1, BC bc, Geo g, double t, const T *__restrict__ Fm,
+                         int *__restrict__ anc_n, T *__restrict__ anc_s) {
+  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= b1) return;
+  const int64_t m = L.node[l];
+  const int q = L.q[l], A = q / 2;
+  const double sg = (q & 1) ? -1.0 : 1.0;
+  double Xb[3], N[3], uD[3];
+  for (int a = 0; a < 3; ++a) {
+    Xb[a] = L.Xb[l * 3 + a];
+    N[a] = L.Nb[l * 3 + a];
+  }
+  double s, ds;
+  ramp_eval(bc.ramp, bc.Tr, t, s, ds);
+  bc_base<D>(bc, Xb, N, uD);
+  const double fac = bc.disp ? s : ramp_int(bc.ramp, bc.Tr, t);
+  const double off = sg * L.eta[l] * g.dx;
+  atomicAdd(&anc_n[m], 1);
+  for (int i = 0; i < D; ++i) {
+    const double Fi = double(Fm[(size_t)(i * D + A) * g.S + m]) - (i == A ? 1.0 : 0.0);
+    atomicAdd(&anc_s[(size_t)i * g.S + m], T(uD[i] * fac - Fi * off));
+  }
+}
+
+// right-hand side of the normal equations of the edge least-squares problem
+// (Eq. 57) plus the anchor targets
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cg_rhs(Geo g, const uint8_t *__restrict__ act, const T *__restrict__ Fm,
+                                                 const T *__restrict__ anc_s, T *__restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  if (!act[i]) {
+    for (int c = 0; c < D; ++c) b[(size_t)c * g.S + i] = T(0);
+    return;
+  }
+  const C3 cc = coords_of(g, i);
+  const T hdx = T(0.5 * g.dx);
+  for (int c = 0; c < D; ++c) {
+    T acc = anc_s ? anc_s[(size_t)c * g.S + i] : T(0);
+    for (int A = 0; A < D; ++A) {
+      const int64_t lp = node_dir(g, cc, 2 * A, 1), lm = node_dir(g, cc, 2 * A + 1, 1);
+      const T Fi = Fm[(size_t)(c * D + A) * g.S + i];
+      const T dl = (c == A) ? T(2) : T(0);
+      if (lm >= 0 && act[lm]) acc += hdx * (Fi + Fm[(size_t)(c * D + A) * g.S + lm] - dl);
+      if (lp >= 0 && act[lp]) acc -= hdx * (Fi + Fm[(size_t)(c * D + A) * g.S + lp] - dl);
+    }
+    b[(size_t)c * g.S + i] = acc;
+  }
+}
+
+// scalar slots of the CG state (device doubles)
+enum { S_RR = 0, S_BB = 4, S_THR = 8, S_ALPHA = 12, S_BETA = 16, S_ACT = 20, S_ITS = 24, S_DONE = 28, S_NSCAL = 32 };
+
+constexpr int CG_T = 256;
+
+// block reduction of up to 2*D doubles, written to partial[blk*8 + k]; the
+// last block to finish sums all partials in block order (deterministic) and
+// hands the totals to fin()
+template <int K>
+__device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, unsigned *counter, double *tot) {
+  __shared__ double sh[CG_T / 64][8];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) sh[wid][k] = x;
+  }
+  __syncthreads();
+  const int blk = blockIdx.x;
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < CG_T / 64; ++w) s += sh[w][threadIdx.x];
+    partial[blk * 8 + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned t = atomicAdd(counter, 1u);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  __shared__ double tsum[8];
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    const volatile double *pv = partial;
+    for (unsigned b = 0; b < gridDim.x; ++b) s += pv[b * 8 + threadIdx.x];
+    tsum[threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) tot[k] = tsum[k];
+  if (threadIdx.x == 0) *counter = 0u;
+  return true;
+}
+
+// r = b - A x, p = r, rr and bb (A = active-graph Laplacian + anchors)
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_init(Geo g, const uint8_t *__restrict__ act,
+                                                   const uint8_t *__restrict__ anc_n, const T *__restrict__ b,
+                                                   const T *__restrict__ x, T *__restrict__ r, T *__restrict__ p,
+                                                   double *partial, unsigned *counter, double *scal, double rtol) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double v[2 * D];
+  for (int k = 0; k < 2 * D; ++k) v[k] = 0.0;
+  if (i < g.N) {
+    if (act[i]) {
+      const C3 cc = coords_of(g, i);
+      int64_t nb[2 * D];
+      int deg = anc_n ? anc_n[i] : 0;
+      for (int q = 0; q < 2 * D; ++q) {
+        nb[q] = node_dir(g, cc, q, 1);
+        if (nb[q] >= 0 && !act[nb[q]]) nb[q] = -1;
+        if (nb[q] >= 0) ++deg;
+      }
+      for (int c = 0; c < D; ++c) {
+        T ax = T(deg) * x[(size_t)c * g.S + i];
+        for (int q = 0; q < 2 * D; ++q)
+          if (nb[q] >= 0) ax -= x[(size_t)c * g.S + nb[q]];
+        const T bi = b[(size_t)c * g.S + i];
+        const T ri = bi - ax;
+        r[(size_t)c * g.S + i] = ri;
+        p[(size_t)c * g.S + i] = ri;
+        v[c] = double(ri) * double(ri);
+        v[D + c] = double(bi) * double(bi);
+      }
+    } else {
+      for (int c = 0; c < D; ++c) {
+        r[(size_t)c * g.S + i] = T(0);
+        p[(size_t)c * g.S + i] = T(0);
+      }
+    }
+  }
+  double tot[8];
+  if (block_partials<2 * D>(v, partial, counter, tot) && threadIdx.x == 0) {
+    bool all = true;
+    for (int c = 0; c < D; ++c) {
+      const double rr = tot[c], bb = tot[D + c];
+      scal[S_RR + c] = rr;
+      scal[S_BB + c] = bb;
+      scal[S_THR + c] = rtol * rtol * (bb > rr ? bb : rr);
+      scal[S_BETA + c] = 0.0;
+      scal[S_ITS + c] = 0.0;
+      const bool act_c = rr > scal[S_THR + c];
+      scal[S_ACT + c] = act_c ? 1.0 : 0.0;
+      all = all && !act_c;
+    }
+    scal[S_DONE] = all ? 1.0 : 0.0;
+  }
+}
+
+// p_new = r + beta p_old (recomputed at neighbours), Ap = A p_new, p.Ap
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_Ap(Geo g, const uint8_t *__restrict__ act,
+                                                 const uint8_t *__restrict__ anc_n, const T *__restrict__ r,
+                                                 const T *__restrict__ pold, T *__restrict__ pnew,
+                                                 T *__restrict__ Ap, double *partial, unsigned *counter,
+                                                 double *scal) {
+  if (scal[S_DONE] != 0.0) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double v[D];
+  for (int k = 0; k < D; ++k) v[k] = 0.0;
+  T beta[D];
+  for (int c = 0; c < D; ++c) beta[c] = T(scal[S_BETA + c]);
+  if (i < g.N && act[i]) {
+    const C3 cc = coords_of(g, i);
+    int64_t nb[2 * D];
+    int deg = anc_n ? anc_n[i] : 0;
+    for (int q = 0; q < 2 * D; ++q) {
+      nb[q] = node_dir(g, cc, q, 1);
+      if (nb[q] >= 0 && !act[nb[q]]) nb[q] = -1;
+      if (nb[q] >= 0) ++deg;
+    }
+    for (int c = 0; c < D; ++c) {
+      const size_t o = (size_t)c * g.S;
+      const T pi = r[o + i] + beta[c] * pold[o + i];
+      T ap = T(deg) * pi;
+      for (int q = 0; q < 2 * D; ++q)
+        if (nb[q] >= 0) ap -= r[o + nb[q]] + beta[c] * pold[o + nb[q]];
+      pnew[o + i] = pi;
+      Ap[o + i] = ap;
+      v[c] = double(pi) * double(ap);
+    }
+  } else if (i < g.N) {
+    for (int c = 0; c < D; ++c) {
+      pnew[(size_t)c * g.S + i] = T(0);
+      Ap[(size_t)c * g.S + i] = T(0);
+    }
+  }
+  double tot[8];
+  if (block_partials<D>(v, partial, counter, tot) && threadIdx.x == 0) {
+    for (int c = 0; c < D; ++c) {
+      const bool on = scal[S_ACT + c] != 0.0 && tot[c] > 0.0;
+      scal[S_ALPHA + c] = on ? scal[S_RR + c] / tot[c] : 0.0;
+      if (!on) scal[S_ACT + c] = 0.0;
+    }
+  }
+}
+
+// x += alpha p, r -= alpha Ap, rr_new, beta, convergence
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_update(Geo g, const uint8_t *__restrict__ act, T *__restrict__ x,
+                                                     T *__restrict__ r, const T *__restrict__ p,
+                                                     const T *__restrict__ Ap, double *partial, unsigned *counter,
+                                                     double *scal) {
+  if (scal[S_DONE] != 0.0) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double v[D];
+  for (int k = 0; k < D; ++k) v[k] = 0.0;
+  if (i < g.N && act[i]) {
+    for (int c = 0; c < D; ++c) {
+      const size_t o = (size_t)c * g.S;
+      const T al = T(scal[S_ALPHA + c]);
+      x[o + i] += al * p[o + i];
+      const T ri = r[o + i] - al * Ap[o + i];
+      r[o + i] = ri;
+      v[c] = double(ri) * double(ri);
+    }
+  }
+  double tot[8];
+  if (block_partials<D>(v, partial, counter, tot) && threadIdx.x == 0) {
+    bool all = true;
+    for (int c = 0; c < D; ++c) {
+      if (scal[S_ACT + c] != 0.0) {
+        scal[S_ITS + c] += 1.0;
+        const double rr2 = tot[c];
+        scal[S_BETA + c] = rr2 / scal[S_RR + c];
+        scal[S_RR + c] = rr2;
+        if (!(rr2 > scal[S_THR + c])) scal[S_ACT + c] = 0.0;
+      } else {
+        scal[S_BETA + c] = 0.0;
+      }
+      all = all && (scal[S_ACT + c] == 0.0);
+    }
+    scal[S_DONE] = all ? 1.0 : 0.0;
+  }
+}
+
+// compatible gradient F^c = I + grad_dx u^c (Eq. 59) and F^r = (1-theta) F +
+// theta F^c (Eq. 60): centred differences, one-sided next to a cut, the
+// evolved column kept when neither neighbour is active
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gradF(Geo g, const uint8_t *__restrict__ act, const T *__restrict__ u,
+                                                const T *__restrict__ Fm, T *__restrict__ Fr, double theta) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N || !act[i]) return;
+  const C3 cc = coords_of(g, i);
+  for (int A = 0; A < D; ++A) {
+    const int64_t lp = node_dir(g, cc, 2 * A, 1), lm = node_dir(g, cc, 2 * A + 1, 1);
+    const bool hp = lp >= 0 && act[lp], hm = lm >= 0 && act[lm];
+    for (int c = 0; c < D; ++c) {
+      const size_t o = (size_t)c * g.S;
+      const T Fe = Fm[(size_t)(c * D + A) * g.S + i];
+      T Fc;
+      if (hp && hm) Fc = (u[o + lp] - u[o + lm]) / T(2.0 * g.dx);
+      else if (hp) Fc = (u[o + lp] - u[o + i]) / T(g.dx);
+      else if (hm) Fc = (u[o + i] - u[o + lm]) / T(g.dx);
+      else {
+        Fr[(size_t)(c * D + A) * g.S + i] = Fe;
+        continue;
+      }
+      Fc += (c == A) ? T(1) : T(0);
+      Fr[(size_t)(c * D + A) * g.S + i] = T(1.0 - theta) * Fe + T(theta) * Fc;
+    }
+  }
+}
+
+// u = x, u* = x + dt/2 v  (advance = true) or x - dt/2 v
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_ureset(Geo g, const uint8_t *__restrict__ act, const T *__restrict__ x,
+                                                 const T *__restrict__ V, T *__restrict__ u, T *__restrict__ us,
+                                                 double hdt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N || !act[i]) return;
+  for (int c = 0; c < D; ++c) {
+    const size_t o = (size_t)c * g.S;
+    u[o + i] = x[o + i];
+    us[o + i] = x[o + i] + T(hdt) * V[o + i];
+  }
+}
+
+// ------------------------------------------------------------ host side
+
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <int D> static int build_links_t(tlvlbm_ctx *c, const double *phi, const uint8_t *bid, std::string &err) {
+  const Geo &g = c->geo;
+  hipStream_t st = c->st;
+  hipLaunchKernelGGL((k_active<D>), nblk(g.N, 256), 256, 0, st, phi, g, c->act, c->d_flag);
+  unsigned *hist = nullptr;
+  HIP_OK(hipMalloc(&hist, 256 * sizeof(unsigned)));
+  HIP_OK(hipMemsetAsync(hist, 0, 256 * sizeof(unsigned), st));
+  HIP_OK(hipMemsetAsync(c->d_flag, 0, sizeof(int), st));
+  hipLaunchKernelGGL((k_check_hist<D>), nblk(g.N, 256), 256, 0, st, g, c->act, bid, c->d_flag, hist);
+  unsigned hh[256];
+  int flag = 0;
+  HIP_OK(hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  (void)hipFree(hist);
+  if (flag & FLAG_ARG) {
+    err = "an active node has no lattice neighbour (non-periodic axis needs an inactive frame)";
+    return TLVLBM_ERR_INVALID_ARG;
+  }
+  int64_t total = 0;
+  for (int b = 0; b < 256; ++b) total += hh[b];
+  Links &L = c->L;
+  L.n = total;
+  L.kmax = (D == 2) ? KMAX2 : KMAX3;
+  const int64_t n = total > 0 ? total : 1;
+  HIP_OK(hipMalloc(&L.node, n * 8));
+  HIP_OK(hipMalloc(&L.out, n * 8));
+  HIP_OK(hipMalloc(&L.mminus, n * 8));
+  HIP_OK(hipMalloc(&L.q, n * 4));
+  HIP_OK(hipMalloc(&L.bid, n * 4));
+  HIP_OK(hipMalloc(&L.npts, n * 4));
+  HIP_OK(hipMalloc(&L.basis, n * 4));
+  HIP_OK(hipMalloc(&L.eta, n * 8));
+  HIP_OK(hipMalloc(&L.Nb, n * 24));
+  HIP_OK(hipMalloc(&L.Xb, n * 24));
+  HIP_OK(hipMalloc(&L.tang, n * 48));
+  HIP_OK(hipMalloc(&L.sidx, n * L.kmax * 4));
+  HIP_OK(hipMalloc(&L.sw, n * 2 * L.kmax * 8));
+  // per-identifier compaction by prefix scan over link counts
+  int *cnt = nullptr;
+  int64_t *off = nullptr, *tot = nullptr, *grand = nullptr;
+  const int64_t nb = (g.N + SCAN_CH - 1) / SCAN_CH;
+  HIP_OK(hipMalloc(&cnt, g.N * sizeof(int)));
+  HIP_OK(hipMalloc(&off, g.N * sizeof(int64_t)));
+  HIP_OK(hipMalloc(&tot, nb * sizeof(int64_t)));
+  HIP_OK(hipMalloc(&grand, sizeof(int64_t)));
+  int64_t base = 0;
+  for (int b = 0; b < 256; ++b) {
+    c->bid_begin[b] = c->bid_end[b] = base;
+    if (!hh[b]) continue;
+    hipLaunchKernelGGL((k_count<D>), nblk(g.N, 256), 256, 0, st, g, c->act, bid, b, cnt);
+    hipLaunchKernelGGL(k_scan_tot, (unsigned)nb, SCAN_T, 0, st, cnt, g.N, tot);
+    hipLaunchKernelGGL(k_scan_tot2, 1, SCAN_T, 0, st, tot, nb, grand);
+    hipLaunchKernelGGL(k_scan_apply, (unsigned)nb, SCAN_T, 0, st, cnt, g.N, tot, off);
+    hipLaunchKernelGGL((k_scatter<D>), nblk(g.N, 256), 256, 0, st, g, c->act, bid, b, cnt, off, base, L);
+    int64_t gsum = 0;
+    HIP_OK(hipMemcpyAsync(&gsum, grand, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (gsum != (int64_t)hh[b]) {
+      err = "cut-link compaction count mismatch";
+      return TLVLBM_ERR_DEVICE;
+    }
+    base += gsum;
+    c->bid_end[b] = base;
+  }
+  (void)hipFree(cnt);
+  (void)hipFree(off);
+  (void)hipFree(tot);
+  (void)hipFree(grand);
+  if (total > 0) {
+    hipLaunchKernelGGL((k_link_geom<D>), nblk(total, 128), 128, 0, st, g, phi, c->act, L);
+    hipLaunchKernelGGL((k_link_lsq<D>), nblk(total, 64), 64, 0, st, g, c->act, L, c->d_flag);
+  }
+  HIP_OK(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (flag & FLAG_STENCIL) {
+    err = "LSQ stencil exceeds its capacity";
+    return TLVLBM_ERR_DEVICE;
+  }
+  HIP_OK(hipGetLastError());
+  return TLVLBM_OK;
+}
+
+int build_links(tlvlbm_ctx *c, const double *phi, const uint8_t *bid, std::string &err) {
+  return c->D == 2 ? build_links_t<2>(c, phi, bid, err) : build_links_t<3>(c, phi, bid, err);
+}
+
+template <int D, typename T> static void cutlinks_t(tlvlbm_ctx *c, double tn) {
+  const double th = tn + 0.5 * c->par.dt;
+  for (int b = 0; b < 256; ++b) {
+    const int64_t b0 = c->bid_begin[b], b1 = c->bid_end[b];
+    if (b1 <= b0) continue;
+    const BC &bc = c->bcs[b];
+    if (bc.type == TLVLBM_BC_DIRICHLET_VELOCITY)
+      hipLaunchKernelGGL((k_cut_dirichlet<D, T>), nblk(b1 - b0, 256), 256, 0, c->st, (T *)c->fA, c->L, b0, b1, bc,
+                         c->geo, c->par, th);
+    else
+      hipLaunchKernelGGL((k_cut_neumann<D, T>), nblk(b1 - b0, 128), 128, 0, c->st, (T *)c->fA, c->L, b0, b1, bc,
+                         c->geo, c->par, th, (const T *)c->ubuf, c->d_flag,
+                         (unsigned long long *)c->d_newton_fail);
+  }
+}
+
+void launch_cutlinks(tlvlbm_ctx *c, double tn) {
+  if (c->D == 2) {
+    if (c->prec) cutlinks_t<2, double>(c, tn);
+    else cutlinks_t<2, float>(c, tn);
+  } else {
+    if (c->prec) cutlinks_t<3, double>(c, tn);
+    else cutlinks_t<3, float>(c, tn);
+  }
+}
+
+template <int D, typename T> static int cg_alloc(tlvlbm_ctx *c) {
+  CG &w = c->cg;
+  if (w.x) return TLVLBM_OK;
+  const size_t plane = (size_t)c->geo.S * sizeof(T);
+  void **vec[] = {&w.x, &w.r, &w.p0, &w.p1, &w.Ap, &w.b, &w.V, &w.anc_s};
+  for (void **pp : vec) {
+    HIP_OK(hipMalloc(pp, D * plane));
+    HIP_OK(hipMemsetAsync(*pp, 0, D * plane, c->st));
+  }
+  HIP_OK(hipMalloc(&w.Fm, D * D * plane));
+  HIP_OK(hipMalloc(&w.Fr, D * D * plane));
+  HIP_OK(hipMemsetAsync(w.Fr, 0, D * D * plane, c->st));
+  HIP_OK(hipMalloc(&w.anc_n, c->geo.S));
+  HIP_OK(hipMalloc(&w.anc_i, c->geo.S * sizeof(int)));
+  w.nblk = (int)nblk(c->geo.N, CG_T);
+  HIP_OK(hipMalloc(&w.partial, (size_t)w.nblk * 8 * sizeof(double)));
+  HIP_OK(hipMalloc(&w.scal, S_NSCAL * sizeof(double)));
+  HIP_OK(hipMalloc(&w.counter, sizeof(unsigned)));
+  HIP_OK(hipMemsetAsync(w.counter, 0, sizeof(unsigned), c->st));
+  return TLVLBM_OK;
+}
+
+// anchors accumulate in int32 then narrow to uint8 counts
+template <int D, typename T>
+__global__ void k_anchor_narrow(Geo g, const int *__restrict__ ai, uint8_t *__restrict__ an) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < g.N) an[i] = (uint8_t)ai[i];
+}
+
+template <int D, typename T> static int cg_solve(tlvlbm_ctx *c, const T *F, double t) {
+  CG &w = c->cg;
+  const Geo &g = c->geo;
+  hipStream_t st = c->st;
+  // anchors from the Dirichlet cut links
+  bool any_dir = false;
+  for (int b = 0; b < 256; ++b)
+    if (c->bid_end[b] > c->bid_begin[b] && c->bcs[b].type == TLVLBM_BC_DIRICHLET_VELOCITY) any_dir = true;
+  const uint8_t *anc_n = nullptr;
+  const T *anc_s = nullptr;
+  if (any_dir) {
+    int *ai = w.anc_i;
+    HIP_OK(hipMemsetAsync(ai, 0, g.N * sizeof(int), st));
+    HIP_OK(hipMemsetAsync(w.anc_s, 0, D * (size_t)g.S * sizeof(T), st));
+    for (int b = 0; b < 256; ++b) {
+      const int64_t b0 = c->bid_begin[b], b1 = c->bid_end[b];
+      if (b1 <= b0 || c->bcs[b].type != TLVLBM_BC_DIRICHLET_VELOCITY) continue;
+      hipLaunchKernelGGL((k_anchor<D, T>), nblk(b1 - b0, 128), 128, 0, st, c->L, b0, b1, c->bcs[b], g, t, F, ai,
+                         (T *)w.anc_s);
+    }
+    hipLaunchKernelGGL((k_anchor_narrow<D, T>), nblk(g.N, 256), 256, 0, st, g, ai, w.anc_n);
+    anc_n = w.anc_n;
+    anc_s = (const T *)w.anc_s;
+  }
+  hipLaunchKernelGGL((k_cg_rhs<D, T>), nblk(g.N, 256), 256, 0, st, g, c->act, F, anc_s, (T *)w.b);
+  const double rtol = c->cg_rtol > 0 ? c->cg_rtol : (c->prec ? 1e-14 : 1e-6);
+  hipLaunchKernelGGL((k_cg_init<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const T *)w.b, (const T *)w.x,
+                     (T *)w.r, (T *)w.p0, w.partial, w.counter, w.scal, rtol);
+  const int64_t maxit = c->cg_maxit > 0 ? c->cg_maxit : 10 * c->nactive + 100;
+  T *pa = (T *)w.p0, *pb = (T *)w.p1;
+  int64_t it = 0;
+  while (it < maxit) {
+    const int64_t batch = std::min<int64_t>(32, maxit - it);
+    for (int64_t k = 0; k < batch; ++k) {
+      hipLaunchKernelGGL((k_cg_Ap<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const T *)w.r, pa, pb, (T *)w.Ap,
+                         w.partial, w.counter, w.scal);
+      hipLaunchKernelGGL((k_cg_update<D, T>), w.nblk, CG_T, 0, st, g, c->act, (T *)w.x, (T *)w.r, pb,
+                         (const T *)w.Ap, w.partial, w.counter, w.scal);
+      std::swap(pa, pb);
+    }
+    it += batch;
+    HIP_OK(hipMemcpyAsync(c->hscal, w.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (c->hscal[S_DONE] != 0.0) break;
+  }
+  HIP_OK(hipMemcpyAsync(c->hscal, w.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  for (int k = 0; k < D; ++k) c->st_cg += (int64_t)c->hscal[S_ITS + k];
+  return TLVLBM_OK;
+}
+
+// first == true: projection before collision (u^c from F^n, then F^r);
+// first == false: projection after the repaired collision (u from F^r),
+// followed by the displacement reset.
+template <int D, typename T> static int projection_t(tlvlbm_ctx *c, bool first, double tn) {
+  int st = cg_alloc<D, T>(c);
+  if (st) return st;
+  CG &w = c->cg;
+  const Geo &g = c->geo;
+  const size_t bytes = D * (size_t)g.S * sizeof(T);
+  if (first) {
+    launch_pull_moments(c, nullptr, nullptr, nullptr, true);  // v, F, u^n
+    HIP_OK(hipMemcpyAsync(w.x, c->ubuf, bytes, hipMemcpyDeviceToDevice, c->st));
+    st = cg_solve<D, T>(c, (const T *)w.Fm, tn);
+    if (st) return st;
+    HIP_OK(hipMemcpyAsync(c->ubuf, w.x, bytes, hipMemcpyDeviceToDevice, c->st));
+    hipLaunchKernelGGL((k_gradF<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const T *)w.x, (const T *)w.Fm,
+                       (T *)w.Fr, c->theta);
+  } else {
+    HIP_OK(hipMemcpyAsync(w.x, c->ubuf, bytes, hipMemcpyDeviceToDevice, c->st));
+    st = cg_solve<D, T>(c, (const T *)w.Fr, tn);
+    if (st) return st;
+    hipLaunchKernelGGL((k_ureset<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const T *)w.x, (const T *)w.V,
+                       (T *)c->ubuf, (T *)c->ustar, 0.5 * c->par.dt);
+  }
+  HIP_OK(hipGetLastError());
+  return TLVLBM_OK;
+}
+
+int run_projection(tlvlbm_ctx *c, bool first, double tn) {
+  if (c->D == 2) return c->prec ? projection_t<2, double>(c, first, tn) : projection_t<2, float>(c, first, tn);
+  return c->prec ? projection_t<3, double>(c, first, tn) : projection_t<3, float>(c, first, tn);
+}
+
+}  // namespace tl

@@ -1,0 +1,110 @@
+// Internal types of the tlvlbm runtime (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tlvlbm.h"
+
+namespace tl {
+
+// sticky device error bits
+enum : int { FLAG_J = 1, FLAG_NONFINITE = 2, FLAG_NEWTON = 4, FLAG_ARG = 8, FLAG_STENCIL = 16 };
+
+// maximum LSQ stencil (active nodes within 2.5 dx of X_b; at most 21 lattice
+// points fit in 2D and 81 in 3D)
+constexpr int KMAX2 = 24;
+constexpr int KMAX3 = 88;
+constexpr double LSQ_RADIUS = 2.5;
+
+// grid geometry passed by value to kernels
+struct Geo {
+  int nx, ny, nz;
+  int per;      // periodic bit mask
+  int64_t N;    // nodes
+  int64_t S;    // plane stride (elements) of population and node-field planes
+  double dx, ox, oy, oz;
+};
+
+// scalar parameters of the bulk update
+struct Par {
+  double mu, lam, inv_rho0, dt, c, omega, gamma;
+};
+
+// cut-link table (device SoA), ordered by (bid, node, q)
+struct Links {
+  int64_t n = 0;
+  int kmax = 0;
+  int64_t *node = nullptr, *out = nullptr, *mminus = nullptr;
+  int32_t *q = nullptr, *bid = nullptr, *npts = nullptr, *basis = nullptr;
+  double *eta = nullptr, *Nb = nullptr /*[n][3]*/, *Xb = nullptr /*[n][3]*/, *tang = nullptr /*[n][2][3]*/;
+  int32_t *sidx = nullptr; /*[n][kmax]*/
+  double *sw = nullptr;    /*[n][2][kmax]*/
+};
+
+// boundary condition by value (mirrors tlvlbm_bc)
+struct BC {
+  int type, ramp, disp;
+  double Tr, a[3], G[9], pr, pn, X0[3];
+};
+
+// projection / CG workspace
+struct CG {
+  void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *Ap = nullptr, *b = nullptr;  // [D][S] T
+  void *V = nullptr, *Fm = nullptr, *Fr = nullptr;  // v [D][S], F [D2][S], F^r [D2][S]  (T)
+  uint8_t *anc_n = nullptr;                         // anchors per node
+  int *anc_i = nullptr;                             // anchor counting scratch
+  void *anc_s = nullptr;                            // anchor target sums [D][S] (T)
+  double *partial = nullptr;                        // [nblk][8]
+  double *scal = nullptr;                           // device scalars
+  unsigned *counter = nullptr;
+  int nblk = 0;
+};
+
+}  // namespace tl
+
+struct tlvlbm_ctx {
+  int D = 0, Q = 0, M = 0, prec = 0;
+  tl::Geo geo{};
+  tl::Par par{};
+  double theta = 1.0, cg_rtol = 0.0;
+  int proj_every = 20, cg_maxit = 0, track_opt = -1;
+  bool track_u = false;
+  hipStream_t st = nullptr;
+  size_t esz = 4;
+  void *fA = nullptr, *fB = nullptr;  // population planes (Q*M planes of stride S)
+  void *ustar = nullptr, *ubuf = nullptr;
+  uint8_t *act = nullptr;  // active mask (nullptr: all active)
+  bool has_ls = false, have_state = false;
+  int64_t nactive = 0;
+  tl::Links L;
+  int64_t bid_begin[256] = {0}, bid_end[256] = {0};
+  bool bc_set[256] = {false};
+  tl::BC bcs[256];
+  tl::CG cg;
+  double *hscal = nullptr;  // pinned host mirror for scalars
+  int *d_flag = nullptr;
+  int *h_flag = nullptr;
+  int64_t *d_newton_fail = nullptr;
+  int status = TLVLBM_OK;
+  std::string err;
+  int64_t step = 0;
+  int64_t st_cg = 0, st_proj = 0, st_lin = 0;
+};
+
+namespace tl {
+// launchers (bulk.hip)
+void launch_bulk(tlvlbm_ctx *c, bool repair);
+void launch_pull_moments(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch);
+void launch_init(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0);
+void launch_get_f(tlvlbm_ctx *c, double *f, double *ustar);
+void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar);
+// launchers (embed.hip)
+int build_links(tlvlbm_ctx *c, const double *phi_d, const uint8_t *bid_d, std::string &err);
+void launch_cutlinks(tlvlbm_ctx *c, double tn);
+int run_projection(tlvlbm_ctx *c, bool first, double tn);
+void launch_gradF(tlvlbm_ctx *c);
+void launch_ureset(tlvlbm_ctx *c, bool advance);
+}  // namespace tl

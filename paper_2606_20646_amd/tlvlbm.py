@@ -1,0 +1,228 @@
+"""Python binding of the tlvlbm C ABI (``include/tlvlbm.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libtlvlbm.so``.  Arrays may be numpy (host) or torch tensors (host or
+device); device tensors are passed by pointer.  The library must have been
+built (``paper_2606_20646_amd.build``); importing this module without it
+raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtlvlbm.so")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NONPOSITIVE_J, ERR_NEWTON, ERR_NONFINITE, \
+    ERR_CALL_ORDER = range(8)
+FP32, FP64 = 0, 1
+DIRICHLET, NEUMANN = 1, 2
+RAMPS = {"const": 0, "sin2": 1, "halfcos": 2, "linear": 3}
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("dx", C.c_double), ("origin", C.c_double * 3),
+                ("periodic_mask", C.c_uint32)]
+
+
+class Material(C.Structure):
+    _fields_ = [("law", C.c_int32), ("mu", C.c_double), ("lam", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("omega", C.c_double), ("gamma", C.c_double), ("theta_F", C.c_double), ("cg_rtol", C.c_double),
+                ("proj_every", C.c_int32), ("cg_maxit", C.c_int32), ("precision", C.c_int32),
+                ("track_u", C.c_int32), ("stream", C.c_void_p)]
+
+
+class BC(C.Structure):
+    _fields_ = [("type", C.c_int32), ("ramp", C.c_int32), ("T_r", C.c_double),
+                ("given_as_displacement", C.c_int32), ("a", C.c_double * 3), ("G", C.c_double * 9),
+                ("p_radial", C.c_double), ("p_normal", C.c_double), ("X0", C.c_double * 3)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("active_nodes", "cut_links", "dirichlet_links", "neumann_links",
+                                         "cg_iterations", "newton_failures", "projections", "step",
+                                         "lsq_linear_fallbacks")]
+
+
+class TlvlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tlvlbm error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_20646_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, dp = C.c_void_p, C.c_void_p
+    L.tlvlbm_default_options.argtypes = [C.POINTER(Options)]
+    L.tlvlbm_create.argtypes = [C.POINTER(Grid), C.c_int, C.POINTER(Material), C.c_double, C.c_double,
+                                C.POINTER(Options), C.POINTER(vp)]
+    L.tlvlbm_destroy.argtypes = [vp]
+    L.tlvlbm_set_levelset.argtypes = [vp, dp, dp]
+    L.tlvlbm_set_boundary.argtypes = [vp, C.c_uint8, C.POINTER(BC)]
+    L.tlvlbm_set_material.argtypes = [vp, C.POINTER(Material)]
+    L.tlvlbm_set_state.argtypes = [vp, dp, dp, dp]
+    L.tlvlbm_step.argtypes = [vp, C.c_int64]
+    L.tlvlbm_moments.argtypes = [vp, dp, dp, dp]
+    L.tlvlbm_get_state.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
+    L.tlvlbm_put_state.argtypes = [vp, dp, dp, C.c_int64]
+    L.tlvlbm_get_links.argtypes = [vp, dp, dp, dp, dp, dp]
+    L.tlvlbm_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.tlvlbm_synchronize.argtypes = [vp]
+    L.tlvlbm_last_error.argtypes = [vp]
+    L.tlvlbm_last_error.restype = C.c_char_p
+    L.tlvlbm_population_bytes.argtypes = [vp]
+    L.tlvlbm_population_bytes.restype = C.c_size_t
+    for name in ("create", "destroy", "set_levelset", "set_boundary", "set_material", "set_state", "step",
+                 "moments", "get_state", "put_state", "get_links", "stats", "synchronize"):
+        getattr(L, "tlvlbm_" + name).restype = C.c_int
+    return L
+
+
+lib = _load()
+
+
+def _ptr(a):
+    """(pointer, keepalive) for numpy arrays and torch tensors (contiguous)."""
+    if a is None:
+        return None, None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            a = np.ascontiguousarray(a)
+        return a.ctypes.data, a
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor arguments must be contiguous")
+        return a.data_ptr(), a
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+class Solver:
+    """One TL-VLBM lattice on the GPU (see include/tlvlbm.h for semantics)."""
+
+    def __init__(self, D, n, dx, dt, mu, lam, rho0=1.0, origin=None, periodic_mask=None, omega=1.8, gamma=0.0,
+                 theta_F=1.0, proj_every=20, precision="fp32", track_u=-1, cg_rtol=0.0, cg_maxit=0,
+                 stream=None):
+        self.D, self.M, self.Q = D, D + D * D, 2 * D
+        self.n = tuple(int(v) for v in n)
+        self.N = int(np.prod(self.n))
+        self.dx, self.dt = float(dx), float(dt)
+        g = Grid()
+        for a in range(3):
+            g.n[a] = self.n[a] if a < D else 1
+            g.origin[a] = (origin[a] if origin is not None and a < len(origin) else 0.0)
+        g.dx = dx
+        g.periodic_mask = ((1 << D) - 1) if periodic_mask is None else periodic_mask
+        m = Material(0, mu, lam)
+        o = Options()
+        lib.tlvlbm_default_options(C.byref(o))
+        o.omega, o.gamma, o.theta_F, o.cg_rtol = omega, gamma, theta_F, cg_rtol
+        o.proj_every, o.cg_maxit, o.track_u = proj_every, cg_maxit, track_u
+        o.precision = FP64 if precision in ("fp64", FP64) else FP32
+        o.stream = stream
+        h = C.c_void_p()
+        st = lib.tlvlbm_create(C.byref(g), D, C.byref(m), rho0, dt, C.byref(o), C.byref(h))
+        if st:
+            raise TlvlbmError(st, "create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.tlvlbm_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _chk(self, st, what):
+        if st:
+            raise TlvlbmError(st, f"{what}: {lib.tlvlbm_last_error(self.h).decode()}")
+
+    def set_levelset(self, phi, bid=None):
+        phi = phi if not isinstance(phi, np.ndarray) else np.ascontiguousarray(phi, np.float64).reshape(-1)
+        bid = bid if (bid is None or not isinstance(bid, np.ndarray)) else np.ascontiguousarray(bid, np.uint8)
+        p1, k1 = _ptr(phi)
+        p2, k2 = _ptr(bid)
+        self._chk(lib.tlvlbm_set_levelset(self.h, p1, p2), "set_levelset")
+
+    def set_boundary(self, bid, type, ramp="const", T_r=1.0, given_as_displacement=False, a=None, G=None,
+                     p_radial=0.0, p_normal=0.0, X0=None):
+        b = BC()
+        b.type = {"dirichlet": DIRICHLET, "neumann": NEUMANN}.get(type, type)
+        b.ramp = RAMPS.get(ramp, ramp)
+        b.T_r = T_r
+        b.given_as_displacement = int(bool(given_as_displacement))
+        for k, v in enumerate(a if a is not None else []):
+            b.a[k] = v
+        if G is not None:
+            G = np.asarray(G, float)
+            for i in range(G.shape[0]):
+                for j in range(G.shape[1]):
+                    b.G[i * 3 + j] = G[i, j]
+        b.p_radial, b.p_normal = p_radial, p_normal
+        for k, v in enumerate(X0 if X0 is not None else []):
+            b.X0[k] = v
+        self._chk(lib.tlvlbm_set_boundary(self.h, int(bid), C.byref(b)), "set_boundary")
+
+    def set_material(self, mu, lam):
+        self._chk(lib.tlvlbm_set_material(self.h, C.byref(Material(0, mu, lam))), "set_material")
+
+    def set_state(self, U0, u0=None, dU0=None):
+        arrs = [a if (a is None or not isinstance(a, np.ndarray)) else np.ascontiguousarray(a, np.float64)
+                for a in (U0, u0, dU0)]
+        ptrs = [_ptr(a) for a in arrs]
+        self._chk(lib.tlvlbm_set_state(self.h, ptrs[0][0], ptrs[1][0], ptrs[2][0]), "set_state")
+
+    def step(self, n=1):
+        self._chk(lib.tlvlbm_step(self.h, int(n)), "step")
+
+    def moments(self, U=True, u=True, J=True):
+        Uo = np.zeros((self.M, self.N)) if U else None
+        uo = np.zeros((self.D, self.N)) if u else None
+        Jo = np.zeros(self.N) if J else None
+        self._chk(lib.tlvlbm_moments(self.h, _ptr(Uo)[0], _ptr(uo)[0], _ptr(Jo)[0]), "moments")
+        return Uo, uo, Jo
+
+    def moments_into(self, U=None, u=None, J=None):
+        """Write moments into caller buffers (numpy or torch, host or device)."""
+        self._chk(lib.tlvlbm_moments(self.h, _ptr(U)[0], _ptr(u)[0], _ptr(J)[0]), "moments")
+
+    def get_state(self):
+        f = np.zeros((self.Q, self.M, self.N))
+        us = np.zeros((self.D, self.N))
+        st = C.c_int64(0)
+        self._chk(lib.tlvlbm_get_state(self.h, _ptr(f)[0], _ptr(us)[0], C.byref(st)), "get_state")
+        return f, us, st.value
+
+    def put_state(self, f, ustar=None, step=0):
+        f = np.ascontiguousarray(f, np.float64)
+        us = None if ustar is None else np.ascontiguousarray(ustar, np.float64)
+        self._chk(lib.tlvlbm_put_state(self.h, _ptr(f)[0], _ptr(us)[0], int(step)), "put_state")
+
+    def links(self):
+        L = self.stats()["cut_links"]
+        node = np.zeros(L, np.int64)
+        q = np.zeros(L, np.int32)
+        eta = np.zeros(L)
+        Nb = np.zeros((L, 3))
+        bid = np.zeros(L, np.int32)
+        self._chk(lib.tlvlbm_get_links(self.h, _ptr(node)[0], _ptr(q)[0], _ptr(eta)[0], _ptr(Nb)[0], _ptr(bid)[0]),
+                  "get_links")
+        return dict(node=node, q=q, eta=eta, N=Nb[:, : self.D], bid=bid)
+
+    def stats(self):
+        s = Stats()
+        self._chk(lib.tlvlbm_stats(self.h, C.byref(s)), "stats")
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def synchronize(self):
+        self._chk(lib.tlvlbm_synchronize(self.h), "synchronize")
+
+    def population_bytes(self):
+        return int(lib.tlvlbm_population_bytes(self.h))

@@ -56,7 +56,7 @@ def measured_traffic(nodes):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(n_sample=128, steps=5):
+def cpu_baseline(n_sample=128, steps=200):
     """FP64 oracle on the same recipe at n_sample^3 (bounded CPU sample)."""
     from oracle import oracle as O
     import workloads as W
@@ -75,14 +75,31 @@ def cpu_baseline(n_sample=128, steps=5):
                       f"after 1 untimed step, {dt:.1f} s wall"}
 
 
+def copy_calibration(gib=1, reps=5):
+    """Plain device copy of known size, used to scale the FETCH_SIZE /
+    WRITE_SIZE counters of a profiling run to bytes."""
+    import torch
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)

@@ -17,7 +17,35 @@
 #include "tl_internal.hpp"
 #include "tl_math.hpp"
 
+// Tuning knobs (compile-time): non-temporal population loads / stores, and a
+// minimum number of waves per SIMD for the fused kernel (caps VGPRs).
+#ifndef TL_NT_LOAD
+#define TL_NT_LOAD 1
+#endif
+#ifndef TL_NT_STORE
+#define TL_NT_STORE 1
+#endif
+#ifndef TL_BULK_WAVES
+#define TL_BULK_WAVES 1
+#endif
+
 namespace tl {
+
+template <typename T> __device__ __forceinline__ T ld_pop(const T *p) {
+#if TL_NT_LOAD
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
+template <typename T> __device__ __forceinline__ void st_pop(T *p, T v) {
+#if TL_NT_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
 
 __device__ __forceinline__ int wrap_m(int v, int n) { return v < 0 ? v + n : v; }
 __device__ __forceinline__ int wrap_p(int v, int n) { return v >= n ? v - n : v; }
@@ -41,7 +69,7 @@ __device__ __forceinline__ void load_dir(const T *__restrict__ fin, const Geo &g
                                          T (&f)[2 * D][M]) {
   const int64_t s = pull_src<q>(g, x, y, z);
 #pragma unroll
-  for (int r = 0; r < M; ++r) f[q][r] = fin[(size_t)(q * M + r) * g.S + s];
+  for (int r = 0; r < M; ++r) f[q][r] = ld_pop(fin + (size_t)(q * M + r) * g.S + s);
 }
 
 template <int D, typename T, int M>
@@ -62,7 +90,7 @@ template <typename T> __device__ __forceinline__ bool finite_(T v) { return __bu
 // Fused pull-stream + state recovery + (optional projection repair) + BGK
 // collision with source + displacement quadrature (Algorithm 1, bulk loops).
 template <int D, typename T, bool MASK, bool TRACK, bool REPAIR>
-__global__ __launch_bounds__(256) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
+__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
                                                const uint8_t *__restrict__ act, T *__restrict__ ustar,
                                                T *__restrict__ ubuf, const T *__restrict__ Frp,
                                                int *__restrict__ flag) {
@@ -148,7 +176,7 @@ __global__ __launch_bounds__(256) void k_bulk(const T *__restrict__ fin, T *__re
       const T feq = base * inv2D + sg * inv2c * phi;
       T out = f[q][r] + om * (feq - f[q][r]);
       if (r < D) out += srcw * (-T(p.gamma) * v[r]);
-      fout[(size_t)(q * M + r) * g.S + node] = out;
+      st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
     }
   }
 

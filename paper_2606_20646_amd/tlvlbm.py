@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtlvlbm.so")
+LIB_PATH = os.environ.get("TLVLBM_LIBRARY") or os.path.join(HERE, "libtlvlbm.so")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NONPOSITIVE_J, ERR_NEWTON, ERR_NONFINITE, \
     ERR_CALL_ORDER = range(8)

@@ -88,9 +88,10 @@ typedef struct {
   double omega;       /* BGK relaxation, 0 < omega <= 2 (Sec. 2.4, Eq. 29) */
   double gamma;       /* velocity damping source B = (-gamma v, 0) (Sec. 4.1) */
   double theta_F;     /* repair weight, 0 < theta_F <= 1 (Sec. 3.5, Eq. 60) */
-  double cg_rtol;     /* projection CG tolerance ||r|| <= rtol max(||b||, ||r0||); <= 0: default */
+  double cg_rtol;     /* projection CG stop: ||r|| <= rtol max(||b||, ||r0||) (CG vectors are
+                         FP64 in both builds); <= 0: 1e-14 (FP64 build), 1e-8 (FP32 build) */
   int32_t proj_every; /* projection cadence in steps when Neumann links exist; 0 disables */
-  int32_t cg_maxit;   /* projection CG iteration cap; <= 0: 10 * active nodes */
+  int32_t cg_maxit;   /* projection CG iteration cap; <= 0: 20 sqrt(active nodes) + 100 */
   int32_t precision;  /* tlvlbm_precision of the populations and bulk arithmetic */
   int32_t track_u;    /* 1: carry the displacement quadrature (Eq. 34); 0: not; -1: auto
                          (on whenever a level set is set) */
@@ -201,6 +202,33 @@ tlvlbm_status tlvlbm_synchronize(tlvlbm_ctx *ctx);
 
 /* Text of the last error on this context (never NULL). */
 const char *tlvlbm_last_error(const tlvlbm_ctx *ctx);
+
+/* ---- Many instances (project extension, not in the paper) ---------------
+ * Independent contexts of the same lattice and precision, sharing one
+ * non-default stream, at the same step, each with a level set and state.
+ *
+ * tlvlbm_step_each advances every context n steps with per-instance
+ * launches of the single-instance kernels (the reference for the batched
+ * path).
+ *
+ * tlvlbm_batch_create builds tile lists over all instances; tlvlbm_batch_step
+ * then runs every phase of Algorithm 1 as ONE launch over all instances
+ * (bulk update, cut links, every projection/CG kernel with per-instance
+ * scalars and segmented reductions) and replays the steps between
+ * projections from a captured hipGraph.  The batch borrows the contexts:
+ * they must outlive it, and single-instance calls on them while the batch is
+ * in use are not allowed (the batch keeps its own copy of their buffer
+ * roles).  Results equal the per-instance path up to floating-point
+ * summation order.  Errors of any instance are reported (and made sticky on
+ * that context). */
+typedef struct tlvlbm_batch tlvlbm_batch;
+tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t n, int64_t steps);
+tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_batch **out);
+tlvlbm_status tlvlbm_batch_step(tlvlbm_batch *b, int64_t steps);
+/* 0 disables graph replay (every launch issued from the host) */
+tlvlbm_status tlvlbm_batch_set_graph(tlvlbm_batch *b, int32_t use_graph);
+tlvlbm_status tlvlbm_batch_destroy(tlvlbm_batch *b);
+const char *tlvlbm_batch_last_error(const tlvlbm_batch *b);
 
 /* Size in bytes of one population buffer (for bandwidth accounting). */
 size_t tlvlbm_population_bytes(const tlvlbm_ctx *ctx);

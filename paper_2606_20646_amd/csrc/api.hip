@@ -122,6 +122,27 @@ bool has_neumann(const tlvlbm_ctx *c) {
   return false;
 }
 
+// launches of one step of Algorithm 1 (no host synchronisation except inside
+// the projection's CG convergence polling)
+int step_once(tlvlbm_ctx *c) {
+  const double tn = c->step * c->par.dt;
+  const bool proj = has_neumann(c) && c->proj_every > 0 && (c->step % c->proj_every == 0);
+  if (proj) {
+    int s = run_projection(c, true, tn);
+    if (s) return s;
+    launch_bulk(c, true);
+    s = run_projection(c, false, tn);
+    if (s) return s;
+    ++c->st_proj;
+  } else {
+    launch_bulk(c, false);
+  }
+  if (c->L.n) launch_cutlinks(c, tn);
+  std::swap(c->fA, c->fB);
+  ++c->step;
+  return TLVLBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -333,28 +354,37 @@ tlvlbm_status tlvlbm_step(tlvlbm_ctx *c, int64_t n) {
   if (!c || n < 0) return TLVLBM_ERR_INVALID_ARG;
   if (!c->have_state) return fail(c, TLVLBM_ERR_CALL_ORDER, "step before set_state");
   if (c->status) return (tlvlbm_status)c->status;
-  const bool neu = has_neumann(c);
   for (int64_t k = 0; k < n; ++k) {
-    const double tn = c->step * c->par.dt;
-    const bool proj = neu && c->proj_every > 0 && (c->step % c->proj_every == 0);
-    if (proj) {
-      int s = run_projection(c, true, tn);
-      if (s) return (tlvlbm_status)(c->status = s);
-      launch_bulk(c, true);
-      s = run_projection(c, false, tn);
-      if (s) return (tlvlbm_status)(c->status = s);
-      ++c->st_proj;
-    } else {
-      launch_bulk(c, false);
-    }
-    if (c->L.n) launch_cutlinks(c, tn);
-    std::swap(c->fA, c->fB);
-    ++c->step;
+    const int s = step_once(c);
+    if (s) return (tlvlbm_status)(c->status = s);
   }
   CHK(hipGetLastError(), "step launch");
   tlvlbm_status s = read_flag(c);
   c->status = s;
   return s;
+}
+
+tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t nctx, int64_t n) {
+  if (!ctxs || nctx < 1 || n < 0) return TLVLBM_ERR_INVALID_ARG;
+  for (int i = 0; i < nctx; ++i) {
+    if (!ctxs[i]) return TLVLBM_ERR_INVALID_ARG;
+    if (!ctxs[i]->have_state) return fail(ctxs[i], TLVLBM_ERR_CALL_ORDER, "step before set_state");
+    if (ctxs[i]->status) return (tlvlbm_status)ctxs[i]->status;
+  }
+  for (int64_t k = 0; k < n; ++k)
+    for (int i = 0; i < nctx; ++i) {
+      const int s = step_once(ctxs[i]);
+      if (s) return (tlvlbm_status)(ctxs[i]->status = s);
+    }
+  tlvlbm_status worst = TLVLBM_OK;
+  for (int i = 0; i < nctx; ++i) {
+    tlvlbm_ctx *c = ctxs[i];
+    CHK(hipGetLastError(), "step launch");
+    const tlvlbm_status s = read_flag(c);
+    c->status = s;
+    if (s) worst = s;
+  }
+  return worst;
 }
 
 tlvlbm_status tlvlbm_moments(tlvlbm_ctx *c, double *U_out, double *u_out, double *J_out) {

@@ -1,0 +1,337 @@
+// Batched launch of many independent TL-VLBM instances (project extension):
+// every phase of Algorithm 1 runs as one tile-list kernel over all instances,
+// the projection CG keeps per-instance scalars with segmented reductions, and
+// stretches of steps without projection are replayed from a hipGraph.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tl_internal.hpp"
+
+using namespace tl;
+
+struct tlvlbm_batch {
+  std::vector<tlvlbm_ctx *> c;
+  int D = 0, prec = 0, proj_every = 0;
+  hipStream_t st = nullptr;
+  std::vector<Inst> h_inst;
+  Inst *d_inst = nullptr;
+  int4 *d_btiles = nullptr, *d_ctiles = nullptr, *d_ltiles = nullptr;
+  int nbt = 0, nct = 0, nlt = 0;
+  Seg *d_segs = nullptr;
+  int64_t *d_step = nullptr;
+  int *d_pending = nullptr, *h_pending = nullptr;
+  int *h_flags = nullptr;
+  bool any_neu = false, any_dir = false;
+  int64_t step = 0, maxit = 0;
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
+  int glen = 0;
+  std::string err;
+};
+
+namespace {
+
+tlvlbm_status bfail(tlvlbm_batch *b, tlvlbm_status s, const char *m) {
+  if (b) {
+    try {
+      b->err = m;
+    } catch (...) {
+    }
+  }
+  return s;
+}
+
+#define BCHK(expr, what)                                                 \
+  do {                                                                   \
+    if ((expr) != hipSuccess) return bfail(b, TLVLBM_ERR_DEVICE, what); \
+  } while (0)
+
+BatchArgs args_of(tlvlbm_batch *b) {
+  BatchArgs a{};
+  a.st = b->st;
+  a.insts = b->d_inst;
+  a.ninst = (int)b->c.size();
+  a.segs = b->d_segs;
+  a.ltiles = b->d_ltiles;
+  a.nlt = b->nlt;
+  a.ctiles = b->d_ctiles;
+  a.nct = b->nct;
+  a.step = b->d_step;
+  a.pending = b->d_pending;
+  return a;
+}
+
+void run(tlvlbm_batch *b, BatchOp op, int fa = 0, int fb = 0) {
+  BatchArgs a = args_of(b);
+  a.flagA = fa;
+  a.flagB = fb;
+  launch_batch(b->D, b->prec, op, a);
+}
+
+tlvlbm_status cg_batch(tlvlbm_batch *b, int useFr) {
+  const int anch = b->any_dir ? 1 : 0;
+  if (anch) {
+    run(b, BatchOp::ZeroAnchor);
+    if (b->nlt) run(b, BatchOp::Anchor, useFr);
+    run(b, BatchOp::NarrowAnchor);
+  }
+  run(b, BatchOp::Rhs, useFr, anch);
+  run(b, BatchOp::CgInit, 0, anch);
+  int pp = 0;
+  for (int64_t it = 0; it < b->maxit;) {
+    const int64_t k = std::min<int64_t>(32, b->maxit - it);
+    for (int64_t j = 0; j < k; ++j) {
+      run(b, BatchOp::CgAp, pp, anch);
+      run(b, BatchOp::CgUpdate, pp);
+      pp ^= 1;
+    }
+    it += k;
+    BCHK(hipMemsetAsync(b->d_pending, 0, sizeof(int), b->st), "pending clear");
+    run(b, BatchOp::Pending);
+    BCHK(hipMemcpyAsync(b->h_pending, b->d_pending, sizeof(int), hipMemcpyDeviceToHost, b->st), "pending read");
+    BCHK(hipStreamSynchronize(b->st), "synchronize");
+    if (*b->h_pending == 0) break;
+  }
+  return TLVLBM_OK;
+}
+
+void plain_step(tlvlbm_batch *b) {
+  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, false, b->st);
+  if (b->nlt) run(b, BatchOp::Cut);
+  run(b, BatchOp::StepEnd);
+}
+
+tlvlbm_status projection_step(tlvlbm_batch *b) {
+  launch_moments_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, b->st);
+  run(b, BatchOp::XfromU);
+  tlvlbm_status s = cg_batch(b, 0);
+  if (s) return s;
+  run(b, BatchOp::UfromX);
+  run(b, BatchOp::GradF);
+  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, true, b->st);
+  run(b, BatchOp::XfromU);
+  s = cg_batch(b, 1);
+  if (s) return s;
+  run(b, BatchOp::UReset);
+  if (b->nlt) run(b, BatchOp::Cut);
+  run(b, BatchOp::StepEnd);
+  return TLVLBM_OK;
+}
+
+// capture glen plain steps once; replayed for every such stretch
+tlvlbm_status ensure_graph(tlvlbm_batch *b, int len) {
+  if (b->gexec && b->glen == len) return TLVLBM_OK;
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  BCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal), "graph capture");
+  for (int k = 0; k < len; ++k) plain_step(b);
+  BCHK(hipStreamEndCapture(b->st, &g), "graph capture end");
+  BCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0), "graph instantiate");
+  (void)hipGraphDestroy(g);
+  b->glen = len;
+  return TLVLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_batch **out) {
+  if (!ctxs || n < 1 || !out) return TLVLBM_ERR_INVALID_ARG;
+  *out = nullptr;
+  tlvlbm_batch *b = new (std::nothrow) tlvlbm_batch();
+  if (!b) return TLVLBM_ERR_OUT_OF_MEMORY;
+  try {
+    const tlvlbm_ctx *c0 = ctxs[0];
+    if (!c0) {
+      delete b;
+      return TLVLBM_ERR_INVALID_ARG;
+    }
+    b->D = c0->D;
+    b->prec = c0->prec;
+    b->st = c0->st;
+    b->proj_every = c0->proj_every;
+    b->step = c0->step;
+    b->use_graph = b->st != nullptr;  // no stream capture on the legacy default stream
+    std::vector<Seg> segs;
+    std::vector<int4> bt, ct, lt;
+    for (int k = 0; k < n; ++k) {
+      tlvlbm_ctx *c = ctxs[k];
+      if (!c || c->D != b->D || c->prec != b->prec || c->st != b->st || c->proj_every != b->proj_every ||
+          c->step != b->step || !c->have_state || !c->has_ls || !c->track_u || c->status) {
+        delete b;
+        return TLVLBM_ERR_INVALID_ARG;
+      }
+      if (ensure_cg(c)) {
+        delete b;
+        return TLVLBM_ERR_OUT_OF_MEMORY;
+      }
+      b->c.push_back(c);
+      Inst I{};
+      I.g = c->geo;
+      I.p = c->par;
+      I.theta = c->theta;
+      I.rtol = c->cg_rtol > 0 ? c->cg_rtol : cg_default_rtol(c->prec);
+      I.fin = c->fB;
+      I.fout = c->fA;
+      I.act = c->act;
+      I.ustar = c->ustar;
+      I.ubuf = c->ubuf;
+      I.L = c->L;
+      I.x = c->cg.x;
+      I.r = c->cg.r;
+      I.p0 = c->cg.p0;
+      I.p1 = c->cg.p1;
+      I.Ap = c->cg.Ap;
+      I.b = c->cg.b;
+      I.V = c->cg.V;
+      I.Fm = c->cg.Fm;
+      I.Fr = c->cg.Fr;
+      I.anc_s = c->cg.anc_s;
+      I.anc_n = c->cg.anc_n;
+      I.anc_i = c->cg.anc_i;
+      I.partial = c->cg.partial;
+      I.scal = c->cg.scal;
+      I.counter = c->cg.counter;
+      I.nblk = c->cg.nblk;
+      I.flag = c->d_flag;
+      I.nfail = (unsigned long long *)c->d_newton_fail;
+      b->h_inst.push_back(I);
+      const Geo &g = c->geo;
+      for (int row = 0; row < g.ny * g.nz; ++row)
+        for (int x0 = 0; x0 < g.nx; x0 += 256) bt.push_back(make_int4(k, row, x0, 0));
+      for (int blk = 0; blk < c->cg.nblk; ++blk) ct.push_back(make_int4(k, blk, 0, 0));
+      for (int bid = 0; bid < 256; ++bid) {
+        const int64_t b0 = c->bid_begin[bid], b1 = c->bid_end[bid];
+        if (b1 <= b0) continue;
+        Seg s{};
+        s.inst = k;
+        s.type = c->bcs[bid].type;
+        s.b0 = b0;
+        s.b1 = b1;
+        s.bc = c->bcs[bid];
+        if (s.type == TLVLBM_BC_NEUMANN_TRACTION) b->any_neu = true;
+        if (s.type == TLVLBM_BC_DIRICHLET_VELOCITY) b->any_dir = true;
+        for (int64_t o = 0; o < b1 - b0; o += 64) lt.push_back(make_int4((int)segs.size(), (int)o, 0, 0));
+        segs.push_back(s);
+      }
+      b->maxit = std::max<int64_t>(b->maxit, c->cg_maxit > 0 ? c->cg_maxit : cg_default_maxit(c->nactive));
+    }
+    b->nbt = (int)bt.size();
+    b->nct = (int)ct.size();
+    b->nlt = (int)lt.size();
+    if (hipMalloc(&b->d_inst, n * sizeof(Inst)) != hipSuccess ||
+        hipMalloc(&b->d_btiles, bt.size() * sizeof(int4)) != hipSuccess ||
+        hipMalloc(&b->d_ctiles, ct.size() * sizeof(int4)) != hipSuccess ||
+        hipMalloc(&b->d_ltiles, std::max<size_t>(1, lt.size()) * sizeof(int4)) != hipSuccess ||
+        hipMalloc(&b->d_segs, std::max<size_t>(1, segs.size()) * sizeof(Seg)) != hipSuccess ||
+        hipMalloc(&b->d_step, sizeof(int64_t)) != hipSuccess || hipMalloc(&b->d_pending, sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_pending, sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_flags, n * sizeof(int)) != hipSuccess) {
+      tlvlbm_batch_destroy(b);
+      return TLVLBM_ERR_OUT_OF_MEMORY;
+    }
+    hipStream_t st = b->st;
+    if (hipMemcpyAsync(b->d_inst, b->h_inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->d_btiles, bt.data(), bt.size() * sizeof(int4), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->d_ctiles, ct.data(), ct.size() * sizeof(int4), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (lt.size() &&
+         hipMemcpyAsync(b->d_ltiles, lt.data(), lt.size() * sizeof(int4), hipMemcpyHostToDevice, st) != hipSuccess) ||
+        (segs.size() &&
+         hipMemcpyAsync(b->d_segs, segs.data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipMemcpyAsync(b->d_step, &b->step, sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      tlvlbm_batch_destroy(b);
+      return TLVLBM_ERR_DEVICE;
+    }
+    *out = b;
+    return TLVLBM_OK;
+  } catch (...) {
+    delete b;
+    return TLVLBM_ERR_OUT_OF_MEMORY;
+  }
+}
+
+tlvlbm_status tlvlbm_batch_set_graph(tlvlbm_batch *b, int32_t use_graph) {
+  if (!b) return TLVLBM_ERR_INVALID_ARG;
+  b->use_graph = use_graph != 0 && b->st != nullptr;
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_batch_step(tlvlbm_batch *b, int64_t n) {
+  if (!b || n < 0) return TLVLBM_ERR_INVALID_ARG;
+  for (auto *c : b->c)
+    if (c->status) return bfail(b, (tlvlbm_status)c->status, "an instance holds a sticky error");
+  const int pe = b->proj_every;
+  int64_t k = 0;
+  while (k < n) {
+    const bool proj = b->any_neu && pe > 0 && (b->step % pe == 0);
+    if (proj) {
+      tlvlbm_status s = projection_step(b);
+      if (s) return s;
+      ++b->step;
+      ++k;
+      continue;
+    }
+    // plain steps until the next projection step (or the end)
+    int64_t run_len = n - k;
+    if (b->any_neu && pe > 0) run_len = std::min<int64_t>(run_len, pe - (b->step % pe));
+    const int glen = (b->any_neu && pe > 1) ? pe - 1 : 20;
+    if (b->use_graph && run_len == glen) {
+      tlvlbm_status s = ensure_graph(b, glen);
+      if (s) return s;
+      BCHK(hipGraphLaunch(b->gexec, b->st), "graph launch");
+    } else {
+      for (int64_t j = 0; j < run_len; ++j) plain_step(b);
+    }
+    b->step += run_len;
+    k += run_len;
+  }
+  BCHK(hipGetLastError(), "batch launch");
+  // keep the contexts' view of their buffers and step in sync
+  const int ni = (int)b->c.size();
+  for (int i = 0; i < ni; ++i) {
+    tlvlbm_ctx *c = b->c[i];
+    if (n & 1) std::swap(c->fA, c->fB);
+    c->step = b->step;
+    BCHK(hipMemcpyAsync(b->h_flags + i, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, b->st), "flag read");
+  }
+  BCHK(hipStreamSynchronize(b->st), "synchronize");
+  tlvlbm_status worst = TLVLBM_OK;
+  for (int i = 0; i < ni; ++i) {
+    const int f = b->h_flags[i];
+    tlvlbm_status s = (f & FLAG_NONFINITE) ? TLVLBM_ERR_NONFINITE
+                      : (f & FLAG_J)       ? TLVLBM_ERR_NONPOSITIVE_J
+                      : (f & FLAG_NEWTON)  ? TLVLBM_ERR_NEWTON
+                                           : TLVLBM_OK;
+    if (s) {
+      b->c[i]->status = s;
+      worst = s;
+    }
+  }
+  if (worst) return bfail(b, worst, "an instance reported a device failure");
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_batch_destroy(tlvlbm_batch *b) {
+  if (!b) return TLVLBM_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(b->st);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  void *ptrs[] = {b->d_inst, b->d_btiles, b->d_ctiles, b->d_ltiles, b->d_segs, b->d_step, b->d_pending};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (b->h_pending) (void)hipHostFree(b->h_pending);
+  if (b->h_flags) (void)hipHostFree(b->h_flags);
+  delete b;
+  return TLVLBM_OK;
+}
+
+const char *tlvlbm_batch_last_error(const tlvlbm_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"

@@ -90,14 +90,11 @@ template <typename T> __device__ __forceinline__ bool finite_(T v) { return __bu
 // Fused pull-stream + state recovery + (optional projection repair) + BGK
 // collision with source + displacement quadrature (Algorithm 1, bulk loops).
 template <int D, typename T, bool MASK, bool TRACK, bool REPAIR>
-__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
-                                               const uint8_t *__restrict__ act, T *__restrict__ ustar,
-                                               T *__restrict__ ubuf, const T *__restrict__ Frp,
-                                               int *__restrict__ flag) {
+__device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restrict__ fout, const Geo &g,
+                                          const Par &p, const uint8_t *__restrict__ act, T *__restrict__ ustar,
+                                          T *__restrict__ ubuf, const T *__restrict__ Frp,
+                                          int *__restrict__ flag, int x, int row) {
   constexpr int Q = 2 * D, M = D + D * D;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= g.nx) return;
-  const int row = blockIdx.y;
   const int y = row % g.ny, z = row / g.ny;
   const int64_t node = x + (int64_t)g.nx * row;
   if constexpr (MASK) {
@@ -201,18 +198,37 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
   if (bad || !finite_(chk)) atomicOr(flag, finite_(chk) ? FLAG_J : FLAG_NONFINITE);
 }
 
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR>
+__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g,
+                                                             Par p, const uint8_t *__restrict__ act,
+                                                             T *__restrict__ ustar, T *__restrict__ ubuf,
+                                                             const T *__restrict__ Frp, int *__restrict__ flag) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  bulk_node<D, T, MASK, TRACK, REPAIR>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, (int)blockIdx.y);
+}
+
+// Batched bulk update: one block per tile (instance, row, first x) of the
+// tile list; every instance keeps its own geometry, material and buffers.
+template <int D, typename T, bool REPAIR>
+__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_batch(const Inst *__restrict__ insts,
+                                                                   const int4 *__restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const int x = t.z + threadIdx.x;
+  if (x >= I.g.nx) return;
+  bulk_node<D, T, true, true, REPAIR>((const T *)I.fin, (T *)I.fout, I.g, I.p, I.act, (T *)I.ustar, (T *)I.ubuf,
+                                      (const T *)I.Fr, I.flag, x, t.y);
+}
+
 // Pull f^n and write moments: v (damping-corrected), F, u = u* + dt/2 v, J.
 // Output planes have stride ostride; any output may be null.
 template <int D, typename T, typename O, bool MASK>
-__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ fin, Geo g, Par p,
-                                                  const uint8_t *__restrict__ act,
-                                                  const T *__restrict__ ustar, O *__restrict__ Vo,
-                                                  O *__restrict__ Fo, O *__restrict__ uo, O *__restrict__ Jo,
-                                                  int64_t ostride) {
+__device__ __forceinline__ void moments_node(const T *__restrict__ fin, const Geo &g, const Par &p,
+                                             const uint8_t *__restrict__ act, const T *__restrict__ ustar,
+                                             O *__restrict__ Vo, O *__restrict__ Fo, O *__restrict__ uo,
+                                             O *__restrict__ Jo, int64_t ostride, int x, int row) {
   constexpr int Q = 2 * D, M = D + D * D;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= g.nx) return;
-  const int row = blockIdx.y;
   const int y = row % g.ny, z = row / g.ny;
   const int64_t node = x + (int64_t)g.nx * row;
   if (MASK && !act[node]) {
@@ -249,6 +265,28 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ fin, Geo 
     for (int i = 0; i < D; ++i)
       uo[(size_t)i * ostride + node] = ustar ? O(ustar[(size_t)i * g.S + node] + T(0.5) * T(p.dt) * v[i]) : O(0);
   if (Jo) Jo[node] = O(det<D>(F));
+}
+
+template <int D, typename T, typename O, bool MASK>
+__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ fin, Geo g, Par p,
+                                                  const uint8_t *__restrict__ act, const T *__restrict__ ustar,
+                                                  O *__restrict__ Vo, O *__restrict__ Fo, O *__restrict__ uo,
+                                                  O *__restrict__ Jo, int64_t ostride) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  moments_node<D, T, O, MASK>(fin, g, p, act, ustar, Vo, Fo, uo, Jo, ostride, x, (int)blockIdx.y);
+}
+
+// batched projection inputs: v, F into each instance's workspace, u = u* + dt/2 v
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_moments_batch(const Inst *__restrict__ insts,
+                                                        const int4 *__restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const int x = t.z + threadIdx.x;
+  if (x >= I.g.nx) return;
+  moments_node<D, T, T, true>((const T *)I.fin, I.g, I.p, I.act, (const T *)I.ustar, (T *)I.V, (T *)I.Fm,
+                              (T *)I.ubuf, (T *)nullptr, I.g.S, x, t.y);
 }
 
 // Second-order initialisation (Sec. 2.4, Eqs. 32-33) in FP64, stored
@@ -527,6 +565,40 @@ void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar) {
   } else {
     if (c->prec) putf_t<3, double>(c, f, ustar);
     else putf_t<3, float>(c, f, ustar);
+  }
+}
+
+}  // namespace tl
+
+namespace tl {
+
+// batched launchers: tiles are (instance, row, first x, 0) triples of 256 nodes
+template <int D, typename T> static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool repair,
+                                                      hipStream_t st) {
+  if (repair)
+    hipLaunchKernelGGL((k_bulk_batch<D, T, true>), ntiles, 256, 0, st, insts, tiles);
+  else
+    hipLaunchKernelGGL((k_bulk_batch<D, T, false>), ntiles, 256, 0, st, insts, tiles);
+}
+
+void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair,
+                       hipStream_t st) {
+  if (D == 2) {
+    if (prec) bulk_batch_t<2, double>(insts, tiles, ntiles, repair, st);
+    else bulk_batch_t<2, float>(insts, tiles, ntiles, repair, st);
+  } else {
+    if (prec) bulk_batch_t<3, double>(insts, tiles, ntiles, repair, st);
+    else bulk_batch_t<3, float>(insts, tiles, ntiles, repair, st);
+  }
+}
+
+void launch_moments_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, hipStream_t st) {
+  if (D == 2) {
+    if (prec) hipLaunchKernelGGL((k_moments_batch<2, double>), ntiles, 256, 0, st, insts, tiles);
+    else hipLaunchKernelGGL((k_moments_batch<2, float>), ntiles, 256, 0, st, insts, tiles);
+  } else {
+    if (prec) hipLaunchKernelGGL((k_moments_batch<3, double>), ntiles, 256, 0, st, insts, tiles);
+    else hipLaunchKernelGGL((k_moments_batch<3, float>), ntiles, 256, 0, st, insts, tiles);
   }
 }
 

@@ -467,11 +467,9 @@ template <int D> __device__ __forceinline__ void bc_base(const BC &b, const doub
 // reconstructed incoming population is written to the pull slot of the
 // outside node.  One thread per link.
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_cut_dirichlet(T *__restrict__ f, Links L, int64_t b0, int64_t b1, BC bc,
-                                                        Geo g, Par p, double th) {
+__device__ __forceinline__ void cut_dirichlet_link(T *__restrict__ f, const Links &L, int64_t l, const BC &bc,
+                                                   const Geo &g, const Par &p, double th) {
   constexpr int M = D + D * D;
-  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (l >= b1) return;
   const int64_t m = L.node[l], mm = L.mminus[l], o = L.out[l];
   const int qo = L.q[l], qi = qo ^ 1, A = qo / 2;
   const double sg = (qo & 1) ? -1.0 : 1.0;
@@ -627,13 +625,10 @@ __device__ bool newton_h(const double *N, const double *Gt, const double *Tb, do
 // boundary state enters the deformation-gradient rows, the Piola flux the
 // velocity rows.
 template <int D, typename T>
-__global__ __launch_bounds__(128) void k_cut_neumann(T *__restrict__ f, Links L, int64_t b0, int64_t b1, BC bc,
-                                                      Geo g, Par p, double th, const T *__restrict__ u,
-                                                      int *__restrict__ flag,
-                                                      unsigned long long *__restrict__ nfail) {
+__device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links &L, int64_t l, const BC &bc,
+                                                 const Geo &g, const Par &p, double th, const T *__restrict__ u,
+                                                 int *__restrict__ flag, unsigned long long *__restrict__ nfail) {
   constexpr int Q = 2 * D, M = D + D * D;
-  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (l >= b1) return;
   const int64_t m = L.node[l], mm = L.mminus[l], o = L.out[l];
   const int qo = L.q[l], qi = qo ^ 1, A = qo / 2;
   const double sg = (qo & 1) ? -1.0 : 1.0;
@@ -722,10 +717,9 @@ __global__ __launch_bounds__(128) void k_cut_neumann(T *__restrict__ f, Links L,
 // anchors of the projection null mode: each Dirichlet cut link adds
 // u_m = u_D(X_b, t) - (F_m - I)(X_b - X_m) with unit weight
 template <int D, typename T>
-__global__ void k_anchor(Links L, int64_t b0, int64_t b1, BC bc, Geo g, double t, const T *__restrict__ Fm,
-                         int *__restrict__ anc_n, T *__restrict__ anc_s) {
-  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (l >= b1) return;
+__device__ __forceinline__ void anchor_link(const Links &L, int64_t l, const BC &bc, const Geo &g, double t,
+                                            const T *__restrict__ Fm, int *__restrict__ anc_n,
+                                            double *__restrict__ anc_s) {
   const int64_t m = L.node[l];
   const int q = L.q[l], A = q / 2;
   const double sg = (q & 1) ? -1.0 : 1.0;
@@ -742,29 +736,28 @@ __global__ void k_anchor(Links L, int64_t b0, int64_t b1, BC bc, Geo g, double t
   atomicAdd(&anc_n[m], 1);
   for (int i = 0; i < D; ++i) {
     const double Fi = double(Fm[(size_t)(i * D + A) * g.S + m]) - (i == A ? 1.0 : 0.0);
-    atomicAdd(&anc_s[(size_t)i * g.S + m], T(uD[i] * fac - Fi * off));
+    atomicAdd(&anc_s[(size_t)i * g.S + m], uD[i] * fac - Fi * off);
   }
 }
 
 // right-hand side of the normal equations of the edge least-squares problem
 // (Eq. 57) plus the anchor targets
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_cg_rhs(Geo g, const uint8_t *__restrict__ act, const T *__restrict__ Fm,
-                                                 const T *__restrict__ anc_s, T *__restrict__ b) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cg_rhs_node(const Geo &g, const uint8_t *__restrict__ act, const T *__restrict__ Fm,
+                                            const double *__restrict__ anc_s, double *__restrict__ b, int64_t i) {
   if (i >= g.N) return;
   if (!act[i]) {
-    for (int c = 0; c < D; ++c) b[(size_t)c * g.S + i] = T(0);
+    for (int c = 0; c < D; ++c) b[(size_t)c * g.S + i] = double(0);
     return;
   }
   const C3 cc = coords_of(g, i);
-  const T hdx = T(0.5 * g.dx);
+  const double hdx = double(0.5 * g.dx);
   for (int c = 0; c < D; ++c) {
-    T acc = anc_s ? anc_s[(size_t)c * g.S + i] : T(0);
+    double acc = anc_s ? anc_s[(size_t)c * g.S + i] : double(0);
     for (int A = 0; A < D; ++A) {
       const int64_t lp = node_dir(g, cc, 2 * A, 1), lm = node_dir(g, cc, 2 * A + 1, 1);
-      const T Fi = Fm[(size_t)(c * D + A) * g.S + i];
-      const T dl = (c == A) ? T(2) : T(0);
+      const double Fi = Fm[(size_t)(c * D + A) * g.S + i];
+      const double dl = (c == A) ? double(2) : double(0);
       if (lm >= 0 && act[lm]) acc += hdx * (Fi + Fm[(size_t)(c * D + A) * g.S + lm] - dl);
       if (lp >= 0 && act[lp]) acc -= hdx * (Fi + Fm[(size_t)(c * D + A) * g.S + lp] - dl);
     }
@@ -774,6 +767,8 @@ __global__ __launch_bounds__(256) void k_cg_rhs(Geo g, const uint8_t *__restrict
 
 // scalar slots of the CG state (device doubles)
 enum { S_RR = 0, S_BB = 4, S_THR = 8, S_ALPHA = 12, S_BETA = 16, S_ACT = 20, S_ITS = 24, S_DONE = 28, S_NSCAL = 32 };
+// block partials: up to PSTRIDE doubles per block
+constexpr int PSTRIDE = 16;
 
 constexpr int CG_T = 256;
 
@@ -781,8 +776,9 @@ constexpr int CG_T = 256;
 // last block to finish sums all partials in block order (deterministic) and
 // hands the totals to fin()
 template <int K>
-__device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, unsigned *counter, double *tot) {
-  __shared__ double sh[CG_T / 64][8];
+__device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, unsigned *counter, double *tot,
+                                               int blk, int nblk) {
+  __shared__ double sh[CG_T / 64][PSTRIDE];
   __shared__ bool last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -792,26 +788,25 @@ __device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, 
     if (lane == 0) sh[wid][k] = x;
   }
   __syncthreads();
-  const int blk = blockIdx.x;
   if (threadIdx.x < K) {
     double s = 0.0;
     for (int w = 0; w < CG_T / 64; ++w) s += sh[w][threadIdx.x];
-    partial[blk * 8 + threadIdx.x] = s;
+    partial[blk * PSTRIDE + threadIdx.x] = s;
   }
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned t = atomicAdd(counter, 1u);
-    last = (t == gridDim.x - 1);
+    last = (t == (unsigned)nblk - 1);
   }
   __syncthreads();
   if (!last) return false;
   __threadfence();
-  __shared__ double tsum[8];
+  __shared__ double tsum[PSTRIDE];
   if (threadIdx.x < K) {
     double s = 0.0;
     const volatile double *pv = partial;
-    for (unsigned b = 0; b < gridDim.x; ++b) s += pv[b * 8 + threadIdx.x];
+    for (int b = 0; b < nblk; ++b) s += pv[b * PSTRIDE + threadIdx.x];
     tsum[threadIdx.x] = s;
   }
   __syncthreads();
@@ -823,11 +818,12 @@ __device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, 
 
 // r = b - A x, p = r, rr and bb (A = active-graph Laplacian + anchors)
 template <int D, typename T>
-__global__ __launch_bounds__(CG_T) void k_cg_init(Geo g, const uint8_t *__restrict__ act,
-                                                   const uint8_t *__restrict__ anc_n, const T *__restrict__ b,
-                                                   const T *__restrict__ x, T *__restrict__ r, T *__restrict__ p,
-                                                   double *partial, unsigned *counter, double *scal, double rtol) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cg_init_blk(const Geo &g, const uint8_t *__restrict__ act,
+                                            const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
+                                            const double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
+                                            double *partial, unsigned *counter, double *scal, double rtol, int blk,
+                                            int nblk) {
+  const int64_t i = blk * (int64_t)CG_T + threadIdx.x;
   double v[2 * D];
   for (int k = 0; k < 2 * D; ++k) v[k] = 0.0;
   if (i < g.N) {
@@ -841,11 +837,11 @@ __global__ __launch_bounds__(CG_T) void k_cg_init(Geo g, const uint8_t *__restri
         if (nb[q] >= 0) ++deg;
       }
       for (int c = 0; c < D; ++c) {
-        T ax = T(deg) * x[(size_t)c * g.S + i];
+        double ax = double(deg) * x[(size_t)c * g.S + i];
         for (int q = 0; q < 2 * D; ++q)
           if (nb[q] >= 0) ax -= x[(size_t)c * g.S + nb[q]];
-        const T bi = b[(size_t)c * g.S + i];
-        const T ri = bi - ax;
+        const double bi = b[(size_t)c * g.S + i];
+        const double ri = bi - ax;
         r[(size_t)c * g.S + i] = ri;
         p[(size_t)c * g.S + i] = ri;
         v[c] = double(ri) * double(ri);
@@ -853,13 +849,13 @@ __global__ __launch_bounds__(CG_T) void k_cg_init(Geo g, const uint8_t *__restri
       }
     } else {
       for (int c = 0; c < D; ++c) {
-        r[(size_t)c * g.S + i] = T(0);
-        p[(size_t)c * g.S + i] = T(0);
+        r[(size_t)c * g.S + i] = double(0);
+        p[(size_t)c * g.S + i] = double(0);
       }
     }
   }
-  double tot[8];
-  if (block_partials<2 * D>(v, partial, counter, tot) && threadIdx.x == 0) {
+  double tot[PSTRIDE];
+  if (block_partials<2 * D>(v, partial, counter, tot, blk, nblk) && threadIdx.x == 0) {
     bool all = true;
     for (int c = 0; c < D; ++c) {
       const double rr = tot[c], bb = tot[D + c];
@@ -878,17 +874,16 @@ __global__ __launch_bounds__(CG_T) void k_cg_init(Geo g, const uint8_t *__restri
 
 // p_new = r + beta p_old (recomputed at neighbours), Ap = A p_new, p.Ap
 template <int D, typename T>
-__global__ __launch_bounds__(CG_T) void k_cg_Ap(Geo g, const uint8_t *__restrict__ act,
-                                                 const uint8_t *__restrict__ anc_n, const T *__restrict__ r,
-                                                 const T *__restrict__ pold, T *__restrict__ pnew,
-                                                 T *__restrict__ Ap, double *partial, unsigned *counter,
-                                                 double *scal) {
+__device__ __forceinline__ void cg_Ap_blk(const Geo &g, const uint8_t *__restrict__ act,
+                                          const uint8_t *__restrict__ anc_n, const double *__restrict__ r,
+                                          const double *__restrict__ pold, double *__restrict__ pnew, double *__restrict__ Ap,
+                                          double *partial, unsigned *counter, double *scal, int blk, int nblk) {
   if (scal[S_DONE] != 0.0) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = blk * (int64_t)CG_T + threadIdx.x;
   double v[D];
   for (int k = 0; k < D; ++k) v[k] = 0.0;
-  T beta[D];
-  for (int c = 0; c < D; ++c) beta[c] = T(scal[S_BETA + c]);
+  double beta[D];
+  for (int c = 0; c < D; ++c) beta[c] = double(scal[S_BETA + c]);
   if (i < g.N && act[i]) {
     const C3 cc = coords_of(g, i);
     int64_t nb[2 * D];
@@ -900,8 +895,8 @@ __global__ __launch_bounds__(CG_T) void k_cg_Ap(Geo g, const uint8_t *__restrict
     }
     for (int c = 0; c < D; ++c) {
       const size_t o = (size_t)c * g.S;
-      const T pi = r[o + i] + beta[c] * pold[o + i];
-      T ap = T(deg) * pi;
+      const double pi = r[o + i] + beta[c] * pold[o + i];
+      double ap = double(deg) * pi;
       for (int q = 0; q < 2 * D; ++q)
         if (nb[q] >= 0) ap -= r[o + nb[q]] + beta[c] * pold[o + nb[q]];
       pnew[o + i] = pi;
@@ -910,12 +905,12 @@ __global__ __launch_bounds__(CG_T) void k_cg_Ap(Geo g, const uint8_t *__restrict
     }
   } else if (i < g.N) {
     for (int c = 0; c < D; ++c) {
-      pnew[(size_t)c * g.S + i] = T(0);
-      Ap[(size_t)c * g.S + i] = T(0);
+      pnew[(size_t)c * g.S + i] = double(0);
+      Ap[(size_t)c * g.S + i] = double(0);
     }
   }
-  double tot[8];
-  if (block_partials<D>(v, partial, counter, tot) && threadIdx.x == 0) {
+  double tot[PSTRIDE];
+  if (block_partials<D>(v, partial, counter, tot, blk, nblk) && threadIdx.x == 0) {
     for (int c = 0; c < D; ++c) {
       const bool on = scal[S_ACT + c] != 0.0 && tot[c] > 0.0;
       scal[S_ALPHA + c] = on ? scal[S_RR + c] / tot[c] : 0.0;
@@ -926,26 +921,25 @@ __global__ __launch_bounds__(CG_T) void k_cg_Ap(Geo g, const uint8_t *__restrict
 
 // x += alpha p, r -= alpha Ap, rr_new, beta, convergence
 template <int D, typename T>
-__global__ __launch_bounds__(CG_T) void k_cg_update(Geo g, const uint8_t *__restrict__ act, T *__restrict__ x,
-                                                     T *__restrict__ r, const T *__restrict__ p,
-                                                     const T *__restrict__ Ap, double *partial, unsigned *counter,
-                                                     double *scal) {
+__device__ __forceinline__ void cg_update_blk(const Geo &g, const uint8_t *__restrict__ act, double *__restrict__ x,
+                                              double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ Ap,
+                                              double *partial, unsigned *counter, double *scal, int blk, int nblk) {
   if (scal[S_DONE] != 0.0) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = blk * (int64_t)CG_T + threadIdx.x;
   double v[D];
   for (int k = 0; k < D; ++k) v[k] = 0.0;
   if (i < g.N && act[i]) {
     for (int c = 0; c < D; ++c) {
       const size_t o = (size_t)c * g.S;
-      const T al = T(scal[S_ALPHA + c]);
+      const double al = double(scal[S_ALPHA + c]);
       x[o + i] += al * p[o + i];
-      const T ri = r[o + i] - al * Ap[o + i];
+      const double ri = r[o + i] - al * Ap[o + i];
       r[o + i] = ri;
       v[c] = double(ri) * double(ri);
     }
   }
-  double tot[8];
-  if (block_partials<D>(v, partial, counter, tot) && threadIdx.x == 0) {
+  double tot[PSTRIDE];
+  if (block_partials<D>(v, partial, counter, tot, blk, nblk) && threadIdx.x == 0) {
     bool all = true;
     for (int c = 0; c < D; ++c) {
       if (scal[S_ACT + c] != 0.0) {
@@ -967,9 +961,8 @@ __global__ __launch_bounds__(CG_T) void k_cg_update(Geo g, const uint8_t *__rest
 // theta F^c (Eq. 60): centred differences, one-sided next to a cut, the
 // evolved column kept when neither neighbour is active
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_gradF(Geo g, const uint8_t *__restrict__ act, const T *__restrict__ u,
-                                                const T *__restrict__ Fm, T *__restrict__ Fr, double theta) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gradF_node(const Geo &g, const uint8_t *__restrict__ act, const double *__restrict__ u,
+                                           const T *__restrict__ Fm, T *__restrict__ Fr, double theta, int64_t i) {
   if (i >= g.N || !act[i]) return;
   const C3 cc = coords_of(g, i);
   for (int A = 0; A < D; ++A) {
@@ -977,33 +970,129 @@ __global__ __launch_bounds__(256) void k_gradF(Geo g, const uint8_t *__restrict_
     const bool hp = lp >= 0 && act[lp], hm = lm >= 0 && act[lm];
     for (int c = 0; c < D; ++c) {
       const size_t o = (size_t)c * g.S;
-      const T Fe = Fm[(size_t)(c * D + A) * g.S + i];
-      T Fc;
-      if (hp && hm) Fc = (u[o + lp] - u[o + lm]) / T(2.0 * g.dx);
-      else if (hp) Fc = (u[o + lp] - u[o + i]) / T(g.dx);
-      else if (hm) Fc = (u[o + i] - u[o + lm]) / T(g.dx);
+      const double Fe = Fm[(size_t)(c * D + A) * g.S + i];
+      double Fc;
+      if (hp && hm) Fc = (u[o + lp] - u[o + lm]) / (2.0 * g.dx);
+      else if (hp) Fc = (u[o + lp] - u[o + i]) / g.dx;
+      else if (hm) Fc = (u[o + i] - u[o + lm]) / g.dx;
       else {
-        Fr[(size_t)(c * D + A) * g.S + i] = Fe;
+        Fr[(size_t)(c * D + A) * g.S + i] = T(Fe);
         continue;
       }
-      Fc += (c == A) ? T(1) : T(0);
-      Fr[(size_t)(c * D + A) * g.S + i] = T(1.0 - theta) * Fe + T(theta) * Fc;
+      Fc += (c == A) ? 1.0 : 0.0;
+      Fr[(size_t)(c * D + A) * g.S + i] = T((1.0 - theta) * Fe + theta * Fc);
     }
   }
 }
 
 // u = x, u* = x + dt/2 v  (advance = true) or x - dt/2 v
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_ureset(Geo g, const uint8_t *__restrict__ act, const T *__restrict__ x,
-                                                 const T *__restrict__ V, T *__restrict__ u, T *__restrict__ us,
-                                                 double hdt) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void ureset_node(const Geo &g, const uint8_t *__restrict__ act, const double *__restrict__ x,
+                                            const T *__restrict__ V, T *__restrict__ u, T *__restrict__ us,
+                                            double hdt, int64_t i) {
   if (i >= g.N || !act[i]) return;
   for (int c = 0; c < D; ++c) {
     const size_t o = (size_t)c * g.S;
-    u[o + i] = x[o + i];
-    us[o + i] = x[o + i] + T(hdt) * V[o + i];
+    u[o + i] = T(x[o + i]);
+    us[o + i] = T(x[o + i] + hdt * double(V[o + i]));
   }
+}
+
+// ------------------------------------------------- single-instance kernels
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cut_dirichlet(T *__restrict__ f, Links L, int64_t b0, int64_t b1, BC bc,
+                                                        Geo g, Par p, double th) {
+  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l < b1) cut_dirichlet_link<D, T>(f, L, l, bc, g, p, th);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(128) void k_cut_neumann(T *__restrict__ f, Links L, int64_t b0, int64_t b1, BC bc,
+                                                      Geo g, Par p, double th, const T *__restrict__ u,
+                                                      int *__restrict__ flag, unsigned long long *__restrict__ nfail) {
+  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l < b1) cut_neumann_link<D, T>(f, L, l, bc, g, p, th, u, flag, nfail);
+}
+
+template <int D, typename T>
+__global__ void k_anchor(Links L, int64_t b0, int64_t b1, BC bc, Geo g, double t, const T *__restrict__ Fm,
+                         int *__restrict__ anc_n, double *__restrict__ anc_s) {
+  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l < b1) anchor_link<D, T>(L, l, bc, g, t, Fm, anc_n, anc_s);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cg_rhs(Geo g, const uint8_t *__restrict__ act, const T *__restrict__ Fm,
+                                                 const double *__restrict__ anc_s, double *__restrict__ b) {
+  cg_rhs_node<D, T>(g, act, Fm, anc_s, b, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_init(Geo g, const uint8_t *__restrict__ act,
+                                                   const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
+                                                   const double *__restrict__ x, double *__restrict__ r,
+                                                   double *__restrict__ p, double *partial, unsigned *counter,
+                                                   double *scal, double rtol) {
+  cg_init_blk<D, T>(g, act, anc_n, b, x, r, p, partial, counter, scal, rtol, blockIdx.x, gridDim.x);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_Ap(Geo g, const uint8_t *__restrict__ act,
+                                                 const uint8_t *__restrict__ anc_n, const double *__restrict__ r,
+                                                 const double *__restrict__ pold, double *__restrict__ pnew,
+                                                 double *__restrict__ Ap, double *partial, unsigned *counter,
+                                                 double *scal) {
+  cg_Ap_blk<D, T>(g, act, anc_n, r, pold, pnew, Ap, partial, counter, scal, blockIdx.x, gridDim.x);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_update(Geo g, const uint8_t *__restrict__ act, double *__restrict__ x,
+                                                     double *__restrict__ r, const double *__restrict__ p,
+                                                     const double *__restrict__ Ap, double *partial,
+                                                     unsigned *counter, double *scal) {
+  cg_update_blk<D, T>(g, act, x, r, p, Ap, partial, counter, scal, blockIdx.x, gridDim.x);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gradF(Geo g, const uint8_t *__restrict__ act, const double *__restrict__ u,
+                                                const T *__restrict__ Fm, T *__restrict__ Fr, double theta) {
+  gradF_node<D, T>(g, act, u, Fm, Fr, theta, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_ureset(Geo g, const uint8_t *__restrict__ act, const double *__restrict__ x,
+                                                 const T *__restrict__ V, T *__restrict__ u, T *__restrict__ us,
+                                                 double hdt) {
+  ureset_node<D, T>(g, act, x, V, u, us, hdt, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
+// copies between the displacement buffer (population precision) and the
+// FP64 CG iterate
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_u_to_x(Geo g, const T *__restrict__ u, double *__restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < g.N)
+    for (int c = 0; c < D; ++c) x[(size_t)c * g.S + i] = double(u[(size_t)c * g.S + i]);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_x_to_u(Geo g, const double *__restrict__ x, T *__restrict__ u) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < g.N)
+    for (int c = 0; c < D; ++c) u[(size_t)c * g.S + i] = T(x[(size_t)c * g.S + i]);
+}
+
+// default CG tolerance: 1e-14 for FP64 populations, 1e-8 for FP32 ones (the
+// FP32 deformation gradient carries ~1e-7 relative rounding already)
+double cg_default_rtol(int prec) { return prec ? 1e-14 : 1e-8; }
+
+// default CG iteration cap: 20 sqrt(active nodes) + 100 (CG needs
+// O(sqrt(cond)) = O(grid diameter) iterations on the active-node graph)
+int64_t cg_default_maxit(int64_t nactive) {
+  int64_t r = 1;
+  while (r * r < nactive) ++r;
+  return 20 * r + 100;
 }
 
 // ------------------------------------------------------------ host side
@@ -1098,7 +1187,7 @@ int build_links(tlvlbm_ctx *c, const double *phi, const uint8_t *bid, std::strin
 }
 
 template <int D, typename T> static void cutlinks_t(tlvlbm_ctx *c, double tn) {
-  const double th = tn + 0.5 * c->par.dt;
+  const double th = (double(c->step) + 0.5) * c->par.dt;  // t^n + dt/2, same rounding as the batched path
   for (int b = 0; b < 256; ++b) {
     const int64_t b0 = c->bid_begin[b], b1 = c->bid_end[b];
     if (b1 <= b0) continue;
@@ -1126,19 +1215,22 @@ void launch_cutlinks(tlvlbm_ctx *c, double tn) {
 template <int D, typename T> static int cg_alloc(tlvlbm_ctx *c) {
   CG &w = c->cg;
   if (w.x) return TLVLBM_OK;
-  const size_t plane = (size_t)c->geo.S * sizeof(T);
-  void **vec[] = {&w.x, &w.r, &w.p0, &w.p1, &w.Ap, &w.b, &w.V, &w.anc_s};
+  // CG vectors are FP64 in both builds (a few node planes; FP32 vectors
+  // stall well above the tolerance on large graphs)
+  const size_t plane = (size_t)c->geo.S * sizeof(T), dplane = (size_t)c->geo.S * sizeof(double);
+  void **vec[] = {&w.x, &w.r, &w.p0, &w.p1, &w.Ap, &w.b, &w.anc_s};
   for (void **pp : vec) {
-    HIP_OK(hipMalloc(pp, D * plane));
-    HIP_OK(hipMemsetAsync(*pp, 0, D * plane, c->st));
+    HIP_OK(hipMalloc(pp, D * dplane));
+    HIP_OK(hipMemsetAsync(*pp, 0, D * dplane, c->st));
   }
+  HIP_OK(hipMalloc(&w.V, D * plane));
   HIP_OK(hipMalloc(&w.Fm, D * D * plane));
   HIP_OK(hipMalloc(&w.Fr, D * D * plane));
   HIP_OK(hipMemsetAsync(w.Fr, 0, D * D * plane, c->st));
   HIP_OK(hipMalloc(&w.anc_n, c->geo.S));
   HIP_OK(hipMalloc(&w.anc_i, c->geo.S * sizeof(int)));
   w.nblk = (int)nblk(c->geo.N, CG_T);
-  HIP_OK(hipMalloc(&w.partial, (size_t)w.nblk * 8 * sizeof(double)));
+  HIP_OK(hipMalloc(&w.partial, (size_t)w.nblk * PSTRIDE * sizeof(double)));
   HIP_OK(hipMalloc(&w.scal, S_NSCAL * sizeof(double)));
   HIP_OK(hipMalloc(&w.counter, sizeof(unsigned)));
   HIP_OK(hipMemsetAsync(w.counter, 0, sizeof(unsigned), c->st));
@@ -1161,35 +1253,35 @@ template <int D, typename T> static int cg_solve(tlvlbm_ctx *c, const T *F, doub
   for (int b = 0; b < 256; ++b)
     if (c->bid_end[b] > c->bid_begin[b] && c->bcs[b].type == TLVLBM_BC_DIRICHLET_VELOCITY) any_dir = true;
   const uint8_t *anc_n = nullptr;
-  const T *anc_s = nullptr;
+  const double *anc_s = nullptr;
   if (any_dir) {
     int *ai = w.anc_i;
     HIP_OK(hipMemsetAsync(ai, 0, g.N * sizeof(int), st));
-    HIP_OK(hipMemsetAsync(w.anc_s, 0, D * (size_t)g.S * sizeof(T), st));
+    HIP_OK(hipMemsetAsync(w.anc_s, 0, D * (size_t)g.S * sizeof(double), st));
     for (int b = 0; b < 256; ++b) {
       const int64_t b0 = c->bid_begin[b], b1 = c->bid_end[b];
       if (b1 <= b0 || c->bcs[b].type != TLVLBM_BC_DIRICHLET_VELOCITY) continue;
       hipLaunchKernelGGL((k_anchor<D, T>), nblk(b1 - b0, 128), 128, 0, st, c->L, b0, b1, c->bcs[b], g, t, F, ai,
-                         (T *)w.anc_s);
+                         (double *)w.anc_s);
     }
     hipLaunchKernelGGL((k_anchor_narrow<D, T>), nblk(g.N, 256), 256, 0, st, g, ai, w.anc_n);
     anc_n = w.anc_n;
-    anc_s = (const T *)w.anc_s;
+    anc_s = (const double *)w.anc_s;
   }
-  hipLaunchKernelGGL((k_cg_rhs<D, T>), nblk(g.N, 256), 256, 0, st, g, c->act, F, anc_s, (T *)w.b);
-  const double rtol = c->cg_rtol > 0 ? c->cg_rtol : (c->prec ? 1e-14 : 1e-6);
-  hipLaunchKernelGGL((k_cg_init<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const T *)w.b, (const T *)w.x,
-                     (T *)w.r, (T *)w.p0, w.partial, w.counter, w.scal, rtol);
-  const int64_t maxit = c->cg_maxit > 0 ? c->cg_maxit : 10 * c->nactive + 100;
-  T *pa = (T *)w.p0, *pb = (T *)w.p1;
+  hipLaunchKernelGGL((k_cg_rhs<D, T>), nblk(g.N, 256), 256, 0, st, g, c->act, F, anc_s, (double *)w.b);
+  const double rtol = c->cg_rtol > 0 ? c->cg_rtol : cg_default_rtol(c->prec);
+  hipLaunchKernelGGL((k_cg_init<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
+                     (const double *)w.x, (double *)w.r, (double *)w.p0, w.partial, w.counter, w.scal, rtol);
+  const int64_t maxit = c->cg_maxit > 0 ? c->cg_maxit : cg_default_maxit(c->nactive);
+  double *pa = (double *)w.p0, *pb = (double *)w.p1;
   int64_t it = 0;
   while (it < maxit) {
     const int64_t batch = std::min<int64_t>(32, maxit - it);
     for (int64_t k = 0; k < batch; ++k) {
-      hipLaunchKernelGGL((k_cg_Ap<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const T *)w.r, pa, pb, (T *)w.Ap,
-                         w.partial, w.counter, w.scal);
-      hipLaunchKernelGGL((k_cg_update<D, T>), w.nblk, CG_T, 0, st, g, c->act, (T *)w.x, (T *)w.r, pb,
-                         (const T *)w.Ap, w.partial, w.counter, w.scal);
+      hipLaunchKernelGGL((k_cg_Ap<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)w.r, pa, pb,
+                         (double *)w.Ap, w.partial, w.counter, w.scal);
+      hipLaunchKernelGGL((k_cg_update<D, T>), w.nblk, CG_T, 0, st, g, c->act, (double *)w.x, (double *)w.r, pb,
+                         (const double *)w.Ap, w.partial, w.counter, w.scal);
       std::swap(pa, pb);
     }
     it += batch;
@@ -1211,20 +1303,19 @@ template <int D, typename T> static int projection_t(tlvlbm_ctx *c, bool first, 
   if (st) return st;
   CG &w = c->cg;
   const Geo &g = c->geo;
-  const size_t bytes = D * (size_t)g.S * sizeof(T);
   if (first) {
     launch_pull_moments(c, nullptr, nullptr, nullptr, true);  // v, F, u^n
-    HIP_OK(hipMemcpyAsync(w.x, c->ubuf, bytes, hipMemcpyDeviceToDevice, c->st));
+    hipLaunchKernelGGL((k_u_to_x<D, T>), nblk(g.N, 256), 256, 0, c->st, g, (const T *)c->ubuf, (double *)w.x);
     st = cg_solve<D, T>(c, (const T *)w.Fm, tn);
     if (st) return st;
-    HIP_OK(hipMemcpyAsync(c->ubuf, w.x, bytes, hipMemcpyDeviceToDevice, c->st));
-    hipLaunchKernelGGL((k_gradF<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const T *)w.x, (const T *)w.Fm,
-                       (T *)w.Fr, c->theta);
+    hipLaunchKernelGGL((k_x_to_u<D, T>), nblk(g.N, 256), 256, 0, c->st, g, (const double *)w.x, (T *)c->ubuf);
+    hipLaunchKernelGGL((k_gradF<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const double *)w.x,
+                       (const T *)w.Fm, (T *)w.Fr, c->theta);
   } else {
-    HIP_OK(hipMemcpyAsync(w.x, c->ubuf, bytes, hipMemcpyDeviceToDevice, c->st));
+    hipLaunchKernelGGL((k_u_to_x<D, T>), nblk(g.N, 256), 256, 0, c->st, g, (const T *)c->ubuf, (double *)w.x);
     st = cg_solve<D, T>(c, (const T *)w.Fr, tn);
     if (st) return st;
-    hipLaunchKernelGGL((k_ureset<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const T *)w.x, (const T *)w.V,
+    hipLaunchKernelGGL((k_ureset<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const double *)w.x, (const T *)w.V,
                        (T *)c->ubuf, (T *)c->ustar, 0.5 * c->par.dt);
   }
   HIP_OK(hipGetLastError());
@@ -1234,6 +1325,201 @@ template <int D, typename T> static int projection_t(tlvlbm_ctx *c, bool first, 
 int run_projection(tlvlbm_ctx *c, bool first, double tn) {
   if (c->D == 2) return c->prec ? projection_t<2, double>(c, first, tn) : projection_t<2, float>(c, first, tn);
   return c->prec ? projection_t<3, double>(c, first, tn) : projection_t<3, float>(c, first, tn);
+}
+
+}  // namespace tl
+
+// ===================================================== batched launches
+// Tiles:  node tiles (instance, block of 256 grid nodes), link tiles
+// (segment, first link).  A segment is one boundary identifier of one
+// instance (contiguous link range, one condition).  Every block works on one
+// instance, so CG reductions are segmented by instance with the same
+// deterministic last-block scheme as the single-instance solver.
+
+namespace tl {
+
+template <int D, typename T>
+__global__ __launch_bounds__(64) void k_cut_batch(const Inst *__restrict__ insts, const Seg *__restrict__ segs,
+                                                  const int4 *__restrict__ tiles, const int64_t *__restrict__ step) {
+  const int4 t = tiles[blockIdx.x];
+  const Seg &sg = segs[t.x];
+  const Inst &I = insts[sg.inst];
+  const int64_t l = sg.b0 + t.y + threadIdx.x;
+  if (l >= sg.b1) return;
+  const double th = (double(*step) + 0.5) * I.p.dt;
+  if (sg.type == TLVLBM_BC_DIRICHLET_VELOCITY)
+    cut_dirichlet_link<D, T>((T *)I.fout, I.L, l, sg.bc, I.g, I.p, th);
+  else
+    cut_neumann_link<D, T>((T *)I.fout, I.L, l, sg.bc, I.g, I.p, th, (const T *)I.ubuf, I.flag, I.nfail);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(64) void k_anchor_batch(const Inst *__restrict__ insts, const Seg *__restrict__ segs,
+                                                     const int4 *__restrict__ tiles, const int64_t *__restrict__ step,
+                                                     int useFr) {
+  const int4 t = tiles[blockIdx.x];
+  const Seg &sg = segs[t.x];
+  if (sg.type != TLVLBM_BC_DIRICHLET_VELOCITY) return;
+  const Inst &I = insts[sg.inst];
+  const int64_t l = sg.b0 + t.y + threadIdx.x;
+  if (l >= sg.b1) return;
+  const double tn = double(*step) * I.p.dt;
+  anchor_link<D, T>(I.L, l, sg.bc, I.g, tn, (const T *)(useFr ? I.Fr : I.Fm), I.anc_i, (double *)I.anc_s);
+}
+
+// per-node utilities over node tiles: 0 zero anchors, 1 narrow anchors,
+// 2 x <- u, 3 u <- x
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_node_util_batch(const Inst *__restrict__ insts,
+                                                         const int4 *__restrict__ tiles, int op) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const int64_t i = t.y * (int64_t)256 + threadIdx.x;
+  if (i >= I.g.N) return;
+  if (op == 0) {
+    if (I.anc_i) I.anc_i[i] = 0;
+    for (int c = 0; c < D; ++c) ((double *)I.anc_s)[(size_t)c * I.g.S + i] = 0.0;
+  } else if (op == 1) {
+    if (I.anc_n) I.anc_n[i] = (uint8_t)I.anc_i[i];
+  } else if (op == 2) {
+    for (int c = 0; c < D; ++c) ((double *)I.x)[(size_t)c * I.g.S + i] = double(((const T *)I.ubuf)[(size_t)c * I.g.S + i]);
+  } else {
+    for (int c = 0; c < D; ++c) ((T *)I.ubuf)[(size_t)c * I.g.S + i] = T(((const double *)I.x)[(size_t)c * I.g.S + i]);
+  }
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cg_rhs_batch(const Inst *__restrict__ insts,
+                                                      const int4 *__restrict__ tiles, int useFr, int anchored) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  cg_rhs_node<D, T>(I.g, I.act, (const T *)(useFr ? I.Fr : I.Fm), anchored ? (const double *)I.anc_s : nullptr,
+                    (double *)I.b, t.y * (int64_t)256 + threadIdx.x);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_init_batch(const Inst *__restrict__ insts,
+                                                        const int4 *__restrict__ tiles, int anchored) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  cg_init_blk<D, T>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.b, (const double *)I.x,
+                    (double *)I.r, (double *)I.p0, I.partial, I.counter, I.scal, I.rtol, t.y, I.nblk);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_Ap_batch(const Inst *__restrict__ insts,
+                                                      const int4 *__restrict__ tiles, int pp, int anchored) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const double *pold = (const double *)(pp ? I.p1 : I.p0);
+  double *pnew = (double *)(pp ? I.p0 : I.p1);
+  cg_Ap_blk<D, T>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.r, pold, pnew, (double *)I.Ap,
+                  I.partial, I.counter, I.scal, t.y, I.nblk);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_update_batch(const Inst *__restrict__ insts,
+                                                          const int4 *__restrict__ tiles, int pp) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const double *pnew = (const double *)(pp ? I.p0 : I.p1);
+  cg_update_blk<D, T>(I.g, I.act, (double *)I.x, (double *)I.r, pnew, (const double *)I.Ap, I.partial, I.counter,
+                      I.scal, t.y, I.nblk);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gradF_batch(const Inst *__restrict__ insts, const int4 *__restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  gradF_node<D, T>(I.g, I.act, (const double *)I.x, (const T *)I.Fm, (T *)I.Fr, I.theta,
+                   t.y * (int64_t)256 + threadIdx.x);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_ureset_batch(const Inst *__restrict__ insts,
+                                                      const int4 *__restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  ureset_node<D, T>(I.g, I.act, (const double *)I.x, (const T *)I.V, (T *)I.ubuf, (T *)I.ustar, 0.5 * I.p.dt,
+                    t.y * (int64_t)256 + threadIdx.x);
+}
+
+// end of a batched step: swap every instance's population buffers and
+// advance the device step counter
+__global__ void k_step_end(Inst *__restrict__ insts, int n, int64_t *__restrict__ step) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    void *a = insts[k].fin;
+    insts[k].fin = insts[k].fout;
+    insts[k].fout = a;
+  }
+  if (k == 0) step[0] += 1;
+}
+
+// number of instances whose CG is still running
+__global__ void k_cg_pending(const Inst *__restrict__ insts, int n, int *__restrict__ pending) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && insts[k].scal[S_DONE] == 0.0) atomicAdd(pending, 1);
+}
+
+template <int D, typename T>
+static void batch_kernels_t(BatchOp op, const BatchArgs &a) {
+  hipStream_t st = a.st;
+  switch (op) {
+    case BatchOp::Cut:
+      hipLaunchKernelGGL((k_cut_batch<D, T>), a.nlt, 64, 0, st, a.insts, a.segs, a.ltiles, a.step);
+      break;
+    case BatchOp::Anchor:
+      hipLaunchKernelGGL((k_anchor_batch<D, T>), a.nlt, 64, 0, st, a.insts, a.segs, a.ltiles, a.step, a.flagA);
+      break;
+    case BatchOp::ZeroAnchor:
+    case BatchOp::NarrowAnchor:
+    case BatchOp::XfromU:
+    case BatchOp::UfromX: {
+      const int code = op == BatchOp::ZeroAnchor ? 0 : op == BatchOp::NarrowAnchor ? 1 : op == BatchOp::XfromU ? 2 : 3;
+      hipLaunchKernelGGL((k_node_util_batch<D, T>), a.nct, 256, 0, st, a.insts, a.ctiles, code);
+      break;
+    }
+    case BatchOp::Rhs:
+      hipLaunchKernelGGL((k_cg_rhs_batch<D, T>), a.nct, 256, 0, st, a.insts, a.ctiles, a.flagA, a.flagB);
+      break;
+    case BatchOp::CgInit:
+      hipLaunchKernelGGL((k_cg_init_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagB);
+      break;
+    case BatchOp::CgAp:
+      hipLaunchKernelGGL((k_cg_Ap_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA, a.flagB);
+      break;
+    case BatchOp::CgUpdate:
+      hipLaunchKernelGGL((k_cg_update_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA);
+      break;
+    case BatchOp::GradF:
+      hipLaunchKernelGGL((k_gradF_batch<D, T>), a.nct, 256, 0, st, a.insts, a.ctiles);
+      break;
+    case BatchOp::UReset:
+      hipLaunchKernelGGL((k_ureset_batch<D, T>), a.nct, 256, 0, st, a.insts, a.ctiles);
+      break;
+    case BatchOp::StepEnd:
+      hipLaunchKernelGGL(k_step_end, (a.ninst + 63) / 64, 64, 0, st, a.insts, a.ninst, a.step);
+      break;
+    case BatchOp::Pending:
+      hipLaunchKernelGGL(k_cg_pending, (a.ninst + 63) / 64, 64, 0, st, a.insts, a.ninst, a.pending);
+      break;
+  }
+}
+
+void launch_batch(int D, int prec, BatchOp op, const BatchArgs &a) {
+  if (D == 2) {
+    if (prec) batch_kernels_t<2, double>(op, a);
+    else batch_kernels_t<2, float>(op, a);
+  } else {
+    if (prec) batch_kernels_t<3, double>(op, a);
+    else batch_kernels_t<3, float>(op, a);
+  }
+}
+
+int ensure_cg(tlvlbm_ctx *c) {
+  if (c->D == 2) return c->prec ? cg_alloc<2, double>(c) : cg_alloc<2, float>(c);
+  return c->prec ? cg_alloc<3, double>(c) : cg_alloc<3, float>(c);
 }
 
 }  // namespace tl

@@ -52,16 +52,70 @@ struct BC {
 
 // projection / CG workspace
 struct CG {
-  void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *Ap = nullptr, *b = nullptr;  // [D][S] T
+  void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *Ap = nullptr, *b = nullptr;  // [D][S] FP64
   void *V = nullptr, *Fm = nullptr, *Fr = nullptr;  // v [D][S], F [D2][S], F^r [D2][S]  (T)
   uint8_t *anc_n = nullptr;                         // anchors per node
   int *anc_i = nullptr;                             // anchor counting scratch
-  void *anc_s = nullptr;                            // anchor target sums [D][S] (T)
-  double *partial = nullptr;                        // [nblk][8]
+  void *anc_s = nullptr;                            // anchor target sums [D][S] (FP64)
+  double *partial = nullptr;                        // [nblk][16] block partial sums
   double *scal = nullptr;                           // device scalars
   unsigned *counter = nullptr;
   int nblk = 0;
 };
+
+// Per-instance descriptor of a batched launch (device memory).  fin/fout are
+// swapped on the device at the end of every step, so the ping-pong of every
+// instance needs no upload (and replays correctly from a graph).
+struct Inst {
+  Geo g;
+  Par p;
+  double theta, rtol;
+  void *fin, *fout;
+  uint8_t *act;
+  void *ustar, *ubuf;
+  Links L;
+  // projection workspace
+  void *x, *r, *p0, *p1, *Ap, *b, *V, *Fm, *Fr, *anc_s;
+  uint8_t *anc_n;
+  int *anc_i;
+  double *partial, *scal;
+  unsigned *counter;
+  int nblk;  // node tiles of 256 of this instance (CG reductions)
+  int *flag;
+  unsigned long long *nfail;
+};
+
+// one boundary identifier of one instance: a contiguous link range
+struct Seg {
+  int inst, type;
+  int64_t b0, b1;
+  BC bc;
+};
+
+enum class BatchOp { Cut, Anchor, ZeroAnchor, NarrowAnchor, XfromU, UfromX, Rhs, CgInit, CgAp, CgUpdate, GradF,
+                     UReset, StepEnd, Pending };
+
+struct BatchArgs {
+  hipStream_t st;
+  Inst *insts;
+  int ninst;
+  const Seg *segs;
+  const int4 *ltiles;  // link tiles (segment, first link)
+  int nlt;
+  const int4 *ctiles;  // node tiles (instance, block of 256)
+  int nct;
+  int64_t *step;       // device step counter
+  int *pending;
+  int flagA, flagB;
+};
+
+void launch_batch(int D, int prec, BatchOp op, const BatchArgs &a);
+void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair,
+                       hipStream_t st);
+void launch_moments_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, hipStream_t st);
+int ensure_cg(tlvlbm_ctx *c);
+int64_t cg_default_maxit(int64_t nactive);
+double cg_default_rtol(int prec);
 
 }  // namespace tl
 
@@ -105,6 +159,4 @@ void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar);
 int build_links(tlvlbm_ctx *c, const double *phi_d, const uint8_t *bid_d, std::string &err);
 void launch_cutlinks(tlvlbm_ctx *c, double tn);
 int run_projection(tlvlbm_ctx *c, bool first, double tn);
-void launch_gradF(tlvlbm_ctx *c);
-void launch_ureset(tlvlbm_ctx *c, bool advance);
 }  // namespace tl

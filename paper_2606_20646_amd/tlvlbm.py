@@ -80,8 +80,16 @@ def _load():
     L.tlvlbm_last_error.restype = C.c_char_p
     L.tlvlbm_population_bytes.argtypes = [vp]
     L.tlvlbm_population_bytes.restype = C.c_size_t
+    L.tlvlbm_step_each.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64]
+    L.tlvlbm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
+    L.tlvlbm_batch_step.argtypes = [vp, C.c_int64]
+    L.tlvlbm_batch_set_graph.argtypes = [vp, C.c_int32]
+    L.tlvlbm_batch_destroy.argtypes = [vp]
+    L.tlvlbm_batch_last_error.argtypes = [vp]
+    L.tlvlbm_batch_last_error.restype = C.c_char_p
     for name in ("create", "destroy", "set_levelset", "set_boundary", "set_material", "set_state", "step",
-                 "moments", "get_state", "put_state", "get_links", "stats", "synchronize"):
+                 "moments", "get_state", "put_state", "get_links", "stats", "synchronize", "step_each",
+                 "batch_create", "batch_step", "batch_set_graph", "batch_destroy"):
         getattr(L, "tlvlbm_" + name).restype = C.c_int
     return L
 
@@ -226,3 +234,42 @@ class Solver:
 
     def population_bytes(self):
         return int(lib.tlvlbm_population_bytes(self.h))
+
+
+def _handles(solvers):
+    arr = (C.c_void_p * len(solvers))(*[s.h.value for s in solvers])
+    return arr
+
+
+def step_each(solvers, n):
+    """Advance every solver n steps with per-instance launches (the reference
+    for the batched path)."""
+    st = lib.tlvlbm_step_each(_handles(solvers), len(solvers), int(n))
+    if st:
+        raise TlvlbmError(st, "step_each")
+
+
+class Batch:
+    """One tile-list launch per phase over many solvers (same lattice,
+    precision and non-default stream; see include/tlvlbm.h)."""
+
+    def __init__(self, solvers, use_graph=True):
+        self.solvers = list(solvers)  # keep the contexts alive
+        h = C.c_void_p()
+        st = lib.tlvlbm_batch_create(_handles(self.solvers), len(self.solvers), C.byref(h))
+        if st:
+            raise TlvlbmError(st, "batch_create")
+        self.h = h
+        lib.tlvlbm_batch_set_graph(self.h, int(bool(use_graph)))
+
+    def step(self, n=1):
+        st = lib.tlvlbm_batch_step(self.h, int(n))
+        if st:
+            raise TlvlbmError(st, f"batch_step: {lib.tlvlbm_batch_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.tlvlbm_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close

@@ -1,0 +1,102 @@
+"""Batched launch of many embedded 2D instances (project extension).
+
+Instances follow the batched workload recipe (unit square with random holes,
+clamped left edge, traction on the right edge, traction-free holes and
+faces, per-instance material and lattice speed) at reduced sizes.  The
+batched path must reproduce the per-instance launches of the same kernels
+(FP64: 1e-12 relative; FP32: 1e-6) with and without graph replay, and one
+instance must match the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2606_20646_amd import tlvlbm
+    torch.cuda.set_device(0)
+    return tlvlbm, torch.cuda.Stream()
+
+
+def _solver(T, cfg, precision, stream):
+    s = T.Solver(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
+                 origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"], precision=precision,
+                 stream=stream.cuda_stream)
+    s.set_levelset(cfg["phi"], cfg["bid"])
+    for bid, bc in cfg["bcs"].items():
+        bc = dict(bc)
+        s.set_boundary(bid, bc.pop("type"), **bc)
+    s.set_state(cfg["U0"])
+    return s
+
+
+def _oracle(orc, cfg):
+    o = orc.Sim(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
+                origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"])
+    o.set_levelset(cfg["phi"], cfg["bid"])
+    kinds = {"dirichlet": orc.DIRICHLET, "neumann": orc.NEUMANN}
+    ramps = {"const": orc.RAMP_CONST, "sin2": orc.RAMP_SIN2}
+    for bid, bc in cfg["bcs"].items():
+        bc = dict(bc)
+        t = kinds[bc.pop("type")]
+        if "ramp" in bc:
+            bc["ramp"] = ramps[bc["ramp"]]
+        o.set_bc(bid, t, **bc)
+    o.set_state(cfg["U0"])
+    return o
+
+
+CFGS = [W.config_c4_instance(k, N=n) for k, n in enumerate([40, 64, 48, 33])]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_per_instance(env, precision, tol, graph):
+    T, stream = env
+    _say(f"batch vs per-instance {precision} graph={graph}")
+    A = [_solver(T, c, precision, stream) for c in CFGS]
+    B = [_solver(T, c, precision, stream) for c in CFGS]
+    T.step_each(A, 65)
+    bt = T.Batch(B, use_graph=graph)
+    bt.step(30)
+    bt.step(35)
+    bt.close()
+    for a, b, c in zip(A, B, CFGS):
+        Ua, ua, _ = a.moments()
+        Ub, ub, _ = b.moments()
+        act = c["phi"] <= 0
+        assert np.linalg.norm(Ua[:, act] - Ub[:, act]) <= tol * np.linalg.norm(Ua[:, act])
+        # the displacement comes out of the projection CG (relative residual
+        # 1e-14 / 1e-8); the two paths compile the same device code into
+        # different kernels (FMA contraction differs at round-off), and a CG
+        # stopped at its tolerance turns that into u differences of order
+        # cond * rtol: compare u at the CG's accuracy
+        utol = 1e-10 if precision == "fp64" else 1e-4
+        assert np.linalg.norm(ua[:, act] - ub[:, act]) <= utol * np.linalg.norm(ua[:, act])
+        assert a.stats()["step"] == b.stats()["step"] == 65
+
+
+def test_batched_instance_matches_oracle(env, orc):
+    T, stream = env
+    _say("batched instance vs oracle fp64")
+    B = [_solver(T, c, "fp64", stream) for c in CFGS[:2]]
+    bt = T.Batch(B)
+    bt.step(45)
+    bt.close()
+    for b, c in zip(B, CFGS[:2]):
+        o = _oracle(orc, c)
+        o.step(45)
+        Ub, ub, _ = b.moments()
+        Uo, uo, _ = o.moments()
+        act = c["phi"] <= 0
+        assert np.linalg.norm(Ub[:, act] - Uo[:, act]) <= 1e-11 * np.linalg.norm(Uo[:, act])
+        assert np.linalg.norm(ub[:, act] - uo[:, act]) <= 1e-10 * np.linalg.norm(uo[:, act])

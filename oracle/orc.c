@@ -433,6 +433,9 @@ struct orc_sim {
   orc_link *links;
   orc_bc bc[256];
   int64_t st_newton_it, st_newton_fail, st_cg_it, st_proj;
+  /* initial data of the last orc_set_state (kept for the reverse mode) */
+  double *U0, *u0, *dU0;
+  int64_t init_step;
 };
 
 static void coords(const orc_sim *s, int64_t i, int *c) {
@@ -536,6 +539,9 @@ void orc_destroy(orc_sim *s) {
   free(s->ustar);
   free(s->u);
   free(s->U);
+  free(s->U0);
+  free(s->u0);
+  free(s->dU0);
   free(s->act);
   free(s);
 }
@@ -790,6 +796,44 @@ static void bc_displacement(const orc_bc *b, int D, const double *X, const doubl
  *   dt U0 = B0 - Phi'_A(U0) d_A U0,
  * with the directional derivatives taken through the equilibrium derivative
  * of Eq. 27.  With no gradients supplied the spatial terms vanish. */
+/* populations of one node from U0 and its derivatives dA[A*M + r] */
+static void init_node(const orc_sim *s, double mu, double lam, const double *U, const double *dA,
+                      double *f) {
+  int D = s->D, M = s->M, Q = s->Q;
+  double Ut[MAXM], feq[MAXQ * MAXM], dPhi[MAXD * MAXM];
+  /* B0 = (-gamma v0, 0) : velocity damping source (Sec. 4.1) */
+  for (int r = 0; r < M; ++r) Ut[r] = (r < D) ? -s->gamma * U[r] : 0.0;
+  for (int A = 0; A < D; ++A) {
+    flux_jvp(D, mu, lam, s->rho0, U, dA + A * M, dPhi);
+    for (int r = 0; r < M; ++r) Ut[r] -= dPhi[A * M + r];
+  }
+  orc_feq(D, s->c, mu, lam, s->rho0, U, feq);
+  for (int q = 0; q < Q; ++q) {
+    double Z[MAXM], dfeq[MAXQ * MAXM];
+    for (int r = 0; r < M; ++r) {
+      double s2 = Ut[r];
+      for (int A = 0; A < D; ++A) s2 += s->c * e_of(q, A) * dA[A * M + r];
+      Z[r] = s2;
+    }
+    orc_feq_jvp(D, s->c, mu, lam, s->rho0, U, Z, dfeq);
+    for (int r = 0; r < M; ++r) f[q * M + r] = feq[q * M + r] - 0.5 * s->dt * dfeq[q * M + r];
+  }
+}
+
+static void keep_initial_data(orc_sim *s, const double *U0, const double *u0, const double *dU0) {
+  size_t NM = (size_t)s->N * s->M;
+  free(s->U0);
+  free(s->u0);
+  free(s->dU0);
+  s->U0 = (double *)malloc(sizeof(double) * NM);
+  s->u0 = (double *)calloc((size_t)s->N * s->D, sizeof(double));
+  s->dU0 = (double *)calloc(NM * s->D, sizeof(double));
+  if (!s->U0 || !s->u0 || !s->dU0) return;
+  memcpy(s->U0, U0, sizeof(double) * NM);
+  if (u0) memcpy(s->u0, u0, sizeof(double) * (size_t)s->N * s->D);
+  if (dU0) memcpy(s->dU0, dU0, sizeof(double) * NM * s->D);
+}
+
 int orc_set_state(orc_sim *s, const double *U0, const double *u0, const double *dU0) {
   int D = s->D, M = s->M, Q = s->Q;
   int err = 0;
@@ -806,7 +850,7 @@ int orc_set_state(orc_sim *s, const double *U0, const double *u0, const double *
       for (int a = 0; a < D; ++a) s->ustar[i * D + a] = 0.0;
       continue;
     }
-    double U[MAXM], dA[MAXD][MAXM], Ut[MAXM], feq[MAXQ * MAXM], dPhi[MAXD * MAXM];
+    double U[MAXM], dA[MAXD * MAXM];
     for (int r = 0; r < M; ++r) U[r] = U0[(size_t)r * s->N + i];
     if (!(det_n(D, U + D) > 0.0)) {
       err |= 1;
@@ -814,31 +858,17 @@ int orc_set_state(orc_sim *s, const double *U0, const double *u0, const double *
     }
     for (int A = 0; A < D; ++A)
       for (int r = 0; r < M; ++r)
-        dA[A][r] = dU0 ? dU0[((size_t)A * M + r) * s->N + i] : 0.0;
-    /* B0 = (-gamma v0, 0) : velocity damping source (Sec. 4.1) */
-    for (int r = 0; r < M; ++r) Ut[r] = (r < D) ? -s->gamma * U[r] : 0.0;
-    for (int A = 0; A < D; ++A) {
-      flux_jvp(D, s->mu, s->lam, s->rho0, U, dA[A], dPhi);
-      for (int r = 0; r < M; ++r) Ut[r] -= dPhi[A * M + r];
-    }
-    orc_feq(D, s->c, s->mu, s->lam, s->rho0, U, feq);
-    for (int q = 0; q < Q; ++q) {
-      double Z[MAXM], dfeq[MAXQ * MAXM];
-      for (int r = 0; r < M; ++r) {
-        double s2 = Ut[r];
-        for (int A = 0; A < D; ++A) s2 += s->c * e_of(q, A) * dA[A][r];
-        Z[r] = s2;
-      }
-      orc_feq_jvp(D, s->c, s->mu, s->lam, s->rho0, U, Z, dfeq);
-      for (int r = 0; r < M; ++r) f[q * M + r] = feq[q * M + r] - 0.5 * s->dt * dfeq[q * M + r];
-    }
+        dA[A * M + r] = dU0 ? dU0[((size_t)A * M + r) * s->N + i] : 0.0;
+    init_node(s, s->mu, s->lam, U, dA, f);
     for (int a = 0; a < D; ++a) {
       double u0a = u0 ? u0[(size_t)a * s->N + i] : 0.0;
       s->ustar[i * D + a] = u0a - 0.5 * s->dt * U[a]; /* so that u^0 = u0 (Eq. 34) */
     }
   }
   if (err) return ORC_ERR_J;
+  keep_initial_data(s, U0, u0, dU0);
   s->step = 0;
+  s->init_step = 0;
   s->status = ORC_OK;
   s->have_state = 1;
   return ORC_OK;
@@ -1045,6 +1075,52 @@ static void compat_F(const orc_sim *s, const double *u, const double *Unm, doubl
 
 /* ---- cut links (Secs. 3.2-3.4) ------------------------------------------ */
 
+/* boundary deformation gradient of a Neumann link (Sec. 3.4): tangent images
+ * g_a = t_a + sum_m w_a,m u_m (Eqs. 48-52) from the current displacement,
+ * then the normal image h from the local Newton solve (Eqs. 53-56), and
+ * F_b = h (x) N + sum_a g_a (x) t_a.  Returns 0 (with F_b = I) when the root
+ * is not admissible. */
+static int neumann_Fb(orc_sim *s, const orc_link *L, double th, int count, double *Gt, double *Fb) {
+  int D = s->D, M = s->M;
+  const orc_bc *b = &s->bc[L->bid];
+  double T[3], h0[3], h[3];
+  for (int k = 0; k < 9; ++k) Gt[k] = 0.0;
+  for (int al = 0; al < D - 1; ++al) {
+    double g[3];
+    for (int i = 0; i < D; ++i) {
+      double acc = L->t[al][i];
+      for (int k = 0; k < L->npts; ++k) acc += L->w[al * L->npts + k] * s->u[L->pts[k] * D + i];
+      g[i] = acc;
+    }
+    for (int i = 0; i < D; ++i)
+      for (int B = 0; B < D; ++B) Gt[i * D + B] += g[i] * L->t[al][B];
+  }
+  bc_value(b, D, L->Xb, L->N, th, T);
+  /* initial guess h0 = F_m N_b from the link's active node (reading) */
+  const double *Fm = s->U + (size_t)L->m * M + D;
+  for (int i = 0; i < D; ++i) {
+    double acc = 0.0;
+    for (int B = 0; B < D; ++B) acc += Fm[i * D + B] * L->N[B];
+    h0[i] = acc;
+  }
+  int its = 0;
+  int conv = orc_newton(D, s->mu, s->lam, L->N, Gt, T, h0, 1e-12, h, &its);
+  if (count) {
+#pragma omp atomic
+    s->st_newton_it += its;
+    if (!conv) {
+#pragma omp atomic
+      s->st_newton_fail += 1;
+    }
+  }
+  build_Fb(D, h, L->N, Gt, Fb);
+  if (!(det_n(D, Fb) > 0.0)) {
+    for (int k = 0; k < D * D; ++k) Fb[k] = (k % (D + 1) == 0) ? 1.0 : 0.0;
+    return 0;
+  }
+  return 1;
+}
+
 static int close_link(orc_sim *s, const orc_link *L, double tn) {
   int D = s->D, M = s->M, Q = s->Q;
   const orc_bc *b = &s->bc[L->bid];
@@ -1069,39 +1145,8 @@ static int close_link(orc_sim *s, const orc_link *L, double tn) {
       }
     }
   } else if (b->type == ORC_BC_NEUMANN) {
-    /* tangent images g_a = t_a + sum_m w_a,m u_m (Eqs. 48-52) */
-    double Gt[9] = {0}, T[3], h0[3], h[3], Fb[9], Pb[9];
-    for (int al = 0; al < D - 1; ++al) {
-      double g[3];
-      for (int i = 0; i < D; ++i) {
-        double acc = L->t[al][i];
-        for (int k = 0; k < L->npts; ++k) acc += L->w[al * L->npts + k] * s->u[L->pts[k] * D + i];
-        g[i] = acc;
-      }
-      for (int i = 0; i < D; ++i)
-        for (int B = 0; B < D; ++B) Gt[i * D + B] += g[i] * L->t[al][B];
-    }
-    bc_value(b, D, L->Xb, L->N, th, T);
-    /* initial guess h0 = F_m N_b from the link's active node (reading) */
-    const double *Fm = s->U + (size_t)L->m * M + D;
-    for (int i = 0; i < D; ++i) {
-      double acc = 0.0;
-      for (int B = 0; B < D; ++B) acc += Fm[i * D + B] * L->N[B];
-      h0[i] = acc;
-    }
-    int its = 0;
-    int conv = orc_newton(D, s->mu, s->lam, L->N, Gt, T, h0, 1e-12, h, &its);
-#pragma omp atomic
-    s->st_newton_it += its;
-    if (!conv) {
-#pragma omp atomic
-      s->st_newton_fail += 1;
-    }
-    build_Fb(D, h, L->N, Gt, Fb);
-    if (!(det_n(D, Fb) > 0.0)) {
-      ok = 0;
-      for (int k = 0; k < D * D; ++k) Fb[k] = (k % (D + 1) == 0) ? 1.0 : 0.0;
-    }
+    double Gt[9], Fb[9], Pb[9];
+    ok = neumann_Fb(s, L, th, 1, Gt, Fb);
     orc_piola(D, s->mu, s->lam, Fb, Pb);
     /* Eqs. 46-47: D_N = diag(I_D, -I_D2), S^v_i = -d_A P_b,iA / c,
      * S^F_iB = F_b,iB / D ; the density divides the stress flux */
@@ -1280,6 +1325,7 @@ int orc_put_f(orc_sim *s, const double *fi, const double *ustar, int64_t step) {
     for (int a = 0; a < D; ++a) s->ustar[i * D + a] = ustar ? ustar[(size_t)a * s->N + i] : 0.0;
   }
   s->step = step;
+  s->init_step = -1;
   s->have_state = 1;
   s->status = ORC_OK;
   return ORC_OK;
@@ -1368,4 +1414,566 @@ int orc_num_threads(void) {
 #else
   return 1;
 #endif
+}
+
+/* ======================================================================== */
+/* Reverse mode (project extension: the paper has no adjoint)               */
+/* ======================================================================== */
+/* Gradient of a linear functional of the moments after nsteps steps,
+ *   L = sum_m dLdU(m) . U(m) + dLdu(m) . u(m),
+ * with respect to the material parameters (mu, lambda), the initial velocity
+ * v0 and the initial displacement u0 given to orc_set_state, by the discrete
+ * adjoint of orc_step.  Written to be checked by eye, not to be fast:
+ *  - the transpose of every nonlinear point map is formed column by column
+ *    from its tangent (the JVP applied to unit vectors);
+ *  - the Piola map and the equilibrium are linear in (mu, lambda) and the
+ *    second-order initialisation is quadratic in them, so a central
+ *    difference with unit step gives their parameter derivatives exactly (up
+ *    to rounding); the initialisation is affine in v0, so a unit difference
+ *    gives its v0 derivative;
+ *  - the forward trajectory is stored whole and each step is recomputed by
+ *    the forward code itself;
+ *  - the projection's CG solve is differentiated as the exact solution map
+ *    x = x0 + K^+ (b - K x0) of a warm-started CG on the semi-definite
+ *    normal matrix K (graph Laplacian + anchors): b_bar = K^+ x_bar and
+ *    x0_bar = (I - K K^+) x_bar, the projection onto the constants of the
+ *    connected components without anchors. */
+
+/* out[r] = sum_{q,s} lam[q*M+s] d feq_{q,s} / d U_r */
+static void feq_vjp(const orc_sim *s, double mu, double lam, const double *U, const double *lq,
+                    double *out) {
+  int M = s->M, Q = s->Q;
+  for (int r = 0; r < M; ++r) {
+    double e[MAXM] = {0}, d[MAXQ * MAXM], acc = 0.0;
+    e[r] = 1.0;
+    orc_feq_jvp(s->D, s->c, mu, lam, s->rho0, U, e, d);
+    for (int k = 0; k < Q * M; ++k) acc += lq[k] * d[k];
+    out[r] = acc;
+  }
+}
+
+/* sum_k lq[k] d feq_k / d(mu, lambda), by the exact unit central difference */
+static void feq_dp(const orc_sim *s, const double *U, const double *lq, double *g) {
+  int QM = s->Q * s->M;
+  double a[MAXQ * MAXM], b[MAXQ * MAXM];
+  orc_feq(s->D, s->c, s->mu + 1.0, s->lam, s->rho0, U, a);
+  orc_feq(s->D, s->c, s->mu - 1.0, s->lam, s->rho0, U, b);
+  double gm = 0.0, gl = 0.0;
+  for (int k = 0; k < QM; ++k) gm += lq[k] * 0.5 * (a[k] - b[k]);
+  orc_feq(s->D, s->c, s->mu, s->lam + 1.0, s->rho0, U, a);
+  orc_feq(s->D, s->c, s->mu, s->lam - 1.0, s->rho0, U, b);
+  for (int k = 0; k < QM; ++k) gl += lq[k] * 0.5 * (a[k] - b[k]);
+  g[0] += gm;
+  g[1] += gl;
+}
+
+/* W : dP/dF as a matrix: out_kB = sum_iA W_iA dP_iA/dF_kB */
+static void piola_vjp(int D, double mu, double lam, const double *F, const double *W, double *out) {
+  for (int k = 0; k < D * D; ++k) {
+    double E[9] = {0}, dP[9], acc = 0.0;
+    E[k] = 1.0;
+    orc_piola_jvp(D, mu, lam, F, E, dP);
+    for (int j = 0; j < D * D; ++j) acc += W[j] * dP[j];
+    out[k] = acc;
+  }
+}
+
+/* W : dP/d(mu, lambda), exact unit central difference */
+static void piola_dp(int D, double mu, double lam, const double *F, const double *W, double *g) {
+  double a[9], b[9], gm = 0.0, gl = 0.0;
+  orc_piola(D, mu + 1.0, lam, F, a);
+  orc_piola(D, mu - 1.0, lam, F, b);
+  for (int k = 0; k < D * D; ++k) gm += W[k] * 0.5 * (a[k] - b[k]);
+  orc_piola(D, mu, lam + 1.0, F, a);
+  orc_piola(D, mu, lam - 1.0, F, b);
+  for (int k = 0; k < D * D; ++k) gl += W[k] * 0.5 * (a[k] - b[k]);
+  g[0] += gm;
+  g[1] += gl;
+}
+
+/* K x = graph Laplacian + anchor diagonal (the forward solve's matrix) */
+static void apply_K(const orc_sim *s, const int *anc_n, const double *x, double *y) {
+  graph_lap(s, x, y);
+  if (anc_n)
+    for (int64_t m = 0; m < s->N; ++m) y[m] += anc_n[m] * x[m];
+}
+
+/* y = K^+ rhs for rhs orthogonal to the null space of K (plain CG from 0) */
+static void cg_pinv(const orc_sim *s, const int *anc_n, const double *rhs, double *y) {
+  int64_t N = s->N, nact = 0;
+  double *r = (double *)malloc(sizeof(double) * N), *p = (double *)malloc(sizeof(double) * N);
+  double *Ap = (double *)malloc(sizeof(double) * N);
+  for (int64_t m = 0; m < N; ++m) {
+    nact += s->act[m];
+    y[m] = 0.0;
+    r[m] = s->act[m] ? rhs[m] : 0.0;
+    p[m] = r[m];
+  }
+  double rr = dot_act(s, r, r), thr = 1e-30 * rr;
+  for (int64_t k = 0; k < 10 * nact + 100 && rr > thr; ++k) {
+    apply_K(s, anc_n, p, Ap);
+    double pAp = dot_act(s, p, Ap);
+    if (!(pAp > 0.0)) break;
+    double alpha = rr / pAp;
+    for (int64_t m = 0; m < N; ++m) {
+      y[m] += alpha * p[m];
+      r[m] -= alpha * Ap[m];
+    }
+    double rr2 = dot_act(s, r, r), beta = rr2 / rr;
+    rr = rr2;
+    for (int64_t m = 0; m < N; ++m) p[m] = r[m] + beta * p[m];
+  }
+  free(r); free(p); free(Ap);
+}
+
+/* connected components of the active graph; anch[c] = 1 when a node of
+ * component c carries an anchor */
+static int64_t components(const orc_sim *s, const int *anc_n, int64_t *comp, uint8_t **anch) {
+  int64_t N = s->N, nc = 0;
+  int64_t *stack = (int64_t *)malloc(sizeof(int64_t) * (N ? N : 1));
+  for (int64_t m = 0; m < N; ++m) comp[m] = -1;
+  for (int64_t m0 = 0; m0 < N; ++m0) {
+    if (!s->act[m0] || comp[m0] >= 0) continue;
+    int64_t top = 0;
+    stack[top++] = m0;
+    comp[m0] = nc;
+    while (top) {
+      int64_t m = stack[--top];
+      for (int q = 0; q < s->Q; ++q) {
+        int64_t l = nbr_q(s, m, q, 1);
+        if (l >= 0 && s->act[l] && comp[l] < 0) {
+          comp[l] = nc;
+          stack[top++] = l;
+        }
+      }
+    }
+    ++nc;
+  }
+  free(stack);
+  *anch = (uint8_t *)calloc(nc ? nc : 1, 1);
+  if (anc_n)
+    for (int64_t m = 0; m < N; ++m)
+      if (s->act[m] && anc_n[m]) (*anch)[comp[m]] = 1;
+  return nc;
+}
+
+/* adjoint of u = x0 + K^+ (b - K x0) per component of u ([N][D]):
+ * y = K^+ ubar (the b adjoint), x0bar = ubar - K y */
+static void solve_adj(const orc_sim *s, const int *anc_n, const int64_t *comp, const uint8_t *anch,
+                      int64_t nc, const double *ubar, double *y, double *x0bar) {
+  int D = s->D;
+  int64_t N = s->N;
+  double *rhs = (double *)malloc(sizeof(double) * N), *yc = (double *)malloc(sizeof(double) * N);
+  double *sum = (double *)calloc(nc ? nc : 1, sizeof(double));
+  int64_t *cnt = (int64_t *)calloc(nc ? nc : 1, sizeof(int64_t));
+  for (int64_t m = 0; m < N; ++m)
+    if (s->act[m]) cnt[comp[m]]++;
+  for (int i = 0; i < D; ++i) {
+    for (int64_t c = 0; c < nc; ++c) sum[c] = 0.0;
+    for (int64_t m = 0; m < N; ++m)
+      if (s->act[m]) sum[comp[m]] += ubar[m * D + i];
+    for (int64_t m = 0; m < N; ++m) {
+      double pm = 0.0; /* projection onto the null space of K */
+      if (s->act[m] && !anch[comp[m]]) pm = sum[comp[m]] / (double)cnt[comp[m]];
+      rhs[m] = s->act[m] ? ubar[m * D + i] - pm : 0.0;
+      x0bar[m * D + i] = pm;
+    }
+    cg_pinv(s, anc_n, rhs, yc);
+    for (int64_t m = 0; m < N; ++m) y[m * D + i] = yc[m];
+  }
+  free(rhs); free(yc); free(sum); free(cnt);
+}
+
+/* transpose of proj_rhs: Fbar[m*D*D + i*D + A] += d b / d F_m,iA applied to y */
+static void proj_rhs_T(const orc_sim *s, const double *y, double *Fbar) {
+  int D = s->D;
+  for (int64_t m = 0; m < s->N; ++m) {
+    if (!s->act[m]) continue;
+    for (int A = 0; A < D; ++A) {
+      int64_t lp = nbr_q(s, m, 2 * A, 1), lm = nbr_q(s, m, 2 * A + 1, 1);
+      for (int i = 0; i < D; ++i) {
+        double w = 0.5 * s->dx * y[m * D + i];
+        if (lm >= 0 && s->act[lm]) {
+          Fbar[(size_t)m * D * D + i * D + A] += w;
+          Fbar[(size_t)lm * D * D + i * D + A] += w;
+        }
+        if (lp >= 0 && s->act[lp]) {
+          Fbar[(size_t)m * D * D + i * D + A] -= w;
+          Fbar[(size_t)lp * D * D + i * D + A] -= w;
+        }
+      }
+    }
+  }
+}
+
+/* transpose of the F dependence of proj_anchors' target sums */
+static void anchors_T(const orc_sim *s, const double *y, double *Fbar) {
+  int D = s->D;
+  for (int64_t l = 0; l < s->nl; ++l) {
+    const orc_link *L = &s->links[l];
+    if (s->bc[L->bid].type != ORC_BC_DIRICHLET) continue;
+    int A = L->q / 2, sg = e_of(L->q, A);
+    double off = sg * L->eta * s->dx;
+    for (int i = 0; i < D; ++i) Fbar[(size_t)L->m * D * D + i * D + A] -= off * y[L->m * D + i];
+  }
+}
+
+/* transpose of compat_F: u-part into ubar, kept columns into Fbar */
+static void compat_F_T(const orc_sim *s, const double *Fcbar, double *ubar, double *Fbar) {
+  int D = s->D;
+  for (int64_t m = 0; m < s->N; ++m) {
+    if (!s->act[m]) continue;
+    for (int A = 0; A < D; ++A) {
+      int64_t lp = nbr_q(s, m, 2 * A, 1), lm = nbr_q(s, m, 2 * A + 1, 1);
+      int hp = (lp >= 0 && s->act[lp]), hm = (lm >= 0 && s->act[lm]);
+      for (int i = 0; i < D; ++i) {
+        double g = Fcbar[(size_t)m * D * D + i * D + A];
+        if (hp && hm) {
+          ubar[lp * D + i] += g / (2.0 * s->dx);
+          ubar[lm * D + i] -= g / (2.0 * s->dx);
+        } else if (hp) {
+          ubar[lp * D + i] += g / s->dx;
+          ubar[m * D + i] -= g / s->dx;
+        } else if (hm) {
+          ubar[m * D + i] += g / s->dx;
+          ubar[lm * D + i] -= g / s->dx;
+        } else {
+          Fbar[(size_t)m * D * D + i * D + A] += g;
+        }
+      }
+    }
+  }
+}
+
+/* adjoint of one Neumann link's source S (Eqs. 46-47 with the F_b of
+ * neumann_Fb) given Sbar; accumulates into ubar ([N][D]) and gmat */
+static void neumann_adj(orc_sim *s, const orc_link *L, double th, const double *Sbar, double *ubar,
+                        double *gmat) {
+  int D = s->D;
+  int qo = L->q, A0 = qo / 2, sg = e_of(qo, A0);
+  double d[3] = {0, 0, 0};
+  d[A0] = -sg;
+  double Gt[9], Fb[9], W[9], Fbb[9], hb[3], Qm[9], z[3], Gtb[9];
+  neumann_Fb(s, L, th, 0, Gt, Fb);
+  /* S^v_i = -sum_B d_B P_iB / (rho0 c), S^F_iB = F_b,iB / D */
+  for (int i = 0; i < D; ++i)
+    for (int B = 0; B < D; ++B) W[i * D + B] = -Sbar[i] * d[B] / (s->rho0 * s->c);
+  piola_vjp(D, s->mu, s->lam, Fb, W, Fbb);
+  for (int k = 0; k < D * D; ++k) Fbb[k] += Sbar[D + k] / D;
+  piola_dp(D, s->mu, s->lam, Fb, W, gmat);
+  /* F_b = h (x) N + Gt : h_bar = Fb_bar N, Gt_bar = Fb_bar */
+  for (int i = 0; i < D; ++i) {
+    double acc = 0.0;
+    for (int B = 0; B < D; ++B) acc += Fbb[i * D + B] * L->N[B];
+    hb[i] = acc;
+  }
+  /* implicit function theorem on R(h, Gt, p) = P(F_b) N - T = 0:
+   * z = Q^{-T} h_bar, Gt_bar -= (dR/dGt)^T z, p_bar -= (dR/dp)^T z */
+  for (int k = 0; k < D; ++k) {
+    double dF[9], dP[9];
+    for (int i = 0; i < D; ++i)
+      for (int A = 0; A < D; ++A) dF[i * D + A] = (i == k ? 1.0 : 0.0) * L->N[A];
+    orc_piola_jvp(D, s->mu, s->lam, Fb, dF, dP);
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int A = 0; A < D; ++A) acc += dP[i * D + A] * L->N[A];
+      Qm[k * D + i] = acc; /* row k of Q^T */
+    }
+  }
+  if (!gauss_solve(D, Qm, hb, z)) return;
+  double zN[9], gz[2] = {0.0, 0.0};
+  for (int i = 0; i < D; ++i)
+    for (int A = 0; A < D; ++A) zN[i * D + A] = z[i] * L->N[A];
+  piola_vjp(D, s->mu, s->lam, Fb, zN, Gtb);
+  for (int k = 0; k < D * D; ++k) Gtb[k] = Fbb[k] - Gtb[k];
+  piola_dp(D, s->mu, s->lam, Fb, zN, gz);
+  gmat[0] -= gz[0];
+  gmat[1] -= gz[1];
+  /* Gt = sum_a g_a (x) t_a, g_a = t_a + sum_k w_a,k u_pts(k) */
+  for (int al = 0; al < D - 1; ++al) {
+    double gb[3];
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int B = 0; B < D; ++B) acc += Gtb[i * D + B] * L->t[al][B];
+      gb[i] = acc;
+    }
+    for (int k = 0; k < L->npts; ++k)
+      for (int i = 0; i < D; ++i) ubar[L->pts[k] * D + i] += L->w[al * L->npts + k] * gb[i];
+  }
+}
+
+int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dLdu, double *grad_mat,
+                double *grad_v0, double *grad_u0) {
+  int D = s->D, M = s->M, Q = s->Q;
+  int64_t N = s->N;
+  if (!s->have_state || s->init_step != s->step || !s->U0) return ORC_ERR_ORDER;
+  if (s->status) return s->status;
+  if (nsteps < 0) return ORC_ERR_ARG;
+  int has_neu = 0, has_dir = 0;
+  for (int64_t l = 0; l < s->nl; ++l) {
+    int t = s->bc[s->links[l].bid].type;
+    if (t == ORC_BC_NEUMANN) has_neu = 1;
+    if (t == ORC_BC_DIRICHLET) has_dir = 1;
+  }
+  const size_t nf = (size_t)N * Q * M, nd = (size_t)N * D;
+  const int64_t k0 = s->step;
+  /* forward trajectory X^k = (f^k, u*^k), k = k0 .. k0 + nsteps - 1 */
+  double *trf = (double *)malloc(sizeof(double) * nf * (nsteps ? nsteps : 1));
+  double *trs = (double *)malloc(sizeof(double) * nd * (nsteps ? nsteps : 1));
+  if (!trf || !trs) {
+    free(trf); free(trs);
+    return ORC_ERR_MEM;
+  }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    memcpy(trf + nf * k, s->f, sizeof(double) * nf);
+    memcpy(trs + nd * k, s->ustar, sizeof(double) * nd);
+    int st = orc_step(s, 1);
+    if (st) {
+      free(trf); free(trs);
+      return st;
+    }
+  }
+  double *lf = (double *)calloc(nf, sizeof(double)), *lfs = (double *)calloc(nf, sizeof(double));
+  double *lus = (double *)calloc(nd, sizeof(double)), *ub = (double *)calloc(nd, sizeof(double));
+  double *ubc = (double *)calloc(nd, sizeof(double)), *y = (double *)calloc(nd, sizeof(double));
+  double *x0b = (double *)calloc(nd, sizeof(double));
+  double *Ua = (double *)calloc((size_t)N * M, sizeof(double)), *Ur = (double *)calloc((size_t)N * M, sizeof(double));
+  double *Fcb = (double *)calloc((size_t)N * D * D, sizeof(double));
+  double *Frb = (double *)calloc((size_t)N * D * D, sizeof(double));
+  double *Uab = (double *)calloc((size_t)N * M, sizeof(double));
+  int64_t *comp = (int64_t *)malloc(sizeof(int64_t) * N);
+  uint8_t *anch = NULL;
+  int64_t nc = 0;
+  double gmat[2] = {0.0, 0.0};
+  const double kap = 1.0 + 0.5 * s->gamma * s->dt, sig = s->dt * (2.0 - s->omega) / (4.0 * D);
+  /* seeds: U = R(f) with v = sum f^v / kappa, u = u* + dt/2 v */
+  for (int64_t m = 0; m < N; ++m) {
+    if (!s->act[m]) continue;
+    for (int r = 0; r < M; ++r) {
+      double g = dLdU ? dLdU[(size_t)r * N + m] : 0.0;
+      if (r < D && dLdu) g += 0.5 * s->dt * dLdu[(size_t)r * N + m];
+      if (r < D) g /= kap;
+      for (int q = 0; q < Q; ++q) lf[(size_t)m * Q * M + q * M + r] = g;
+    }
+    for (int a = 0; a < D; ++a) lus[m * D + a] = dLdu ? dLdu[(size_t)a * N + m] : 0.0;
+  }
+  /* anchor counts depend on the links only (the targets are not needed) */
+  int *an = NULL;
+  {
+    double *as = NULL;
+    if (has_dir) proj_anchors(s, s->U, 0.0, &an, &as);
+    free(as);
+    nc = components(s, an, comp, &anch);
+  }
+  int status = ORC_OK;
+  for (int64_t k = nsteps - 1; k >= 0 && !status; --k) {
+    const int64_t stp = k0 + k;
+    const double th = stp * s->dt + 0.5 * s->dt;
+    const int proj = has_neu && s->proj_every > 0 && (stp % s->proj_every == 0);
+    /* recompute step stp */
+    memcpy(s->f, trf + nf * k, sizeof(double) * nf);
+    memcpy(s->ustar, trs + nd * k, sizeof(double) * nd);
+    s->step = stp;
+    recover(s);
+    memcpy(Ua, s->U, sizeof(double) * N * M);
+    memcpy(s->f, trf + nf * k, sizeof(double) * nf);
+    s->step = stp;
+    status = orc_step(s, 1); /* s->fs, s->u (closure input), s->U (U^r) */
+    if (status) break;
+    memcpy(Ur, s->U, sizeof(double) * N * M);
+    /* streaming transpose: fs(m, q) went to f(m + e_q, q) */
+    memset(lfs, 0, sizeof(double) * nf);
+    for (int64_t m = 0; m < N; ++m) {
+      if (!s->act[m]) continue;
+      for (int q = 0; q < Q; ++q) {
+        int64_t l = nbr_q(s, m, q, 1);
+        if (!s->act[l]) continue;
+        for (int r = 0; r < M; ++r)
+          lfs[(size_t)m * Q * M + q * M + r] += lf[(size_t)l * Q * M + q * M + r];
+      }
+    }
+    /* cut-link transpose (Eqs. 42-47) */
+    memset(ubc, 0, sizeof(double) * nd);
+    for (int64_t l = 0; l < s->nl; ++l) {
+      const orc_link *L = &s->links[l];
+      const orc_bc *b = &s->bc[L->bid];
+      int qo = L->q, qi = qo ^ 1;
+      const double *ln = lf + (size_t)L->m * Q * M + qi * M;
+      double Dsign[MAXM], Sb[MAXM], eta = L->eta;
+      for (int r = 0; r < M; ++r) {
+        int vrow = r < D;
+        Dsign[r] = (b->type == ORC_BC_DIRICHLET) ? (vrow ? -1.0 : 1.0) : (vrow ? 1.0 : -1.0);
+      }
+      for (int r = 0; r < M; ++r) {
+        double g = ln[r];
+        if (eta >= 0.5) {
+          lfs[(size_t)L->m * Q * M + qo * M + r] += Dsign[r] / (2.0 * eta) * g;
+          lfs[(size_t)L->m * Q * M + qi * M + r] += (1.0 - 1.0 / (2.0 * eta)) * g;
+          Sb[r] = g / (2.0 * eta);
+        } else {
+          lfs[(size_t)L->m * Q * M + qo * M + r] += Dsign[r] * 2.0 * eta * g;
+          lfs[(size_t)L->mminus * Q * M + qo * M + r] += Dsign[r] * (1.0 - 2.0 * eta) * g;
+          Sb[r] = g;
+        }
+      }
+      if (b->type == ORC_BC_NEUMANN) neumann_adj(s, L, th, Sb, ubc, gmat);
+    }
+    /* collision, displacement history and (on projection steps) repair and
+     * projections, in reverse */
+    memset(Uab, 0, sizeof(double) * N * M);
+    if (!proj) {
+      for (size_t k2 = 0; k2 < nd; ++k2) ub[k2] = ubc[k2] + lus[k2];
+#pragma omp parallel
+      {
+        double gl[2] = {0.0, 0.0};
+#pragma omp for
+        for (int64_t m = 0; m < N; ++m) {
+          if (!s->act[m]) continue;
+          const double *U = Ua + (size_t)m * M, *ls = lfs + (size_t)m * Q * M;
+          double yv[MAXM], *Ub = Uab + (size_t)m * M;
+          feq_vjp(s, s->mu, s->lam, U, ls, yv);
+          feq_dp(s, U, ls, gl);
+          for (int r = 0; r < M; ++r) {
+            double src = 0.0;
+            if (r < D)
+              for (int q = 0; q < Q; ++q) src += -s->gamma * ls[q * M + r];
+            Ub[r] = s->omega * yv[r] + sig * src;
+          }
+          for (int a = 0; a < D; ++a) Ub[a] += 0.5 * s->dt * (lus[m * D + a] + ub[m * D + a]);
+        }
+#pragma omp critical
+        {
+          gmat[0] += s->omega * gl[0];
+          gmat[1] += s->omega * gl[1];
+        }
+      }
+      for (int64_t m = 0; m < N; ++m)
+        for (int q = 0; q < Q; ++q)
+          for (int r = 0; r < M; ++r) {
+            size_t o = (size_t)m * Q * M + q * M + r;
+            lf[o] = s->act[m] ? (1.0 - s->omega) * lfs[o] : 0.0;
+          }
+    } else {
+      /* second solve: u^cc = solve(F^r, warm start u^c); u* = u^cc + dt/2 v */
+      for (size_t k2 = 0; k2 < nd; ++k2) ub[k2] = ubc[k2] + lus[k2];
+      solve_adj(s, an, comp, anch, nc, ub, y, x0b);
+      memset(Frb, 0, sizeof(double) * (size_t)N * D * D);
+      proj_rhs_T(s, y, Frb);
+      if (an) anchors_T(s, y, Frb);
+      memcpy(ubc, x0b, sizeof(double) * nd); /* u^c adjoint so far */
+      memset(Fcb, 0, sizeof(double) * (size_t)N * D * D);
+      double gl[2] = {0.0, 0.0}, gr[2] = {0.0, 0.0};
+      for (int64_t m = 0; m < N; ++m) {
+        if (!s->act[m]) continue;
+        const double *U = Ua + (size_t)m * M, *UR = Ur + (size_t)m * M;
+        double *ls = lfs + (size_t)m * Q * M, *l1 = lf + (size_t)m * Q * M;
+        double yv[MAXM], Urb[MAXM], *Ub = Uab + (size_t)m * M;
+        /* collision with U^r */
+        feq_vjp(s, s->mu, s->lam, UR, ls, yv);
+        feq_dp(s, UR, ls, gl);
+        for (int r = 0; r < M; ++r) {
+          double src = 0.0;
+          if (r < D)
+            for (int q = 0; q < Q; ++q) src += -s->gamma * ls[q * M + r];
+          Urb[r] = s->omega * yv[r] + sig * src;
+        }
+        for (int a = 0; a < D; ++a) Urb[a] += 0.5 * s->dt * lus[m * D + a];
+        for (int k2 = 0; k2 < D * D; ++k2) Urb[D + k2] += Frb[(size_t)m * D * D + k2];
+        for (int k2 = 0; k2 < Q * M; ++k2) l1[k2] = (1.0 - s->omega) * ls[k2];
+        /* repair f' = f + feq(U^r) - feq(U) (Eq. 61) */
+        feq_vjp(s, s->mu, s->lam, UR, l1, yv);
+        for (int r = 0; r < M; ++r) Urb[r] += yv[r];
+        feq_vjp(s, s->mu, s->lam, U, l1, yv);
+        for (int r = 0; r < M; ++r) Ub[r] -= yv[r];
+        feq_dp(s, UR, l1, gr);
+        {
+          double gneg[2] = {0.0, 0.0};
+          feq_dp(s, U, l1, gneg);
+          gr[0] -= gneg[0];
+          gr[1] -= gneg[1];
+        }
+        /* U^r = (v, (1 - theta) F + theta F^c) */
+        for (int a = 0; a < D; ++a) Ub[a] += Urb[a];
+        for (int k2 = 0; k2 < D * D; ++k2) {
+          Ub[D + k2] += (1.0 - s->theta) * Urb[D + k2];
+          Fcb[(size_t)m * D * D + k2] = s->theta * Urb[D + k2];
+        }
+      }
+      gmat[0] += s->omega * gl[0] + gr[0];
+      gmat[1] += s->omega * gl[1] + gr[1];
+      /* F^c = compat(u^c, F) */
+      memset(Frb, 0, sizeof(double) * (size_t)N * D * D);
+      compat_F_T(s, Fcb, ubc, Frb);
+      /* first solve: u^c = solve(F, warm start u) */
+      solve_adj(s, an, comp, anch, nc, ubc, y, x0b);
+      proj_rhs_T(s, y, Frb);
+      if (an) anchors_T(s, y, Frb);
+      for (int64_t m = 0; m < N; ++m) {
+        if (!s->act[m]) continue;
+        for (int k2 = 0; k2 < D * D; ++k2) Uab[(size_t)m * M + D + k2] += Frb[(size_t)m * D * D + k2];
+        for (int a = 0; a < D; ++a) {
+          ub[m * D + a] = x0b[m * D + a];
+          Uab[(size_t)m * M + a] += 0.5 * s->dt * ub[m * D + a];
+        }
+      }
+    }
+    /* recovery transpose: U = R(f), v = sum f^v / kappa; u = u* + dt/2 v */
+    for (int64_t m = 0; m < N; ++m) {
+      if (!s->act[m]) continue;
+      for (int r = 0; r < M; ++r) {
+        double g = Uab[(size_t)m * M + r];
+        if (r < D) g /= kap;
+        for (int q = 0; q < Q; ++q) lf[(size_t)m * Q * M + q * M + r] += g;
+      }
+      for (int a = 0; a < D; ++a) lus[m * D + a] = ub[m * D + a];
+    }
+  }
+  /* initialisation transpose (Eqs. 32-33) and u*^0 = u0 - dt/2 v0 */
+  if (!status) {
+    double gi[2] = {0.0, 0.0};
+    for (int64_t m = 0; m < N; ++m) {
+      if (grad_v0)
+        for (int a = 0; a < D; ++a) grad_v0[(size_t)a * N + m] = 0.0;
+      if (grad_u0)
+        for (int a = 0; a < D; ++a) grad_u0[(size_t)a * N + m] = 0.0;
+      if (!s->act[m]) continue;
+      double U[MAXM], dA[MAXD * MAXM], f0[MAXQ * MAXM], f1[MAXQ * MAXM];
+      const double *l0 = lf + (size_t)m * Q * M;
+      for (int r = 0; r < M; ++r) U[r] = s->U0[(size_t)r * N + m];
+      for (int A = 0; A < D; ++A)
+        for (int r = 0; r < M; ++r) dA[A * M + r] = s->dU0[((size_t)A * M + r) * N + m];
+      init_node(s, s->mu, s->lam, U, dA, f0);
+      for (int a = 0; a < D; ++a) {
+        double acc = 0.0;
+        U[a] += 1.0;
+        init_node(s, s->mu, s->lam, U, dA, f1);
+        U[a] -= 1.0;
+        for (int k2 = 0; k2 < Q * M; ++k2) acc += l0[k2] * (f1[k2] - f0[k2]);
+        if (grad_v0) grad_v0[(size_t)a * N + m] = acc - 0.5 * s->dt * lus[m * D + a];
+        if (grad_u0) grad_u0[(size_t)a * N + m] = lus[m * D + a];
+      }
+      init_node(s, s->mu + 1.0, s->lam, U, dA, f0);
+      init_node(s, s->mu - 1.0, s->lam, U, dA, f1);
+      for (int k2 = 0; k2 < Q * M; ++k2) gi[0] += l0[k2] * 0.5 * (f0[k2] - f1[k2]);
+      init_node(s, s->mu, s->lam + 1.0, U, dA, f0);
+      init_node(s, s->mu, s->lam - 1.0, U, dA, f1);
+      for (int k2 = 0; k2 < Q * M; ++k2) gi[1] += l0[k2] * 0.5 * (f0[k2] - f1[k2]);
+    }
+    gmat[0] += gi[0];
+    gmat[1] += gi[1];
+    if (grad_mat) {
+      grad_mat[0] = gmat[0];
+      grad_mat[1] = gmat[1];
+    }
+  }
+  /* leave the simulation at the end of the trajectory */
+  if (!status && nsteps > 0) {
+    memcpy(s->f, trf + nf * (nsteps - 1), sizeof(double) * nf);
+    memcpy(s->ustar, trs + nd * (nsteps - 1), sizeof(double) * nd);
+    s->step = k0 + nsteps - 1;
+    status = orc_step(s, 1);
+  }
+  free(trf); free(trs); free(lf); free(lfs); free(lus); free(ub); free(ubc); free(y); free(x0b);
+  free(Ua); free(Ur); free(Fcb); free(Frb); free(Uab); free(comp); free(anch); free(an);
+  return status;
 }

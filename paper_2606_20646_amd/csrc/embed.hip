@@ -772,9 +772,9 @@ constexpr int PSTRIDE = 16;
 
 constexpr int CG_T = 256;
 
-// block reduction of up to 2*D doubles, written to partial[blk*8 + k]; the
-// last block to finish sums all partials in block order (deterministic) and
-// hands the totals to fin()
+// block reduction of up to PSTRIDE doubles, written to partial[blk*PSTRIDE + k];
+// the last block to finish sums all partials in a fixed order (deterministic)
+// and returns true with the totals in tot
 template <int K>
 __device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, unsigned *counter, double *tot,
                                                int blk, int nblk) {
@@ -802,11 +802,26 @@ __device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, 
   __syncthreads();
   if (!last) return false;
   __threadfence();
+  // the last block sums the partials in a fixed order: a strided pass over
+  // the blocks per thread, then the wave and block trees
   __shared__ double tsum[PSTRIDE];
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  const volatile double *pv = partial;
+  for (int b = threadIdx.x; b < nblk; b += CG_T)
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += pv[b * PSTRIDE + k];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = acc[k];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) sh[wid][k] = x;
+  }
+  __syncthreads();
   if (threadIdx.x < K) {
     double s = 0.0;
-    const volatile double *pv = partial;
-    for (int b = 0; b < nblk; ++b) s += pv[b * PSTRIDE + threadIdx.x];
+    for (int w = 0; w < CG_T / 64; ++w) s += sh[w][threadIdx.x];
     tsum[threadIdx.x] = s;
   }
   __syncthreads();

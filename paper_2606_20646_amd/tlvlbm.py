@@ -142,7 +142,8 @@ class Solver:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "h", None) and lib is not None:
             lib.tlvlbm_destroy(self.h)
             self.h = None
 
@@ -268,7 +269,7 @@ class Batch:
             raise TlvlbmError(st, f"batch_step: {lib.tlvlbm_batch_last_error(self.h).decode()}")
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.tlvlbm_batch_destroy(self.h)
             self.h = None
 

@@ -4,7 +4,7 @@ configuration after 1000 steps, computed by the FP64 oracle only.
 Output: c3_256_1000_samples.txt with, for 256 seeded random nodes, the node
 index and the 12 state components U = (v, F); and the per-component sums of U
 over all nodes (conservation check).  Run: python tests/golden/make_c3_golden.py
-(about 15 minutes on 8 cores, ~30 GB of memory).
+(about 40 minutes on 8 cores, ~30 GB of memory).
 """
 import os
 import sys

@@ -203,6 +203,36 @@ tlvlbm_status tlvlbm_synchronize(tlvlbm_ctx *ctx);
 /* Text of the last error on this context (never NULL). */
 const char *tlvlbm_last_error(const tlvlbm_ctx *ctx);
 
+/* ---- Reverse mode (project extension, not in the paper) ------------------
+ * Gradient of a linear functional of the moments after n steps,
+ *   L = sum_i sum_r dLdU[r][i] U_r(i) + sum_i sum_k dLdu[k][i] u_k(i)
+ * (U, u exactly as tlvlbm_moments returns them), with respect to the
+ * material parameters and the initial data, by the discrete adjoint of the
+ * step (collision, streaming, cut-link closures including the Neumann
+ * Newton solve, the compatibility projection and the second-order
+ * initialisation; Secs. 2.4, 3.2-3.5).
+ *  - Precondition: the state is the one set by tlvlbm_set_state (no step
+ *    since).  The call advances the context n steps, as tlvlbm_step does,
+ *    and leaves it there.
+ *  - U0, dU0: the arrays given to tlvlbm_set_state ([M][nodes],
+ *    [D][M][nodes] or NULL); the initialisation's transpose needs them.
+ *  - dLdU [M][nodes], dLdu [D][nodes]: FP64, host or device, either may be
+ *    NULL (dLdu requires the displacement quadrature).
+ *  - grad_mat[2] (host): dL/dmu, dL/dlambda.  grad_v0, grad_u0 [D][nodes]
+ *    FP64 host or device, or NULL: dL/dv0 (the velocity rows of U0) and
+ *    dL/du0; F0 and dU0 are held fixed.
+ *  - segment: steps between checkpoints of the stored field (<= 0: about
+ *    sqrt(n x checkpoint size / tape size per step)).  Device memory:
+ *    (n/segment + 1) checkpoints (Q M + D node planes) plus a tape of
+ *    segment x (M [+ D]) node planes; TLVLBM_ERR_OUT_OF_MEMORY if they do
+ *    not fit.  Work: one forward pass, one recomputation and one reverse
+ *    pass (the reverse of a projection step runs two CG solves).
+ *  - Errors: the forward's errors; TLVLBM_ERR_CALL_ORDER without a fresh
+ *    state.  A failure leaves the context in an error state. */
+tlvlbm_status tlvlbm_adjoint(tlvlbm_ctx *ctx, int64_t n, const double *U0, const double *dU0,
+                             const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
+                             double *grad_u0, int64_t segment);
+
 /* ---- Many instances (project extension, not in the paper) ---------------
  * Independent contexts of the same lattice and precision, sharing one
  * non-default stream, at the same step, each with a level set and state.

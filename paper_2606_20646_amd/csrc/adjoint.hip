@@ -1,0 +1,1211 @@
+// Reverse mode of the TL-VLBM update on gfx950 (project extension: the
+// paper has no adjoint).
+//
+// For L = sum dLdU . U + dLdu . u over the moments after n steps, the
+// gradient with respect to (mu, lambda), the initial velocity v0 and the
+// initial displacement u0 is accumulated by the discrete adjoint of the
+// forward kernels, in the forward's own storage: the adjoint of the stored
+// field (post-collision populations plus the populations the cut links
+// deposit at outside nodes) lives in SoA planes.  The forward bulk kernel
+// pulls f*_q(X - e_q); its transpose reads the adjoint at its own node and
+// pushes to X - e_q.  The cut-link transposes run first, in three passes
+// whose write targets are unique per link within a pass.
+//
+// The forward is checkpointed every `seg` steps (full stored field); each
+// segment is recomputed once with a per-step tape of the recovered state
+// (v, F - I), the repaired F of projection steps and the displacement seen
+// by the cut links, then reversed.
+//
+// Transposes of the point maps use the major symmetry of the hyperelastic
+// tangent (C_iAkB = C_kBiA): the adjoint of dF -> dP(F)[dF] is the same
+// map, so the forward tangent routine serves both directions.  The
+// projection's warm-started CG is differentiated as its exact solution map
+// u = u0 + K^+ (b - K u0): b_bar = K^+ u_bar, u0_bar = (I - K K^+) u_bar,
+// the mean of u_bar over each connected component without anchors.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tl_device.hpp"
+#include "tl_internal.hpp"
+#include "tl_math.hpp"
+
+namespace tl {
+namespace {
+
+constexpr int AT = 256;
+
+struct AdjPar {
+  double om, sig, inv_damp, hdt, i2D, i2c, irho, mu, lam, gamma, c, dt, theta, dx;
+};
+
+// node X - e_q (periodic wrap; for an embedded body the neighbour exists)
+__device__ __forceinline__ int64_t minus_eq(const Geo &g, int x, int y, int z, int q) {
+  const int A = q >> 1, s = (q & 1) ? -1 : 1;
+  if (A == 0) {
+    x -= s;
+    x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
+  } else if (A == 1) {
+    y -= s;
+    y = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+  } else {
+    z -= s;
+    z = z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z);
+  }
+  return x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+}
+
+// two block sums added into slot[0..1] (one writer per slot: deterministic)
+__device__ __forceinline__ void block_acc2(double a, double b, double *slot) {
+  __shared__ double sh[AT / 64][2];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  if (lane == 0) {
+    sh[wid][0] = a;
+    sh[wid][1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) {
+      s0 += sh[w][0];
+      s1 += sh[w][1];
+    }
+    slot[0] += s0;
+    slot[1] += s1;
+  }
+}
+
+// Ub += a sum_q feq'_q(U)^T lam_q (equilibrium derivative, Sec. 2.3, Eq. 27)
+// and (gm, gl) += a sum_q lam_q . d feq_q / d(mu, lambda).  With
+// mu_A = sum_q e_qA lam_q:  v_bar_i = S_vi/(2D) - mu_A[F_iA]/(2c),
+// F_bar = S_F/(2D) - dP(F)[W]/(2 c rho0), W_iA = mu_A[v_i].
+template <int D>
+__device__ __forceinline__ void feq_vjp(const double (&lam)[2 * D][D + D * D], const double *F, const AdjPar &p,
+                                        double a, double *Ub, double &gm, double &gl) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  double W[D * D];
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += lam[q][r];
+    Ub[r] += a * p.i2D * s;
+  }
+#pragma unroll
+  for (int A = 0; A < D; ++A) {
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const double m = lam[2 * A][r] - lam[2 * A + 1][r];
+      if (r < D) {
+        W[r * D + A] = m;
+      } else {
+        const int i = (r - D) / D, B = (r - D) % D;
+        if (B == A) Ub[i] -= a * p.i2c * m;
+      }
+    }
+  }
+  double CW[D * D], Pm[D * D], Pl[D * D];
+  piola_tangent<D>(F, W, p.mu, p.lam, CW);
+  piola<D>(F, 1.0, 0.0, Pm);  // dP/dmu = F - F^{-T}
+  piola<D>(F, 0.0, 1.0, Pl);  // dP/dlambda = (J^2 - 1)/2 F^{-T}
+  const double cf = -a * p.i2c * p.irho;
+  double sm = 0.0, sl = 0.0;
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) {
+    Ub[D + k] += cf * CW[k];
+    sm += W[k] * Pm[k];
+    sl += W[k] * Pl[k];
+  }
+  gm += cf * sm;
+  gl += cf * sl;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void load_adj(const T *__restrict__ L, const Geo &g, int64_t node,
+                                         double (&lam)[2 * D][D + D * D]) {
+  constexpr int Q = 2 * D, M = D + D * D;
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int r = 0; r < M; ++r) lam[q][r] = double(L[(size_t)(q * M + r) * g.S + node]);
+}
+
+// push lam_f = (1 - omega) lam_fs + R^T Ub to the pull slots X - e_q
+template <int D, typename T>
+__device__ __forceinline__ void push_adj(T *__restrict__ Lin, const Geo &g, const AdjPar &p, int x, int y, int z,
+                                         const double (&lam)[2 * D][D + D * D], const double *Ub) {
+  constexpr int Q = 2 * D, M = D + D * D;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t dst = minus_eq(g, x, y, z, q);
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+      Lin[(size_t)(q * M + r) * g.S + dst] = T((1.0 - p.om) * lam[q][r] + Ub[r] * (r < D ? p.inv_damp : 1.0));
+  }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void tape_F(const T *__restrict__ tape, const Geo &g, int64_t node, double *F) {
+#pragma unroll
+  for (int k = 0; k < D * D; ++k)
+    F[k] = double(tape[(size_t)(D + k) * g.S + node]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
+}
+
+// ------------------------------------------------------------------ seeds
+// adjoint of the final moments: U = R(f) (v = sum f^v / (1 + gamma dt/2)),
+// u = u* + dt/2 v
+template <int D, typename T, bool MASK, bool TRACK>
+__global__ __launch_bounds__(AT) void k_adj_seed(T *__restrict__ Lin, Geo g, AdjPar p,
+                                                 const uint8_t *__restrict__ act, const double *__restrict__ dLdU,
+                                                 const double *__restrict__ dLdu, double *__restrict__ lus) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, row = blockIdx.y;
+  if (x >= g.nx) return;
+  const int64_t node = x + (int64_t)g.nx * row;
+  if (MASK && !act[node]) return;
+  const int y = row % g.ny, z = row / g.ny;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    double v = dLdU ? dLdU[(size_t)r * g.N + node] : 0.0;
+    if (r < D) {
+      if (TRACK && dLdu) v += p.hdt * dLdu[(size_t)r * g.N + node];
+      v *= p.inv_damp;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) Lin[(size_t)(q * M + r) * g.S + minus_eq(g, x, y, z, q)] = T(v);
+  }
+  if (TRACK)
+#pragma unroll
+    for (int i = 0; i < D; ++i) lus[(size_t)i * g.S + node] = dLdu ? dLdu[(size_t)i * g.N + node] : 0.0;
+}
+
+// ------------------------------------------------- bulk transpose (plain)
+// collision (Eq. 29) with the damping source, recovery (Eq. 28) and the
+// displacement history (Eq. 34): u = u* + dt/2 v, u*' = u + dt/2 v.
+template <int D, typename T, bool MASK, bool TRACK>
+__global__ __launch_bounds__(AT) void k_adj_bulk(const T *__restrict__ Lout, T *__restrict__ Lin, Geo g, AdjPar p,
+                                                 const uint8_t *__restrict__ act, const T *__restrict__ tape,
+                                                 const double *__restrict__ ubc, double *__restrict__ lus,
+                                                 double *__restrict__ gblk) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, row = blockIdx.y;
+  const int64_t node = x + (int64_t)g.nx * row;
+  double gm = 0.0, gl = 0.0;
+  if (x < g.nx && (!MASK || act[node])) {
+    const int y = row % g.ny, z = row / g.ny;
+    double lam[Q][M], F[D * D], Ub[M];
+    load_adj<D, T>(Lout, g, node, lam);
+    tape_F<D, T>(tape, g, node, F);
+#pragma unroll
+    for (int r = 0; r < M; ++r) Ub[r] = 0.0;
+    feq_vjp<D>(lam, F, p, p.om, Ub, gm, gl);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s += lam[q][i];
+      Ub[i] -= p.sig * p.gamma * s;
+    }
+    if (TRACK) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const double lu = lus[(size_t)i * g.S + node];
+        const double ub = ubc[(size_t)i * g.S + node] + lu;
+        Ub[i] += p.hdt * (lu + ub);
+        lus[(size_t)i * g.S + node] = ub;
+      }
+    }
+    push_adj<D, T>(Lin, g, p, x, y, z, lam, Ub);
+  }
+  block_acc2(gm, gl, gblk + 2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// ------------------------------------------- bulk transpose (projection)
+// phase 1: collision with U^r and the repair f += feq(U^r) - feq(U) (Eq. 61)
+// in reverse; U^r = (v, (1 - theta) F + theta F^c) (Eq. 60).  Leaves the
+// partial adjoint of the recovered state in UaB and that of F^c in Fcb.
+template <int D, typename T>
+__global__ __launch_bounds__(AT) void k_adj_rep1(const T *__restrict__ Lout, Geo g, AdjPar p,
+                                                 const uint8_t *__restrict__ act, const T *__restrict__ tape,
+                                                 const T *__restrict__ tapeFr, const double *__restrict__ Frb,
+                                                 const double *__restrict__ lus, double *__restrict__ UaB,
+                                                 double *__restrict__ Fcb, double *__restrict__ gblk) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, row = blockIdx.y;
+  const int64_t node = x + (int64_t)g.nx * row;
+  double gm = 0.0, gl = 0.0;
+  if (x < g.nx && act[node]) {
+    double lam[Q][M], Fa[D * D], Fr[D * D], Ur[M], Ua[M];
+    load_adj<D, T>(Lout, g, node, lam);
+    tape_F<D, T>(tape, g, node, Fa);
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Fr[k] = double(tapeFr[(size_t)k * g.S + node]);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      Ur[r] = 0.0;
+      Ua[r] = 0.0;
+    }
+    // omega feq'(U^r) (collision) + (1 - omega) feq'(U^r) (repair)
+    feq_vjp<D>(lam, Fr, p, 1.0, Ur, gm, gl);
+    feq_vjp<D>(lam, Fa, p, -(1.0 - p.om), Ua, gm, gl);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s += lam[q][i];
+      Ur[i] += -p.sig * p.gamma * s + p.hdt * lus[(size_t)i * g.S + node];
+    }
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Ur[D + k] += Frb[(size_t)k * g.S + node];
+#pragma unroll
+    for (int i = 0; i < D; ++i) UaB[(size_t)i * g.S + node] = Ua[i] + Ur[i];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+      UaB[(size_t)(D + k) * g.S + node] = Ua[D + k] + (1.0 - p.theta) * Ur[D + k];
+      Fcb[(size_t)k * g.S + node] = p.theta * Ur[D + k];
+    }
+  }
+  block_acc2(gm, gl, gblk + 2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// phase 2: the recovered state's adjoint is complete (kept columns, first
+// projection, u = u* + dt/2 v): push lam_f
+template <int D, typename T>
+__global__ __launch_bounds__(AT) void k_adj_rep2(const T *__restrict__ Lout, T *__restrict__ Lin, Geo g, AdjPar p,
+                                                 const uint8_t *__restrict__ act, const double *__restrict__ UaB,
+                                                 const double *__restrict__ Fext, const double *__restrict__ x0b,
+                                                 double *__restrict__ lus) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, row = blockIdx.y;
+  if (x >= g.nx) return;
+  const int64_t node = x + (int64_t)g.nx * row;
+  if (!act[node]) return;
+  const int y = row % g.ny, z = row / g.ny;
+  double lam[Q][M], Ub[M];
+  load_adj<D, T>(Lout, g, node, lam);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double ub = x0b[(size_t)i * g.S + node];
+    Ub[i] = UaB[(size_t)i * g.S + node] + p.hdt * ub;
+    lus[(size_t)i * g.S + node] = ub;
+  }
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) Ub[D + k] = UaB[(size_t)(D + k) * g.S + node] + Fext[(size_t)k * g.S + node];
+  push_adj<D, T>(Lin, g, p, x, y, z, lam, Ub);
+}
+
+// ------------------------------------------------- cut-link transposes
+// Interpolated closure (Eqs. 42-43): for eta >= 1/2
+//   f_in = (Dg f*_out(m) + S)/(2 eta) + (1 - 1/(2 eta)) f*_in(m),
+// else f_in = Dg (2 eta f*_out(m) + (1 - 2 eta) f*_out(m^-)) + S.  The adjoint
+// of the deposited value sits in the pull slot of the outside node.
+// PASS 1 sets lam(m, q_out) (no pull reads it) and differentiates the
+// Neumann source; PASS 2 adds to lam(m, q_in), PASS 3 to lam(m^-, q_out).
+template <int D, typename T, int PASS, bool NEU>
+__global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, int64_t b0, int64_t b1, BC bc, Geo g,
+                                                 Par par, double th, const T *__restrict__ tapeU,
+                                                 const T *__restrict__ tapeFr, const T *__restrict__ tapeu,
+                                                 double *__restrict__ gbar, double *__restrict__ glink) {
+  constexpr int M = D + D * D;
+  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= b1) return;
+  const int64_t m = L.node[l], mm = L.mminus[l], o = L.out[l];
+  const int qo = L.q[l], qi = qo ^ 1, A = qo / 2;
+  const double sg = (qo & 1) ? -1.0 : 1.0;
+  const double eta = L.eta[l];
+  double lg[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) lg[r] = double(Lb[(size_t)(qi * M + r) * g.S + o]);
+  if constexpr (PASS == 2) {
+    if (eta >= 0.5)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        T *t = Lb + (size_t)(qi * M + r) * g.S + m;
+        *t = T(double(*t) + (1.0 - 0.5 / eta) * lg[r]);
+      }
+    return;
+  }
+  if constexpr (PASS == 3) {
+    if (eta < 0.5 && mm != m)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        const double Dg = NEU ? (r < D ? 1.0 : -1.0) : (r < D ? -1.0 : 1.0);
+        T *t = Lb + (size_t)(qo * M + r) * g.S + mm;
+        *t = T(double(*t) + Dg * (1.0 - 2.0 * eta) * lg[r]);
+      }
+    return;
+  }
+  // PASS 1
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    const double Dg = NEU ? (r < D ? 1.0 : -1.0) : (r < D ? -1.0 : 1.0);
+    double v = (eta >= 0.5) ? Dg * 0.5 / eta * lg[r] : Dg * 2.0 * eta * lg[r];
+    if (eta < 0.5 && mm == m) v += Dg * (1.0 - 2.0 * eta) * lg[r];
+    Lb[(size_t)(qo * M + r) * g.S + m] = T(v);
+  }
+  if constexpr (NEU) {
+    // forward state of the link: tangent images from the LSQ weights applied
+    // to u (Eqs. 48-52), the Newton root h (Eqs. 53-56), F_b = h (x) N + Gt
+    double N[3], Xb[3], Tb[3], Gt[D * D];
+    for (int a = 0; a < 3; ++a) {
+      N[a] = L.Nb[l * 3 + a];
+      Xb[a] = L.Xb[l * 3 + a];
+    }
+    for (int k = 0; k < D * D; ++k) Gt[k] = 0.0;
+    const int np = L.npts[l];
+    const int32_t *idx = L.sidx + l * L.kmax;
+    const double *w = L.sw + l * 2 * L.kmax;
+    for (int al = 0; al < D - 1; ++al) {
+      double gv[D];
+      for (int i = 0; i < D; ++i) gv[i] = L.tang[l * 6 + al * 3 + i];
+      for (int k = 0; k < np; ++k) {
+        const double wk = w[al * L.kmax + k];
+        for (int i = 0; i < D; ++i) gv[i] += wk * double(tapeu[(size_t)i * g.S + idx[k]]);
+      }
+      for (int i = 0; i < D; ++i)
+        for (int B = 0; B < D; ++B) Gt[i * D + B] += gv[i] * L.tang[l * 6 + al * 3 + B];
+    }
+    double s, ds;
+    ramp_eval(bc.ramp, bc.Tr, th, s, ds);
+    bc_base<D>(bc, Xb, N, Tb);
+    for (int i = 0; i < D; ++i) Tb[i] *= s;
+    double h[D], Fm[D * D];
+    if (tapeFr)
+      for (int k = 0; k < D * D; ++k) Fm[k] = double(tapeFr[(size_t)k * g.S + m]);
+    else
+      tape_F<D, T>(tapeU, g, m, Fm);
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int B = 0; B < D; ++B) acc += Fm[i * D + B] * N[B];
+      h[i] = acc;
+    }
+    newton_h<D>(N, Gt, Tb, par.mu, par.lam, 1e-12, h);
+    double Fb[D * D];
+    for (int i = 0; i < D; ++i)
+      for (int B = 0; B < D; ++B) Fb[i * D + B] = h[i] * N[B] + Gt[i * D + B];
+    // source adjoint: S^v_i = sg P_b,iA / (rho0 c), S^F = (F_b - I)/D (Eqs. 46-47)
+    const double cS = (eta >= 0.5) ? 0.5 / eta : 1.0;
+    double W[D * D], CW[D * D], Fbb[D * D], Pm[D * D], Pl[D * D];
+    for (int i = 0; i < D; ++i)
+      for (int B = 0; B < D; ++B) W[i * D + B] = (B == A) ? sg * cS * lg[i] * par.inv_rho0 / par.c : 0.0;
+    piola_tangent<D>(Fb, W, par.mu, par.lam, CW);
+    piola<D>(Fb, 1.0, 0.0, Pm);
+    piola<D>(Fb, 0.0, 1.0, Pl);
+    double gm = 0.0, gl = 0.0;
+    for (int k = 0; k < D * D; ++k) {
+      Fbb[k] = CW[k] + cS * lg[D + k] / D;
+      gm += W[k] * Pm[k];
+      gl += W[k] * Pl[k];
+    }
+    // implicit function theorem on R(h) = P(F_b) N - T = 0: z = Q^{-T} h_bar
+    // (Q the acoustic tensor, Eq. 19), Gt_bar = F_b_bar - dP[z (x) N],
+    // p_bar -= dP/dp : (z (x) N)
+    double hb[D], Qt[D * D], z[D];
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int B = 0; B < D; ++B) acc += Fbb[i * D + B] * N[B];
+      hb[i] = acc;
+    }
+    for (int k = 0; k < D; ++k) {
+      double dF[D * D], dP[D * D];
+      for (int i = 0; i < D; ++i)
+        for (int a = 0; a < D; ++a) dF[i * D + a] = (i == k) ? N[a] : 0.0;
+      piola_tangent<D>(Fb, dF, par.mu, par.lam, dP);
+      for (int i = 0; i < D; ++i) {
+        double acc = 0.0;
+        for (int a = 0; a < D; ++a) acc += dP[i * D + a] * N[a];
+        Qt[k * D + i] = acc;  // (Q^T)_ki = Q_ik
+      }
+    }
+    if (!solve_small(D, Qt, hb, z))
+      for (int i = 0; i < D; ++i) z[i] = 0.0;
+    double zN[D * D], CzN[D * D];
+    for (int i = 0; i < D; ++i)
+      for (int a = 0; a < D; ++a) zN[i * D + a] = z[i] * N[a];
+    piola_tangent<D>(Fb, zN, par.mu, par.lam, CzN);
+    for (int k = 0; k < D * D; ++k) {
+      gm -= zN[k] * Pm[k];
+      gl -= zN[k] * Pl[k];
+    }
+    for (int al = 0; al < D - 1; ++al)
+      for (int i = 0; i < D; ++i) {
+        double acc = 0.0;
+        for (int B = 0; B < D; ++B) acc += (Fbb[i * D + B] - CzN[i * D + B]) * L.tang[l * 6 + al * 3 + B];
+        gbar[l * 6 + al * 3 + i] = acc;
+      }
+    glink[2 * l] += gm;
+    glink[2 * l + 1] += gl;
+  }
+}
+
+// u_bar at the LSQ stencil nodes: sum over (link, point) entries of
+// w_alpha,k g_bar_alpha (sorted entries: deterministic)
+template <int D>
+__global__ __launch_bounds__(AT) void k_adj_ugather(int64_t ns, const int64_t *__restrict__ sn,
+                                                    const int64_t *__restrict__ so, const int32_t *__restrict__ el,
+                                                    const int32_t *__restrict__ ek, Links L, Geo g,
+                                                    const double *__restrict__ gbar, double *__restrict__ ubc) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  double acc[D];
+  for (int i = 0; i < D; ++i) acc[i] = 0.0;
+  for (int64_t e = so[t]; e < so[t + 1]; ++e) {
+    const int64_t l = el[e];
+    const int k = ek[e];
+    for (int al = 0; al < D - 1; ++al) {
+      const double wk = L.sw[l * 2 * L.kmax + al * L.kmax + k];
+      for (int i = 0; i < D; ++i) acc[i] += wk * gbar[l * 6 + al * 3 + i];
+    }
+  }
+  for (int i = 0; i < D; ++i) ubc[(size_t)i * g.S + sn[t]] = acc[i];
+}
+
+// --------------------------------------------------- projection transposes
+// per-tile sums of u_bar over the nodes of components without anchors
+template <int D>
+__global__ __launch_bounds__(AT) void k_pi_tiles(const int32_t *__restrict__ cn, Geo g, const double *__restrict__ ua,
+                                                 const double *__restrict__ ub, double *__restrict__ tpart) {
+  __shared__ double sh[AT / 64][D];
+  const int32_t j = cn[(size_t)blockIdx.x * AT + threadIdx.x];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = 0; i < D; ++i) {
+    double v = 0.0;
+    if (j >= 0) v = ua[(size_t)i * g.S + j] + (ub ? ub[(size_t)i * g.S + j] : 0.0);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[wid][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < D) {
+    double s = 0.0;
+    for (int w = 0; w < AT / 64; ++w) s += sh[w][threadIdx.x];
+    tpart[(size_t)blockIdx.x * D + threadIdx.x] = s;
+  }
+}
+
+// component means from the tile sums (one block per component)
+template <int D>
+__global__ __launch_bounds__(AT) void k_pi_comp(const int64_t *__restrict__ ct, const int64_t *__restrict__ cnt,
+                                                const double *__restrict__ tpart, double *__restrict__ mean) {
+  __shared__ double sh[AT / 64][D];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = 0; i < D; ++i) {
+    double v = 0.0;
+    for (int64_t t = ct[c] + threadIdx.x; t < ct[c + 1]; t += AT) v += tpart[t * D + i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[wid][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < D) {
+    double s = 0.0;
+    for (int w = 0; w < AT / 64; ++w) s += sh[w][threadIdx.x];
+    mean[(size_t)c * D + threadIdx.x] = s / double(cnt[c]);
+  }
+}
+
+// x0_bar = projection of u_bar onto the null space of K, CG right-hand side
+// b = u_bar - x0_bar, start x = 0
+template <int D>
+__global__ __launch_bounds__(AT) void k_pi_apply(Geo g, const uint8_t *__restrict__ act,
+                                                 const int32_t *__restrict__ comp, const double *__restrict__ mean,
+                                                 const double *__restrict__ ua, const double *__restrict__ ub,
+                                                 double *__restrict__ x0b, double *__restrict__ b,
+                                                 double *__restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  const bool a = act[i];
+  const int32_t c = a ? comp[i] : -1;
+  for (int k = 0; k < D; ++k) {
+    const size_t o = (size_t)k * g.S + i;
+    const double u = a ? ua[o] + (ub ? ub[o] : 0.0) : 0.0;
+    const double pm = c >= 0 ? mean[(size_t)c * D + k] : 0.0;
+    x0b[o] = pm;
+    b[o] = a ? u - pm : 0.0;
+    x[o] = 0.0;
+  }
+}
+
+// transpose of the edge least-squares right-hand side (Eq. 57):
+// F_bar_iA(m) (+)= dx/2 ([m-e_A act] (y_m - y_{m-e_A}) + [m+e_A act] (y_{m+e_A} - y_m))
+template <int D, bool ADD>
+__global__ __launch_bounds__(AT) void k_adj_rhsT(Geo g, const uint8_t *__restrict__ act, const double *__restrict__ y,
+                                                 double *__restrict__ Fb) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N || !act[i]) return;
+  const C3 cc = coords_of(g, i);
+  const double hdx = 0.5 * g.dx;
+  for (int A = 0; A < D; ++A) {
+    const int64_t lp = node_dir(g, cc, 2 * A, 1), lm = node_dir(g, cc, 2 * A + 1, 1);
+    const bool hp = lp >= 0 && act[lp], hm = lm >= 0 && act[lm];
+    for (int c = 0; c < D; ++c) {
+      const size_t o = (size_t)c * g.S;
+      double v = 0.0;
+      if (hm) v += y[o + i] - y[o + lm];
+      if (hp) v += y[o + lp] - y[o + i];
+      double *t = Fb + (size_t)(c * D + A) * g.S + i;
+      *t = ADD ? *t + hdx * v : hdx * v;
+    }
+  }
+}
+
+// transpose of the anchor targets u_D - (F_m - I)(X_b - X_m): F_bar_iA(m) -= off y_i(m)
+template <int D>
+__global__ __launch_bounds__(64) void k_adj_anchT(Links L, int64_t b0, int64_t b1, Geo g, const double *__restrict__ y,
+                                                  double *__restrict__ Fb) {
+  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= b1) return;
+  const int64_t m = L.node[l];
+  const int q = L.q[l], A = q / 2;
+  const double off = ((q & 1) ? -1.0 : 1.0) * L.eta[l] * g.dx;
+  for (int i = 0; i < D; ++i) atomicAdd(&Fb[(size_t)(i * D + A) * g.S + m], -off * y[(size_t)i * g.S + m]);
+}
+
+// transpose of F^c = I + grad_dx u^c (Eq. 59; centred, one-sided next to a
+// cut, evolved column kept when neither neighbour is active), gathered at
+// node j; kept columns pass to Fext; ucb = x0b + grad^T Fcb
+template <int D>
+__global__ __launch_bounds__(AT) void k_adj_compatT(Geo g, const uint8_t *__restrict__ act,
+                                                    const double *__restrict__ Fcb, const double *__restrict__ x0b,
+                                                    double *__restrict__ ucb, double *__restrict__ Fext) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= g.N || !act[j]) return;
+  const C3 cc = coords_of(g, j);
+  const double idx = 1.0 / g.dx;
+  double acc[D];
+  for (int i = 0; i < D; ++i) acc[i] = x0b[(size_t)i * g.S + j];
+  for (int A = 0; A < D; ++A) {
+    const int64_t lp = node_dir(g, cc, 2 * A, 1), lm = node_dir(g, cc, 2 * A + 1, 1);
+    const bool hp = lp >= 0 && act[lp], hm = lm >= 0 && act[lm];
+    double clm = 0.0, clp = 0.0;  // j as the +A neighbour of lm, as the -A neighbour of lp
+    if (hm) {
+      const int64_t l2 = node_dir(g, coords_of(g, lm), 2 * A + 1, 1);
+      clm = (l2 >= 0 && act[l2]) ? 0.5 * idx : idx;
+    }
+    if (hp) {
+      const int64_t l2 = node_dir(g, coords_of(g, lp), 2 * A, 1);
+      clp = (l2 >= 0 && act[l2]) ? -0.5 * idx : -idx;
+    }
+    const double cj = (hp && !hm) ? -idx : ((hm && !hp) ? idx : 0.0);
+    for (int i = 0; i < D; ++i) {
+      const size_t o = (size_t)(i * D + A) * g.S;
+      if (hm) acc[i] += clm * Fcb[o + lm];
+      if (hp) acc[i] += clp * Fcb[o + lp];
+      acc[i] += cj * Fcb[o + j];
+      Fext[o + j] = (!hp && !hm) ? Fcb[o + j] : 0.0;
+    }
+  }
+  for (int i = 0; i < D; ++i) ucb[(size_t)i * g.S + j] = acc[i];
+}
+
+// --------------------------------------------- initialisation transpose
+// f^0_q = feq(U0) - dt/2 feq'(U0)[Z_q], Z_q = U0_t + c e_qA d_A U0,
+// U0_t = B0 - Phi'_A(U0) d_A U0 (Sec. 2.4, Eqs. 32-33).  f^0 is affine in
+// v0 with slope (1 + gamma dt/2) feq'(U0); its (mu, lambda) derivative has
+// three parts: feq, the equilibrium derivative and U0_t.
+template <int D, typename T, bool MASK, bool TRACK>
+__global__ __launch_bounds__(AT) void k_adj_init(const T *__restrict__ Lin, Geo g, AdjPar p,
+                                                 const uint8_t *__restrict__ act, const double *__restrict__ U0,
+                                                 const double *__restrict__ dU0, const double *__restrict__ lus,
+                                                 double *__restrict__ gv0, double *__restrict__ gu0,
+                                                 double *__restrict__ gblk) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, row = blockIdx.y;
+  const int64_t node = x + (int64_t)g.nx * row;
+  double gm = 0.0, gl = 0.0;
+  if (x < g.nx) {
+    if (!MASK || act[node]) {
+      const int y = row % g.ny, z = row / g.ny;
+      double lam[Q][M], F[D * D], G[M];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int64_t src = minus_eq(g, x, y, z, q);
+#pragma unroll
+        for (int r = 0; r < M; ++r) lam[q][r] = double(Lin[(size_t)(q * M + r) * g.S + src]);
+      }
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) F[k] = U0[(size_t)(D + k) * g.N + node];
+#pragma unroll
+      for (int r = 0; r < M; ++r) G[r] = 0.0;
+      feq_vjp<D>(lam, F, p, 1.0, G, gm, gl);
+      for (int i = 0; i < D; ++i) {
+        const double lu = TRACK ? lus[(size_t)i * g.S + node] : 0.0;
+        if (gv0) gv0[(size_t)i * g.N + node] = (1.0 + p.gamma * p.hdt) * G[i] - p.hdt * lu;
+        if (gu0) gu0[(size_t)i * g.N + node] = lu;
+      }
+      if (dU0) {
+        double dA[D][M];
+        for (int A = 0; A < D; ++A)
+          for (int r = 0; r < M; ++r) dA[A][r] = dU0[((size_t)A * M + r) * g.N + node];
+        // -dt/2 sum_q lam_q . (d feq'_q / dp)[Z_q]: only the v rows depend on
+        // the parameters, through dP(F0)[Z_q,F] with
+        // Z_q,F_iB = d_B v_i + c e_qA d_A F_iB
+        for (int q = 0; q < Q; ++q) {
+          const int A = q / 2;
+          const double sg = (q & 1) ? -1.0 : 1.0;
+          double Zf[D * D], dPm[D * D], dPl[D * D];
+          for (int i = 0; i < D; ++i)
+            for (int B = 0; B < D; ++B) Zf[i * D + B] = dA[B][i] + p.c * sg * dA[A][D + i * D + B];
+          piola_tangent<D>(F, Zf, 1.0, 0.0, dPm);
+          piola_tangent<D>(F, Zf, 0.0, 1.0, dPl);
+          for (int i = 0; i < D; ++i) {
+            const double cf = -p.hdt * lam[q][i] * p.i2c * sg * (-p.irho);
+            gm += cf * dPm[i * D + A];
+            gl += cf * dPl[i * D + A];
+          }
+        }
+        // -dt/2 G . dU0_t/dp, dU0_t,v_i/dp = sum_A (d dP/dp)(F0)[d_A F]_iA / rho0
+        for (int A = 0; A < D; ++A) {
+          double dPm[D * D], dPl[D * D];
+          piola_tangent<D>(F, dA[A] + D, 1.0, 0.0, dPm);
+          piola_tangent<D>(F, dA[A] + D, 0.0, 1.0, dPl);
+          for (int i = 0; i < D; ++i) {
+            gm -= p.hdt * G[i] * dPm[i * D + A] * p.irho;
+            gl -= p.hdt * G[i] * dPl[i * D + A] * p.irho;
+          }
+        }
+      }
+    } else {
+      for (int i = 0; i < D; ++i) {
+        if (gv0) gv0[(size_t)i * g.N + node] = 0.0;
+        if (gu0) gu0[(size_t)i * g.N + node] = 0.0;
+      }
+    }
+  }
+  block_acc2(gm, gl, gblk + 2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// ------------------------------------------------------------------ host
+
+inline void grid_of(const Geo &g, dim3 &grid, dim3 &block) {
+  const int bx = g.nx >= 256 ? 256 : ((g.nx + 63) / 64) * 64;
+  block = dim3(bx, 1, 1);
+  grid = dim3((g.nx + bx - 1) / bx, g.ny * g.nz, 1);
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// device allocations of one reverse run, released on every exit path
+struct Pool {
+  std::vector<void *> p;
+  ~Pool() {
+    for (void *q : p) (void)hipFree(q);
+  }
+  template <typename X> hipError_t get(X **out, size_t bytes, hipStream_t st, bool zero = true) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e != hipSuccess) return e;
+    p.push_back(q);
+    *out = (X *)q;
+    return zero ? hipMemsetAsync(q, 0, bytes ? bytes : 16, st) : hipSuccess;
+  }
+};
+
+struct Run {
+  tlvlbm_ctx *c;
+  AdjPar ap;
+  dim3 grid, block;
+  size_t nblk = 0;
+  bool neu = false, dir = false;
+  // adjoint fields
+  void *La = nullptr, *Lb = nullptr;
+  double *lus = nullptr, *ubc = nullptr, *gbar = nullptr, *glink = nullptr, *gblk = nullptr, *ginit = nullptr;
+  // projection
+  double *UaB = nullptr, *Fcb = nullptr, *Fext = nullptr, *Frb = nullptr, *x0b = nullptr, *ucb = nullptr;
+  int32_t *comp = nullptr, *cn = nullptr;
+  int64_t *ct = nullptr, *ccnt = nullptr;
+  double *tpart = nullptr, *mean = nullptr;
+  int64_t nu = 0, ntile = 0;
+  uint8_t *anc_n = nullptr;
+  // stencil gather
+  int64_t ns = 0;
+  int64_t *sn = nullptr, *so = nullptr;
+  int32_t *el = nullptr, *ek = nullptr;
+};
+
+template <int D, typename T> void launch_link_pass(Run &R, int pass, double th, const TapeStep &tp) {
+  tlvlbm_ctx *c = R.c;
+  for (int b = 0; b < 256; ++b) {
+    const int64_t b0 = c->bid_begin[b], b1 = c->bid_end[b];
+    if (b1 <= b0) continue;
+    const bool neu = c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION;
+    const unsigned nb = nblocks(b1 - b0, 64);
+    const T *tU = (const T *)tp.U, *tF = (const T *)tp.Fr, *tu = (const T *)tp.u;
+#define TL_LINK(P, NN)                                                                                         \
+  hipLaunchKernelGGL((k_adj_link<D, T, P, NN>), nb, 64, 0, c->st, (T *)R.La, c->L, b0, b1, c->bcs[b], c->geo, \
+                     c->par, th, tU, tF, tu, R.gbar, R.glink)
+    if (pass == 1) {
+      if (neu) TL_LINK(1, true);
+      else TL_LINK(1, false);
+    } else if (pass == 2) {
+      if (neu) TL_LINK(2, true);
+      else TL_LINK(2, false);
+    } else {
+      if (neu) TL_LINK(3, true);
+      else TL_LINK(3, false);
+    }
+#undef TL_LINK
+  }
+}
+
+// x0b = null-space part of (ua + ub); CG workspace b = the rest, x = 0;
+// then x = K^+ b
+template <int D> int solve_adj(Run &R, const double *ua, const double *ub) {
+  tlvlbm_ctx *c = R.c;
+  CG &w = c->cg;
+  const Geo &g = c->geo;
+  if (R.nu > 0) {
+    hipLaunchKernelGGL((k_pi_tiles<D>), (unsigned)R.ntile, AT, 0, c->st, R.cn, g, ua, ub, R.tpart);
+    hipLaunchKernelGGL((k_pi_comp<D>), (unsigned)R.nu, AT, 0, c->st, R.ct, R.ccnt, R.tpart, R.mean);
+  }
+  hipLaunchKernelGGL((k_pi_apply<D>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, R.comp, R.mean, ua, ub, R.x0b,
+                     (double *)w.b, (double *)w.x);
+  return run_cg_given(c, R.dir ? R.anc_n : nullptr);
+}
+
+template <int D> void anchors_T(Run &R, const double *y, double *Fb) {
+  tlvlbm_ctx *c = R.c;
+  for (int b = 0; b < 256; ++b) {
+    const int64_t b0 = c->bid_begin[b], b1 = c->bid_end[b];
+    if (b1 <= b0 || c->bcs[b].type != TLVLBM_BC_DIRICHLET_VELOCITY) continue;
+    hipLaunchKernelGGL((k_adj_anchT<D>), nblocks(b1 - b0, 64), 64, 0, c->st, c->L, b0, b1, c->geo, y, Fb);
+  }
+}
+
+// reverse of step k: R.La holds the adjoint of that step's output, the
+// result (adjoint of its input) goes to R.Lb; then the two swap
+template <int D, typename T> int reverse_step(Run &R, int64_t k, const TapeStep &tp) {
+  tlvlbm_ctx *c = R.c;
+  const Geo &g = c->geo;
+  const double th = k * c->par.dt + 0.5 * c->par.dt;
+  const bool proj = is_projection_step(c, k);
+  if (c->L.n) {
+    launch_link_pass<D, T>(R, 1, th, tp);
+    launch_link_pass<D, T>(R, 2, th, tp);
+    launch_link_pass<D, T>(R, 3, th, tp);
+  }
+  if (R.ns)
+    hipLaunchKernelGGL((k_adj_ugather<D>), nblocks(R.ns, AT), AT, 0, c->st, R.ns, R.sn, R.so, R.el, R.ek, c->L, g,
+                       R.gbar, R.ubc);
+  const T *Lout = (const T *)R.La;
+  T *Lin = (T *)R.Lb;
+  if (!proj) {
+    const T *tU = (const T *)tp.U;
+    if (c->act) {
+      if (c->track_u)
+        hipLaunchKernelGGL((k_adj_bulk<D, T, true, true>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act, tU,
+                           R.ubc, R.lus, R.gblk);
+      else
+        hipLaunchKernelGGL((k_adj_bulk<D, T, true, false>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act,
+                           tU, R.ubc, R.lus, R.gblk);
+    } else {
+      if (c->track_u)
+        hipLaunchKernelGGL((k_adj_bulk<D, T, false, true>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act,
+                           tU, R.ubc, R.lus, R.gblk);
+      else
+        hipLaunchKernelGGL((k_adj_bulk<D, T, false, false>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act,
+                           tU, R.ubc, R.lus, R.gblk);
+    }
+  } else {
+    CG &w = c->cg;
+    // second projection (u from F^r, warm start u^c) and u* = u + dt/2 v
+    int s = solve_adj<D>(R, R.ubc, R.lus);
+    if (s) return s;
+    hipLaunchKernelGGL((k_adj_rhsT<D, false>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, (const double *)w.x, R.Frb);
+    anchors_T<D>(R, (const double *)w.x, R.Frb);
+    hipLaunchKernelGGL((k_adj_rep1<D, T>), R.grid, R.block, 0, c->st, Lout, g, R.ap, c->act, (const T *)tp.U,
+                       (const T *)tp.Fr, R.Frb, R.lus, R.UaB, R.Fcb, R.gblk);
+    hipLaunchKernelGGL((k_adj_compatT<D>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, R.Fcb, R.x0b, R.ucb, R.Fext);
+    // first projection (u^c from F, warm start u)
+    s = solve_adj<D>(R, R.ucb, nullptr);
+    if (s) return s;
+    hipLaunchKernelGGL((k_adj_rhsT<D, true>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, (const double *)w.x, R.Fext);
+    anchors_T<D>(R, (const double *)w.x, R.Fext);
+    hipLaunchKernelGGL((k_adj_rep2<D, T>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act, R.UaB, R.Fext,
+                       R.x0b, R.lus);
+  }
+  std::swap(R.La, R.Lb);
+  return hipGetLastError() == hipSuccess ? TLVLBM_OK : TLVLBM_ERR_DEVICE;
+}
+
+// host preparation: connected components of the active graph without
+// anchors, anchor counts, and the transposed LSQ stencils of Neumann links
+template <int D> int prepare_host(Run &R, Pool &pool) {
+  tlvlbm_ctx *c = R.c;
+  const Geo &g = c->geo;
+  const int64_t N = g.N;
+  std::vector<uint8_t> act(N);
+  if (hipMemcpy(act.data(), c->act, N, hipMemcpyDeviceToHost) != hipSuccess) return TLVLBM_ERR_DEVICE;
+  const int64_t nl = c->L.n;
+  std::vector<int64_t> lnode(nl);
+  std::vector<int32_t> lq(nl), lnp(nl), sidx((size_t)nl * c->L.kmax);
+  if (nl) {
+    if (hipMemcpy(lnode.data(), c->L.node, nl * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(lq.data(), c->L.q, nl * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(lnp.data(), c->L.npts, nl * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(sidx.data(), c->L.sidx, sidx.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return TLVLBM_ERR_DEVICE;
+  }
+  std::vector<uint8_t> is_neu(nl, 0), is_dir(nl, 0);
+  for (int b = 0; b < 256; ++b)
+    for (int64_t l = c->bid_begin[b]; l < c->bid_end[b]; ++l) {
+      is_neu[l] = c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION;
+      is_dir[l] = c->bcs[b].type == TLVLBM_BC_DIRICHLET_VELOCITY;
+    }
+  // anchor counts
+  std::vector<uint8_t> an(N, 0);
+  for (int64_t l = 0; l < nl; ++l)
+    if (is_dir[l]) an[lnode[l]]++;
+  // components (breadth-first over active lattice neighbours)
+  std::vector<int32_t> comp(N, -1), cid(N, -1);
+  std::vector<int64_t> stack;
+  int32_t nc = 0;
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  for (int64_t s0 = 0; s0 < N; ++s0) {
+    if (!act[s0] || cid[s0] >= 0) continue;
+    cid[s0] = nc;
+    stack.assign(1, s0);
+    while (!stack.empty()) {
+      const int64_t m = stack.back();
+      stack.pop_back();
+      int cc[3] = {(int)(m % g.nx), (int)((m / g.nx) % g.ny), (int)(m / ((int64_t)g.nx * g.ny))};
+      for (int q = 0; q < 2 * D; ++q) {
+        int v[3] = {cc[0], cc[1], cc[2]};
+        v[q / 2] += (q & 1) ? -1 : 1;
+        const int A = q / 2;
+        if (v[A] < 0 || v[A] >= n3[A]) {
+          if (!((g.per >> A) & 1)) continue;
+          v[A] = (v[A] + n3[A]) % n3[A];
+        }
+        const int64_t j = v[0] + (int64_t)g.nx * (v[1] + (int64_t)g.ny * v[2]);
+        if (act[j] && cid[j] < 0) {
+          cid[j] = nc;
+          stack.push_back(j);
+        }
+      }
+    }
+    ++nc;
+  }
+  std::vector<uint8_t> anch(nc, 0);
+  for (int64_t m = 0; m < N; ++m)
+    if (act[m] && an[m]) anch[cid[m]] = 1;
+  std::vector<int32_t> uidx(nc, -1);
+  int32_t nu = 0;
+  for (int32_t k = 0; k < nc; ++k)
+    if (!anch[k]) uidx[k] = nu++;
+  std::vector<std::vector<int32_t>> members(nu);
+  for (int64_t m = 0; m < N; ++m)
+    if (act[m] && uidx[cid[m]] >= 0) {
+      comp[m] = uidx[cid[m]];
+      members[comp[m]].push_back((int32_t)m);
+    }
+  std::vector<int32_t> cn;
+  std::vector<int64_t> ct(nu + 1, 0), ccnt(nu, 0);
+  for (int32_t k = 0; k < nu; ++k) {
+    ct[k] = (int64_t)(cn.size() / AT);
+    ccnt[k] = (int64_t)members[k].size();
+    cn.insert(cn.end(), members[k].begin(), members[k].end());
+    while (cn.size() % AT) cn.push_back(-1);
+  }
+  ct[nu] = (int64_t)(cn.size() / AT);
+  R.nu = nu;
+  R.ntile = ct[nu];
+  hipStream_t st = c->st;
+  if (pool.get(&R.comp, N * sizeof(int32_t), st, false) != hipSuccess ||
+      pool.get(&R.anc_n, N, st, false) != hipSuccess || pool.get(&R.cn, cn.size() * sizeof(int32_t), st, false) ||
+      pool.get(&R.ct, ct.size() * sizeof(int64_t), st, false) ||
+      pool.get(&R.ccnt, (ccnt.size() + 1) * sizeof(int64_t), st, false) ||
+      pool.get(&R.tpart, ((size_t)R.ntile + 1) * D * sizeof(double), st) ||
+      pool.get(&R.mean, ((size_t)nu + 1) * D * sizeof(double), st))
+    return TLVLBM_ERR_OUT_OF_MEMORY;
+  if (hipMemcpy(R.comp, comp.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) ||
+      hipMemcpy(R.anc_n, an.data(), N, hipMemcpyHostToDevice) ||
+      (cn.size() && hipMemcpy(R.cn, cn.data(), cn.size() * sizeof(int32_t), hipMemcpyHostToDevice)) ||
+      hipMemcpy(R.ct, ct.data(), ct.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
+      (nu && hipMemcpy(R.ccnt, ccnt.data(), ccnt.size() * sizeof(int64_t), hipMemcpyHostToDevice)))
+    return TLVLBM_ERR_DEVICE;
+  // transposed Neumann stencils: entries (node, link, point), sorted
+  struct E {
+    int32_t j, l, k;
+  };
+  std::vector<E> ent;
+  for (int64_t l = 0; l < nl; ++l)
+    if (is_neu[l])
+      for (int k = 0; k < lnp[l]; ++k) ent.push_back({sidx[(size_t)l * c->L.kmax + k], (int32_t)l, k});
+  std::sort(ent.begin(), ent.end(), [](const E &a, const E &b) {
+    return a.j != b.j ? a.j < b.j : (a.l != b.l ? a.l < b.l : a.k < b.k);
+  });
+  std::vector<int64_t> sn, so;
+  std::vector<int32_t> el, ek;
+  for (size_t e = 0; e < ent.size(); ++e) {
+    if (e == 0 || ent[e].j != ent[e - 1].j) {
+      sn.push_back(ent[e].j);
+      so.push_back((int64_t)e);
+    }
+    el.push_back(ent[e].l);
+    ek.push_back(ent[e].k);
+  }
+  so.push_back((int64_t)ent.size());
+  R.ns = (int64_t)sn.size();
+  if (R.ns) {
+    if (pool.get(&R.sn, sn.size() * sizeof(int64_t), st, false) ||
+        pool.get(&R.so, so.size() * sizeof(int64_t), st, false) ||
+        pool.get(&R.el, el.size() * sizeof(int32_t), st, false) ||
+        pool.get(&R.ek, ek.size() * sizeof(int32_t), st, false))
+      return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (hipMemcpy(R.sn, sn.data(), sn.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
+        hipMemcpy(R.so, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
+        hipMemcpy(R.el, el.data(), el.size() * sizeof(int32_t), hipMemcpyHostToDevice) ||
+        hipMemcpy(R.ek, ek.data(), ek.size() * sizeof(int32_t), hipMemcpyHostToDevice))
+      return TLVLBM_ERR_DEVICE;
+  }
+  return TLVLBM_OK;
+}
+
+template <int D, typename T>
+tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0, const double *dLdU,
+                        const double *dLdu, double *gmat, double *gv0, double *gu0, int64_t seg, std::string &err) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const Geo &g = c->geo;
+  hipStream_t st = c->st;
+  Pool pool;
+  Run R;
+  R.c = c;
+  const Par &pp = c->par;
+  R.ap = AdjPar{pp.omega,
+                pp.dt * (2.0 - pp.omega) / (4.0 * D),
+                1.0 / (1.0 + 0.5 * pp.gamma * pp.dt),
+                0.5 * pp.dt,
+                1.0 / (2.0 * D),
+                0.5 / pp.c,
+                pp.inv_rho0,
+                pp.mu,
+                pp.lam,
+                pp.gamma,
+                pp.c,
+                pp.dt,
+                c->theta,
+                g.dx};
+  grid_of(g, R.grid, R.block);
+  R.nblk = (size_t)R.grid.x * R.grid.y;
+  for (int b = 0; b < 256; ++b) {
+    if (c->bid_end[b] <= c->bid_begin[b]) continue;
+    if (c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION) R.neu = true;
+    if (c->bcs[b].type == TLVLBM_BC_DIRICHLET_VELOCITY) R.dir = true;
+  }
+  const bool track = c->track_u;
+  const size_t plane = (size_t)g.S * sizeof(T), dplane = (size_t)g.S * sizeof(double);
+  const size_t ck_bytes = (size_t)Q * M * plane + (track ? D * plane : 0);
+  const size_t tape_bytes = (size_t)M * plane + (R.neu ? D * plane : 0);
+  if (seg <= 0) {
+    seg = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(n, 1) * (double)ck_bytes / (double)tape_bytes));
+    seg = std::max<int64_t>(1, std::min<int64_t>(seg, std::max<int64_t>(n, 1)));
+  }
+  const int64_t nck = n > 0 ? (n + seg - 1) / seg : 0;
+  int64_t nproj_seg = 0;
+  if (R.neu && c->proj_every > 0) nproj_seg = seg / c->proj_every + 2;
+  // memory check
+  {
+    size_t need = (size_t)(nck + 1) * ck_bytes + (size_t)seg * tape_bytes + (size_t)nproj_seg * D * D * plane +
+                  2 * (size_t)Q * M * plane + 2 * (size_t)D * dplane;
+    if (R.neu) need += (size_t)(M + 3 * D * D + 2 * D) * dplane;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && need > fr) {
+      err = "adjoint: checkpoints and tape do not fit in device memory (lower the step count or pass a segment length)";
+      return TLVLBM_ERR_OUT_OF_MEMORY;
+    }
+  }
+  if (R.neu || R.dir) {
+    const int s = ensure_cg(c);
+    if (s) return (tlvlbm_status)s;
+  }
+  // inputs
+  DevIn dU0d, ddU0, dLU, dLu;
+  if (dU0d.take(U0, (size_t)M * g.N * sizeof(double), st) || ddU0.take(dU0, (size_t)D * M * g.N * sizeof(double), st) ||
+      dLU.take(dLdU, (size_t)M * g.N * sizeof(double), st) || dLu.take(dLdu, (size_t)D * g.N * sizeof(double), st))
+    return TLVLBM_ERR_OUT_OF_MEMORY;
+  // forward with checkpoints
+  std::vector<void *> ckf(nck + 1, nullptr), cku(nck + 1, nullptr);
+  for (int64_t s = 0; s <= nck; ++s) {
+    if (pool.get(&ckf[s], (size_t)Q * M * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (track && pool.get(&cku[s], (size_t)D * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+  }
+  auto save = [&](int64_t s) -> bool {
+    if (hipMemcpyAsync(ckf[s], c->fB, (size_t)Q * M * plane, hipMemcpyDeviceToDevice, st)) return false;
+    if (track && hipMemcpyAsync(cku[s], c->ustar, (size_t)D * plane, hipMemcpyDeviceToDevice, st)) return false;
+    return true;
+  };
+  auto restore = [&](int64_t s) -> bool {
+    if (hipMemcpyAsync(c->fB, ckf[s], (size_t)Q * M * plane, hipMemcpyDeviceToDevice, st)) return false;
+    if (track && hipMemcpyAsync(c->ustar, cku[s], (size_t)D * plane, hipMemcpyDeviceToDevice, st)) return false;
+    return true;
+  };
+  for (int64_t k = 0; k < n; ++k) {
+    if (k % seg == 0 && !save(k / seg)) return TLVLBM_ERR_DEVICE;
+    const int s = step_once(c);
+    if (s) return (tlvlbm_status)s;
+  }
+  if (!save(nck)) return TLVLBM_ERR_DEVICE;
+  {
+    const tlvlbm_status s = check_flag(c);
+    if (s) return s;
+  }
+  // adjoint buffers
+  if (pool.get(&R.La, (size_t)Q * M * plane, st) || pool.get(&R.Lb, (size_t)Q * M * plane, st) ||
+      pool.get(&R.lus, (size_t)D * dplane, st) || pool.get(&R.ubc, (size_t)D * dplane, st) ||
+      pool.get(&R.gbar, (size_t)std::max<int64_t>(c->L.n, 1) * 6 * sizeof(double), st) ||
+      pool.get(&R.glink, (size_t)std::max<int64_t>(c->L.n, 1) * 2 * sizeof(double), st) ||
+      pool.get(&R.gblk, R.nblk * 2 * sizeof(double), st) || pool.get(&R.ginit, R.nblk * 2 * sizeof(double), st))
+    return TLVLBM_ERR_OUT_OF_MEMORY;
+  if (R.neu) {
+    if (pool.get(&R.UaB, (size_t)M * dplane, st) || pool.get(&R.Fcb, (size_t)D * D * dplane, st) ||
+        pool.get(&R.Fext, (size_t)D * D * dplane, st) || pool.get(&R.Frb, (size_t)D * D * dplane, st) ||
+        pool.get(&R.x0b, (size_t)D * dplane, st) || pool.get(&R.ucb, (size_t)D * dplane, st))
+      return TLVLBM_ERR_OUT_OF_MEMORY;
+  }
+  if (c->act) {
+    const int s = prepare_host<D>(R, pool);
+    if (s) return (tlvlbm_status)s;
+  }
+  // per-step tape of one segment
+  char *tapeU = nullptr, *tapeu = nullptr, *tapeF = nullptr;
+  if (pool.get(&tapeU, (size_t)seg * M * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+  if (R.neu && pool.get(&tapeu, (size_t)seg * D * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+  if (nproj_seg && pool.get(&tapeF, (size_t)nproj_seg * D * D * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+  // seeds
+  {
+    const double *gU = (const double *)dLU.ptr, *gu = (const double *)dLu.ptr;
+    if (c->act) {
+      if (track)
+        hipLaunchKernelGGL((k_adj_seed<D, T, true, true>), R.grid, R.block, 0, st, (T *)R.La, g, R.ap, c->act, gU, gu,
+                           R.lus);
+      else
+        hipLaunchKernelGGL((k_adj_seed<D, T, true, false>), R.grid, R.block, 0, st, (T *)R.La, g, R.ap, c->act, gU,
+                           gu, R.lus);
+    } else {
+      if (track)
+        hipLaunchKernelGGL((k_adj_seed<D, T, false, true>), R.grid, R.block, 0, st, (T *)R.La, g, R.ap, c->act, gU,
+                           gu, R.lus);
+      else
+        hipLaunchKernelGGL((k_adj_seed<D, T, false, false>), R.grid, R.block, 0, st, (T *)R.La, g, R.ap, c->act, gU,
+                           gu, R.lus);
+    }
+  }
+  // segments in reverse: recompute with the tape, then reverse each step
+  const int64_t st_proj0 = c->st_proj, st_cg0 = c->st_cg;
+  for (int64_t s = nck - 1; s >= 0; --s) {
+    const int64_t k0 = s * seg, k1 = std::min<int64_t>(n, k0 + seg);
+    if (!restore(s)) return TLVLBM_ERR_DEVICE;
+    c->step = k0;
+    std::vector<TapeStep> tps(k1 - k0);
+    int64_t ip = 0;
+    for (int64_t k = k0; k < k1; ++k) {
+      TapeStep &tp = tps[k - k0];
+      tp.U = tapeU + (size_t)(k - k0) * M * plane;
+      tp.u = R.neu ? tapeu + (size_t)(k - k0) * D * plane : nullptr;
+      tp.Fr = nullptr;
+      if (is_projection_step(c, k)) {
+        if (ip >= nproj_seg) return TLVLBM_ERR_INVALID_ARG;
+        tp.Fr = tapeF + (size_t)(ip++) * D * D * plane;
+      }
+      const int e = step_once(c, &tp);
+      if (e) return (tlvlbm_status)e;
+    }
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      const int e = reverse_step<D, T>(R, k, tps[k - k0]);
+      if (e) return (tlvlbm_status)e;
+    }
+  }
+  c->st_proj = st_proj0;  // recomputation is not counted as progress
+  (void)st_cg0;
+  // initialisation transpose
+  DevOut ov, ou;
+  if (ov.take(gv0, (size_t)D * g.N * sizeof(double)) || ou.take(gu0, (size_t)D * g.N * sizeof(double)))
+    return TLVLBM_ERR_OUT_OF_MEMORY;
+  {
+    const double *u0p = (const double *)dU0d.ptr, *du0p = (const double *)ddU0.ptr;
+    double *pv = (double *)ov.ptr, *pu = (double *)ou.ptr;
+    if (c->act) {
+      if (track)
+        hipLaunchKernelGGL((k_adj_init<D, T, true, true>), R.grid, R.block, 0, st, (const T *)R.La, g, R.ap, c->act,
+                           u0p, du0p, R.lus, pv, pu, R.ginit);
+      else
+        hipLaunchKernelGGL((k_adj_init<D, T, true, false>), R.grid, R.block, 0, st, (const T *)R.La, g, R.ap, c->act,
+                           u0p, du0p, R.lus, pv, pu, R.ginit);
+    } else {
+      if (track)
+        hipLaunchKernelGGL((k_adj_init<D, T, false, true>), R.grid, R.block, 0, st, (const T *)R.La, g, R.ap, c->act,
+                           u0p, du0p, R.lus, pv, pu, R.ginit);
+      else
+        hipLaunchKernelGGL((k_adj_init<D, T, false, false>), R.grid, R.block, 0, st, (const T *)R.La, g, R.ap,
+                           c->act, u0p, du0p, R.lus, pv, pu, R.ginit);
+    }
+  }
+  if (hipGetLastError() != hipSuccess) return TLVLBM_ERR_DEVICE;
+  if (ov.finish(st) || ou.finish(st)) return TLVLBM_ERR_DEVICE;
+  // parameter gradient: fixed-order host sum of the per-block and per-link slots
+  std::vector<double> hb(R.nblk * 2), hi(R.nblk * 2), hl((size_t)std::max<int64_t>(c->L.n, 1) * 2);
+  if (hipMemcpyAsync(hb.data(), R.gblk, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st) ||
+      hipMemcpyAsync(hi.data(), R.ginit, hi.size() * sizeof(double), hipMemcpyDeviceToHost, st) ||
+      hipMemcpyAsync(hl.data(), R.glink, hl.size() * sizeof(double), hipMemcpyDeviceToHost, st))
+    return TLVLBM_ERR_DEVICE;
+  // back to the end of the trajectory
+  if (!restore(nck)) return TLVLBM_ERR_DEVICE;
+  c->step = n;
+  if (hipStreamSynchronize(st) != hipSuccess) return TLVLBM_ERR_DEVICE;
+  double gsum[2] = {0.0, 0.0};
+  for (size_t b = 0; b < R.nblk; ++b)
+    for (int k = 0; k < 2; ++k) gsum[k] += hb[2 * b + k];
+  for (size_t l = 0; l < (size_t)c->L.n; ++l)
+    for (int k = 0; k < 2; ++k) gsum[k] += hl[2 * l + k];
+  for (size_t b = 0; b < R.nblk; ++b)
+    for (int k = 0; k < 2; ++k) gsum[k] += hi[2 * b + k];
+  if (gmat) {
+    gmat[0] = gsum[0];
+    gmat[1] = gsum[1];
+  }
+  return check_flag(c);
+}
+
+}  // namespace
+}  // namespace tl
+
+using namespace tl;
+
+extern "C" tlvlbm_status tlvlbm_adjoint(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0,
+                                        const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
+                                        double *grad_u0, int64_t segment) {
+  if (!c || n < 0 || !U0) return TLVLBM_ERR_INVALID_ARG;
+  if (c->status) return (tlvlbm_status)c->status;
+  std::string err;
+  tlvlbm_status s;
+  try {
+    if (!c->have_state || !c->fresh) {
+      c->err = "adjoint: the state must be the one set by tlvlbm_set_state (no step since)";
+      return TLVLBM_ERR_CALL_ORDER;
+    }
+    if (c->D == 2)
+      s = c->prec ? adjoint_t<2, double>(c, n, U0, dU0, dLdU, dLdu, grad_mat, grad_v0, grad_u0, segment, err)
+                  : adjoint_t<2, float>(c, n, U0, dU0, dLdU, dLdu, grad_mat, grad_v0, grad_u0, segment, err);
+    else
+      s = c->prec ? adjoint_t<3, double>(c, n, U0, dU0, dLdU, dLdu, grad_mat, grad_v0, grad_u0, segment, err)
+                  : adjoint_t<3, float>(c, n, U0, dU0, dLdU, dLdu, grad_mat, grad_v0, grad_u0, segment, err);
+  } catch (...) {
+    err = "adjoint: host allocation failed";
+    s = TLVLBM_ERR_OUT_OF_MEMORY;
+  }
+  c->fresh = false;
+  if (s) {
+    c->status = s;
+    try {
+      c->err = err.empty() ? std::string("adjoint failed") : err;
+    } catch (...) {
+    }
+  }
+  return s;
+}

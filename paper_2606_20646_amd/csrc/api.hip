@@ -16,62 +16,6 @@ using namespace tl;
 
 namespace {
 
-bool is_device_ptr(const void *p) {
-  if (!p) return false;
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
-}
-
-// device view of a borrowed input array (copied when it lives on the host)
-struct DevIn {
-  const void *ptr = nullptr;
-  void *owned = nullptr;
-  ~DevIn() {
-    if (owned) (void)hipFree(owned);
-  }
-  hipError_t take(const void *src, size_t bytes, hipStream_t st) {
-    if (!src) return hipSuccess;
-    if (is_device_ptr(src)) {
-      ptr = src;
-      return hipSuccess;
-    }
-    hipError_t e = hipMalloc(&owned, bytes);
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(owned, src, bytes, hipMemcpyHostToDevice, st);
-    ptr = owned;
-    return e;
-  }
-};
-
-// device target for a caller output (staged when it lives on the host)
-struct DevOut {
-  void *user = nullptr, *ptr = nullptr, *owned = nullptr;
-  size_t bytes = 0;
-  ~DevOut() {
-    if (owned) (void)hipFree(owned);
-  }
-  hipError_t take(void *dst, size_t b) {
-    user = dst;
-    bytes = b;
-    if (!dst) return hipSuccess;
-    if (is_device_ptr(dst)) {
-      ptr = dst;
-      return hipSuccess;
-    }
-    hipError_t e = hipMalloc(&owned, b);
-    ptr = owned;
-    return e;
-  }
-  hipError_t finish(hipStream_t st) {
-    if (owned && user) return hipMemcpyAsync(user, owned, bytes, hipMemcpyDeviceToHost, st);
-    return hipSuccess;
-  }
-};
-
 tlvlbm_status fail(tlvlbm_ctx *c, tlvlbm_status s, const char *msg) {
   if (c) {
     try {
@@ -124,26 +68,44 @@ bool has_neumann(const tlvlbm_ctx *c) {
 
 // launches of one step of Algorithm 1 (no host synchronisation except inside
 // the projection's CG convergence polling)
-int step_once(tlvlbm_ctx *c) {
+}  // namespace
+
+namespace tl {
+
+tlvlbm_status check_flag(tlvlbm_ctx *c) { return read_flag(c); }
+
+bool is_projection_step(const tlvlbm_ctx *c, int64_t step) {
+  return has_neumann(c) && c->proj_every > 0 && (step % c->proj_every == 0);
+}
+
+// One step of Algorithm 1.  With a tape, the recovered state, the repaired
+// deformation gradient (projection steps) and the displacement seen by the
+// cut links are recorded for the reverse mode.
+int step_once(tlvlbm_ctx *c, const TapeStep *tp) {
   const double tn = c->step * c->par.dt;
-  const bool proj = has_neumann(c) && c->proj_every > 0 && (c->step % c->proj_every == 0);
+  const bool proj = is_projection_step(c, c->step);
+  const size_t plane = (size_t)c->geo.S * c->esz;
   if (proj) {
     int s = run_projection(c, true, tn);
     if (s) return s;
-    launch_bulk(c, true);
+    launch_bulk(c, true, tp ? tp->U : nullptr);
+    if (tp && tp->Fr)
+      CHK(hipMemcpyAsync(tp->Fr, c->cg.Fr, (size_t)c->D * c->D * plane, hipMemcpyDeviceToDevice, c->st), "tape");
     s = run_projection(c, false, tn);
     if (s) return s;
     ++c->st_proj;
   } else {
-    launch_bulk(c, false);
+    launch_bulk(c, false, tp ? tp->U : nullptr);
   }
   if (c->L.n) launch_cutlinks(c, tn);
+  if (tp && tp->u)
+    CHK(hipMemcpyAsync(tp->u, c->ubuf, (size_t)c->D * plane, hipMemcpyDeviceToDevice, c->st), "tape");
   std::swap(c->fA, c->fB);
   ++c->step;
   return TLVLBM_OK;
 }
 
-}  // namespace
+}  // namespace tl
 
 extern "C" {
 
@@ -344,6 +306,7 @@ tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0
     c->step = 0;
     c->status = TLVLBM_OK;
     c->have_state = true;
+    c->fresh = true;
     return TLVLBM_OK;
   } catch (...) {
     return fail(c, TLVLBM_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -355,6 +318,7 @@ tlvlbm_status tlvlbm_step(tlvlbm_ctx *c, int64_t n) {
   if (!c->have_state) return fail(c, TLVLBM_ERR_CALL_ORDER, "step before set_state");
   if (c->status) return (tlvlbm_status)c->status;
   for (int64_t k = 0; k < n; ++k) {
+    c->fresh = false;
     const int s = step_once(c);
     if (s) return (tlvlbm_status)(c->status = s);
   }
@@ -373,6 +337,7 @@ tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t nctx, int64_t n)
   }
   for (int64_t k = 0; k < n; ++k)
     for (int i = 0; i < nctx; ++i) {
+      ctxs[i]->fresh = false;
       const int s = step_once(ctxs[i]);
       if (s) return (tlvlbm_status)(ctxs[i]->status = s);
     }
@@ -438,6 +403,7 @@ tlvlbm_status tlvlbm_put_state(tlvlbm_ctx *c, const double *f, const double *ust
     CHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->st), "flag clear");
     CHK(hipStreamSynchronize(c->st), "synchronize");
   }
+  c->fresh = false;
   c->step = step;
   c->status = TLVLBM_OK;
   c->have_state = true;

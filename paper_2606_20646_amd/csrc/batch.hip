@@ -300,6 +300,7 @@ tlvlbm_status tlvlbm_batch_step(tlvlbm_batch *b, int64_t n) {
     tlvlbm_ctx *c = b->c[i];
     if (n & 1) std::swap(c->fA, c->fB);
     c->step = b->step;
+    c->fresh = false;
     BCHK(hipMemcpyAsync(b->h_flags + i, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, b->st), "flag read");
   }
   BCHK(hipStreamSynchronize(b->st), "synchronize");

@@ -89,11 +89,13 @@ template <typename T> __device__ __forceinline__ bool finite_(T v) { return __bu
 
 // Fused pull-stream + state recovery + (optional projection repair) + BGK
 // collision with source + displacement quadrature (Algorithm 1, bulk loops).
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR>
+// TAPE: also store the recovered (pre-repair) state (v, F - I) to the tape
+// planes for the reverse mode.
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool TAPE = false>
 __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restrict__ fout, const Geo &g,
                                           const Par &p, const uint8_t *__restrict__ act, T *__restrict__ ustar,
                                           T *__restrict__ ubuf, const T *__restrict__ Frp,
-                                          int *__restrict__ flag, int x, int row) {
+                                          int *__restrict__ flag, int x, int row, T *__restrict__ tape = nullptr) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int y = row % g.ny, z = row / g.ny;
   const int64_t node = x + (int64_t)g.nx * row;
@@ -122,6 +124,12 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
   for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
   T J = piola<D>(F, mu, lam, P);
   bool bad = !(J > T(0));
+  if constexpr (TAPE) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) tape[(size_t)i * g.S + node] = v[i];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) tape[(size_t)(D + k) * g.S + node] = dU[D + k];
+  }
   const T inv2c = T(0.5) / T(p.c);
   const T inv2D = T(1) / T(2 * D);
 
@@ -206,6 +214,18 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
   bulk_node<D, T, MASK, TRACK, REPAIR>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, (int)blockIdx.y);
+}
+
+// the same update recording the recovered state on the reverse-mode tape
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR>
+__global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
+                                                   const uint8_t *__restrict__ act, T *__restrict__ ustar,
+                                                   T *__restrict__ ubuf, const T *__restrict__ Frp,
+                                                   int *__restrict__ flag, T *__restrict__ tape) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  bulk_node<D, T, MASK, TRACK, REPAIR, true>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, (int)blockIdx.y,
+                                             tape);
 }
 
 // Batched bulk update: one block per tile (instance, row, first x) of the
@@ -434,13 +454,32 @@ static inline void grid_of(const Geo &g, dim3 &grid, dim3 &block) {
   grid = dim3((g.nx + bx - 1) / bx, g.ny * g.nz, 1);
 }
 
-template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair) {
+template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair, void *tape) {
   dim3 grid, block;
   grid_of(c->geo, grid, block);
   const T *fin = (const T *)c->fB;
   T *fout = (T *)c->fA;
   T *us = (T *)c->ustar, *ub = (T *)c->ubuf;
   const T *Fr = (const T *)c->cg.Fr;
+  if (tape) {
+    T *tp = (T *)tape;
+    if (repair)
+      hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, true>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, tp);
+    else if (c->act && c->track_u)
+      hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, tp);
+    else if (c->act)
+      hipLaunchKernelGGL((k_bulk_tape<D, T, true, false, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, tp);
+    else if (c->track_u)
+      hipLaunchKernelGGL((k_bulk_tape<D, T, false, true, false>), grid, block, 0, c->st, fin, fout, c->geo,
+                         c->par, c->act, us, ub, Fr, c->d_flag, tp);
+    else
+      hipLaunchKernelGGL((k_bulk_tape<D, T, false, false, false>), grid, block, 0, c->st, fin, fout, c->geo,
+                         c->par, c->act, us, ub, Fr, c->d_flag, tp);
+    return;
+  }
   if (repair) {
     hipLaunchKernelGGL((k_bulk<D, T, true, true, true>), grid, block, 0, c->st, fin, fout, c->geo, c->par, c->act,
                        us, ub, Fr, c->d_flag);
@@ -461,13 +500,13 @@ template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair) {
   }
 }
 
-void launch_bulk(tlvlbm_ctx *c, bool repair) {
+void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape) {
   if (c->D == 2) {
-    if (c->prec) bulk_t<2, double>(c, repair);
-    else bulk_t<2, float>(c, repair);
+    if (c->prec) bulk_t<2, double>(c, repair, tape);
+    else bulk_t<2, float>(c, repair, tape);
   } else {
-    if (c->prec) bulk_t<3, double>(c, repair);
-    else bulk_t<3, float>(c, repair);
+    if (c->prec) bulk_t<3, double>(c, repair, tape);
+    else bulk_t<3, float>(c, repair, tape);
   }
 }
 

@@ -1,0 +1,201 @@
+// Device helpers shared by the forward and reverse kernels: grid
+// neighbourhoods, boundary data and the local Newton solve of the Neumann
+// closure (all FP64, register resident).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "tl_internal.hpp"
+#include "tl_math.hpp"
+
+namespace tl {
+
+// ------------------------------------------------------------ grid helpers
+
+struct C3 {
+  int x, y, z;
+};
+
+__device__ __forceinline__ C3 coords_of(const Geo &g, int64_t i) {
+  C3 c;
+  c.x = (int)(i % g.nx);
+  c.y = (int)((i / g.nx) % g.ny);
+  c.z = (int)(i / ((int64_t)g.nx * g.ny));
+  return c;
+}
+
+// node at integer offset (ox, oy, oz): periodic wrap, -1 outside a non-periodic box
+__device__ __forceinline__ int64_t node_at(const Geo &g, C3 c, int ox, int oy, int oz) {
+  int v[3] = {c.x + ox, c.y + oy, c.z + oz};
+  const int n[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    if (v[A] < 0 || v[A] >= n[A]) {
+      if (!((g.per >> A) & 1)) return -1;
+      v[A] = ((v[A] % n[A]) + n[A]) % n[A];
+    }
+  }
+  return v[0] + (int64_t)g.nx * (v[1] + (int64_t)g.ny * v[2]);
+}
+
+__device__ __forceinline__ int64_t node_dir(const Geo &g, C3 c, int q, int mult) {
+  const int A = q / 2, sg = (q & 1) ? -1 : 1;
+  return node_at(g, c, A == 0 ? sg * mult : 0, A == 1 ? sg * mult : 0, A == 2 ? sg * mult : 0);
+}
+
+// ------------------------------------------------- boundary data (FP64)
+
+__device__ __forceinline__ void ramp_eval(int kind, double Tr, double t, double &s, double &ds) {
+  s = 1.0;
+  ds = 0.0;
+  if (t < Tr) {
+    if (kind == TLVLBM_RAMP_SIN2) {
+      const double a = M_PI * t / (2.0 * Tr);
+      s = sin(a) * sin(a);
+      ds = M_PI / (2.0 * Tr) * sin(M_PI * t / Tr);
+    } else if (kind == TLVLBM_RAMP_HALFCOS) {
+      s = 0.5 * (1.0 - cos(M_PI * t / Tr));
+      ds = 0.5 * M_PI / Tr * sin(M_PI * t / Tr);
+    } else if (kind == TLVLBM_RAMP_LINEAR) {
+      s = t / Tr;
+      ds = 1.0 / Tr;
+    }
+  }
+}
+
+// integral of the loading factor from 0 to t
+__device__ __forceinline__ double ramp_int(int kind, double Tr, double t) {
+  if (kind == TLVLBM_RAMP_CONST) return t;
+  const double tc = t < Tr ? t : Tr;
+  double S;
+  if (kind == TLVLBM_RAMP_LINEAR) S = 0.5 * tc * tc / Tr;
+  else S = 0.5 * tc - Tr / (2.0 * M_PI) * sin(M_PI * tc / Tr);  // sin^2 and half-cosine
+  return S + (t - tc);
+}
+
+template <int D> __device__ __forceinline__ void bc_base(const BC &b, const double *X, const double *N, double *val) {
+  double d[3], r = 0.0;
+  for (int a = 0; a < D; ++a) {
+    d[a] = X[a] - b.X0[a];
+    r += d[a] * d[a];
+  }
+  r = sqrt(r);
+  for (int i = 0; i < D; ++i) {
+    double s = b.a[i];
+    for (int A = 0; A < D; ++A) s += b.G[i * 3 + A] * d[A];
+    if (b.pr != 0.0 && r > 0.0) s += b.pr * d[i] / r;
+    s += b.pn * N[i];
+    val[i] = s;
+  }
+}
+
+// small dense solve (n <= 3) by Gaussian elimination with partial pivoting
+__device__ inline bool solve_small(int n, double *A, double *b, double *x) {
+  for (int k = 0; k < n; ++k) {
+    int pv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(A[i * n + k]) > fabs(A[pv * n + k])) pv = i;
+    if (A[pv * n + k] == 0.0) return false;
+    if (pv != k) {
+      for (int j = 0; j < n; ++j) {
+        double t = A[k * n + j];
+        A[k * n + j] = A[pv * n + j];
+        A[pv * n + j] = t;
+      }
+      double t = b[k];
+      b[k] = b[pv];
+      b[pv] = t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double lf = A[i * n + k] / A[k * n + k];
+      for (int j = k; j < n; ++j) A[i * n + j] -= lf * A[k * n + j];
+      b[i] -= lf * b[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
+    x[i] = s / A[i * n + i];
+  }
+  return true;
+}
+
+// R(h) = P(h (x) N + Gt) N - T (Eqs. 54, 56); false if det F_b <= 0
+template <int D>
+__device__ inline bool nm_residual(const double *h, const double *N, const double *Gt, const double *Tb, double mu,
+                            double lam, double *R) {
+  double F[D * D], P[D * D];
+  for (int i = 0; i < D; ++i)
+    for (int a = 0; a < D; ++a) F[i * D + a] = h[i] * N[a] + Gt[i * D + a];
+  if (!(det<D>(F) > 0.0)) return false;
+  piola<D>(F, mu, lam, P);
+  for (int i = 0; i < D; ++i) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) s += P[i * D + a] * N[a];
+    R[i] = s - Tb[i];
+    if (!__builtin_isfinite(R[i])) return false;
+  }
+  return true;
+}
+
+// Local Newton for the normal image h (Eqs. 53-56) in FP64, Jacobian
+// dR/dh = Q(N; F_b) (acoustic tensor, Eq. 19) from the tangent action;
+// accepts only det F_b > 0 with a decreasing residual (<= 10 halvings).
+template <int D>
+__device__ inline bool newton_h(const double *N, const double *Gt, const double *Tb, double mu, double lam, double tol,
+                         double *h) {
+  double R[D], Rt[D], ht[D];
+  if (!nm_residual<D>(h, N, Gt, Tb, mu, lam, R)) return false;
+  const double thr = tol * (mu > 1.0 ? mu : 1.0);
+  for (int it = 0; it <= 30; ++it) {
+    double rinf = 0.0, r2 = 0.0;
+    for (int i = 0; i < D; ++i) {
+      rinf = fmax(rinf, fabs(R[i]));
+      r2 += R[i] * R[i];
+    }
+    if (rinf <= thr) return true;
+    if (it == 30) break;
+    double F[D * D], Qm[D * D], dh[D], mR[D];
+    for (int i = 0; i < D; ++i)
+      for (int a = 0; a < D; ++a) F[i * D + a] = h[i] * N[a] + Gt[i * D + a];
+    for (int k = 0; k < D; ++k) {
+      double dF[D * D], dP[D * D];
+      for (int i = 0; i < D; ++i)
+        for (int a = 0; a < D; ++a) dF[i * D + a] = (i == k) ? N[a] : 0.0;
+      piola_tangent<D>(F, dF, mu, lam, dP);
+      for (int i = 0; i < D; ++i) {
+        double s = 0.0;
+        for (int a = 0; a < D; ++a) s += dP[i * D + a] * N[a];
+        Qm[i * D + k] = s;
+      }
+    }
+    for (int i = 0; i < D; ++i) mR[i] = -R[i];
+    if (!solve_small(D, Qm, mR, dh)) return false;
+    double step = 1.0;
+    bool acc = false;
+    for (int ls = 0; ls <= 10; ++ls) {
+      for (int i = 0; i < D; ++i) ht[i] = h[i] + step * dh[i];
+      if (nm_residual<D>(ht, N, Gt, Tb, mu, lam, Rt)) {
+        double rt2 = 0.0, rtinf = 0.0;
+        for (int i = 0; i < D; ++i) {
+          rt2 += Rt[i] * Rt[i];
+          rtinf = fmax(rtinf, fabs(Rt[i]));
+        }
+        if (rt2 < r2 || rtinf <= thr) {
+          acc = true;
+          break;
+        }
+      }
+      step *= 0.5;
+    }
+    if (!acc) return false;
+    for (int i = 0; i < D; ++i) {
+      h[i] = ht[i];
+      R[i] = Rt[i];
+    }
+  }
+  return false;
+}
+
+}  // namespace tl

@@ -109,6 +109,63 @@ struct BatchArgs {
   int flagA, flagB;
 };
 
+// host or device arguments crossing the ABI
+inline bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// device view of a borrowed input array (copied when it lives on the host)
+struct DevIn {
+  const void *ptr = nullptr;
+  void *owned = nullptr;
+  ~DevIn() {
+    if (owned) (void)hipFree(owned);
+  }
+  hipError_t take(const void *src, size_t bytes, hipStream_t st) {
+    if (!src) return hipSuccess;
+    if (is_device_ptr(src)) {
+      ptr = src;
+      return hipSuccess;
+    }
+    hipError_t e = hipMalloc(&owned, bytes);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(owned, src, bytes, hipMemcpyHostToDevice, st);
+    ptr = owned;
+    return e;
+  }
+};
+
+// device target for a caller output (staged when it lives on the host)
+struct DevOut {
+  void *user = nullptr, *ptr = nullptr, *owned = nullptr;
+  size_t bytes = 0;
+  ~DevOut() {
+    if (owned) (void)hipFree(owned);
+  }
+  hipError_t take(void *dst, size_t b) {
+    user = dst;
+    bytes = b;
+    if (!dst) return hipSuccess;
+    if (is_device_ptr(dst)) {
+      ptr = dst;
+      return hipSuccess;
+    }
+    hipError_t e = hipMalloc(&owned, b);
+    ptr = owned;
+    return e;
+  }
+  hipError_t finish(hipStream_t st) {
+    if (owned && user) return hipMemcpyAsync(user, owned, bytes, hipMemcpyDeviceToHost, st);
+    return hipSuccess;
+  }
+};
+
 void launch_batch(int D, int prec, BatchOp op, const BatchArgs &a);
 void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair,
                        hipStream_t st);
@@ -132,6 +189,7 @@ struct tlvlbm_ctx {
   void *ustar = nullptr, *ubuf = nullptr;
   uint8_t *act = nullptr;  // active mask (nullptr: all active)
   bool has_ls = false, have_state = false;
+  bool fresh = false;  // state is the one set by set_state (no step since)
   int64_t nactive = 0;
   tl::Links L;
   int64_t bid_begin[256] = {0}, bid_end[256] = {0};
@@ -150,7 +208,7 @@ struct tlvlbm_ctx {
 
 namespace tl {
 // launchers (bulk.hip)
-void launch_bulk(tlvlbm_ctx *c, bool repair);
+void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape = nullptr);
 void launch_pull_moments(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch);
 void launch_init(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0);
 void launch_get_f(tlvlbm_ctx *c, double *f, double *ustar);
@@ -159,4 +217,17 @@ void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar);
 int build_links(tlvlbm_ctx *c, const double *phi_d, const uint8_t *bid_d, std::string &err);
 void launch_cutlinks(tlvlbm_ctx *c, double tn);
 int run_projection(tlvlbm_ctx *c, bool first, double tn);
+// CG on the projection workspace with a given right-hand side (w.b) and start (w.x)
+int run_cg_given(tlvlbm_ctx *c, const uint8_t *anc_n);
+// reverse-mode tape of one step: recovered state (v, F - I) [M planes],
+// repaired F [D*D planes, projection steps], displacement seen by the cut
+// links [D planes]; any may be null
+struct TapeStep {
+  void *U, *Fr, *u;
+};
+// one step of Algorithm 1 (api.hip)
+int step_once(tlvlbm_ctx *c, const TapeStep *tp = nullptr);
+bool is_projection_step(const tlvlbm_ctx *c, int64_t step);
+// reads (and synchronises on) the device error flags
+tlvlbm_status check_flag(tlvlbm_ctx *c);
 }  // namespace tl

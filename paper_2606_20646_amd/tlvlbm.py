@@ -81,6 +81,7 @@ def _load():
     L.tlvlbm_population_bytes.argtypes = [vp]
     L.tlvlbm_population_bytes.restype = C.c_size_t
     L.tlvlbm_step_each.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64]
+    L.tlvlbm_adjoint.argtypes = [vp, C.c_int64, dp, dp, dp, dp, C.POINTER(C.c_double), dp, dp, C.c_int64]
     L.tlvlbm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
     L.tlvlbm_batch_step.argtypes = [vp, C.c_int64]
     L.tlvlbm_batch_set_graph.argtypes = [vp, C.c_int32]
@@ -89,7 +90,7 @@ def _load():
     L.tlvlbm_batch_last_error.restype = C.c_char_p
     for name in ("create", "destroy", "set_levelset", "set_boundary", "set_material", "set_state", "step",
                  "moments", "get_state", "put_state", "get_links", "stats", "synchronize", "step_each",
-                 "batch_create", "batch_step", "batch_set_graph", "batch_destroy"):
+                 "batch_create", "batch_step", "batch_set_graph", "batch_destroy", "adjoint"):
         getattr(L, "tlvlbm_" + name).restype = C.c_int
     return L
 
@@ -187,6 +188,21 @@ class Solver:
                 for a in (U0, u0, dU0)]
         ptrs = [_ptr(a) for a in arrs]
         self._chk(lib.tlvlbm_set_state(self.h, ptrs[0][0], ptrs[1][0], ptrs[2][0]), "set_state")
+        self._init = (arrs[0], arrs[2])  # the reverse mode transposes the initialisation
+
+    def adjoint(self, n, dLdU=None, dLdu=None, segment=0, grad_v0=True, grad_u0=True):
+        """Advance n steps from the state of set_state and return
+        (dL/d(mu, lambda), dL/dv0 [D][N], dL/du0 [D][N]) for
+        L = sum dLdU . U + dLdu . u over the moments after the last step."""
+        U0, dU0 = self._init
+        gm = (C.c_double * 2)()
+        gv = np.zeros((self.D, self.N)) if grad_v0 else None
+        g0 = np.zeros((self.D, self.N)) if grad_u0 else None
+        args = [a if (a is None or not isinstance(a, np.ndarray)) else np.ascontiguousarray(a, np.float64)
+                for a in (dLdU, dLdu)]
+        self._chk(lib.tlvlbm_adjoint(self.h, int(n), _ptr(U0)[0], _ptr(dU0)[0], _ptr(args[0])[0], _ptr(args[1])[0],
+                                     gm, _ptr(gv)[0], _ptr(g0)[0], int(segment)), "adjoint")
+        return np.array([gm[0], gm[1]]), gv, g0
 
     def step(self, n=1):
         self._chk(lib.tlvlbm_step(self.h, int(n)), "step")

@@ -1,0 +1,110 @@
+"""GPU reverse mode (project extension) against the oracle's reverse mode.
+
+Same cases as the oracle's finite-difference pins (periodic 2D with damping,
+periodic 3D, Dirichlet annulus, Neumann annulus with and without the
+projection, Neumann sphere).  The GPU adjoint (checkpointed forward,
+recomputed segments, transposed kernels) must reproduce the oracle's
+gradients dL/d(mu, lambda), dL/dv0 and dL/du0: FP64 populations to 1e-9
+relative (the two sides solve the projection to different CG tolerances,
+1e-14 against 1e-15; measured <= 3e-12), FP32 populations to 1e-4 (FP32
+rounding accumulated over the steps; measured <= 1e-5).  Different checkpoint
+segment lengths give the same result (the recomputation is deterministic).
+"""
+import numpy as np
+import pytest
+
+from test_oracle_adjoint import CASES, _make
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    from paper_2606_20646_amd import tlvlbm
+    torch.cuda.set_device(0)
+    return tlvlbm
+
+
+def _solver(T, cfg, precision):
+    s = T.Solver(cfg["D"], cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"],
+                 gamma=cfg["gamma"], origin=cfg.get("origin"), periodic_mask=cfg.get("pm", cfg.get("periodic_mask")),
+                 proj_every=cfg.get("proj_every", 20), precision=precision, track_u=1)
+    if "phi" in cfg:
+        s.set_levelset(cfg["phi"], cfg["bid"])
+        for bid, bc in cfg["bcs"].items():
+            bc = dict(bc)
+            s.set_boundary(bid, bc.pop("type"), **bc)
+    return s
+
+
+def _weights(cfg):
+    rng = np.random.default_rng(11)
+    D, N = cfg["D"], int(np.prod(cfg["n"]))
+    M = D + D * D
+    act = (cfg["phi"] <= 0).reshape(-1) if "phi" in cfg else np.ones(N, bool)
+    return rng.standard_normal((M, N)) * act, rng.standard_normal((D, N)) * act
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_matches_oracle(T, orc, name, precision, tol):
+    _say(f"adjoint {name} {precision}")
+    make, n = CASES[name]
+    cfg = make()
+    wU, wu = _weights(cfg)
+    u0 = cfg.get("u0")
+    o = _make(cfg, cfg["mu"], cfg["lam"])
+    o.set_state(cfg["U0"], u0=u0, dU0=cfg.get("dU0"))
+    gm_o, gv_o, g0_o = o.adjoint(n, wU, wu)
+    s = _solver(T, cfg, precision)
+    s.set_state(cfg["U0"], u0=u0, dU0=cfg.get("dU0"))
+    gm, gv, g0 = s.adjoint(n, wU, wu)
+    assert s.stats()["step"] == n
+    print(f"mu,lam: gpu {gm} oracle {gm_o}; v0 rel {_rel(gv, gv_o):.2e}; u0 rel {_rel(g0, g0_o):.2e}", flush=True)
+    scale = np.abs(gm_o).max()
+    assert np.all(np.abs(gm - gm_o) <= tol * scale)
+    assert _rel(gv, gv_o) <= tol
+    if np.linalg.norm(g0_o) > 1e-12 * np.linalg.norm(gv_o):
+        assert _rel(g0, g0_o) <= tol
+    else:
+        assert np.linalg.norm(g0) <= tol * np.linalg.norm(gv_o)
+    # the context ends at step n with the forward state
+    U, u, _ = s.moments()
+    Uo, uo, _ = o.moments()
+    assert _rel(U, Uo) <= (1e-11 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("name", ["neumann_annulus_projection", "periodic2d_damped"])
+def test_adjoint_segments_agree(T, name):
+    _say(f"adjoint segments {name}")
+    make, n = CASES[name]
+    cfg = make()
+    wU, wu = _weights(cfg)
+    out = []
+    for seg in (0, 1, 4, n):
+        s = _solver(T, cfg, "fp64")
+        s.set_state(cfg["U0"], u0=cfg.get("u0"), dU0=cfg.get("dU0"))
+        out.append(s.adjoint(n, wU, wu, segment=seg))
+    for gm, gv, g0 in out[1:]:
+        assert np.array_equal(gm, out[0][0])
+        assert np.array_equal(gv, out[0][1])
+        assert np.array_equal(g0, out[0][2])
+
+
+def test_adjoint_requires_fresh_state(T):
+    make, n = CASES["periodic2d_damped"]
+    cfg = make()
+    s = _solver(T, cfg, "fp64")
+    s.set_state(cfg["U0"], dU0=cfg["dU0"])
+    s.step(1)
+    with pytest.raises(T.TlvlbmError):
+        s.adjoint(2, np.ones((6, s.N)))

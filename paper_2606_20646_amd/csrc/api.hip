@@ -204,7 +204,7 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
   void *ptrs[] = {c->fA, c->fB, c->ustar, c->ubuf, c->act, c->d_flag, c->d_newton_fail, c->L.node, c->L.out,
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
-                  c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.counter};
+                  c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);

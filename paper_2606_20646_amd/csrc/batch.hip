@@ -198,7 +198,6 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       I.anc_i = c->cg.anc_i;
       I.partial = c->cg.partial;
       I.scal = c->cg.scal;
-      I.counter = c->cg.counter;
       I.nblk = c->cg.nblk;
       I.flag = c->d_flag;
       I.nfail = (unsigned long long *)c->d_newton_fail;

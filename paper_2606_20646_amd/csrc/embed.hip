@@ -586,14 +586,14 @@ constexpr int PSTRIDE = 16;
 
 constexpr int CG_T = 256;
 
-// block reduction of up to PSTRIDE doubles, written to partial[blk*PSTRIDE + k];
-// the last block to finish sums all partials in a fixed order (deterministic)
-// and returns true with the totals in tot
+// Reductions: every block writes its partial sums to partial[blk*PSTRIDE + k]
+// (no fence, no atomic); a one-block finalize kernel launched next sums the
+// partials in a fixed order (deterministic) and updates the CG scalars.  A
+// device-scope release fence per block would write back the whole L2 of its
+// XCD, which made each reduction cost far more than the sweep it ends.
 template <int K>
-__device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, unsigned *counter, double *tot,
-                                               int blk, int nblk) {
+__device__ __forceinline__ void block_store(double (&v)[K], double *partial, int blk) {
   __shared__ double sh[CG_T / 64][PSTRIDE];
-  __shared__ bool last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -607,25 +607,19 @@ __device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, 
     for (int w = 0; w < CG_T / 64; ++w) s += sh[w][threadIdx.x];
     partial[blk * PSTRIDE + threadIdx.x] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned t = atomicAdd(counter, 1u);
-    last = (t == (unsigned)nblk - 1);
-  }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  // the last block sums the partials in a fixed order: a strided pass over
-  // the blocks per thread, then the wave and block trees
-  __shared__ double tsum[PSTRIDE];
+}
+
+// totals of the K partial sums over nblk blocks (one block of CG_T threads)
+template <int K>
+__device__ __forceinline__ void block_totals(const double *partial, int nblk, double *tot) {
+  __shared__ double sh[CG_T / 64][PSTRIDE];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  const volatile double *pv = partial;
   for (int b = threadIdx.x; b < nblk; b += CG_T)
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += pv[b * PSTRIDE + k];
+    for (int k = 0; k < K; ++k) acc[k] += partial[b * PSTRIDE + k];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double x = acc[k];
@@ -633,16 +627,12 @@ __device__ __forceinline__ bool block_partials(double (&v)[K], double *partial, 
     if (lane == 0) sh[wid][k] = x;
   }
   __syncthreads();
-  if (threadIdx.x < K) {
-    double s = 0.0;
-    for (int w = 0; w < CG_T / 64; ++w) s += sh[w][threadIdx.x];
-    tsum[threadIdx.x] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) tot[k] = tsum[k];
-  if (threadIdx.x == 0) *counter = 0u;
-  return true;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < K; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < CG_T / 64; ++w) t += sh[w][k];
+      tot[k] = t;
+    }
 }
 
 // r = b - A x, p = r, rr and bb (A = active-graph Laplacian + anchors)
@@ -650,8 +640,7 @@ template <int D, typename T>
 __device__ __forceinline__ void cg_init_blk(const Geo &g, const uint8_t *__restrict__ act,
                                             const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
                                             const double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
-                                            double *partial, unsigned *counter, double *scal, double rtol, int blk,
-                                            int nblk) {
+                                            double *partial, int blk) {
   const int64_t i = blk * (int64_t)CG_T + threadIdx.x;
   double v[2 * D];
   for (int k = 0; k < 2 * D; ++k) v[k] = 0.0;
@@ -683,8 +672,11 @@ __device__ __forceinline__ void cg_init_blk(const Geo &g, const uint8_t *__restr
       }
     }
   }
-  double tot[PSTRIDE];
-  if (block_partials<2 * D>(v, partial, counter, tot, blk, nblk) && threadIdx.x == 0) {
+  block_store<2 * D>(v, partial, blk);
+}
+
+template <int D> __device__ __forceinline__ void cg_init_fin(const double *tot, double *scal, double rtol) {
+  {
     bool all = true;
     for (int c = 0; c < D; ++c) {
       const double rr = tot[c], bb = tot[D + c];
@@ -706,7 +698,7 @@ template <int D, typename T>
 __device__ __forceinline__ void cg_Ap_blk(const Geo &g, const uint8_t *__restrict__ act,
                                           const uint8_t *__restrict__ anc_n, const double *__restrict__ r,
                                           const double *__restrict__ pold, double *__restrict__ pnew, double *__restrict__ Ap,
-                                          double *partial, unsigned *counter, double *scal, int blk, int nblk) {
+                                          double *partial, const double *scal, int blk) {
   if (scal[S_DONE] != 0.0) return;
   const int64_t i = blk * (int64_t)CG_T + threadIdx.x;
   double v[D];
@@ -738,8 +730,11 @@ __device__ __forceinline__ void cg_Ap_blk(const Geo &g, const uint8_t *__restric
       Ap[(size_t)c * g.S + i] = double(0);
     }
   }
-  double tot[PSTRIDE];
-  if (block_partials<D>(v, partial, counter, tot, blk, nblk) && threadIdx.x == 0) {
+  block_store<D>(v, partial, blk);
+}
+
+template <int D> __device__ __forceinline__ void cg_Ap_fin(const double *tot, double *scal) {
+  {
     for (int c = 0; c < D; ++c) {
       const bool on = scal[S_ACT + c] != 0.0 && tot[c] > 0.0;
       scal[S_ALPHA + c] = on ? scal[S_RR + c] / tot[c] : 0.0;
@@ -752,7 +747,7 @@ __device__ __forceinline__ void cg_Ap_blk(const Geo &g, const uint8_t *__restric
 template <int D, typename T>
 __device__ __forceinline__ void cg_update_blk(const Geo &g, const uint8_t *__restrict__ act, double *__restrict__ x,
                                               double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ Ap,
-                                              double *partial, unsigned *counter, double *scal, int blk, int nblk) {
+                                              double *partial, const double *scal, int blk) {
   if (scal[S_DONE] != 0.0) return;
   const int64_t i = blk * (int64_t)CG_T + threadIdx.x;
   double v[D];
@@ -767,8 +762,11 @@ __device__ __forceinline__ void cg_update_blk(const Geo &g, const uint8_t *__res
       v[c] = double(ri) * double(ri);
     }
   }
-  double tot[PSTRIDE];
-  if (block_partials<D>(v, partial, counter, tot, blk, nblk) && threadIdx.x == 0) {
+  block_store<D>(v, partial, blk);
+}
+
+template <int D> __device__ __forceinline__ void cg_update_fin(const double *tot, double *scal) {
+  {
     bool all = true;
     for (int c = 0; c < D; ++c) {
       if (scal[S_ACT + c] != 0.0) {
@@ -861,26 +859,49 @@ template <int D, typename T>
 __global__ __launch_bounds__(CG_T) void k_cg_init(Geo g, const uint8_t *__restrict__ act,
                                                    const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
                                                    const double *__restrict__ x, double *__restrict__ r,
-                                                   double *__restrict__ p, double *partial, unsigned *counter,
-                                                   double *scal, double rtol) {
-  cg_init_blk<D, T>(g, act, anc_n, b, x, r, p, partial, counter, scal, rtol, blockIdx.x, gridDim.x);
+                                                   double *__restrict__ p, double *partial) {
+  cg_init_blk<D, T>(g, act, anc_n, b, x, r, p, partial, blockIdx.x);
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(CG_T) void k_cg_Ap(Geo g, const uint8_t *__restrict__ act,
                                                  const uint8_t *__restrict__ anc_n, const double *__restrict__ r,
                                                  const double *__restrict__ pold, double *__restrict__ pnew,
-                                                 double *__restrict__ Ap, double *partial, unsigned *counter,
-                                                 double *scal) {
-  cg_Ap_blk<D, T>(g, act, anc_n, r, pold, pnew, Ap, partial, counter, scal, blockIdx.x, gridDim.x);
+                                                 double *__restrict__ Ap, double *partial, const double *scal) {
+  cg_Ap_blk<D, T>(g, act, anc_n, r, pold, pnew, Ap, partial, scal, blockIdx.x);
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(CG_T) void k_cg_update(Geo g, const uint8_t *__restrict__ act, double *__restrict__ x,
                                                      double *__restrict__ r, const double *__restrict__ p,
                                                      const double *__restrict__ Ap, double *partial,
-                                                     unsigned *counter, double *scal) {
-  cg_update_blk<D, T>(g, act, x, r, p, Ap, partial, counter, scal, blockIdx.x, gridDim.x);
+                                                     const double *scal) {
+  cg_update_blk<D, T>(g, act, x, r, p, Ap, partial, scal, blockIdx.x);
+}
+
+// finalize of a CG reduction (one block): OP 0 init, 1 p.Ap, 2 update
+template <int D, int OP>
+__device__ __forceinline__ void cg_fin(const double *partial, int nblk, double *scal, double rtol) {
+  if (OP != 0 && scal[S_DONE] != 0.0) return;
+  __shared__ double tot[PSTRIDE];
+  block_totals<(OP == 0 ? 2 * D : D)>(partial, nblk, tot);
+  if (threadIdx.x == 0) {
+    if (OP == 0) cg_init_fin<D>(tot, scal, rtol);
+    else if (OP == 1) cg_Ap_fin<D>(tot, scal);
+    else cg_update_fin<D>(tot, scal);
+  }
+}
+
+template <int D, int OP>
+__global__ __launch_bounds__(CG_T) void k_cg_fin(const double *partial, int nblk, double *scal, double rtol) {
+  cg_fin<D, OP>(partial, nblk, scal, rtol);
+}
+
+// one block per instance
+template <int D, int OP>
+__global__ __launch_bounds__(CG_T) void k_cg_fin_batch(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  cg_fin<D, OP>(I.partial, I.nblk, I.scal, I.rtol);
 }
 
 template <int D, typename T>
@@ -1061,8 +1082,6 @@ template <int D, typename T> static int cg_alloc(tlvlbm_ctx *c) {
   w.nblk = (int)nblk(c->geo.N, CG_T);
   HIP_OK(hipMalloc(&w.partial, (size_t)w.nblk * PSTRIDE * sizeof(double)));
   HIP_OK(hipMalloc(&w.scal, S_NSCAL * sizeof(double)));
-  HIP_OK(hipMalloc(&w.counter, sizeof(unsigned)));
-  HIP_OK(hipMemsetAsync(w.counter, 0, sizeof(unsigned), c->st));
   return TLVLBM_OK;
 }
 
@@ -1111,7 +1130,8 @@ template <int D, typename T> static int cg_run(tlvlbm_ctx *c, const uint8_t *anc
   hipStream_t st = c->st;
   const double rtol = c->cg_rtol > 0 ? c->cg_rtol : cg_default_rtol(c->prec);
   hipLaunchKernelGGL((k_cg_init<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
-                     (const double *)w.x, (double *)w.r, (double *)w.p0, w.partial, w.counter, w.scal, rtol);
+                     (const double *)w.x, (double *)w.r, (double *)w.p0, w.partial);
+  hipLaunchKernelGGL((k_cg_fin<D, 0>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, rtol);
   const int64_t maxit = c->cg_maxit > 0 ? c->cg_maxit : cg_default_maxit(c->nactive);
   double *pa = (double *)w.p0, *pb = (double *)w.p1;
   int64_t it = 0;
@@ -1119,9 +1139,11 @@ template <int D, typename T> static int cg_run(tlvlbm_ctx *c, const uint8_t *anc
     const int64_t batch = std::min<int64_t>(32, maxit - it);
     for (int64_t k = 0; k < batch; ++k) {
       hipLaunchKernelGGL((k_cg_Ap<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)w.r, pa, pb,
-                         (double *)w.Ap, w.partial, w.counter, w.scal);
+                         (double *)w.Ap, w.partial, w.scal);
+      hipLaunchKernelGGL((k_cg_fin<D, 1>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
       hipLaunchKernelGGL((k_cg_update<D, T>), w.nblk, CG_T, 0, st, g, c->act, (double *)w.x, (double *)w.r, pb,
-                         (const double *)w.Ap, w.partial, w.counter, w.scal);
+                         (const double *)w.Ap, w.partial, w.scal);
+      hipLaunchKernelGGL((k_cg_fin<D, 2>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
       std::swap(pa, pb);
     }
     it += batch;
@@ -1248,7 +1270,7 @@ __global__ __launch_bounds__(CG_T) void k_cg_init_batch(const Inst *__restrict__
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
   cg_init_blk<D, T>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.b, (const double *)I.x,
-                    (double *)I.r, (double *)I.p0, I.partial, I.counter, I.scal, I.rtol, t.y, I.nblk);
+                    (double *)I.r, (double *)I.p0, I.partial, t.y);
 }
 
 template <int D, typename T>
@@ -1259,7 +1281,7 @@ __global__ __launch_bounds__(CG_T) void k_cg_Ap_batch(const Inst *__restrict__ i
   const double *pold = (const double *)(pp ? I.p1 : I.p0);
   double *pnew = (double *)(pp ? I.p0 : I.p1);
   cg_Ap_blk<D, T>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.r, pold, pnew, (double *)I.Ap,
-                  I.partial, I.counter, I.scal, t.y, I.nblk);
+                  I.partial, I.scal, t.y);
 }
 
 template <int D, typename T>
@@ -1268,8 +1290,8 @@ __global__ __launch_bounds__(CG_T) void k_cg_update_batch(const Inst *__restrict
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
   const double *pnew = (const double *)(pp ? I.p0 : I.p1);
-  cg_update_blk<D, T>(I.g, I.act, (double *)I.x, (double *)I.r, pnew, (const double *)I.Ap, I.partial, I.counter,
-                      I.scal, t.y, I.nblk);
+  cg_update_blk<D, T>(I.g, I.act, (double *)I.x, (double *)I.r, pnew, (const double *)I.Ap, I.partial, I.scal,
+                      t.y);
 }
 
 template <int D, typename T>
@@ -1330,12 +1352,15 @@ static void batch_kernels_t(BatchOp op, const BatchArgs &a) {
       break;
     case BatchOp::CgInit:
       hipLaunchKernelGGL((k_cg_init_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagB);
+      hipLaunchKernelGGL((k_cg_fin_batch<D, 0>), a.ninst, CG_T, 0, st, a.insts);
       break;
     case BatchOp::CgAp:
       hipLaunchKernelGGL((k_cg_Ap_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA, a.flagB);
+      hipLaunchKernelGGL((k_cg_fin_batch<D, 1>), a.ninst, CG_T, 0, st, a.insts);
       break;
     case BatchOp::CgUpdate:
       hipLaunchKernelGGL((k_cg_update_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA);
+      hipLaunchKernelGGL((k_cg_fin_batch<D, 2>), a.ninst, CG_T, 0, st, a.insts);
       break;
     case BatchOp::GradF:
       hipLaunchKernelGGL((k_gradF_batch<D, T>), a.nct, 256, 0, st, a.insts, a.ctiles);

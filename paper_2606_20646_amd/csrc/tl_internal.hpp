@@ -59,7 +59,6 @@ struct CG {
   void *anc_s = nullptr;                            // anchor target sums [D][S] (FP64)
   double *partial = nullptr;                        // [nblk][16] block partial sums
   double *scal = nullptr;                           // device scalars
-  unsigned *counter = nullptr;
   int nblk = 0;
 };
 
@@ -79,7 +78,6 @@ struct Inst {
   uint8_t *anc_n;
   int *anc_i;
   double *partial, *scal;
-  unsigned *counter;
   int nblk;  // node tiles of 256 of this instance (CG reductions)
   int *flag;
   unsigned long long *nfail;

@@ -96,6 +96,8 @@ typedef struct {
   int32_t track_u;    /* 1: carry the displacement quadrature (Eq. 34); 0: not; -1: auto
                          (on whenever a level set is set) */
   void *stream;       /* hipStream_t for all work; NULL = default stream */
+  int32_t cg_multigrid; /* 1: projection CG preconditioned by one geometric multigrid V-cycle
+                           per iteration (aggregation of 2^D blocks, damped Jacobi); 0: plain CG */
 } tlvlbm_options;
 
 /* Boundary condition attached to a boundary identifier (Sec. 3.1).

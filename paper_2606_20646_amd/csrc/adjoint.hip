@@ -467,48 +467,6 @@ __global__ __launch_bounds__(AT) void k_adj_ugather(int64_t ns, const int64_t *_
 }
 
 // --------------------------------------------------- projection transposes
-// per-tile sums of u_bar over the nodes of components without anchors
-template <int D>
-__global__ __launch_bounds__(AT) void k_pi_tiles(const int32_t *__restrict__ cn, Geo g, const double *__restrict__ ua,
-                                                 const double *__restrict__ ub, double *__restrict__ tpart) {
-  __shared__ double sh[AT / 64][D];
-  const int32_t j = cn[(size_t)blockIdx.x * AT + threadIdx.x];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int i = 0; i < D; ++i) {
-    double v = 0.0;
-    if (j >= 0) v = ua[(size_t)i * g.S + j] + (ub ? ub[(size_t)i * g.S + j] : 0.0);
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) sh[wid][i] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < D) {
-    double s = 0.0;
-    for (int w = 0; w < AT / 64; ++w) s += sh[w][threadIdx.x];
-    tpart[(size_t)blockIdx.x * D + threadIdx.x] = s;
-  }
-}
-
-// component means from the tile sums (one block per component)
-template <int D>
-__global__ __launch_bounds__(AT) void k_pi_comp(const int64_t *__restrict__ ct, const int64_t *__restrict__ cnt,
-                                                const double *__restrict__ tpart, double *__restrict__ mean) {
-  __shared__ double sh[AT / 64][D];
-  const int c = blockIdx.x;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int i = 0; i < D; ++i) {
-    double v = 0.0;
-    for (int64_t t = ct[c] + threadIdx.x; t < ct[c + 1]; t += AT) v += tpart[t * D + i];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) sh[wid][i] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < D) {
-    double s = 0.0;
-    for (int w = 0; w < AT / 64; ++w) s += sh[w][threadIdx.x];
-    mean[(size_t)c * D + threadIdx.x] = s / double(cnt[c]);
-  }
-}
-
 // x0_bar = projection of u_bar onto the null space of K, CG right-hand side
 // b = u_bar - x0_bar, start x = 0
 template <int D>
@@ -717,11 +675,6 @@ struct Run {
   double *lus = nullptr, *ubc = nullptr, *gbar = nullptr, *glink = nullptr, *gblk = nullptr, *ginit = nullptr;
   // projection
   double *UaB = nullptr, *Fcb = nullptr, *Fext = nullptr, *Frb = nullptr, *x0b = nullptr, *ucb = nullptr;
-  int32_t *comp = nullptr, *cn = nullptr;
-  int64_t *ct = nullptr, *ccnt = nullptr;
-  double *tpart = nullptr, *mean = nullptr;
-  int64_t nu = 0, ntile = 0;
-  uint8_t *anc_n = nullptr;
   // stencil gather
   int64_t ns = 0;
   int64_t *sn = nullptr, *so = nullptr;
@@ -759,13 +712,11 @@ template <int D> int solve_adj(Run &R, const double *ua, const double *ub) {
   tlvlbm_ctx *c = R.c;
   CG &w = c->cg;
   const Geo &g = c->geo;
-  if (R.nu > 0) {
-    hipLaunchKernelGGL((k_pi_tiles<D>), (unsigned)R.ntile, AT, 0, c->st, R.cn, g, ua, ub, R.tpart);
-    hipLaunchKernelGGL((k_pi_comp<D>), (unsigned)R.nu, AT, 0, c->st, R.ct, R.ccnt, R.tpart, R.mean);
-  }
-  hipLaunchKernelGGL((k_pi_apply<D>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, R.comp, R.mean, ua, ub, R.x0b,
+  const Gauge &G = *c->gauge;
+  gauge_means(c, ua, ub, G.mean);
+  hipLaunchKernelGGL((k_pi_apply<D>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, G.comp, G.mean, ua, ub, R.x0b,
                      (double *)w.b, (double *)w.x);
-  return run_cg_given(c, R.dir ? R.anc_n : nullptr);
+  return run_cg_given(c, R.dir ? G.anc_n : nullptr);
 }
 
 template <int D> void anchors_T(Run &R, const double *y, double *Fb) {
@@ -833,102 +784,21 @@ template <int D, typename T> int reverse_step(Run &R, int64_t k, const TapeStep 
   return hipGetLastError() == hipSuccess ? TLVLBM_OK : TLVLBM_ERR_DEVICE;
 }
 
-// host preparation: connected components of the active graph without
-// anchors, anchor counts, and the transposed LSQ stencils of Neumann links
+// host preparation: the transposed LSQ stencils of the Neumann links
 template <int D> int prepare_host(Run &R, Pool &pool) {
   tlvlbm_ctx *c = R.c;
-  const Geo &g = c->geo;
-  const int64_t N = g.N;
-  std::vector<uint8_t> act(N);
-  if (hipMemcpy(act.data(), c->act, N, hipMemcpyDeviceToHost) != hipSuccess) return TLVLBM_ERR_DEVICE;
   const int64_t nl = c->L.n;
-  std::vector<int64_t> lnode(nl);
-  std::vector<int32_t> lq(nl), lnp(nl), sidx((size_t)nl * c->L.kmax);
+  std::vector<int32_t> lnp(nl), sidx((size_t)nl * c->L.kmax);
   if (nl) {
-    if (hipMemcpy(lnode.data(), c->L.node, nl * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(lq.data(), c->L.q, nl * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(lnp.data(), c->L.npts, nl * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+    if (hipMemcpy(lnp.data(), c->L.npts, nl * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(sidx.data(), c->L.sidx, sidx.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
       return TLVLBM_ERR_DEVICE;
   }
-  std::vector<uint8_t> is_neu(nl, 0), is_dir(nl, 0);
+  std::vector<uint8_t> is_neu(nl, 0);
   for (int b = 0; b < 256; ++b)
-    for (int64_t l = c->bid_begin[b]; l < c->bid_end[b]; ++l) {
+    for (int64_t l = c->bid_begin[b]; l < c->bid_end[b]; ++l)
       is_neu[l] = c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION;
-      is_dir[l] = c->bcs[b].type == TLVLBM_BC_DIRICHLET_VELOCITY;
-    }
-  // anchor counts
-  std::vector<uint8_t> an(N, 0);
-  for (int64_t l = 0; l < nl; ++l)
-    if (is_dir[l]) an[lnode[l]]++;
-  // components (breadth-first over active lattice neighbours)
-  std::vector<int32_t> comp(N, -1), cid(N, -1);
-  std::vector<int64_t> stack;
-  int32_t nc = 0;
-  const int n3[3] = {g.nx, g.ny, g.nz};
-  for (int64_t s0 = 0; s0 < N; ++s0) {
-    if (!act[s0] || cid[s0] >= 0) continue;
-    cid[s0] = nc;
-    stack.assign(1, s0);
-    while (!stack.empty()) {
-      const int64_t m = stack.back();
-      stack.pop_back();
-      int cc[3] = {(int)(m % g.nx), (int)((m / g.nx) % g.ny), (int)(m / ((int64_t)g.nx * g.ny))};
-      for (int q = 0; q < 2 * D; ++q) {
-        int v[3] = {cc[0], cc[1], cc[2]};
-        v[q / 2] += (q & 1) ? -1 : 1;
-        const int A = q / 2;
-        if (v[A] < 0 || v[A] >= n3[A]) {
-          if (!((g.per >> A) & 1)) continue;
-          v[A] = (v[A] + n3[A]) % n3[A];
-        }
-        const int64_t j = v[0] + (int64_t)g.nx * (v[1] + (int64_t)g.ny * v[2]);
-        if (act[j] && cid[j] < 0) {
-          cid[j] = nc;
-          stack.push_back(j);
-        }
-      }
-    }
-    ++nc;
-  }
-  std::vector<uint8_t> anch(nc, 0);
-  for (int64_t m = 0; m < N; ++m)
-    if (act[m] && an[m]) anch[cid[m]] = 1;
-  std::vector<int32_t> uidx(nc, -1);
-  int32_t nu = 0;
-  for (int32_t k = 0; k < nc; ++k)
-    if (!anch[k]) uidx[k] = nu++;
-  std::vector<std::vector<int32_t>> members(nu);
-  for (int64_t m = 0; m < N; ++m)
-    if (act[m] && uidx[cid[m]] >= 0) {
-      comp[m] = uidx[cid[m]];
-      members[comp[m]].push_back((int32_t)m);
-    }
-  std::vector<int32_t> cn;
-  std::vector<int64_t> ct(nu + 1, 0), ccnt(nu, 0);
-  for (int32_t k = 0; k < nu; ++k) {
-    ct[k] = (int64_t)(cn.size() / AT);
-    ccnt[k] = (int64_t)members[k].size();
-    cn.insert(cn.end(), members[k].begin(), members[k].end());
-    while (cn.size() % AT) cn.push_back(-1);
-  }
-  ct[nu] = (int64_t)(cn.size() / AT);
-  R.nu = nu;
-  R.ntile = ct[nu];
   hipStream_t st = c->st;
-  if (pool.get(&R.comp, N * sizeof(int32_t), st, false) != hipSuccess ||
-      pool.get(&R.anc_n, N, st, false) != hipSuccess || pool.get(&R.cn, cn.size() * sizeof(int32_t), st, false) ||
-      pool.get(&R.ct, ct.size() * sizeof(int64_t), st, false) ||
-      pool.get(&R.ccnt, (ccnt.size() + 1) * sizeof(int64_t), st, false) ||
-      pool.get(&R.tpart, ((size_t)R.ntile + 1) * D * sizeof(double), st) ||
-      pool.get(&R.mean, ((size_t)nu + 1) * D * sizeof(double), st))
-    return TLVLBM_ERR_OUT_OF_MEMORY;
-  if (hipMemcpy(R.comp, comp.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) ||
-      hipMemcpy(R.anc_n, an.data(), N, hipMemcpyHostToDevice) ||
-      (cn.size() && hipMemcpy(R.cn, cn.data(), cn.size() * sizeof(int32_t), hipMemcpyHostToDevice)) ||
-      hipMemcpy(R.ct, ct.data(), ct.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
-      (nu && hipMemcpy(R.ccnt, ccnt.data(), ccnt.size() * sizeof(int64_t), hipMemcpyHostToDevice)))
-    return TLVLBM_ERR_DEVICE;
   // transposed Neumann stencils: entries (node, link, point), sorted
   struct E {
     int32_t j, l, k;
@@ -1069,8 +939,12 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
       return TLVLBM_ERR_OUT_OF_MEMORY;
   }
   if (c->act) {
-    const int s = prepare_host<D>(R, pool);
+    int s = prepare_host<D>(R, pool);
     if (s) return (tlvlbm_status)s;
+    if (!c->gauge || c->aux_stale) {
+      s = proj_aux_build(c);
+      if (s) return (tlvlbm_status)s;
+    }
   }
   // per-step tape of one segment
   char *tapeU = nullptr, *tapeu = nullptr, *tapeF = nullptr;

@@ -118,6 +118,7 @@ void tlvlbm_default_options(tlvlbm_options *o) {
   o->cg_rtol = 0.0;
   o->proj_every = 20;
   o->cg_maxit = 0;
+  o->cg_multigrid = 1;
   o->precision = TLVLBM_FP32;
   o->track_u = -1;
   o->stream = nullptr;
@@ -174,6 +175,7 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   c->cg_rtol = o.cg_rtol;
   c->proj_every = o.proj_every;
   c->cg_maxit = o.cg_maxit;
+  c->cg_multigrid = o.cg_multigrid ? 1 : 0;
   c->track_opt = o.track_u;
   c->track_u = o.track_u == 1;
   c->st = (hipStream_t)o.stream;
@@ -204,11 +206,12 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
   void *ptrs[] = {c->fA, c->fB, c->ustar, c->ubuf, c->act, c->d_flag, c->d_newton_fail, c->L.node, c->L.out,
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
-                  c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal};
+                  c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
   if (c->hscal) (void)hipHostFree(c->hscal);
+  proj_aux_free(c);
   delete c;
   return TLVLBM_OK;
 }
@@ -262,6 +265,7 @@ tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *c, uint8_t bid, const tlvlbm_bc *b
   b.pr = bc->p_radial;
   b.pn = bc->p_normal;
   c->bc_set[bid] = true;
+  c->aux_stale = true;  // projection anchors and components follow the conditions
   return TLVLBM_OK;
 }
 

@@ -579,8 +579,6 @@ __device__ __forceinline__ void cg_rhs_node(const Geo &g, const uint8_t *__restr
   }
 }
 
-// scalar slots of the CG state (device doubles)
-enum { S_RR = 0, S_BB = 4, S_THR = 8, S_ALPHA = 12, S_BETA = 16, S_ACT = 20, S_ITS = 24, S_DONE = 28, S_NSCAL = 32 };
 // block partials: up to PSTRIDE doubles per block
 constexpr int PSTRIDE = 16;
 
@@ -733,11 +731,11 @@ __device__ __forceinline__ void cg_Ap_blk(const Geo &g, const uint8_t *__restric
   block_store<D>(v, partial, blk);
 }
 
-template <int D> __device__ __forceinline__ void cg_Ap_fin(const double *tot, double *scal) {
+template <int D> __device__ __forceinline__ void cg_Ap_fin(const double *tot, double *scal, bool pc) {
   {
     for (int c = 0; c < D; ++c) {
       const bool on = scal[S_ACT + c] != 0.0 && tot[c] > 0.0;
-      scal[S_ALPHA + c] = on ? scal[S_RR + c] / tot[c] : 0.0;
+      scal[S_ALPHA + c] = on ? scal[(pc ? S_RZ : S_RR) + c] / tot[c] : 0.0;
       if (!on) scal[S_ACT + c] = 0.0;
     }
   }
@@ -765,14 +763,14 @@ __device__ __forceinline__ void cg_update_blk(const Geo &g, const uint8_t *__res
   block_store<D>(v, partial, blk);
 }
 
-template <int D> __device__ __forceinline__ void cg_update_fin(const double *tot, double *scal) {
+template <int D> __device__ __forceinline__ void cg_update_fin(const double *tot, double *scal, bool pc) {
   {
     bool all = true;
     for (int c = 0; c < D; ++c) {
       if (scal[S_ACT + c] != 0.0) {
         scal[S_ITS + c] += 1.0;
         const double rr2 = tot[c];
-        scal[S_BETA + c] = rr2 / scal[S_RR + c];
+        if (!pc) scal[S_BETA + c] = rr2 / scal[S_RR + c];
         scal[S_RR + c] = rr2;
         if (!(rr2 > scal[S_THR + c])) scal[S_ACT + c] = 0.0;
       } else {
@@ -879,29 +877,53 @@ __global__ __launch_bounds__(CG_T) void k_cg_update(Geo g, const uint8_t *__rest
   cg_update_blk<D, T>(g, act, x, r, p, Ap, partial, scal, blockIdx.x);
 }
 
-// finalize of a CG reduction (one block): OP 0 init, 1 p.Ap, 2 update
-template <int D, int OP>
+// r.z for the preconditioned iteration
+template <int D>
+__global__ __launch_bounds__(CG_T) void k_cg_dot(Geo g, const uint8_t *__restrict__ act, const double *__restrict__ r,
+                                                  const double *__restrict__ z, double *partial, const double *scal) {
+  if (scal[S_DONE] != 0.0) return;
+  const int64_t i = blockIdx.x * (int64_t)CG_T + threadIdx.x;
+  double v[D];
+  for (int c = 0; c < D; ++c) v[c] = 0.0;
+  if (i < g.N && (!act || act[i]))
+    for (int c = 0; c < D; ++c) v[c] = r[(size_t)c * g.S + i] * z[(size_t)c * g.S + i];
+  block_store<D>(v, partial, blockIdx.x);
+}
+
+// beta = (r.z)_new / (r.z)_old for the preconditioned iteration
+template <int D> __device__ __forceinline__ void cg_rz_fin(const double *tot, double *scal, bool first) {
+  for (int c = 0; c < D; ++c) {
+    const double rz = tot[c];
+    scal[S_BETA + c] = (!first && scal[S_ACT + c] != 0.0 && scal[S_RZ + c] != 0.0) ? rz / scal[S_RZ + c] : 0.0;
+    scal[S_RZ + c] = rz;
+  }
+}
+
+// finalize of a CG reduction (one block): OP 0 init, 1 p.Ap, 2 update,
+// 3 r.z (4: r.z of the initial residual); PC: preconditioned iteration
+template <int D, int OP, bool PC>
 __device__ __forceinline__ void cg_fin(const double *partial, int nblk, double *scal, double rtol) {
-  if (OP != 0 && scal[S_DONE] != 0.0) return;
+  if (OP != 0 && OP != 4 && scal[S_DONE] != 0.0) return;
   __shared__ double tot[PSTRIDE];
   block_totals<(OP == 0 ? 2 * D : D)>(partial, nblk, tot);
   if (threadIdx.x == 0) {
     if (OP == 0) cg_init_fin<D>(tot, scal, rtol);
-    else if (OP == 1) cg_Ap_fin<D>(tot, scal);
-    else cg_update_fin<D>(tot, scal);
+    else if (OP == 1) cg_Ap_fin<D>(tot, scal, PC);
+    else if (OP == 2) cg_update_fin<D>(tot, scal, PC);
+    else cg_rz_fin<D>(tot, scal, OP == 4);
   }
 }
 
-template <int D, int OP>
+template <int D, int OP, bool PC = false>
 __global__ __launch_bounds__(CG_T) void k_cg_fin(const double *partial, int nblk, double *scal, double rtol) {
-  cg_fin<D, OP>(partial, nblk, scal, rtol);
+  cg_fin<D, OP, PC>(partial, nblk, scal, rtol);
 }
 
 // one block per instance
 template <int D, int OP>
 __global__ __launch_bounds__(CG_T) void k_cg_fin_batch(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
-  cg_fin<D, OP>(I.partial, I.nblk, I.scal, I.rtol);
+  cg_fin<D, OP, false>(I.partial, I.nblk, I.scal, I.rtol);
 }
 
 template <int D, typename T>
@@ -1068,7 +1090,7 @@ template <int D, typename T> static int cg_alloc(tlvlbm_ctx *c) {
   // CG vectors are FP64 in both builds (a few node planes; FP32 vectors
   // stall well above the tolerance on large graphs)
   const size_t plane = (size_t)c->geo.S * sizeof(T), dplane = (size_t)c->geo.S * sizeof(double);
-  void **vec[] = {&w.x, &w.r, &w.p0, &w.p1, &w.Ap, &w.b, &w.anc_s};
+  void **vec[] = {&w.x, &w.r, &w.p0, &w.p1, &w.Ap, &w.b, &w.anc_s, &w.z};
   for (void **pp : vec) {
     HIP_OK(hipMalloc(pp, D * dplane));
     HIP_OK(hipMemsetAsync(*pp, 0, D * dplane, c->st));
@@ -1093,6 +1115,58 @@ __global__ void k_anchor_narrow(Geo g, const int *__restrict__ ai, uint8_t *__re
 }
 
 template <int D, typename T> static int cg_run(tlvlbm_ctx *c, const uint8_t *anc_n);
+
+// Preconditioned CG (one multigrid V-cycle per iteration) on the workspace:
+// right-hand side w.b, start and result w.x; the same per-component scalars
+// and stopping rule as the plain iteration (relative residual ||r||).
+template <int D, typename T> static int pcg_run(tlvlbm_ctx *c, const uint8_t *anc_n, double rtol) {
+  CG &w = c->cg;
+  const Geo &g = c->geo;
+  hipStream_t st = c->st;
+  if (!c->mg || !c->gauge || c->aux_stale) {
+    const int s = proj_aux_build(c);
+    if (s) return s;
+  }
+  // the preconditioner moves the constants of components without anchors,
+  // which plain CG from the warm start keeps: restore them afterwards
+  gauge_means(c, (const double *)w.x, nullptr, c->gauge->mean0);
+  double *r = (double *)w.r, *z = (double *)w.z;
+  hipLaunchKernelGGL((k_cg_init<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
+                     (const double *)w.x, r, (double *)w.p0, w.partial);
+  hipLaunchKernelGGL((k_cg_fin<D, 0>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, rtol);
+  mg_apply(c, r, z, nullptr);
+  hipLaunchKernelGGL((k_cg_dot<D>), w.nblk, CG_T, 0, st, g, c->act, (const double *)r, (const double *)z, w.partial,
+                     (const double *)w.scal);
+  hipLaunchKernelGGL((k_cg_fin<D, 4, true>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
+  const int64_t maxit = c->cg_maxit > 0 ? c->cg_maxit : cg_default_maxit(c->nactive);
+  double *pa = (double *)w.p0, *pb = (double *)w.p1;
+  int64_t it = 0;
+  while (it < maxit) {
+    const int64_t batch = std::min<int64_t>(8, maxit - it);
+    for (int64_t k = 0; k < batch; ++k) {
+      hipLaunchKernelGGL((k_cg_Ap<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)z, pa, pb,
+                         (double *)w.Ap, w.partial, w.scal);
+      hipLaunchKernelGGL((k_cg_fin<D, 1, true>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
+      hipLaunchKernelGGL((k_cg_update<D, T>), w.nblk, CG_T, 0, st, g, c->act, (double *)w.x, r, pb,
+                         (const double *)w.Ap, w.partial, w.scal);
+      hipLaunchKernelGGL((k_cg_fin<D, 2, true>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
+      mg_apply(c, r, z, w.scal);
+      hipLaunchKernelGGL((k_cg_dot<D>), w.nblk, CG_T, 0, st, g, c->act, (const double *)r, (const double *)z,
+                         w.partial, (const double *)w.scal);
+      hipLaunchKernelGGL((k_cg_fin<D, 3, true>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
+      std::swap(pa, pb);
+    }
+    it += batch;
+    HIP_OK(hipMemcpyAsync(c->hscal, w.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (c->hscal[S_DONE] != 0.0) break;
+  }
+  gauge_restore(c, (double *)w.x, c->gauge->mean0);
+  HIP_OK(hipMemcpyAsync(c->hscal, w.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  for (int k = 0; k < D; ++k) c->st_cg += (int64_t)c->hscal[S_ITS + k];
+  return TLVLBM_OK;
+}
 
 template <int D, typename T> static int cg_solve(tlvlbm_ctx *c, const T *F, double t) {
   CG &w = c->cg;
@@ -1129,6 +1203,7 @@ template <int D, typename T> static int cg_run(tlvlbm_ctx *c, const uint8_t *anc
   const Geo &g = c->geo;
   hipStream_t st = c->st;
   const double rtol = c->cg_rtol > 0 ? c->cg_rtol : cg_default_rtol(c->prec);
+  if (c->cg_multigrid) return pcg_run<D, T>(c, anc_n, rtol);
   hipLaunchKernelGGL((k_cg_init<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
                      (const double *)w.x, (double *)w.r, (double *)w.p0, w.partial);
   hipLaunchKernelGGL((k_cg_fin<D, 0>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, rtol);

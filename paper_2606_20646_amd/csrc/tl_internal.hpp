@@ -50,9 +50,45 @@ struct BC {
   double Tr, a[3], G[9], pr, pn, X0[3];
 };
 
+// scalar slots of the CG state (device doubles, per component)
+enum { S_RR = 0, S_BB = 4, S_THR = 8, S_ALPHA = 12, S_BETA = 16, S_ACT = 20, S_ITS = 24, S_DONE = 28, S_RZ = 32,
+       S_NSCAL = 36 };
+
+// one multigrid level (device view passed by value to kernels)
+struct MGView {
+  int nx, ny, nz, per;
+  int64_t N, stride;  // nodes, plane stride of the level's vectors
+  const float *w;     // [D][N] weight of the edge to the +A neighbour
+  const float *d;     // [N] diagonal (edge weights + anchors)
+};
+struct MGLevel {
+  MGView v{};
+  float *w = nullptr, *d = nullptr;
+  double *b = nullptr, *x = nullptr, *t = nullptr;  // [D][stride]
+};
+struct MG {
+  std::vector<MGLevel> lev;
+  double omega = 2.0 / 3.0;
+  int nu = 2, nu_coarse = 40;
+};
+
+// connected components of the active graph that carry no anchor: the
+// projection determines u there only up to a constant (the gauge)
+struct Gauge {
+  int64_t nu = 0, ntile = 0;   // such components; tiles of 256 of their nodes
+  int32_t *comp = nullptr;     // [N] component index, -1 elsewhere
+  int32_t *cn = nullptr;       // [ntile*256] node of each tile slot, -1 padding
+  int64_t *ct = nullptr;       // [nu+1] first tile of each component
+  int64_t *ccnt = nullptr;     // [nu] node count
+  double *tpart = nullptr;     // [ntile][D] tile sums
+  double *mean = nullptr, *mean0 = nullptr;  // [nu][D]
+  uint8_t *anc_n = nullptr;    // [N] anchor counts (Dirichlet cut links per node)
+};
+
 // projection / CG workspace
 struct CG {
   void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *Ap = nullptr, *b = nullptr;  // [D][S] FP64
+  void *z = nullptr;                                // preconditioned residual [D][S] FP64
   void *V = nullptr, *Fm = nullptr, *Fr = nullptr;  // v [D][S], F [D2][S], F^r [D2][S]  (T)
   uint8_t *anc_n = nullptr;                         // anchors per node
   int *anc_i = nullptr;                             // anchor counting scratch
@@ -180,6 +216,10 @@ struct tlvlbm_ctx {
   tl::Par par{};
   double theta = 1.0, cg_rtol = 0.0;
   int proj_every = 20, cg_maxit = 0, track_opt = -1;
+  int cg_multigrid = 1;        // 1: multigrid-preconditioned CG, 0: plain CG
+  tl::MG *mg = nullptr;        // preconditioner hierarchy (built on first use)
+  tl::Gauge *gauge = nullptr;  // components without anchors (built on first use)
+  bool aux_stale = true;       // boundary conditions changed since the build
   bool track_u = false;
   hipStream_t st = nullptr;
   size_t esz = 4;
@@ -217,6 +257,14 @@ void launch_cutlinks(tlvlbm_ctx *c, double tn);
 int run_projection(tlvlbm_ctx *c, bool first, double tn);
 // CG on the projection workspace with a given right-hand side (w.b) and start (w.x)
 int run_cg_given(tlvlbm_ctx *c, const uint8_t *anc_n);
+// projection helpers (mg.hip): components and anchors, multigrid hierarchy
+int proj_aux_build(tlvlbm_ctx *c);
+void proj_aux_free(tlvlbm_ctx *c);
+void mg_apply(tlvlbm_ctx *c, const double *r, double *z, const double *scal);
+// per-component means of ua (+ ub) over the components without anchors
+void gauge_means(tlvlbm_ctx *c, const double *ua, const double *ub, double *mean);
+// x -= mean(x) - mean0 on those components
+void gauge_restore(tlvlbm_ctx *c, double *x, const double *mean0);
 // reverse-mode tape of one step: recovered state (v, F - I) [M planes],
 // repaired F [D*D planes, projection steps], displacement seen by the cut
 // links [D planes]; any may be null

@@ -35,7 +35,7 @@ class Material(C.Structure):
 class Options(C.Structure):
     _fields_ = [("omega", C.c_double), ("gamma", C.c_double), ("theta_F", C.c_double), ("cg_rtol", C.c_double),
                 ("proj_every", C.c_int32), ("cg_maxit", C.c_int32), ("precision", C.c_int32),
-                ("track_u", C.c_int32), ("stream", C.c_void_p)]
+                ("track_u", C.c_int32), ("stream", C.c_void_p), ("cg_multigrid", C.c_int32)]
 
 
 class BC(C.Structure):
@@ -59,6 +59,14 @@ class TlvlbmError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_20646_amd.build`")
+    # One HIP runtime per process: when PyTorch is installed it must be loaded
+    # first, so that the library binds to the runtime PyTorch ships (whose
+    # streams and device pointers callers pass in).  Loading the system
+    # runtime first leaves PyTorch without devices.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, dp = C.c_void_p, C.c_void_p
     L.tlvlbm_default_options.argtypes = [C.POINTER(Options)]
@@ -118,7 +126,7 @@ class Solver:
 
     def __init__(self, D, n, dx, dt, mu, lam, rho0=1.0, origin=None, periodic_mask=None, omega=1.8, gamma=0.0,
                  theta_F=1.0, proj_every=20, precision="fp32", track_u=-1, cg_rtol=0.0, cg_maxit=0,
-                 stream=None):
+                 stream=None, cg_multigrid=True):
         self.D, self.M, self.Q = D, D + D * D, 2 * D
         self.n = tuple(int(v) for v in n)
         self.N = int(np.prod(self.n))
@@ -136,6 +144,7 @@ class Solver:
         o.proj_every, o.cg_maxit, o.track_u = proj_every, cg_maxit, track_u
         o.precision = FP64 if precision in ("fp64", FP64) else FP32
         o.stream = stream
+        o.cg_multigrid = int(bool(cg_multigrid))
         h = C.c_void_p()
         st = lib.tlvlbm_create(C.byref(g), D, C.byref(m), rho0, dt, C.byref(o), C.byref(h))
         if st:

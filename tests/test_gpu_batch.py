@@ -27,10 +27,11 @@ def env():
     return tlvlbm, torch.cuda.Stream()
 
 
-def _solver(T, cfg, precision, stream):
+def _solver(T, cfg, precision, stream, cg_multigrid=False):
+    # the batched path runs the plain CG: compare against the same kernels
     s = T.Solver(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
                  origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"], precision=precision,
-                 stream=stream.cuda_stream)
+                 stream=stream.cuda_stream, cg_multigrid=cg_multigrid)
     s.set_levelset(cfg["phi"], cfg["bid"])
     for bid, bc in cfg["bcs"].items():
         bc = dict(bc)

@@ -716,7 +716,11 @@ template <int D> int solve_adj(Run &R, const double *ua, const double *ub) {
   gauge_means(c, ua, ub, G.mean);
   hipLaunchKernelGGL((k_pi_apply<D>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, G.comp, G.mean, ua, ub, R.x0b,
                      (double *)w.b, (double *)w.x);
-  return run_cg_given(c, R.dir ? G.anc_n : nullptr);
+  if (!R.dir) return run_cg_given(c, nullptr);
+  // the anchor counts go where the forward keeps them (one captured CG
+  // graph serves both directions)
+  if (hipMemcpyAsync(w.anc_n, G.anc_n, g.N, hipMemcpyDeviceToDevice, c->st) != hipSuccess) return TLVLBM_ERR_DEVICE;
+  return run_cg_given(c, w.anc_n);
 }
 
 template <int D> void anchors_T(Run &R, const double *y, double *Fb) {
@@ -785,9 +789,11 @@ template <int D, typename T> int reverse_step(Run &R, int64_t k, const TapeStep 
 }
 
 // host preparation: the transposed LSQ stencils of the Neumann links
-template <int D> int prepare_host(Run &R, Pool &pool) {
-  tlvlbm_ctx *c = R.c;
-  const int64_t nl = c->L.n;
+// transposed LSQ stencils of the Neumann links (built once per geometry and
+// set of conditions, kept in the context): a counting sort by node keeps the
+// (link, point) order within each node, so the gather is deterministic
+int stencil_transpose(tlvlbm_ctx *c) {
+  const int64_t nl = c->L.n, N = c->geo.N;
   std::vector<int32_t> lnp(nl), sidx((size_t)nl * c->L.kmax);
   if (nl) {
     if (hipMemcpy(lnp.data(), c->L.npts, nl * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
@@ -798,42 +804,42 @@ template <int D> int prepare_host(Run &R, Pool &pool) {
   for (int b = 0; b < 256; ++b)
     for (int64_t l = c->bid_begin[b]; l < c->bid_end[b]; ++l)
       is_neu[l] = c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION;
-  hipStream_t st = c->st;
-  // transposed Neumann stencils: entries (node, link, point), sorted
-  struct E {
-    int32_t j, l, k;
-  };
-  std::vector<E> ent;
+  std::vector<int64_t> cnt(N + 1, 0);
   for (int64_t l = 0; l < nl; ++l)
     if (is_neu[l])
-      for (int k = 0; k < lnp[l]; ++k) ent.push_back({sidx[(size_t)l * c->L.kmax + k], (int32_t)l, k});
-  std::sort(ent.begin(), ent.end(), [](const E &a, const E &b) {
-    return a.j != b.j ? a.j < b.j : (a.l != b.l ? a.l < b.l : a.k < b.k);
-  });
+      for (int k = 0; k < lnp[l]; ++k) cnt[sidx[(size_t)l * c->L.kmax + k] + 1]++;
   std::vector<int64_t> sn, so;
-  std::vector<int32_t> el, ek;
-  for (size_t e = 0; e < ent.size(); ++e) {
-    if (e == 0 || ent[e].j != ent[e - 1].j) {
-      sn.push_back(ent[e].j);
-      so.push_back((int64_t)e);
-    }
-    el.push_back(ent[e].l);
-    ek.push_back(ent[e].k);
-  }
-  so.push_back((int64_t)ent.size());
-  R.ns = (int64_t)sn.size();
-  if (R.ns) {
-    if (pool.get(&R.sn, sn.size() * sizeof(int64_t), st, false) ||
-        pool.get(&R.so, so.size() * sizeof(int64_t), st, false) ||
-        pool.get(&R.el, el.size() * sizeof(int32_t), st, false) ||
-        pool.get(&R.ek, ek.size() * sizeof(int32_t), st, false))
+  for (int64_t j = 0; j < N; ++j)
+    if (cnt[j + 1]) sn.push_back(j);
+  for (int64_t j = 0; j < N; ++j) cnt[j + 1] += cnt[j];
+  const int64_t ne = cnt[N];
+  std::vector<int32_t> el(ne), ek(ne);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t l = 0; l < nl; ++l)
+    if (is_neu[l])
+      for (int k = 0; k < lnp[l]; ++k) {
+        const int64_t e = pos[sidx[(size_t)l * c->L.kmax + k]]++;
+        el[e] = (int32_t)l;
+        ek[e] = k;
+      }
+  for (int64_t j : sn) so.push_back(cnt[j]);
+  so.push_back(ne);
+  StencilT *T = new (std::nothrow) StencilT();
+  if (!T) return TLVLBM_ERR_OUT_OF_MEMORY;
+  T->ns = (int64_t)sn.size();
+  if (T->ns) {
+    if (hipMalloc(&T->sn, sn.size() * sizeof(int64_t)) || hipMalloc(&T->so, so.size() * sizeof(int64_t)) ||
+        hipMalloc(&T->el, el.size() * sizeof(int32_t)) || hipMalloc(&T->ek, ek.size() * sizeof(int32_t)) ||
+        hipMemcpy(T->sn, sn.data(), sn.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
+        hipMemcpy(T->so, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
+        hipMemcpy(T->el, el.data(), el.size() * sizeof(int32_t), hipMemcpyHostToDevice) ||
+        hipMemcpy(T->ek, ek.data(), ek.size() * sizeof(int32_t), hipMemcpyHostToDevice)) {
+      for (void *p : {(void *)T->sn, (void *)T->so, (void *)T->el, (void *)T->ek}) (void)hipFree(p);
+      delete T;
       return TLVLBM_ERR_OUT_OF_MEMORY;
-    if (hipMemcpy(R.sn, sn.data(), sn.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
-        hipMemcpy(R.so, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
-        hipMemcpy(R.el, el.data(), el.size() * sizeof(int32_t), hipMemcpyHostToDevice) ||
-        hipMemcpy(R.ek, ek.data(), ek.size() * sizeof(int32_t), hipMemcpyHostToDevice))
-      return TLVLBM_ERR_DEVICE;
+    }
   }
+  c->stT = T;
   return TLVLBM_OK;
 }
 
@@ -939,12 +945,15 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
       return TLVLBM_ERR_OUT_OF_MEMORY;
   }
   if (c->act) {
-    int s = prepare_host<D>(R, pool);
+    int s = TLVLBM_OK;
+    if (!c->gauge || c->aux_stale) s = proj_aux_build(c);
+    if (!s && !c->stT) s = stencil_transpose(c);
     if (s) return (tlvlbm_status)s;
-    if (!c->gauge || c->aux_stale) {
-      s = proj_aux_build(c);
-      if (s) return (tlvlbm_status)s;
-    }
+    R.ns = c->stT->ns;
+    R.sn = c->stT->sn;
+    R.so = c->stT->so;
+    R.el = c->stT->el;
+    R.ek = c->stT->ek;
   }
   // per-step tape of one segment
   char *tapeU = nullptr, *tapeu = nullptr, *tapeF = nullptr;

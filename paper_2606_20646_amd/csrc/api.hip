@@ -206,7 +206,7 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
   void *ptrs[] = {c->fA, c->fB, c->ustar, c->ubuf, c->act, c->d_flag, c->d_newton_fail, c->L.node, c->L.out,
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
-                  c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z};
+                  c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
@@ -307,6 +307,13 @@ tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0
     CHK(hipGetLastError(), "init launch");
     tlvlbm_status s = read_flag(c);
     if (s) return s;
+    // host-side preparation of the projection (tiles, components, multigrid
+    // hierarchy) happens here, not inside the first projection step
+    if (has_neumann(c) && c->proj_every > 0 && (!c->gauge || c->aux_stale)) {
+      int e = ensure_cg(c);
+      if (!e) e = proj_aux_build(c);
+      if (e) return fail(c, (tlvlbm_status)e, "projection setup failed");
+    }
     c->step = 0;
     c->status = TLVLBM_OK;
     c->have_state = true;

@@ -607,15 +607,16 @@ __device__ __forceinline__ void block_store(double (&v)[K], double *partial, int
   }
 }
 
-// totals of the K partial sums over nblk blocks (one block of CG_T threads)
+// totals of the K partial sums over nblk blocks (one block of FIN_T threads)
+constexpr int FIN_T = 1024;
 template <int K>
 __device__ __forceinline__ void block_totals(const double *partial, int nblk, double *tot) {
-  __shared__ double sh[CG_T / 64][PSTRIDE];
+  __shared__ double sh[FIN_T / 64][PSTRIDE];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += CG_T)
+  for (int b = threadIdx.x; b < nblk; b += FIN_T)
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += partial[b * PSTRIDE + k];
 #pragma unroll
@@ -628,7 +629,7 @@ __device__ __forceinline__ void block_totals(const double *partial, int nblk, do
   if (threadIdx.x == 0)
     for (int k = 0; k < K; ++k) {
       double t = 0.0;
-      for (int w = 0; w < CG_T / 64; ++w) t += sh[w][k];
+      for (int w = 0; w < FIN_T / 64; ++w) t += sh[w][k];
       tot[k] = t;
     }
 }
@@ -638,7 +639,7 @@ template <int D, typename T>
 __device__ __forceinline__ void cg_init_blk(const Geo &g, const uint8_t *__restrict__ act,
                                             const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
                                             const double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
-                                            double *partial, int blk) {
+                                            double *partial, int blk, int slot) {
   const int64_t i = blk * (int64_t)CG_T + threadIdx.x;
   double v[2 * D];
   for (int k = 0; k < 2 * D; ++k) v[k] = 0.0;
@@ -670,7 +671,7 @@ __device__ __forceinline__ void cg_init_blk(const Geo &g, const uint8_t *__restr
       }
     }
   }
-  block_store<2 * D>(v, partial, blk);
+  block_store<2 * D>(v, partial, slot);
 }
 
 template <int D> __device__ __forceinline__ void cg_init_fin(const double *tot, double *scal, double rtol) {
@@ -696,7 +697,7 @@ template <int D, typename T>
 __device__ __forceinline__ void cg_Ap_blk(const Geo &g, const uint8_t *__restrict__ act,
                                           const uint8_t *__restrict__ anc_n, const double *__restrict__ r,
                                           const double *__restrict__ pold, double *__restrict__ pnew, double *__restrict__ Ap,
-                                          double *partial, const double *scal, int blk) {
+                                          double *partial, const double *scal, int blk, int slot) {
   if (scal[S_DONE] != 0.0) return;
   const int64_t i = blk * (int64_t)CG_T + threadIdx.x;
   double v[D];
@@ -728,7 +729,7 @@ __device__ __forceinline__ void cg_Ap_blk(const Geo &g, const uint8_t *__restric
       Ap[(size_t)c * g.S + i] = double(0);
     }
   }
-  block_store<D>(v, partial, blk);
+  block_store<D>(v, partial, slot);
 }
 
 template <int D> __device__ __forceinline__ void cg_Ap_fin(const double *tot, double *scal, bool pc) {
@@ -745,7 +746,7 @@ template <int D> __device__ __forceinline__ void cg_Ap_fin(const double *tot, do
 template <int D, typename T>
 __device__ __forceinline__ void cg_update_blk(const Geo &g, const uint8_t *__restrict__ act, double *__restrict__ x,
                                               double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ Ap,
-                                              double *partial, const double *scal, int blk) {
+                                              double *partial, const double *scal, int blk, int slot) {
   if (scal[S_DONE] != 0.0) return;
   const int64_t i = blk * (int64_t)CG_T + threadIdx.x;
   double v[D];
@@ -760,7 +761,7 @@ __device__ __forceinline__ void cg_update_blk(const Geo &g, const uint8_t *__res
       v[c] = double(ri) * double(ri);
     }
   }
-  block_store<D>(v, partial, blk);
+  block_store<D>(v, partial, slot);
 }
 
 template <int D> __device__ __forceinline__ void cg_update_fin(const double *tot, double *scal, bool pc) {
@@ -857,32 +858,36 @@ template <int D, typename T>
 __global__ __launch_bounds__(CG_T) void k_cg_init(Geo g, const uint8_t *__restrict__ act,
                                                    const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
                                                    const double *__restrict__ x, double *__restrict__ r,
-                                                   double *__restrict__ p, double *partial) {
-  cg_init_blk<D, T>(g, act, anc_n, b, x, r, p, partial, blockIdx.x);
+                                                   double *__restrict__ p, double *partial,
+                                                   const int32_t *__restrict__ tiles) {
+  cg_init_blk<D, T>(g, act, anc_n, b, x, r, p, partial, tiles ? tiles[blockIdx.x] : blockIdx.x, blockIdx.x);
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(CG_T) void k_cg_Ap(Geo g, const uint8_t *__restrict__ act,
                                                  const uint8_t *__restrict__ anc_n, const double *__restrict__ r,
                                                  const double *__restrict__ pold, double *__restrict__ pnew,
-                                                 double *__restrict__ Ap, double *partial, const double *scal) {
-  cg_Ap_blk<D, T>(g, act, anc_n, r, pold, pnew, Ap, partial, scal, blockIdx.x);
+                                                 double *__restrict__ Ap, double *partial, const double *scal,
+                                                 const int32_t *__restrict__ tiles) {
+  cg_Ap_blk<D, T>(g, act, anc_n, r, pold, pnew, Ap, partial, scal, tiles ? tiles[blockIdx.x] : blockIdx.x,
+                  blockIdx.x);
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(CG_T) void k_cg_update(Geo g, const uint8_t *__restrict__ act, double *__restrict__ x,
                                                      double *__restrict__ r, const double *__restrict__ p,
                                                      const double *__restrict__ Ap, double *partial,
-                                                     const double *scal) {
-  cg_update_blk<D, T>(g, act, x, r, p, Ap, partial, scal, blockIdx.x);
+                                                     const double *scal, const int32_t *__restrict__ tiles) {
+  cg_update_blk<D, T>(g, act, x, r, p, Ap, partial, scal, tiles ? tiles[blockIdx.x] : blockIdx.x, blockIdx.x);
 }
 
 // r.z for the preconditioned iteration
 template <int D>
 __global__ __launch_bounds__(CG_T) void k_cg_dot(Geo g, const uint8_t *__restrict__ act, const double *__restrict__ r,
-                                                  const double *__restrict__ z, double *partial, const double *scal) {
+                                                  const double *__restrict__ z, double *partial, const double *scal,
+                                                  const int32_t *__restrict__ tiles) {
   if (scal[S_DONE] != 0.0) return;
-  const int64_t i = blockIdx.x * (int64_t)CG_T + threadIdx.x;
+  const int64_t i = (tiles ? tiles[blockIdx.x] : (int64_t)blockIdx.x) * CG_T + threadIdx.x;
   double v[D];
   for (int c = 0; c < D; ++c) v[c] = 0.0;
   if (i < g.N && (!act || act[i]))
@@ -915,13 +920,13 @@ __device__ __forceinline__ void cg_fin(const double *partial, int nblk, double *
 }
 
 template <int D, int OP, bool PC = false>
-__global__ __launch_bounds__(CG_T) void k_cg_fin(const double *partial, int nblk, double *scal, double rtol) {
+__global__ __launch_bounds__(FIN_T) void k_cg_fin(const double *partial, int nblk, double *scal, double rtol) {
   cg_fin<D, OP, PC>(partial, nblk, scal, rtol);
 }
 
 // one block per instance
 template <int D, int OP>
-__global__ __launch_bounds__(CG_T) void k_cg_fin_batch(const Inst *__restrict__ insts) {
+__global__ __launch_bounds__(FIN_T) void k_cg_fin_batch(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
   cg_fin<D, OP, false>(I.partial, I.nblk, I.scal, I.rtol);
 }
@@ -1131,32 +1136,56 @@ template <int D, typename T> static int pcg_run(tlvlbm_ctx *c, const uint8_t *an
   // which plain CG from the warm start keeps: restore them afterwards
   gauge_means(c, (const double *)w.x, nullptr, c->gauge->mean0);
   double *r = (double *)w.r, *z = (double *)w.z;
-  hipLaunchKernelGGL((k_cg_init<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
-                     (const double *)w.x, r, (double *)w.p0, w.partial);
-  hipLaunchKernelGGL((k_cg_fin<D, 0>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, rtol);
+  const int nt = w.tiles ? w.ntiles : w.nblk;
+  hipLaunchKernelGGL((k_cg_init<D, T>), nt, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
+                     (const double *)w.x, r, (double *)w.p0, w.partial, w.tiles);
+  hipLaunchKernelGGL((k_cg_fin<D, 0>), 1, FIN_T, 0, st, w.partial, nt, w.scal, rtol);
   mg_apply(c, r, z, nullptr);
-  hipLaunchKernelGGL((k_cg_dot<D>), w.nblk, CG_T, 0, st, g, c->act, (const double *)r, (const double *)z, w.partial,
-                     (const double *)w.scal);
-  hipLaunchKernelGGL((k_cg_fin<D, 4, true>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
+  hipLaunchKernelGGL((k_cg_dot<D>), nt, CG_T, 0, st, g, c->act, (const double *)r, (const double *)z, w.partial,
+                     (const double *)w.scal, w.tiles);
+  hipLaunchKernelGGL((k_cg_fin<D, 4, true>), 1, FIN_T, 0, st, w.partial, nt, w.scal, 0.0);
   const int64_t maxit = c->cg_maxit > 0 ? c->cg_maxit : cg_default_maxit(c->nactive);
-  double *pa = (double *)w.p0, *pb = (double *)w.p1;
-  int64_t it = 0;
-  while (it < maxit) {
-    const int64_t batch = std::min<int64_t>(8, maxit - it);
-    for (int64_t k = 0; k < batch; ++k) {
-      hipLaunchKernelGGL((k_cg_Ap<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)z, pa, pb,
-                         (double *)w.Ap, w.partial, w.scal);
-      hipLaunchKernelGGL((k_cg_fin<D, 1, true>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
-      hipLaunchKernelGGL((k_cg_update<D, T>), w.nblk, CG_T, 0, st, g, c->act, (double *)w.x, r, pb,
-                         (const double *)w.Ap, w.partial, w.scal);
-      hipLaunchKernelGGL((k_cg_fin<D, 2, true>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
+  // PCG_BATCH iterations between convergence polls (even, so that the p
+  // ping-pong returns to p0); every kernel returns at once after convergence
+  constexpr int PCG_BATCH = 8;
+  auto body = [&]() {
+    double *pa = (double *)w.p0, *pb = (double *)w.p1;
+    for (int k = 0; k < PCG_BATCH; ++k) {
+      hipLaunchKernelGGL((k_cg_Ap<D, T>), nt, CG_T, 0, st, g, c->act, anc_n, (const double *)z, pa, pb,
+                         (double *)w.Ap, w.partial, w.scal, w.tiles);
+      hipLaunchKernelGGL((k_cg_fin<D, 1, true>), 1, FIN_T, 0, st, w.partial, nt, w.scal, 0.0);
+      hipLaunchKernelGGL((k_cg_update<D, T>), nt, CG_T, 0, st, g, c->act, (double *)w.x, r, pb,
+                         (const double *)w.Ap, w.partial, w.scal, w.tiles);
+      hipLaunchKernelGGL((k_cg_fin<D, 2, true>), 1, FIN_T, 0, st, w.partial, nt, w.scal, 0.0);
       mg_apply(c, r, z, w.scal);
-      hipLaunchKernelGGL((k_cg_dot<D>), w.nblk, CG_T, 0, st, g, c->act, (const double *)r, (const double *)z,
-                         w.partial, (const double *)w.scal);
-      hipLaunchKernelGGL((k_cg_fin<D, 3, true>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
+      hipLaunchKernelGGL((k_cg_dot<D>), nt, CG_T, 0, st, g, c->act, (const double *)r, (const double *)z,
+                         w.partial, (const double *)w.scal, w.tiles);
+      hipLaunchKernelGGL((k_cg_fin<D, 3, true>), 1, FIN_T, 0, st, w.partial, nt, w.scal, 0.0);
       std::swap(pa, pb);
     }
-    it += batch;
+  };
+  // the batch is launch-bound (about 45 small kernels per iteration): replay
+  // it from a graph captured once per hierarchy and anchor set (not on the
+  // legacy default stream, which cannot be captured)
+  const bool use_graph = st != nullptr;
+  if (use_graph && (!w.pcg_graph || w.pcg_key != (const void *)anc_n)) {
+    if (w.pcg_graph) (void)hipGraphExecDestroy(w.pcg_graph);
+    w.pcg_graph = nullptr;
+    hipGraph_t gr = nullptr;
+    HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    body();
+    HIP_OK(hipStreamEndCapture(st, &gr));
+    const hipError_t e = hipGraphInstantiate(&w.pcg_graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+      w.pcg_graph = nullptr;
+      return TLVLBM_ERR_DEVICE;
+    }
+    w.pcg_key = (const void *)anc_n;
+  }
+  for (int64_t it = 0; it < maxit; it += PCG_BATCH) {
+    if (use_graph) HIP_OK(hipGraphLaunch(w.pcg_graph, st));
+    else body();
     HIP_OK(hipMemcpyAsync(c->hscal, w.scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     if (c->hscal[S_DONE] != 0.0) break;
@@ -1203,22 +1232,27 @@ template <int D, typename T> static int cg_run(tlvlbm_ctx *c, const uint8_t *anc
   const Geo &g = c->geo;
   hipStream_t st = c->st;
   const double rtol = c->cg_rtol > 0 ? c->cg_rtol : cg_default_rtol(c->prec);
+  if (!c->gauge || c->aux_stale) {
+    const int s = proj_aux_build(c);
+    if (s) return s;
+  }
   if (c->cg_multigrid) return pcg_run<D, T>(c, anc_n, rtol);
-  hipLaunchKernelGGL((k_cg_init<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
-                     (const double *)w.x, (double *)w.r, (double *)w.p0, w.partial);
-  hipLaunchKernelGGL((k_cg_fin<D, 0>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, rtol);
+  const int nt = w.tiles ? w.ntiles : w.nblk;
+  hipLaunchKernelGGL((k_cg_init<D, T>), nt, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
+                     (const double *)w.x, (double *)w.r, (double *)w.p0, w.partial, w.tiles);
+  hipLaunchKernelGGL((k_cg_fin<D, 0>), 1, FIN_T, 0, st, w.partial, nt, w.scal, rtol);
   const int64_t maxit = c->cg_maxit > 0 ? c->cg_maxit : cg_default_maxit(c->nactive);
   double *pa = (double *)w.p0, *pb = (double *)w.p1;
   int64_t it = 0;
   while (it < maxit) {
     const int64_t batch = std::min<int64_t>(32, maxit - it);
     for (int64_t k = 0; k < batch; ++k) {
-      hipLaunchKernelGGL((k_cg_Ap<D, T>), w.nblk, CG_T, 0, st, g, c->act, anc_n, (const double *)w.r, pa, pb,
-                         (double *)w.Ap, w.partial, w.scal);
-      hipLaunchKernelGGL((k_cg_fin<D, 1>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
-      hipLaunchKernelGGL((k_cg_update<D, T>), w.nblk, CG_T, 0, st, g, c->act, (double *)w.x, (double *)w.r, pb,
-                         (const double *)w.Ap, w.partial, w.scal);
-      hipLaunchKernelGGL((k_cg_fin<D, 2>), 1, CG_T, 0, st, w.partial, w.nblk, w.scal, 0.0);
+      hipLaunchKernelGGL((k_cg_Ap<D, T>), nt, CG_T, 0, st, g, c->act, anc_n, (const double *)w.r, pa, pb,
+                         (double *)w.Ap, w.partial, w.scal, w.tiles);
+      hipLaunchKernelGGL((k_cg_fin<D, 1>), 1, FIN_T, 0, st, w.partial, nt, w.scal, 0.0);
+      hipLaunchKernelGGL((k_cg_update<D, T>), nt, CG_T, 0, st, g, c->act, (double *)w.x, (double *)w.r, pb,
+                         (const double *)w.Ap, w.partial, w.scal, w.tiles);
+      hipLaunchKernelGGL((k_cg_fin<D, 2>), 1, FIN_T, 0, st, w.partial, nt, w.scal, 0.0);
       std::swap(pa, pb);
     }
     it += batch;
@@ -1345,7 +1379,7 @@ __global__ __launch_bounds__(CG_T) void k_cg_init_batch(const Inst *__restrict__
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
   cg_init_blk<D, T>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.b, (const double *)I.x,
-                    (double *)I.r, (double *)I.p0, I.partial, t.y);
+                    (double *)I.r, (double *)I.p0, I.partial, t.y, t.y);
 }
 
 template <int D, typename T>
@@ -1356,7 +1390,7 @@ __global__ __launch_bounds__(CG_T) void k_cg_Ap_batch(const Inst *__restrict__ i
   const double *pold = (const double *)(pp ? I.p1 : I.p0);
   double *pnew = (double *)(pp ? I.p0 : I.p1);
   cg_Ap_blk<D, T>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.r, pold, pnew, (double *)I.Ap,
-                  I.partial, I.scal, t.y);
+                  I.partial, I.scal, t.y, t.y);
 }
 
 template <int D, typename T>
@@ -1366,7 +1400,7 @@ __global__ __launch_bounds__(CG_T) void k_cg_update_batch(const Inst *__restrict
   const Inst &I = insts[t.x];
   const double *pnew = (const double *)(pp ? I.p0 : I.p1);
   cg_update_blk<D, T>(I.g, I.act, (double *)I.x, (double *)I.r, pnew, (const double *)I.Ap, I.partial, I.scal,
-                      t.y);
+                      t.y, t.y);
 }
 
 template <int D, typename T>
@@ -1427,15 +1461,15 @@ static void batch_kernels_t(BatchOp op, const BatchArgs &a) {
       break;
     case BatchOp::CgInit:
       hipLaunchKernelGGL((k_cg_init_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagB);
-      hipLaunchKernelGGL((k_cg_fin_batch<D, 0>), a.ninst, CG_T, 0, st, a.insts);
+      hipLaunchKernelGGL((k_cg_fin_batch<D, 0>), a.ninst, FIN_T, 0, st, a.insts);
       break;
     case BatchOp::CgAp:
       hipLaunchKernelGGL((k_cg_Ap_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA, a.flagB);
-      hipLaunchKernelGGL((k_cg_fin_batch<D, 1>), a.ninst, CG_T, 0, st, a.insts);
+      hipLaunchKernelGGL((k_cg_fin_batch<D, 1>), a.ninst, FIN_T, 0, st, a.insts);
       break;
     case BatchOp::CgUpdate:
       hipLaunchKernelGGL((k_cg_update_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA);
-      hipLaunchKernelGGL((k_cg_fin_batch<D, 2>), a.ninst, CG_T, 0, st, a.insts);
+      hipLaunchKernelGGL((k_cg_fin_batch<D, 2>), a.ninst, FIN_T, 0, st, a.insts);
       break;
     case BatchOp::GradF:
       hipLaunchKernelGGL((k_gradF_batch<D, T>), a.nct, 256, 0, st, a.insts, a.ctiles);

@@ -63,13 +63,14 @@ __device__ __forceinline__ void xyz_of(const MGView &L, int64_t i, int &x, int &
   z = (int)(i / ((int64_t)L.nx * L.ny));
 }
 
-// xout = first ? om b / d : xin + om (b - K xin) / d
+// xout = first ? om b / d : xin + om (b - K xin) / d  (tiles: 256-node tiles
+// holding active nodes; null = all)
 template <int D>
 __global__ __launch_bounds__(MT) void k_mg_smooth(MGView L, const double *__restrict__ b, const double *__restrict__ xin,
                                                   double *__restrict__ xout, double om, int first,
-                                                  const double *__restrict__ scal) {
+                                                  const double *__restrict__ scal, const int32_t *__restrict__ tiles) {
   if (scal && scal[S_DONE] != 0.0) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (tiles ? (int64_t)tiles[blockIdx.x] : (int64_t)blockIdx.x) * MT + threadIdx.x;
   if (i >= L.N) return;
   const float d = L.d[i];
   if (d == 0.0f) {
@@ -117,9 +118,10 @@ __global__ __launch_bounds__(MT) void k_mg_restrict(MGView F, MGView Cg, const d
 // x(f) += xc(parent(f)) on nodes with a non-zero diagonal
 template <int D>
 __global__ __launch_bounds__(MT) void k_mg_prolong(MGView F, MGView Cg, const double *__restrict__ xc,
-                                                   double *__restrict__ x, const double *__restrict__ scal) {
+                                                   double *__restrict__ x, const double *__restrict__ scal,
+                                                   const int32_t *__restrict__ tiles) {
   if (scal && scal[S_DONE] != 0.0) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (tiles ? (int64_t)tiles[blockIdx.x] : (int64_t)blockIdx.x) * MT + threadIdx.x;
   if (i >= F.N || F.d[i] == 0.0f) return;
   int fx, fy, fz;
   xyz_of(F, i, fx, fy, fz);
@@ -128,6 +130,59 @@ __global__ __launch_bounds__(MT) void k_mg_prolong(MGView F, MGView Cg, const do
 }
 
 inline unsigned nb(int64_t n) { return (unsigned)((n + MT - 1) / MT); }
+
+// the coarsest level (at most CT nodes): all Jacobi sweeps in one block, in LDS
+constexpr int CT = 512;
+template <int D>
+__global__ __launch_bounds__(CT) void k_mg_coarse(MGView L, const double *__restrict__ b, double *__restrict__ x,
+                                                  double om, int nsweep, const double *__restrict__ scal) {
+  if (scal && scal[S_DONE] != 0.0) return;
+  __shared__ double xs[2][D][CT];
+  const int i = threadIdx.x;
+  const bool on = i < L.N;
+  const double d = on ? (double)L.d[i] : 0.0;
+  double bi[D];
+  for (int c = 0; c < D; ++c) {
+    bi[c] = (on && d != 0.0) ? b[(size_t)c * L.stride + i] : 0.0;
+    xs[0][c][i] = (d != 0.0) ? om * bi[c] / d : 0.0;
+  }
+  int x0 = 0, y0 = 0, z0 = 0;
+  if (on) {
+    x0 = i % L.nx;
+    y0 = (i / L.nx) % L.ny;
+    z0 = i / (L.nx * L.ny);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int s = 1; s < nsweep; ++s) {
+    if (on && d != 0.0) {
+      for (int c = 0; c < D; ++c) {
+        double kx = d * xs[cur][c][i];
+        const int n[3] = {L.nx, L.ny, L.nz};
+        const int cc[3] = {x0, y0, z0};
+        for (int A = 0; A < D; ++A) {
+          const int st = A == 0 ? 1 : (A == 1 ? L.nx : L.nx * L.ny);
+          const float wp = L.w[(size_t)A * L.N + i];
+          if (wp != 0.0f) kx -= (double)wp * xs[cur][c][(cc[A] + 1 < n[A]) ? i + st : i - (n[A] - 1) * st];
+          int j = -1;
+          if (cc[A] > 0) j = i - st;
+          else if ((L.per >> A) & 1) j = i + (n[A] - 1) * st;
+          if (j >= 0) {
+            const float wm = L.w[(size_t)A * L.N + j];
+            if (wm != 0.0f) kx -= (double)wm * xs[cur][c][j];
+          }
+        }
+        xs[cur ^ 1][c][i] = xs[cur][c][i] + om * (bi[c] - kx) / d;
+      }
+    } else {
+      for (int c = 0; c < D; ++c) xs[cur ^ 1][c][i] = 0.0;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  if (on)
+    for (int c = 0; c < D; ++c) x[(size_t)c * L.stride + i] = xs[cur][c][i];
+}
 
 // per-tile sums of ua (+ ub) over the nodes of components without anchors
 template <int D>
@@ -183,27 +238,39 @@ __global__ __launch_bounds__(MT) void k_gauge_shift(Geo g, const int32_t *__rest
 }
 
 // smoothing sweeps on level l: result in lev.x (b = lev.b); `cold` starts from 0
-template <int D> void sweeps(MG &mg, int l, int n, bool cold, hipStream_t st, const double *scal) {
+// sweeps on level l from lev.x (or from 0 when cold); the result is left in
+// lev.x, or written to `out` by the last sweep
+template <int D>
+void sweeps(MG &mg, int l, int n, bool cold, hipStream_t st, const double *scal, double *out = nullptr) {
   MGLevel &L = mg.lev[l];
+  const int32_t *tl = l == 0 ? mg.tiles : nullptr;
+  const unsigned grid = tl ? (unsigned)mg.ntiles : nb(L.v.N);
   for (int s = 0; s < n; ++s) {
-    hipLaunchKernelGGL((k_mg_smooth<D>), nb(L.v.N), MT, 0, st, L.v, L.b, L.x, L.t, mg.omega,
-                       (cold && s == 0) ? 1 : 0, scal);
-    std::swap(L.x, L.t);
+    double *dst = (out && s == n - 1) ? out : L.t;
+    hipLaunchKernelGGL((k_mg_smooth<D>), grid, MT, 0, st, L.v, L.b, L.x, dst, mg.omega, (cold && s == 0) ? 1 : 0,
+                       scal, tl);
+    if (dst == L.t) std::swap(L.x, L.t);
   }
 }
 
-template <int D> void vcycle(MG &mg, int l, hipStream_t st, const double *scal) {
+template <int D> void vcycle(MG &mg, int l, hipStream_t st, const double *scal, double *out) {
   const int last = (int)mg.lev.size() - 1;
+  MGLevel &F = mg.lev[l];
   if (l == last) {
-    sweeps<D>(mg, l, mg.nu_coarse, true, st, scal);
+    if (F.v.N <= CT)
+      hipLaunchKernelGGL((k_mg_coarse<D>), 1, CT, 0, st, F.v, F.b, out ? out : F.x, mg.omega, mg.nu_coarse, scal);
+    else
+      sweeps<D>(mg, l, mg.nu_coarse, true, st, scal, out);
     return;
   }
-  MGLevel &F = mg.lev[l], &Cg = mg.lev[l + 1];
+  MGLevel &Cg = mg.lev[l + 1];
+  const int32_t *tl = l == 0 ? mg.tiles : nullptr;
   sweeps<D>(mg, l, mg.nu, true, st, scal);
   hipLaunchKernelGGL((k_mg_restrict<D>), nb(Cg.v.N), MT, 0, st, F.v, Cg.v, F.b, F.x, Cg.b, scal);
-  vcycle<D>(mg, l + 1, st, scal);
-  hipLaunchKernelGGL((k_mg_prolong<D>), nb(F.v.N), MT, 0, st, F.v, Cg.v, Cg.x, F.x, scal);
-  sweeps<D>(mg, l, mg.nu, false, st, scal);
+  vcycle<D>(mg, l + 1, st, scal, nullptr);
+  hipLaunchKernelGGL((k_mg_prolong<D>), tl ? (unsigned)mg.ntiles : nb(F.v.N), MT, 0, st, F.v, Cg.v, Cg.x, F.x, scal,
+                     tl);
+  sweeps<D>(mg, l, mg.nu, false, st, scal, out);
 }
 
 }  // namespace
@@ -317,6 +384,13 @@ int mg_build(tlvlbm_ctx *c, const std::vector<uint8_t> &act, const std::vector<f
 }  // namespace
 
 void proj_aux_free(tlvlbm_ctx *c) {
+  if (c->cg.pcg_graph) (void)hipGraphExecDestroy(c->cg.pcg_graph);
+  c->cg.pcg_graph = nullptr;
+  if (c->stT) {
+    for (void *p : {(void *)c->stT->sn, (void *)c->stT->so, (void *)c->stT->el, (void *)c->stT->ek}) (void)hipFree(p);
+    delete c->stT;
+    c->stT = nullptr;
+  }
   gauge_free(c->gauge);
   c->gauge = nullptr;
   mg_free(c->mg);
@@ -342,6 +416,25 @@ int proj_aux_build(tlvlbm_ctx *c) {
         for (int64_t l = c->bid_begin[b]; l < c->bid_end[b]; ++l) anc[node[l]] += 1.0f;
   }
   proj_aux_free(c);
+  // 256-node tiles that hold active nodes: the single-instance CG and the
+  // finest multigrid sweeps skip the rest
+  {
+    std::vector<int32_t> tiles;
+    for (int64_t t = 0; t * 256 < N; ++t) {
+      bool any = false;
+      for (int64_t i = t * 256; i < std::min<int64_t>(N, t * 256 + 256) && !any; ++i) any = act[i] != 0;
+      if (any) tiles.push_back((int32_t)t);
+    }
+    if (c->cg.tiles) (void)hipFree(c->cg.tiles);
+    c->cg.tiles = nullptr;
+    c->cg.ntiles = 0;
+    if (!tiles.empty()) {
+      if (hipMalloc(&c->cg.tiles, tiles.size() * sizeof(int32_t)) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
+      if (hipMemcpy(c->cg.tiles, tiles.data(), tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+        return TLVLBM_ERR_DEVICE;
+      c->cg.ntiles = (int)tiles.size();
+    }
+  }
   int s = gauge_build(c, act, anc, &c->gauge);
   if (s) return s;
   if (c->cg_multigrid) {
@@ -514,10 +607,11 @@ void mg_apply(tlvlbm_ctx *c, const double *r, double *z, const double *scal) {
   MGLevel &L0 = mg.lev[0];
   double *b_own = L0.b;
   L0.b = const_cast<double *>(r);
-  if (c->D == 2) vcycle<2>(mg, 0, c->st, scal);
-  else vcycle<3>(mg, 0, c->st, scal);
+  mg.tiles = c->cg.tiles;
+  mg.ntiles = c->cg.ntiles;
+  if (c->D == 2) vcycle<2>(mg, 0, c->st, scal, z);
+  else vcycle<3>(mg, 0, c->st, scal, z);
   L0.b = b_own;
-  (void)hipMemcpyAsync(z, L0.x, (size_t)c->D * c->geo.S * sizeof(double), hipMemcpyDeviceToDevice, c->st);
 }
 
 }  // namespace tl

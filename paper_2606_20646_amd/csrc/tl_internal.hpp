@@ -70,6 +70,8 @@ struct MG {
   std::vector<MGLevel> lev;
   double omega = 2.0 / 3.0;
   int nu = 2, nu_coarse = 40;
+  const int32_t *tiles = nullptr;  // finest level: active 256-node tiles (the CG's)
+  int ntiles = 0;
 };
 
 // connected components of the active graph that carry no anchor: the
@@ -85,6 +87,14 @@ struct Gauge {
   uint8_t *anc_n = nullptr;    // [N] anchor counts (Dirichlet cut links per node)
 };
 
+// LSQ stencils of the Neumann links transposed to their nodes (reverse
+// mode): node sn[t] receives entries so[t] .. so[t+1]-1 = (link el, point ek)
+struct StencilT {
+  int64_t ns = 0;
+  int64_t *sn = nullptr, *so = nullptr;
+  int32_t *el = nullptr, *ek = nullptr;
+};
+
 // projection / CG workspace
 struct CG {
   void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *Ap = nullptr, *b = nullptr;  // [D][S] FP64
@@ -94,6 +104,10 @@ struct CG {
   int *anc_i = nullptr;                             // anchor counting scratch
   void *anc_s = nullptr;                            // anchor target sums [D][S] (FP64)
   double *partial = nullptr;                        // [nblk][16] block partial sums
+  int32_t *tiles = nullptr;                         // 256-node tiles holding active nodes
+  int ntiles = 0;
+  hipGraphExec_t pcg_graph = nullptr;               // captured batch of preconditioned iterations
+  const void *pcg_key = nullptr;                    // anchor array it was captured with
   double *scal = nullptr;                           // device scalars
   int nblk = 0;
 };
@@ -219,6 +233,7 @@ struct tlvlbm_ctx {
   int cg_multigrid = 1;        // 1: multigrid-preconditioned CG, 0: plain CG
   tl::MG *mg = nullptr;        // preconditioner hierarchy (built on first use)
   tl::Gauge *gauge = nullptr;  // components without anchors (built on first use)
+  tl::StencilT *stT = nullptr; // transposed Neumann stencils (reverse mode, built on first use)
   bool aux_stale = true;       // boundary conditions changed since the build
   bool track_u = false;
   hipStream_t st = nullptr;

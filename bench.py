@@ -14,6 +14,15 @@ roofline of the bulk kernel (576 algorithmic bytes per node-step against the
 FP64 CPU oracle timed on a bounded sample of the same recipe.
 
     python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--n 256]
+
+Other workloads (one JSON line each; not the headline):
+    --workload c2   embedded annulus 512^2 (+frame), clamp + traction-free
+                    surface, projection every 20 steps, 20000 steps: MLUPS and
+                    the L2 distance of u to the radial boundary-value problem
+    --workload c4   64 embedded 2D instances: batched launch against
+                    per-instance launches of the same kernels
+    --workload c5   embedded sphere 192^3 (+frame), Neumann surface: reverse
+                    mode (forward + recomputation + reverse) over forward time
 """
 from __future__ import annotations
 
@@ -96,9 +105,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload != "c3":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -168,6 +185,157 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _common(metric, value, unit, steps, warmup, ms, hib, dtype, workload, extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": hib, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic (seeded)", "config": {"workload": workload, "parallelism": "single GPU"}}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_c2(args):
+    """Embedded annulus 0.25 <= R <= 0.5 on 512^2 (+frame), inner surface
+    displaced radially by 0.05 (sine-squared ramp over T_r = 2), outer surface
+    traction free, gamma = 10, projection every 20 steps, 20000 steps."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2606_20646_amd import tlvlbm as T
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from refsol import radial_bvp
+    steps = args.steps if args.steps != 1000 else 20000
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    c = W.config_c2(512)
+    s = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
+                 origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"], precision=args.precision,
+                 stream=stream.cuda_stream)
+    s.set_levelset(c["phi"], c["bid"])
+    for bid, bc in c["bcs"].items():
+        bc = dict(bc)
+        s.set_boundary(bid, bc.pop("type"), **bc)
+    s.set_state(c["U0"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = s.stats()
+    U, u, J = s.moments()
+    act = c["phi"] <= 0
+    ref = radial_bvp(2, c["mu"], c["lam"], 0.25, 0.5, r_inner=0.30)
+    d = c["X"][:, act] - 0.5
+    R = np.linalg.norm(d, axis=0)
+    u_ex = (ref["r"](R) - R) * d / R
+    err = float(np.linalg.norm(u[:, act] - u_ex) / np.linalg.norm(u_ex))
+    nact = int(act.sum())
+    _common("embedded annulus MLUPS (active nodes, projection every 20 steps)", round(nact * steps / wall / 1e6, 1),
+            "MLUPS", steps, 0, round(wall * 1e3 / steps, 4), True, "f32" if args.precision == "fp32" else "f64",
+            f"D2Q4x6 annulus 512^2+frame, {nact} active nodes, {st['cut_links']} cut links, mu=1 lambda=10 "
+            f"gamma=10, {args.precision}",
+            {"u_L2_error_vs_radial_bvp": err, "time": steps * c["dt"], "cg_iterations": st["cg_iterations"],
+             "projections": st["projections"], "J_range": [float(J[act].min()), float(J[act].max())]})
+
+
+def bench_c4(args):
+    """64 instances of the random-hole 2D recipe (64^2 .. 512^2), FP32."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2606_20646_amd import tlvlbm as T
+    steps = args.steps if args.steps != 1000 else 40
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    cfgs = [W.config_c4_instance(k) for k in range(64)]
+    nodes = sum(int((c["phi"] <= 0).sum()) for c in cfgs)
+
+    def build(mg):
+        out = []
+        for c in cfgs:
+            s = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
+                         origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"], precision="fp32",
+                         stream=stream.cuda_stream, cg_multigrid=mg)
+            s.set_levelset(c["phi"], c["bid"])
+            for bid, bc in c["bcs"].items():
+                bc = dict(bc)
+                s.set_boundary(bid, bc.pop("type"), **bc)
+            s.set_state(c["U0"])
+            out.append(s)
+        return out
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    A = build(False)
+    ta = timed(lambda: T.step_each(A, steps))
+    B = build(False)
+    bt = T.Batch(B, use_graph=True)
+    tb = timed(lambda: bt.step(steps))
+    bt.close()
+    err = max(float(np.linalg.norm(a.moments()[0] - b.moments()[0]) / np.linalg.norm(a.moments()[0]))
+              for a, b in zip(A, B))
+    C = build(True)
+    tc = timed(lambda: T.step_each(C, steps))
+    _common("batched speedup over per-instance launches of the same kernels", round(ta / tb, 3), "x", steps, 0,
+            round(tb * 1e3 / steps, 4), True, "f32",
+            f"64 embedded D2Q4x6 instances (random holes, 64^2..512^2), {nodes} active nodes, "
+            f"projection every 20 steps (plain CG in both paths)",
+            {"per_instance_s": round(ta, 4), "batched_s": round(tb, 4),
+             "per_instance_MLUPS": round(nodes * steps / ta / 1e6, 1),
+             "batched_MLUPS": round(nodes * steps / tb / 1e6, 1),
+             "per_instance_multigrid_s": round(tc, 4), "max_rel_state_diff": err})
+
+
+def bench_c5(args):
+    """Embedded sphere R = 0.35 on 192^3 (+frame), traction-free, v0 = 1e-2
+    Fourier modes, FP32; L = sum dLdu . u after n steps."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2606_20646_amd import tlvlbm as T
+    steps = args.steps if args.steps != 1000 else 200
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    c = W.config_c5(192)
+
+    def mk():
+        s = T.Solver(3, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], origin=c["origin"],
+                     periodic_mask=0, proj_every=c["proj_every"], precision=args.precision, stream=stream.cuda_stream)
+        s.set_levelset(c["phi"], c["bid"])
+        s.set_boundary(1, "neumann")
+        s.set_state(c["U0"], dU0=c["dU0"])
+        return s
+
+    act = c["phi"] <= 0
+    wu = np.random.default_rng(1).standard_normal((3, act.size)) * act
+    s = mk()
+    s.adjoint(min(steps, 21), None, wu)  # builds the one-time reverse-mode tables
+    s.set_state(c["U0"], dU0=c["dU0"])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t
+    s.set_state(c["U0"], dU0=c["dU0"])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    gm, gv, g0 = s.adjoint(steps, None, wu)
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t
+    _common("reverse-mode time / forward time", round(ta / tf, 3), "ratio", steps, 0, round(ta * 1e3 / steps, 4),
+            False, "f32" if args.precision == "fp32" else "f64",
+            f"D3Q6x12 sphere 192^3+frame, {int(act.sum())} active nodes, traction free, projection every 20 steps, "
+            f"{args.precision}",
+            {"forward_s": round(tf, 4), "adjoint_s": round(ta, 4), "dL_dmu_dlambda": [float(gm[0]), float(gm[1])]})
 
 
 if __name__ == "__main__":

@@ -206,14 +206,120 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
   if (bad || !finite_(chk)) atomicOr(flag, finite_(chk) ? FLAG_J : FLAG_NONFINITE);
 }
 
+// The single-instance kernel keeps the update inline: routed through the
+// device function above, the compiler schedules its address arithmetic
+// differently and the kernel runs 2.6% slower at 256^3 (measured).  The two
+// bodies are kept identical (a CPU test compares them).
 template <int D, typename T, bool MASK, bool TRACK, bool REPAIR>
-__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g,
-                                                             Par p, const uint8_t *__restrict__ act,
-                                                             T *__restrict__ ustar, T *__restrict__ ubuf,
-                                                             const T *__restrict__ Frp, int *__restrict__ flag) {
+__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
+                                               const uint8_t *__restrict__ act, T *__restrict__ ustar,
+                                               T *__restrict__ ubuf, const T *__restrict__ Frp,
+                                               int *__restrict__ flag) {
+  constexpr int Q = 2 * D, M = D + D * D;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
-  bulk_node<D, T, MASK, TRACK, REPAIR>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, (int)blockIdx.y);
+  const int row = blockIdx.y;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = x + (int64_t)g.nx * row;
+  if constexpr (MASK) {
+    if (!act[node]) return;
+  }
+  T f[Q][M];
+  pull_all<D, T, M>(fin, g, x, y, z, f);
+
+  // state recovery with the half-step damping source (Eq. 28): the velocity
+  // is implicit in B = (-gamma v, 0), v = sum_q f^v / (1 + gamma dt / 2)
+  T dU[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    T s = f[0][r];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) s += f[q][r];
+    dU[r] = s;
+  }
+  const T dt = T(p.dt), mu = T(p.mu), lam = T(p.lam), irho = T(p.inv_rho0);
+  const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
+  T v[D], F[D * D], P[D * D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) v[i] = dU[i] * inv_damp;
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
+  T J = piola<D>(F, mu, lam, P);
+  bool bad = !(J > T(0));
+  const T inv2c = T(0.5) / T(p.c);
+  const T inv2D = T(1) / T(2 * D);
+
+  if constexpr (REPAIR) {
+    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61)
+    T Fr[D * D], P1[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Fr[k] = Frp[(size_t)k * g.S + node];
+    const T J1 = piola<D>(Fr, mu, lam, P1);
+    bad |= !(J1 > T(0));
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int A = q / 2;
+      const T sg = (q & 1) ? T(-1) : T(1);
+#pragma unroll
+      for (int i = 0; i < D; ++i) f[q][i] += sg * inv2c * (-(P1[i * D + A] - P[i * D + A]) * irho);
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) f[q][D + k] += (Fr[k] - F[k]) * inv2D;
+    }
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+      F[k] = Fr[k];
+      P[k] = P1[k];
+      dU[D + k] = Fr[k] - ((k % (D + 1) == 0) ? T(1) : T(0));
+    }
+    J = J1;
+  }
+
+  // BGK collision with source weights 1/(4D) (Eqs. 29-30).  Shifted
+  // equilibrium: feq_q - U_I/(2D) = (U - U_I)/(2D) + e_qA Phi_A(U) / (2c).
+  const T om = T(p.omega);
+  const T srcw = dt * (T(2) - om) / T(4 * D);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int A = q / 2;
+    const T sg = (q & 1) ? T(-1) : T(1);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      T phi;
+      T base;
+      if (r < D) {
+        phi = -P[r * D + A] * irho;
+        base = v[r];
+      } else {
+        const int i = (r - D) / D, B = (r - D) % D;
+        phi = (A == B) ? -v[i] : T(0);
+        base = dU[r];
+      }
+      const T feq = base * inv2D + sg * inv2c * phi;
+      T out = f[q][r] + om * (feq - f[q][r]);
+      if (r < D) out += srcw * (-T(p.gamma) * v[r]);
+      st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
+    }
+  }
+
+  if constexpr (TRACK) {
+    // trapezoidal displacement quadrature (Eq. 34)
+    const T hdt = T(0.5) * dt;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T uu;
+      if constexpr (REPAIR) {
+        uu = ubuf[(size_t)i * g.S + node];
+      } else {
+        uu = ustar[(size_t)i * g.S + node] + hdt * v[i];
+        ubuf[(size_t)i * g.S + node] = uu;
+      }
+      ustar[(size_t)i * g.S + node] = uu + hdt * v[i];
+    }
+  }
+  T chk = J;
+#pragma unroll
+  for (int i = 0; i < D; ++i) chk += v[i];
+  if (bad || !finite_(chk)) atomicOr(flag, finite_(chk) ? FLAG_J : FLAG_NONFINITE);
 }
 
 // the same update recording the recovered state on the reverse-mode tape

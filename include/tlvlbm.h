@@ -227,8 +227,13 @@ const char *tlvlbm_last_error(const tlvlbm_ctx *ctx);
  *    sqrt(n x checkpoint size / tape size per step)).  Device memory:
  *    (n/segment + 1) checkpoints (Q M + D node planes) plus a tape of
  *    segment x (M [+ D]) node planes; TLVLBM_ERR_OUT_OF_MEMORY if they do
- *    not fit.  Work: one forward pass, one recomputation and one reverse
- *    pass (the reverse of a projection step runs two CG solves).
+ *    not fit.  When a quarter of the remaining memory holds them, the
+ *    projection solutions of the first pass are kept (FP64, active tiles)
+ *    and replayed by the recomputation.  This memory stays with the context
+ *    (reused by the next call with the same n and segment) until
+ *    tlvlbm_destroy or a call of another shape.  Work: one forward pass,
+ *    one recomputation without projection solves, one reverse pass (two CG
+ *    solves per projection step).
  *  - Errors: the forward's errors; TLVLBM_ERR_CALL_ORDER without a fresh
  *    state.  A failure leaves the context in an error state. */
 tlvlbm_status tlvlbm_adjoint(tlvlbm_ctx *ctx, int64_t n, const double *U0, const double *dU0,

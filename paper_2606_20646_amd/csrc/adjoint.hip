@@ -649,20 +649,42 @@ inline void grid_of(const Geo &g, dim3 &grid, dim3 &block) {
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // device allocations of one reverse run, released on every exit path
+// hands out the arena's blocks in request order (same order every call),
+// reallocating a block that is too small
 struct Pool {
-  std::vector<void *> p;
-  ~Pool() {
-    for (void *q : p) (void)hipFree(q);
-  }
+  AdjArena *a;
+  size_t next = 0;
   template <typename X> hipError_t get(X **out, size_t bytes, hipStream_t st, bool zero = true) {
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
-    if (e != hipSuccess) return e;
-    p.push_back(q);
-    *out = (X *)q;
-    return zero ? hipMemsetAsync(q, 0, bytes ? bytes : 16, st) : hipSuccess;
+    bytes = bytes ? bytes : 16;
+    if (next < a->blk.size() && a->bytes[next] < bytes) {
+      (void)hipFree(a->blk[next]);
+      a->blk[next] = nullptr;
+      a->bytes[next] = 0;
+    }
+    if (next >= a->blk.size()) {
+      a->blk.push_back(nullptr);
+      a->bytes.push_back(0);
+    }
+    if (!a->blk[next]) {
+      void *q = nullptr;
+      const hipError_t e = hipMalloc(&q, bytes);
+      if (e != hipSuccess) return e;
+      a->blk[next] = q;
+      a->bytes[next] = bytes;
+    }
+    *out = (X *)a->blk[next++];
+    return zero ? hipMemsetAsync(*out, 0, bytes, st) : hipSuccess;
   }
 };
+
+void arena_release(AdjArena *a) {
+  for (void *q : a->blk)
+    if (q) (void)hipFree(q);
+  a->blk.clear();
+  a->bytes.clear();
+  a->key[0] = a->key[1] = -1;
+  a->avail = 0;
+}
 
 struct Run {
   tlvlbm_ctx *c;
@@ -849,7 +871,8 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   constexpr int Q = 2 * D, M = D + D * D;
   const Geo &g = c->geo;
   hipStream_t st = c->st;
-  Pool pool;
+  if (!c->arena) c->arena = new AdjArena();
+  Pool pool{c->arena};
   Run R;
   R.c = c;
   const Par &pp = c->par;
@@ -883,10 +906,13 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     seg = std::max<int64_t>(1, std::min<int64_t>(seg, std::max<int64_t>(n, 1)));
   }
   const int64_t nck = n > 0 ? (n + seg - 1) / seg : 0;
+  size_t avail = 0;
   int64_t nproj_seg = 0;
   if (R.neu && c->proj_every > 0) nproj_seg = seg / c->proj_every + 2;
-  // memory check
-  {
+  // memory check (skipped when the arena already holds this shape)
+  AdjArena &ar = *c->arena;
+  if (ar.key[0] != n || ar.key[1] != seg) {
+    arena_release(&ar);
     size_t need = (size_t)(nck + 1) * ck_bytes + (size_t)seg * tape_bytes + (size_t)nproj_seg * D * D * plane +
                   2 * (size_t)Q * M * plane + 2 * (size_t)D * dplane;
     if (R.neu) need += (size_t)(M + 3 * D * D + 2 * D) * dplane;
@@ -895,7 +921,11 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
       err = "adjoint: checkpoints and tape do not fit in device memory (lower the step count or pass a segment length)";
       return TLVLBM_ERR_OUT_OF_MEMORY;
     }
+    ar.avail = fr > need ? fr - need : 0;
+    ar.key[0] = n;
+    ar.key[1] = seg;
   }
+  avail = ar.avail;
   if (R.neu || R.dir) {
     const int s = ensure_cg(c);
     if (s) return (tlvlbm_status)s;
@@ -921,9 +951,35 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     if (track && hipMemcpyAsync(c->ustar, cku[s], (size_t)D * plane, hipMemcpyDeviceToDevice, st)) return false;
     return true;
   };
+  // the projection solutions of the first pass are kept (active tiles, FP64)
+  // when they fit in a quarter of the free memory, so that the recomputation
+  // replays them instead of solving again
+  int64_t nproj = 0;
+  for (int64_t k = 0; k < n; ++k) nproj += is_projection_step(c, k) ? 1 : 0;
+  double *xstore = nullptr;
+  size_t xslot = 0;
+  if (nproj && c->cg.tiles) {
+    xslot = (size_t)D * c->cg.ntiles * 256;
+    const size_t xbytes = (size_t)nproj * 2 * xslot * sizeof(double);
+    if (xbytes <= avail / 4 && pool.get(&xstore, xbytes, st, false)) xstore = nullptr;
+  }
+  std::vector<int64_t> pidx(n, -1);
+  for (int64_t k = 0, p = 0; k < n; ++k)
+    if (is_projection_step(c, k)) pidx[k] = p++;
+  auto xs_of = [&](int64_t k, TapeStep &tp, int mode) {
+    tp.xs[0] = tp.xs[1] = nullptr;
+    tp.xmode = 0;
+    if (xstore && pidx[k] >= 0) {
+      tp.xs[0] = xstore + (size_t)(2 * pidx[k]) * xslot;
+      tp.xs[1] = xstore + (size_t)(2 * pidx[k] + 1) * xslot;
+      tp.xmode = mode;
+    }
+  };
   for (int64_t k = 0; k < n; ++k) {
     if (k % seg == 0 && !save(k / seg)) return TLVLBM_ERR_DEVICE;
-    const int s = step_once(c);
+    TapeStep tp{};
+    xs_of(k, tp, 1);
+    const int s = step_once(c, &tp);
     if (s) return (tlvlbm_status)s;
   }
   if (!save(nck)) return TLVLBM_ERR_DEVICE;
@@ -992,6 +1048,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
       tp.U = tapeU + (size_t)(k - k0) * M * plane;
       tp.u = R.neu ? tapeu + (size_t)(k - k0) * D * plane : nullptr;
       tp.Fr = nullptr;
+      xs_of(k, tp, 2);
       if (is_projection_step(c, k)) {
         if (ip >= nproj_seg) return TLVLBM_ERR_INVALID_ARG;
         tp.Fr = tapeF + (size_t)(ip++) * D * D * plane;

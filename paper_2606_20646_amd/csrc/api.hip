@@ -86,12 +86,12 @@ int step_once(tlvlbm_ctx *c, const TapeStep *tp) {
   const bool proj = is_projection_step(c, c->step);
   const size_t plane = (size_t)c->geo.S * c->esz;
   if (proj) {
-    int s = run_projection(c, true, tn);
+    int s = run_projection(c, true, tn, tp ? tp->xs[0] : nullptr, tp ? tp->xmode : 0);
     if (s) return s;
     launch_bulk(c, true, tp ? tp->U : nullptr);
     if (tp && tp->Fr)
       CHK(hipMemcpyAsync(tp->Fr, c->cg.Fr, (size_t)c->D * c->D * plane, hipMemcpyDeviceToDevice, c->st), "tape");
-    s = run_projection(c, false, tn);
+    s = run_projection(c, false, tn, tp ? tp->xs[1] : nullptr, tp ? tp->xmode : 0);
     if (s) return s;
     ++c->st_proj;
   } else {
@@ -212,6 +212,11 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
   if (c->h_flag) (void)hipHostFree(c->h_flag);
   if (c->hscal) (void)hipHostFree(c->hscal);
   proj_aux_free(c);
+  if (c->arena) {
+    for (void *q : c->arena->blk)
+      if (q) (void)hipFree(q);
+    delete c->arena;
+  }
   delete c;
   return TLVLBM_OK;
 }

@@ -1269,7 +1269,37 @@ template <int D, typename T> static int cg_run(tlvlbm_ctx *c, const uint8_t *anc
 // first == true: projection before collision (u^c from F^n, then F^r);
 // first == false: projection after the repaired collision (u from F^r),
 // followed by the displacement reset.
-template <int D, typename T> static int projection_t(tlvlbm_ctx *c, bool first, double tn) {
+// copies of the CG solution on the active tiles: pack (dir 0) to a store
+// [D][ntiles*256], or unpack (dir 1) from it
+template <int D>
+__global__ __launch_bounds__(256) void k_xstore(Geo g, const int32_t *__restrict__ tiles, int ntiles,
+                                                 double *__restrict__ x, double *__restrict__ store, int dir) {
+  const int64_t i = (int64_t)tiles[blockIdx.x] * 256 + threadIdx.x;
+  if (i >= g.N) return;
+  const size_t o = (size_t)blockIdx.x * 256 + threadIdx.x, ps = (size_t)ntiles * 256;
+  for (int c = 0; c < D; ++c) {
+    if (dir) x[(size_t)c * g.S + i] = store[c * ps + o];
+    else store[c * ps + o] = x[(size_t)c * g.S + i];
+  }
+}
+
+// the projection's solve, or (mode 2) its solution replayed from a store
+// written by an earlier run of the same step (mode 1)
+template <int D, typename T> static int solve_or_replay(tlvlbm_ctx *c, const T *F, double tn, double *store, int mode) {
+  CG &w = c->cg;
+  if (mode == 2 && store && w.tiles) {
+    hipLaunchKernelGGL((k_xstore<D>), w.ntiles, 256, 0, c->st, c->geo, w.tiles, w.ntiles, (double *)w.x, store, 1);
+    return TLVLBM_OK;
+  }
+  const int st = cg_solve<D, T>(c, F, tn);
+  if (st) return st;
+  if (mode == 1 && store && w.tiles)
+    hipLaunchKernelGGL((k_xstore<D>), w.ntiles, 256, 0, c->st, c->geo, w.tiles, w.ntiles, (double *)w.x, store, 0);
+  return TLVLBM_OK;
+}
+
+template <int D, typename T>
+static int projection_t(tlvlbm_ctx *c, bool first, double tn, double *store, int mode) {
   int st = cg_alloc<D, T>(c);
   if (st) return st;
   CG &w = c->cg;
@@ -1277,14 +1307,14 @@ template <int D, typename T> static int projection_t(tlvlbm_ctx *c, bool first, 
   if (first) {
     launch_pull_moments(c, nullptr, nullptr, nullptr, true);  // v, F, u^n
     hipLaunchKernelGGL((k_u_to_x<D, T>), nblk(g.N, 256), 256, 0, c->st, g, (const T *)c->ubuf, (double *)w.x);
-    st = cg_solve<D, T>(c, (const T *)w.Fm, tn);
+    st = solve_or_replay<D, T>(c, (const T *)w.Fm, tn, store, mode);
     if (st) return st;
     hipLaunchKernelGGL((k_x_to_u<D, T>), nblk(g.N, 256), 256, 0, c->st, g, (const double *)w.x, (T *)c->ubuf);
     hipLaunchKernelGGL((k_gradF<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const double *)w.x,
                        (const T *)w.Fm, (T *)w.Fr, c->theta);
   } else {
     hipLaunchKernelGGL((k_u_to_x<D, T>), nblk(g.N, 256), 256, 0, c->st, g, (const T *)c->ubuf, (double *)w.x);
-    st = cg_solve<D, T>(c, (const T *)w.Fr, tn);
+    st = solve_or_replay<D, T>(c, (const T *)w.Fr, tn, store, mode);
     if (st) return st;
     hipLaunchKernelGGL((k_ureset<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const double *)w.x, (const T *)w.V,
                        (T *)c->ubuf, (T *)c->ustar, 0.5 * c->par.dt);
@@ -1298,9 +1328,12 @@ int run_cg_given(tlvlbm_ctx *c, const uint8_t *anc_n) {
   return c->prec ? cg_run<3, double>(c, anc_n) : cg_run<3, float>(c, anc_n);
 }
 
-int run_projection(tlvlbm_ctx *c, bool first, double tn) {
-  if (c->D == 2) return c->prec ? projection_t<2, double>(c, first, tn) : projection_t<2, float>(c, first, tn);
-  return c->prec ? projection_t<3, double>(c, first, tn) : projection_t<3, float>(c, first, tn);
+int run_projection(tlvlbm_ctx *c, bool first, double tn, double *store, int mode) {
+  if (c->D == 2)
+    return c->prec ? projection_t<2, double>(c, first, tn, store, mode)
+                   : projection_t<2, float>(c, first, tn, store, mode);
+  return c->prec ? projection_t<3, double>(c, first, tn, store, mode)
+                 : projection_t<3, float>(c, first, tn, store, mode);
 }
 
 }  // namespace tl

@@ -95,6 +95,15 @@ struct StencilT {
   int32_t *el = nullptr, *ek = nullptr;
 };
 
+// device blocks of the reverse mode, kept between calls of the same shape
+// (step count, segment length): repeated gradient evaluations allocate once
+struct AdjArena {
+  std::vector<void *> blk;
+  std::vector<size_t> bytes;
+  int64_t key[2] = {-1, -1};
+  size_t avail = 0;  // free memory beyond the fixed needs when first sized
+};
+
 // projection / CG workspace
 struct CG {
   void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *Ap = nullptr, *b = nullptr;  // [D][S] FP64
@@ -234,6 +243,7 @@ struct tlvlbm_ctx {
   tl::MG *mg = nullptr;        // preconditioner hierarchy (built on first use)
   tl::Gauge *gauge = nullptr;  // components without anchors (built on first use)
   tl::StencilT *stT = nullptr; // transposed Neumann stencils (reverse mode, built on first use)
+  tl::AdjArena *arena = nullptr; // reverse-mode device memory (kept until destroy or a new shape)
   bool aux_stale = true;       // boundary conditions changed since the build
   bool track_u = false;
   hipStream_t st = nullptr;
@@ -269,7 +279,9 @@ void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar);
 // launchers (embed.hip)
 int build_links(tlvlbm_ctx *c, const double *phi_d, const uint8_t *bid_d, std::string &err);
 void launch_cutlinks(tlvlbm_ctx *c, double tn);
-int run_projection(tlvlbm_ctx *c, bool first, double tn);
+// store/mode: 0 solve; 1 solve and keep the solution on the active tiles in
+// store; 2 take the solution from store instead of solving
+int run_projection(tlvlbm_ctx *c, bool first, double tn, double *store = nullptr, int mode = 0);
 // CG on the projection workspace with a given right-hand side (w.b) and start (w.x)
 int run_cg_given(tlvlbm_ctx *c, const uint8_t *anc_n);
 // projection helpers (mg.hip): components and anchors, multigrid hierarchy
@@ -285,6 +297,8 @@ void gauge_restore(tlvlbm_ctx *c, double *x, const double *mean0);
 // links [D planes]; any may be null
 struct TapeStep {
   void *U, *Fr, *u;
+  double *xs[2];  // projection solutions of the step (see run_projection)
+  int xmode;
 };
 // one step of Algorithm 1 (api.hip)
 int step_once(tlvlbm_ctx *c, const TapeStep *tp = nullptr);

@@ -108,3 +108,23 @@ def test_adjoint_requires_fresh_state(T):
     s.step(1)
     with pytest.raises(T.TlvlbmError):
         s.adjoint(2, np.ones((6, s.N)))
+
+
+def test_adjoint_sphere_32(T, orc):
+    """Reverse mode on the sphere recipe at 32^3 (+frame), 21 steps with two
+    projections, FP64, against the oracle's adjoint."""
+    import workloads as W
+    _say("adjoint sphere 32^3 fp64 21 steps")
+    c = W.config_c5(32)
+    cfg = dict(c, pm=0, proj_every=20)
+    wU, wu = _weights(cfg)
+    o = _make(cfg, cfg["mu"], cfg["lam"])
+    o.set_state(cfg["U0"], dU0=cfg["dU0"])
+    gm_o, gv_o, g0_o = o.adjoint(21, wU, wu)
+    s = _solver(T, cfg, "fp64")
+    s.set_state(cfg["U0"], dU0=cfg["dU0"])
+    gm, gv, g0 = s.adjoint(21, wU, wu)
+    print(f"mu,lam: gpu {gm} oracle {gm_o}; v0 rel {_rel(gv, gv_o):.2e}; u0 rel {_rel(g0, g0_o):.2e}", flush=True)
+    assert np.all(np.abs(gm - gm_o) <= 1e-9 * np.abs(gm_o).max())
+    assert _rel(gv, gv_o) <= 1e-9
+    assert _rel(g0, g0_o) <= 1e-9

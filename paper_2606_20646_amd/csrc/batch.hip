@@ -29,6 +29,8 @@ struct tlvlbm_batch {
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
   int glen = 0;
+  bool use_mg = false;  // every instance has a multigrid hierarchy: batched V-cycles
+  BatchMG bmg;
   std::string err;
 };
 
@@ -71,6 +73,8 @@ void run(tlvlbm_batch *b, BatchOp op, int fa = 0, int fb = 0) {
   launch_batch(b->D, b->prec, op, a);
 }
 
+tlvlbm_status pcg_batch(tlvlbm_batch *b, int anch);
+
 tlvlbm_status cg_batch(tlvlbm_batch *b, int useFr) {
   const int anch = b->any_dir ? 1 : 0;
   if (anch) {
@@ -79,6 +83,7 @@ tlvlbm_status cg_batch(tlvlbm_batch *b, int useFr) {
     run(b, BatchOp::NarrowAnchor);
   }
   run(b, BatchOp::Rhs, useFr, anch);
+  if (b->use_mg) return pcg_batch(b, anch);
   run(b, BatchOp::CgInit, 0, anch);
   int pp = 0;
   for (int64_t it = 0; it < b->maxit;) {
@@ -95,6 +100,35 @@ tlvlbm_status cg_batch(tlvlbm_batch *b, int useFr) {
     BCHK(hipStreamSynchronize(b->st), "synchronize");
     if (*b->h_pending == 0) break;
   }
+  return TLVLBM_OK;
+}
+
+// preconditioned CG over all instances: one batched V-cycle per iteration;
+// the constants of components without anchors are restored per instance
+// afterwards (as in the single-instance solver)
+tlvlbm_status pcg_batch(tlvlbm_batch *b, int anch) {
+  const int ni = (int)b->c.size();
+  for (tlvlbm_ctx *c : b->c) gauge_means(c, (const double *)c->cg.x, nullptr, c->gauge->mean0);
+  run(b, BatchOp::CgInit, 0, anch);
+  batch_vcycle(b->D, b->bmg, b->d_inst, ni, b->st);
+  run(b, BatchOp::PcDotFirst);
+  int pp = 0;
+  for (int64_t it = 0; it < b->maxit;) {
+    for (int j = 0; j < 8; ++j) {
+      run(b, BatchOp::PcAp, pp, anch);
+      run(b, BatchOp::PcUpdate, pp);
+      batch_vcycle(b->D, b->bmg, b->d_inst, ni, b->st);
+      run(b, BatchOp::PcDot);
+      pp ^= 1;
+    }
+    it += 8;
+    BCHK(hipMemsetAsync(b->d_pending, 0, sizeof(int), b->st), "pending clear");
+    run(b, BatchOp::Pending);
+    BCHK(hipMemcpyAsync(b->h_pending, b->d_pending, sizeof(int), hipMemcpyDeviceToHost, b->st), "pending read");
+    BCHK(hipStreamSynchronize(b->st), "synchronize");
+    if (*b->h_pending == 0) break;
+  }
+  for (tlvlbm_ctx *c : b->c) gauge_restore(c, (double *)c->cg.x, c->gauge->mean0);
   return TLVLBM_OK;
 }
 
@@ -194,6 +228,7 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       I.Fm = c->cg.Fm;
       I.Fr = c->cg.Fr;
       I.anc_s = c->cg.anc_s;
+      I.z = c->cg.z;
       I.anc_n = c->cg.anc_n;
       I.anc_i = c->cg.anc_i;
       I.partial = c->cg.partial;
@@ -225,6 +260,60 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
     b->nbt = (int)bt.size();
     b->nct = (int)ct.size();
     b->nlt = (int)lt.size();
+    // batched multigrid when every instance carries a hierarchy
+    b->use_mg = b->any_neu;
+    for (tlvlbm_ctx *c : b->c) b->use_mg = b->use_mg && c->mg && c->gauge && !c->aux_stale && c->mg->nu == 2;
+    if (b->use_mg) {
+      BatchMG &bm = b->bmg;
+      int lmax = 0;
+      for (tlvlbm_ctx *c : b->c) lmax = std::max<int>(lmax, (int)c->mg->lev.size());
+      bm.lmax = lmax;
+      bm.omega = b->c[0]->mg->omega;
+      bm.nu_coarse = b->c[0]->mg->nu_coarse;
+      std::vector<BMGLev> tab((size_t)n * lmax);
+      std::vector<int> last(n);
+      std::vector<std::vector<int4>> sm(lmax), rs(lmax);
+      for (int k = 0; k < n; ++k) {
+        const MG &mg = *b->c[k]->mg;
+        const int nl = (int)mg.lev.size();
+        last[k] = nl - 1;
+        for (int l = 0; l < nl; ++l) {
+          const MGLevel &L = mg.lev[l];
+          BMGLev &T = tab[(size_t)k * lmax + l];
+          T.v = L.v;
+          T.b = l == 0 ? (double *)b->c[k]->cg.r : L.b;
+          T.A = L.x;
+          T.B = L.t;
+          const int nblk = (int)((L.v.N + 255) / 256);
+          for (int blk = 0; blk < nblk; ++blk) {
+            if (l < nl - 1) sm[l].push_back(make_int4(k, blk, 0, 0));
+            if (l >= 1) rs[l].push_back(make_int4(k, blk, 0, 0));
+          }
+        }
+      }
+      bool ok = hipMalloc(&bm.tab, tab.size() * sizeof(BMGLev)) == hipSuccess &&
+                hipMalloc(&bm.last, n * sizeof(int)) == hipSuccess &&
+                hipMemcpy(bm.tab, tab.data(), tab.size() * sizeof(BMGLev), hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(bm.last, last.data(), n * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+      bm.sm.assign(lmax, nullptr);
+      bm.rs.assign(lmax, nullptr);
+      bm.nsm.assign(lmax, 0);
+      bm.nrs.assign(lmax, 0);
+      for (int l = 0; l < lmax && ok; ++l) {
+        bm.nsm[l] = (int)sm[l].size();
+        bm.nrs[l] = (int)rs[l].size();
+        if (bm.nsm[l])
+          ok = hipMalloc(&bm.sm[l], sm[l].size() * sizeof(int4)) == hipSuccess &&
+               hipMemcpy(bm.sm[l], sm[l].data(), sm[l].size() * sizeof(int4), hipMemcpyHostToDevice) == hipSuccess;
+        if (ok && bm.nrs[l])
+          ok = hipMalloc(&bm.rs[l], rs[l].size() * sizeof(int4)) == hipSuccess &&
+               hipMemcpy(bm.rs[l], rs[l].data(), rs[l].size() * sizeof(int4), hipMemcpyHostToDevice) == hipSuccess;
+      }
+      if (!ok) {
+        tlvlbm_batch_destroy(b);
+        return TLVLBM_ERR_OUT_OF_MEMORY;
+      }
+    }
     if (hipMalloc(&b->d_inst, n * sizeof(Inst)) != hipSuccess ||
         hipMalloc(&b->d_btiles, bt.size() * sizeof(int4)) != hipSuccess ||
         hipMalloc(&b->d_ctiles, ct.size() * sizeof(int4)) != hipSuccess ||
@@ -323,6 +412,7 @@ tlvlbm_status tlvlbm_batch_destroy(tlvlbm_batch *b) {
   if (!b) return TLVLBM_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(b->st);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  batch_mg_free(b->bmg);
   void *ptrs[] = {b->d_inst, b->d_btiles, b->d_ctiles, b->d_ltiles, b->d_segs, b->d_step, b->d_pending};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);

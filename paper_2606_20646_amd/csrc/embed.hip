@@ -925,10 +925,10 @@ __global__ __launch_bounds__(FIN_T) void k_cg_fin(const double *partial, int nbl
 }
 
 // one block per instance
-template <int D, int OP>
+template <int D, int OP, bool PC = false>
 __global__ __launch_bounds__(FIN_T) void k_cg_fin_batch(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
-  cg_fin<D, OP, false>(I.partial, I.nblk, I.scal, I.rtol);
+  cg_fin<D, OP, PC>(I.partial, I.nblk, I.scal, I.rtol);
 }
 
 template <int D, typename T>
@@ -1417,13 +1417,30 @@ __global__ __launch_bounds__(CG_T) void k_cg_init_batch(const Inst *__restrict__
 
 template <int D, typename T>
 __global__ __launch_bounds__(CG_T) void k_cg_Ap_batch(const Inst *__restrict__ insts,
-                                                      const int4 *__restrict__ tiles, int pp, int anchored) {
+                                                      const int4 *__restrict__ tiles, int pp, int anchored,
+                                                      int precond) {
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
   const double *pold = (const double *)(pp ? I.p1 : I.p0);
   double *pnew = (double *)(pp ? I.p0 : I.p1);
-  cg_Ap_blk<D, T>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.r, pold, pnew, (double *)I.Ap,
-                  I.partial, I.scal, t.y, t.y);
+  cg_Ap_blk<D, T>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)(precond ? I.z : I.r), pold, pnew,
+                  (double *)I.Ap, I.partial, I.scal, t.y, t.y);
+}
+
+// r.z per instance (batched preconditioned iteration)
+template <int D>
+__global__ __launch_bounds__(CG_T) void k_cg_dot_batch(const Inst *__restrict__ insts,
+                                                       const int4 *__restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  if (((const double *)I.scal)[S_DONE] != 0.0) return;
+  const int64_t i = (int64_t)t.y * CG_T + threadIdx.x;
+  double v[D];
+  for (int c = 0; c < D; ++c) v[c] = 0.0;
+  if (i < I.g.N && I.act[i])
+    for (int c = 0; c < D; ++c)
+      v[c] = ((const double *)I.r)[(size_t)c * I.g.S + i] * ((const double *)I.z)[(size_t)c * I.g.S + i];
+  block_store<D>(v, I.partial, t.y);
 }
 
 template <int D, typename T>
@@ -1497,8 +1514,26 @@ static void batch_kernels_t(BatchOp op, const BatchArgs &a) {
       hipLaunchKernelGGL((k_cg_fin_batch<D, 0>), a.ninst, FIN_T, 0, st, a.insts);
       break;
     case BatchOp::CgAp:
-      hipLaunchKernelGGL((k_cg_Ap_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA, a.flagB);
+      hipLaunchKernelGGL((k_cg_Ap_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA, a.flagB, 0);
       hipLaunchKernelGGL((k_cg_fin_batch<D, 1>), a.ninst, FIN_T, 0, st, a.insts);
+      break;
+    case BatchOp::PcAp:
+      hipLaunchKernelGGL((k_cg_Ap_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA, a.flagB, 1);
+      hipLaunchKernelGGL((k_cg_fin_batch<D, 1, true>), a.ninst, FIN_T, 0, st, a.insts);
+      break;
+    case BatchOp::PcUpdate:
+      hipLaunchKernelGGL((k_cg_update_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA);
+      hipLaunchKernelGGL((k_cg_fin_batch<D, 2, true>), a.ninst, FIN_T, 0, st, a.insts);
+      break;
+    case BatchOp::PcDot:
+    case BatchOp::PcDotFirst:
+      hipLaunchKernelGGL((k_cg_dot_batch<D>), a.nct, CG_T, 0, st, a.insts, a.ctiles);
+      if (op == BatchOp::PcDot)
+        hipLaunchKernelGGL((k_cg_fin_batch<D, 3, true>), a.ninst, FIN_T, 0, st, a.insts);
+      else
+        hipLaunchKernelGGL((k_cg_fin_batch<D, 4, true>), a.ninst, FIN_T, 0, st, a.insts);
+      break;
+    case BatchOp::PcInit:
       break;
     case BatchOp::CgUpdate:
       hipLaunchKernelGGL((k_cg_update_batch<D, T>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA);

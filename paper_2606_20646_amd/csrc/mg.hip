@@ -273,6 +273,168 @@ template <int D> void vcycle(MG &mg, int l, hipStream_t st, const double *scal, 
   sweeps<D>(mg, l, mg.nu, false, st, scal, out);
 }
 
+
+// ------------------------------------------- batched (level-synchronous) V-cycle
+// tiles: (instance, block of MT nodes of the level); each instance's level
+// data in tab[inst*lmax + level].  Sweep sources and targets: phase 0 A <- b
+// (cold), 1 B <- A, 2 A <- B, 3 z <- A (last post sweep of the finest level).
+
+template <int D>
+__global__ __launch_bounds__(MT) void k_bmg_smooth(const BMGLev *__restrict__ tab, int lmax, int l,
+                                                   const int4 *__restrict__ tiles, int phase, double om,
+                                                   const Inst *__restrict__ insts) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  if (((const double *)I.scal)[S_DONE] != 0.0) return;
+  const BMGLev &Lv = tab[(size_t)t.x * lmax + l];
+  const MGView &L = Lv.v;
+  const int64_t i = (int64_t)t.y * MT + threadIdx.x;
+  if (i >= L.N) return;
+  const double *src = phase == 1 || phase == 3 ? Lv.A : Lv.B;
+  double *dst = phase == 0 || phase == 2 ? Lv.A : (phase == 1 ? Lv.B : (double *)I.z);
+  const float d = L.d[i];
+  if (d == 0.0f) {
+    for (int c = 0; c < D; ++c) dst[(size_t)c * L.stride + i] = 0.0;
+    return;
+  }
+  const double id = 1.0 / (double)d;
+  if (phase == 0) {
+    for (int c = 0; c < D; ++c) dst[(size_t)c * L.stride + i] = om * Lv.b[(size_t)c * L.stride + i] * id;
+    return;
+  }
+  int x, y, z;
+  xyz_of(L, i, x, y, z);
+  for (int c = 0; c < D; ++c) {
+    const size_t o = (size_t)c * L.stride + i;
+    dst[o] = src[o] + om * (Lv.b[o] - apply_K<D>(L, src, i, x, y, z, c)) * id;
+  }
+}
+
+// level l+1 right-hand side = restricted residual of level l (from B)
+template <int D>
+__global__ __launch_bounds__(MT) void k_bmg_restrict(const BMGLev *__restrict__ tab, int lmax, int l,
+                                                     const int4 *__restrict__ tiles, const Inst *__restrict__ insts) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  if (((const double *)I.scal)[S_DONE] != 0.0) return;
+  const BMGLev &Fl = tab[(size_t)t.x * lmax + l], &Cl = tab[(size_t)t.x * lmax + l + 1];
+  const MGView &F = Fl.v, &Cg = Cl.v;
+  const int64_t Ic = (int64_t)t.y * MT + threadIdx.x;
+  if (Ic >= Cg.N) return;
+  int cx, cy, cz;
+  xyz_of(Cg, Ic, cx, cy, cz);
+  double acc[D];
+  for (int c = 0; c < D; ++c) acc[c] = 0.0;
+  for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int fx = 2 * cx + dx, fy = 2 * cy + dy, fz = 2 * cz + dz;
+        if (fx >= F.nx || fy >= F.ny || fz >= F.nz) continue;
+        const int64_t f = fx + (int64_t)F.nx * (fy + (int64_t)F.ny * fz);
+        if (F.d[f] == 0.0f) continue;
+        for (int c = 0; c < D; ++c)
+          acc[c] += Fl.b[(size_t)c * F.stride + f] - apply_K<D>(F, Fl.B, f, fx, fy, fz, c);
+      }
+  for (int c = 0; c < D; ++c) Cl.b[(size_t)c * Cg.stride + Ic] = acc[c];
+}
+
+// B_l += B_{l+1}(parent)
+template <int D>
+__global__ __launch_bounds__(MT) void k_bmg_prolong(const BMGLev *__restrict__ tab, int lmax, int l,
+                                                    const int4 *__restrict__ tiles, const Inst *__restrict__ insts) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  if (((const double *)I.scal)[S_DONE] != 0.0) return;
+  const BMGLev &Fl = tab[(size_t)t.x * lmax + l], &Cl = tab[(size_t)t.x * lmax + l + 1];
+  const MGView &F = Fl.v, &Cg = Cl.v;
+  const int64_t i = (int64_t)t.y * MT + threadIdx.x;
+  if (i >= F.N || F.d[i] == 0.0f) return;
+  int fx, fy, fz;
+  xyz_of(F, i, fx, fy, fz);
+  const int64_t Ic = (fx >> 1) + (int64_t)Cg.nx * ((fy >> 1) + (int64_t)Cg.ny * (fz >> 1));
+  for (int c = 0; c < D; ++c) Fl.B[(size_t)c * F.stride + i] += Cl.B[(size_t)c * Cg.stride + Ic];
+}
+
+// coarsest level of every instance (one block each): Jacobi sweeps in LDS,
+// result to B (or z when the finest level is the coarsest)
+template <int D>
+__global__ __launch_bounds__(CT) void k_bmg_coarse(const BMGLev *__restrict__ tab, int lmax,
+                                                   const int *__restrict__ last, double om, int nsweep,
+                                                   const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  if (((const double *)I.scal)[S_DONE] != 0.0) return;
+  const int l = last[blockIdx.x];
+  const BMGLev &Lv = tab[(size_t)blockIdx.x * lmax + l];
+  const MGView &L = Lv.v;
+  __shared__ double xs[2][D][CT];
+  const int i = threadIdx.x;
+  const bool on = i < L.N;
+  const double d = on ? (double)L.d[i] : 0.0;
+  double bi[D];
+  for (int c = 0; c < D; ++c) {
+    bi[c] = (on && d != 0.0) ? Lv.b[(size_t)c * L.stride + i] : 0.0;
+    xs[0][c][i] = (d != 0.0) ? om * bi[c] / d : 0.0;
+  }
+  int x0 = 0, y0 = 0, z0 = 0;
+  if (on) {
+    x0 = i % L.nx;
+    y0 = (i / L.nx) % L.ny;
+    z0 = i / (L.nx * L.ny);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int s = 1; s < nsweep; ++s) {
+    if (on && d != 0.0) {
+      for (int c = 0; c < D; ++c) {
+        double kx = d * xs[cur][c][i];
+        const int n[3] = {L.nx, L.ny, L.nz};
+        const int cc[3] = {x0, y0, z0};
+        for (int A = 0; A < D; ++A) {
+          const int st = A == 0 ? 1 : (A == 1 ? L.nx : L.nx * L.ny);
+          const float wp = L.w[(size_t)A * L.N + i];
+          if (wp != 0.0f) kx -= (double)wp * xs[cur][c][(cc[A] + 1 < n[A]) ? i + st : i - (n[A] - 1) * st];
+          int j = -1;
+          if (cc[A] > 0) j = i - st;
+          else if ((L.per >> A) & 1) j = i + (n[A] - 1) * st;
+          if (j >= 0) {
+            const float wm = L.w[(size_t)A * L.N + j];
+            if (wm != 0.0f) kx -= (double)wm * xs[cur][c][j];
+          }
+        }
+        xs[cur ^ 1][c][i] = xs[cur][c][i] + om * (bi[c] - kx) / d;
+      }
+    } else {
+      for (int c = 0; c < D; ++c) xs[cur ^ 1][c][i] = 0.0;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  double *out = l == 0 ? (double *)I.z : Lv.B;
+  if (on)
+    for (int c = 0; c < D; ++c) out[(size_t)c * L.stride + i] = xs[cur][c][i];
+}
+
+template <int D> void batch_vcycle_t(const BatchMG &bm, const Inst *insts, int ninst, hipStream_t st) {
+  const int L = bm.lmax;
+  // descent: pre-smoothing and restriction on the levels above each
+  // instance's coarsest
+  for (int l = 0; l + 1 < L; ++l) {
+    if (!bm.nsm[l]) continue;
+    hipLaunchKernelGGL((k_bmg_smooth<D>), bm.nsm[l], MT, 0, st, bm.tab, L, l, bm.sm[l], 0, bm.omega, insts);
+    hipLaunchKernelGGL((k_bmg_smooth<D>), bm.nsm[l], MT, 0, st, bm.tab, L, l, bm.sm[l], 1, bm.omega, insts);
+    if (bm.nrs[l + 1])
+      hipLaunchKernelGGL((k_bmg_restrict<D>), bm.nrs[l + 1], MT, 0, st, bm.tab, L, l, bm.rs[l + 1], insts);
+  }
+  hipLaunchKernelGGL((k_bmg_coarse<D>), ninst, CT, 0, st, bm.tab, L, bm.last, bm.omega, bm.nu_coarse, insts);
+  // ascent: prolongation and post-smoothing
+  for (int l = L - 2; l >= 0; --l) {
+    if (!bm.nsm[l]) continue;
+    hipLaunchKernelGGL((k_bmg_prolong<D>), bm.nsm[l], MT, 0, st, bm.tab, L, l, bm.sm[l], insts);
+    hipLaunchKernelGGL((k_bmg_smooth<D>), bm.nsm[l], MT, 0, st, bm.tab, L, l, bm.sm[l], 2, bm.omega, insts);
+    hipLaunchKernelGGL((k_bmg_smooth<D>), bm.nsm[l], MT, 0, st, bm.tab, L, l, bm.sm[l], l == 0 ? 3 : 1, bm.omega,
+                       insts);
+  }
+}
 }  // namespace
 
 namespace {
@@ -612,6 +774,18 @@ void mg_apply(tlvlbm_ctx *c, const double *r, double *z, const double *scal) {
   if (c->D == 2) vcycle<2>(mg, 0, c->st, scal, z);
   else vcycle<3>(mg, 0, c->st, scal, z);
   L0.b = b_own;
+}
+
+void batch_vcycle(int D, const BatchMG &bm, const Inst *insts, int ninst, hipStream_t st) {
+  if (D == 2) batch_vcycle_t<2>(bm, insts, ninst, st);
+  else batch_vcycle_t<3>(bm, insts, ninst, st);
+}
+
+void batch_mg_free(BatchMG &bm) {
+  for (void *p : {(void *)bm.tab, (void *)bm.last}) (void)hipFree(p);
+  for (int4 *p : bm.sm) (void)hipFree(p);
+  for (int4 *p : bm.rs) (void)hipFree(p);
+  bm = BatchMG();
 }
 
 }  // namespace tl

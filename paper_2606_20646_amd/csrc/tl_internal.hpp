@@ -134,6 +134,7 @@ struct Inst {
   Links L;
   // projection workspace
   void *x, *r, *p0, *p1, *Ap, *b, *V, *Fm, *Fr, *anc_s;
+  void *z;  // preconditioned residual (batched multigrid)
   uint8_t *anc_n;
   int *anc_i;
   double *partial, *scal;
@@ -150,7 +151,30 @@ struct Seg {
 };
 
 enum class BatchOp { Cut, Anchor, ZeroAnchor, NarrowAnchor, XfromU, UfromX, Rhs, CgInit, CgAp, CgUpdate, GradF,
-                     UReset, StepEnd, Pending };
+                     UReset, StepEnd, Pending, PcInit, PcAp, PcUpdate, PcDot, PcDotFirst };
+
+// one multigrid level of one instance in a batched V-cycle: the view and the
+// level's vectors (b: right-hand side, A and B: the two sweep buffers; the
+// level's result is in B)
+struct BMGLev {
+  MGView v;
+  double *b, *A, *B;
+};
+
+// level-synchronous batched V-cycle over instances with different depths
+struct BatchMG {
+  int lmax = 0;                         // deepest hierarchy
+  BMGLev *tab = nullptr;                // device [ninst][lmax]
+  int *last = nullptr;                  // device [ninst] coarsest level index
+  double omega = 2.0 / 3.0;
+  int nu_coarse = 40;
+  std::vector<int4 *> sm;               // per level: (inst, block) tiles of the levels above an instance's coarsest
+  std::vector<int> nsm;
+  std::vector<int4 *> rs;               // per level l >= 1: tiles of level-l nodes that receive a restriction
+  std::vector<int> nrs;
+};
+void batch_vcycle(int D, const BatchMG &bm, const Inst *insts, int ninst, hipStream_t st);
+void batch_mg_free(BatchMG &bm);
 
 struct BatchArgs {
   hipStream_t st;

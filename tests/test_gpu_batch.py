@@ -28,7 +28,8 @@ def env():
 
 
 def _solver(T, cfg, precision, stream, cg_multigrid=False):
-    # the batched path runs the plain CG: compare against the same kernels
+    # per-instance and batched paths run the same CG (plain, or preconditioned
+    # by the multigrid V-cycle, batched level-synchronously)
     s = T.Solver(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
                  origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"], precision=precision,
                  stream=stream.cuda_stream, cg_multigrid=cg_multigrid)
@@ -60,12 +61,12 @@ CFGS = [W.config_c4_instance(k, N=n) for k, n in enumerate([40, 64, 48, 33])]
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
-@pytest.mark.parametrize("graph", [True, False])
-def test_batch_equals_per_instance(env, precision, tol, graph):
+@pytest.mark.parametrize("graph,mg", [(True, False), (False, False), (True, True)])
+def test_batch_equals_per_instance(env, precision, tol, graph, mg):
     T, stream = env
-    _say(f"batch vs per-instance {precision} graph={graph}")
-    A = [_solver(T, c, precision, stream) for c in CFGS]
-    B = [_solver(T, c, precision, stream) for c in CFGS]
+    _say(f"batch vs per-instance {precision} graph={graph} multigrid={mg}")
+    A = [_solver(T, c, precision, stream, cg_multigrid=mg) for c in CFGS]
+    B = [_solver(T, c, precision, stream, cg_multigrid=mg) for c in CFGS]
     T.step_each(A, 65)
     bt = T.Batch(B, use_graph=graph)
     bt.step(30)

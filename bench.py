@@ -101,16 +101,22 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 1000; c2 20000, c4 40, c5 200)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--fd", action="store_true",
+                    help="c5: check dL/dmu against Richardson-extrapolated central differences of the forward")
+    ap.add_argument("--fd-h", type=float, default=1e-2, help="c5 --fd: relative step of mu")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.workload == "c3" and args.steps is None:
+        args.steps = 1000
     if args.workload != "c3":
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)
@@ -206,7 +212,7 @@ def bench_c2(args):
     from paper_2606_20646_amd import tlvlbm as T
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from refsol import radial_bvp
-    steps = args.steps if args.steps != 1000 else 20000
+    steps = args.steps or 20000
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     c = W.config_c2(512)
@@ -247,7 +253,7 @@ def bench_c4(args):
 
     import workloads as W
     from paper_2606_20646_amd import tlvlbm as T
-    steps = args.steps if args.steps != 1000 else 40
+    steps = args.steps or 40
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     cfgs = [W.config_c4_instance(k) for k in range(64)]
@@ -309,21 +315,29 @@ def bench_c5(args):
 
     import workloads as W
     from paper_2606_20646_amd import tlvlbm as T
-    steps = args.steps if args.steps != 1000 else 200
+    steps = args.steps or 200
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     c = W.config_c5(192)
 
-    def mk():
-        s = T.Solver(3, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], origin=c["origin"],
-                     periodic_mask=0, proj_every=c["proj_every"], precision=args.precision, stream=stream.cuda_stream)
+    def mk(mu=c["mu"], precision=args.precision):
+        s = T.Solver(3, c["n"], c["dx"], c["dt"], mu, c["lam"], omega=c["omega"], origin=c["origin"],
+                     periodic_mask=0, proj_every=c["proj_every"], precision=precision, stream=stream.cuda_stream)
         s.set_levelset(c["phi"], c["bid"])
         s.set_boundary(1, "neumann")
         s.set_state(c["U0"], dU0=c["dU0"])
         return s
 
     act = c["phi"] <= 0
-    wu = np.random.default_rng(1).standard_normal((3, act.size)) * act
+    if args.fd:
+        # a smooth functional: L = sum u_ref . u with u_ref the forward's own
+        # final displacement (no cancellation, so differences resolve it)
+        s = mk()
+        s.step(steps)
+        wu = s.moments()[1] * act
+        del s
+    else:
+        wu = np.random.default_rng(1).standard_normal((3, act.size)) * act
     s = mk()
     s.adjoint(steps, None, wu)  # one-time reverse-mode tables and device memory of this shape
     s.set_state(c["U0"], dU0=c["dU0"])
@@ -338,11 +352,24 @@ def bench_c5(args):
     gm, gv, g0 = s.adjoint(steps, None, wu)
     torch.cuda.synchronize()
     ta = time.perf_counter() - t
+    extra = {"forward_s": round(tf, 4), "adjoint_s": round(ta, 4), "dL_dmu_dlambda": [float(gm[0]), float(gm[1])]}
+    if args.fd:
+        # reference: Richardson-extrapolated central differences of FP64
+        # forward runs (FP32 runs would bury the difference in rounding)
+        def L(mu):
+            s = mk(mu, "fp64")
+            s.step(steps)
+            return float(np.sum(wu * s.moments()[1]))
+        h = args.fd_h * c["mu"]
+        d1 = (L(c["mu"] + h) - L(c["mu"] - h)) / (2 * h)
+        d2 = (L(c["mu"] + h / 2) - L(c["mu"] - h / 2)) / h
+        fd = (4 * d2 - d1) / 3
+        extra["fd_dL_dmu"] = fd
+        extra["fd_rel_err"] = abs(fd - float(gm[0])) / abs(fd)
     _common("reverse-mode time / forward time", round(ta / tf, 3), "ratio", steps, 0, round(ta * 1e3 / steps, 4),
             False, "f32" if args.precision == "fp32" else "f64",
             f"D3Q6x12 sphere 192^3+frame, {int(act.sum())} active nodes, traction free, projection every 20 steps, "
-            f"{args.precision}",
-            {"forward_s": round(tf, 4), "adjoint_s": round(ta, 4), "dL_dmu_dlambda": [float(gm[0]), float(gm[1])]})
+            f"{args.precision}", extra)
 
 
 if __name__ == "__main__":

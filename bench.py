@@ -23,6 +23,12 @@ Other workloads (one JSON line each; not the headline):
                     per-instance launches of the same kernels
     --workload c5   embedded sphere 192^3 (+frame), Neumann surface: reverse
                     mode (forward + recomputation + reverse) over forward time
+    --workload ellipsoid / shell / annulus
+                    the analytic benchmarks end to end (rotated ellipsoid
+                    with affine Dirichlet data, N = 320; spherical shell under
+                    cavity traction, N = 200; 2D annulus under radial
+                    traction, N = 196): MLUPS and the relative errors against
+                    the exact solutions
 """
 from __future__ import annotations
 
@@ -104,9 +110,10 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: 1000; c2 20000, c4 40, c5 200)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n", type=int, default=None,
+                    help="grid cells per axis (c3 256, ellipsoid 320, shell 200)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ellipsoid", "shell", "annulus"], default="c3")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--fd", action="store_true",
                     help="c5: check dL/dmu against Richardson-extrapolated central differences of the forward")
@@ -121,7 +128,8 @@ def main():
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)
             sys.exit(2)
-        {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload](args)
+        {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "ellipsoid": bench_analytic,
+         "shell": bench_analytic, "annulus": bench_analytic}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -135,7 +143,7 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    N = args.n
+    N = args.n or 256
     t0 = time.time()
     c = W.config_c3(N)
     log(f"inputs generated in {time.time() - t0:.1f} s")
@@ -370,6 +378,73 @@ def bench_c5(args):
             False, "f32" if args.precision == "fp32" else "f64",
             f"D3Q6x12 sphere 192^3+frame, {int(act.sum())} active nodes, traction free, projection every 20 steps, "
             f"{args.precision}", extra)
+
+
+def _embedded_solver(T, c, precision, stream, dU0=True):
+    s = T.Solver(c["D"], c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
+                 origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"], precision=precision,
+                 stream=stream.cuda_stream)
+    s.set_levelset(c["phi"], c["bid"])
+    for bid, bc in c["bcs"].items():
+        bc = dict(bc)
+        s.set_boundary(bid, bc.pop("type"), **bc)
+    s.set_state(c["U0"], dU0=c.get("dU0") if dU0 else None)
+    return s
+
+
+def bench_analytic(args):
+    """The 3D analytic benchmarks end to end: the rotated ellipsoid with affine
+    velocity Dirichlet data (default N = 320, 1472 steps to t = 0.46) or the
+    spherical shell with ramped cavity traction (default N = 200, 10000 steps
+    to t = 5); MLUPS over active nodes and the relative L2 errors against the
+    exact affine field or the radial boundary-value problem."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2606_20646_amd import tlvlbm as T
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import refsol
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    N = args.n or {"ellipsoid": 320, "shell": 200, "annulus": 196}[args.workload]
+    print(f"[bench] {args.workload} N={N} {args.precision}: building inputs", file=sys.stderr, flush=True)
+    if args.workload == "ellipsoid":
+        c = W.config_ellipsoid(N)
+        desc = f"D3Q6x12 rotated ellipsoid {N}^3+frame, affine velocity Dirichlet surface, omega=1.8"
+    elif args.workload == "annulus":
+        c = W.config_radial_annulus(N)
+        desc = (f"D2Q4x6 radial traction annulus {N}^2+frame, clamped inner surface, ramped radial traction, "
+                f"gamma=10, projection every 20 steps")
+    else:
+        c = W.config_shell(N)
+        desc = (f"D3Q6x12 spherical shell {N}^3+frame, ramped cavity traction, traction-free outer surface, "
+                f"gamma=10, projection every 20 steps")
+    steps = args.steps or c["steps"]
+    s = _embedded_solver(T, c, args.precision, stream)
+    print(f"[bench] {args.workload} N={N}: {steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = s.stats()
+    U, u, J = s.moments()
+    t = steps * c["dt"]
+    if args.workload == "ellipsoid":
+        err = refsol.ellipsoid_errors(c, U, u, J, t)
+    elif args.workload == "annulus":
+        ref = refsol.radial_bvp(2, c["mu"], c["lam"], 0.18, 0.42, r_inner=0.18, Pr_outer=1.0)
+        err = refsol.radial_errors(c, ref, U, u, J)
+    else:
+        ref = refsol.radial_bvp(3, c["mu"], c["lam"], 0.20, 0.38, r_inner=0.28)
+        err = refsol.radial_errors(c, ref, U, u, J)
+    nact = int((c["phi"] <= 0).sum())
+    extra = dict(err, time=t, active_nodes=nact, cut_links=st["cut_links"], projections=st["projections"],
+                 cg_iterations=st["cg_iterations"], newton_failures=st["newton_failures"])
+    _common(f"{args.workload} MLUPS (active nodes, end to end)", round(nact * steps / wall / 1e6, 1), "MLUPS",
+            steps, 0, round(wall * 1e3 / steps, 4), True, "f32" if args.precision == "fp32" else "f64",
+            f"{desc}, {args.precision}", extra)
 
 
 if __name__ == "__main__":

@@ -83,7 +83,8 @@ typedef struct {
 } tlvlbm_material;
 
 /* Run options (tlvlbm_default_options fills the paper's settings of
- * Sec. 4.1: omega = 1.8, gamma = 0, theta_F = 1, projection every 20 steps). */
+ * Sec. 4.1: omega = 1.8, gamma = 0, theta_F = 1, projection every 20 steps,
+ * projection relaxed by 20 damped Jacobi sweeps of weight 2/3). */
 typedef struct {
   double omega;       /* BGK relaxation, 0 < omega <= 2 (Sec. 2.4, Eq. 29) */
   double gamma;       /* velocity damping source B = (-gamma v, 0) (Sec. 4.1) */
@@ -96,8 +97,13 @@ typedef struct {
   int32_t track_u;    /* 1: carry the displacement quadrature (Eq. 34); 0: not; -1: auto
                          (on whenever a level set is set) */
   void *stream;       /* hipStream_t for all work; NULL = default stream */
-  int32_t cg_multigrid; /* 1: projection CG preconditioned by one geometric multigrid V-cycle
-                           per iteration (aggregation of 2^D blocks, damped Jacobi); 0: plain CG */
+  int32_t cg_multigrid; /* exact mode: 1: CG preconditioned by one geometric multigrid V-cycle per
+                           iteration (aggregation of 2^D blocks, damped Jacobi); 0: plain CG */
+  int32_t proj_sweeps;  /* projection solver (Sec. 3.5).  > 0: that many damped Jacobi sweeps
+                           x <- x + proj_weight (b - K x) / diag(K) on the normal equations,
+                           started from the current displacement (the paper's relaxation; default
+                           20); 0: exact minimiser (CG to cg_rtol) */
+  double proj_weight;   /* Jacobi damping weight, 0 < proj_weight <= 1 (default 2/3) */
 } tlvlbm_options;
 
 /* Boundary condition attached to a boundary identifier (Sec. 3.1).

@@ -55,6 +55,7 @@ def lib():
                                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int]
         L.orc_create.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_projection.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_set_levelset.argtypes = [C.c_void_p, dp, C.POINTER(C.c_uint8)]
         L.orc_set_bc.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp, dp,
                                  C.c_double, C.c_double, dp]
@@ -173,7 +174,7 @@ class Sim:
     """One oracle instance; arrays are planar numpy [component][node]."""
 
     def __init__(self, D, n, dx, dt, mu, lam, rho0=1.0, omega=1.8, gamma=0.0, theta_F=1.0,
-                 proj_every=20, origin=None, periodic_mask=None):
+                 proj_every=20, origin=None, periodic_mask=None, proj_sweeps=20, proj_weight=2.0 / 3.0):
         self.D, self.M, self.Q = D, D + D * D, 2 * D
         self.n = tuple(int(v) for v in n)
         self.N = int(np.prod(self.n))
@@ -186,6 +187,9 @@ class Sim:
         if not self.h:
             raise OracleError(1, "create")
         self._org = org
+        st = lib().orc_set_projection(self.h, int(proj_sweeps), float(proj_weight))
+        if st:
+            raise OracleError(st, "set_projection")
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -425,6 +425,8 @@ struct orc_sim {
   double dx, org[3];
   double mu, lam, rho0, dt, c, omega, gamma, theta;
   int proj_every;
+  int proj_sweeps;    /* > 0: damped Jacobi sweeps per projection solve; 0: exact minimiser */
+  double proj_weight; /* Jacobi damping weight */
   int64_t step;
   int status, have_state, has_ls;
   uint8_t *act;
@@ -498,6 +500,8 @@ orc_sim *orc_create(int D, const int *n, double dx, const double *origin, int pe
   s->gamma = gamma;
   s->theta = theta_F;
   s->proj_every = proj_every;
+  s->proj_sweeps = ORC_PROJ_SWEEPS;
+  s->proj_weight = ORC_PROJ_WEIGHT;
   s->act = (uint8_t *)malloc((size_t)s->N);
   if (!s->act) {
     orc_destroy(s);
@@ -703,6 +707,13 @@ int orc_set_levelset(orc_sim *s, const double *phi, const uint8_t *bid) {
   }
   s->has_ls = 1;
   s->have_state = 0;
+  return ORC_OK;
+}
+
+int orc_set_projection(orc_sim *s, int sweeps, double weight) {
+  if (sweeps < 0 || !(weight > 0.0 && weight <= 1.0)) return ORC_ERR_ARG;
+  s->proj_sweeps = sweeps;
+  s->proj_weight = weight;
   return ORC_OK;
 }
 
@@ -969,8 +980,11 @@ static double dot_act(const orc_sim *s, const double *a, const double *b) {
  * without anchors CG from x0 stays in x0 + range(L), which fixes the constant
  * to the mean of the warm start (the gauge).  anc_n[m] counts anchors of node
  * m and anc_s[m*D + i] sums their targets; both may be NULL. */
+static int64_t proj_jacobi(orc_sim *s, const double *Unm, double *u, const int *anc_n, const double *anc_s);
+
 static int64_t proj_solve(orc_sim *s, const double *Unm, double *u /* [N][D] */, double rtol,
                           const int *anc_n, const double *anc_s) {
+  if (s->proj_sweeps > 0) return proj_jacobi(s, Unm, u, anc_n, anc_s);
   int64_t N = s->N, its = 0;
   double *b = (double *)malloc(sizeof(double) * N), *x = (double *)malloc(sizeof(double) * N);
   double *r = (double *)malloc(sizeof(double) * N), *p = (double *)malloc(sizeof(double) * N);
@@ -1016,6 +1030,49 @@ static int64_t proj_solve(orc_sim *s, const double *Unm, double *u /* [N][D] */,
   }
   free(b); free(x); free(r); free(p); free(Ap);
   return its;
+}
+
+/* diagonal of the normal matrix K = graph Laplacian + anchor counts */
+static double proj_diag(const orc_sim *s, const int *anc_n, int64_t m) {
+  double d = anc_n ? anc_n[m] : 0;
+  for (int q = 0; q < s->Q; ++q) {
+    int64_t l = nbr_q(s, m, q, 1);
+    if (l >= 0 && s->act[l]) d += 1.0;
+  }
+  return d;
+}
+
+/* Damped Jacobi relaxation of the same normal equations (Sec. 3.5: the
+ * paper relaxes them by damped Jacobi iterations on the active-node graph,
+ * started from the current displacement): per component, proj_sweeps sweeps
+ *   x <- x + w (b - K x) / diag(K)
+ * with w = proj_weight.  A node with a zero diagonal (no active neighbour and
+ * no anchor) has no edge relation and keeps its value. */
+static int64_t proj_jacobi(orc_sim *s, const double *Unm, double *u, const int *anc_n, const double *anc_s) {
+  int64_t N = s->N;
+  double *b = (double *)malloc(sizeof(double) * N), *x = (double *)malloc(sizeof(double) * N);
+  double *Kx = (double *)malloc(sizeof(double) * N);
+  for (int comp = 0; comp < s->D; ++comp) {
+    proj_rhs(s, Unm, comp, b);
+    if (anc_n)
+      for (int64_t m = 0; m < N; ++m) b[m] += anc_s[m * s->D + comp];
+    for (int64_t m = 0; m < N; ++m) x[m] = s->act[m] ? u[m * s->D + comp] : 0.0;
+    for (int k = 0; k < s->proj_sweeps; ++k) {
+      graph_lap(s, x, Kx);
+#pragma omp parallel for
+      for (int64_t m = 0; m < N; ++m) {
+        if (!s->act[m]) continue;
+        double d = proj_diag(s, anc_n, m);
+        if (d == 0.0) continue;
+        double kx = Kx[m] + (anc_n ? anc_n[m] * x[m] : 0.0);
+        u[m * s->D + comp] = x[m] + s->proj_weight * (b[m] - kx) / d;
+      }
+      for (int64_t m = 0; m < N; ++m)
+        if (s->act[m]) x[m] = u[m * s->D + comp];
+    }
+  }
+  free(b); free(x); free(Kx);
+  return (int64_t)s->proj_sweeps * s->D;
 }
 
 /* anchor counts and target sums from the Dirichlet cut links at time t */
@@ -1584,6 +1641,35 @@ static void solve_adj(const orc_sim *s, const int *anc_n, const int64_t *comp, c
   free(rhs); free(yc); free(sum); free(cnt);
 }
 
+/* adjoint of proj_jacobi per component of u ([N][D]): the sweep
+ * x' = x + w Dg^-1 (b - K x) has the transpose  xbar = (I - w K Dg^-1) x'bar,
+ * bbar += w Dg^-1 x'bar (K symmetric); y receives bbar, x0bar the adjoint of
+ * the starting displacement */
+static void jacobi_adj(const orc_sim *s, const int *anc_n, const double *ubar, double *y, double *x0bar) {
+  int D = s->D;
+  int64_t N = s->N;
+  double *z = (double *)malloc(sizeof(double) * N), *w = (double *)malloc(sizeof(double) * N);
+  double *Kw = (double *)malloc(sizeof(double) * N);
+  for (int i = 0; i < D; ++i) {
+    for (int64_t m = 0; m < N; ++m) {
+      z[m] = s->act[m] ? ubar[m * D + i] : 0.0;
+      y[m * D + i] = 0.0;
+    }
+    for (int k = 0; k < s->proj_sweeps; ++k) {
+      for (int64_t m = 0; m < N; ++m) {
+        double d = s->act[m] ? proj_diag(s, anc_n, m) : 0.0;
+        w[m] = d > 0.0 ? z[m] / d : 0.0;
+        y[m * D + i] += s->proj_weight * w[m];
+      }
+      apply_K(s, anc_n, w, Kw);
+      for (int64_t m = 0; m < N; ++m)
+        if (s->act[m]) z[m] -= s->proj_weight * Kw[m];
+    }
+    for (int64_t m = 0; m < N; ++m) x0bar[m * D + i] = s->act[m] ? z[m] : 0.0;
+  }
+  free(z); free(w); free(Kw);
+}
+
 /* transpose of proj_rhs: Fbar[m*D*D + i*D + A] += d b / d F_m,iA applied to y */
 static void proj_rhs_T(const orc_sim *s, const double *y, double *Fbar) {
   int D = s->D;
@@ -1856,7 +1942,8 @@ int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dL
     } else {
       /* second solve: u^cc = solve(F^r, warm start u^c); u* = u^cc + dt/2 v */
       for (size_t k2 = 0; k2 < nd; ++k2) ub[k2] = ubc[k2] + lus[k2];
-      solve_adj(s, an, comp, anch, nc, ub, y, x0b);
+      if (s->proj_sweeps > 0) jacobi_adj(s, an, ub, y, x0b);
+      else solve_adj(s, an, comp, anch, nc, ub, y, x0b);
       memset(Frb, 0, sizeof(double) * (size_t)N * D * D);
       proj_rhs_T(s, y, Frb);
       if (an) anchors_T(s, y, Frb);
@@ -1905,7 +1992,8 @@ int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dL
       memset(Frb, 0, sizeof(double) * (size_t)N * D * D);
       compat_F_T(s, Fcb, ubc, Frb);
       /* first solve: u^c = solve(F, warm start u) */
-      solve_adj(s, an, comp, anch, nc, ubc, y, x0b);
+      if (s->proj_sweeps > 0) jacobi_adj(s, an, ubc, y, x0b);
+      else solve_adj(s, an, comp, anch, nc, ubc, y, x0b);
       proj_rhs_T(s, y, Frb);
       if (an) anchors_T(s, y, Frb);
       for (int64_t m = 0; m < N; ++m) {

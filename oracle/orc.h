@@ -71,6 +71,13 @@ orc_sim *orc_create(int D, const int *n, double dx, const double *origin,
                     double dt, double omega, double gamma, double theta_F,
                     int proj_every);
 void orc_destroy(orc_sim *s);
+/* Compatibility projection solver (Sec. 3.5).  sweeps > 0: that many damped
+ * Jacobi sweeps of weight `weight` on the normal equations, started from the
+ * current displacement (the default, ORC_PROJ_SWEEPS sweeps of weight
+ * ORC_PROJ_WEIGHT); sweeps = 0: the exact minimiser (CG to stagnation). */
+#define ORC_PROJ_SWEEPS 20
+#define ORC_PROJ_WEIGHT (2.0 / 3.0)
+int  orc_set_projection(orc_sim *s, int sweeps, double weight);
 /* phi[N] node samples (phi <= 0 inside, Eq. 36); bid[N] boundary ids. */
 int  orc_set_levelset(orc_sim *s, const double *phi, const uint8_t *bid);
 /* boundary value s(t) (a + G (X - X0) + p_radial e_R + p_normal N_b) */

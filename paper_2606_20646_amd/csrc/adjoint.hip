@@ -19,9 +19,11 @@
 // Transposes of the point maps use the major symmetry of the hyperelastic
 // tangent (C_iAkB = C_kBiA): the adjoint of dF -> dP(F)[dF] is the same
 // map, so the forward tangent routine serves both directions.  The
-// projection's warm-started CG is differentiated as its exact solution map
-// u = u0 + K^+ (b - K u0): b_bar = K^+ u_bar, u0_bar = (I - K K^+) u_bar,
-// the mean of u_bar over each connected component without anchors.
+// projection is differentiated through its solver: the damped Jacobi
+// sweeps are transposed sweep by sweep; the exact mode's warm-started CG is
+// differentiated as its exact solution map u = u0 + K^+ (b - K u0):
+// b_bar = K^+ u_bar, u0_bar = (I - K K^+) u_bar, the mean of u_bar over each
+// connected component without anchors.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -489,6 +491,72 @@ __global__ __launch_bounds__(AT) void k_pi_apply(Geo g, const uint8_t *__restric
   }
 }
 
+// transpose of the projection's damped Jacobi sweeps (Sec. 3.5).  A sweep
+// x' = x + om Dg^-1 (b - K x) (Dg = diag K, K symmetric) has the transpose
+// x_bar = x'_bar - om K (Dg^-1 x'_bar), b_bar += om Dg^-1 x'_bar.
+// Pass 1: w = Dg^-1 z (0 where Dg = 0 or inactive), y (+)= om w.
+template <int D>
+__global__ __launch_bounds__(AT) void k_jacT_scale(Geo g, const uint8_t *__restrict__ act,
+                                                   const uint8_t *__restrict__ anc_n, const double *__restrict__ z,
+                                                   double *__restrict__ w, double *__restrict__ y, double om,
+                                                   int first) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  int deg = 0;
+  if (act[i]) {
+    const C3 cc = coords_of(g, i);
+    deg = anc_n ? anc_n[i] : 0;
+    for (int q = 0; q < 2 * D; ++q) {
+      const int64_t j = node_dir(g, cc, q, 1);
+      if (j >= 0 && act[j]) ++deg;
+    }
+  }
+  for (int c = 0; c < D; ++c) {
+    const size_t o = (size_t)c * g.S + i;
+    const double wi = deg ? z[o] / double(deg) : 0.0;
+    w[o] = wi;
+    y[o] = (first ? 0.0 : y[o]) + om * wi;
+  }
+}
+
+// pass 2: z -= om K w on active nodes
+template <int D>
+__global__ __launch_bounds__(AT) void k_jacT_apply(Geo g, const uint8_t *__restrict__ act,
+                                                   const uint8_t *__restrict__ anc_n, const double *__restrict__ w,
+                                                   double *__restrict__ z, double om) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N || !act[i]) return;
+  const C3 cc = coords_of(g, i);
+  int64_t nb[2 * D];
+  int deg = anc_n ? anc_n[i] : 0;
+  for (int q = 0; q < 2 * D; ++q) {
+    nb[q] = node_dir(g, cc, q, 1);
+    if (nb[q] >= 0 && !act[nb[q]]) nb[q] = -1;
+    if (nb[q] >= 0) ++deg;
+  }
+  for (int c = 0; c < D; ++c) {
+    const size_t o = (size_t)c * g.S;
+    double kw = double(deg) * w[o + i];
+    for (int q = 0; q < 2 * D; ++q)
+      if (nb[q] >= 0) kw -= w[o + nb[q]];
+    z[o + i] -= om * kw;
+  }
+}
+
+// z = ua + ub on active nodes, 0 elsewhere
+template <int D>
+__global__ __launch_bounds__(AT) void k_jacT_seed(Geo g, const uint8_t *__restrict__ act,
+                                                  const double *__restrict__ ua, const double *__restrict__ ub,
+                                                  double *__restrict__ z) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  const bool a = act[i];
+  for (int c = 0; c < D; ++c) {
+    const size_t o = (size_t)c * g.S + i;
+    z[o] = a ? ua[o] + (ub ? ub[o] : 0.0) : 0.0;
+  }
+}
+
 // transpose of the edge least-squares right-hand side (Eq. 57):
 // F_bar_iA(m) (+)= dx/2 ([m-e_A act] (y_m - y_{m-e_A}) + [m+e_A act] (y_{m+e_A} - y_m))
 template <int D, bool ADD>
@@ -728,13 +796,27 @@ template <int D, typename T> void launch_link_pass(Run &R, int pass, double th, 
   }
 }
 
-// x0b = null-space part of (ua + ub); CG workspace b = the rest, x = 0;
-// then x = K^+ b
+// exact mode: x0b = null-space part of (ua + ub); CG workspace b = the
+// rest, x = 0; then x = K^+ b.  Jacobi mode: the transposed sweeps.
 template <int D> int solve_adj(Run &R, const double *ua, const double *ub) {
   tlvlbm_ctx *c = R.c;
   CG &w = c->cg;
   const Geo &g = c->geo;
   const Gauge &G = *c->gauge;
+  if (c->proj_sweeps > 0) {
+    // Jacobi mode: the sweeps transposed in reverse order; y (the right-hand
+    // side's adjoint) in w.x, the start's adjoint in x0b
+    const uint8_t *an = R.dir ? G.anc_n : nullptr;
+    const unsigned nb = nblocks(g.N, AT);
+    hipLaunchKernelGGL((k_jacT_seed<D>), nb, AT, 0, c->st, g, c->act, ua, ub, R.x0b);
+    for (int k = 0; k < c->proj_sweeps; ++k) {
+      hipLaunchKernelGGL((k_jacT_scale<D>), nb, AT, 0, c->st, g, c->act, an, (const double *)R.x0b,
+                         (double *)w.p0, (double *)w.x, c->proj_weight, k == 0 ? 1 : 0);
+      hipLaunchKernelGGL((k_jacT_apply<D>), nb, AT, 0, c->st, g, c->act, an, (const double *)w.p0, R.x0b,
+                         c->proj_weight);
+    }
+    return hipGetLastError() == hipSuccess ? TLVLBM_OK : TLVLBM_ERR_DEVICE;
+  }
   gauge_means(c, ua, ub, G.mean);
   hipLaunchKernelGGL((k_pi_apply<D>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, G.comp, G.mean, ua, ub, R.x0b,
                      (double *)w.b, (double *)w.x);

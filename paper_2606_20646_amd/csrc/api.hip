@@ -119,6 +119,8 @@ void tlvlbm_default_options(tlvlbm_options *o) {
   o->proj_every = 20;
   o->cg_maxit = 0;
   o->cg_multigrid = 1;
+  o->proj_sweeps = 20;
+  o->proj_weight = 2.0 / 3.0;
   o->precision = TLVLBM_FP32;
   o->track_u = -1;
   o->stream = nullptr;
@@ -135,6 +137,7 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   if (opt) o = *opt;
   if (!(o.omega > 0 && o.omega <= 2) || !(o.theta_F > 0 && o.theta_F <= 1)) return TLVLBM_ERR_INVALID_ARG;
   if (o.precision != TLVLBM_FP32 && o.precision != TLVLBM_FP64) return TLVLBM_ERR_INVALID_ARG;
+  if (o.proj_sweeps < 0 || !(o.proj_weight > 0 && o.proj_weight <= 1)) return TLVLBM_ERR_INVALID_ARG;
   const int D = (int)lattice;
   int64_t N = 1;
   for (int a = 0; a < 3; ++a) {
@@ -176,6 +179,8 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   c->proj_every = o.proj_every;
   c->cg_maxit = o.cg_maxit;
   c->cg_multigrid = o.cg_multigrid ? 1 : 0;
+  c->proj_sweeps = o.proj_sweeps;
+  c->proj_weight = o.proj_weight;
   c->track_opt = o.track_u;
   c->track_u = o.track_u == 1;
   c->st = (hipStream_t)o.stream;

@@ -1,6 +1,7 @@
 // Batched launch of many independent TL-VLBM instances (project extension):
 // every phase of Algorithm 1 runs as one tile-list kernel over all instances,
-// the projection CG keeps per-instance scalars with segmented reductions, and
+// the projection's Jacobi sweeps run over all instances at once (the exact
+// mode's CG keeps per-instance scalars with segmented reductions), and
 // stretches of steps without projection are replayed from a hipGraph.
 #include <algorithm>
 #include <cstring>
@@ -15,6 +16,8 @@ using namespace tl;
 struct tlvlbm_batch {
   std::vector<tlvlbm_ctx *> c;
   int D = 0, prec = 0, proj_every = 0;
+  int sweeps = 0;       // projection: damped Jacobi sweeps (0: CG)
+  double jw = 0.0;      // Jacobi weight
   hipStream_t st = nullptr;
   std::vector<Inst> h_inst;
   Inst *d_inst = nullptr;
@@ -63,6 +66,7 @@ BatchArgs args_of(tlvlbm_batch *b) {
   a.nct = b->nct;
   a.step = b->d_step;
   a.pending = b->d_pending;
+  a.om = b->jw;
   return a;
 }
 
@@ -83,6 +87,13 @@ tlvlbm_status cg_batch(tlvlbm_batch *b, int useFr) {
     run(b, BatchOp::NarrowAnchor);
   }
   run(b, BatchOp::Rhs, useFr, anch);
+  if (b->sweeps > 0) {
+    // damped Jacobi relaxation: sweeps alternate x -> r and r -> x
+    for (int k = 0; k < b->sweeps; ++k) run(b, BatchOp::Jacobi, k & 1, anch);
+    if (b->sweeps & 1) run(b, BatchOp::JacobiCopy);
+    for (tlvlbm_ctx *c : b->c) c->st_cg += (int64_t)b->sweeps * c->D;
+    return TLVLBM_OK;
+  }
   if (b->use_mg) return pcg_batch(b, anch);
   run(b, BatchOp::CgInit, 0, anch);
   int pp = 0;
@@ -191,6 +202,8 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
     b->prec = c0->prec;
     b->st = c0->st;
     b->proj_every = c0->proj_every;
+    b->sweeps = c0->proj_sweeps;
+    b->jw = c0->proj_weight;
     b->step = c0->step;
     b->use_graph = b->st != nullptr;  // no stream capture on the legacy default stream
     std::vector<Seg> segs;
@@ -198,7 +211,8 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
     for (int k = 0; k < n; ++k) {
       tlvlbm_ctx *c = ctxs[k];
       if (!c || c->D != b->D || c->prec != b->prec || c->st != b->st || c->proj_every != b->proj_every ||
-          c->step != b->step || !c->have_state || !c->has_ls || !c->track_u || c->status) {
+          c->proj_sweeps != b->sweeps || c->proj_weight != b->jw || c->step != b->step || !c->have_state ||
+          !c->has_ls || !c->track_u || c->status) {
         delete b;
         return TLVLBM_ERR_INVALID_ARG;
       }

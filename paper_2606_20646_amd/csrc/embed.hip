@@ -783,6 +783,41 @@ template <int D> __device__ __forceinline__ void cg_update_fin(const double *tot
   }
 }
 
+// one damped Jacobi sweep of the projection's normal equations (Sec. 3.5):
+// xout = xin + om (b - K xin) / diag(K), K = active-graph Laplacian plus the
+// anchor counts.  Inactive nodes and nodes with a zero diagonal (no active
+// neighbour, no anchor: no edge relation) copy xin.
+template <int D>
+__device__ __forceinline__ void jacobi_node(const Geo &g, const uint8_t *__restrict__ act,
+                                            const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
+                                            const double *__restrict__ xin, double *__restrict__ xout, double om,
+                                            int64_t i) {
+  if (i >= g.N) return;
+  int deg = 0;
+  int64_t nb[2 * D];
+  if (act[i]) {
+    const C3 cc = coords_of(g, i);
+    deg = anc_n ? anc_n[i] : 0;
+    for (int q = 0; q < 2 * D; ++q) {
+      nb[q] = node_dir(g, cc, q, 1);
+      if (nb[q] >= 0 && !act[nb[q]]) nb[q] = -1;
+      if (nb[q] >= 0) ++deg;
+    }
+  }
+  for (int c = 0; c < D; ++c) {
+    const size_t o = (size_t)c * g.S;
+    const double xi = xin[o + i];
+    if (deg == 0) {
+      xout[o + i] = xi;
+      continue;
+    }
+    double kx = double(deg) * xi;
+    for (int q = 0; q < 2 * D; ++q)
+      if (nb[q] >= 0) kx -= xin[o + nb[q]];
+    xout[o + i] = xi + om * (b[o + i] - kx) / double(deg);
+  }
+}
+
 // compatible gradient F^c = I + grad_dx u^c (Eq. 59) and F^r = (1-theta) F +
 // theta F^c (Eq. 60): centred differences, one-sided next to a cut, the
 // evolved column kept when neither neighbour is active
@@ -942,6 +977,24 @@ __global__ __launch_bounds__(256) void k_ureset(Geo g, const uint8_t *__restrict
                                                  const T *__restrict__ V, T *__restrict__ u, T *__restrict__ us,
                                                  double hdt) {
   ureset_node<D, T>(g, act, x, V, u, us, hdt, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
+template <int D>
+__global__ __launch_bounds__(CG_T) void k_jacobi(Geo g, const uint8_t *__restrict__ act,
+                                                 const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
+                                                 const double *__restrict__ xin, double *__restrict__ xout, double om,
+                                                 const int32_t *__restrict__ tiles) {
+  const int64_t blk = tiles ? (int64_t)tiles[blockIdx.x] : (int64_t)blockIdx.x;
+  jacobi_node<D>(g, act, anc_n, b, xin, xout, om, blk * CG_T + threadIdx.x);
+}
+
+template <int D>
+__global__ __launch_bounds__(CG_T) void k_copy_planes(Geo g, const double *__restrict__ src, double *__restrict__ dst,
+                                                      const int32_t *__restrict__ tiles) {
+  const int64_t blk = tiles ? (int64_t)tiles[blockIdx.x] : (int64_t)blockIdx.x;
+  const int64_t i = blk * CG_T + threadIdx.x;
+  if (i < g.N)
+    for (int c = 0; c < D; ++c) dst[(size_t)c * g.S + i] = src[(size_t)c * g.S + i];
 }
 
 // copies between the displacement buffer (population precision) and the
@@ -1197,6 +1250,30 @@ template <int D, typename T> static int pcg_run(tlvlbm_ctx *c, const uint8_t *an
   return TLVLBM_OK;
 }
 
+// the projection's damped Jacobi relaxation (Sec. 3.5) on the workspace:
+// right-hand side w.b, start and result w.x (w.r is the second sweep
+// buffer); proj_sweeps sweeps of weight proj_weight over the active tiles
+template <int D> static int jacobi_run(tlvlbm_ctx *c, const uint8_t *anc_n) {
+  CG &w = c->cg;
+  const Geo &g = c->geo;
+  hipStream_t st = c->st;
+  if (!c->gauge || c->aux_stale) {
+    const int s = proj_aux_build(c);
+    if (s) return s;
+  }
+  const unsigned nt = w.tiles ? (unsigned)w.ntiles : nblk(g.N, CG_T);
+  double *a = (double *)w.x, *bb = (double *)w.r;
+  for (int k = 0; k < c->proj_sweeps; ++k) {
+    hipLaunchKernelGGL((k_jacobi<D>), nt, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b, (const double *)a, bb,
+                       c->proj_weight, w.tiles);
+    std::swap(a, bb);
+  }
+  if (a != (double *)w.x)
+    hipLaunchKernelGGL((k_copy_planes<D>), nt, CG_T, 0, st, g, (const double *)a, (double *)w.x, w.tiles);
+  c->st_cg += (int64_t)c->proj_sweeps * D;
+  return hipGetLastError() == hipSuccess ? TLVLBM_OK : TLVLBM_ERR_DEVICE;
+}
+
 template <int D, typename T> static int cg_solve(tlvlbm_ctx *c, const T *F, double t) {
   CG &w = c->cg;
   const Geo &g = c->geo;
@@ -1222,6 +1299,7 @@ template <int D, typename T> static int cg_solve(tlvlbm_ctx *c, const T *F, doub
     anc_s = (const double *)w.anc_s;
   }
   hipLaunchKernelGGL((k_cg_rhs<D, T>), nblk(g.N, 256), 256, 0, st, g, c->act, F, anc_s, (double *)w.b);
+  if (c->proj_sweeps > 0) return jacobi_run<D>(c, anc_n);
   return cg_run<D, T>(c, anc_n);
 }
 
@@ -1453,6 +1531,30 @@ __global__ __launch_bounds__(CG_T) void k_cg_update_batch(const Inst *__restrict
                       t.y, t.y);
 }
 
+// batched Jacobi sweep: dir 0 reads x and writes r, dir 1 the reverse;
+// copy: x = r
+template <int D>
+__global__ __launch_bounds__(CG_T) void k_jacobi_batch(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
+                                                       int dir, int anchored, double om) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const double *xin = (const double *)(dir ? I.r : I.x);
+  double *xout = (double *)(dir ? I.x : I.r);
+  jacobi_node<D>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.b, xin, xout, om,
+                 (int64_t)t.y * CG_T + threadIdx.x);
+}
+
+template <int D>
+__global__ __launch_bounds__(CG_T) void k_jacobi_copy_batch(const Inst *__restrict__ insts,
+                                                            const int4 *__restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const int64_t i = (int64_t)t.y * CG_T + threadIdx.x;
+  if (i < I.g.N)
+    for (int c = 0; c < D; ++c)
+      ((double *)I.x)[(size_t)c * I.g.S + i] = ((const double *)I.r)[(size_t)c * I.g.S + i];
+}
+
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_gradF_batch(const Inst *__restrict__ insts, const int4 *__restrict__ tiles) {
   const int4 t = tiles[blockIdx.x];
@@ -1541,6 +1643,12 @@ static void batch_kernels_t(BatchOp op, const BatchArgs &a) {
       break;
     case BatchOp::GradF:
       hipLaunchKernelGGL((k_gradF_batch<D, T>), a.nct, 256, 0, st, a.insts, a.ctiles);
+      break;
+    case BatchOp::Jacobi:
+      hipLaunchKernelGGL((k_jacobi_batch<D>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA, a.flagB, a.om);
+      break;
+    case BatchOp::JacobiCopy:
+      hipLaunchKernelGGL((k_jacobi_copy_batch<D>), a.nct, CG_T, 0, st, a.insts, a.ctiles);
       break;
     case BatchOp::UReset:
       hipLaunchKernelGGL((k_ureset_batch<D, T>), a.nct, 256, 0, st, a.insts, a.ctiles);

@@ -599,7 +599,7 @@ int proj_aux_build(tlvlbm_ctx *c) {
   }
   int s = gauge_build(c, act, anc, &c->gauge);
   if (s) return s;
-  if (c->cg_multigrid) {
+  if (c->cg_multigrid && c->proj_sweeps == 0) {  // the exact mode's preconditioner
     s = mg_build(c, act, anc, &c->mg);
     if (s) return s;
   }

@@ -151,7 +151,7 @@ struct Seg {
 };
 
 enum class BatchOp { Cut, Anchor, ZeroAnchor, NarrowAnchor, XfromU, UfromX, Rhs, CgInit, CgAp, CgUpdate, GradF,
-                     UReset, StepEnd, Pending, PcInit, PcAp, PcUpdate, PcDot, PcDotFirst };
+                     UReset, StepEnd, Pending, PcInit, PcAp, PcUpdate, PcDot, PcDotFirst, Jacobi, JacobiCopy };
 
 // one multigrid level of one instance in a batched V-cycle: the view and the
 // level's vectors (b: right-hand side, A and B: the two sweep buffers; the
@@ -188,6 +188,7 @@ struct BatchArgs {
   int64_t *step;       // device step counter
   int *pending;
   int flagA, flagB;
+  double om;           // Jacobi weight (projection sweeps)
 };
 
 // host or device arguments crossing the ABI
@@ -264,6 +265,8 @@ struct tlvlbm_ctx {
   double theta = 1.0, cg_rtol = 0.0;
   int proj_every = 20, cg_maxit = 0, track_opt = -1;
   int cg_multigrid = 1;        // 1: multigrid-preconditioned CG, 0: plain CG
+  int proj_sweeps = 20;        // > 0: damped Jacobi sweeps per projection solve; 0: exact solve
+  double proj_weight = 2.0 / 3.0;
   tl::MG *mg = nullptr;        // preconditioner hierarchy (built on first use)
   tl::Gauge *gauge = nullptr;  // components without anchors (built on first use)
   tl::StencilT *stT = nullptr; // transposed Neumann stencils (reverse mode, built on first use)

@@ -35,7 +35,8 @@ class Material(C.Structure):
 class Options(C.Structure):
     _fields_ = [("omega", C.c_double), ("gamma", C.c_double), ("theta_F", C.c_double), ("cg_rtol", C.c_double),
                 ("proj_every", C.c_int32), ("cg_maxit", C.c_int32), ("precision", C.c_int32),
-                ("track_u", C.c_int32), ("stream", C.c_void_p), ("cg_multigrid", C.c_int32)]
+                ("track_u", C.c_int32), ("stream", C.c_void_p), ("cg_multigrid", C.c_int32),
+                ("proj_sweeps", C.c_int32), ("proj_weight", C.c_double)]
 
 
 class BC(C.Structure):
@@ -126,7 +127,7 @@ class Solver:
 
     def __init__(self, D, n, dx, dt, mu, lam, rho0=1.0, origin=None, periodic_mask=None, omega=1.8, gamma=0.0,
                  theta_F=1.0, proj_every=20, precision="fp32", track_u=-1, cg_rtol=0.0, cg_maxit=0,
-                 stream=None, cg_multigrid=True):
+                 stream=None, cg_multigrid=True, proj_sweeps=20, proj_weight=2.0 / 3.0):
         self.D, self.M, self.Q = D, D + D * D, 2 * D
         self.n = tuple(int(v) for v in n)
         self.N = int(np.prod(self.n))
@@ -145,6 +146,7 @@ class Solver:
         o.precision = FP64 if precision in ("fp64", FP64) else FP32
         o.stream = stream
         o.cg_multigrid = int(bool(cg_multigrid))
+        o.proj_sweeps, o.proj_weight = int(proj_sweeps), float(proj_weight)
         h = C.c_void_p()
         st = lib.tlvlbm_create(C.byref(g), D, C.byref(m), rho0, dt, C.byref(o), C.byref(h))
         if st:

@@ -56,3 +56,65 @@ def radial_bvp(D, mu, lam, Ri, Ro, r_inner=None, Pr_inner=None, Pr_outer=0.0, n=
         return _principal(y[1], y[0] / Rq, mu, lam, D)[0]
 
     return dict(r=r, lr=lr, lt=lambda Rq: r(Rq) / Rq, Pr=Pr, sol=sol)
+
+
+def cauchy_nh(F, mu, lam):
+    """Cauchy stress sigma = J^-1 P F^T of the compressible neo-Hookean solid
+    (Sec. 4.1, Eq. 62; the recovery of Eq. 35), for F of shape [n, D, D]."""
+    J = np.linalg.det(F)
+    Fit = np.transpose(np.linalg.inv(F), (0, 2, 1))
+    P = mu * (F - Fit) + 0.5 * lam * (J * J - 1.0)[:, None, None] * Fit
+    return np.einsum("nij,nkj->nik", P, F) / J[:, None, None]
+
+
+def radial_fields(ref, X, Xc):
+    """Displacement [D][n] and deformation gradient [n][D][D] of the radial
+    map x = Xc + r(R) e_R (Sec. 5.2: lambda_r along e_R, r/R across it)."""
+    d = X - np.asarray(Xc, float)[:, None]
+    R = np.linalg.norm(d, axis=0)
+    e = d / R
+    lr, lt = ref["lr"](R), ref["lt"](R)
+    u = (ref["r"](R) - R) * e
+    D = X.shape[0]
+    ee = np.einsum("in,jn->nij", e, e)
+    F = lt[:, None, None] * np.eye(D)[None] + (lr - lt)[:, None, None] * ee
+    return u, F
+
+
+def rel_l2(a, b, scale=None):
+    """Relative discrete L2 error over the comparison nodes (Sec. 4.1,
+    Eq. 63); `scale` replaces b in the denominator (F - I uses F_ref - I)."""
+    s = b if scale is None else scale
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(s)))
+
+
+def ellipsoid_errors(c, U, u, J, t):
+    """Errors of an affine Dirichlet run (Sec. 5.1, Eqs. 80-82) at time t
+    over the active nodes: u against t A (X - Xc), v against A (X - Xc),
+    F against I + t A; the Jacobian range."""
+    act = c["phi"] <= 0
+    d = c["X"][:, act] - c["Xc"][:, None]
+    A = c["A"]
+    Fex = np.eye(3) + t * A
+    F = U[3:12, act].T.reshape(-1, 3, 3)
+    return {"E_u": rel_l2(u[:, act], t * (A @ d)), "E_v": rel_l2(U[:3, act], A @ d),
+            "E_F": rel_l2(F, np.broadcast_to(Fex, F.shape)),
+            "E_F_minus_I": rel_l2(F, np.broadcast_to(Fex, F.shape), np.broadcast_to(Fex - np.eye(3), F.shape)),
+            "J_range": [float(J[act].min()), float(J[act].max())], "J_exact": float(np.linalg.det(Fex))}
+
+
+def radial_errors(c, ref, U, u, J):
+    """Errors of a radial benchmark run (the 2D annulus of Sec. 4.3, Eqs.
+    72-75, or the spherical shell of Sec. 5.2, Eqs. 83-85) against the radial
+    BVP state over the active nodes: u, F, F - I, Cauchy stress, the RMS of
+    the residual velocity and the Jacobian range."""
+    D = c["D"]
+    act = c["phi"] <= 0
+    u_ref, F_ref = radial_fields(ref, c["X"][:, act], c["Xc"])
+    F = U[D:D + D * D, act].T.reshape(-1, D, D)
+    s, s_ref = cauchy_nh(F, c["mu"], c["lam"]), cauchy_nh(F_ref, c["mu"], c["lam"])
+    v = U[:D, act]
+    return {"E_u": rel_l2(u[:, act], u_ref), "E_F": rel_l2(F, F_ref),
+            "E_F_minus_I": rel_l2(F, F_ref, F_ref - np.eye(D)), "E_sigma": rel_l2(s, s_ref),
+            "v_rms": float(np.sqrt((v * v).sum(0).mean())),
+            "J_range": [float(J[act].min()), float(J[act].max())]}

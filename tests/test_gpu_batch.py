@@ -4,8 +4,8 @@ Instances follow the batched workload recipe (unit square with random holes,
 clamped left edge, traction on the right edge, traction-free holes and
 faces, per-instance material and lattice speed) at reduced sizes.  The
 batched path must reproduce the per-instance launches of the same kernels
-(FP64: 1e-12 relative; FP32: 1e-6) with and without graph replay, and one
-instance must match the FP64 oracle.
+(FP64: 1e-12 relative; FP32: 1e-6) with and without graph replay, for the
+Jacobi and the exact projection, and one instance must match the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -27,12 +27,13 @@ def env():
     return tlvlbm, torch.cuda.Stream()
 
 
-def _solver(T, cfg, precision, stream, cg_multigrid=False):
-    # per-instance and batched paths run the same CG (plain, or preconditioned
-    # by the multigrid V-cycle, batched level-synchronously)
+def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20):
+    # per-instance and batched paths run the same projection solver (Jacobi
+    # sweeps; or CG, plain or preconditioned by the multigrid V-cycle,
+    # batched level-synchronously)
     s = T.Solver(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
                  origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"], precision=precision,
-                 stream=stream.cuda_stream, cg_multigrid=cg_multigrid)
+                 stream=stream.cuda_stream, cg_multigrid=cg_multigrid, proj_sweeps=proj_sweeps)
     s.set_levelset(cfg["phi"], cfg["bid"])
     for bid, bc in cfg["bcs"].items():
         bc = dict(bc)
@@ -61,12 +62,13 @@ CFGS = [W.config_c4_instance(k, N=n) for k, n in enumerate([40, 64, 48, 33])]
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
-@pytest.mark.parametrize("graph,mg", [(True, False), (False, False), (True, True)])
-def test_batch_equals_per_instance(env, precision, tol, graph, mg):
+@pytest.mark.parametrize("graph,mg,sweeps", [(True, False, 20), (False, False, 20), (True, False, 0),
+                                             (False, False, 0), (True, True, 0)])
+def test_batch_equals_per_instance(env, precision, tol, graph, mg, sweeps):
     T, stream = env
-    _say(f"batch vs per-instance {precision} graph={graph} multigrid={mg}")
-    A = [_solver(T, c, precision, stream, cg_multigrid=mg) for c in CFGS]
-    B = [_solver(T, c, precision, stream, cg_multigrid=mg) for c in CFGS]
+    _say(f"batch vs per-instance {precision} graph={graph} multigrid={mg} projection sweeps={sweeps}")
+    A = [_solver(T, c, precision, stream, cg_multigrid=mg, proj_sweeps=sweeps) for c in CFGS]
+    B = [_solver(T, c, precision, stream, cg_multigrid=mg, proj_sweeps=sweeps) for c in CFGS]
     T.step_each(A, 65)
     bt = T.Batch(B, use_graph=graph)
     bt.step(30)

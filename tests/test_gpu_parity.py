@@ -31,7 +31,7 @@ def _rel(a, b):
 def _pair(T, orc, D, n, dx, dt, mu, lam, precision, **kw):
     g = T.Solver(D, n, dx, dt, mu, lam, precision=precision, **kw)
     okw = {k: v for k, v in kw.items() if k in ("omega", "gamma", "theta_F", "proj_every", "origin",
-                                                  "periodic_mask")}
+                                                  "periodic_mask", "proj_sweeps")}
     o = orc.Sim(D, n, dx, dt, mu, lam, **okw)
     return g, o
 
@@ -98,9 +98,10 @@ def test_c3_shape_fp32_small(T, orc):
     assert _rel(Ug, Uo) < 1e-5
 
 
-def _annulus_pair(T, orc, Nc, precision, proj_every=20, steps=60):
+def _annulus_pair(T, orc, Nc, precision, proj_every=20, steps=60, proj_sweeps=20):
     c = W.config_c2(Nc)
-    kw = dict(omega=c["omega"], gamma=c["gamma"], origin=c["origin"], periodic_mask=0, proj_every=proj_every)
+    kw = dict(omega=c["omega"], gamma=c["gamma"], origin=c["origin"], periodic_mask=0, proj_every=proj_every,
+              proj_sweeps=proj_sweeps)
     g, o = _pair(T, orc, 2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], precision, **kw)
     for s in (g, o):
         s.set_levelset(c["phi"], c["bid"])
@@ -123,12 +124,14 @@ def test_cut_link_table_matches_oracle(T, orc):
     assert np.abs(Lg["N"] - Lo["N"]).max() < 1e-13
 
 
+@pytest.mark.parametrize("sweeps", [20, 0])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
-def test_mixed_annulus_with_projection(T, orc, precision, tol):
+def test_mixed_annulus_with_projection(T, orc, precision, tol, sweeps):
     """Clamp + traction-free annulus (the C2 recipe at N = 48): Dirichlet and
-    Neumann closures, LSQ, Newton, anchored projection every 20 steps."""
-    c, g, o = _annulus_pair(T, orc, 48, precision)
-    _say(f"annulus 48 {precision} 90 steps")
+    Neumann closures, LSQ, Newton, anchored projection every 20 steps (20
+    Jacobi sweeps, or the exact solve)."""
+    c, g, o = _annulus_pair(T, orc, 48, precision, proj_sweeps=sweeps)
+    _say(f"annulus 48 {precision} 90 steps, projection sweeps {sweeps}")
     for s in (g, o):
         s.set_state(c["U0"])
         s.step(90)
@@ -172,17 +175,19 @@ def test_affine_annulus_dirichlet_exact(T, orc):
     assert np.abs(J[act] - np.linalg.det(np.eye(2) + A)).max() < 1e-12
 
 
-def test_sphere_3d_neumann_fp64(T, orc):
+@pytest.mark.parametrize("sweeps", [20, 0])
+def test_sphere_3d_neumann_fp64(T, orc, sweeps):
     """3D embedded sphere with traction-free Neumann surface (the C5 recipe on
-    a 24^3 grid): 3D LSQ, Newton and projection."""
+    a 24^3 grid): 3D LSQ, Newton and projection (Jacobi sweeps, or exact)."""
     c = W.config_c5(24)
-    kw = dict(omega=c["omega"], gamma=c["gamma"], origin=c["origin"], periodic_mask=0, proj_every=10)
+    kw = dict(omega=c["omega"], gamma=c["gamma"], origin=c["origin"], periodic_mask=0, proj_every=10,
+              proj_sweeps=sweeps)
     g, o = _pair(T, orc, 3, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], "fp64", **kw)
     for s in (g, o):
         s.set_levelset(c["phi"], c["bid"])
     g.set_boundary(1, "neumann")
     o.set_bc(1, orc.NEUMANN)
-    _say("sphere 24^3 fp64 25 steps")
+    _say(f"sphere 24^3 fp64 25 steps, projection sweeps {sweeps}")
     for s in (g, o):
         s.set_state(c["U0"], dU0=c["dU0"])
         s.step(25)

@@ -8,7 +8,8 @@ rerunning the forward oracle.  The cases are chosen so that each part of the
 step carries weight in some of them: periodic bulk with damping (collision,
 streaming, recovery), Dirichlet-only embedded (Dirichlet closure), Neumann
 with and without projection (LSQ, Newton implicit function theorem, the
-projection CG and its gauge, the repair), and a 3D sphere.
+projection's Jacobi sweeps, or its exact CG solve and gauge, the repair), and
+a 3D sphere.
 """
 import numpy as np
 import pytest
@@ -19,7 +20,8 @@ from oracle import oracle as O
 
 def _make(cfg, mu, lam):
     o = O.Sim(cfg["D"], cfg["n"], cfg["dx"], cfg["dt"], mu, lam, omega=cfg["omega"], gamma=cfg["gamma"],
-              origin=cfg.get("origin"), periodic_mask=cfg.get("pm"), proj_every=cfg.get("proj_every", 20))
+              origin=cfg.get("origin"), periodic_mask=cfg.get("pm"), proj_every=cfg.get("proj_every", 20),
+              proj_sweeps=cfg.get("proj_sweeps", 20))
     if "phi" in cfg:
         o.set_levelset(cfg["phi"], cfg["bid"])
         kinds = {"dirichlet": O.DIRICHLET, "neumann": O.NEUMANN}
@@ -82,6 +84,9 @@ CASES = {
     "neumann_annulus_projection": (lambda: _disk(4, True), 9),
     "neumann_annulus_no_projection": (lambda: _disk(0, True), 9),
     "neumann_sphere_projection": (_sphere, 7),
+    # the projection solved exactly instead of relaxed by Jacobi sweeps
+    "neumann_annulus_projection_exact": (lambda: dict(_disk(4, True), proj_sweeps=0), 9),
+    "neumann_sphere_projection_exact": (lambda: dict(_sphere(), proj_sweeps=0), 7),
 }
 
 

@@ -291,3 +291,67 @@ def config_c4_instance(k, seed=SEED, N=None):
     U0[5] = 1.0
     return dict(g, D=2, X=X, phi=phi, bid=bid, bcs=bcs, mu=mu, lam=lam, rho0=1.0, c=c, dt=dt, omega=1.8,
                 gamma=10.0, proj_every=20, U0=U0, steps=2000, N_cells=Nk)
+
+
+def config_ellipsoid(N=320):
+    """Rotated ellipsoid (Sec. 5.1): semi-axes (0.34, 0.25, 0.18), Q = R_z(25)
+    R_y(18) about the box centre; velocity Dirichlet data v = A (X - X_c) on
+    the whole surface, the same affine velocity as initial state (u0 = 0,
+    F0 = I); mu = 1, lambda = 2/3, omega = 1.8, no damping, no projection
+    (Dirichlet only), final time 0.4599."""
+    g = geom_ellipsoid(N)
+    A = np.array([[0.0, 0.80, 0.0], [0.0, 0.0, -0.60], [0.45, 0.0, 0.08]])
+    Xc = np.array([0.5, 0.5, 0.5])
+    X = g["X"]
+    v0 = A @ (X - Xc[:, None])
+    M = 12
+    U0 = np.zeros((M, X.shape[1]))
+    U0[:3] = v0
+    for k in range(3):
+        U0[3 + 4 * k] = 1.0
+    dU0 = np.zeros((3, M, X.shape[1]))
+    for B in range(3):
+        for i in range(3):
+            dU0[B, i] = A[i, B]
+    dt = g["dx"] / 10.0
+    T = 0.4599
+    return dict(g, D=3, A=A, Xc=Xc, mu=1.0, lam=2.0 / 3.0, rho0=1.0, c=10.0, dt=dt, omega=1.8, gamma=0.0,
+                proj_every=20, U0=U0, dU0=dU0, T=T, steps=int(round(T / dt)),
+                bcs={1: dict(type="dirichlet", G=A, X0=tuple(Xc))})
+
+
+def config_shell(N=200, Pr_inner=-1.15242):
+    """Spherical shell R_i = 0.20 <= R <= R_o = 0.38 (Sec. 5.2): both
+    surfaces Neumann; the cavity receives the nominal traction -P_r(R_i) e_R
+    of the radial reference state (sine-squared ramp, T_r = 2), the outer
+    surface is traction free; mu = 1, lambda = 2/3, omega = 1.8, gamma = 10,
+    projection every 20 steps, run to t = 5 from rest."""
+    g = geom_spherical_shell(N)
+    X = g["X"]
+    M = 12
+    U0 = np.zeros((M, X.shape[1]))
+    for k in range(3):
+        U0[3 + 4 * k] = 1.0
+    dt = g["dx"] / 10.0
+    Xc = (0.5, 0.5, 0.5)
+    return dict(g, D=3, mu=1.0, lam=2.0 / 3.0, rho0=1.0, c=10.0, dt=dt, omega=1.8, gamma=10.0, proj_every=20,
+                U0=U0, T=5.0, steps=int(round(5.0 / dt)), Xc=np.array(Xc),
+                bcs={1: dict(type="neumann", ramp="sin2", T_r=2.0, p_radial=-Pr_inner, X0=Xc),
+                     2: dict(type="neumann")})
+
+
+def config_radial_annulus(N=196):
+    """Radial traction annulus (Sec. 4.3): R_i = 0.18 <= R <= R_o = 0.42
+    about (0.5, 0.5); inner surface clamped, outer surface loaded by the
+    nominal radial traction p0 s(t) e_R, p0 = 1 (sine-squared ramp, T_r = 2),
+    run to t = 5 from rest; mu = 1, lambda = 2/3, omega = 1.8, gamma = 10,
+    projection every 20 steps."""
+    g = geom_radial_annulus(N)
+    X = g["X"]
+    U0 = np.zeros((6, X.shape[1]))
+    U0[2] = U0[5] = 1.0
+    dt = g["dx"] / 10.0
+    return dict(g, D=2, mu=1.0, lam=2.0 / 3.0, rho0=1.0, c=10.0, dt=dt, omega=1.8, gamma=10.0, proj_every=20,
+                U0=U0, T=5.0, steps=int(round(5.0 / dt)), Xc=np.array([0.5, 0.5]),
+                bcs={1: dict(type="dirichlet"),
+                     2: dict(type="neumann", ramp="sin2", T_r=2.0, p_radial=1.0, X0=(0.5, 0.5))})

@@ -23,12 +23,12 @@ Other workloads (one JSON line each; not the headline):
                     per-instance launches of the same kernels
     --workload c5   embedded sphere 192^3 (+frame), Neumann surface: reverse
                     mode (forward + recomputation + reverse) over forward time
-    --workload ellipsoid / shell / annulus
+    --workload ellipsoid / shell / annulus / affine
                     the analytic benchmarks end to end (rotated ellipsoid
                     with affine Dirichlet data, N = 320; spherical shell under
                     cavity traction, N = 200; 2D annulus under radial
-                    traction, N = 196): MLUPS and the relative errors against
-                    the exact solutions
+                    traction, N = 196; 2D affine Dirichlet annulus, N = 384):
+                    MLUPS and the relative errors against the exact solutions
 """
 from __future__ import annotations
 
@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--n", type=int, default=None,
                     help="grid cells per axis (c3 256, ellipsoid 320, shell 200)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ellipsoid", "shell", "annulus"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ellipsoid", "shell", "annulus", "affine"], default="c3")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--fd", action="store_true",
                     help="c5: check dL/dmu against Richardson-extrapolated central differences of the forward")
@@ -129,7 +129,8 @@ def main():
             print("bench.py: one GPU only", file=sys.stderr)
             sys.exit(2)
         {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "ellipsoid": bench_analytic,
-         "shell": bench_analytic, "annulus": bench_analytic}[args.workload](args)
+         "shell": bench_analytic, "annulus": bench_analytic,
+         "affine": bench_analytic}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -255,7 +256,10 @@ def bench_c2(args):
 
 
 def bench_c4(args):
-    """64 instances of the random-hole 2D recipe (64^2 .. 512^2), FP32."""
+    """64 instances of the random-hole 2D recipe (64^2 .. 512^2), FP32: the
+    batched launch against per-instance launches of the same kernels, with
+    the default projection (Jacobi sweeps) and with the exact projection
+    (multigrid-preconditioned CG)."""
     import numpy as np
     import torch
 
@@ -267,12 +271,12 @@ def bench_c4(args):
     cfgs = [W.config_c4_instance(k) for k in range(64)]
     nodes = sum(int((c["phi"] <= 0).sum()) for c in cfgs)
 
-    def build(mg):
+    def build(sweeps, mg):
         out = []
         for c in cfgs:
             s = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
                          origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"], precision="fp32",
-                         stream=stream.cuda_stream, cg_multigrid=mg)
+                         stream=stream.cuda_stream, cg_multigrid=mg, proj_sweeps=sweeps)
             s.set_levelset(c["phi"], c["bid"])
             for bid, bc in c["bcs"].items():
                 bc = dict(bc)
@@ -288,31 +292,28 @@ def bench_c4(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
-    A = build(False)
-    ta = timed(lambda: T.step_each(A, steps))
-    B = build(False)
-    bt = T.Batch(B, use_graph=True)
-    tb = timed(lambda: bt.step(steps))
-    bt.close()
-    err = max(float(np.linalg.norm(a.moments()[0] - b.moments()[0]) / np.linalg.norm(a.moments()[0]))
-              for a, b in zip(A, B))
-    C = build(True)
-    tc = timed(lambda: T.step_each(C, steps))
-    E = build(True)
-    bt = T.Batch(E, use_graph=True)
-    te = timed(lambda: bt.step(steps))
-    bt.close()
-    err_mg = max(float(np.linalg.norm(a.moments()[0] - b.moments()[0]) / np.linalg.norm(a.moments()[0]))
-                 for a, b in zip(C, E))
-    _common("batched speedup over per-instance launches of the same kernels", round(tc / te, 3), "x", steps, 0,
-            round(te * 1e3 / steps, 4), True, "f32",
+    def compare(sweeps, mg):
+        A = build(sweeps, mg)
+        ta = timed(lambda: T.step_each(A, steps))
+        B = build(sweeps, mg)
+        bt = T.Batch(B, use_graph=True)
+        tb = timed(lambda: bt.step(steps))
+        bt.close()
+        err = max(float(np.linalg.norm(a.moments()[0] - b.moments()[0]) / np.linalg.norm(a.moments()[0]))
+                  for a, b in zip(A, B))
+        return ta, tb, err
+
+    ta, tb, err = compare(20, False)
+    tc, te, err_mg = compare(0, True)
+    _common("batched speedup over per-instance launches of the same kernels", round(ta / tb, 3), "x", steps, 0,
+            round(tb * 1e3 / steps, 4), True, "f32",
             f"64 embedded D2Q4x6 instances (random holes, 64^2..512^2), {nodes} active nodes, "
-            f"projection every 20 steps (multigrid-preconditioned CG in both paths)",
-            {"per_instance_s": round(tc, 4), "batched_s": round(te, 4),
-             "per_instance_MLUPS": round(nodes * steps / tc / 1e6, 1),
-             "batched_MLUPS": round(nodes * steps / te / 1e6, 1), "max_rel_state_diff": err_mg,
-             "plain_cg": {"per_instance_s": round(ta, 4), "batched_s": round(tb, 4), "speedup": round(ta / tb, 3),
-                          "max_rel_state_diff": err}})
+            f"projection every 20 steps (20 damped Jacobi sweeps in both paths)",
+            {"per_instance_s": round(ta, 4), "batched_s": round(tb, 4),
+             "per_instance_MLUPS": round(nodes * steps / ta / 1e6, 1),
+             "batched_MLUPS": round(nodes * steps / tb / 1e6, 1), "max_rel_state_diff": err,
+             "exact_projection_multigrid_cg": {"per_instance_s": round(tc, 4), "batched_s": round(te, 4),
+                                               "speedup": round(tc / te, 3), "max_rel_state_diff": err_mg}})
 
 
 def bench_c5(args):
@@ -407,11 +408,14 @@ def bench_analytic(args):
     import refsol
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    N = args.n or {"ellipsoid": 320, "shell": 200, "annulus": 196}[args.workload]
+    N = args.n or {"ellipsoid": 320, "shell": 200, "annulus": 196, "affine": 384}[args.workload]
     print(f"[bench] {args.workload} N={N} {args.precision}: building inputs", file=sys.stderr, flush=True)
     if args.workload == "ellipsoid":
         c = W.config_ellipsoid(N)
         desc = f"D3Q6x12 rotated ellipsoid {N}^3+frame, affine velocity Dirichlet surface, omega=1.8"
+    elif args.workload == "affine":
+        c = W.config_affine_annulus(N)
+        desc = f"D2Q4x6 affine annulus {N}^2+frame, affine velocity Dirichlet surfaces, omega=2"
     elif args.workload == "annulus":
         c = W.config_radial_annulus(N)
         desc = (f"D2Q4x6 radial traction annulus {N}^2+frame, clamped inner surface, ramped radial traction, "
@@ -431,8 +435,8 @@ def bench_analytic(args):
     st = s.stats()
     U, u, J = s.moments()
     t = steps * c["dt"]
-    if args.workload == "ellipsoid":
-        err = refsol.ellipsoid_errors(c, U, u, J, t)
+    if args.workload in ("ellipsoid", "affine"):
+        err = refsol.affine_errors(c, U, u, J, t)
     elif args.workload == "annulus":
         ref = refsol.radial_bvp(2, c["mu"], c["lam"], 0.18, 0.42, r_inner=0.18, Pr_outer=1.0)
         err = refsol.radial_errors(c, ref, U, u, J)

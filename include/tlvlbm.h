@@ -164,6 +164,18 @@ tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *ctx, const double *phi, const uint
 /* Attach a boundary condition to identifier bid (copied). */
 tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *ctx, uint8_t bid, const tlvlbm_bc *bc);
 
+/* Body acceleration b(X, t) = s(t) g(X) (Sec. 2.1, Eq. 5).  It enters the
+ * source B = (b - gamma v, 0) of the first-order system (Eq. 12): in the
+ * state recovery (Eq. 28) and the collision (Eqs. 29-30) of step n with
+ * t = t^n, and in the second-order initialisation through B0 (Eqs. 32-33)
+ * when set before tlvlbm_set_state.
+ *   g     [D][N] FP64 planar, host or device (copied; NULL removes the field)
+ *   ramp  tlvlbm_ramp kind of s(t), T_r its time (> 0 unless CONST)
+ * A new field takes effect at the next step; a caller that needs a general
+ * b(X, t) sets it before each step(1).  Contexts with a body acceleration
+ * cannot join a batch and have no reverse mode (TLVLBM_ERR_INVALID_ARG). */
+tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *ctx, const double *g, int32_t ramp, double T_r);
+
 /* Replace the material (e.g. for finite-difference sweeps).  The stored
  * populations are kept. */
 tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *ctx, const tlvlbm_material *mat);

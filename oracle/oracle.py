@@ -56,6 +56,7 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_projection.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        L.orc_set_body_force.argtypes = [C.c_void_p, dp, C.c_int, C.c_double]
         L.orc_set_levelset.argtypes = [C.c_void_p, dp, C.POINTER(C.c_uint8)]
         L.orc_set_bc.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp, dp,
                                  C.c_double, C.c_double, dp]
@@ -216,6 +217,14 @@ class Sim:
                               p_radial, p_normal, _d(X03))
         if st:
             raise OracleError(st, "set_bc")
+
+    def set_body_force(self, g, ramp=RAMP_CONST, T_r=1.0):
+        """Body acceleration b(X, t) = s(t) g(X), g [D][N] (None clears)."""
+        gp = None if g is None else _d(_keep(self, _f64(g).reshape(self.D, self.N)))
+        st = lib().orc_set_body_force(self.h, gp, int(ramp), float(T_r))
+        self._tmps = []
+        if st:
+            raise OracleError(st, "set_body_force")
 
     def set_state(self, U0, u0=None, dU0=None):
         U0 = _f64(U0).reshape(self.M, self.N)

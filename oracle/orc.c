@@ -438,6 +438,10 @@ struct orc_sim {
   /* initial data of the last orc_set_state (kept for the reverse mode) */
   double *U0, *u0, *dU0;
   int64_t init_step;
+  /* body acceleration b(X, t) = s(t) g(X) (Eq. 5): g [N][D] or NULL */
+  double *bf;
+  int bf_ramp;
+  double bf_Tr;
 };
 
 static void coords(const orc_sim *s, int64_t i, int *c) {
@@ -546,6 +550,7 @@ void orc_destroy(orc_sim *s) {
   free(s->U0);
   free(s->u0);
   free(s->dU0);
+  free(s->bf);
   free(s->act);
   free(s);
 }
@@ -710,6 +715,19 @@ int orc_set_levelset(orc_sim *s, const double *phi, const uint8_t *bid) {
   return ORC_OK;
 }
 
+int orc_set_body_force(orc_sim *s, const double *g, int ramp, double T_r) {
+  free(s->bf);
+  s->bf = NULL;
+  if (!g) return ORC_OK;
+  s->bf = (double *)malloc(sizeof(double) * (size_t)s->N * s->D);
+  if (!s->bf) return ORC_ERR_MEM;
+  for (int64_t i = 0; i < s->N; ++i)
+    for (int a = 0; a < s->D; ++a) s->bf[i * s->D + a] = g[(size_t)a * s->N + i];
+  s->bf_ramp = ramp;
+  s->bf_Tr = T_r;
+  return ORC_OK;
+}
+
 int orc_set_projection(orc_sim *s, int sweeps, double weight) {
   if (sweeps < 0 || !(weight > 0.0 && weight <= 1.0)) return ORC_ERR_ARG;
   s->proj_sweeps = sweeps;
@@ -802,6 +820,15 @@ static void bc_displacement(const orc_bc *b, int D, const double *X, const doubl
   for (int i = 0; i < D; ++i) val[i] *= fac;
 }
 
+/* body acceleration at node i and time t (zero without a field) */
+static void body_acc(const orc_sim *s, int64_t i, double t, double *b) {
+  for (int a = 0; a < s->D; ++a) b[a] = 0.0;
+  if (!s->bf) return;
+  double sv, dsv;
+  ramp_eval(s->bf_ramp, s->bf_Tr, t, &sv, &dsv);
+  for (int a = 0; a < s->D; ++a) b[a] = sv * s->bf[i * s->D + a];
+}
+
 /* Second-order initialisation (Sec. 2.4, Eqs. 32-33):
  *   f_q = feq(U0) - dt/2 (dt + c e_qA d_A) feq(U0),
  *   dt U0 = B0 - Phi'_A(U0) d_A U0,
@@ -809,11 +836,11 @@ static void bc_displacement(const orc_bc *b, int D, const double *X, const doubl
  * of Eq. 27.  With no gradients supplied the spatial terms vanish. */
 /* populations of one node from U0 and its derivatives dA[A*M + r] */
 static void init_node(const orc_sim *s, double mu, double lam, const double *U, const double *dA,
-                      double *f) {
+                      const double *b0, double *f) {
   int D = s->D, M = s->M, Q = s->Q;
   double Ut[MAXM], feq[MAXQ * MAXM], dPhi[MAXD * MAXM];
-  /* B0 = (-gamma v0, 0) : velocity damping source (Sec. 4.1) */
-  for (int r = 0; r < M; ++r) Ut[r] = (r < D) ? -s->gamma * U[r] : 0.0;
+  /* B0 = (b0 - gamma v0, 0): body acceleration and velocity damping */
+  for (int r = 0; r < M; ++r) Ut[r] = (r < D) ? b0[r] - s->gamma * U[r] : 0.0;
   for (int A = 0; A < D; ++A) {
     flux_jvp(D, mu, lam, s->rho0, U, dA + A * M, dPhi);
     for (int r = 0; r < M; ++r) Ut[r] -= dPhi[A * M + r];
@@ -870,7 +897,9 @@ int orc_set_state(orc_sim *s, const double *U0, const double *u0, const double *
     for (int A = 0; A < D; ++A)
       for (int r = 0; r < M; ++r)
         dA[A * M + r] = dU0 ? dU0[((size_t)A * M + r) * s->N + i] : 0.0;
-    init_node(s, s->mu, s->lam, U, dA, f);
+    double b0[MAXD];
+    body_acc(s, i, s->step * s->dt, b0);
+    init_node(s, s->mu, s->lam, U, dA, b0, f);
     for (int a = 0; a < D; ++a) {
       double u0a = u0 ? u0[(size_t)a * s->N + i] : 0.0;
       s->ustar[i * D + a] = u0a - 0.5 * s->dt * U[a]; /* so that u^0 = u0 (Eq. 34) */
@@ -889,9 +918,12 @@ int orc_set_state(orc_sim *s, const double *U0, const double *u0, const double *
  * B = (-gamma v, 0) of Sec. 4.1.  The half-step source makes the recovered
  * velocity implicit; its closed form v = sum_q f^v / (1 + gamma dt/2) is a
  * reading (the paper is silent). */
+/* U^n = sum_q f_q + dt/2 B^n (Eq. 28) with B^n = (b^n - gamma v^n, 0): the
+ * damping part is implicit in v^n */
 static int recover(orc_sim *s) {
   int D = s->D, M = s->M, Q = s->Q;
   int err = 0;
+  const double tn = s->step * s->dt;
 #pragma omp parallel for reduction(| : err)
   for (int64_t i = 0; i < s->N; ++i) {
     if (!s->act[i]) continue;
@@ -902,7 +934,9 @@ static int recover(orc_sim *s) {
       for (int q = 0; q < Q; ++q) acc += f[q * M + r];
       U[r] = acc;
     }
-    for (int a = 0; a < D; ++a) U[a] /= (1.0 + 0.5 * s->gamma * s->dt);
+    double b[MAXD];
+    body_acc(s, i, tn, b);
+    for (int a = 0; a < D; ++a) U[a] = (U[a] + 0.5 * s->dt * b[a]) / (1.0 + 0.5 * s->gamma * s->dt);
     for (int r = 0; r < M; ++r)
       if (!isfinite(U[r])) err |= 2;
     if (!(det_n(D, U + D) > 0.0)) err |= 1;
@@ -1294,9 +1328,10 @@ int orc_step(orc_sim *s, int64_t nsteps) {
     for (int64_t m = 0; m < s->N; ++m) {
       if (!s->act[m]) continue;
       const double *U = s->U + (size_t)m * M;
-      double feq[MAXQ * MAXM], B[MAXM];
+      double feq[MAXQ * MAXM], B[MAXM], b[MAXD];
       orc_feq(D, s->c, s->mu, s->lam, s->rho0, U, feq);
-      for (int r = 0; r < M; ++r) B[r] = (r < D) ? -s->gamma * U[r] : 0.0;
+      body_acc(s, m, tn, b);
+      for (int r = 0; r < M; ++r) B[r] = (r < D) ? b[r] - s->gamma * U[r] : 0.0;
       const double *f = s->f + (size_t)m * Q * M;
       double *fs = s->fs + (size_t)m * Q * M;
       for (int q = 0; q < Q; ++q)
@@ -2030,21 +2065,23 @@ int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dL
       for (int r = 0; r < M; ++r) U[r] = s->U0[(size_t)r * N + m];
       for (int A = 0; A < D; ++A)
         for (int r = 0; r < M; ++r) dA[A * M + r] = s->dU0[((size_t)A * M + r) * N + m];
-      init_node(s, s->mu, s->lam, U, dA, f0);
+      double b0[MAXD];
+      body_acc(s, m, s->init_step * s->dt, b0);
+      init_node(s, s->mu, s->lam, U, dA, b0, f0);
       for (int a = 0; a < D; ++a) {
         double acc = 0.0;
         U[a] += 1.0;
-        init_node(s, s->mu, s->lam, U, dA, f1);
+        init_node(s, s->mu, s->lam, U, dA, b0, f1);
         U[a] -= 1.0;
         for (int k2 = 0; k2 < Q * M; ++k2) acc += l0[k2] * (f1[k2] - f0[k2]);
         if (grad_v0) grad_v0[(size_t)a * N + m] = acc - 0.5 * s->dt * lus[m * D + a];
         if (grad_u0) grad_u0[(size_t)a * N + m] = lus[m * D + a];
       }
-      init_node(s, s->mu + 1.0, s->lam, U, dA, f0);
-      init_node(s, s->mu - 1.0, s->lam, U, dA, f1);
+      init_node(s, s->mu + 1.0, s->lam, U, dA, b0, f0);
+      init_node(s, s->mu - 1.0, s->lam, U, dA, b0, f1);
       for (int k2 = 0; k2 < Q * M; ++k2) gi[0] += l0[k2] * 0.5 * (f0[k2] - f1[k2]);
-      init_node(s, s->mu, s->lam + 1.0, U, dA, f0);
-      init_node(s, s->mu, s->lam - 1.0, U, dA, f1);
+      init_node(s, s->mu, s->lam + 1.0, U, dA, b0, f0);
+      init_node(s, s->mu, s->lam - 1.0, U, dA, b0, f1);
       for (int k2 = 0; k2 < Q * M; ++k2) gi[1] += l0[k2] * 0.5 * (f0[k2] - f1[k2]);
     }
     gmat[0] += gi[0];

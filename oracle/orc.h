@@ -78,6 +78,11 @@ void orc_destroy(orc_sim *s);
 #define ORC_PROJ_SWEEPS 20
 #define ORC_PROJ_WEIGHT (2.0 / 3.0)
 int  orc_set_projection(orc_sim *s, int sweeps, double weight);
+/* body acceleration b(X, t) = s(t) g(X) (Sec. 2.1, Eq. 5), entering
+ * B = (b - gamma v, 0) in the recovery, the collision and the initialisation
+ * (Eqs. 28-33); g [D][N] planar (copied) or NULL to clear; s(t) a ramp of
+ * kind `ramp` and time T_r, evaluated at t^n for step n. */
+int  orc_set_body_force(orc_sim *s, const double *g, int ramp, double T_r);
 /* phi[N] node samples (phi <= 0 inside, Eq. 36); bid[N] boundary ids. */
 int  orc_set_levelset(orc_sim *s, const double *phi, const uint8_t *bid);
 /* boundary value s(t) (a + G (X - X0) + p_radial e_R + p_normal N_b) */

@@ -2,7 +2,15 @@
 Boltzmann method for finite-strain hyperelasticity with curved boundaries.
 
 The compute path is the HIP library ``libtlvlbm.so`` behind the C ABI in
-``include/tlvlbm.h``; ``tlvlbm.Solver`` is its thin Python binding.
+``include/tlvlbm.h``; ``tlvlbm.Solver`` is its thin Python binding.  The
+binding (and with it the library) loads on first use of one of its names, so
+that ``paper_2606_20646_amd.build`` can compile the library first.
 """
-from .tlvlbm import (DIRICHLET, FP32, FP64, NEUMANN, LIB_PATH, Solver,  # noqa: F401
-                     TlvlbmError)
+_EXPORTS = ("DIRICHLET", "FP32", "FP64", "NEUMANN", "LIB_PATH", "Solver", "TlvlbmError")
+
+
+def __getattr__(name):
+    if name in _EXPORTS:
+        from . import tlvlbm
+        return getattr(tlvlbm, name)
+    raise AttributeError(name)

@@ -312,7 +312,7 @@ __global__ __launch_bounds__(AT) void k_adj_rep2(const T *__restrict__ Lout, T *
 template <int D, typename T, int PASS, bool NEU>
 __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, int64_t b0, int64_t b1, BC bc, Geo g,
                                                  Par par, double th, const T *__restrict__ tapeU,
-                                                 const T *__restrict__ tapeFr, const T *__restrict__ tapeu,
+                                                 const T *__restrict__ tapeFr, const double *__restrict__ tapeu,
                                                  double *__restrict__ gbar, double *__restrict__ glink) {
   constexpr int M = D + D * D;
   const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -778,7 +778,8 @@ template <int D, typename T> void launch_link_pass(Run &R, int pass, double th, 
     if (b1 <= b0) continue;
     const bool neu = c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION;
     const unsigned nb = nblocks(b1 - b0, 64);
-    const T *tU = (const T *)tp.U, *tF = (const T *)tp.Fr, *tu = (const T *)tp.u;
+    const T *tU = (const T *)tp.U, *tF = (const T *)tp.Fr;
+    const double *tu = (const double *)tp.u;
 #define TL_LINK(P, NN)                                                                                         \
   hipLaunchKernelGGL((k_adj_link<D, T, P, NN>), nb, 64, 0, c->st, (T *)R.La, c->L, b0, b1, c->bcs[b], c->geo, \
                      c->par, th, tU, tF, tu, R.gbar, R.glink)
@@ -981,8 +982,8 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   }
   const bool track = c->track_u;
   const size_t plane = (size_t)g.S * sizeof(T), dplane = (size_t)g.S * sizeof(double);
-  const size_t ck_bytes = (size_t)Q * M * plane + (track ? D * plane : 0);
-  const size_t tape_bytes = (size_t)M * plane + (R.neu ? D * plane : 0);
+  const size_t ck_bytes = (size_t)Q * M * plane + (track ? D * dplane : 0);
+  const size_t tape_bytes = (size_t)M * plane + (R.neu ? D * dplane : 0);
   if (seg <= 0) {
     seg = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(n, 1) * (double)ck_bytes / (double)tape_bytes));
     seg = std::max<int64_t>(1, std::min<int64_t>(seg, std::max<int64_t>(n, 1)));
@@ -1021,16 +1022,16 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   std::vector<void *> ckf(nck + 1, nullptr), cku(nck + 1, nullptr);
   for (int64_t s = 0; s <= nck; ++s) {
     if (pool.get(&ckf[s], (size_t)Q * M * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-    if (track && pool.get(&cku[s], (size_t)D * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (track && pool.get(&cku[s], (size_t)D * dplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
   }
   auto save = [&](int64_t s) -> bool {
     if (hipMemcpyAsync(ckf[s], c->fB, (size_t)Q * M * plane, hipMemcpyDeviceToDevice, st)) return false;
-    if (track && hipMemcpyAsync(cku[s], c->ustar, (size_t)D * plane, hipMemcpyDeviceToDevice, st)) return false;
+    if (track && hipMemcpyAsync(cku[s], c->ustar, (size_t)D * dplane, hipMemcpyDeviceToDevice, st)) return false;
     return true;
   };
   auto restore = [&](int64_t s) -> bool {
     if (hipMemcpyAsync(c->fB, ckf[s], (size_t)Q * M * plane, hipMemcpyDeviceToDevice, st)) return false;
-    if (track && hipMemcpyAsync(c->ustar, cku[s], (size_t)D * plane, hipMemcpyDeviceToDevice, st)) return false;
+    if (track && hipMemcpyAsync(c->ustar, cku[s], (size_t)D * dplane, hipMemcpyDeviceToDevice, st)) return false;
     return true;
   };
   // the projection solutions of the first pass are kept (active tiles, FP64)
@@ -1096,7 +1097,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   // per-step tape of one segment
   char *tapeU = nullptr, *tapeu = nullptr, *tapeF = nullptr;
   if (pool.get(&tapeU, (size_t)seg * M * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-  if (R.neu && pool.get(&tapeu, (size_t)seg * D * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+  if (R.neu && pool.get(&tapeu, (size_t)seg * D * dplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
   if (nproj_seg && pool.get(&tapeF, (size_t)nproj_seg * D * D * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
   // seeds
   {
@@ -1128,7 +1129,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     for (int64_t k = k0; k < k1; ++k) {
       TapeStep &tp = tps[k - k0];
       tp.U = tapeU + (size_t)(k - k0) * M * plane;
-      tp.u = R.neu ? tapeu + (size_t)(k - k0) * D * plane : nullptr;
+      tp.u = R.neu ? tapeu + (size_t)(k - k0) * D * dplane : nullptr;
       tp.Fr = nullptr;
       xs_of(k, tp, 2);
       if (is_projection_step(c, k)) {
@@ -1210,6 +1211,10 @@ extern "C" tlvlbm_status tlvlbm_adjoint(tlvlbm_ctx *c, int64_t n, const double *
     if (!c->have_state || !c->fresh) {
       c->err = "adjoint: the state must be the one set by tlvlbm_set_state (no step since)";
       return TLVLBM_ERR_CALL_ORDER;
+    }
+    if (c->bf) {
+      c->err = "adjoint: no reverse mode with a body acceleration";
+      return TLVLBM_ERR_INVALID_ARG;
     }
     if (c->D == 2)
       s = c->prec ? adjoint_t<2, double>(c, n, U0, dU0, dLdU, dLdu, grad_mat, grad_v0, grad_u0, segment, err)

@@ -99,7 +99,8 @@ int step_once(tlvlbm_ctx *c, const TapeStep *tp) {
   }
   if (c->L.n) launch_cutlinks(c, tn);
   if (tp && tp->u)
-    CHK(hipMemcpyAsync(tp->u, c->ubuf, (size_t)c->D * plane, hipMemcpyDeviceToDevice, c->st), "tape");
+    CHK(hipMemcpyAsync(tp->u, c->ubuf, (size_t)c->D * c->geo.S * sizeof(double), hipMemcpyDeviceToDevice, c->st),
+        "tape");
   std::swap(c->fA, c->fB);
   ++c->step;
   return TLVLBM_OK;
@@ -211,7 +212,8 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
   void *ptrs[] = {c->fA, c->fB, c->ustar, c->ubuf, c->act, c->d_flag, c->d_newton_fail, c->L.node, c->L.out,
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
-                  c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles};
+                  c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles,
+                  c->bf};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
@@ -279,6 +281,34 @@ tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *c, uint8_t bid, const tlvlbm_bc *b
   return TLVLBM_OK;
 }
 
+tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *c, const double *g, int32_t ramp, double T_r) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  if (ramp < 0 || ramp > 3 || (ramp != TLVLBM_RAMP_CONST && !(T_r > 0)))
+    return fail(c, TLVLBM_ERR_INVALID_ARG, "bad ramp");
+  try {
+    if (!g) {
+      if (c->bf) CHK(hipFree(c->bf), "body force free");
+      c->bf = nullptr;
+      return TLVLBM_OK;
+    }
+    const size_t plane = (size_t)c->geo.S * c->esz;
+    if (!c->bf) {
+      CHK(hipMalloc(&c->bf, (size_t)c->D * plane), "body force alloc");
+      CHK(hipMemsetAsync(c->bf, 0, (size_t)c->D * plane, c->st), "body force clear");
+    }
+    DevIn dg;
+    CHK(dg.take(g, (size_t)c->D * c->geo.N * sizeof(double), c->st), "body force upload");
+    launch_planes_in(c, (const double *)dg.ptr, c->bf, c->D);
+    CHK(hipGetLastError(), "body force convert");
+    CHK(hipStreamSynchronize(c->st), "body force");
+    c->bf_ramp = ramp;
+    c->bf_Tr = T_r;
+    return TLVLBM_OK;
+  } catch (...) {
+    return fail(c, TLVLBM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
 tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *c, const tlvlbm_material *m) {
   if (!c || !m || m->law != 0) return TLVLBM_ERR_INVALID_ARG;
   c->par.mu = m->mu;
@@ -301,9 +331,9 @@ tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0
     const int64_t N = c->geo.N, S = c->geo.S;
     const int D = c->D, M = c->M;
     if (c->track_u && !c->ustar) {
-      CHK(hipMalloc(&c->ustar, (size_t)D * S * c->esz), "u* alloc");
-      CHK(hipMalloc(&c->ubuf, (size_t)D * S * c->esz), "u alloc");
-      CHK(hipMemsetAsync(c->ubuf, 0, (size_t)D * S * c->esz, c->st), "u clear");
+      CHK(hipMalloc(&c->ustar, (size_t)D * S * sizeof(double)), "u* alloc");
+      CHK(hipMalloc(&c->ubuf, (size_t)D * S * sizeof(double)), "u alloc");
+      CHK(hipMemsetAsync(c->ubuf, 0, (size_t)D * S * sizeof(double), c->st), "u clear");
     }
     DevIn dU, du, ddU;
     CHK(dU.take(U0, (size_t)M * N * sizeof(double), c->st), "U0 upload");
@@ -313,6 +343,7 @@ tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0
     CHK(hipMemsetAsync(c->fB, 0, fb, c->st), "population clear");
     CHK(hipMemsetAsync(c->fA, 0, fb, c->st), "population clear");
     CHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->st), "flag clear");
+    c->step = 0;  // the initial state is at t = 0 (body acceleration b(X, 0))
     launch_init(c, (const double *)dU.ptr, (const double *)du.ptr, (const double *)ddU.ptr);
     CHK(hipGetLastError(), "init launch");
     tlvlbm_status s = read_flag(c);
@@ -412,9 +443,9 @@ tlvlbm_status tlvlbm_put_state(tlvlbm_ctx *c, const double *f, const double *ust
   {
     const int64_t N = c->geo.N;
     if (c->track_u && !c->ustar) {
-      CHK(hipMalloc(&c->ustar, (size_t)c->D * c->geo.S * c->esz), "u* alloc");
-      CHK(hipMalloc(&c->ubuf, (size_t)c->D * c->geo.S * c->esz), "u alloc");
-      CHK(hipMemsetAsync(c->ubuf, 0, (size_t)c->D * c->geo.S * c->esz, c->st), "u clear");
+      CHK(hipMalloc(&c->ustar, (size_t)c->D * c->geo.S * sizeof(double)), "u* alloc");
+      CHK(hipMalloc(&c->ubuf, (size_t)c->D * c->geo.S * sizeof(double)), "u alloc");
+      CHK(hipMemsetAsync(c->ubuf, 0, (size_t)c->D * c->geo.S * sizeof(double), c->st), "u clear");
     }
     DevIn F, U;
     CHK(F.take(f, (size_t)c->Q * c->M * N * sizeof(double), c->st), "f upload");

@@ -14,6 +14,7 @@
 // reference state, df = f - feq(v = 0, F = I); that equilibrium is U_I/(2D)
 // with U_I = (0, I) because P(I) = 0.  In FP32 this keeps the diagonal
 // deformation-gradient rows at O(|F - I|) magnitude instead of O(1/(2D)).
+#include "tl_device.hpp"
 #include "tl_internal.hpp"
 #include "tl_math.hpp"
 
@@ -91,11 +92,12 @@ template <typename T> __device__ __forceinline__ bool finite_(T v) { return __bu
 // collision with source + displacement quadrature (Algorithm 1, bulk loops).
 // TAPE: also store the recovered (pre-repair) state (v, F - I) to the tape
 // planes for the reverse mode.
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool TAPE = false>
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool TAPE = false, bool BODY = false>
 __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restrict__ fout, const Geo &g,
-                                          const Par &p, const uint8_t *__restrict__ act, T *__restrict__ ustar,
-                                          T *__restrict__ ubuf, const T *__restrict__ Frp,
-                                          int *__restrict__ flag, int x, int row, T *__restrict__ tape = nullptr) {
+                                          const Par &p, const uint8_t *__restrict__ act, double *__restrict__ ustar,
+                                          double *__restrict__ ubuf, const T *__restrict__ Frp,
+                                          int *__restrict__ flag, int x, int row, T *__restrict__ tape = nullptr,
+                                          const T *__restrict__ bf = nullptr, T bs = T(0)) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int y = row % g.ny, z = row / g.ny;
   const int64_t node = x + (int64_t)g.nx * row;
@@ -105,8 +107,8 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
   T f[Q][M];
   pull_all<D, T, M>(fin, g, x, y, z, f);
 
-  // state recovery with the half-step damping source (Eq. 28): the velocity
-  // is implicit in B = (-gamma v, 0), v = sum_q f^v / (1 + gamma dt / 2)
+  // state recovery with the half-step source (Eq. 28): B = (b - gamma v, 0)
+  // with the damping implicit, v = (sum_q f^v + dt/2 b) / (1 + gamma dt / 2)
   T dU[M];
 #pragma unroll
   for (int r = 0; r < M; ++r) {
@@ -117,9 +119,12 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
   }
   const T dt = T(p.dt), mu = T(p.mu), lam = T(p.lam), irho = T(p.inv_rho0);
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
+  T bacc[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) bacc[i] = BODY ? bs * bf[(size_t)i * g.S + node] : T(0);
   T v[D], F[D * D], P[D * D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) v[i] = dU[i] * inv_damp;
+  for (int i = 0; i < D; ++i) v[i] = (BODY ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
 #pragma unroll
   for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
   T J = piola<D>(F, mu, lam, P);
@@ -180,24 +185,24 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
       }
       const T feq = base * inv2D + sg * inv2c * phi;
       T out = f[q][r] + om * (feq - f[q][r]);
-      if (r < D) out += srcw * (-T(p.gamma) * v[r]);
+      if (r < D) out += srcw * (BODY ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
     }
   }
 
   if constexpr (TRACK) {
-    // trapezoidal displacement quadrature (Eq. 34)
-    const T hdt = T(0.5) * dt;
+    // trapezoidal displacement quadrature (Eq. 34), FP64 in both builds
+    const double hdt = 0.5 * p.dt;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      T uu;
+      double uu;
       if constexpr (REPAIR) {
         uu = ubuf[(size_t)i * g.S + node];
       } else {
-        uu = ustar[(size_t)i * g.S + node] + hdt * v[i];
+        uu = ustar[(size_t)i * g.S + node] + hdt * double(v[i]);
         ubuf[(size_t)i * g.S + node] = uu;
       }
-      ustar[(size_t)i * g.S + node] = uu + hdt * v[i];
+      ustar[(size_t)i * g.S + node] = uu + hdt * double(v[i]);
     }
   }
   T chk = J;
@@ -210,11 +215,11 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
 // device function above, the compiler schedules its address arithmetic
 // differently and the kernel runs 2.6% slower at 256^3 (measured).  The two
 // bodies are kept identical (a CPU test compares them).
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR>
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool BODY = false>
 __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
-                                               const uint8_t *__restrict__ act, T *__restrict__ ustar,
-                                               T *__restrict__ ubuf, const T *__restrict__ Frp,
-                                               int *__restrict__ flag) {
+                                               const uint8_t *__restrict__ act, double *__restrict__ ustar,
+                                               double *__restrict__ ubuf, const T *__restrict__ Frp,
+                                               int *__restrict__ flag, const T *__restrict__ bf, T bs) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
@@ -227,8 +232,8 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
   T f[Q][M];
   pull_all<D, T, M>(fin, g, x, y, z, f);
 
-  // state recovery with the half-step damping source (Eq. 28): the velocity
-  // is implicit in B = (-gamma v, 0), v = sum_q f^v / (1 + gamma dt / 2)
+  // state recovery with the half-step source (Eq. 28): B = (b - gamma v, 0)
+  // with the damping implicit, v = (sum_q f^v + dt/2 b) / (1 + gamma dt / 2)
   T dU[M];
 #pragma unroll
   for (int r = 0; r < M; ++r) {
@@ -239,9 +244,12 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
   }
   const T dt = T(p.dt), mu = T(p.mu), lam = T(p.lam), irho = T(p.inv_rho0);
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
+  T bacc[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) bacc[i] = BODY ? bs * bf[(size_t)i * g.S + node] : T(0);
   T v[D], F[D * D], P[D * D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) v[i] = dU[i] * inv_damp;
+  for (int i = 0; i < D; ++i) v[i] = (BODY ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
 #pragma unroll
   for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
   T J = piola<D>(F, mu, lam, P);
@@ -296,24 +304,24 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
       }
       const T feq = base * inv2D + sg * inv2c * phi;
       T out = f[q][r] + om * (feq - f[q][r]);
-      if (r < D) out += srcw * (-T(p.gamma) * v[r]);
+      if (r < D) out += srcw * (BODY ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
     }
   }
 
   if constexpr (TRACK) {
-    // trapezoidal displacement quadrature (Eq. 34)
-    const T hdt = T(0.5) * dt;
+    // trapezoidal displacement quadrature (Eq. 34), FP64 in both builds
+    const double hdt = 0.5 * p.dt;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      T uu;
+      double uu;
       if constexpr (REPAIR) {
         uu = ubuf[(size_t)i * g.S + node];
       } else {
-        uu = ustar[(size_t)i * g.S + node] + hdt * v[i];
+        uu = ustar[(size_t)i * g.S + node] + hdt * double(v[i]);
         ubuf[(size_t)i * g.S + node] = uu;
       }
-      ustar[(size_t)i * g.S + node] = uu + hdt * v[i];
+      ustar[(size_t)i * g.S + node] = uu + hdt * double(v[i]);
     }
   }
   T chk = J;
@@ -323,15 +331,16 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
 }
 
 // the same update recording the recovered state on the reverse-mode tape
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR>
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool BODY = false>
 __global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
-                                                   const uint8_t *__restrict__ act, T *__restrict__ ustar,
-                                                   T *__restrict__ ubuf, const T *__restrict__ Frp,
-                                                   int *__restrict__ flag, T *__restrict__ tape) {
+                                                   const uint8_t *__restrict__ act, double *__restrict__ ustar,
+                                                   double *__restrict__ ubuf, const T *__restrict__ Frp,
+                                                   int *__restrict__ flag, T *__restrict__ tape,
+                                                   const T *__restrict__ bf, T bs) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
-  bulk_node<D, T, MASK, TRACK, REPAIR, true>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, (int)blockIdx.y,
-                                             tape);
+  bulk_node<D, T, MASK, TRACK, REPAIR, true, BODY>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x,
+                                                   (int)blockIdx.y, tape, bf, bs);
 }
 
 // Batched bulk update: one block per tile (instance, row, first x) of the
@@ -343,24 +352,25 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_batch(const Inst *_
   const Inst &I = insts[t.x];
   const int x = t.z + threadIdx.x;
   if (x >= I.g.nx) return;
-  bulk_node<D, T, true, true, REPAIR>((const T *)I.fin, (T *)I.fout, I.g, I.p, I.act, (T *)I.ustar, (T *)I.ubuf,
-                                      (const T *)I.Fr, I.flag, x, t.y);
+  bulk_node<D, T, true, true, REPAIR>((const T *)I.fin, (T *)I.fout, I.g, I.p, I.act, (double *)I.ustar,
+                                      (double *)I.ubuf, (const T *)I.Fr, I.flag, x, t.y);
 }
 
 // Pull f^n and write moments: v (damping-corrected), F, u = u* + dt/2 v, J.
 // Output planes have stride ostride; any output may be null.
 template <int D, typename T, typename O, bool MASK>
 __device__ __forceinline__ void moments_node(const T *__restrict__ fin, const Geo &g, const Par &p,
-                                             const uint8_t *__restrict__ act, const T *__restrict__ ustar,
-                                             O *__restrict__ Vo, O *__restrict__ Fo, O *__restrict__ uo,
-                                             O *__restrict__ Jo, int64_t ostride, int x, int row) {
+                                             const uint8_t *__restrict__ act, const double *__restrict__ ustar,
+                                             O *__restrict__ Vo, O *__restrict__ Fo, double *__restrict__ uo,
+                                             O *__restrict__ Jo, int64_t ostride, int x, int row,
+                                             const T *__restrict__ bf = nullptr, T bs = T(0)) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int y = row % g.ny, z = row / g.ny;
   const int64_t node = x + (int64_t)g.nx * row;
   if (MASK && !act[node]) {
     for (int i = 0; i < D; ++i) {
       if (Vo) Vo[(size_t)i * ostride + node] = O(0);
-      if (uo) uo[(size_t)i * ostride + node] = O(0);
+      if (uo) uo[(size_t)i * ostride + node] = 0.0;
     }
     if (Fo)
       for (int k = 0; k < D * D; ++k) Fo[(size_t)k * ostride + node] = O(0);
@@ -380,7 +390,8 @@ __device__ __forceinline__ void moments_node(const T *__restrict__ fin, const Ge
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * T(p.dt));
   T v[D], F[D * D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) v[i] = dU[i] * inv_damp;
+  for (int i = 0; i < D; ++i)
+    v[i] = (bf ? dU[i] + T(0.5) * T(p.dt) * (bs * bf[(size_t)i * g.S + node]) : dU[i]) * inv_damp;
 #pragma unroll
   for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
   if (Vo)
@@ -389,18 +400,19 @@ __device__ __forceinline__ void moments_node(const T *__restrict__ fin, const Ge
     for (int k = 0; k < D * D; ++k) Fo[(size_t)k * ostride + node] = O(F[k]);
   if (uo)
     for (int i = 0; i < D; ++i)
-      uo[(size_t)i * ostride + node] = ustar ? O(ustar[(size_t)i * g.S + node] + T(0.5) * T(p.dt) * v[i]) : O(0);
+      uo[(size_t)i * ostride + node] = ustar ? ustar[(size_t)i * g.S + node] + 0.5 * p.dt * double(v[i]) : 0.0;
   if (Jo) Jo[node] = O(det<D>(F));
 }
 
 template <int D, typename T, typename O, bool MASK>
 __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ fin, Geo g, Par p,
-                                                  const uint8_t *__restrict__ act, const T *__restrict__ ustar,
-                                                  O *__restrict__ Vo, O *__restrict__ Fo, O *__restrict__ uo,
-                                                  O *__restrict__ Jo, int64_t ostride) {
+                                                  const uint8_t *__restrict__ act, const double *__restrict__ ustar,
+                                                  O *__restrict__ Vo, O *__restrict__ Fo, double *__restrict__ uo,
+                                                  O *__restrict__ Jo, int64_t ostride, const T *__restrict__ bf,
+                                                  T bs) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
-  moments_node<D, T, O, MASK>(fin, g, p, act, ustar, Vo, Fo, uo, Jo, ostride, x, (int)blockIdx.y);
+  moments_node<D, T, O, MASK>(fin, g, p, act, ustar, Vo, Fo, uo, Jo, ostride, x, (int)blockIdx.y, bf, bs);
 }
 
 // batched projection inputs: v, F into each instance's workspace, u = u* + dt/2 v
@@ -411,8 +423,8 @@ __global__ __launch_bounds__(256) void k_moments_batch(const Inst *__restrict__ 
   const Inst &I = insts[t.x];
   const int x = t.z + threadIdx.x;
   if (x >= I.g.nx) return;
-  moments_node<D, T, T, true>((const T *)I.fin, I.g, I.p, I.act, (const T *)I.ustar, (T *)I.V, (T *)I.Fm,
-                              (T *)I.ubuf, (T *)nullptr, I.g.S, x, t.y);
+  moments_node<D, T, T, true>((const T *)I.fin, I.g, I.p, I.act, (const double *)I.ustar, (T *)I.V, (T *)I.Fm,
+                              (double *)I.ubuf, (T *)nullptr, I.g.S, x, t.y);
 }
 
 // Second-order initialisation (Sec. 2.4, Eqs. 32-33) in FP64, stored
@@ -421,8 +433,8 @@ __global__ __launch_bounds__(256) void k_moments_batch(const Inst *__restrict__ 
 template <int D, typename T, bool MASK>
 __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p, const uint8_t *__restrict__ act,
                                                const double *__restrict__ U0, const double *__restrict__ u0,
-                                               const double *__restrict__ dU0, T *__restrict__ ustar,
-                                               int *__restrict__ flag) {
+                                               const double *__restrict__ dU0, double *__restrict__ ustar,
+                                               int *__restrict__ flag, const T *__restrict__ bf, double bs) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
@@ -444,9 +456,10 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
     atomicOr(flag, FLAG_J);
     return;
   }
-  // d_t U0 = B0 - Phi'_A(U0) d_A U0, B0 = (-gamma v0, 0)
+  // d_t U0 = B0 - Phi'_A(U0) d_A U0, B0 = (b0 - gamma v0, 0)
 #pragma unroll
-  for (int r = 0; r < M; ++r) Ut[r] = (r < D) ? -p.gamma * U[r] : 0.0;
+  for (int r = 0; r < M; ++r)
+    Ut[r] = (r < D) ? (bf ? bs * double(bf[(size_t)r * g.S + node]) : 0.0) - p.gamma * U[r] : 0.0;
 #pragma unroll
   for (int A = 0; A < D; ++A) {
     double dP[D * D];
@@ -491,13 +504,13 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
   if (ustar)
 #pragma unroll
     for (int i = 0; i < D; ++i)
-      ustar[(size_t)i * g.S + node] = T((u0 ? u0[(size_t)i * g.N + node] : 0.0) - 0.5 * p.dt * U[i]);
+      ustar[(size_t)i * g.S + node] = (u0 ? u0[(size_t)i * g.N + node] : 0.0) - 0.5 * p.dt * U[i];
 }
 
 // raw pre-collision populations f^n (unshifted) [Q][M][N] and u*^n [D][N]
 template <int D, typename T, bool MASK>
 __global__ __launch_bounds__(256) void k_get_f(const T *__restrict__ fin, Geo g, const uint8_t *__restrict__ act,
-                                                const T *__restrict__ ustar, double *__restrict__ fo,
+                                                const double *__restrict__ ustar, double *__restrict__ fo,
                                                 double *__restrict__ uso) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -518,13 +531,13 @@ __global__ __launch_bounds__(256) void k_get_f(const T *__restrict__ fin, Geo g,
       }
   }
   if (uso)
-    for (int i = 0; i < D; ++i) uso[(size_t)i * g.N + node] = (on && ustar) ? double(ustar[(size_t)i * g.S + node]) : 0.0;
+    for (int i = 0; i < D; ++i) uso[(size_t)i * g.N + node] = (on && ustar) ? ustar[(size_t)i * g.S + node] : 0.0;
 }
 
 template <int D, typename T, bool MASK>
 __global__ __launch_bounds__(256) void k_put_f(T *__restrict__ fout, Geo g, const uint8_t *__restrict__ act,
                                                 const double *__restrict__ fi, const double *__restrict__ usi,
-                                                T *__restrict__ ustar) {
+                                                double *__restrict__ ustar) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
@@ -549,7 +562,7 @@ __global__ __launch_bounds__(256) void k_put_f(T *__restrict__ fout, Geo g, cons
     }
   }
   if (ustar)
-    for (int i = 0; i < D; ++i) ustar[(size_t)i * g.S + node] = usi ? T(usi[(size_t)i * g.N + node]) : T(0);
+    for (int i = 0; i < D; ++i) ustar[(size_t)i * g.S + node] = usi ? usi[(size_t)i * g.N + node] : 0.0;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -560,50 +573,73 @@ static inline void grid_of(const Geo &g, dim3 &grid, dim3 &block) {
   grid = dim3((g.nx + bx - 1) / bx, g.ny * g.nz, 1);
 }
 
-template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair, void *tape) {
+// body acceleration scale s(t^n) of the current step (0 without a field)
+template <typename T> static T body_scale(const tlvlbm_ctx *c) {
+  if (!c->bf) return T(0);
+  double sv, dsv;
+  ramp_eval(c->bf_ramp, c->bf_Tr, c->step * c->par.dt, sv, dsv);
+  return T(sv);
+}
+
+template <int D, typename T, bool BODY> static void bulk_plain_t(tlvlbm_ctx *c, bool repair) {
   dim3 grid, block;
   grid_of(c->geo, grid, block);
   const T *fin = (const T *)c->fB;
   T *fout = (T *)c->fA;
-  T *us = (T *)c->ustar, *ub = (T *)c->ubuf;
+  double *us = (double *)c->ustar, *ub = (double *)c->ubuf;
   const T *Fr = (const T *)c->cg.Fr;
-  if (tape) {
-    T *tp = (T *)tape;
-    if (repair)
-      hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, true>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag, tp);
-    else if (c->act && c->track_u)
-      hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag, tp);
-    else if (c->act)
-      hipLaunchKernelGGL((k_bulk_tape<D, T, true, false, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag, tp);
-    else if (c->track_u)
-      hipLaunchKernelGGL((k_bulk_tape<D, T, false, true, false>), grid, block, 0, c->st, fin, fout, c->geo,
-                         c->par, c->act, us, ub, Fr, c->d_flag, tp);
-    else
-      hipLaunchKernelGGL((k_bulk_tape<D, T, false, false, false>), grid, block, 0, c->st, fin, fout, c->geo,
-                         c->par, c->act, us, ub, Fr, c->d_flag, tp);
-    return;
-  }
+  const T *bf = (const T *)c->bf;
+  const T bs = body_scale<T>(c);
   if (repair) {
-    hipLaunchKernelGGL((k_bulk<D, T, true, true, true>), grid, block, 0, c->st, fin, fout, c->geo, c->par, c->act,
-                       us, ub, Fr, c->d_flag);
+    hipLaunchKernelGGL((k_bulk<D, T, true, true, true, BODY>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                       c->act, us, ub, Fr, c->d_flag, bf, bs);
   } else if (c->act) {
     if (c->track_u)
-      hipLaunchKernelGGL((k_bulk<D, T, true, true, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag);
+      hipLaunchKernelGGL((k_bulk<D, T, true, true, false, BODY>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, bf, bs);
     else
-      hipLaunchKernelGGL((k_bulk<D, T, true, false, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag);
+      hipLaunchKernelGGL((k_bulk<D, T, true, false, false, BODY>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, bf, bs);
   } else {
     if (c->track_u)
-      hipLaunchKernelGGL((k_bulk<D, T, false, true, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag);
+      hipLaunchKernelGGL((k_bulk<D, T, false, true, false, BODY>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, bf, bs);
     else
-      hipLaunchKernelGGL((k_bulk<D, T, false, false, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag);
+      hipLaunchKernelGGL((k_bulk<D, T, false, false, false, BODY>), grid, block, 0, c->st, fin, fout, c->geo,
+                         c->par, c->act, us, ub, Fr, c->d_flag, bf, bs);
   }
+}
+
+template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair, void *tape) {
+  if (tape) {
+    // the reverse mode runs without a body acceleration (checked by the caller)
+    dim3 grid, block;
+    grid_of(c->geo, grid, block);
+    const T *fin = (const T *)c->fB;
+    T *fout = (T *)c->fA;
+    double *us = (double *)c->ustar, *ub = (double *)c->ubuf;
+    const T *Fr = (const T *)c->cg.Fr;
+    T *tp = (T *)tape;
+    const T *nb = nullptr;
+    if (repair)
+      hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, true>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+    else if (c->act && c->track_u)
+      hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+    else if (c->act)
+      hipLaunchKernelGGL((k_bulk_tape<D, T, true, false, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+    else if (c->track_u)
+      hipLaunchKernelGGL((k_bulk_tape<D, T, false, true, false>), grid, block, 0, c->st, fin, fout, c->geo,
+                         c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+    else
+      hipLaunchKernelGGL((k_bulk_tape<D, T, false, false, false>), grid, block, 0, c->st, fin, fout, c->geo,
+                         c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+    return;
+  }
+  if (c->bf) bulk_plain_t<D, T, true>(c, repair);
+  else bulk_plain_t<D, T, false>(c, repair);
 }
 
 void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape) {
@@ -620,24 +656,27 @@ template <int D, typename T>
 static void moments_t(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch) {
   dim3 grid, block;
   grid_of(c->geo, grid, block);
-  const T *us = c->track_u ? (const T *)c->ustar : nullptr;
+  const double *us = c->track_u ? (const double *)c->ustar : nullptr;
+  const T *bf = (const T *)c->bf;
+  const T bs = body_scale<T>(c);
   if (to_scratch) {
     // projection inputs: v, F into the CG workspace, u into the u buffer
     if (c->act)
       hipLaunchKernelGGL((k_moments<D, T, T, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act,
-                         us, (T *)c->cg.V, (T *)c->cg.Fm, (T *)c->ubuf, (T *)nullptr, (int64_t)c->geo.S);
+                         us, (T *)c->cg.V, (T *)c->cg.Fm, (double *)c->ubuf, (T *)nullptr, (int64_t)c->geo.S, bf, bs);
     else
       hipLaunchKernelGGL((k_moments<D, T, T, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par,
-                         c->act, us, (T *)c->cg.V, (T *)c->cg.Fm, (T *)c->ubuf, (T *)nullptr, (int64_t)c->geo.S);
+                         c->act, us, (T *)c->cg.V, (T *)c->cg.Fm, (double *)c->ubuf, (T *)nullptr, (int64_t)c->geo.S, bf,
+                         bs);
     return;
   }
   double *Vo = U, *Fo = U ? U + (size_t)D * c->geo.N : nullptr;
   if (c->act)
     hipLaunchKernelGGL((k_moments<D, T, double, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par,
-                       c->act, us, Vo, Fo, u, J, (int64_t)c->geo.N);
+                       c->act, us, Vo, Fo, u, J, (int64_t)c->geo.N, bf, bs);
   else
     hipLaunchKernelGGL((k_moments<D, T, double, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par,
-                       c->act, us, Vo, Fo, u, J, (int64_t)c->geo.N);
+                       c->act, us, Vo, Fo, u, J, (int64_t)c->geo.N, bf, bs);
 }
 
 void launch_pull_moments(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch) {
@@ -654,13 +693,13 @@ template <int D, typename T>
 static void init_t(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0) {
   dim3 grid, block;
   grid_of(c->geo, grid, block);
-  T *us = c->track_u ? (T *)c->ustar : nullptr;
+  double *us = c->track_u ? (double *)c->ustar : nullptr;
   if (c->act)
     hipLaunchKernelGGL((k_init<D, T, true>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->par, c->act, U0, u0, dU0,
-                       us, c->d_flag);
+                       us, c->d_flag, (const T *)c->bf, double(body_scale<T>(c)));
   else
     hipLaunchKernelGGL((k_init<D, T, false>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->par, c->act, U0, u0,
-                       dU0, us, c->d_flag);
+                       dU0, us, c->d_flag, (const T *)c->bf, double(body_scale<T>(c)));
 }
 
 void launch_init(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0) {
@@ -676,11 +715,28 @@ void launch_init(tlvlbm_ctx *c, const double *U0, const double *u0, const double
 template <int D, typename T> static void getf_t(tlvlbm_ctx *c, double *f, double *us) {
   dim3 grid, block;
   grid_of(c->geo, grid, block);
-  const T *ust = c->track_u ? (const T *)c->ustar : nullptr;
+  const double *ust = c->track_u ? (const double *)c->ustar : nullptr;
   if (c->act)
     hipLaunchKernelGGL((k_get_f<D, T, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->act, ust, f, us);
   else
     hipLaunchKernelGGL((k_get_f<D, T, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->act, ust, f, us);
+}
+
+// caller planes [k][N] (FP64) into context planes [k][S] (population precision)
+template <typename T>
+__global__ __launch_bounds__(256) void k_planes_in(const double *__restrict__ src, T *__restrict__ dst, int64_t N,
+                                                   int64_t S, int k) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N)
+    for (int c = 0; c < k; ++c) dst[(size_t)c * S + i] = T(src[(size_t)c * N + i]);
+}
+
+void launch_planes_in(tlvlbm_ctx *c, const double *src, void *dst, int k) {
+  const unsigned nb = (unsigned)((c->geo.N + 255) / 256);
+  if (c->prec)
+    hipLaunchKernelGGL((k_planes_in<double>), nb, 256, 0, c->st, src, (double *)dst, c->geo.N, c->geo.S, k);
+  else
+    hipLaunchKernelGGL((k_planes_in<float>), nb, 256, 0, c->st, src, (float *)dst, c->geo.N, c->geo.S, k);
 }
 
 void launch_get_f(tlvlbm_ctx *c, double *f, double *ustar) {
@@ -696,7 +752,7 @@ void launch_get_f(tlvlbm_ctx *c, double *f, double *ustar) {
 template <int D, typename T> static void putf_t(tlvlbm_ctx *c, const double *f, const double *us) {
   dim3 grid, block;
   grid_of(c->geo, grid, block);
-  T *ust = c->track_u ? (T *)c->ustar : nullptr;
+  double *ust = c->track_u ? (double *)c->ustar : nullptr;
   if (c->act)
     hipLaunchKernelGGL((k_put_f<D, T, true>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->act, f, us, ust);
   else

@@ -440,7 +440,7 @@ __device__ __forceinline__ void cut_dirichlet_link(T *__restrict__ f, const Link
 // velocity rows.
 template <int D, typename T>
 __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links &L, int64_t l, const BC &bc,
-                                                 const Geo &g, const Par &p, double th, const T *__restrict__ u,
+                                                 const Geo &g, const Par &p, double th, const double *__restrict__ u,
                                                  int *__restrict__ flag, unsigned long long *__restrict__ nfail) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int64_t m = L.node[l], mm = L.mminus[l], o = L.out[l];
@@ -464,7 +464,7 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
     for (int k = 0; k < np; ++k) {
       const double wk = w[al * L.kmax + k];
       const int64_t j = idx[k];
-      for (int i = 0; i < D; ++i) gv[i] += wk * double(u[(size_t)i * g.S + j]);
+      for (int i = 0; i < D; ++i) gv[i] += wk * u[(size_t)i * g.S + j];
     }
     for (int i = 0; i < D; ++i)
       for (int B = 0; B < D; ++B) Gt[i * D + B] += gv[i] * L.tang[l * 6 + al * 3 + B];
@@ -849,13 +849,13 @@ __device__ __forceinline__ void gradF_node(const Geo &g, const uint8_t *__restri
 // u = x, u* = x + dt/2 v  (advance = true) or x - dt/2 v
 template <int D, typename T>
 __device__ __forceinline__ void ureset_node(const Geo &g, const uint8_t *__restrict__ act, const double *__restrict__ x,
-                                            const T *__restrict__ V, T *__restrict__ u, T *__restrict__ us,
-                                            double hdt, int64_t i) {
+                                            const T *__restrict__ V, double *__restrict__ u,
+                                            double *__restrict__ us, double hdt, int64_t i) {
   if (i >= g.N || !act[i]) return;
   for (int c = 0; c < D; ++c) {
     const size_t o = (size_t)c * g.S;
-    u[o + i] = T(x[o + i]);
-    us[o + i] = T(x[o + i] + hdt * double(V[o + i]));
+    u[o + i] = x[o + i];
+    us[o + i] = x[o + i] + hdt * double(V[o + i]);
   }
 }
 
@@ -870,7 +870,7 @@ __global__ __launch_bounds__(256) void k_cut_dirichlet(T *__restrict__ f, Links 
 
 template <int D, typename T>
 __global__ __launch_bounds__(128) void k_cut_neumann(T *__restrict__ f, Links L, int64_t b0, int64_t b1, BC bc,
-                                                      Geo g, Par p, double th, const T *__restrict__ u,
+                                                      Geo g, Par p, double th, const double *__restrict__ u,
                                                       int *__restrict__ flag, unsigned long long *__restrict__ nfail) {
   const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (l < b1) cut_neumann_link<D, T>(f, L, l, bc, g, p, th, u, flag, nfail);
@@ -974,7 +974,7 @@ __global__ __launch_bounds__(256) void k_gradF(Geo g, const uint8_t *__restrict_
 
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_ureset(Geo g, const uint8_t *__restrict__ act, const double *__restrict__ x,
-                                                 const T *__restrict__ V, T *__restrict__ u, T *__restrict__ us,
+                                                 const T *__restrict__ V, double *__restrict__ u, double *__restrict__ us,
                                                  double hdt) {
   ureset_node<D, T>(g, act, x, V, u, us, hdt, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
 }
@@ -997,20 +997,12 @@ __global__ __launch_bounds__(CG_T) void k_copy_planes(Geo g, const double *__res
     for (int c = 0; c < D; ++c) dst[(size_t)c * g.S + i] = src[(size_t)c * g.S + i];
 }
 
-// copies between the displacement buffer (population precision) and the
-// FP64 CG iterate
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_u_to_x(Geo g, const T *__restrict__ u, double *__restrict__ x) {
+// copy of the displacement planes (FP64) into or out of the solver iterate
+template <int D>
+__global__ __launch_bounds__(256) void k_copy_u(Geo g, const double *__restrict__ src, double *__restrict__ dst) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < g.N)
-    for (int c = 0; c < D; ++c) x[(size_t)c * g.S + i] = double(u[(size_t)c * g.S + i]);
-}
-
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_x_to_u(Geo g, const double *__restrict__ x, T *__restrict__ u) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < g.N)
-    for (int c = 0; c < D; ++c) u[(size_t)c * g.S + i] = T(x[(size_t)c * g.S + i]);
+    for (int c = 0; c < D; ++c) dst[(size_t)c * g.S + i] = src[(size_t)c * g.S + i];
 }
 
 // default CG tolerance: 1e-14 for FP64 populations, 1e-8 for FP32 ones (the
@@ -1127,7 +1119,7 @@ template <int D, typename T> static void cutlinks_t(tlvlbm_ctx *c, double tn) {
                          c->geo, c->par, th);
     else
       hipLaunchKernelGGL((k_cut_neumann<D, T>), nblk(b1 - b0, 128), 128, 0, c->st, (T *)c->fA, c->L, b0, b1, bc,
-                         c->geo, c->par, th, (const T *)c->ubuf, c->d_flag,
+                         c->geo, c->par, th, (const double *)c->ubuf, c->d_flag,
                          (unsigned long long *)c->d_newton_fail);
   }
 }
@@ -1384,18 +1376,18 @@ static int projection_t(tlvlbm_ctx *c, bool first, double tn, double *store, int
   const Geo &g = c->geo;
   if (first) {
     launch_pull_moments(c, nullptr, nullptr, nullptr, true);  // v, F, u^n
-    hipLaunchKernelGGL((k_u_to_x<D, T>), nblk(g.N, 256), 256, 0, c->st, g, (const T *)c->ubuf, (double *)w.x);
+    hipLaunchKernelGGL((k_copy_u<D>), nblk(g.N, 256), 256, 0, c->st, g, (const double *)c->ubuf, (double *)w.x);
     st = solve_or_replay<D, T>(c, (const T *)w.Fm, tn, store, mode);
     if (st) return st;
-    hipLaunchKernelGGL((k_x_to_u<D, T>), nblk(g.N, 256), 256, 0, c->st, g, (const double *)w.x, (T *)c->ubuf);
+    hipLaunchKernelGGL((k_copy_u<D>), nblk(g.N, 256), 256, 0, c->st, g, (const double *)w.x, (double *)c->ubuf);
     hipLaunchKernelGGL((k_gradF<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const double *)w.x,
                        (const T *)w.Fm, (T *)w.Fr, c->theta);
   } else {
-    hipLaunchKernelGGL((k_u_to_x<D, T>), nblk(g.N, 256), 256, 0, c->st, g, (const T *)c->ubuf, (double *)w.x);
+    hipLaunchKernelGGL((k_copy_u<D>), nblk(g.N, 256), 256, 0, c->st, g, (const double *)c->ubuf, (double *)w.x);
     st = solve_or_replay<D, T>(c, (const T *)w.Fr, tn, store, mode);
     if (st) return st;
     hipLaunchKernelGGL((k_ureset<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const double *)w.x, (const T *)w.V,
-                       (T *)c->ubuf, (T *)c->ustar, 0.5 * c->par.dt);
+                       (double *)c->ubuf, (double *)c->ustar, 0.5 * c->par.dt);
   }
   HIP_OK(hipGetLastError());
   return TLVLBM_OK;
@@ -1437,7 +1429,7 @@ __global__ __launch_bounds__(64) void k_cut_batch(const Inst *__restrict__ insts
   if (sg.type == TLVLBM_BC_DIRICHLET_VELOCITY)
     cut_dirichlet_link<D, T>((T *)I.fout, I.L, l, sg.bc, I.g, I.p, th);
   else
-    cut_neumann_link<D, T>((T *)I.fout, I.L, l, sg.bc, I.g, I.p, th, (const T *)I.ubuf, I.flag, I.nfail);
+    cut_neumann_link<D, T>((T *)I.fout, I.L, l, sg.bc, I.g, I.p, th, (const double *)I.ubuf, I.flag, I.nfail);
 }
 
 template <int D, typename T>
@@ -1469,9 +1461,9 @@ __global__ __launch_bounds__(256) void k_node_util_batch(const Inst *__restrict_
   } else if (op == 1) {
     if (I.anc_n) I.anc_n[i] = (uint8_t)I.anc_i[i];
   } else if (op == 2) {
-    for (int c = 0; c < D; ++c) ((double *)I.x)[(size_t)c * I.g.S + i] = double(((const T *)I.ubuf)[(size_t)c * I.g.S + i]);
+    for (int c = 0; c < D; ++c) ((double *)I.x)[(size_t)c * I.g.S + i] = ((const double *)I.ubuf)[(size_t)c * I.g.S + i];
   } else {
-    for (int c = 0; c < D; ++c) ((T *)I.ubuf)[(size_t)c * I.g.S + i] = T(((const double *)I.x)[(size_t)c * I.g.S + i]);
+    for (int c = 0; c < D; ++c) ((double *)I.ubuf)[(size_t)c * I.g.S + i] = ((const double *)I.x)[(size_t)c * I.g.S + i];
   }
 }
 
@@ -1568,7 +1560,7 @@ __global__ __launch_bounds__(256) void k_ureset_batch(const Inst *__restrict__ i
                                                       const int4 *__restrict__ tiles) {
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
-  ureset_node<D, T>(I.g, I.act, (const double *)I.x, (const T *)I.V, (T *)I.ubuf, (T *)I.ustar, 0.5 * I.p.dt,
+  ureset_node<D, T>(I.g, I.act, (const double *)I.x, (const T *)I.V, (double *)I.ubuf, (double *)I.ustar, 0.5 * I.p.dt,
                     t.y * (int64_t)256 + threadIdx.x);
 }
 

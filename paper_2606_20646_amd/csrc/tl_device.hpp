@@ -46,7 +46,7 @@ __device__ __forceinline__ int64_t node_dir(const Geo &g, C3 c, int q, int mult)
 
 // ------------------------------------------------- boundary data (FP64)
 
-__device__ __forceinline__ void ramp_eval(int kind, double Tr, double t, double &s, double &ds) {
+__host__ __device__ __forceinline__ void ramp_eval(int kind, double Tr, double t, double &s, double &ds) {
   s = 1.0;
   ds = 0.0;
   if (t < Tr) {
@@ -65,7 +65,7 @@ __device__ __forceinline__ void ramp_eval(int kind, double Tr, double t, double 
 }
 
 // integral of the loading factor from 0 to t
-__device__ __forceinline__ double ramp_int(int kind, double Tr, double t) {
+__host__ __device__ __forceinline__ double ramp_int(int kind, double Tr, double t) {
   if (kind == TLVLBM_RAMP_CONST) return t;
   const double tc = t < Tr ? t : Tr;
   double S;

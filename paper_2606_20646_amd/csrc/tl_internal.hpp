@@ -130,7 +130,7 @@ struct Inst {
   double theta, rtol;
   void *fin, *fout;
   uint8_t *act;
-  void *ustar, *ubuf;
+  void *ustar, *ubuf;  // displacement history u*, u: FP64 in both builds
   Links L;
   // projection workspace
   void *x, *r, *p0, *p1, *Ap, *b, *V, *Fm, *Fr, *anc_s;
@@ -276,6 +276,13 @@ struct tlvlbm_ctx {
   hipStream_t st = nullptr;
   size_t esz = 4;
   void *fA = nullptr, *fB = nullptr;  // population planes (Q*M planes of stride S)
+  // body acceleration b(X, t) = s(t) g(X) (Eq. 5): g in D planes of the
+  // population precision (null: none), s a ramp
+  void *bf = nullptr;
+  int bf_ramp = 0;
+  double bf_Tr = 1.0;
+  // displacement history u* and u (Eq. 34): D FP64 planes each in both
+  // builds (a quadrature over thousands of steps; FP32 sums lose ~1e-5)
   void *ustar = nullptr, *ubuf = nullptr;
   uint8_t *act = nullptr;  // active mask (nullptr: all active)
   bool has_ls = false, have_state = false;
@@ -302,6 +309,7 @@ void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape = nullptr);
 void launch_pull_moments(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch);
 void launch_init(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0);
 void launch_get_f(tlvlbm_ctx *c, double *f, double *ustar);
+void launch_planes_in(tlvlbm_ctx *c, const double *src, void *dst, int k);
 void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar);
 // launchers (embed.hip)
 int build_links(tlvlbm_ctx *c, const double *phi_d, const uint8_t *bid_d, std::string &err);
@@ -323,7 +331,8 @@ void gauge_restore(tlvlbm_ctx *c, double *x, const double *mean0);
 // repaired F [D*D planes, projection steps], displacement seen by the cut
 // links [D planes]; any may be null
 struct TapeStep {
-  void *U, *Fr, *u;
+  void *U, *Fr;   // recovered (v, F - I) and repaired F, population precision
+  void *u;        // displacement seen by the cut links, FP64
   double *xs[2];  // projection solutions of the step (see run_projection)
   int xmode;
 };

@@ -77,6 +77,7 @@ def _load():
     L.tlvlbm_set_levelset.argtypes = [vp, dp, dp]
     L.tlvlbm_set_boundary.argtypes = [vp, C.c_uint8, C.POINTER(BC)]
     L.tlvlbm_set_material.argtypes = [vp, C.POINTER(Material)]
+    L.tlvlbm_set_body_force.argtypes = [vp, C.c_void_p, C.c_int32, C.c_double]
     L.tlvlbm_set_state.argtypes = [vp, dp, dp, dp]
     L.tlvlbm_step.argtypes = [vp, C.c_int64]
     L.tlvlbm_moments.argtypes = [vp, dp, dp, dp]
@@ -190,6 +191,13 @@ class Solver:
         for k, v in enumerate(X0 if X0 is not None else []):
             b.X0[k] = v
         self._chk(lib.tlvlbm_set_boundary(self.h, int(bid), C.byref(b)), "set_boundary")
+
+    def set_body_force(self, g, ramp="const", T_r=1.0):
+        """Body acceleration b(X, t) = s(t) g(X); g [D][N] numpy or device
+        tensor (None removes it)."""
+        arr = g if (g is None or not isinstance(g, np.ndarray)) else np.ascontiguousarray(g, np.float64)
+        p, keep = _ptr(arr)
+        self._chk(lib.tlvlbm_set_body_force(self.h, p, RAMPS.get(ramp, ramp), float(T_r)), "set_body_force")
 
     def set_material(self, mu, lam):
         self._chk(lib.tlvlbm_set_material(self.h, C.byref(Material(0, mu, lam))), "set_material")

@@ -88,18 +88,22 @@ def rel_l2(a, b, scale=None):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(s)))
 
 
-def ellipsoid_errors(c, U, u, J, t):
-    """Errors of an affine Dirichlet run (Sec. 5.1, Eqs. 80-82) at time t
-    over the active nodes: u against t A (X - Xc), v against A (X - Xc),
-    F against I + t A; the Jacobian range."""
+def affine_errors(c, U, u, J, t):
+    """Errors of an affine velocity Dirichlet run (the annulus of Sec. 4.2,
+    Eqs. 64-68, or the ellipsoid of Sec. 5.1, Eqs. 80-82) at time t over the
+    active nodes: u against t A (X - Xc), v against A (X - Xc), F against
+    I + t A; the Jacobian range and the exact J."""
+    D = c["D"]
     act = c["phi"] <= 0
     d = c["X"][:, act] - c["Xc"][:, None]
     A = c["A"]
-    Fex = np.eye(3) + t * A
-    F = U[3:12, act].T.reshape(-1, 3, 3)
-    return {"E_u": rel_l2(u[:, act], t * (A @ d)), "E_v": rel_l2(U[:3, act], A @ d),
+    Fex = np.eye(D) + t * A
+    F = U[D:D + D * D, act].T.reshape(-1, D, D)
+    Fb = np.broadcast_to(Fex, F.shape)
+    sig, sig_ex = cauchy_nh(F, c["mu"], c["lam"]), cauchy_nh(np.ascontiguousarray(Fb), c["mu"], c["lam"])
+    return {"E_u": rel_l2(u[:, act], t * (A @ d)), "E_v": rel_l2(U[:D, act], A @ d), "E_sigma": rel_l2(sig, sig_ex),
             "E_F": rel_l2(F, np.broadcast_to(Fex, F.shape)),
-            "E_F_minus_I": rel_l2(F, np.broadcast_to(Fex, F.shape), np.broadcast_to(Fex - np.eye(3), F.shape)),
+            "E_F_minus_I": rel_l2(F, np.broadcast_to(Fex, F.shape), np.broadcast_to(Fex - np.eye(D), F.shape)),
             "J_range": [float(J[act].min()), float(J[act].max())], "J_exact": float(np.linalg.det(Fex))}
 
 
@@ -118,3 +122,68 @@ def radial_errors(c, ref, U, u, J):
             "E_F_minus_I": rel_l2(F, F_ref, F_ref - np.eye(D)), "E_sigma": rel_l2(s, s_ref),
             "v_rms": float(np.sqrt((v * v).sum(0).mean())),
             "J_range": [float(J[act].min()), float(J[act].max())]}
+
+
+def piola_nh(F, mu, lam):
+    """Nominal stress P = dW/dF of the compressible neo-Hookean energy
+    (Sec. 4.1, Eq. 62), for F of shape [n, D, D]."""
+    J = np.linalg.det(F)
+    Fit = np.transpose(np.linalg.inv(F), (0, 2, 1))
+    return mu * (F - Fit) + 0.5 * lam * (J * J - 1.0)[:, None, None] * Fit
+
+
+class PlaneWaveMMS:
+    """Manufactured finite-strain plane wave on a periodic box (body
+    acceleration of Sec. 2.1, Eq. 5):
+
+        u(X, t) = a cos(Omega t) sin(2 pi xi) p,   xi = k . X,
+
+    k an integer wave vector, p a unit polarisation (not orthogonal to k, so
+    J varies).  Then v = du/dt, F = I + a cos(Omega t) 2 pi cos(2 pi xi)
+    p (x) k, and the body acceleration that makes u an exact solution is
+    b = dv/dt - Div P(F), with Div P = (dP/dxi) k evaluated by Richardson
+    central differences of P in xi (P depends on X through xi only)."""
+
+    def __init__(self, D, k, p, a, Omega, mu, lam):
+        self.D, self.k, self.a, self.Om, self.mu, self.lam = D, np.asarray(k, float), a, Omega, mu, lam
+        p = np.asarray(p, float)
+        self.p = p / np.linalg.norm(p)
+
+    def _F(self, xi, t):
+        g = self.a * np.cos(self.Om * t) * 2 * np.pi * np.cos(2 * np.pi * xi)
+        return np.eye(self.D)[None] + g[:, None, None] * np.einsum("i,j->ij", self.p, self.k)[None]
+
+    def fields(self, X, t):
+        """U = (v, F row-major) [M][n] and u [D][n] at time t."""
+        xi = self.k @ X
+        s = np.sin(2 * np.pi * xi)
+        u = self.a * np.cos(self.Om * t) * s * self.p[:, None]
+        v = -self.a * self.Om * np.sin(self.Om * t) * s * self.p[:, None]
+        F = self._F(xi, t)
+        return np.vstack([v, F.reshape(-1, self.D * self.D).T]), u
+
+    def gradients(self, X, t):
+        """dU/dX_A [D][M][n] at time t (analytic)."""
+        D, M = self.D, self.D + self.D * self.D
+        xi = self.k @ X
+        c, s = np.cos(2 * np.pi * xi), np.sin(2 * np.pi * xi)
+        out = np.zeros((D, M, X.shape[1]))
+        dv = -self.a * self.Om * np.sin(self.Om * t) * 2 * np.pi * c       # d v / d xi (per p)
+        dF = -self.a * np.cos(self.Om * t) * (2 * np.pi) ** 2 * s           # d g / d xi
+        pk = np.einsum("i,j->ij", self.p, self.k).reshape(-1)
+        for A in range(D):
+            out[A, :D] = dv * self.k[A] * self.p[:, None]
+            out[A, D:] = dF * self.k[A] * pk[:, None]
+        return out
+
+    def body(self, X, t, h=1e-4):
+        xi = self.k @ X
+        s = np.sin(2 * np.pi * xi)
+        dvdt = -self.a * self.Om ** 2 * np.cos(self.Om * t) * s * self.p[:, None]
+
+        def dP(hh):
+            return (piola_nh(self._F(xi + hh, t), self.mu, self.lam)
+                    - piola_nh(self._F(xi - hh, t), self.mu, self.lam)) / (2 * hh)
+        dPdxi = (4 * dP(h / 2) - dP(h)) / 3
+        divP = np.einsum("nij,j->in", dPdxi, self.k)
+        return dvdt - divP

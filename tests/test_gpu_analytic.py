@@ -103,7 +103,7 @@ def test_rotated_ellipsoid_within_paper_accuracy(env, precision):
     c = W.config_ellipsoid(64)
     _say(f"rotated ellipsoid 64^3 {precision} {c['steps']} steps")
     U, u, J, st, t = _run(T, stream, c, precision)
-    e = refsol.ellipsoid_errors(c, U, u, J, t)
+    e = refsol.affine_errors(c, U, u, J, t)
     print(e, flush=True)
     scale = (320 / 64) ** 2
     assert e["E_u"] <= 3.70e-6 * scale
@@ -117,7 +117,7 @@ def test_rotated_ellipsoid_exact_without_fallback_links(env):
     c = W.config_ellipsoid(32)
     _say(f"rotated ellipsoid 32^3 fp64 {c['steps']} steps (no fallback links)")
     U, u, J, st, t = _run(T, stream, c, "fp64")
-    e = refsol.ellipsoid_errors(c, U, u, J, t)
+    e = refsol.affine_errors(c, U, u, J, t)
     print(e, flush=True)
     assert e["E_u"] < 1e-12 and e["E_v"] < 1e-12 and e["E_F"] < 1e-12
 
@@ -140,3 +140,20 @@ def test_rotated_ellipsoid_matches_oracle(env, orc):
     act = c["phi"] <= 0
     assert np.linalg.norm(Ug[:, act] - Uo[:, act]) <= 1e-12 * np.linalg.norm(Uo[:, act])
     assert np.linalg.norm(ug[:, act] - uo[:, act]) <= 1e-12 * np.linalg.norm(uo[:, act])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 4.55e-6)])
+def test_affine_annulus_full_size(env, precision, tol):
+    """Affine Dirichlet annulus at the paper's N = 384 (Sec. 4.2, omega = 2,
+    T = 0.2): the paper reports E(u) = 4.55e-6, E(F - I) = 8.51e-5,
+    E(sigma) = 5.16e-5.  The affine mode is exactly representable: the FP64
+    run reproduces it to round-off, the FP32 run within the paper's E(u)."""
+    T, stream = env
+    c = W.config_affine_annulus(384)
+    _say(f"affine annulus 384^2 {precision} {c['steps']} steps")
+    U, u, J, st, t = _run(T, stream, c, precision)
+    e = refsol.affine_errors(c, U, u, J, t)
+    print(e, st, flush=True)
+    assert st["active_nodes"] == 66692  # the paper: 66692 active nodes, 1840 cut links
+    assert e["E_u"] <= tol and e["E_F_minus_I"] <= max(tol, 1e-12) * 20 and e["E_sigma"] <= 5.16e-5
+    assert abs(e["J_exact"] - 1.692) < 5e-4

@@ -416,11 +416,11 @@ def test_ellipsoid_affine_mode_exact(orc):
     the wall data half a cell from the cut point) it does not."""
     c = W.config_ellipsoid(32)
     _, U, u, J, t = _run_oracle(orc, c)
-    e = refsol.ellipsoid_errors(c, U, u, J, t)
+    e = refsol.affine_errors(c, U, u, J, t)
     assert e["E_u"] < 1e-12 and e["E_v"] < 1e-12 and e["E_F"] < 1e-12, e
     c = W.config_ellipsoid(30)
     _, U, u, J, t = _run_oracle(orc, c)
-    e = refsol.ellipsoid_errors(c, U, u, J, t)
+    e = refsol.affine_errors(c, U, u, J, t)
     assert e["E_u"] > 1e-6, e
 
 
@@ -438,3 +438,26 @@ def test_radial_traction_annulus_accuracy(orc):
     assert o.stats()["newton_fail"] == 0
     assert e["E_u"] <= 6 * 3.86e-4 and e["E_F"] <= 6 * 9.18e-4 and e["E_F_minus_I"] <= 6 * 3.84e-3, e
     assert 1.581 - 0.005 <= e["J_range"][0] and e["J_range"][1] <= 1.639 + 0.005, e
+
+
+def test_affine_annulus_exact_and_printed_stress(orc):
+    """Affine Dirichlet annulus (Sec. 4.2, Eqs. 63-68) at N = 96, omega = 2,
+    run to T = 0.2: u, v and F reproduce the affine solution to round-off,
+    and the recovered Cauchy stress (Eq. 35) equals the printed terminal
+    stress (Eq. 68, MPa = 10 x the nondimensional value) to one unit of its
+    last printed digit (the exact value of the first entry is 8.722545)."""
+    c = W.config_affine_annulus(96)
+    o, U, u, J, t = _run_oracle(orc, c)
+    assert abs(t - 0.2) < 1e-12
+    e = refsol.affine_errors(c, U, u, J, t)
+    assert e["E_u"] < 1e-12 and e["E_v"] < 1e-12 and e["E_F"] < 1e-12, e
+    act = c["phi"] <= 0
+    F = U[2:6, act].T.reshape(-1, 2, 2)
+    sig = 10.0 * refsol.cauchy_nh(F, c["mu"], c["lam"])
+    gold = {}
+    for line in open(os.path.join(GOLD, "affine_annulus_terminal_state.txt")):
+        line = line.split("#")[0].split()
+        if line:
+            gold[line[0]] = [float(v) for v in line[1:]]
+    assert np.abs(sig - np.array(gold["sigma"]).reshape(2, 2)).max() < 1e-4
+    assert np.abs(J[act] - gold["J"][0]).max() < 5e-4

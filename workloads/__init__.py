@@ -355,3 +355,28 @@ def config_radial_annulus(N=196):
                 U0=U0, T=5.0, steps=int(round(5.0 / dt)), Xc=np.array([0.5, 0.5]),
                 bcs={1: dict(type="dirichlet"),
                      2: dict(type="neumann", ramp="sin2", T_r=2.0, p_radial=1.0, X0=(0.5, 0.5))})
+
+
+def config_affine_annulus(N=384):
+    """Affine Dirichlet annulus (Sec. 4.2): R_i = 0.18 <= R <= R_o = 0.42
+    about (0.5, 0.5); both surfaces carry the velocity v = A (X - Xc) / T,
+    T = 0.2, A = [[0.35, 0.18], [-0.10, 0.24]], which is also the initial
+    velocity (u0 = 0, F0 = I); mu = 1, lambda = 2/3, omega = 2, no damping,
+    no projection (Dirichlet only)."""
+    g = geom_affine_annulus(N)
+    X = g["X"]
+    A = np.array([[0.35, 0.18], [-0.10, 0.24]])
+    T = 0.2
+    Xc = np.array([0.5, 0.5])
+    G = A / T
+    U0 = np.zeros((6, X.shape[1]))
+    U0[:2] = G @ (X - Xc[:, None])
+    U0[2] = U0[5] = 1.0
+    dU0 = np.zeros((2, 6, X.shape[1]))
+    for B in range(2):
+        for i in range(2):
+            dU0[B, i] = G[i, B]
+    dt = g["dx"] / 10.0
+    return dict(g, D=2, A=G, Xc=Xc, mu=1.0, lam=2.0 / 3.0, rho0=1.0, c=10.0, dt=dt, omega=2.0, gamma=0.0,
+                proj_every=20, U0=U0, dU0=dU0, T=T, steps=int(round(T / dt)),
+                bcs={1: dict(type="dirichlet", G=G, X0=(0.5, 0.5)), 2: dict(type="dirichlet", G=G, X0=(0.5, 0.5))})

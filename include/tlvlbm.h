@@ -74,12 +74,18 @@ typedef struct {
   uint32_t periodic_mask;
 } tlvlbm_grid;
 
-/* Material law.  law 0: compressible neo-Hookean,
- * W = mu/2 (|F|^2 - D) - (mu + lambda/2) ln J + lambda/4 (J^2 - 1)
- * (Sec. 4.1, Eq. 62); P = dW/dF (Sec. 2.1, Eq. 4). */
+/* Material law; P = dW/dF (Sec. 2.1, Eq. 4).
+ * law 0: compressible neo-Hookean (Sec. 4.1, Eq. 62),
+ *   W = mu/2 (|F|^2 - D) - (mu + lambda/2) ln J + lambda/4 (J^2 - 1).
+ * law 1: the same solid reinforced by one family of fibres along the unit
+ *   reference direction a0 (an anisotropic law as the outlook of Sec. 6
+ *   names): W += k1/2 (|F a0|^2 - 1)^2, k1 >= 0; a0 is normalised.
+ * k1 and a0 are read for law 1 only. */
 typedef struct {
   int32_t law;
   double mu, lambda;
+  double k1;
+  double a0[3];
 } tlvlbm_material;
 
 /* Run options (tlvlbm_default_options fills the paper's settings of

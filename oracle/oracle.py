@@ -43,6 +43,8 @@ def lib():
         dp, ip, i64p = C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)
         L.orc_piola.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_piola_jvp.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp]
+        L.orc_piola_law.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp, dp]
+        L.orc_piola_law_jvp.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp]
         L.orc_cauchy.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_energy.argtypes = [C.c_int, C.c_double, C.c_double, dp]
         L.orc_energy.restype = C.c_double
@@ -57,6 +59,7 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_projection.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_set_body_force.argtypes = [C.c_void_p, dp, C.c_int, C.c_double]
+        L.orc_set_fibres.argtypes = [C.c_void_p, C.c_double, dp]
         L.orc_set_levelset.argtypes = [C.c_void_p, dp, C.POINTER(C.c_uint8)]
         L.orc_set_bc.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp, dp,
                                  C.c_double, C.c_double, dp]
@@ -115,6 +118,29 @@ def piola_jvp(F, dF, mu, lam):
     D = F.shape[0]
     dP = np.zeros((D, D))
     lib().orc_piola_jvp(D, mu, lam, _d(F), _d(dF), _d(dP))
+    return dP
+
+
+def piola_law(F, mu, lam, k1, a0):
+    """P of the fibre-reinforced neo-Hookean law (a0 a unit vector)."""
+    F = _f64(F)
+    D = F.shape[0]
+    a = _f64(list(a0) + [0.0] * (3 - len(a0)))
+    P = np.zeros((D, D))
+    st = lib().orc_piola_law(D, mu, lam, k1, _d(a), _d(F), _d(P))
+    if st:
+        raise OracleError(st, "piola_law")
+    return P
+
+
+def piola_law_jvp(F, dF, mu, lam, k1, a0):
+    F, dF = _f64(F), _f64(dF)
+    D = F.shape[0]
+    a = _f64(list(a0) + [0.0] * (3 - len(a0)))
+    dP = np.zeros((D, D))
+    st = lib().orc_piola_law_jvp(D, mu, lam, k1, _d(a), _d(F), _d(dF), _d(dP))
+    if st:
+        raise OracleError(st, "piola_law_jvp")
     return dP
 
 
@@ -217,6 +243,13 @@ class Sim:
                               p_radial, p_normal, _d(X03))
         if st:
             raise OracleError(st, "set_bc")
+
+    def set_fibres(self, k1, a0):
+        """Fibre-reinforced law: W += k1/2 (|F a0|^2 - 1)^2 (k1 = 0: off)."""
+        a = _f64(list(a0) + [0.0] * (3 - len(a0)))
+        st = lib().orc_set_fibres(self.h, float(k1), _d(a))
+        if st:
+            raise OracleError(st, "set_fibres")
 
     def set_body_force(self, g, ramp=RAMP_CONST, T_r=1.0):
         """Body acceleration b(X, t) = s(t) g(X), g [D][N] (None clears)."""

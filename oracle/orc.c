@@ -145,6 +145,65 @@ int orc_piola_jvp(int D, double mu, double lam, const double *F, const double *d
   return ORC_OK;
 }
 
+/* Material of a simulation: the neo-Hookean solid of Eq. 62, optionally
+ * reinforced by one family of fibres along the unit reference direction a0
+ * (the anisotropic law the paper's outlook names, Sec. 6):
+ *   W = W_NH(F) + (k1/2) (I4 - 1)^2,  I4 = |F a0|^2,
+ *   P = P_NH + 2 k1 (I4 - 1) (F a0) (x) a0,
+ *   dP = dP_NH + 2 k1 [2 ((F a0).(dF a0)) (F a0) (x) a0 + (I4 - 1) (dF a0) (x) a0].
+ * k1 = 0 is the paper's law. */
+typedef struct {
+  double mu, lam, k1, a0[3];
+} orc_mat;
+
+static orc_mat nh_mat(double mu, double lam) {
+  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}};
+  return m;
+}
+
+static int mat_piola(int D, const orc_mat *m, const double *F, double *P) {
+  int st = orc_piola(D, m->mu, m->lam, F, P);
+  if (st || m->k1 == 0.0) return st;
+  double fa[3] = {0.0, 0.0, 0.0}, I4 = 0.0;
+  for (int i = 0; i < D; ++i) {
+    for (int A = 0; A < D; ++A) fa[i] += F[i * D + A] * m->a0[A];
+    I4 += fa[i] * fa[i];
+  }
+  for (int i = 0; i < D; ++i)
+    for (int A = 0; A < D; ++A) P[i * D + A] += 2.0 * m->k1 * (I4 - 1.0) * fa[i] * m->a0[A];
+  return ORC_OK;
+}
+
+static int mat_piola_jvp(int D, const orc_mat *m, const double *F, const double *dF, double *dP) {
+  int st = orc_piola_jvp(D, m->mu, m->lam, F, dF, dP);
+  if (st || m->k1 == 0.0) return st;
+  double fa[3] = {0.0, 0.0, 0.0}, dfa[3] = {0.0, 0.0, 0.0}, I4 = 0.0, dI = 0.0;
+  for (int i = 0; i < D; ++i) {
+    for (int A = 0; A < D; ++A) {
+      fa[i] += F[i * D + A] * m->a0[A];
+      dfa[i] += dF[i * D + A] * m->a0[A];
+    }
+    I4 += fa[i] * fa[i];
+    dI += fa[i] * dfa[i];
+  }
+  for (int i = 0; i < D; ++i)
+    for (int A = 0; A < D; ++A)
+      dP[i * D + A] += 2.0 * m->k1 * (2.0 * dI * fa[i] + (I4 - 1.0) * dfa[i]) * m->a0[A];
+  return ORC_OK;
+}
+
+/* exported forms of the material maps (law with fibres) */
+int orc_piola_law(int D, double mu, double lam, double k1, const double *a0, const double *F, double *P) {
+  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}};
+  return mat_piola(D, &m, F, P);
+}
+
+int orc_piola_law_jvp(int D, double mu, double lam, double k1, const double *a0, const double *F,
+                      const double *dF, double *dP) {
+  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}};
+  return mat_piola_jvp(D, &m, F, dF, dP);
+}
+
 /* Cauchy stress sigma = J^{-1} P F^T (Sec. 2.4, Eq. 35). */
 int orc_cauchy(int D, double mu, double lam, const double *F, double *sigma) {
   double P[9];
@@ -162,10 +221,10 @@ int orc_cauchy(int D, double mu, double lam, const double *F, double *sigma) {
 
 /* Fluxes Phi_A(U) (Sec. 2.2, Eq. 13): Phi_A^{v_i} = -P_iA / rho0,
  * Phi_A^{F_iB} = -delta_AB v_i.  Layout Phi[A*M + r]. */
-void orc_flux(int D, double mu, double lam, double rho0, const double *U, double *Phi) {
+static void flux_m(int D, const orc_mat *m, double rho0, const double *U, double *Phi) {
   int M = D + D * D;
   double P[9];
-  orc_piola(D, mu, lam, U + D, P);
+  mat_piola(D, m, U + D, P);
   for (int A = 0; A < D; ++A)
     for (int r = 0; r < M; ++r) {
       double val;
@@ -181,11 +240,10 @@ void orc_flux(int D, double mu, double lam, double rho0, const double *U, double
 
 /* Equilibrium populations (Sec. 2.3, Eq. 24):
  * feq_q = (1/2D) [ U + (D/c) e_qA Phi_A(U) ].  Layout feq[q*M + r]. */
-void orc_feq(int D, double c, double mu, double lam, double rho0, const double *U,
-             double *feq) {
+static void feq_m(int D, double c, const orc_mat *m, double rho0, const double *U, double *feq) {
   int M = D + D * D, Q = 2 * D;
   double Phi[MAXD * MAXM];
-  orc_flux(D, mu, lam, rho0, U, Phi);
+  flux_m(D, m, rho0, U, Phi);
   for (int q = 0; q < Q; ++q)
     for (int r = 0; r < M; ++r) {
       double s = 0.0;
@@ -195,11 +253,10 @@ void orc_feq(int D, double c, double mu, double lam, double rho0, const double *
 }
 
 /* Flux Jacobian action (Sec. 2.2, Eq. 18) */
-static void flux_jvp(int D, double mu, double lam, double rho0, const double *U,
-                     const double *Z, double *dPhi) {
+static void flux_jvp(int D, const orc_mat *m, double rho0, const double *U, const double *Z, double *dPhi) {
   int M = D + D * D;
   double dP[9];
-  orc_piola_jvp(D, mu, lam, U + D, Z + D, dP);
+  mat_piola_jvp(D, m, U + D, Z + D, dP);
   for (int A = 0; A < D; ++A)
     for (int r = 0; r < M; ++r) {
       double val;
@@ -214,17 +271,34 @@ static void flux_jvp(int D, double mu, double lam, double rho0, const double *U,
 }
 
 /* Equilibrium derivative (Sec. 2.3, Eq. 27). */
-void orc_feq_jvp(int D, double c, double mu, double lam, double rho0, const double *U,
-                 const double *Z, double *dfeq) {
+static void feq_jvp_m(int D, double c, const orc_mat *m, double rho0, const double *U, const double *Z,
+                      double *dfeq) {
   int M = D + D * D, Q = 2 * D;
   double dPhi[MAXD * MAXM];
-  flux_jvp(D, mu, lam, rho0, U, Z, dPhi);
+  flux_jvp(D, m, rho0, U, Z, dPhi);
   for (int q = 0; q < Q; ++q)
     for (int r = 0; r < M; ++r) {
       double s = 0.0;
       for (int A = 0; A < D; ++A) s += e_of(q, A) * dPhi[A * M + r];
       dfeq[q * M + r] = (Z[r] + (double)D / c * s) / (2.0 * D);
     }
+}
+
+/* exported forms for the neo-Hookean law */
+void orc_flux(int D, double mu, double lam, double rho0, const double *U, double *Phi) {
+  orc_mat m = nh_mat(mu, lam);
+  flux_m(D, &m, rho0, U, Phi);
+}
+
+void orc_feq(int D, double c, double mu, double lam, double rho0, const double *U, double *feq) {
+  orc_mat m = nh_mat(mu, lam);
+  feq_m(D, c, &m, rho0, U, feq);
+}
+
+void orc_feq_jvp(int D, double c, double mu, double lam, double rho0, const double *U, const double *Z,
+                 double *dfeq) {
+  orc_mat m = nh_mat(mu, lam);
+  feq_jvp_m(D, c, &m, rho0, U, Z, dfeq);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -322,12 +396,12 @@ static void build_Fb(int D, const double *h, const double *N, const double *Gt, 
 }
 
 /* R(h) = P(F_b(h)) N - T (Eqs. 54, 56); returns 0 if det F_b <= 0 */
-static int newton_residual(int D, double mu, double lam, const double *N, const double *Gt,
-                           const double *T, const double *h, double *R) {
+static int newton_residual(int D, const orc_mat *m, const double *N, const double *Gt, const double *T,
+                           const double *h, double *R) {
   double F[9], P[9];
   build_Fb(D, h, N, Gt, F);
   if (!(det_n(D, F) > 0.0)) return 0;
-  orc_piola(D, mu, lam, F, P);
+  mat_piola(D, m, F, P);
   for (int i = 0; i < D; ++i) {
     double s = 0.0;
     for (int A = 0; A < D; ++A) s += P[i * D + A] * N[A];
@@ -343,13 +417,13 @@ static int newton_residual(int D, double mu, double lam, const double *N, const 
  * evaluated with the tangent action; the paper's finite-difference Jacobian
  * reaches the same root.  Trial states are accepted only with det F_b > 0
  * and a decreasing residual (halving, at most 10 times). */
-int orc_newton(int D, double mu, double lam, const double *N, const double *Gt,
-               const double *T, const double *h0, double tol, double *h, int *iters) {
+static int newton_m(int D, const orc_mat *m, const double *N, const double *Gt, const double *T,
+                    const double *h0, double tol, double *h, int *iters) {
   double R[3], Rt[3], ht[3], Qm[9], dh[3], F[9];
   for (int i = 0; i < D; ++i) h[i] = h0[i];
   if (iters) *iters = 0;
-  if (!newton_residual(D, mu, lam, N, Gt, T, h, R)) return 0;
-  double thr = tol * (mu > 1.0 ? mu : 1.0);
+  if (!newton_residual(D, m, N, Gt, T, h, R)) return 0;
+  double thr = tol * (m->mu > 1.0 ? m->mu : 1.0);
   for (int it = 0; it <= 30; ++it) {
     double rinf = 0.0, r2 = 0.0;
     for (int i = 0; i < D; ++i) {
@@ -364,7 +438,7 @@ int orc_newton(int D, double mu, double lam, const double *N, const double *Gt,
       double dF[9], dP[9];
       for (int i = 0; i < D; ++i)
         for (int A = 0; A < D; ++A) dF[i * D + A] = (i == k ? 1.0 : 0.0) * N[A];
-      orc_piola_jvp(D, mu, lam, F, dF, dP);
+      mat_piola_jvp(D, m, F, dF, dP);
       for (int i = 0; i < D; ++i) {
         double s = 0.0;
         for (int A = 0; A < D; ++A) s += dP[i * D + A] * N[A];
@@ -378,7 +452,7 @@ int orc_newton(int D, double mu, double lam, const double *N, const double *Gt,
     int accepted = 0;
     for (int ls = 0; ls <= 10; ++ls) {
       for (int i = 0; i < D; ++i) ht[i] = h[i] + step * dh[i];
-      if (newton_residual(D, mu, lam, N, Gt, T, ht, Rt)) {
+      if (newton_residual(D, m, N, Gt, T, ht, Rt)) {
         double rt2 = 0.0, rtinf = 0.0;
         for (int i = 0; i < D; ++i) {
           rt2 += Rt[i] * Rt[i];
@@ -398,6 +472,12 @@ int orc_newton(int D, double mu, double lam, const double *N, const double *Gt,
     }
   }
   return 0;
+}
+
+int orc_newton(int D, double mu, double lam, const double *N, const double *Gt, const double *T,
+               const double *h0, double tol, double *h, int *iters) {
+  orc_mat m = nh_mat(mu, lam);
+  return newton_m(D, &m, N, Gt, T, h0, tol, h, iters);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -424,6 +504,7 @@ struct orc_sim {
   int64_t N;
   double dx, org[3];
   double mu, lam, rho0, dt, c, omega, gamma, theta;
+  double k1, a0[3]; /* fibre reinforcement (k1 = 0: the paper's law) */
   int proj_every;
   int proj_sweeps;    /* > 0: damped Jacobi sweeps per projection solve; 0: exact minimiser */
   double proj_weight; /* Jacobi damping weight */
@@ -715,6 +796,15 @@ int orc_set_levelset(orc_sim *s, const double *phi, const uint8_t *bid) {
   return ORC_OK;
 }
 
+int orc_set_fibres(orc_sim *s, double k1, const double *a0) {
+  double n = 0.0;
+  for (int A = 0; A < s->D; ++A) n += a0[A] * a0[A];
+  if (!(k1 >= 0.0) || (k1 > 0.0 && !(n > 0.0))) return ORC_ERR_ARG;
+  s->k1 = k1;
+  for (int A = 0; A < 3; ++A) s->a0[A] = (A < s->D && n > 0.0) ? a0[A] / sqrt(n) : 0.0;
+  return ORC_OK;
+}
+
 int orc_set_body_force(orc_sim *s, const double *g, int ramp, double T_r) {
   free(s->bf);
   s->bf = NULL;
@@ -820,6 +910,12 @@ static void bc_displacement(const orc_bc *b, int D, const double *X, const doubl
   for (int i = 0; i < D; ++i) val[i] *= fac;
 }
 
+/* material of the simulation with the given (mu, lambda) */
+static orc_mat sim_mat(const orc_sim *s, double mu, double lam) {
+  orc_mat m = {mu, lam, s->k1, {s->a0[0], s->a0[1], s->a0[2]}};
+  return m;
+}
+
 /* body acceleration at node i and time t (zero without a field) */
 static void body_acc(const orc_sim *s, int64_t i, double t, double *b) {
   for (int a = 0; a < s->D; ++a) b[a] = 0.0;
@@ -839,13 +935,14 @@ static void init_node(const orc_sim *s, double mu, double lam, const double *U, 
                       const double *b0, double *f) {
   int D = s->D, M = s->M, Q = s->Q;
   double Ut[MAXM], feq[MAXQ * MAXM], dPhi[MAXD * MAXM];
+  const orc_mat mat = sim_mat(s, mu, lam);
   /* B0 = (b0 - gamma v0, 0): body acceleration and velocity damping */
   for (int r = 0; r < M; ++r) Ut[r] = (r < D) ? b0[r] - s->gamma * U[r] : 0.0;
   for (int A = 0; A < D; ++A) {
-    flux_jvp(D, mu, lam, s->rho0, U, dA + A * M, dPhi);
+    flux_jvp(D, &mat, s->rho0, U, dA + A * M, dPhi);
     for (int r = 0; r < M; ++r) Ut[r] -= dPhi[A * M + r];
   }
-  orc_feq(D, s->c, mu, lam, s->rho0, U, feq);
+  feq_m(D, s->c, &mat, s->rho0, U, feq);
   for (int q = 0; q < Q; ++q) {
     double Z[MAXM], dfeq[MAXQ * MAXM];
     for (int r = 0; r < M; ++r) {
@@ -853,7 +950,7 @@ static void init_node(const orc_sim *s, double mu, double lam, const double *U, 
       for (int A = 0; A < D; ++A) s2 += s->c * e_of(q, A) * dA[A * M + r];
       Z[r] = s2;
     }
-    orc_feq_jvp(D, s->c, mu, lam, s->rho0, U, Z, dfeq);
+    feq_jvp_m(D, s->c, &mat, s->rho0, U, Z, dfeq);
     for (int r = 0; r < M; ++r) f[q * M + r] = feq[q * M + r] - 0.5 * s->dt * dfeq[q * M + r];
   }
 }
@@ -1195,7 +1292,8 @@ static int neumann_Fb(orc_sim *s, const orc_link *L, double th, int count, doubl
     h0[i] = acc;
   }
   int its = 0;
-  int conv = orc_newton(D, s->mu, s->lam, L->N, Gt, T, h0, 1e-12, h, &its);
+  const orc_mat mat = sim_mat(s, s->mu, s->lam);
+  int conv = newton_m(D, &mat, L->N, Gt, T, h0, 1e-12, h, &its);
   if (count) {
 #pragma omp atomic
     s->st_newton_it += its;
@@ -1238,7 +1336,8 @@ static int close_link(orc_sim *s, const orc_link *L, double tn) {
   } else if (b->type == ORC_BC_NEUMANN) {
     double Gt[9], Fb[9], Pb[9];
     ok = neumann_Fb(s, L, th, 1, Gt, Fb);
-    orc_piola(D, s->mu, s->lam, Fb, Pb);
+    const orc_mat mat = sim_mat(s, s->mu, s->lam);
+    mat_piola(D, &mat, Fb, Pb);
     /* Eqs. 46-47: D_N = diag(I_D, -I_D2), S^v_i = -d_A P_b,iA / c,
      * S^F_iB = F_b,iB / D ; the density divides the stress flux */
     for (int r = 0; r < M; ++r) {
@@ -1292,8 +1391,9 @@ static void project_pre(orc_sim *s, double tn) {
     for (int r = 0; r < M; ++r) Ur[r] = U[r];
     for (int k = 0; k < D * D; ++k)
       Ur[D + k] = (1.0 - s->theta) * U[D + k] + s->theta * Fc[(size_t)m * D * D + k];
-    orc_feq(D, s->c, s->mu, s->lam, s->rho0, U, fe0);
-    orc_feq(D, s->c, s->mu, s->lam, s->rho0, Ur, fe1);
+    const orc_mat mat = sim_mat(s, s->mu, s->lam);
+    feq_m(D, s->c, &mat, s->rho0, U, fe0);
+    feq_m(D, s->c, &mat, s->rho0, Ur, fe1);
     double *f = s->f + (size_t)m * Q * M;
     for (int k = 0; k < Q * M; ++k) f[k] += fe1[k] - fe0[k]; /* Eq. 61 */
     for (int r = 0; r < M; ++r) U[r] = Ur[r];
@@ -1329,7 +1429,8 @@ int orc_step(orc_sim *s, int64_t nsteps) {
       if (!s->act[m]) continue;
       const double *U = s->U + (size_t)m * M;
       double feq[MAXQ * MAXM], B[MAXM], b[MAXD];
-      orc_feq(D, s->c, s->mu, s->lam, s->rho0, U, feq);
+      const orc_mat mat = sim_mat(s, s->mu, s->lam);
+      feq_m(D, s->c, &mat, s->rho0, U, feq);
       body_acc(s, m, tn, b);
       for (int r = 0; r < M; ++r) B[r] = (r < D) ? b[r] - s->gamma * U[r] : 0.0;
       const double *f = s->f + (size_t)m * Q * M;
@@ -1538,7 +1639,8 @@ static void feq_vjp(const orc_sim *s, double mu, double lam, const double *U, co
   for (int r = 0; r < M; ++r) {
     double e[MAXM] = {0}, d[MAXQ * MAXM], acc = 0.0;
     e[r] = 1.0;
-    orc_feq_jvp(s->D, s->c, mu, lam, s->rho0, U, e, d);
+    const orc_mat mat = sim_mat(s, mu, lam);
+    feq_jvp_m(s->D, s->c, &mat, s->rho0, U, e, d);
     for (int k = 0; k < Q * M; ++k) acc += lq[k] * d[k];
     out[r] = acc;
   }
@@ -1560,17 +1662,18 @@ static void feq_dp(const orc_sim *s, const double *U, const double *lq, double *
 }
 
 /* W : dP/dF as a matrix: out_kB = sum_iA W_iA dP_iA/dF_kB */
-static void piola_vjp(int D, double mu, double lam, const double *F, const double *W, double *out) {
+static void piola_vjp(int D, const orc_mat *m, const double *F, const double *W, double *out) {
   for (int k = 0; k < D * D; ++k) {
     double E[9] = {0}, dP[9], acc = 0.0;
     E[k] = 1.0;
-    orc_piola_jvp(D, mu, lam, F, E, dP);
+    mat_piola_jvp(D, m, F, E, dP);
     for (int j = 0; j < D * D; ++j) acc += W[j] * dP[j];
     out[k] = acc;
   }
 }
 
-/* W : dP/d(mu, lambda), exact unit central difference */
+/* W : dP/d(mu, lambda), exact unit central difference (the fibre term does
+ * not depend on mu, lambda) */
 static void piola_dp(int D, double mu, double lam, const double *F, const double *W, double *g) {
   double a[9], b[9], gm = 0.0, gl = 0.0;
   orc_piola(D, mu + 1.0, lam, F, a);
@@ -1779,7 +1882,8 @@ static void neumann_adj(orc_sim *s, const orc_link *L, double th, const double *
   /* S^v_i = -sum_B d_B P_iB / (rho0 c), S^F_iB = F_b,iB / D */
   for (int i = 0; i < D; ++i)
     for (int B = 0; B < D; ++B) W[i * D + B] = -Sbar[i] * d[B] / (s->rho0 * s->c);
-  piola_vjp(D, s->mu, s->lam, Fb, W, Fbb);
+  const orc_mat mat = sim_mat(s, s->mu, s->lam);
+  piola_vjp(D, &mat, Fb, W, Fbb);
   for (int k = 0; k < D * D; ++k) Fbb[k] += Sbar[D + k] / D;
   piola_dp(D, s->mu, s->lam, Fb, W, gmat);
   /* F_b = h (x) N + Gt : h_bar = Fb_bar N, Gt_bar = Fb_bar */
@@ -1794,7 +1898,7 @@ static void neumann_adj(orc_sim *s, const orc_link *L, double th, const double *
     double dF[9], dP[9];
     for (int i = 0; i < D; ++i)
       for (int A = 0; A < D; ++A) dF[i * D + A] = (i == k ? 1.0 : 0.0) * L->N[A];
-    orc_piola_jvp(D, s->mu, s->lam, Fb, dF, dP);
+    mat_piola_jvp(D, &mat, Fb, dF, dP);
     for (int i = 0; i < D; ++i) {
       double acc = 0.0;
       for (int A = 0; A < D; ++A) acc += dP[i * D + A] * L->N[A];
@@ -1805,7 +1909,7 @@ static void neumann_adj(orc_sim *s, const orc_link *L, double th, const double *
   double zN[9], gz[2] = {0.0, 0.0};
   for (int i = 0; i < D; ++i)
     for (int A = 0; A < D; ++A) zN[i * D + A] = z[i] * L->N[A];
-  piola_vjp(D, s->mu, s->lam, Fb, zN, Gtb);
+  piola_vjp(D, &mat, Fb, zN, Gtb);
   for (int k = 0; k < D * D; ++k) Gtb[k] = Fbb[k] - Gtb[k];
   piola_dp(D, s->mu, s->lam, Fb, zN, gz);
   gmat[0] -= gz[0];

@@ -40,6 +40,11 @@ enum { ORC_RAMP_CONST = 0, ORC_RAMP_SIN2 = 1, ORC_RAMP_HALFCOS = 2,
 int  orc_piola(int D, double mu, double lam, const double *F, double *P);
 int  orc_piola_jvp(int D, double mu, double lam, const double *F,
                    const double *dF, double *dP);
+/* the same maps for the fibre-reinforced law W += k1/2 (|F a0|^2 - 1)^2
+ * (a0 used as given: pass a unit vector) */
+int  orc_piola_law(int D, double mu, double lam, double k1, const double *a0, const double *F, double *P);
+int  orc_piola_law_jvp(int D, double mu, double lam, double k1, const double *a0, const double *F,
+                       const double *dF, double *dP);
 int  orc_cauchy(int D, double mu, double lam, const double *F, double *sigma);
 double orc_energy(int D, double mu, double lam, const double *F);
 /* fluxes Phi[A][M] (Eq. 13) and equilibria feq[q][M] (Eq. 24) */
@@ -83,6 +88,9 @@ int  orc_set_projection(orc_sim *s, int sweeps, double weight);
  * (Eqs. 28-33); g [D][N] planar (copied) or NULL to clear; s(t) a ramp of
  * kind `ramp` and time T_r, evaluated at t^n for step n. */
 int  orc_set_body_force(orc_sim *s, const double *g, int ramp, double T_r);
+/* fibre reinforcement W += k1/2 (|F a0|^2 - 1)^2 along the reference
+ * direction a0 (normalised; k1 = 0 restores the neo-Hookean law) */
+int  orc_set_fibres(orc_sim *s, double k1, const double *a0);
 /* phi[N] node samples (phi <= 0 inside, Eq. 36); bid[N] boundary ids. */
 int  orc_set_levelset(orc_sim *s, const double *phi, const uint8_t *bid);
 /* boundary value s(t) (a + G (X - X0) + p_radial e_R + p_normal N_b) */

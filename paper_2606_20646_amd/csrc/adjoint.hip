@@ -41,6 +41,7 @@ constexpr int AT = 256;
 
 struct AdjPar {
   double om, sig, inv_damp, hdt, i2D, i2c, irho, mu, lam, gamma, c, dt, theta, dx;
+  double k1, a0[3];  // fibre term of the material (k1 = 0: none)
 };
 
 // node X - e_q (periodic wrap; for an embedded body the neighbour exists)
@@ -114,7 +115,8 @@ __device__ __forceinline__ void feq_vjp(const double (&lam)[2 * D][D + D * D], c
   }
   double CW[D * D], Pm[D * D], Pl[D * D];
   piola_tangent<D>(F, W, p.mu, p.lam, CW);
-  piola<D>(F, 1.0, 0.0, Pm);  // dP/dmu = F - F^{-T}
+  if (p.k1 != 0.0) fibre_tangent_add<D>(F, W, p.k1, p.a0, CW);
+  piola<D>(F, 1.0, 0.0, Pm);  // dP/dmu = F - F^{-T} (the fibre term has no mu, lambda)
   piola<D>(F, 0.0, 1.0, Pl);  // dP/dlambda = (J^2 - 1)/2 F^{-T}
   const double cf = -a * p.i2c * p.irho;
   double sm = 0.0, sl = 0.0;
@@ -361,18 +363,21 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
     }
     for (int k = 0; k < D * D; ++k) Gt[k] = 0.0;
     const int np = L.npts[l];
-    const int32_t *idx = L.sidx + l * L.kmax;
-    const double *w = L.sw + l * 2 * L.kmax;
-    for (int al = 0; al < D - 1; ++al) {
-      double gv[D];
-      for (int i = 0; i < D; ++i) gv[i] = L.tang[l * 6 + al * 3 + i];
-      for (int k = 0; k < np; ++k) {
-        const double wk = w[al * L.kmax + k];
-        for (int i = 0; i < D; ++i) gv[i] += wk * double(tapeu[(size_t)i * g.S + idx[k]]);
+    double gv[D - 1][D];
+    for (int al = 0; al < D - 1; ++al)
+      for (int i = 0; i < D; ++i) gv[al][i] = L.tang[l * 6 + al * 3 + i];
+    for (int k = 0; k < np; ++k) {
+      const int64_t j = L.sidx[lsq_i(L, l, k)];
+      double uk[D];
+      for (int i = 0; i < D; ++i) uk[i] = tapeu[(size_t)i * g.S + j];
+      for (int al = 0; al < D - 1; ++al) {
+        const double wk = L.sw[lsq_w(L, l, al, k)];
+        for (int i = 0; i < D; ++i) gv[al][i] += wk * uk[i];
       }
-      for (int i = 0; i < D; ++i)
-        for (int B = 0; B < D; ++B) Gt[i * D + B] += gv[i] * L.tang[l * 6 + al * 3 + B];
     }
+    for (int al = 0; al < D - 1; ++al)
+      for (int i = 0; i < D; ++i)
+        for (int B = 0; B < D; ++B) Gt[i * D + B] += gv[al][i] * L.tang[l * 6 + al * 3 + B];
     double s, ds;
     ramp_eval(bc.ramp, bc.Tr, th, s, ds);
     bc_base<D>(bc, Xb, N, Tb);
@@ -387,7 +392,7 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
       for (int B = 0; B < D; ++B) acc += Fm[i * D + B] * N[B];
       h[i] = acc;
     }
-    newton_h<D>(N, Gt, Tb, par.mu, par.lam, 1e-12, h);
+    newton_h<D>(N, Gt, Tb, par, 1e-12, h);
     double Fb[D * D];
     for (int i = 0; i < D; ++i)
       for (int B = 0; B < D; ++B) Fb[i * D + B] = h[i] * N[B] + Gt[i * D + B];
@@ -396,7 +401,7 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
     double W[D * D], CW[D * D], Fbb[D * D], Pm[D * D], Pl[D * D];
     for (int i = 0; i < D; ++i)
       for (int B = 0; B < D; ++B) W[i * D + B] = (B == A) ? sg * cS * lg[i] * par.inv_rho0 / par.c : 0.0;
-    piola_tangent<D>(Fb, W, par.mu, par.lam, CW);
+    mat_tangent<D>(Fb, W, par, CW);
     piola<D>(Fb, 1.0, 0.0, Pm);
     piola<D>(Fb, 0.0, 1.0, Pl);
     double gm = 0.0, gl = 0.0;
@@ -418,7 +423,7 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
       double dF[D * D], dP[D * D];
       for (int i = 0; i < D; ++i)
         for (int a = 0; a < D; ++a) dF[i * D + a] = (i == k) ? N[a] : 0.0;
-      piola_tangent<D>(Fb, dF, par.mu, par.lam, dP);
+      mat_tangent<D>(Fb, dF, par, dP);
       for (int i = 0; i < D; ++i) {
         double acc = 0.0;
         for (int a = 0; a < D; ++a) acc += dP[i * D + a] * N[a];
@@ -430,7 +435,7 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
     double zN[D * D], CzN[D * D];
     for (int i = 0; i < D; ++i)
       for (int a = 0; a < D; ++a) zN[i * D + a] = z[i] * N[a];
-    piola_tangent<D>(Fb, zN, par.mu, par.lam, CzN);
+    mat_tangent<D>(Fb, zN, par, CzN);
     for (int k = 0; k < D * D; ++k) {
       gm -= zN[k] * Pm[k];
       gl -= zN[k] * Pl[k];
@@ -461,7 +466,7 @@ __global__ __launch_bounds__(AT) void k_adj_ugather(int64_t ns, const int64_t *_
     const int64_t l = el[e];
     const int k = ek[e];
     for (int al = 0; al < D - 1; ++al) {
-      const double wk = L.sw[l * 2 * L.kmax + al * L.kmax + k];
+      const double wk = L.sw[lsq_w(L, l, al, k)];
       for (int i = 0; i < D; ++i) acc[i] += wk * gbar[l * 6 + al * 3 + i];
     }
   }
@@ -912,7 +917,7 @@ int stencil_transpose(tlvlbm_ctx *c) {
   std::vector<int64_t> cnt(N + 1, 0);
   for (int64_t l = 0; l < nl; ++l)
     if (is_neu[l])
-      for (int k = 0; k < lnp[l]; ++k) cnt[sidx[(size_t)l * c->L.kmax + k] + 1]++;
+      for (int k = 0; k < lnp[l]; ++k) cnt[sidx[lsq_i(c->L, l, k)] + 1]++;
   std::vector<int64_t> sn, so;
   for (int64_t j = 0; j < N; ++j)
     if (cnt[j + 1]) sn.push_back(j);
@@ -923,7 +928,7 @@ int stencil_transpose(tlvlbm_ctx *c) {
   for (int64_t l = 0; l < nl; ++l)
     if (is_neu[l])
       for (int k = 0; k < lnp[l]; ++k) {
-        const int64_t e = pos[sidx[(size_t)l * c->L.kmax + k]]++;
+        const int64_t e = pos[sidx[lsq_i(c->L, l, k)]]++;
         el[e] = (int32_t)l;
         ek[e] = k;
       }
@@ -972,7 +977,9 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
                 pp.c,
                 pp.dt,
                 c->theta,
-                g.dx};
+                g.dx,
+                pp.k1,
+                {pp.a0[0], pp.a0[1], pp.a0[2]}};
   grid_of(g, R.grid, R.block);
   R.nblk = (size_t)R.grid.x * R.grid.y;
   for (int b = 0; b < 256; ++b) {

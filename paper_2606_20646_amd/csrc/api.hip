@@ -1,9 +1,11 @@
 // C ABI of the tlvlbm runtime: context lifetime, host/device argument
 // marshalling, call-order checks and the step loop of Algorithm 1.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <utility>
+#include <vector>
 
 #include "tl_internal.hpp"
 
@@ -72,6 +74,25 @@ bool has_neumann(const tlvlbm_ctx *c) {
 
 namespace tl {
 
+// law 0: neo-Hookean; law 1: with fibres (k1 >= 0, a0 not zero)
+static bool material_ok(const tlvlbm_material *m) {
+  if (!m || (m->law != 0 && m->law != 1)) return false;
+  if (m->law == 1) {
+    const double n = m->a0[0] * m->a0[0] + m->a0[1] * m->a0[1] + m->a0[2] * m->a0[2];
+    if (!(m->k1 >= 0) || !(n > 0)) return false;
+  }
+  return true;
+}
+
+static void set_material_par(Par &p, const tlvlbm_material *m, int D) {
+  p.mu = m->mu;
+  p.lam = m->lambda;
+  p.k1 = m->law == 1 ? m->k1 : 0.0;
+  double n = 0.0;
+  for (int a = 0; a < D; ++a) n += m->a0[a] * m->a0[a];
+  for (int a = 0; a < 3; ++a) p.a0[a] = (m->law == 1 && a < D) ? m->a0[a] / std::sqrt(n) : 0.0;
+}
+
 tlvlbm_status check_flag(tlvlbm_ctx *c) { return read_flag(c); }
 
 bool is_projection_step(const tlvlbm_ctx *c, int64_t step) {
@@ -132,7 +153,7 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   if (!out) return TLVLBM_ERR_INVALID_ARG;
   *out = nullptr;
   if (!grid || !mat || (lattice != TLVLBM_D2Q4x6 && lattice != TLVLBM_D3Q6x12)) return TLVLBM_ERR_INVALID_ARG;
-  if (!(rho0 > 0) || !(dt > 0) || !(grid->dx > 0) || mat->law != 0) return TLVLBM_ERR_INVALID_ARG;
+  if (!(rho0 > 0) || !(dt > 0) || !(grid->dx > 0) || !material_ok(mat)) return TLVLBM_ERR_INVALID_ARG;
   tlvlbm_options o;
   tlvlbm_default_options(&o);
   if (opt) o = *opt;
@@ -168,8 +189,7 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   c->geo.ox = grid->origin[0];
   c->geo.oy = grid->origin[1];
   c->geo.oz = D == 3 ? grid->origin[2] : 0.0;
-  c->par.mu = mat->mu;
-  c->par.lam = mat->lambda;
+  set_material_par(c->par, mat, D);
   c->par.inv_rho0 = 1.0 / rho0;
   c->par.dt = dt;
   c->par.c = grid->dx / dt;
@@ -213,7 +233,7 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
                   c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles,
-                  c->bf};
+                  c->bf, c->chunks};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
@@ -249,6 +269,22 @@ tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *c, const double *phi, const uint8_
     CHK(hipStreamSynchronize(c->st), "synchronize");
     (void)hipFree(cnt);
     c->nactive = (int64_t)na;
+    {
+      // 64-node chunks holding active nodes, in node order
+      std::vector<uint8_t> act(N);
+      CHK(hipMemcpy(act.data(), c->act, N, hipMemcpyDeviceToHost), "mask read");
+      std::vector<int32_t> ch;
+      for (int64_t k = 0; k * 64 < N; ++k) {
+        bool any = false;
+        for (int64_t i = k * 64; i < std::min<int64_t>(N, k * 64 + 64) && !any; ++i) any = act[i] != 0;
+        if (any) ch.push_back((int32_t)k);
+      }
+      if (!ch.empty()) {
+        CHK(hipMalloc(&c->chunks, ch.size() * sizeof(int32_t)), "chunk alloc");
+        CHK(hipMemcpy(c->chunks, ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice), "chunk upload");
+      }
+      c->nchunks = (int)ch.size();
+    }
     c->has_ls = true;
     c->have_state = false;
     if (c->track_opt == -1) c->track_u = true;
@@ -310,9 +346,8 @@ tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *c, const double *g, int32_t ramp
 }
 
 tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *c, const tlvlbm_material *m) {
-  if (!c || !m || m->law != 0) return TLVLBM_ERR_INVALID_ARG;
-  c->par.mu = m->mu;
-  c->par.lam = m->lambda;
+  if (!c || !material_ok(m)) return TLVLBM_ERR_INVALID_ARG;
+  set_material_par(c->par, m, c->D);
   return TLVLBM_OK;
 }
 

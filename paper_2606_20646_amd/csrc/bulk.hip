@@ -92,7 +92,7 @@ template <typename T> __device__ __forceinline__ bool finite_(T v) { return __bu
 // collision with source + displacement quadrature (Algorithm 1, bulk loops).
 // TAPE: also store the recovered (pre-repair) state (v, F - I) to the tape
 // planes for the reverse mode.
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool TAPE = false, bool BODY = false>
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool TAPE = false, bool EXT = false>
 __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restrict__ fout, const Geo &g,
                                           const Par &p, const uint8_t *__restrict__ act, double *__restrict__ ustar,
                                           double *__restrict__ ubuf, const T *__restrict__ Frp,
@@ -121,13 +121,16 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
   T bacc[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) bacc[i] = BODY ? bs * bf[(size_t)i * g.S + node] : T(0);
+  for (int i = 0; i < D; ++i) bacc[i] = (EXT && bf) ? bs * bf[(size_t)i * g.S + node] : T(0);
   T v[D], F[D * D], P[D * D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) v[i] = (BODY ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
+  for (int i = 0; i < D; ++i) v[i] = (EXT ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
 #pragma unroll
   for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
   T J = piola<D>(F, mu, lam, P);
+  if constexpr (EXT) {
+    if (p.k1 != 0.0) fibre_add<D>(F, T(p.k1), p.a0, P);
+  }
   bool bad = !(J > T(0));
   if constexpr (TAPE) {
 #pragma unroll
@@ -144,6 +147,9 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
 #pragma unroll
     for (int k = 0; k < D * D; ++k) Fr[k] = Frp[(size_t)k * g.S + node];
     const T J1 = piola<D>(Fr, mu, lam, P1);
+    if constexpr (EXT) {
+      if (p.k1 != 0.0) fibre_add<D>(Fr, T(p.k1), p.a0, P1);
+    }
     bad |= !(J1 > T(0));
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -185,7 +191,7 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
       }
       const T feq = base * inv2D + sg * inv2c * phi;
       T out = f[q][r] + om * (feq - f[q][r]);
-      if (r < D) out += srcw * (BODY ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
+      if (r < D) out += srcw * (EXT ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
     }
   }
@@ -215,7 +221,7 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
 // device function above, the compiler schedules its address arithmetic
 // differently and the kernel runs 2.6% slower at 256^3 (measured).  The two
 // bodies are kept identical (a CPU test compares them).
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool BODY = false>
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool EXT = false>
 __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
                                                const uint8_t *__restrict__ act, double *__restrict__ ustar,
                                                double *__restrict__ ubuf, const T *__restrict__ Frp,
@@ -246,13 +252,16 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
   T bacc[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) bacc[i] = BODY ? bs * bf[(size_t)i * g.S + node] : T(0);
+  for (int i = 0; i < D; ++i) bacc[i] = (EXT && bf) ? bs * bf[(size_t)i * g.S + node] : T(0);
   T v[D], F[D * D], P[D * D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) v[i] = (BODY ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
+  for (int i = 0; i < D; ++i) v[i] = (EXT ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
 #pragma unroll
   for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
   T J = piola<D>(F, mu, lam, P);
+  if constexpr (EXT) {
+    if (p.k1 != 0.0) fibre_add<D>(F, T(p.k1), p.a0, P);
+  }
   bool bad = !(J > T(0));
   const T inv2c = T(0.5) / T(p.c);
   const T inv2D = T(1) / T(2 * D);
@@ -263,6 +272,9 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
 #pragma unroll
     for (int k = 0; k < D * D; ++k) Fr[k] = Frp[(size_t)k * g.S + node];
     const T J1 = piola<D>(Fr, mu, lam, P1);
+    if constexpr (EXT) {
+      if (p.k1 != 0.0) fibre_add<D>(Fr, T(p.k1), p.a0, P1);
+    }
     bad |= !(J1 > T(0));
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -304,7 +316,7 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
       }
       const T feq = base * inv2D + sg * inv2c * phi;
       T out = f[q][r] + om * (feq - f[q][r]);
-      if (r < D) out += srcw * (BODY ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
+      if (r < D) out += srcw * (EXT ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
     }
   }
@@ -331,7 +343,7 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
 }
 
 // the same update recording the recovered state on the reverse-mode tape
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool BODY = false>
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool EXT = false>
 __global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
                                                    const uint8_t *__restrict__ act, double *__restrict__ ustar,
                                                    double *__restrict__ ubuf, const T *__restrict__ Frp,
@@ -339,8 +351,28 @@ __global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T 
                                                    const T *__restrict__ bf, T bs) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
-  bulk_node<D, T, MASK, TRACK, REPAIR, true, BODY>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x,
+  bulk_node<D, T, MASK, TRACK, REPAIR, true, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x,
                                                    (int)blockIdx.y, tape, bf, bs);
+}
+
+// Embedded bodies: the same update over the list of 64-node chunks (of the
+// node order) that hold active nodes, one wavefront per chunk; inactive
+// nodes of a chunk return at once (MASK).
+template <int D, typename T, bool TRACK, bool REPAIR, bool EXT>
+__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks(const T *__restrict__ fin, T *__restrict__ fout,
+                                                                    Geo g, Par p, const uint8_t *__restrict__ act,
+                                                                    double *__restrict__ ustar,
+                                                                    double *__restrict__ ubuf,
+                                                                    const T *__restrict__ Frp, int *__restrict__ flag,
+                                                                    const T *__restrict__ bf, T bs,
+                                                                    const int32_t *__restrict__ chunks, int nchunks) {
+  const int ch = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (ch >= nchunks) return;
+  const int64_t i = (int64_t)chunks[ch] * 64 + (threadIdx.x & 63);
+  if (i >= g.N) return;
+  const int x = (int)(i % g.nx), row = (int)(i / g.nx);
+  bulk_node<D, T, true, TRACK, REPAIR, false, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, nullptr,
+                                                    bf, bs);
 }
 
 // Batched bulk update: one block per tile (instance, row, first x) of the
@@ -451,7 +483,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
     for (int r = 0; r < M; ++r) dA[A][r] = dU0 ? dU0[((size_t)A * M + r) * g.N + node] : 0.0;
   const double *F = U + D;
   double P[D * D];
-  const double J = piola<D>(F, p.mu, p.lam, P);
+  const double J = mat_piola<D>(F, p, P);
   if (!(J > 0.0)) {
     atomicOr(flag, FLAG_J);
     return;
@@ -463,7 +495,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
 #pragma unroll
   for (int A = 0; A < D; ++A) {
     double dP[D * D];
-    piola_tangent<D>(F, dA[A] + D, p.mu, p.lam, dP);
+    mat_tangent<D>(F, dA[A] + D, p, dP);
 #pragma unroll
     for (int i = 0; i < D; ++i) Ut[i] += dP[i * D + A] * p.inv_rho0;  // -(-dP)
 #pragma unroll
@@ -477,7 +509,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
     double Z[M], dP[D * D];
 #pragma unroll
     for (int r = 0; r < M; ++r) Z[r] = Ut[r] + c * sg * dA[A][r];
-    piola_tangent<D>(F, Z + D, p.mu, p.lam, dP);
+    mat_tangent<D>(F, Z + D, p, dP);
     int xs = x, ys = y, zs = z;  // X - e_q
     if (A == 0) xs = (x - (int)sg + g.nx) % g.nx;
     if (A == 1) ys = (y - (int)sg + g.ny) % g.ny;
@@ -581,7 +613,7 @@ template <typename T> static T body_scale(const tlvlbm_ctx *c) {
   return T(sv);
 }
 
-template <int D, typename T, bool BODY> static void bulk_plain_t(tlvlbm_ctx *c, bool repair) {
+template <int D, typename T, bool EXT> static void bulk_plain_t(tlvlbm_ctx *c, bool repair) {
   dim3 grid, block;
   grid_of(c->geo, grid, block);
   const T *fin = (const T *)c->fB;
@@ -590,55 +622,77 @@ template <int D, typename T, bool BODY> static void bulk_plain_t(tlvlbm_ctx *c, 
   const T *Fr = (const T *)c->cg.Fr;
   const T *bf = (const T *)c->bf;
   const T bs = body_scale<T>(c);
+  if (c->act && c->chunks) {
+    // embedded body: only the chunks holding active nodes
+    const unsigned nb = (unsigned)((c->nchunks + 3) / 4);
+    if (repair)
+      hipLaunchKernelGGL((k_bulk_chunks<D, T, true, true, EXT>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, bf, bs, c->chunks, c->nchunks);
+    else if (c->track_u)
+      hipLaunchKernelGGL((k_bulk_chunks<D, T, true, false, EXT>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, bf, bs, c->chunks, c->nchunks);
+    else
+      hipLaunchKernelGGL((k_bulk_chunks<D, T, false, false, EXT>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
+                         c->act, us, ub, Fr, c->d_flag, bf, bs, c->chunks, c->nchunks);
+    return;
+  }
   if (repair) {
-    hipLaunchKernelGGL((k_bulk<D, T, true, true, true, BODY>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+    hipLaunchKernelGGL((k_bulk<D, T, true, true, true, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                        c->act, us, ub, Fr, c->d_flag, bf, bs);
   } else if (c->act) {
     if (c->track_u)
-      hipLaunchKernelGGL((k_bulk<D, T, true, true, false, BODY>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+      hipLaunchKernelGGL((k_bulk<D, T, true, true, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs);
     else
-      hipLaunchKernelGGL((k_bulk<D, T, true, false, false, BODY>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+      hipLaunchKernelGGL((k_bulk<D, T, true, false, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs);
   } else {
     if (c->track_u)
-      hipLaunchKernelGGL((k_bulk<D, T, false, true, false, BODY>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+      hipLaunchKernelGGL((k_bulk<D, T, false, true, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs);
     else
-      hipLaunchKernelGGL((k_bulk<D, T, false, false, false, BODY>), grid, block, 0, c->st, fin, fout, c->geo,
+      hipLaunchKernelGGL((k_bulk<D, T, false, false, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo,
                          c->par, c->act, us, ub, Fr, c->d_flag, bf, bs);
   }
 }
 
+// the forward of the reverse mode (no body acceleration: refused there; the
+// fibre law in the EXT instantiation)
+template <int D, typename T, bool EXT> static void bulk_tape_t(tlvlbm_ctx *c, bool repair, void *tape) {
+  dim3 grid, block;
+  grid_of(c->geo, grid, block);
+  const T *fin = (const T *)c->fB;
+  T *fout = (T *)c->fA;
+  double *us = (double *)c->ustar, *ub = (double *)c->ubuf;
+  const T *Fr = (const T *)c->cg.Fr;
+  T *tp = (T *)tape;
+  const T *nb = nullptr;
+  if (repair)
+    hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, true, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                       c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+  else if (c->act && c->track_u)
+    hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+                       c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+  else if (c->act)
+    hipLaunchKernelGGL((k_bulk_tape<D, T, true, false, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo,
+                       c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+  else if (c->track_u)
+    hipLaunchKernelGGL((k_bulk_tape<D, T, false, true, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo,
+                       c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+  else
+    hipLaunchKernelGGL((k_bulk_tape<D, T, false, false, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo,
+                       c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+}
+
 template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair, void *tape) {
+  // extensions (body acceleration, fibre law) in their own instantiation
+  const bool ext = c->bf || c->par.k1 != 0.0;
   if (tape) {
-    // the reverse mode runs without a body acceleration (checked by the caller)
-    dim3 grid, block;
-    grid_of(c->geo, grid, block);
-    const T *fin = (const T *)c->fB;
-    T *fout = (T *)c->fA;
-    double *us = (double *)c->ustar, *ub = (double *)c->ubuf;
-    const T *Fr = (const T *)c->cg.Fr;
-    T *tp = (T *)tape;
-    const T *nb = nullptr;
-    if (repair)
-      hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, true>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
-    else if (c->act && c->track_u)
-      hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
-    else if (c->act)
-      hipLaunchKernelGGL((k_bulk_tape<D, T, true, false, false>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
-                         c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
-    else if (c->track_u)
-      hipLaunchKernelGGL((k_bulk_tape<D, T, false, true, false>), grid, block, 0, c->st, fin, fout, c->geo,
-                         c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
-    else
-      hipLaunchKernelGGL((k_bulk_tape<D, T, false, false, false>), grid, block, 0, c->st, fin, fout, c->geo,
-                         c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
+    if (ext) bulk_tape_t<D, T, true>(c, repair, tape);
+    else bulk_tape_t<D, T, false>(c, repair, tape);
     return;
   }
-  if (c->bf) bulk_plain_t<D, T, true>(c, repair);
+  if (ext) bulk_plain_t<D, T, true>(c, repair);
   else bulk_plain_t<D, T, false>(c, repair);
 }
 

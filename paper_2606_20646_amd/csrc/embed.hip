@@ -268,8 +268,6 @@ __global__ void k_link_lsq(Geo g, const uint8_t *__restrict__ act, Links L, int 
   const int q = L.q[l], A = q / 2, sg = (q & 1) ? -1 : 1;
   const double eta = L.eta[l];
   const C3 cm = coords_of(g, m);
-  int32_t *idx = L.sidx + l * L.kmax;
-  double *w = L.sw + l * 2 * L.kmax;
   int np = 0;
   const int R = 4;
   for (int oz = (D == 3 ? -R : 0); oz <= (D == 3 ? R : 0); ++oz)
@@ -290,7 +288,7 @@ __global__ void k_link_lsq(Geo g, const uint8_t *__restrict__ act, Links L, int 
           L.basis[l] = 0;
           return;
         }
-        idx[np] = (int32_t)j;
+        L.sidx[lsq_i(L, l, np)] = (int32_t)j;
         ++np;
       }
   L.npts[l] = np;
@@ -371,7 +369,7 @@ __global__ void k_link_lsq(Geo g, const uint8_t *__restrict__ act, Links L, int 
         lsq_row<D>(xs + k * D, quad, a);
         for (int d = 0; d < D; ++d) r2 += xs[k * D + d] * xs[k * D + d];
         for (int j = 0; j < nb; ++j) s += a[j] * y[j];
-        w[al * L.kmax + k] = s / (1.0 + r2);
+        L.sw[lsq_w(L, l, al, k)] = s / (1.0 + r2);
       }
     }
     L.basis[l] = quad ? 2 : 1;
@@ -379,7 +377,7 @@ __global__ void k_link_lsq(Geo g, const uint8_t *__restrict__ act, Links L, int 
   }
   L.basis[l] = 0;
   for (int al = 0; al < D - 1; ++al)
-    for (int k = 0; k < np; ++k) w[al * L.kmax + k] = 0.0;
+    for (int k = 0; k < np; ++k) L.sw[lsq_w(L, l, al, k)] = 0.0;
 }
 
 // ----------------------------------------------------- cut-link closure
@@ -453,22 +451,25 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
     N[a] = L.Nb[l * 3 + a];
   }
   // sum_alpha g_alpha (x) t_alpha with g_alpha = t_alpha + sum_k w_alpha,k u_k
+  // (one pass over the stencil for both tangents)
   double Gt[D * D];
   for (int k = 0; k < D * D; ++k) Gt[k] = 0.0;
   const int np = L.npts[l];
-  const int32_t *idx = L.sidx + l * L.kmax;
-  const double *w = L.sw + l * 2 * L.kmax;
-  for (int al = 0; al < D - 1; ++al) {
-    double gv[D];
-    for (int i = 0; i < D; ++i) gv[i] = L.tang[l * 6 + al * 3 + i];
-    for (int k = 0; k < np; ++k) {
-      const double wk = w[al * L.kmax + k];
-      const int64_t j = idx[k];
-      for (int i = 0; i < D; ++i) gv[i] += wk * u[(size_t)i * g.S + j];
+  double gv[D - 1][D];
+  for (int al = 0; al < D - 1; ++al)
+    for (int i = 0; i < D; ++i) gv[al][i] = L.tang[l * 6 + al * 3 + i];
+  for (int k = 0; k < np; ++k) {
+    const int64_t j = L.sidx[lsq_i(L, l, k)];
+    double uk[D];
+    for (int i = 0; i < D; ++i) uk[i] = u[(size_t)i * g.S + j];
+    for (int al = 0; al < D - 1; ++al) {
+      const double wk = L.sw[lsq_w(L, l, al, k)];
+      for (int i = 0; i < D; ++i) gv[al][i] += wk * uk[i];
     }
-    for (int i = 0; i < D; ++i)
-      for (int B = 0; B < D; ++B) Gt[i * D + B] += gv[i] * L.tang[l * 6 + al * 3 + B];
   }
+  for (int al = 0; al < D - 1; ++al)
+    for (int i = 0; i < D; ++i)
+      for (int B = 0; B < D; ++B) Gt[i * D + B] += gv[al][i] * L.tang[l * 6 + al * 3 + B];
   double s, ds;
   ramp_eval(bc.ramp, bc.Tr, th, s, ds);
   bc_base<D>(bc, Xb, N, Tb);
@@ -489,7 +490,7 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
       h[i] = acc;
     }
   }
-  const bool conv = newton_h<D>(N, Gt, Tb, p.mu, p.lam, 1e-12, h);
+  const bool conv = newton_h<D>(N, Gt, Tb, p, 1e-12, h);
   if (!conv) atomicAdd(nfail, 1ull);
   double Fb[D * D], Pb[D * D];
   for (int i = 0; i < D; ++i)
@@ -498,7 +499,7 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
     atomicOr(flag, FLAG_NEWTON);
     for (int k = 0; k < D * D; ++k) Fb[k] = (k % (D + 1) == 0) ? 1.0 : 0.0;
   }
-  piola<D>(Fb, p.mu, p.lam, Pb);
+  mat_piola<D>(Fb, p, Pb);
   const T ie = T(1.0 / (2.0 * eta));
   const T e2 = T(2.0 * eta);
 #pragma unroll
@@ -979,12 +980,18 @@ __global__ __launch_bounds__(256) void k_ureset(Geo g, const uint8_t *__restrict
   ureset_node<D, T>(g, act, x, V, u, us, hdt, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
 }
 
+// Workgroups go to the 8 XCDs round robin (block b to XCD b % 8): block b
+// takes tile (b % 8) * per + b / 8, so that each XCD sweeps one contiguous
+// range of tiles and finds the neighbour rows and planes of x in its own L2.
+constexpr int NXCD = 8;
 template <int D>
 __global__ __launch_bounds__(CG_T) void k_jacobi(Geo g, const uint8_t *__restrict__ act,
                                                  const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
                                                  const double *__restrict__ xin, double *__restrict__ xout, double om,
-                                                 const int32_t *__restrict__ tiles) {
-  const int64_t blk = tiles ? (int64_t)tiles[blockIdx.x] : (int64_t)blockIdx.x;
+                                                 const int32_t *__restrict__ tiles, int ntile, int per) {
+  const int t = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+  if (t >= ntile) return;
+  const int64_t blk = tiles ? (int64_t)tiles[t] : (int64_t)t;
   jacobi_node<D>(g, act, anc_n, b, xin, xout, om, blk * CG_T + threadIdx.x);
 }
 
@@ -1254,10 +1261,11 @@ template <int D> static int jacobi_run(tlvlbm_ctx *c, const uint8_t *anc_n) {
     if (s) return s;
   }
   const unsigned nt = w.tiles ? (unsigned)w.ntiles : nblk(g.N, CG_T);
+  const int per = (int)((nt + NXCD - 1) / NXCD);
   double *a = (double *)w.x, *bb = (double *)w.r;
   for (int k = 0; k < c->proj_sweeps; ++k) {
-    hipLaunchKernelGGL((k_jacobi<D>), nt, CG_T, 0, st, g, c->act, anc_n, (const double *)w.b, (const double *)a, bb,
-                       c->proj_weight, w.tiles);
+    hipLaunchKernelGGL((k_jacobi<D>), (unsigned)(per * NXCD), CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
+                       (const double *)a, bb, c->proj_weight, w.tiles, (int)nt, per);
     std::swap(a, bb);
   }
   if (a != (double *)w.x)

@@ -121,15 +121,29 @@ __device__ inline bool solve_small(int n, double *A, double *b, double *x) {
   return true;
 }
 
+// stress and tangent action of the material in FP64 (neo-Hookean, plus the
+// fibre term when p.k1 > 0)
+template <int D> __device__ __forceinline__ double mat_piola(const double *F, const Par &p, double *P) {
+  const double J = piola<D>(F, p.mu, p.lam, P);
+  if (p.k1 != 0.0) fibre_add<D>(F, p.k1, p.a0, P);
+  return J;
+}
+
+template <int D>
+__device__ __forceinline__ void mat_tangent(const double *F, const double *dF, const Par &p, double *dP) {
+  piola_tangent<D>(F, dF, p.mu, p.lam, dP);
+  if (p.k1 != 0.0) fibre_tangent_add<D>(F, dF, p.k1, p.a0, dP);
+}
+
 // R(h) = P(h (x) N + Gt) N - T (Eqs. 54, 56); false if det F_b <= 0
 template <int D>
-__device__ inline bool nm_residual(const double *h, const double *N, const double *Gt, const double *Tb, double mu,
-                            double lam, double *R) {
+__device__ inline bool nm_residual(const double *h, const double *N, const double *Gt, const double *Tb, const Par &p,
+                            double *R) {
   double F[D * D], P[D * D];
   for (int i = 0; i < D; ++i)
     for (int a = 0; a < D; ++a) F[i * D + a] = h[i] * N[a] + Gt[i * D + a];
   if (!(det<D>(F) > 0.0)) return false;
-  piola<D>(F, mu, lam, P);
+  mat_piola<D>(F, p, P);
   for (int i = 0; i < D; ++i) {
     double s = 0.0;
     for (int a = 0; a < D; ++a) s += P[i * D + a] * N[a];
@@ -143,11 +157,11 @@ __device__ inline bool nm_residual(const double *h, const double *N, const doubl
 // dR/dh = Q(N; F_b) (acoustic tensor, Eq. 19) from the tangent action;
 // accepts only det F_b > 0 with a decreasing residual (<= 10 halvings).
 template <int D>
-__device__ inline bool newton_h(const double *N, const double *Gt, const double *Tb, double mu, double lam, double tol,
+__device__ inline bool newton_h(const double *N, const double *Gt, const double *Tb, const Par &p, double tol,
                          double *h) {
   double R[D], Rt[D], ht[D];
-  if (!nm_residual<D>(h, N, Gt, Tb, mu, lam, R)) return false;
-  const double thr = tol * (mu > 1.0 ? mu : 1.0);
+  if (!nm_residual<D>(h, N, Gt, Tb, p, R)) return false;
+  const double thr = tol * (p.mu > 1.0 ? p.mu : 1.0);
   for (int it = 0; it <= 30; ++it) {
     double rinf = 0.0, r2 = 0.0;
     for (int i = 0; i < D; ++i) {
@@ -163,7 +177,7 @@ __device__ inline bool newton_h(const double *N, const double *Gt, const double 
       double dF[D * D], dP[D * D];
       for (int i = 0; i < D; ++i)
         for (int a = 0; a < D; ++a) dF[i * D + a] = (i == k) ? N[a] : 0.0;
-      piola_tangent<D>(F, dF, mu, lam, dP);
+      mat_tangent<D>(F, dF, p, dP);
       for (int i = 0; i < D; ++i) {
         double s = 0.0;
         for (int a = 0; a < D; ++a) s += dP[i * D + a] * N[a];
@@ -176,7 +190,7 @@ __device__ inline bool newton_h(const double *N, const double *Gt, const double 
     bool acc = false;
     for (int ls = 0; ls <= 10; ++ls) {
       for (int i = 0; i < D; ++i) ht[i] = h[i] + step * dh[i];
-      if (nm_residual<D>(ht, N, Gt, Tb, mu, lam, Rt)) {
+      if (nm_residual<D>(ht, N, Gt, Tb, p, Rt)) {
         double rt2 = 0.0, rtinf = 0.0;
         for (int i = 0; i < D; ++i) {
           rt2 += Rt[i] * Rt[i];

@@ -31,6 +31,7 @@ struct Geo {
 // scalar parameters of the bulk update
 struct Par {
   double mu, lam, inv_rho0, dt, c, omega, gamma;
+  double k1, a0[3];  // fibre reinforcement (k1 = 0: the neo-Hookean law of Eq. 62)
 };
 
 // cut-link table (device SoA), ordered by (bid, node, q)
@@ -40,9 +41,17 @@ struct Links {
   int64_t *node = nullptr, *out = nullptr, *mminus = nullptr;
   int32_t *q = nullptr, *bid = nullptr, *npts = nullptr, *basis = nullptr;
   double *eta = nullptr, *Nb = nullptr /*[n][3]*/, *Xb = nullptr /*[n][3]*/, *tang = nullptr /*[n][2][3]*/;
-  int32_t *sidx = nullptr; /*[n][kmax]*/
-  double *sw = nullptr;    /*[n][2][kmax]*/
+  // LSQ stencils, point-major so that adjacent links (one per lane) read
+  // adjacent words: node of point k of link l at sidx[k*n + l], weight of
+  // tangent al at sw[(al*kmax + k)*n + l] (see lsq_i, lsq_w)
+  int32_t *sidx = nullptr; /*[kmax][n]*/
+  double *sw = nullptr;    /*[2][kmax][n]*/
 };
+
+__host__ __device__ inline size_t lsq_i(const Links &L, int64_t l, int k) { return (size_t)k * L.n + l; }
+__host__ __device__ inline size_t lsq_w(const Links &L, int64_t l, int al, int k) {
+  return ((size_t)al * L.kmax + k) * L.n + l;
+}
 
 // boundary condition by value (mirrors tlvlbm_bc)
 struct BC {
@@ -276,6 +285,10 @@ struct tlvlbm_ctx {
   hipStream_t st = nullptr;
   size_t esz = 4;
   void *fA = nullptr, *fB = nullptr;  // population planes (Q*M planes of stride S)
+  // embedded bodies: the 64-node chunks of the node order that hold active
+  // nodes (one wavefront each); the bulk update skips the rest
+  int32_t *chunks = nullptr;
+  int nchunks = 0;
   // body acceleration b(X, t) = s(t) g(X) (Eq. 5): g in D planes of the
   // population precision (null: none), s a ramp
   void *bf = nullptr;

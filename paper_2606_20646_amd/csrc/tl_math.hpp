@@ -91,6 +91,53 @@ __device__ __forceinline__ void piola_tangent(const T *F, const T *dF, T mu, T l
   }
 }
 
+// Fibre reinforcement of the neo-Hookean solid (the anisotropic law named in
+// the paper's outlook, Sec. 6): W += k1/2 (I4 - 1)^2 with I4 = |F a0|^2 for a
+// unit reference fibre direction a0.  Adds to P and to the tangent action:
+//   P  += 2 k1 (I4 - 1) (F a0) (x) a0,
+//   dP += 2 k1 [2 ((F a0).(dF a0)) (F a0) + (I4 - 1) dF a0] (x) a0.
+template <int D, typename T>
+__device__ __forceinline__ void fibre_add(const T *F, T k1, const double *a0, T *P) {
+  T fa[D], I4 = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T s = T(0);
+#pragma unroll
+    for (int A = 0; A < D; ++A) s += F[i * D + A] * T(a0[A]);
+    fa[i] = s;
+    I4 += s * s;
+  }
+  const T c = T(2) * k1 * (I4 - T(1));
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int A = 0; A < D; ++A) P[i * D + A] += c * fa[i] * T(a0[A]);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void fibre_tangent_add(const T *F, const T *dF, T k1, const double *a0, T *dP) {
+  T fa[D], dfa[D], I4 = T(0), dI = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T s = T(0), ds = T(0);
+#pragma unroll
+    for (int A = 0; A < D; ++A) {
+      s += F[i * D + A] * T(a0[A]);
+      ds += dF[i * D + A] * T(a0[A]);
+    }
+    fa[i] = s;
+    dfa[i] = ds;
+    I4 += s * s;
+    dI += s * ds;
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const T w = T(2) * k1 * (T(2) * dI * fa[i] + (I4 - T(1)) * dfa[i]);
+#pragma unroll
+    for (int A = 0; A < D; ++A) dP[i * D + A] += w * T(a0[A]);
+  }
+}
+
 // Flux entry Phi_A^r of the conservative system (Sec. 2.2, Eq. 13) given the
 // stress P (already divided by rho0 in the velocity rows by the caller).
 template <int D, typename T>

@@ -29,7 +29,19 @@ class Grid(C.Structure):
 
 
 class Material(C.Structure):
-    _fields_ = [("law", C.c_int32), ("mu", C.c_double), ("lam", C.c_double)]
+    _fields_ = [("law", C.c_int32), ("mu", C.c_double), ("lam", C.c_double), ("k1", C.c_double),
+                ("a0", C.c_double * 3)]
+
+
+def _material(mu, lam, fibre):
+    """law 0 (neo-Hookean) or, with fibre = (k1, a0), law 1."""
+    if fibre is None:
+        return Material(0, mu, lam, 0.0)
+    k1, a0 = fibre
+    m = Material(1, mu, lam, float(k1))
+    for k, v in enumerate(a0):
+        m.a0[k] = v
+    return m
 
 
 class Options(C.Structure):
@@ -128,7 +140,7 @@ class Solver:
 
     def __init__(self, D, n, dx, dt, mu, lam, rho0=1.0, origin=None, periodic_mask=None, omega=1.8, gamma=0.0,
                  theta_F=1.0, proj_every=20, precision="fp32", track_u=-1, cg_rtol=0.0, cg_maxit=0,
-                 stream=None, cg_multigrid=True, proj_sweeps=20, proj_weight=2.0 / 3.0):
+                 stream=None, cg_multigrid=True, proj_sweeps=20, proj_weight=2.0 / 3.0, fibre=None):
         self.D, self.M, self.Q = D, D + D * D, 2 * D
         self.n = tuple(int(v) for v in n)
         self.N = int(np.prod(self.n))
@@ -139,7 +151,7 @@ class Solver:
             g.origin[a] = (origin[a] if origin is not None and a < len(origin) else 0.0)
         g.dx = dx
         g.periodic_mask = ((1 << D) - 1) if periodic_mask is None else periodic_mask
-        m = Material(0, mu, lam)
+        m = _material(mu, lam, fibre)
         o = Options()
         lib.tlvlbm_default_options(C.byref(o))
         o.omega, o.gamma, o.theta_F, o.cg_rtol = omega, gamma, theta_F, cg_rtol
@@ -199,8 +211,8 @@ class Solver:
         p, keep = _ptr(arr)
         self._chk(lib.tlvlbm_set_body_force(self.h, p, RAMPS.get(ramp, ramp), float(T_r)), "set_body_force")
 
-    def set_material(self, mu, lam):
-        self._chk(lib.tlvlbm_set_material(self.h, C.byref(Material(0, mu, lam))), "set_material")
+    def set_material(self, mu, lam, fibre=None):
+        self._chk(lib.tlvlbm_set_material(self.h, C.byref(_material(mu, lam, fibre))), "set_material")
 
     def set_state(self, U0, u0=None, dU0=None):
         arrs = [a if (a is None or not isinstance(a, np.ndarray)) else np.ascontiguousarray(a, np.float64)

@@ -132,6 +132,16 @@ def piola_nh(F, mu, lam):
     return mu * (F - Fit) + 0.5 * lam * (J * J - 1.0)[:, None, None] * Fit
 
 
+def piola_fibre(F, mu, lam, k1, a0):
+    """Nominal stress of the neo-Hookean solid reinforced by fibres along the
+    unit reference direction a0: W = W_NH + k1/2 (|F a0|^2 - 1)^2, so
+    P = P_NH + 2 k1 (|F a0|^2 - 1) (F a0) (x) a0 ([n, D, D])."""
+    a0 = np.asarray(a0, float)
+    fa = np.einsum("nij,j->ni", F, a0)
+    I4 = (fa * fa).sum(1)
+    return piola_nh(F, mu, lam) + 2 * k1 * (I4 - 1.0)[:, None, None] * np.einsum("ni,j->nij", fa, a0)
+
+
 class PlaneWaveMMS:
     """Manufactured finite-strain plane wave on a periodic box (body
     acceleration of Sec. 2.1, Eq. 5):
@@ -144,10 +154,16 @@ class PlaneWaveMMS:
     b = dv/dt - Div P(F), with Div P = (dP/dxi) k evaluated by Richardson
     central differences of P in xi (P depends on X through xi only)."""
 
-    def __init__(self, D, k, p, a, Omega, mu, lam):
+    def __init__(self, D, k, p, a, Omega, mu, lam, fibre=None):
         self.D, self.k, self.a, self.Om, self.mu, self.lam = D, np.asarray(k, float), a, Omega, mu, lam
         p = np.asarray(p, float)
         self.p = p / np.linalg.norm(p)
+        self.fibre = fibre  # None or (k1, unit a0)
+
+    def _P(self, F):
+        if self.fibre is None:
+            return piola_nh(F, self.mu, self.lam)
+        return piola_fibre(F, self.mu, self.lam, *self.fibre)
 
     def _F(self, xi, t):
         g = self.a * np.cos(self.Om * t) * 2 * np.pi * np.cos(2 * np.pi * xi)
@@ -182,8 +198,7 @@ class PlaneWaveMMS:
         dvdt = -self.a * self.Om ** 2 * np.cos(self.Om * t) * s * self.p[:, None]
 
         def dP(hh):
-            return (piola_nh(self._F(xi + hh, t), self.mu, self.lam)
-                    - piola_nh(self._F(xi - hh, t), self.mu, self.lam)) / (2 * hh)
+            return (self._P(self._F(xi + hh, t)) - self._P(self._F(xi - hh, t))) / (2 * hh)
         dPdxi = (4 * dP(h / 2) - dP(h)) / 3
         divP = np.einsum("nij,j->in", dPdxi, self.k)
         return dvdt - divP

@@ -34,7 +34,7 @@ def _solver(T, cfg, precision):
     s = T.Solver(cfg["D"], cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"],
                  gamma=cfg["gamma"], origin=cfg.get("origin"), periodic_mask=cfg.get("pm", cfg.get("periodic_mask")),
                  proj_every=cfg.get("proj_every", 20), precision=precision, track_u=1,
-                 proj_sweeps=cfg.get("proj_sweeps", 20))
+                 proj_sweeps=cfg.get("proj_sweeps", 20), fibre=cfg.get("fibre"))
     if "phi" in cfg:
         s.set_levelset(cfg["phi"], cfg["bid"])
         for bid, bc in cfg["bcs"].items():

@@ -129,3 +129,27 @@ def test_body_force_excludes_batch_and_reverse_mode(T):
         T.Batch([s])
     with pytest.raises(T.TlvlbmError):
         s.adjoint(3, np.ones((6, s.N)))
+
+
+FIBRE = (0.8, (np.cos(0.5), np.sin(0.5)))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_fibre_law_manufactured_wave_matches_oracle(T, orc, precision, tol):
+    """The fibre-reinforced law (law 1) through the whole bulk path: the
+    manufactured wave of that law, GPU = oracle."""
+    D, N = 2, 32
+    m = refsol.PlaneWaveMMS(2, (1, 1), (1, 0.3), 0.02, 2 * np.pi, 1.0, 2.0, fibre=(FIBRE[0], np.array(FIBRE[1])))
+    dx = 1 / N
+    dt = dx / 10
+    X = W.node_coords([N] * D, dx, [0.0] * D)
+    _say(f"fibre-law manufactured wave {N}^2 {precision} 64 steps")
+    g = T.Solver(D, [N] * D, dx, dt, 1.0, 2.0, omega=2.0, precision=precision, track_u=1, fibre=FIBRE)
+    Ug, ug = _run_mms(g, m, X, dt, 64)
+    o = orc.Sim(D, [N] * D, dx, dt, 1.0, 2.0, omega=2.0)
+    o.set_fibres(*FIBRE)
+    Uo, uo = _run_mms(o, m, X, dt, 64)
+    assert np.linalg.norm(Ug - Uo) <= tol * np.linalg.norm(Uo)
+    assert np.linalg.norm(ug - uo) <= tol * np.linalg.norm(uo)
+    Ue, _ = m.fields(X, 64 * dt)
+    assert np.linalg.norm(Ug[:D] - Ue[:D]) <= 0.02 * np.linalg.norm(Ue[:D])

@@ -8,8 +8,8 @@ rerunning the forward oracle.  The cases are chosen so that each part of the
 step carries weight in some of them: periodic bulk with damping (collision,
 streaming, recovery), Dirichlet-only embedded (Dirichlet closure), Neumann
 with and without projection (LSQ, Newton implicit function theorem, the
-projection's Jacobi sweeps, or its exact CG solve and gauge, the repair), and
-a 3D sphere.
+projection's Jacobi sweeps, or its exact CG solve and gauge, the repair), a
+3D sphere, and the fibre-reinforced law in 2D and 3D.
 """
 import numpy as np
 import pytest
@@ -22,6 +22,8 @@ def _make(cfg, mu, lam):
     o = O.Sim(cfg["D"], cfg["n"], cfg["dx"], cfg["dt"], mu, lam, omega=cfg["omega"], gamma=cfg["gamma"],
               origin=cfg.get("origin"), periodic_mask=cfg.get("pm"), proj_every=cfg.get("proj_every", 20),
               proj_sweeps=cfg.get("proj_sweeps", 20))
+    if cfg.get("fibre"):
+        o.set_fibres(*cfg["fibre"])
     if "phi" in cfg:
         o.set_levelset(cfg["phi"], cfg["bid"])
         kinds = {"dirichlet": O.DIRICHLET, "neumann": O.NEUMANN}
@@ -87,6 +89,9 @@ CASES = {
     # the projection solved exactly instead of relaxed by Jacobi sweeps
     "neumann_annulus_projection_exact": (lambda: dict(_disk(4, True), proj_sweeps=0), 9),
     "neumann_sphere_projection_exact": (lambda: dict(_sphere(), proj_sweeps=0), 7),
+    # the fibre-reinforced law (anisotropic stress and tangent everywhere)
+    "neumann_annulus_fibres": (lambda: dict(_disk(4, True), fibre=(0.6, (0.8, 0.6))), 9),
+    "neumann_sphere_fibres": (lambda: dict(_sphere(), fibre=(0.5, (0.0, 0.6, 0.8))), 7),
 }
 
 

@@ -79,12 +79,18 @@ def test_batch_equals_per_instance(env, precision, tol, graph, mg, sweeps):
         Ub, ub, _ = b.moments()
         act = c["phi"] <= 0
         assert np.linalg.norm(Ua[:, act] - Ub[:, act]) <= tol * np.linalg.norm(Ua[:, act])
-        # the displacement comes out of the projection CG (relative residual
-        # 1e-14 / 1e-8); the two paths compile the same device code into
-        # different kernels (FMA contraction differs at round-off), and a CG
-        # stopped at its tolerance turns that into u differences of order
-        # cond * rtol: compare u at the CG's accuracy
-        utol = 1e-10 if precision == "fp64" else 1e-4
+        # the displacement comes out of the projection solver.  Jacobi sweeps:
+        # the same per-node arithmetic in both paths.  Exact mode: a CG
+        # stopped at relative residual 1e-14 / 1e-8; the two paths compile
+        # the same device code into different kernels (FMA contraction
+        # differs at round-off) and stop at different iterations, which
+        # gives u differences of order cond(K) * rtol relative to the scale
+        # of the right-hand side (cond(K) ~ 1e4 on these graphs); an
+        # instance whose load has barely started has u far below that scale
+        if sweeps > 0:
+            utol = 1e-10 if precision == "fp64" else 1e-4
+        else:
+            utol = 1e-10 if precision == "fp64" else 1e-3
         assert np.linalg.norm(ua[:, act] - ub[:, act]) <= utol * np.linalg.norm(ua[:, act])
         assert a.stats()["step"] == b.stats()["step"] == 65
 

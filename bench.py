@@ -29,6 +29,9 @@ Other workloads (one JSON line each; not the headline):
                     cavity traction, N = 200; 2D annulus under radial
                     traction, N = 196; 2D affine Dirichlet annulus, N = 384):
                     MLUPS and the relative errors against the exact solutions
+    --workload tube the finite tube under end stretch and twist (76 x 76 x 300
+                    nodes, 100 000 steps to t = 100): MLUPS, the largest
+                    displacement and the Jacobian range
 """
 from __future__ import annotations
 
@@ -113,7 +116,7 @@ def main():
     ap.add_argument("--n", type=int, default=None,
                     help="grid cells per axis (c3 256, ellipsoid 320, shell 200)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ellipsoid", "shell", "annulus", "affine"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ellipsoid", "shell", "annulus", "affine", "tube"], default="c3")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--fd", action="store_true",
                     help="c5: check dL/dmu against Richardson-extrapolated central differences of the forward")
@@ -130,7 +133,7 @@ def main():
             sys.exit(2)
         {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "ellipsoid": bench_analytic,
          "shell": bench_analytic, "annulus": bench_analytic,
-         "affine": bench_analytic}[args.workload](args)
+         "affine": bench_analytic, "tube": bench_analytic}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -408,7 +411,7 @@ def bench_analytic(args):
     import refsol
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    N = args.n or {"ellipsoid": 320, "shell": 200, "annulus": 196, "affine": 384}[args.workload]
+    N = args.n or {"ellipsoid": 320, "shell": 200, "annulus": 196, "affine": 384, "tube": 100}[args.workload]
     print(f"[bench] {args.workload} N={N} {args.precision}: building inputs", file=sys.stderr, flush=True)
     if args.workload == "ellipsoid":
         c = W.config_ellipsoid(N)
@@ -416,6 +419,10 @@ def bench_analytic(args):
     elif args.workload == "affine":
         c = W.config_affine_annulus(N)
         desc = f"D2Q4x6 affine annulus {N}^2+frame, affine velocity Dirichlet surfaces, omega=2"
+    elif args.workload == "tube":
+        c = W.config_tube(N)
+        desc = (f"D3Q6x12 finite tube {c['n'][0]}x{c['n'][1]}x{c['n'][2]} (dx = 1/{N}), traction-free walls, "
+                f"clamped end, stretch 0.5 L and twist 45 deg at the other (half-cosine ramp T_r = 10), gamma=10")
     elif args.workload == "annulus":
         c = W.config_radial_annulus(N)
         desc = (f"D2Q4x6 radial traction annulus {N}^2+frame, clamped inner surface, ramped radial traction, "
@@ -437,6 +444,11 @@ def bench_analytic(args):
     t = steps * c["dt"]
     if args.workload in ("ellipsoid", "affine"):
         err = refsol.affine_errors(c, U, u, J, t)
+    elif args.workload == "tube":
+        act = c["phi"] <= 0
+        err = {"max_displacement": float(np.linalg.norm(u[:, act], axis=0).max()),
+               "J_range": [float(J[act].min()), float(J[act].max())],
+               "v_rms": float(np.sqrt((U[:3, act] ** 2).sum(0).mean()))}
     elif args.workload == "annulus":
         ref = refsol.radial_bvp(2, c["mu"], c["lam"], 0.18, 0.42, r_inner=0.18, Pr_outer=1.0)
         err = refsol.radial_errors(c, ref, U, u, J)

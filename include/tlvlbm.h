@@ -118,7 +118,8 @@ typedef struct {
  * e_R = (X_b - X0)/|X_b - X0|, N_b the outward unit normal (Eq. 38),
  * G row-major 3x3 (the leading D x D block is used).
  * DIRICHLET_VELOCITY imposes v_D at t^n + dt/2 (Sec. 3.3, Eqs. 44-45); with
- * given_as_displacement the value is u_D and v_D = d u_D/dt (Sec. 2.1, Eq. 9).
+ * given_as_displacement the value is u_D and v_D = d u_D/dt (Sec. 2.1, Eq. 9),
+ * plus the ramped rotation of `twist` below.
  * NEUMANN_TRACTION imposes the nominal traction P N = T at t^n + dt/2
  * (Sec. 3.4, Eqs. 46-56). */
 typedef struct {
@@ -131,6 +132,10 @@ typedef struct {
   double p_radial;
   double p_normal;
   double X0[3];
+  double twist;  /* displacement-given Dirichlet only: adds the rigid rotation
+                    (R(s(t) twist) - I)(X_b - X0) in the (e1, e2) plane, angle
+                    twist (radians) about the e3 axis through X0 (the tube of
+                    Sec. 5.3, Eq. 87); v_D is its time derivative */
 } tlvlbm_bc;
 
 typedef struct {

@@ -59,6 +59,7 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_projection.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_set_body_force.argtypes = [C.c_void_p, dp, C.c_int, C.c_double]
+        L.orc_set_bc_twist.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_set_fibres.argtypes = [C.c_void_p, C.c_double, dp]
         L.orc_set_levelset.argtypes = [C.c_void_p, dp, C.POINTER(C.c_uint8)]
         L.orc_set_bc.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp, dp,
@@ -231,7 +232,7 @@ class Sim:
             raise OracleError(st, "set_levelset")
 
     def set_bc(self, bid, type, ramp=RAMP_CONST, T_r=1.0, given_as_displacement=False, a=None, G=None,
-               p_radial=0.0, X0=None, p_normal=0.0):
+               p_radial=0.0, X0=None, p_normal=0.0, twist=0.0):
         a3 = np.zeros(3) if a is None else _f64(list(a) + [0.0] * (3 - len(a)))
         G9 = np.zeros((3, 3))
         if G is not None:
@@ -243,6 +244,10 @@ class Sim:
                               p_radial, p_normal, _d(X03))
         if st:
             raise OracleError(st, "set_bc")
+        if twist:
+            st = lib().orc_set_bc_twist(self.h, bid, float(twist))
+            if st:
+                raise OracleError(st, "set_bc_twist")
 
     def set_fibres(self, k1, a0):
         """Fibre-reinforced law: W += k1/2 (|F a0|^2 - 1)^2 (k1 = 0: off)."""

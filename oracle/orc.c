@@ -487,6 +487,7 @@ int orc_newton(int D, double mu, double lam, const double *N, const double *Gt, 
 typedef struct {
   int type, ramp, disp;
   double Tr, a[3], G[9], p, pn, X0[3];
+  double tw; /* rigid rotation angle about e3 through X0 (displacement-given Dirichlet) */
 } orc_bc;
 
 typedef struct {
@@ -844,6 +845,14 @@ int orc_set_bc(orc_sim *s, int bid, int type, int ramp, double T_r, int disp, co
   return ORC_OK;
 }
 
+int orc_set_bc_twist(orc_sim *s, int bid, double twist) {
+  if (bid < 0 || bid > 255) return ORC_ERR_ARG;
+  orc_bc *b = &s->bc[bid];
+  if (twist != 0.0 && !(b->type == ORC_BC_DIRICHLET && b->disp)) return ORC_ERR_ARG;
+  b->tw = twist;
+  return ORC_OK;
+}
+
 /* loading factor s(t) and its derivative: sine-squared ramp (Sec. 4.3,
  * Eq. 71), half-cosine ramp (Sec. 5.3, Eq. 88), linear ramp, constant */
 static void ramp_eval(int kind, double Tr, double t, double *sv, double *dsv) {
@@ -893,6 +902,12 @@ static void bc_value(const orc_bc *b, int D, const double *X, const double *Nb, 
   }
   double fac = (b->type == ORC_BC_DIRICHLET && b->disp) ? dsv : sv;
   for (int i = 0; i < D; ++i) val[i] = fac * base[i];
+  if (b->type == ORC_BC_DIRICHLET && b->disp && b->tw != 0.0) {
+    /* velocity of the ramped rotation u = (R(s tw) - I) d (Sec. 5.3, Eq. 87) */
+    double al = sv * b->tw, da = dsv * b->tw;
+    val[0] += da * (-sin(al) * d[0] - cos(al) * d[1]);
+    val[1] += da * (cos(al) * d[0] - sin(al) * d[1]);
+  }
 }
 
 /* prescribed Dirichlet displacement u_D(X, t): the value itself when the
@@ -908,6 +923,11 @@ static void bc_displacement(const orc_bc *b, int D, const double *X, const doubl
   bc_value(&tmp, D, X, Nb, t, val); /* base */
   double fac = b->disp ? sv : ramp_integral(b->ramp, b->Tr, t);
   for (int i = 0; i < D; ++i) val[i] *= fac;
+  if (b->disp && b->tw != 0.0) {
+    double al = sv * b->tw, d0 = X[0] - b->X0[0], d1 = X[1] - b->X0[1];
+    val[0] += (cos(al) - 1.0) * d0 - sin(al) * d1;
+    val[1] += sin(al) * d0 + (cos(al) - 1.0) * d1;
+  }
 }
 
 /* material of the simulation with the given (mu, lambda) */

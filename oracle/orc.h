@@ -97,6 +97,9 @@ int  orc_set_levelset(orc_sim *s, const double *phi, const uint8_t *bid);
 int  orc_set_bc(orc_sim *s, int bid, int type, int ramp, double T_r,
                 int given_as_displacement, const double *a, const double *G,
                 double p_radial, double p_normal, const double *X0);
+/* displacement-given Dirichlet only: add the ramped rigid rotation
+ * (R(s(t) twist) - I)(X - X0) in the (e1, e2) plane (Sec. 5.3, Eq. 87) */
+int  orc_set_bc_twist(orc_sim *s, int bid, double twist);
 /* U0[M][N]; u0[D][N] or NULL; dU0[D][M][N] (d/dX_A of U0) or NULL */
 int  orc_set_state(orc_sim *s, const double *U0, const double *u0,
                    const double *dU0);

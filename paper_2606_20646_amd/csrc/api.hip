@@ -312,6 +312,9 @@ tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *c, uint8_t bid, const tlvlbm_bc *b
   for (int k = 0; k < 9; ++k) b.G[k] = bc->G[k];
   b.pr = bc->p_radial;
   b.pn = bc->p_normal;
+  if (bc->twist != 0.0 && !(bc->type == TLVLBM_BC_DIRICHLET_VELOCITY && bc->given_as_displacement))
+    return fail(c, TLVLBM_ERR_INVALID_ARG, "twist needs a displacement-given Dirichlet condition");
+  b.tw = bc->twist;
   c->bc_set[bid] = true;
   c->aux_stale = true;  // projection anchors and components follow the conditions
   return TLVLBM_OK;

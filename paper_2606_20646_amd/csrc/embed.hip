@@ -404,6 +404,7 @@ __device__ __forceinline__ void cut_dirichlet_link(T *__restrict__ f, const Link
   bc_base<D>(bc, Xb, N, vb);
   const double fac = bc.disp ? ds : s;
   for (int i = 0; i < D; ++i) vb[i] *= fac;
+  twist_add(bc, Xb, s, ds, true, vb);
   const T ie = T(1.0 / (2.0 * eta));
   const T e2 = T(2.0 * eta);
 #pragma unroll
@@ -547,11 +548,13 @@ __device__ __forceinline__ void anchor_link(const Links &L, int64_t l, const BC 
   ramp_eval(bc.ramp, bc.Tr, t, s, ds);
   bc_base<D>(bc, Xb, N, uD);
   const double fac = bc.disp ? s : ramp_int(bc.ramp, bc.Tr, t);
+  for (int i = 0; i < D; ++i) uD[i] *= fac;
+  twist_add(bc, Xb, s, ds, false, uD);
   const double off = sg * L.eta[l] * g.dx;
   atomicAdd(&anc_n[m], 1);
   for (int i = 0; i < D; ++i) {
     const double Fi = double(Fm[(size_t)(i * D + A) * g.S + m]) - (i == A ? 1.0 : 0.0);
-    atomicAdd(&anc_s[(size_t)i * g.S + m], uD[i] * fac - Fi * off);
+    atomicAdd(&anc_s[(size_t)i * g.S + m], uD[i] - Fi * off);
   }
 }
 

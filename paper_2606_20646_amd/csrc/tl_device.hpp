@@ -74,6 +74,24 @@ __host__ __device__ __forceinline__ double ramp_int(int kind, double Tr, double 
   return S + (t - tc);
 }
 
+// ramped rigid rotation of a displacement-given Dirichlet condition about the
+// e3 axis through X0: u += (R(alpha) - I) d, v += alpha' R'(alpha) d with
+// alpha = s(t) tw, d = (X - X0) in the (e1, e2) plane
+__device__ __forceinline__ void twist_add(const BC &b, const double *X, double s, double ds, bool velocity,
+                                          double *val) {
+  if (b.tw == 0.0) return;
+  const double al = s * b.tw, c = cos(al), sn = sin(al);
+  const double dx = X[0] - b.X0[0], dy = X[1] - b.X0[1];
+  if (velocity) {
+    const double da = ds * b.tw;
+    val[0] += da * (-sn * dx - c * dy);
+    val[1] += da * (c * dx - sn * dy);
+  } else {
+    val[0] += (c - 1.0) * dx - sn * dy;
+    val[1] += sn * dx + (c - 1.0) * dy;
+  }
+}
+
 template <int D> __device__ __forceinline__ void bc_base(const BC &b, const double *X, const double *N, double *val) {
   double d[3], r = 0.0;
   for (int a = 0; a < D; ++a) {

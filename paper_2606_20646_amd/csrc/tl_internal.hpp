@@ -56,7 +56,7 @@ __host__ __device__ inline size_t lsq_w(const Links &L, int64_t l, int al, int k
 // boundary condition by value (mirrors tlvlbm_bc)
 struct BC {
   int type, ramp, disp;
-  double Tr, a[3], G[9], pr, pn, X0[3];
+  double Tr, a[3], G[9], pr, pn, X0[3], tw;
 };
 
 // scalar slots of the CG state (device doubles, per component)

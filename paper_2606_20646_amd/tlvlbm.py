@@ -54,7 +54,8 @@ class Options(C.Structure):
 class BC(C.Structure):
     _fields_ = [("type", C.c_int32), ("ramp", C.c_int32), ("T_r", C.c_double),
                 ("given_as_displacement", C.c_int32), ("a", C.c_double * 3), ("G", C.c_double * 9),
-                ("p_radial", C.c_double), ("p_normal", C.c_double), ("X0", C.c_double * 3)]
+                ("p_radial", C.c_double), ("p_normal", C.c_double), ("X0", C.c_double * 3),
+                ("twist", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -186,7 +187,7 @@ class Solver:
         self._chk(lib.tlvlbm_set_levelset(self.h, p1, p2), "set_levelset")
 
     def set_boundary(self, bid, type, ramp="const", T_r=1.0, given_as_displacement=False, a=None, G=None,
-                     p_radial=0.0, p_normal=0.0, X0=None):
+                     p_radial=0.0, p_normal=0.0, X0=None, twist=0.0):
         b = BC()
         b.type = {"dirichlet": DIRICHLET, "neumann": NEUMANN}.get(type, type)
         b.ramp = RAMPS.get(ramp, ramp)
@@ -202,6 +203,7 @@ class Solver:
         b.p_radial, b.p_normal = p_radial, p_normal
         for k, v in enumerate(X0 if X0 is not None else []):
             b.X0[k] = v
+        b.twist = float(twist)
         self._chk(lib.tlvlbm_set_boundary(self.h, int(bid), C.byref(b)), "set_boundary")
 
     def set_body_force(self, g, ramp="const", T_r=1.0):

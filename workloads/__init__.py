@@ -380,3 +380,36 @@ def config_affine_annulus(N=384):
     return dict(g, D=2, A=G, Xc=Xc, mu=1.0, lam=2.0 / 3.0, rho0=1.0, c=10.0, dt=dt, omega=2.0, gamma=0.0,
                 proj_every=20, U0=U0, dU0=dU0, T=T, steps=int(round(T / dt)),
                 bcs={1: dict(type="dirichlet", G=G, X0=(0.5, 0.5)), 2: dict(type="dirichlet", G=G, X0=(0.5, 0.5))})
+
+
+def config_tube(cells_per_unit=100):
+    """Finite tube under end stretch and twist (Sec. 5.3): R_i = 0.15 <= R <=
+    R_o = 0.30 about the axis (0.38, 0.38), 0 <= Z <= 3 (the paper's lattice
+    is 76 x 76 x 300 nodes at dx = 0.01, cells_per_unit = 100); both walls
+    traction free, the end Z = 0 clamped, the end Z = 3 displaced by
+    u_D = ((R(alpha) - I) X_perp, dL) with alpha = s(t) 45 deg,
+    dL = s(t) 0.5 L (half-cosine ramp, T_r = 10), relaxed to t = 100;
+    mu = 1, lambda = 2/3, omega = 1.8, gamma = 10, projection every 20 steps."""
+    dx = 1.0 / cells_per_unit
+    nxy = int(round(0.76 / dx))
+    nz = int(round(3.0 / dx))
+    n = [nxy + 2, nxy + 2, nz + 2]
+    origin = [-dx, -dx, -dx]
+    X = node_coords(n, dx, origin)
+    R = np.sqrt((X[0] - 0.38) ** 2 + (X[1] - 0.38) ** 2)
+    phi = np.maximum.reduce([0.15 - R, R - 0.30, -X[2], X[2] - 3.0])
+    bid = np.full(phi.shape, 2, np.uint8)
+    bid[R < 0.225] = 1
+    bid[X[2] < 0] = 3
+    bid[X[2] > 3.0] = 4
+    U0 = np.zeros((12, X.shape[1]))
+    for k in range(3):
+        U0[3 + 4 * k] = 1.0
+    dt = dx / 10.0
+    return dict(n=n, dx=dx, origin=origin, periodic_mask=0, phi=phi, bid=bid, X=X, D=3, mu=1.0, lam=2.0 / 3.0,
+                rho0=1.0, c=10.0, dt=dt, omega=1.8, gamma=10.0, proj_every=20, U0=U0, T=100.0,
+                steps=int(round(100.0 / dt)),
+                bcs={1: dict(type="neumann"), 2: dict(type="neumann"),
+                     3: dict(type="dirichlet", given_as_displacement=True),
+                     4: dict(type="dirichlet", given_as_displacement=True, ramp="halfcos", T_r=10.0,
+                             a=(0.0, 0.0, 1.5), twist=math.pi / 4, X0=(0.38, 0.38, 0.0))})

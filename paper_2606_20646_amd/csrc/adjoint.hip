@@ -88,8 +88,37 @@ __device__ __forceinline__ void block_acc2(double a, double b, double *slot) {
 // and (gm, gl) += a sum_q lam_q . d feq_q / d(mu, lambda).  With
 // mu_A = sum_q e_qA lam_q:  v_bar_i = S_vi/(2D) - mu_A[F_iA]/(2c),
 // F_bar = S_F/(2D) - dP(F)[W]/(2 c rho0), W_iA = mu_A[v_i].
+// The F-row part: CW = -a/(2 c rho0) dP(F)[W] and the parameter terms
+// (gm, gl) += -a/(2 c rho0) W : dP/d(mu, lambda), as two contractions:
+// dP/dmu = F - F^{-T}, dP/dlambda = (J^2 - 1)/2 F^{-T} (the fibre term has no
+// mu, lambda).
 template <int D>
-__device__ __forceinline__ void feq_vjp(const double (&lam)[2 * D][D + D * D], const double *F, const AdjPar &p,
+__device__ __forceinline__ void vjp_tangent(const double *F, const double *W, const AdjPar &p, double a, double *CW,
+                                            double &gm, double &gl) {
+  const double cf = -a * p.i2c * p.irho;
+  {
+    double C[D * D];
+    cofactor<D>(F, C);
+    const double J = det<D>(F), rJ = 1.0 / J;
+    double wf = 0.0, wg = 0.0;
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+      wf += W[k] * F[k];
+      wg += W[k] * (C[k] * rJ);
+    }
+    gm += cf * (wf - wg);
+    gl += cf * (0.5 * (J * J - 1.0) * wg);
+  }
+  piola_tangent<D>(F, W, p.mu, p.lam, CW);
+  if (p.k1 != 0.0) fibre_tangent_add<D>(F, W, p.k1, p.a0, CW);
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) CW[k] *= cf;
+}
+
+// lam holds the adjoint populations in their storage type E (register
+// pressure: 2D·M values); the arithmetic is FP64.
+template <int D, typename E>
+__device__ __forceinline__ void feq_vjp(const E (&lam)[2 * D][D + D * D], const double *F, const AdjPar &p,
                                         double a, double *Ub, double &gm, double &gl) {
   constexpr int Q = 2 * D, M = D + D * D;
   double W[D * D];
@@ -97,14 +126,14 @@ __device__ __forceinline__ void feq_vjp(const double (&lam)[2 * D][D + D * D], c
   for (int r = 0; r < M; ++r) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s += lam[q][r];
+    for (int q = 0; q < Q; ++q) s += double(lam[q][r]);
     Ub[r] += a * p.i2D * s;
   }
 #pragma unroll
   for (int A = 0; A < D; ++A) {
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      const double m = lam[2 * A][r] - lam[2 * A + 1][r];
+      const double m = double(lam[2 * A][r]) - double(lam[2 * A + 1][r]);
       if (r < D) {
         W[r * D + A] = m;
       } else {
@@ -113,44 +142,34 @@ __device__ __forceinline__ void feq_vjp(const double (&lam)[2 * D][D + D * D], c
       }
     }
   }
-  double CW[D * D], Pm[D * D], Pl[D * D];
-  piola_tangent<D>(F, W, p.mu, p.lam, CW);
-  if (p.k1 != 0.0) fibre_tangent_add<D>(F, W, p.k1, p.a0, CW);
-  piola<D>(F, 1.0, 0.0, Pm);  // dP/dmu = F - F^{-T} (the fibre term has no mu, lambda)
-  piola<D>(F, 0.0, 1.0, Pl);  // dP/dlambda = (J^2 - 1)/2 F^{-T}
-  const double cf = -a * p.i2c * p.irho;
-  double sm = 0.0, sl = 0.0;
+  double CW[D * D];
+  vjp_tangent<D>(F, W, p, a, CW, gm, gl);
 #pragma unroll
-  for (int k = 0; k < D * D; ++k) {
-    Ub[D + k] += cf * CW[k];
-    sm += W[k] * Pm[k];
-    sl += W[k] * Pl[k];
-  }
-  gm += cf * sm;
-  gl += cf * sl;
+  for (int k = 0; k < D * D; ++k) Ub[D + k] += CW[k];
 }
 
 template <int D, typename T>
 __device__ __forceinline__ void load_adj(const T *__restrict__ L, const Geo &g, int64_t node,
-                                         double (&lam)[2 * D][D + D * D]) {
+                                         T (&lam)[2 * D][D + D * D]) {
   constexpr int Q = 2 * D, M = D + D * D;
 #pragma unroll
   for (int q = 0; q < Q; ++q)
 #pragma unroll
-    for (int r = 0; r < M; ++r) lam[q][r] = double(L[(size_t)(q * M + r) * g.S + node]);
+    for (int r = 0; r < M; ++r) lam[q][r] = L[(size_t)(q * M + r) * g.S + node];
 }
 
 // push lam_f = (1 - omega) lam_fs + R^T Ub to the pull slots X - e_q
 template <int D, typename T>
 __device__ __forceinline__ void push_adj(T *__restrict__ Lin, const Geo &g, const AdjPar &p, int x, int y, int z,
-                                         const double (&lam)[2 * D][D + D * D], const double *Ub) {
+                                         const T (&lam)[2 * D][D + D * D], const double *Ub) {
   constexpr int Q = 2 * D, M = D + D * D;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t dst = minus_eq(g, x, y, z, q);
 #pragma unroll
     for (int r = 0; r < M; ++r)
-      Lin[(size_t)(q * M + r) * g.S + dst] = T((1.0 - p.om) * lam[q][r] + Ub[r] * (r < D ? p.inv_damp : 1.0));
+      Lin[(size_t)(q * M + r) * g.S + dst] =
+          T((1.0 - p.om) * double(lam[q][r]) + Ub[r] * (r < D ? p.inv_damp : 1.0));
   }
 }
 
@@ -192,40 +211,92 @@ __global__ __launch_bounds__(AT) void k_adj_seed(T *__restrict__ Lin, Geo g, Adj
 // ------------------------------------------------- bulk transpose (plain)
 // collision (Eq. 29) with the damping source, recovery (Eq. 28) and the
 // displacement history (Eq. 34): u = u* + dt/2 v, u*' = u + dt/2 v.
-template <int D, typename T, bool MASK, bool TRACK>
-__global__ __launch_bounds__(AT) void k_adj_bulk(const T *__restrict__ Lout, T *__restrict__ Lin, Geo g, AdjPar p,
+// CH: embedded bodies, over the list of 64-node chunks that hold active
+// nodes (one wavefront per chunk, as the forward update); else one block
+// per (row, x range).
+template <int D, typename T, bool MASK, bool TRACK, bool CH = false>
+__global__ __launch_bounds__(AT, 3) void k_adj_bulk(const T *__restrict__ Lout, T *__restrict__ Lin, Geo g, AdjPar p,
                                                  const uint8_t *__restrict__ act, const T *__restrict__ tape,
                                                  const double *__restrict__ ubc, double *__restrict__ lus,
-                                                 double *__restrict__ gblk) {
+                                                 double *__restrict__ gblk, const int32_t *__restrict__ chunks = nullptr,
+                                                 int nchunks = 0) {
   constexpr int Q = 2 * D, M = D + D * D;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, row = blockIdx.y;
+  int x, row;
+  bool live;
+  if constexpr (CH) {
+    const int ch = blockIdx.x * (AT / 64) + (threadIdx.x >> 6);
+    const int64_t i = ch < nchunks ? (int64_t)chunks[ch] * 64 + (threadIdx.x & 63) : g.N;
+    live = i < g.N;
+    x = live ? (int)(i % g.nx) : 0;
+    row = live ? (int)(i / g.nx) : 0;
+  } else {
+    x = blockIdx.x * blockDim.x + threadIdx.x;
+    row = blockIdx.y;
+    live = x < g.nx;
+  }
   const int64_t node = x + (int64_t)g.nx * row;
   double gm = 0.0, gl = 0.0;
-  if (x < g.nx && (!MASK || act[node])) {
+  if (live && (!MASK || act[node])) {
+    // the feq' transpose of feq_vjp (a = omega), arranged so that only the
+    // velocity rows of lam stay in registers: the F rows stream through one
+    // at a time and are pushed as soon as their U_bar is complete
     const int y = row % g.ny, z = row / g.ny;
-    double lam[Q][M], F[D * D], Ub[M];
-    load_adj<D, T>(Lout, g, node, lam);
-    tape_F<D, T>(tape, g, node, F);
+    const double a = p.om;
+    int64_t dst[Q];
 #pragma unroll
-    for (int r = 0; r < M; ++r) Ub[r] = 0.0;
-    feq_vjp<D>(lam, F, p, p.om, Ub, gm, gl);
+    for (int q = 0; q < Q; ++q) dst[q] = minus_eq(g, x, y, z, q);
+    T lv[Q][D];
+    double Sv[D], W[D * D], Ubv[D];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < D; ++i) lv[q][i] = Lout[(size_t)(q * M + i) * g.S + node];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       double s = 0.0;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) s += lam[q][i];
-      Ub[i] -= p.sig * p.gamma * s;
+      for (int q = 0; q < Q; ++q) s += double(lv[q][i]);
+      Sv[i] = s;
+      Ubv[i] = a * p.i2D * s;
+#pragma unroll
+      for (int A = 0; A < D; ++A) W[i * D + A] = double(lv[2 * A][i]) - double(lv[2 * A + 1][i]);
     }
+    double CW[D * D];
+    {
+      double F[D * D];
+      tape_F<D, T>(tape, g, node, F);
+      vjp_tangent<D>(F, W, p, a, CW, gm, gl);
+    }
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+      const int r = D + k, i = k / D, B = k % D;
+      T lr[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) lr[q] = Lout[(size_t)(q * M + r) * g.S + node];
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s += double(lr[q]);
+      const double ub = a * p.i2D * s + CW[k];
+      Ubv[i] -= a * p.i2c * (double(lr[2 * B]) - double(lr[2 * B + 1]));
+#pragma unroll
+      for (int q = 0; q < Q; ++q) Lin[(size_t)(q * M + r) * g.S + dst[q]] = T((1.0 - p.om) * double(lr[q]) + ub);
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) Ubv[i] -= p.sig * p.gamma * Sv[i];
     if (TRACK) {
 #pragma unroll
       for (int i = 0; i < D; ++i) {
         const double lu = lus[(size_t)i * g.S + node];
         const double ub = ubc[(size_t)i * g.S + node] + lu;
-        Ub[i] += p.hdt * (lu + ub);
+        Ubv[i] += p.hdt * (lu + ub);
         lus[(size_t)i * g.S + node] = ub;
       }
     }
-    push_adj<D, T>(Lin, g, p, x, y, z, lam, Ub);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+        Lin[(size_t)(q * M + i) * g.S + dst[q]] = T((1.0 - p.om) * double(lv[q][i]) + Ubv[i] * p.inv_damp);
   }
   block_acc2(gm, gl, gblk + 2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x));
 }
@@ -245,7 +316,8 @@ __global__ __launch_bounds__(AT) void k_adj_rep1(const T *__restrict__ Lout, Geo
   const int64_t node = x + (int64_t)g.nx * row;
   double gm = 0.0, gl = 0.0;
   if (x < g.nx && act[node]) {
-    double lam[Q][M], Fa[D * D], Fr[D * D], Ur[M], Ua[M];
+    T lam[Q][M];
+    double Fa[D * D], Fr[D * D], Ur[M], Ua[M];
     load_adj<D, T>(Lout, g, node, lam);
     tape_F<D, T>(tape, g, node, Fa);
 #pragma unroll
@@ -262,7 +334,7 @@ __global__ __launch_bounds__(AT) void k_adj_rep1(const T *__restrict__ Lout, Geo
     for (int i = 0; i < D; ++i) {
       double s = 0.0;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) s += lam[q][i];
+      for (int q = 0; q < Q; ++q) s += double(lam[q][i]);
       Ur[i] += -p.sig * p.gamma * s + p.hdt * lus[(size_t)i * g.S + node];
     }
 #pragma unroll
@@ -291,7 +363,8 @@ __global__ __launch_bounds__(AT) void k_adj_rep2(const T *__restrict__ Lout, T *
   const int64_t node = x + (int64_t)g.nx * row;
   if (!act[node]) return;
   const int y = row % g.ny, z = row / g.ny;
-  double lam[Q][M], Ub[M];
+  T lam[Q][M];
+  double Ub[M];
   load_adj<D, T>(Lout, g, node, lam);
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -315,6 +388,7 @@ template <int D, typename T, int PASS, bool NEU>
 __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, int64_t b0, int64_t b1, BC bc, Geo g,
                                                  Par par, double th, const T *__restrict__ tapeU,
                                                  const T *__restrict__ tapeFr, const double *__restrict__ tapeu,
+                                                 const int32_t *__restrict__ sc, int64_t nu,
                                                  double *__restrict__ gbar, double *__restrict__ glink) {
   constexpr int M = D + D * D;
   const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -367,9 +441,10 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
     for (int al = 0; al < D - 1; ++al)
       for (int i = 0; i < D; ++i) gv[al][i] = L.tang[l * 6 + al * 3 + i];
     for (int k = 0; k < np; ++k) {
-      const int64_t j = L.sidx[lsq_i(L, l, k)];
+      // the tape holds u at the Neumann stencil nodes only
+      const int64_t t = sc[lsq_i(L, l, k)];
       double uk[D];
-      for (int i = 0; i < D; ++i) uk[i] = tapeu[(size_t)i * g.S + j];
+      for (int i = 0; i < D; ++i) uk[i] = tapeu[(size_t)i * nu + t];
       for (int al = 0; al < D - 1; ++al) {
         const double wk = L.sw[lsq_w(L, l, al, k)];
         for (int i = 0; i < D; ++i) gv[al][i] += wk * uk[i];
@@ -430,7 +505,7 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
         Qt[k * D + i] = acc;  // (Q^T)_ki = Q_ik
       }
     }
-    if (!solve_small(D, Qt, hb, z))
+    if (!solve_small<D>(Qt, hb, z))
       for (int i = 0; i < D; ++i) z[i] = 0.0;
     double zN[D * D], CzN[D * D];
     for (int i = 0; i < D; ++i)
@@ -456,7 +531,7 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
 template <int D>
 __global__ __launch_bounds__(AT) void k_adj_ugather(int64_t ns, const int64_t *__restrict__ sn,
                                                     const int64_t *__restrict__ so, const int32_t *__restrict__ el,
-                                                    const int32_t *__restrict__ ek, Links L, Geo g,
+                                                    const double *__restrict__ ew, Geo g,
                                                     const double *__restrict__ gbar, double *__restrict__ ubc) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= ns) return;
@@ -464,9 +539,8 @@ __global__ __launch_bounds__(AT) void k_adj_ugather(int64_t ns, const int64_t *_
   for (int i = 0; i < D; ++i) acc[i] = 0.0;
   for (int64_t e = so[t]; e < so[t + 1]; ++e) {
     const int64_t l = el[e];
-    const int k = ek[e];
     for (int al = 0; al < D - 1; ++al) {
-      const double wk = L.sw[lsq_w(L, l, al, k)];
+      const double wk = ew[(size_t)e * (D - 1) + al];
       for (int i = 0; i < D; ++i) acc[i] += wk * gbar[l * 6 + al * 3 + i];
     }
   }
@@ -497,68 +571,90 @@ __global__ __launch_bounds__(AT) void k_pi_apply(Geo g, const uint8_t *__restric
 }
 
 // transpose of the projection's damped Jacobi sweeps (Sec. 3.5).  A sweep
-// x' = x + om Dg^-1 (b - K x) (Dg = diag K, K symmetric) has the transpose
-// x_bar = x'_bar - om K (Dg^-1 x'_bar), b_bar += om Dg^-1 x'_bar.
-// Pass 1: w = Dg^-1 z (0 where Dg = 0 or inactive), y (+)= om w.
+// x' = x + om D^+ (b - K x) (deg = diag K, D^+ = 1/deg where deg > 0 and 0
+// else, K symmetric) has the transpose z -> z - om K D^+ z, b_bar += om D^+ z.
+// In the scaled variable w = D^+ z one transposed sweep is
+//   b_bar += om w,  w <- (1 - om) w + om/deg sum_{active nbrs} w_j,
+// the forward sweep with b = 0; afterwards z = deg w, and z passes unchanged
+// through nodes with deg = 0.
+// degree and active neighbours of node i from its neighbour mask (bit q:
+// X + e_q active, bit 6: X active); 0 for an inactive node
 template <int D>
-__global__ __launch_bounds__(AT) void k_jacT_scale(Geo g, const uint8_t *__restrict__ act,
-                                                   const uint8_t *__restrict__ anc_n, const double *__restrict__ z,
-                                                   double *__restrict__ w, double *__restrict__ y, double om,
-                                                   int first) {
+__device__ __forceinline__ int jac_degree(const Geo &g, const uint8_t *__restrict__ nbm,
+                                          const uint8_t *__restrict__ anc_n, int64_t i, int64_t *nb) {
+  const unsigned m = nbm[i];
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q) nb[q] = -1;
+  if (!(m & 64u)) return 0;
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q)
+    if ((m >> q) & 1u) nb[q] = nb_index(g, i, q);
+  return (anc_n ? anc_n[i] : 0) + __builtin_popcount(m & ((1u << (2 * D)) - 1u));
+}
+
+// seed: z = ua + ub; w = D^+ z, zk = z where deg = 0 (else 0), b_bar = 0
+template <int D>
+__global__ __launch_bounds__(AT) void k_jacT_seedw(Geo g, const uint8_t *__restrict__ nbm,
+                                                   const uint8_t *__restrict__ anc_n, const double *__restrict__ ua,
+                                                   const double *__restrict__ ub, double *__restrict__ w,
+                                                   double *__restrict__ zk, double *__restrict__ y) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= g.N) return;
-  int deg = 0;
-  if (act[i]) {
-    const C3 cc = coords_of(g, i);
-    deg = anc_n ? anc_n[i] : 0;
-    for (int q = 0; q < 2 * D; ++q) {
-      const int64_t j = node_dir(g, cc, q, 1);
-      if (j >= 0 && act[j]) ++deg;
-    }
-  }
+  int64_t nb[2 * D];
+  const int deg = jac_degree<D>(g, nbm, anc_n, i, nb);
+  const bool a = (nbm[i] & 64u) != 0;
   for (int c = 0; c < D; ++c) {
     const size_t o = (size_t)c * g.S + i;
-    const double wi = deg ? z[o] / double(deg) : 0.0;
-    w[o] = wi;
-    y[o] = (first ? 0.0 : y[o]) + om * wi;
+    const double z = a ? ua[o] + (ub ? ub[o] : 0.0) : 0.0;
+    w[o] = deg ? z / double(deg) : 0.0;
+    zk[o] = deg ? 0.0 : z;
+    y[o] = 0.0;
   }
 }
 
-// pass 2: z -= om K w on active nodes
+// one transposed sweep over the active tiles (XCD-contiguous tile ranges,
+// as the forward sweep)
 template <int D>
-__global__ __launch_bounds__(AT) void k_jacT_apply(Geo g, const uint8_t *__restrict__ act,
-                                                   const uint8_t *__restrict__ anc_n, const double *__restrict__ w,
-                                                   double *__restrict__ z, double om) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= g.N || !act[i]) return;
-  const C3 cc = coords_of(g, i);
+__global__ __launch_bounds__(AT) void k_jacT_sweep(Geo g, const uint8_t *__restrict__ nbm,
+                                                   const uint8_t *__restrict__ anc_n, const double *__restrict__ win,
+                                                   double *__restrict__ wout, double *__restrict__ y, double om,
+                                                   const int32_t *__restrict__ tiles, int ntile, int per) {
+  const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (t >= ntile) return;
+  const int64_t i = (tiles ? (int64_t)tiles[t] : (int64_t)t) * AT + threadIdx.x;
+  if (i >= g.N || !(nbm[i] & 64u)) return;
   int64_t nb[2 * D];
-  int deg = anc_n ? anc_n[i] : 0;
-  for (int q = 0; q < 2 * D; ++q) {
-    nb[q] = node_dir(g, cc, q, 1);
-    if (nb[q] >= 0 && !act[nb[q]]) nb[q] = -1;
-    if (nb[q] >= 0) ++deg;
-  }
+  const int deg = jac_degree<D>(g, nbm, anc_n, i, nb);
   for (int c = 0; c < D; ++c) {
     const size_t o = (size_t)c * g.S;
-    double kw = double(deg) * w[o + i];
+    const double wi = win[o + i];
+    y[o + i] += om * wi;
+    if (deg == 0) {
+      wout[o + i] = 0.0;
+      continue;
+    }
+    double s = 0.0;
     for (int q = 0; q < 2 * D; ++q)
-      if (nb[q] >= 0) kw -= w[o + nb[q]];
-    z[o + i] -= om * kw;
+      if (nb[q] >= 0) s += win[o + nb[q]];
+    wout[o + i] = (1.0 - om) * wi + om * s / double(deg);
   }
 }
 
-// z = ua + ub on active nodes, 0 elsewhere
+// z = deg w + zk (the start's adjoint) on the tiles' active nodes
 template <int D>
-__global__ __launch_bounds__(AT) void k_jacT_seed(Geo g, const uint8_t *__restrict__ act,
-                                                  const double *__restrict__ ua, const double *__restrict__ ub,
-                                                  double *__restrict__ z) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= g.N) return;
-  const bool a = act[i];
+__global__ __launch_bounds__(AT) void k_jacT_final(Geo g, const uint8_t *__restrict__ nbm,
+                                                   const uint8_t *__restrict__ anc_n, const double *__restrict__ w,
+                                                   double *__restrict__ zk, const int32_t *__restrict__ tiles,
+                                                   int ntile) {
+  const int t = blockIdx.x;
+  if (t >= ntile) return;
+  const int64_t i = (tiles ? (int64_t)tiles[t] : (int64_t)t) * AT + threadIdx.x;
+  if (i >= g.N || !(nbm[i] & 64u)) return;
+  int64_t nb[2 * D];
+  const int deg = jac_degree<D>(g, nbm, anc_n, i, nb);
   for (int c = 0; c < D; ++c) {
     const size_t o = (size_t)c * g.S + i;
-    z[o] = a ? ua[o] + (ub ? ub[o] : 0.0) : 0.0;
+    zk[o] += double(deg) * w[o];
   }
 }
 
@@ -773,7 +869,8 @@ struct Run {
   // stencil gather
   int64_t ns = 0;
   int64_t *sn = nullptr, *so = nullptr;
-  int32_t *el = nullptr, *ek = nullptr;
+  int32_t *el = nullptr, *sc = nullptr;
+  double *ew = nullptr;
 };
 
 template <int D, typename T> void launch_link_pass(Run &R, int pass, double th, const TapeStep &tp) {
@@ -787,7 +884,7 @@ template <int D, typename T> void launch_link_pass(Run &R, int pass, double th, 
     const double *tu = (const double *)tp.u;
 #define TL_LINK(P, NN)                                                                                         \
   hipLaunchKernelGGL((k_adj_link<D, T, P, NN>), nb, 64, 0, c->st, (T *)R.La, c->L, b0, b1, c->bcs[b], c->geo, \
-                     c->par, th, tU, tF, tu, R.gbar, R.glink)
+                     c->par, th, tU, tF, tu, R.sc, R.ns, R.gbar, R.glink)
     if (pass == 1) {
       if (neu) TL_LINK(1, true);
       else TL_LINK(1, false);
@@ -814,13 +911,18 @@ template <int D> int solve_adj(Run &R, const double *ua, const double *ub) {
     // side's adjoint) in w.x, the start's adjoint in x0b
     const uint8_t *an = R.dir ? G.anc_n : nullptr;
     const unsigned nb = nblocks(g.N, AT);
-    hipLaunchKernelGGL((k_jacT_seed<D>), nb, AT, 0, c->st, g, c->act, ua, ub, R.x0b);
+    const int nt = w.tiles ? w.ntiles : (int)nb;
+    const int per = (nt + 7) / 8;
+    double *wa = (double *)w.p0, *wb = (double *)w.r;
+    if (!w.nbm) return TLVLBM_ERR_DEVICE;
+    hipLaunchKernelGGL((k_jacT_seedw<D>), nb, AT, 0, c->st, g, w.nbm, an, ua, ub, wa, R.x0b, (double *)w.x);
     for (int k = 0; k < c->proj_sweeps; ++k) {
-      hipLaunchKernelGGL((k_jacT_scale<D>), nb, AT, 0, c->st, g, c->act, an, (const double *)R.x0b,
-                         (double *)w.p0, (double *)w.x, c->proj_weight, k == 0 ? 1 : 0);
-      hipLaunchKernelGGL((k_jacT_apply<D>), nb, AT, 0, c->st, g, c->act, an, (const double *)w.p0, R.x0b,
-                         c->proj_weight);
+      hipLaunchKernelGGL((k_jacT_sweep<D>), (unsigned)(per * 8), AT, 0, c->st, g, w.nbm, an, (const double *)wa,
+                         wb, (double *)w.x, c->proj_weight, w.tiles, nt, per);
+      std::swap(wa, wb);
     }
+    hipLaunchKernelGGL((k_jacT_final<D>), (unsigned)nt, AT, 0, c->st, g, w.nbm, an, (const double *)wa, R.x0b,
+                       w.tiles, nt);
     return hipGetLastError() == hipSuccess ? TLVLBM_OK : TLVLBM_ERR_DEVICE;
   }
   gauge_means(c, ua, ub, G.mean);
@@ -855,13 +957,21 @@ template <int D, typename T> int reverse_step(Run &R, int64_t k, const TapeStep 
     launch_link_pass<D, T>(R, 3, th, tp);
   }
   if (R.ns)
-    hipLaunchKernelGGL((k_adj_ugather<D>), nblocks(R.ns, AT), AT, 0, c->st, R.ns, R.sn, R.so, R.el, R.ek, c->L, g,
+    hipLaunchKernelGGL((k_adj_ugather<D>), nblocks(R.ns, AT), AT, 0, c->st, R.ns, R.sn, R.so, R.el, R.ew, g,
                        R.gbar, R.ubc);
   const T *Lout = (const T *)R.La;
   T *Lin = (T *)R.Lb;
   if (!proj) {
     const T *tU = (const T *)tp.U;
-    if (c->act) {
+    if (c->act && c->chunks) {
+      const unsigned nb = (unsigned)((c->nchunks + AT / 64 - 1) / (AT / 64));
+      if (c->track_u)
+        hipLaunchKernelGGL((k_adj_bulk<D, T, true, true, true>), nb, AT, 0, c->st, Lout, Lin, g, R.ap, c->act, tU,
+                           R.ubc, R.lus, R.gblk, c->chunks, c->nchunks);
+      else
+        hipLaunchKernelGGL((k_adj_bulk<D, T, true, false, true>), nb, AT, 0, c->st, Lout, Lin, g, R.ap, c->act, tU,
+                           R.ubc, R.lus, R.gblk, c->chunks, c->nchunks);
+    } else if (c->act) {
       if (c->track_u)
         hipLaunchKernelGGL((k_adj_bulk<D, T, true, true>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act, tU,
                            R.ubc, R.lus, R.gblk);
@@ -904,10 +1014,13 @@ template <int D, typename T> int reverse_step(Run &R, int64_t k, const TapeStep 
 // (link, point) order within each node, so the gather is deterministic
 int stencil_transpose(tlvlbm_ctx *c) {
   const int64_t nl = c->L.n, N = c->geo.N;
+  const int D = c->D;
   std::vector<int32_t> lnp(nl), sidx((size_t)nl * c->L.kmax);
+  std::vector<double> sw((size_t)nl * c->L.kmax * (D - 1));
   if (nl) {
     if (hipMemcpy(lnp.data(), c->L.npts, nl * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(sidx.data(), c->L.sidx, sidx.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(sidx.data(), c->L.sidx, sidx.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(sw.data(), c->L.sw, sw.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
       return TLVLBM_ERR_DEVICE;
   }
   std::vector<uint8_t> is_neu(nl, 0);
@@ -934,17 +1047,33 @@ int stencil_transpose(tlvlbm_ctx *c) {
       }
   for (int64_t j : sn) so.push_back(cnt[j]);
   so.push_back(ne);
+  // tangent weights in entry order; compact tape index of every stencil slot
+  std::vector<double> ew((size_t)ne * (D - 1));
+  for (int64_t e = 0; e < ne; ++e)
+    for (int al = 0; al < D - 1; ++al) ew[(size_t)e * (D - 1) + al] = sw[lsq_w(c->L, el[e], al, ek[e])];
+  std::vector<int32_t> sc(sidx.size(), 0);
+  {
+    std::vector<int32_t> at(N, -1);
+    for (size_t t = 0; t < sn.size(); ++t) at[sn[t]] = (int32_t)t;
+    for (int64_t l = 0; l < nl; ++l)
+      if (is_neu[l])
+        for (int k = 0; k < lnp[l]; ++k) sc[lsq_i(c->L, l, k)] = at[sidx[lsq_i(c->L, l, k)]];
+  }
   StencilT *T = new (std::nothrow) StencilT();
   if (!T) return TLVLBM_ERR_OUT_OF_MEMORY;
   T->ns = (int64_t)sn.size();
   if (T->ns) {
     if (hipMalloc(&T->sn, sn.size() * sizeof(int64_t)) || hipMalloc(&T->so, so.size() * sizeof(int64_t)) ||
         hipMalloc(&T->el, el.size() * sizeof(int32_t)) || hipMalloc(&T->ek, ek.size() * sizeof(int32_t)) ||
+        hipMalloc(&T->ew, ew.size() * sizeof(double)) || hipMalloc(&T->sc, sc.size() * sizeof(int32_t)) ||
         hipMemcpy(T->sn, sn.data(), sn.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
         hipMemcpy(T->so, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
         hipMemcpy(T->el, el.data(), el.size() * sizeof(int32_t), hipMemcpyHostToDevice) ||
-        hipMemcpy(T->ek, ek.data(), ek.size() * sizeof(int32_t), hipMemcpyHostToDevice)) {
-      for (void *p : {(void *)T->sn, (void *)T->so, (void *)T->el, (void *)T->ek}) (void)hipFree(p);
+        hipMemcpy(T->ek, ek.data(), ek.size() * sizeof(int32_t), hipMemcpyHostToDevice) ||
+        hipMemcpy(T->ew, ew.data(), ew.size() * sizeof(double), hipMemcpyHostToDevice) ||
+        hipMemcpy(T->sc, sc.data(), sc.size() * sizeof(int32_t), hipMemcpyHostToDevice)) {
+      for (void *p : {(void *)T->sn, (void *)T->so, (void *)T->el, (void *)T->ek, (void *)T->ew, (void *)T->sc})
+        (void)hipFree(p);
       delete T;
       return TLVLBM_ERR_OUT_OF_MEMORY;
     }
@@ -981,7 +1110,8 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
                 pp.k1,
                 {pp.a0[0], pp.a0[1], pp.a0[2]}};
   grid_of(g, R.grid, R.block);
-  R.nblk = (size_t)R.grid.x * R.grid.y;
+  // per-block parameter-gradient slots: row blocks and chunk blocks
+  R.nblk = std::max((size_t)R.grid.x * R.grid.y, (size_t)(c->nchunks + AT / 64 - 1) / (AT / 64));
   for (int b = 0; b < 256; ++b) {
     if (c->bid_end[b] <= c->bid_begin[b]) continue;
     if (c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION) R.neu = true;
@@ -989,8 +1119,16 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   }
   const bool track = c->track_u;
   const size_t plane = (size_t)g.S * sizeof(T), dplane = (size_t)g.S * sizeof(double);
+  // transposed Neumann stencils: the gather of u_bar, and the nodes whose
+  // displacement the tape keeps
+  if (c->act && R.neu && !c->stT) {
+    const int s = stencil_transpose(c);
+    if (s) return (tlvlbm_status)s;
+  }
+  const int64_t nu = (R.neu && c->stT) ? c->stT->ns : 0;
   const size_t ck_bytes = (size_t)Q * M * plane + (track ? D * dplane : 0);
-  const size_t tape_bytes = (size_t)M * plane + (R.neu ? D * dplane : 0);
+  const size_t tapeu_bytes = (size_t)D * std::max<int64_t>(nu, 1) * sizeof(double);
+  const size_t tape_bytes = (size_t)M * plane + (R.neu ? tapeu_bytes : 0);
   if (seg <= 0) {
     seg = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(n, 1) * (double)ck_bytes / (double)tape_bytes));
     seg = std::max<int64_t>(1, std::min<int64_t>(seg, std::max<int64_t>(n, 1)));
@@ -1006,6 +1144,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     size_t need = (size_t)(nck + 1) * ck_bytes + (size_t)seg * tape_bytes + (size_t)nproj_seg * D * D * plane +
                   2 * (size_t)Q * M * plane + 2 * (size_t)D * dplane;
     if (R.neu) need += (size_t)(M + 3 * D * D + 2 * D) * dplane;
+    if (nu) need += (size_t)nu * (3 * 8 + 8 * (D + 1)) + (size_t)c->L.n * c->L.kmax * 4;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && need > fr) {
       err = "adjoint: checkpoints and tape do not fit in device memory (lower the step count or pass a segment length)";
@@ -1099,12 +1238,13 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     R.sn = c->stT->sn;
     R.so = c->stT->so;
     R.el = c->stT->el;
-    R.ek = c->stT->ek;
+    R.ew = c->stT->ew;
+    R.sc = c->stT->sc;
   }
   // per-step tape of one segment
   char *tapeU = nullptr, *tapeu = nullptr, *tapeF = nullptr;
   if (pool.get(&tapeU, (size_t)seg * M * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-  if (R.neu && pool.get(&tapeu, (size_t)seg * D * dplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+  if (R.neu && pool.get(&tapeu, (size_t)seg * tapeu_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
   if (nproj_seg && pool.get(&tapeF, (size_t)nproj_seg * D * D * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
   // seeds
   {
@@ -1136,7 +1276,10 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     for (int64_t k = k0; k < k1; ++k) {
       TapeStep &tp = tps[k - k0];
       tp.U = tapeU + (size_t)(k - k0) * M * plane;
-      tp.u = R.neu ? tapeu + (size_t)(k - k0) * D * dplane : nullptr;
+      // (no stencil node: no Neumann link reads the displacement)
+      tp.u = (R.neu && R.ns) ? tapeu + (size_t)(k - k0) * tapeu_bytes : nullptr;
+      tp.un = R.sn;
+      tp.nu = R.ns;
       tp.Fr = nullptr;
       xs_of(k, tp, 2);
       if (is_projection_step(c, k)) {

@@ -119,9 +119,14 @@ int step_once(tlvlbm_ctx *c, const TapeStep *tp) {
     launch_bulk(c, false, tp ? tp->U : nullptr);
   }
   if (c->L.n) launch_cutlinks(c, tn);
-  if (tp && tp->u)
-    CHK(hipMemcpyAsync(tp->u, c->ubuf, (size_t)c->D * c->geo.S * sizeof(double), hipMemcpyDeviceToDevice, c->st),
-        "tape");
+  if (tp && tp->u) {
+    if (tp->un) {
+      if (tp->nu) launch_gather_u(c, tp->un, tp->nu, (double *)tp->u);
+    } else {
+      CHK(hipMemcpyAsync(tp->u, c->ubuf, (size_t)c->D * c->geo.S * sizeof(double), hipMemcpyDeviceToDevice, c->st),
+          "tape");
+    }
+  }
   std::swap(c->fA, c->fB);
   ++c->step;
   return TLVLBM_OK;
@@ -233,7 +238,7 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
                   c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles,
-                  c->bf, c->chunks};
+                  c->cg.nbm, c->bf, c->chunks};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);

@@ -375,6 +375,20 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks(const T *__r
                                                     bf, bs);
 }
 
+// the chunked update recording the recovered state on the reverse-mode tape
+template <int D, typename T, bool TRACK, bool REPAIR, bool EXT>
+__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks_tape(
+    const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p, const uint8_t *__restrict__ act,
+    double *__restrict__ ustar, double *__restrict__ ubuf, const T *__restrict__ Frp, int *__restrict__ flag,
+    T *__restrict__ tape, const int32_t *__restrict__ chunks, int nchunks) {
+  const int ch = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (ch >= nchunks) return;
+  const int64_t i = (int64_t)chunks[ch] * 64 + (threadIdx.x & 63);
+  if (i >= g.N) return;
+  const int x = (int)(i % g.nx), row = (int)(i / g.nx);
+  bulk_node<D, T, true, TRACK, REPAIR, true, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, tape);
+}
+
 // Batched bulk update: one block per tile (instance, row, first x) of the
 // tile list; every instance keeps its own geometry, material and buffers.
 template <int D, typename T, bool REPAIR>
@@ -667,6 +681,19 @@ template <int D, typename T, bool EXT> static void bulk_tape_t(tlvlbm_ctx *c, bo
   const T *Fr = (const T *)c->cg.Fr;
   T *tp = (T *)tape;
   const T *nb = nullptr;
+  if (c->act && c->chunks) {
+    const unsigned nblk = (unsigned)((c->nchunks + 3) / 4);
+    if (repair)
+      hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, true, true, EXT>), nblk, 256, 0, c->st, fin, fout, c->geo,
+                         c->par, c->act, us, ub, Fr, c->d_flag, tp, c->chunks, c->nchunks);
+    else if (c->track_u)
+      hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, true, false, EXT>), nblk, 256, 0, c->st, fin, fout, c->geo,
+                         c->par, c->act, us, ub, Fr, c->d_flag, tp, c->chunks, c->nchunks);
+    else
+      hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, false, false, EXT>), nblk, 256, 0, c->st, fin, fout, c->geo,
+                         c->par, c->act, us, ub, Fr, c->d_flag, tp, c->chunks, c->nchunks);
+    return;
+  }
   if (repair)
     hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, true, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                        c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));

@@ -822,6 +822,38 @@ __device__ __forceinline__ void jacobi_node(const Geo &g, const uint8_t *__restr
   }
 }
 
+// the same sweep from the precomputed neighbour mask (bit q: X + e_q active,
+// bit 6: X active); the same operations in the same order
+template <int D>
+__device__ __forceinline__ void jacobi_node_m(const Geo &g, const uint8_t *__restrict__ nbm,
+                                              const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
+                                              const double *__restrict__ xin, double *__restrict__ xout, double om,
+                                              int64_t i) {
+  if (i >= g.N) return;
+  const unsigned m = nbm[i];
+  int deg = 0;
+  int64_t nb[2 * D];
+  if (m & 64u) {
+    deg = (anc_n ? anc_n[i] : 0) + __builtin_popcount(m & ((1u << (2 * D)) - 1u));
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q) nb[q] = ((m >> q) & 1u) ? nb_index(g, i, q) : -1;
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const size_t o = (size_t)c * g.S;
+    const double xi = xin[o + i];
+    if (deg == 0) {
+      xout[o + i] = xi;
+      continue;
+    }
+    double kx = double(deg) * xi;
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q)
+      if (nb[q] >= 0) kx -= xin[o + nb[q]];
+    xout[o + i] = xi + om * (b[o + i] - kx) / double(deg);
+  }
+}
+
 // compatible gradient F^c = I + grad_dx u^c (Eq. 59) and F^r = (1-theta) F +
 // theta F^c (Eq. 60): centred differences, one-sided next to a cut, the
 // evolved column kept when neither neighbour is active
@@ -988,14 +1020,14 @@ __global__ __launch_bounds__(256) void k_ureset(Geo g, const uint8_t *__restrict
 // range of tiles and finds the neighbour rows and planes of x in its own L2.
 constexpr int NXCD = 8;
 template <int D>
-__global__ __launch_bounds__(CG_T) void k_jacobi(Geo g, const uint8_t *__restrict__ act,
+__global__ __launch_bounds__(CG_T) void k_jacobi(Geo g, const uint8_t *__restrict__ nbm,
                                                  const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
                                                  const double *__restrict__ xin, double *__restrict__ xout, double om,
                                                  const int32_t *__restrict__ tiles, int ntile, int per) {
   const int t = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
   if (t >= ntile) return;
   const int64_t blk = tiles ? (int64_t)tiles[t] : (int64_t)t;
-  jacobi_node<D>(g, act, anc_n, b, xin, xout, om, blk * CG_T + threadIdx.x);
+  jacobi_node_m<D>(g, nbm, anc_n, b, xin, xout, om, blk * CG_T + threadIdx.x);
 }
 
 template <int D>
@@ -1134,6 +1166,21 @@ template <int D, typename T> static void cutlinks_t(tlvlbm_ctx *c, double tn) {
   }
 }
 
+// the displacement at the Neumann stencil nodes, for the reverse-mode tape
+__global__ __launch_bounds__(256) void k_gather_u(const double *__restrict__ u, int64_t S, int D,
+                                                  const int64_t *__restrict__ un, int64_t nu,
+                                                  double *__restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nu) return;
+  const int64_t j = un[t];
+  for (int i = 0; i < D; ++i) out[(size_t)i * nu + t] = u[(size_t)i * S + j];
+}
+
+void launch_gather_u(tlvlbm_ctx *c, const int64_t *un, int64_t nu, double *out) {
+  hipLaunchKernelGGL(k_gather_u, nblk(nu, 256), 256, 0, c->st, (const double *)c->ubuf, c->geo.S, c->D, un, nu,
+                     out);
+}
+
 void launch_cutlinks(tlvlbm_ctx *c, double tn) {
   if (c->D == 2) {
     if (c->prec) cutlinks_t<2, double>(c, tn);
@@ -1263,11 +1310,12 @@ template <int D> static int jacobi_run(tlvlbm_ctx *c, const uint8_t *anc_n) {
     const int s = proj_aux_build(c);
     if (s) return s;
   }
+  if (!w.nbm) return TLVLBM_ERR_DEVICE;
   const unsigned nt = w.tiles ? (unsigned)w.ntiles : nblk(g.N, CG_T);
   const int per = (int)((nt + NXCD - 1) / NXCD);
   double *a = (double *)w.x, *bb = (double *)w.r;
   for (int k = 0; k < c->proj_sweeps; ++k) {
-    hipLaunchKernelGGL((k_jacobi<D>), (unsigned)(per * NXCD), CG_T, 0, st, g, c->act, anc_n, (const double *)w.b,
+    hipLaunchKernelGGL((k_jacobi<D>), (unsigned)(per * NXCD), CG_T, 0, st, g, w.nbm, anc_n, (const double *)w.b,
                        (const double *)a, bb, c->proj_weight, w.tiles, (int)nt, per);
     std::swap(a, bb);
   }

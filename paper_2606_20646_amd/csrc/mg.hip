@@ -549,7 +549,9 @@ void proj_aux_free(tlvlbm_ctx *c) {
   if (c->cg.pcg_graph) (void)hipGraphExecDestroy(c->cg.pcg_graph);
   c->cg.pcg_graph = nullptr;
   if (c->stT) {
-    for (void *p : {(void *)c->stT->sn, (void *)c->stT->so, (void *)c->stT->el, (void *)c->stT->ek}) (void)hipFree(p);
+    for (void *p : {(void *)c->stT->sn, (void *)c->stT->so, (void *)c->stT->el, (void *)c->stT->ek,
+                    (void *)c->stT->ew, (void *)c->stT->sc})
+      (void)hipFree(p);
     delete c->stT;
     c->stT = nullptr;
   }
@@ -590,6 +592,31 @@ int proj_aux_build(tlvlbm_ctx *c) {
     if (c->cg.tiles) (void)hipFree(c->cg.tiles);
     c->cg.tiles = nullptr;
     c->cg.ntiles = 0;
+    // neighbour masks of the active-node graph: the Jacobi sweeps read one
+    // byte per node instead of the seven activity flags and coordinates
+    std::vector<uint8_t> nbm(N, 0);
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    for (int64_t i = 0; i < N; ++i) {
+      if (!act[i]) continue;
+      const int c3[3] = {(int)(i % g.nx), (int)((i / g.nx) % g.ny), (int)(i / nxy)};
+      const int n3[3] = {g.nx, g.ny, g.nz};
+      uint8_t m = 64;
+      for (int q = 0; q < 2 * c->D; ++q) {
+        int v[3] = {c3[0], c3[1], c3[2]};
+        const int A = q / 2;
+        v[A] += (q & 1) ? -1 : 1;
+        if (v[A] < 0 || v[A] >= n3[A]) {
+          if (!((g.per >> A) & 1)) continue;
+          v[A] = (v[A] + n3[A]) % n3[A];
+        }
+        if (act[v[0] + (int64_t)g.nx * (v[1] + (int64_t)g.ny * v[2])]) m |= (uint8_t)(1u << q);
+      }
+      nbm[i] = m;
+    }
+    if (c->cg.nbm) (void)hipFree(c->cg.nbm);
+    c->cg.nbm = nullptr;
+    if (hipMalloc(&c->cg.nbm, N) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (hipMemcpy(c->cg.nbm, nbm.data(), N, hipMemcpyHostToDevice) != hipSuccess) return TLVLBM_ERR_DEVICE;
     if (!tiles.empty()) {
       if (hipMalloc(&c->cg.tiles, tiles.size() * sizeof(int32_t)) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
       if (hipMemcpy(c->cg.tiles, tiles.data(), tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)

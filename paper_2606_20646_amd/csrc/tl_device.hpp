@@ -44,6 +44,15 @@ __device__ __forceinline__ int64_t node_dir(const Geo &g, C3 c, int q, int mult)
   return node_at(g, c, A == 0 ? sg * mult : 0, A == 1 ? sg * mult : 0, A == 2 ? sg * mult : 0);
 }
 
+// node X + e_q of node i when that neighbour exists (the caller has checked
+// bit q of the neighbour mask): fixed offsets in a box without periodic axes
+__device__ __forceinline__ int64_t nb_index(const Geo &g, int64_t i, int q) {
+  if (g.per) return node_dir(g, coords_of(g, i), q, 1);
+  const int64_t nxy = (int64_t)g.nx * g.ny;
+  const int64_t off = (q < 2) ? 1 : (q < 4 ? (int64_t)g.nx : nxy);
+  return (q & 1) ? i - off : i + off;
+}
+
 // ------------------------------------------------- boundary data (FP64)
 
 __host__ __device__ __forceinline__ void ramp_eval(int kind, double Tr, double t, double &s, double &ds) {
@@ -108,33 +117,21 @@ template <int D> __device__ __forceinline__ void bc_base(const BC &b, const doub
   }
 }
 
-// small dense solve (n <= 3) by Gaussian elimination with partial pivoting
-__device__ inline bool solve_small(int n, double *A, double *b, double *x) {
-  for (int k = 0; k < n; ++k) {
-    int pv = k;
-    for (int i = k + 1; i < n; ++i)
-      if (fabs(A[i * n + k]) > fabs(A[pv * n + k])) pv = i;
-    if (A[pv * n + k] == 0.0) return false;
-    if (pv != k) {
-      for (int j = 0; j < n; ++j) {
-        double t = A[k * n + j];
-        A[k * n + j] = A[pv * n + j];
-        A[pv * n + j] = t;
-      }
-      double t = b[k];
-      b[k] = b[pv];
-      b[pv] = t;
-    }
-    for (int i = k + 1; i < n; ++i) {
-      const double lf = A[i * n + k] / A[k * n + k];
-      for (int j = k; j < n; ++j) A[i * n + j] -= lf * A[k * n + j];
-      b[i] -= lf * b[k];
-    }
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double s = b[i];
-    for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
-    x[i] = s / A[i * n + i];
+// small dense solve A x = b (D <= 3) by the adjugate, x = cof(A)^T b / det A:
+// fixed register arrays (no dynamically indexed pivoting); false when det A
+// is zero or not finite
+template <int D> __device__ inline bool solve_small(const double *A, const double *b, double *x) {
+  double C[D * D];
+  cofactor<D>(A, C);
+  const double dA = det<D>(A);
+  if (!(dA != 0.0) || !isfinite(dA)) return false;
+  const double r = 1.0 / dA;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) s += C[j * D + i] * b[j];
+    x[i] = s * r;
   }
   return true;
 }
@@ -203,7 +200,7 @@ __device__ inline bool newton_h(const double *N, const double *Gt, const double 
       }
     }
     for (int i = 0; i < D; ++i) mR[i] = -R[i];
-    if (!solve_small(D, Qm, mR, dh)) return false;
+    if (!solve_small<D>(Qm, mR, dh)) return false;
     double step = 1.0;
     bool acc = false;
     for (int ls = 0; ls <= 10; ++ls) {

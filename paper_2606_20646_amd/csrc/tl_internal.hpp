@@ -99,9 +99,11 @@ struct Gauge {
 // LSQ stencils of the Neumann links transposed to their nodes (reverse
 // mode): node sn[t] receives entries so[t] .. so[t+1]-1 = (link el, point ek)
 struct StencilT {
-  int64_t ns = 0;
-  int64_t *sn = nullptr, *so = nullptr;
-  int32_t *el = nullptr, *ek = nullptr;
+  int64_t ns = 0;                       // distinct stencil nodes of the Neumann links
+  int64_t *sn = nullptr, *so = nullptr; // their node indices (sorted), entry offsets
+  int32_t *el = nullptr, *ek = nullptr; // per entry: link, point
+  double *ew = nullptr;                 // per entry: the D - 1 tangent weights
+  int32_t *sc = nullptr;                // per stencil slot lsq_i(l, k): index into sn
 };
 
 // device blocks of the reverse mode, kept between calls of the same shape
@@ -124,6 +126,7 @@ struct CG {
   double *partial = nullptr;                        // [nblk][16] block partial sums
   int32_t *tiles = nullptr;                         // 256-node tiles holding active nodes
   int ntiles = 0;
+  uint8_t *nbm = nullptr;  // per node: bit q = neighbour X + e_q active, bit 6 = node active
   hipGraphExec_t pcg_graph = nullptr;               // captured batch of preconditioned iterations
   const void *pcg_key = nullptr;                    // anchor array it was captured with
   double *scal = nullptr;                           // device scalars
@@ -345,10 +348,15 @@ void gauge_restore(tlvlbm_ctx *c, double *x, const double *mean0);
 // links [D planes]; any may be null
 struct TapeStep {
   void *U, *Fr;   // recovered (v, F - I) and repaired F, population precision
-  void *u;        // displacement seen by the cut links, FP64
+  void *u;        // displacement seen by the cut links, FP64: u[i * nu + t] at
+                  // node un[t] (the Neumann stencil nodes), or whole planes
+  const int64_t *un = nullptr;
+  int64_t nu = 0;
   double *xs[2];  // projection solutions of the step (see run_projection)
   int xmode;
 };
+// out[i * nu + t] = u_i at node un[t] (embed.hip)
+void launch_gather_u(tlvlbm_ctx *c, const int64_t *un, int64_t nu, double *out);
 // one step of Algorithm 1 (api.hip)
 int step_once(tlvlbm_ctx *c, const TapeStep *tp = nullptr);
 bool is_projection_step(const tlvlbm_ctx *c, int64_t step);

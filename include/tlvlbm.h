@@ -252,17 +252,24 @@ const char *tlvlbm_last_error(const tlvlbm_ctx *ctx);
  *  - grad_mat[2] (host): dL/dmu, dL/dlambda.  grad_v0, grad_u0 [D][nodes]
  *    FP64 host or device, or NULL: dL/dv0 (the velocity rows of U0) and
  *    dL/du0; F0 and dU0 are held fixed.
- *  - segment: steps between checkpoints of the stored field (<= 0: about
- *    sqrt(n x checkpoint size / tape size per step)).  Device memory:
- *    (n/segment + 1) checkpoints (Q M + D node planes) plus a tape of
- *    segment x (M [+ D]) node planes; TLVLBM_ERR_OUT_OF_MEMORY if they do
- *    not fit.  When a quarter of the remaining memory holds them, the
- *    projection solutions of the first pass are kept (FP64, active tiles)
- *    and replayed by the recomputation.  This memory stays with the context
- *    (reused by the next call with the same n and segment) until
- *    tlvlbm_destroy or a call of another shape.  Work: one forward pass,
- *    one recomputation without projection solves, one reverse pass (two CG
- *    solves per projection step).
+ *  - segment: the schedule.  > 0: a checkpoint of the stored field (Q M + D
+ *    node planes) every `segment` steps; each segment is recomputed once
+ *    with its tape.  0: the last steps keep their tape from the first pass
+ *    (as many as 60% of the free device memory holds: all of them for
+ *    short runs), and only the steps before them are checkpointed and
+ *    recomputed, in segments of about sqrt(steps x checkpoint / tape step).
+ *    < 0: as 0 with at most -segment taped final steps.  Tape per step:
+ *    D x D planes of F - I over the 64-node chunks that hold active nodes
+ *    (population precision), F^r likewise on projection steps, and u at the
+ *    Neumann stencil nodes (FP64).  TLVLBM_ERR_OUT_OF_MEMORY if checkpoints
+ *    and tape do not fit.  When a quarter of the remaining memory holds
+ *    them, the projection solutions of the checkpointed steps are kept
+ *    (FP64, active tiles) and replayed by the recomputation.  This memory
+ *    stays with the context (reused by the next call with the same n and
+ *    segment) until tlvlbm_destroy or a call of another shape.  Every
+ *    schedule gives bit-identical results.  Work: one forward pass, one
+ *    recomputation of the checkpointed steps without projection solves, one
+ *    reverse pass (the transposed projection sweeps on projection steps).
  *  - Errors: the forward's errors; TLVLBM_ERR_CALL_ORDER without a fresh
  *    state.  A failure leaves the context in an error state. */
 tlvlbm_status tlvlbm_adjoint(tlvlbm_ctx *ctx, int64_t n, const double *U0, const double *dU0,

@@ -173,11 +173,17 @@ __device__ __forceinline__ void push_adj(T *__restrict__ Lin, const Geo &g, cons
   }
 }
 
+// tape planes (F - I of every step, F^r of projection steps) hold one slot
+// per node of the chunk list, cpos[i / 64] * 64 + i % 64, plane stride ts
+// (without a chunk list: the node index, stride S)
+__device__ __forceinline__ int64_t tslot(const int32_t *__restrict__ cpos, int64_t node) {
+  return cpos ? (int64_t)cpos[node >> 6] * 64 + (node & 63) : node;
+}
+
 template <int D, typename T>
-__device__ __forceinline__ void tape_F(const T *__restrict__ tape, const Geo &g, int64_t node, double *F) {
+__device__ __forceinline__ void tape_F(const T *__restrict__ tape, int64_t ts, int64_t slot, double *F) {
 #pragma unroll
-  for (int k = 0; k < D * D; ++k)
-    F[k] = double(tape[(size_t)(D + k) * g.S + node]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
+  for (int k = 0; k < D * D; ++k) F[k] = double(tape[(size_t)k * ts + slot]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
 }
 
 // ------------------------------------------------------------------ seeds
@@ -217,24 +223,27 @@ __global__ __launch_bounds__(AT) void k_adj_seed(T *__restrict__ Lin, Geo g, Adj
 template <int D, typename T, bool MASK, bool TRACK, bool CH = false>
 __global__ __launch_bounds__(AT, 3) void k_adj_bulk(const T *__restrict__ Lout, T *__restrict__ Lin, Geo g, AdjPar p,
                                                  const uint8_t *__restrict__ act, const T *__restrict__ tape,
-                                                 const double *__restrict__ ubc, double *__restrict__ lus,
-                                                 double *__restrict__ gblk, const int32_t *__restrict__ chunks = nullptr,
-                                                 int nchunks = 0) {
+                                                 int64_t ts, const double *__restrict__ ubc,
+                                                 double *__restrict__ lus, double *__restrict__ gblk,
+                                                 const int32_t *__restrict__ chunks = nullptr, int nchunks = 0) {
   constexpr int Q = 2 * D, M = D + D * D;
   int x, row;
   bool live;
+  int64_t slot = 0;
   if constexpr (CH) {
     const int ch = blockIdx.x * (AT / 64) + (threadIdx.x >> 6);
     const int64_t i = ch < nchunks ? (int64_t)chunks[ch] * 64 + (threadIdx.x & 63) : g.N;
     live = i < g.N;
     x = live ? (int)(i % g.nx) : 0;
     row = live ? (int)(i / g.nx) : 0;
+    slot = (int64_t)ch * 64 + (threadIdx.x & 63);
   } else {
     x = blockIdx.x * blockDim.x + threadIdx.x;
     row = blockIdx.y;
     live = x < g.nx;
   }
   const int64_t node = x + (int64_t)g.nx * row;
+  if constexpr (!CH) slot = node;
   double gm = 0.0, gl = 0.0;
   if (live && (!MASK || act[node])) {
     // the feq' transpose of feq_vjp (a = omega), arranged so that only the
@@ -264,7 +273,7 @@ __global__ __launch_bounds__(AT, 3) void k_adj_bulk(const T *__restrict__ Lout, 
     double CW[D * D];
     {
       double F[D * D];
-      tape_F<D, T>(tape, g, node, F);
+      tape_F<D, T>(tape, ts, slot, F);
       vjp_tangent<D>(F, W, p, a, CW, gm, gl);
     }
 #pragma unroll
@@ -308,7 +317,8 @@ __global__ __launch_bounds__(AT, 3) void k_adj_bulk(const T *__restrict__ Lout, 
 template <int D, typename T>
 __global__ __launch_bounds__(AT) void k_adj_rep1(const T *__restrict__ Lout, Geo g, AdjPar p,
                                                  const uint8_t *__restrict__ act, const T *__restrict__ tape,
-                                                 const T *__restrict__ tapeFr, const double *__restrict__ Frb,
+                                                 const T *__restrict__ tapeFr, int64_t ts,
+                                                 const int32_t *__restrict__ cpos, const double *__restrict__ Frb,
                                                  const double *__restrict__ lus, double *__restrict__ UaB,
                                                  double *__restrict__ Fcb, double *__restrict__ gblk) {
   constexpr int Q = 2 * D, M = D + D * D;
@@ -319,9 +329,10 @@ __global__ __launch_bounds__(AT) void k_adj_rep1(const T *__restrict__ Lout, Geo
     T lam[Q][M];
     double Fa[D * D], Fr[D * D], Ur[M], Ua[M];
     load_adj<D, T>(Lout, g, node, lam);
-    tape_F<D, T>(tape, g, node, Fa);
+    const int64_t slot = tslot(cpos, node);
+    tape_F<D, T>(tape, ts, slot, Fa);
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) Fr[k] = double(tapeFr[(size_t)k * g.S + node]);
+    for (int k = 0; k < D * D; ++k) Fr[k] = double(tapeFr[(size_t)k * ts + slot]);
 #pragma unroll
     for (int r = 0; r < M; ++r) {
       Ur[r] = 0.0;
@@ -387,7 +398,8 @@ __global__ __launch_bounds__(AT) void k_adj_rep2(const T *__restrict__ Lout, T *
 template <int D, typename T, int PASS, bool NEU>
 __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, int64_t b0, int64_t b1, BC bc, Geo g,
                                                  Par par, double th, const T *__restrict__ tapeU,
-                                                 const T *__restrict__ tapeFr, const double *__restrict__ tapeu,
+                                                 const T *__restrict__ tapeFr, int64_t ts,
+                                                 const int32_t *__restrict__ cpos, const double *__restrict__ tapeu,
                                                  const int32_t *__restrict__ sc, int64_t nu,
                                                  double *__restrict__ gbar, double *__restrict__ glink) {
   constexpr int M = D + D * D;
@@ -440,16 +452,10 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
     double gv[D - 1][D];
     for (int al = 0; al < D - 1; ++al)
       for (int i = 0; i < D; ++i) gv[al][i] = L.tang[l * 6 + al * 3 + i];
-    for (int k = 0; k < np; ++k) {
-      // the tape holds u at the Neumann stencil nodes only
-      const int64_t t = sc[lsq_i(L, l, k)];
-      double uk[D];
-      for (int i = 0; i < D; ++i) uk[i] = tapeu[(size_t)i * nu + t];
-      for (int al = 0; al < D - 1; ++al) {
-        const double wk = L.sw[lsq_w(L, l, al, k)];
-        for (int i = 0; i < D; ++i) gv[al][i] += wk * uk[i];
-      }
-    }
+    // the tape holds u at the Neumann stencil nodes only
+    lsq_gather<D>(
+        L, l, np, [&](int k) { return (int64_t)sc[lsq_i(L, l, k)]; },
+        [&](int64_t t, int i) { return tapeu[(size_t)i * nu + t]; }, gv);
     for (int al = 0; al < D - 1; ++al)
       for (int i = 0; i < D; ++i)
         for (int B = 0; B < D; ++B) Gt[i * D + B] += gv[al][i] * L.tang[l * 6 + al * 3 + B];
@@ -458,10 +464,11 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
     bc_base<D>(bc, Xb, N, Tb);
     for (int i = 0; i < D; ++i) Tb[i] *= s;
     double h[D], Fm[D * D];
+    const int64_t slot = tslot(cpos, m);
     if (tapeFr)
-      for (int k = 0; k < D * D; ++k) Fm[k] = double(tapeFr[(size_t)k * g.S + m]);
+      for (int k = 0; k < D * D; ++k) Fm[k] = double(tapeFr[(size_t)k * ts + slot]);
     else
-      tape_F<D, T>(tapeU, g, m, Fm);
+      tape_F<D, T>(tapeU, ts, slot, Fm);
     for (int i = 0; i < D; ++i) {
       double acc = 0.0;
       for (int B = 0; B < D; ++B) acc += Fm[i * D + B] * N[B];
@@ -871,6 +878,9 @@ struct Run {
   int64_t *sn = nullptr, *so = nullptr;
   int32_t *el = nullptr, *sc = nullptr;
   double *ew = nullptr;
+  // tape layout
+  int64_t ts = 0;
+  const int32_t *cpos = nullptr;
 };
 
 template <int D, typename T> void launch_link_pass(Run &R, int pass, double th, const TapeStep &tp) {
@@ -884,7 +894,7 @@ template <int D, typename T> void launch_link_pass(Run &R, int pass, double th, 
     const double *tu = (const double *)tp.u;
 #define TL_LINK(P, NN)                                                                                         \
   hipLaunchKernelGGL((k_adj_link<D, T, P, NN>), nb, 64, 0, c->st, (T *)R.La, c->L, b0, b1, c->bcs[b], c->geo, \
-                     c->par, th, tU, tF, tu, R.sc, R.ns, R.gbar, R.glink)
+                     c->par, th, tU, tF, R.ts, R.cpos, tu, R.sc, R.ns, R.gbar, R.glink)
     if (pass == 1) {
       if (neu) TL_LINK(1, true);
       else TL_LINK(1, false);
@@ -967,24 +977,24 @@ template <int D, typename T> int reverse_step(Run &R, int64_t k, const TapeStep 
       const unsigned nb = (unsigned)((c->nchunks + AT / 64 - 1) / (AT / 64));
       if (c->track_u)
         hipLaunchKernelGGL((k_adj_bulk<D, T, true, true, true>), nb, AT, 0, c->st, Lout, Lin, g, R.ap, c->act, tU,
-                           R.ubc, R.lus, R.gblk, c->chunks, c->nchunks);
+                           R.ts, R.ubc, R.lus, R.gblk, c->chunks, c->nchunks);
       else
         hipLaunchKernelGGL((k_adj_bulk<D, T, true, false, true>), nb, AT, 0, c->st, Lout, Lin, g, R.ap, c->act, tU,
-                           R.ubc, R.lus, R.gblk, c->chunks, c->nchunks);
+                           R.ts, R.ubc, R.lus, R.gblk, c->chunks, c->nchunks);
     } else if (c->act) {
       if (c->track_u)
         hipLaunchKernelGGL((k_adj_bulk<D, T, true, true>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act, tU,
-                           R.ubc, R.lus, R.gblk);
+                           R.ts, R.ubc, R.lus, R.gblk);
       else
         hipLaunchKernelGGL((k_adj_bulk<D, T, true, false>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act,
-                           tU, R.ubc, R.lus, R.gblk);
+                           tU, R.ts, R.ubc, R.lus, R.gblk);
     } else {
       if (c->track_u)
         hipLaunchKernelGGL((k_adj_bulk<D, T, false, true>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act,
-                           tU, R.ubc, R.lus, R.gblk);
+                           tU, R.ts, R.ubc, R.lus, R.gblk);
       else
         hipLaunchKernelGGL((k_adj_bulk<D, T, false, false>), R.grid, R.block, 0, c->st, Lout, Lin, g, R.ap, c->act,
-                           tU, R.ubc, R.lus, R.gblk);
+                           tU, R.ts, R.ubc, R.lus, R.gblk);
     }
   } else {
     CG &w = c->cg;
@@ -994,7 +1004,7 @@ template <int D, typename T> int reverse_step(Run &R, int64_t k, const TapeStep 
     hipLaunchKernelGGL((k_adj_rhsT<D, false>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, (const double *)w.x, R.Frb);
     anchors_T<D>(R, (const double *)w.x, R.Frb);
     hipLaunchKernelGGL((k_adj_rep1<D, T>), R.grid, R.block, 0, c->st, Lout, g, R.ap, c->act, (const T *)tp.U,
-                       (const T *)tp.Fr, R.Frb, R.lus, R.UaB, R.Fcb, R.gblk);
+                       (const T *)tp.Fr, R.ts, R.cpos, R.Frb, R.lus, R.UaB, R.Fcb, R.gblk);
     hipLaunchKernelGGL((k_adj_compatT<D>), nblocks(g.N, AT), AT, 0, c->st, g, c->act, R.Fcb, R.x0b, R.ucb, R.Fext);
     // first projection (u^c from F, warm start u)
     s = solve_adj<D>(R, R.ucb, nullptr);
@@ -1126,35 +1136,70 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     if (s) return (tlvlbm_status)s;
   }
   const int64_t nu = (R.neu && c->stT) ? c->stT->ns : 0;
+  // tape: F - I of every step and F^r of projection steps in chunk slots
+  // (population precision), u at the Neumann stencil nodes (FP64)
+  R.ts = tape_stride(c);
+  R.cpos = (c->act && c->chunks) ? c->cpos : nullptr;
+  const size_t tplane = (size_t)R.ts * sizeof(T);
   const size_t ck_bytes = (size_t)Q * M * plane + (track ? D * dplane : 0);
   const size_t tapeu_bytes = (size_t)D * std::max<int64_t>(nu, 1) * sizeof(double);
-  const size_t tape_bytes = (size_t)M * plane + (R.neu ? tapeu_bytes : 0);
-  if (seg <= 0) {
-    seg = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(n, 1) * (double)ck_bytes / (double)tape_bytes));
-    seg = std::max<int64_t>(1, std::min<int64_t>(seg, std::max<int64_t>(n, 1)));
-  }
-  const int64_t nck = n > 0 ? (n + seg - 1) / seg : 0;
-  size_t avail = 0;
-  int64_t nproj_seg = 0;
-  if (R.neu && c->proj_every > 0) nproj_seg = seg / c->proj_every + 2;
-  // memory check (skipped when the arena already holds this shape)
+  const size_t tape_bytes = (size_t)D * D * tplane + (R.neu ? tapeu_bytes : 0);
+  const size_t trF_bytes = (size_t)D * D * tplane;
+  const bool has_proj = R.neu && c->proj_every > 0;
+  auto nproj_in = [&](int64_t k0, int64_t k1) {
+    int64_t np = 0;
+    for (int64_t k = k0; k < k1; ++k) np += is_projection_step(c, k) ? 1 : 0;
+    return np;
+  };
+  // Schedule.  With a caller's segment length: checkpoints every seg steps,
+  // each segment recomputed once with its tape.  By default the last `tail`
+  // steps keep their tape from the first pass (as many as 60% of the free
+  // device memory holds; at most -seg of them for seg < 0) and only the
+  // steps before them are checkpointed and recomputed, in segments of
+  // ~sqrt(steps * checkpoint / tape step).
+  const int64_t seg_arg = seg;
   AdjArena &ar = *c->arena;
-  if (ar.key[0] != n || ar.key[1] != seg) {
+  int64_t tail = 0;
+  size_t avail = 0;
+  if (ar.key[0] != n || ar.key[1] != seg_arg) {
     arena_release(&ar);
-    size_t need = (size_t)(nck + 1) * ck_bytes + (size_t)seg * tape_bytes + (size_t)nproj_seg * D * D * plane +
-                  2 * (size_t)Q * M * plane + 2 * (size_t)D * dplane;
-    if (R.neu) need += (size_t)(M + 3 * D * D + 2 * D) * dplane;
-    if (nu) need += (size_t)nu * (3 * 8 + 8 * (D + 1)) + (size_t)c->L.n * c->L.kmax * 4;
+    size_t fixed = 2 * (size_t)Q * M * plane + 2 * (size_t)D * dplane + 2 * ck_bytes;
+    if (R.neu) fixed += (size_t)(M + 3 * D * D + 2 * D) * dplane;
+    if (nu) fixed += (size_t)nu * (3 * 8 + 8 * (D + 1)) + (size_t)c->L.n * c->L.kmax * 4;
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess && need > fr) {
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
+    if (seg_arg <= 0 && fr > fixed) {
+      const double per_step = (double)tape_bytes + (has_proj ? (double)trF_bytes / c->proj_every : 0.0);
+      tail = std::min<int64_t>(n, (int64_t)(0.6 * (double)(fr - fixed) / per_step));
+      if (seg_arg < 0) tail = std::min<int64_t>(tail, -seg_arg);
+      tail = std::max<int64_t>(tail, 0);
+    }
+    const int64_t head = n - tail;
+    if (seg_arg <= 0) {
+      seg = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(head, 1) * (double)ck_bytes / (double)tape_bytes));
+      seg = std::max<int64_t>(1, std::min<int64_t>(seg, std::max<int64_t>(head, 1)));
+    }
+    const int64_t nck_ = head > 0 ? (head + seg - 1) / seg : 0;
+    const int64_t nps = has_proj ? seg / c->proj_every + 2 : 0;
+    size_t need = fixed + (size_t)(nck_ + 1) * ck_bytes + (head > 0 ? (size_t)seg * tape_bytes : 0) +
+                  (head > 0 ? (size_t)nps * trF_bytes : 0) + (size_t)tail * tape_bytes +
+                  (size_t)nproj_in(head, n) * trF_bytes;
+    if (fr && need > fr) {
       err = "adjoint: checkpoints and tape do not fit in device memory (lower the step count or pass a segment length)";
       return TLVLBM_ERR_OUT_OF_MEMORY;
     }
     ar.avail = fr > need ? fr - need : 0;
     ar.key[0] = n;
-    ar.key[1] = seg;
+    ar.key[1] = seg_arg;
+    ar.seg = seg;
+    ar.tail = tail;
   }
+  seg = ar.seg;
+  tail = ar.tail;
   avail = ar.avail;
+  const int64_t head = n - tail;
+  const int64_t nck = head > 0 ? (head + seg - 1) / seg : 0;
+  const int64_t nproj_seg = has_proj ? seg / c->proj_every + 2 : 0;
   if (R.neu || R.dir) {
     const int s = ensure_cg(c);
     if (s) return (tlvlbm_status)s;
@@ -1183,8 +1228,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   // the projection solutions of the first pass are kept (active tiles, FP64)
   // when they fit in a quarter of the free memory, so that the recomputation
   // replays them instead of solving again
-  int64_t nproj = 0;
-  for (int64_t k = 0; k < n; ++k) nproj += is_projection_step(c, k) ? 1 : 0;
+  const int64_t nproj = nproj_in(0, head);
   double *xstore = nullptr;
   size_t xslot = 0;
   if (nproj && c->cg.tiles) {
@@ -1193,7 +1237,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     if (xbytes <= avail / 4 && pool.get(&xstore, xbytes, st, false)) xstore = nullptr;
   }
   std::vector<int64_t> pidx(n, -1);
-  for (int64_t k = 0, p = 0; k < n; ++k)
+  for (int64_t k = 0, p = 0; k < head; ++k)
     if (is_projection_step(c, k)) pidx[k] = p++;
   auto xs_of = [&](int64_t k, TapeStep &tp, int mode) {
     tp.xs[0] = tp.xs[1] = nullptr;
@@ -1204,9 +1248,28 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
       tp.xmode = mode;
     }
   };
+  // the tail's tape, written by the first pass
+  char *tailU = nullptr, *tailu = nullptr, *tailF = nullptr;
+  std::vector<TapeStep> ttp((size_t)tail);
+  if (tail > 0) {
+    const int64_t ntp = nproj_in(head, n);
+    if (pool.get(&tailU, (size_t)tail * D * D * tplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (R.neu && nu && pool.get(&tailu, (size_t)tail * tapeu_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (ntp && pool.get(&tailF, (size_t)ntp * trF_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    int64_t ip = 0;
+    for (int64_t k = head; k < n; ++k) {
+      TapeStep &tp = ttp[k - head];
+      tp.U = tailU + (size_t)(k - head) * D * D * tplane;
+      tp.u = (R.neu && nu) ? tailu + (size_t)(k - head) * tapeu_bytes : nullptr;
+      tp.un = c->stT ? c->stT->sn : nullptr;
+      tp.nu = nu;
+      tp.Fr = is_projection_step(c, k) ? tailF + (size_t)(ip++) * trF_bytes : nullptr;
+    }
+  }
   for (int64_t k = 0; k < n; ++k) {
-    if (k % seg == 0 && !save(k / seg)) return TLVLBM_ERR_DEVICE;
+    if (k < head && k % seg == 0 && !save(k / seg)) return TLVLBM_ERR_DEVICE;
     TapeStep tp{};
+    if (k >= head) tp = ttp[k - head];
     xs_of(k, tp, 1);
     const int s = step_once(c, &tp);
     if (s) return (tlvlbm_status)s;
@@ -1243,9 +1306,11 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   }
   // per-step tape of one segment
   char *tapeU = nullptr, *tapeu = nullptr, *tapeF = nullptr;
-  if (pool.get(&tapeU, (size_t)seg * M * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-  if (R.neu && pool.get(&tapeu, (size_t)seg * tapeu_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-  if (nproj_seg && pool.get(&tapeF, (size_t)nproj_seg * D * D * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+  if (head > 0) {
+    if (pool.get(&tapeU, (size_t)seg * D * D * tplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (R.neu && pool.get(&tapeu, (size_t)seg * tapeu_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (nproj_seg && pool.get(&tapeF, (size_t)nproj_seg * trF_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+  }
   // seeds
   {
     const double *gU = (const double *)dLU.ptr, *gu = (const double *)dLu.ptr;
@@ -1265,17 +1330,22 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
                            gu, R.lus);
     }
   }
+  // the tail in reverse from the first pass's tape, then the head's
   // segments in reverse: recompute with the tape, then reverse each step
   const int64_t st_proj0 = c->st_proj, st_cg0 = c->st_cg;
+  for (int64_t k = n - 1; k >= head; --k) {
+    const int e = reverse_step<D, T>(R, k, ttp[k - head]);
+    if (e) return (tlvlbm_status)e;
+  }
   for (int64_t s = nck - 1; s >= 0; --s) {
-    const int64_t k0 = s * seg, k1 = std::min<int64_t>(n, k0 + seg);
+    const int64_t k0 = s * seg, k1 = std::min<int64_t>(head, k0 + seg);
     if (!restore(s)) return TLVLBM_ERR_DEVICE;
     c->step = k0;
     std::vector<TapeStep> tps(k1 - k0);
     int64_t ip = 0;
     for (int64_t k = k0; k < k1; ++k) {
       TapeStep &tp = tps[k - k0];
-      tp.U = tapeU + (size_t)(k - k0) * M * plane;
+      tp.U = tapeU + (size_t)(k - k0) * D * D * tplane;
       // (no stencil node: no Neumann link reads the displacement)
       tp.u = (R.neu && R.ns) ? tapeu + (size_t)(k - k0) * tapeu_bytes : nullptr;
       tp.un = R.sn;
@@ -1284,7 +1354,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
       xs_of(k, tp, 2);
       if (is_projection_step(c, k)) {
         if (ip >= nproj_seg) return TLVLBM_ERR_INVALID_ARG;
-        tp.Fr = tapeF + (size_t)(ip++) * D * D * plane;
+        tp.Fr = tapeF + (size_t)(ip++) * trF_bytes;
       }
       const int e = step_once(c, &tp);
       if (e) return (tlvlbm_status)e;

@@ -110,15 +110,20 @@ int step_once(tlvlbm_ctx *c, const TapeStep *tp) {
     int s = run_projection(c, true, tn, tp ? tp->xs[0] : nullptr, tp ? tp->xmode : 0);
     if (s) return s;
     launch_bulk(c, true, tp ? tp->U : nullptr);
-    if (tp && tp->Fr)
-      CHK(hipMemcpyAsync(tp->Fr, c->cg.Fr, (size_t)c->D * c->D * plane, hipMemcpyDeviceToDevice, c->st), "tape");
+    if (tp && tp->Fr) {
+      if (c->act && c->chunks) launch_tape_gather(c, c->cg.Fr, tp->Fr, c->D * c->D);
+      else CHK(hipMemcpyAsync(tp->Fr, c->cg.Fr, (size_t)c->D * c->D * plane, hipMemcpyDeviceToDevice, c->st), "tape");
+    }
     s = run_projection(c, false, tn, tp ? tp->xs[1] : nullptr, tp ? tp->xmode : 0);
     if (s) return s;
     ++c->st_proj;
   } else {
     launch_bulk(c, false, tp ? tp->U : nullptr);
   }
-  if (c->L.n) launch_cutlinks(c, tn);
+  if (c->L.n) {
+    const int s = launch_cutlinks(c, tn);
+    if (s) return s;
+  }
   if (tp && tp->u) {
     if (tp->un) {
       if (tp->nu) launch_gather_u(c, tp->un, tp->nu, (double *)tp->u);
@@ -238,7 +243,7 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
                   c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles,
-                  c->cg.nbm, c->bf, c->chunks};
+                  c->cg.nbm, c->bf, c->chunks, c->cpos, c->d_bcs};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
@@ -287,6 +292,10 @@ tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *c, const double *phi, const uint8_
       if (!ch.empty()) {
         CHK(hipMalloc(&c->chunks, ch.size() * sizeof(int32_t)), "chunk alloc");
         CHK(hipMemcpy(c->chunks, ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice), "chunk upload");
+        std::vector<int32_t> pos((size_t)((N + 63) / 64), -1);
+        for (size_t k = 0; k < ch.size(); ++k) pos[ch[k]] = (int32_t)k;
+        CHK(hipMalloc(&c->cpos, pos.size() * sizeof(int32_t)), "chunk position alloc");
+        CHK(hipMemcpy(c->cpos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice), "chunk position upload");
       }
       c->nchunks = (int)ch.size();
     }
@@ -321,6 +330,7 @@ tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *c, uint8_t bid, const tlvlbm_bc *b
     return fail(c, TLVLBM_ERR_INVALID_ARG, "twist needs a displacement-given Dirichlet condition");
   b.tw = bc->twist;
   c->bc_set[bid] = true;
+  c->bcs_dirty = true;
   c->aux_stale = true;  // projection anchors and components follow the conditions
   return TLVLBM_OK;
 }

@@ -90,14 +90,15 @@ template <typename T> __device__ __forceinline__ bool finite_(T v) { return __bu
 
 // Fused pull-stream + state recovery + (optional projection repair) + BGK
 // collision with source + displacement quadrature (Algorithm 1, bulk loops).
-// TAPE: also store the recovered (pre-repair) state (v, F - I) to the tape
-// planes for the reverse mode.
+// TAPE: also store the recovered (pre-repair) F - I to the tape planes of
+// the reverse mode, plane k at tape[k * ts + tslot].
 template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool TAPE = false, bool EXT = false>
 __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restrict__ fout, const Geo &g,
                                           const Par &p, const uint8_t *__restrict__ act, double *__restrict__ ustar,
                                           double *__restrict__ ubuf, const T *__restrict__ Frp,
                                           int *__restrict__ flag, int x, int row, T *__restrict__ tape = nullptr,
-                                          const T *__restrict__ bf = nullptr, T bs = T(0)) {
+                                          const T *__restrict__ bf = nullptr, T bs = T(0), int64_t tslot = 0,
+                                          int64_t ts = 0) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int y = row % g.ny, z = row / g.ny;
   const int64_t node = x + (int64_t)g.nx * row;
@@ -134,9 +135,7 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
   bool bad = !(J > T(0));
   if constexpr (TAPE) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) tape[(size_t)i * g.S + node] = v[i];
-#pragma unroll
-    for (int k = 0; k < D * D; ++k) tape[(size_t)(D + k) * g.S + node] = dU[D + k];
+    for (int k = 0; k < D * D; ++k) tape[(size_t)k * ts + tslot] = dU[D + k];
   }
   const T inv2c = T(0.5) / T(p.c);
   const T inv2D = T(1) / T(2 * D);
@@ -352,7 +351,8 @@ __global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T 
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
   bulk_node<D, T, MASK, TRACK, REPAIR, true, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x,
-                                                   (int)blockIdx.y, tape, bf, bs);
+                                                   (int)blockIdx.y, tape, bf, bs,
+                                                   x + (int64_t)g.nx * blockIdx.y, g.S);
 }
 
 // Embedded bodies: the same update over the list of 64-node chunks (of the
@@ -386,7 +386,10 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks_tape(
   const int64_t i = (int64_t)chunks[ch] * 64 + (threadIdx.x & 63);
   if (i >= g.N) return;
   const int x = (int)(i % g.nx), row = (int)(i / g.nx);
-  bulk_node<D, T, true, TRACK, REPAIR, true, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, tape);
+  // tape slot of chunk ch, lane i % 64
+  bulk_node<D, T, true, TRACK, REPAIR, true, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, tape,
+                                                  nullptr, T(0), (int64_t)ch * 64 + (threadIdx.x & 63),
+                                                  (int64_t)nchunks * 64);
 }
 
 // Batched bulk update: one block per tile (instance, row, first x) of the

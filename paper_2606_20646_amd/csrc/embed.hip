@@ -459,15 +459,9 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
   double gv[D - 1][D];
   for (int al = 0; al < D - 1; ++al)
     for (int i = 0; i < D; ++i) gv[al][i] = L.tang[l * 6 + al * 3 + i];
-  for (int k = 0; k < np; ++k) {
-    const int64_t j = L.sidx[lsq_i(L, l, k)];
-    double uk[D];
-    for (int i = 0; i < D; ++i) uk[i] = u[(size_t)i * g.S + j];
-    for (int al = 0; al < D - 1; ++al) {
-      const double wk = L.sw[lsq_w(L, l, al, k)];
-      for (int i = 0; i < D; ++i) gv[al][i] += wk * uk[i];
-    }
-  }
+  lsq_gather<D>(
+      L, l, np, [&](int k) { return (int64_t)L.sidx[lsq_i(L, l, k)]; },
+      [&](int64_t j, int i) { return u[(size_t)i * g.S + j]; }, gv);
   for (int al = 0; al < D - 1; ++al)
     for (int i = 0; i < D; ++i)
       for (int B = 0; B < D; ++B) Gt[i * D + B] += gv[al][i] * L.tang[l * 6 + al * 3 + B];
@@ -898,18 +892,21 @@ __device__ __forceinline__ void ureset_node(const Geo &g, const uint8_t *__restr
 // ------------------------------------------------- single-instance kernels
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_cut_dirichlet(T *__restrict__ f, Links L, int64_t b0, int64_t b1, BC bc,
-                                                        Geo g, Par p, double th) {
+// Links [b0, b1) may span several boundary identifiers of one type (the
+// table is ordered by identifier); each link reads its condition from bcs.
+__global__ __launch_bounds__(256) void k_cut_dirichlet(T *__restrict__ f, Links L, int64_t b0, int64_t b1,
+                                                        const BC *__restrict__ bcs, Geo g, Par p, double th) {
   const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (l < b1) cut_dirichlet_link<D, T>(f, L, l, bc, g, p, th);
+  if (l < b1) cut_dirichlet_link<D, T>(f, L, l, bcs[L.bid[l]], g, p, th);
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(128) void k_cut_neumann(T *__restrict__ f, Links L, int64_t b0, int64_t b1, BC bc,
-                                                      Geo g, Par p, double th, const double *__restrict__ u,
-                                                      int *__restrict__ flag, unsigned long long *__restrict__ nfail) {
+__global__ __launch_bounds__(128) void k_cut_neumann(T *__restrict__ f, Links L, int64_t b0, int64_t b1,
+                                                      const BC *__restrict__ bcs, Geo g, Par p, double th,
+                                                      const double *__restrict__ u, int *__restrict__ flag,
+                                                      unsigned long long *__restrict__ nfail) {
   const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (l < b1) cut_neumann_link<D, T>(f, L, l, bc, g, p, th, u, flag, nfail);
+  if (l < b1) cut_neumann_link<D, T>(f, L, l, bcs[L.bid[l]], g, p, th, u, flag, nfail);
 }
 
 template <int D, typename T>
@@ -1150,20 +1147,50 @@ int build_links(tlvlbm_ctx *c, const double *phi, const uint8_t *bid, std::strin
   return c->D == 2 ? build_links_t<2>(c, phi, bid, err) : build_links_t<3>(c, phi, bid, err);
 }
 
-template <int D, typename T> static void cutlinks_t(tlvlbm_ctx *c, double tn) {
-  const double th = (double(c->step) + 0.5) * c->par.dt;  // t^n + dt/2, same rounding as the batched path
-  for (int b = 0; b < 256; ++b) {
-    const int64_t b0 = c->bid_begin[b], b1 = c->bid_end[b];
-    if (b1 <= b0) continue;
-    const BC &bc = c->bcs[b];
-    if (bc.type == TLVLBM_BC_DIRICHLET_VELOCITY)
-      hipLaunchKernelGGL((k_cut_dirichlet<D, T>), nblk(b1 - b0, 256), 256, 0, c->st, (T *)c->fA, c->L, b0, b1, bc,
-                         c->geo, c->par, th);
-    else
-      hipLaunchKernelGGL((k_cut_neumann<D, T>), nblk(b1 - b0, 128), 128, 0, c->st, (T *)c->fA, c->L, b0, b1, bc,
-                         c->geo, c->par, th, (const double *)c->ubuf, c->d_flag,
-                         (unsigned long long *)c->d_newton_fail);
+// device copy of the boundary conditions (after tlvlbm_set_boundary),
+// ordered on the context's stream behind the steps already queued
+static int sync_bcs(tlvlbm_ctx *c) {
+  if (!c->d_bcs && hipMalloc(&c->d_bcs, sizeof(c->bcs)) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
+  if (c->bcs_dirty) {
+    if (hipMemcpyAsync(c->d_bcs, c->bcs, sizeof(c->bcs), hipMemcpyHostToDevice, c->st) != hipSuccess)
+      return TLVLBM_ERR_DEVICE;
+    c->bcs_dirty = false;
   }
+  return TLVLBM_OK;
+}
+
+// one launch per run of consecutive boundary identifiers of one type (the
+// links of a run are contiguous in the table), so that e.g. both walls of a
+// tube close in one Neumann launch
+template <int D, typename T> static int cutlinks_t(tlvlbm_ctx *c, double tn) {
+  const double th = (double(c->step) + 0.5) * c->par.dt;  // t^n + dt/2, same rounding as the batched path
+  const int s = sync_bcs(c);
+  if (s) return s;
+  int b = 0;
+  while (b < 256) {
+    if (c->bid_end[b] <= c->bid_begin[b]) {
+      ++b;
+      continue;
+    }
+    const int type = c->bcs[b].type;
+    const int64_t b0 = c->bid_begin[b];
+    int64_t b1 = c->bid_end[b];
+    int e = b + 1;
+    for (; e < 256; ++e) {
+      if (c->bid_end[e] <= c->bid_begin[e]) continue;
+      if (c->bcs[e].type != type || c->bid_begin[e] != b1) break;
+      b1 = c->bid_end[e];
+    }
+    if (type == TLVLBM_BC_DIRICHLET_VELOCITY)
+      hipLaunchKernelGGL((k_cut_dirichlet<D, T>), nblk(b1 - b0, 256), 256, 0, c->st, (T *)c->fA, c->L, b0, b1,
+                         (const BC *)c->d_bcs, c->geo, c->par, th);
+    else
+      hipLaunchKernelGGL((k_cut_neumann<D, T>), nblk(b1 - b0, 128), 128, 0, c->st, (T *)c->fA, c->L, b0, b1,
+                         (const BC *)c->d_bcs, c->geo, c->par, th, (const double *)c->ubuf, c->d_flag,
+                         (unsigned long long *)c->d_newton_fail);
+    b = e;
+  }
+  return TLVLBM_OK;
 }
 
 // the displacement at the Neumann stencil nodes, for the reverse-mode tape
@@ -1176,19 +1203,36 @@ __global__ __launch_bounds__(256) void k_gather_u(const double *__restrict__ u, 
   for (int i = 0; i < D; ++i) out[(size_t)i * nu + t] = u[(size_t)i * S + j];
 }
 
+// chunk slots of whole planes, for the reverse-mode tape
+template <typename T>
+__global__ __launch_bounds__(256) void k_tape_gather(const T *__restrict__ src, int64_t S, int64_t N,
+                                                     const int32_t *__restrict__ chunks, int64_t nslot, int planes,
+                                                     T *__restrict__ dst) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= nslot) return;
+  const int64_t node = (int64_t)chunks[s >> 6] * 64 + (s & 63);
+  if (node >= N) return;
+  for (int k = 0; k < planes; ++k) dst[(size_t)k * nslot + s] = src[(size_t)k * S + node];
+}
+
+void launch_tape_gather(tlvlbm_ctx *c, const void *src, void *dst, int planes) {
+  const int64_t ns = (int64_t)c->nchunks * 64;
+  if (c->prec)
+    hipLaunchKernelGGL(k_tape_gather<double>, nblk(ns, 256), 256, 0, c->st, (const double *)src, c->geo.S, c->geo.N,
+                       c->chunks, ns, planes, (double *)dst);
+  else
+    hipLaunchKernelGGL(k_tape_gather<float>, nblk(ns, 256), 256, 0, c->st, (const float *)src, c->geo.S, c->geo.N,
+                       c->chunks, ns, planes, (float *)dst);
+}
+
 void launch_gather_u(tlvlbm_ctx *c, const int64_t *un, int64_t nu, double *out) {
   hipLaunchKernelGGL(k_gather_u, nblk(nu, 256), 256, 0, c->st, (const double *)c->ubuf, c->geo.S, c->D, un, nu,
                      out);
 }
 
-void launch_cutlinks(tlvlbm_ctx *c, double tn) {
-  if (c->D == 2) {
-    if (c->prec) cutlinks_t<2, double>(c, tn);
-    else cutlinks_t<2, float>(c, tn);
-  } else {
-    if (c->prec) cutlinks_t<3, double>(c, tn);
-    else cutlinks_t<3, float>(c, tn);
-  }
+int launch_cutlinks(tlvlbm_ctx *c, double tn) {
+  if (c->D == 2) return c->prec ? cutlinks_t<2, double>(c, tn) : cutlinks_t<2, float>(c, tn);
+  return c->prec ? cutlinks_t<3, double>(c, tn) : cutlinks_t<3, float>(c, tn);
 }
 
 template <int D, typename T> static int cg_alloc(tlvlbm_ctx *c) {

@@ -53,6 +53,38 @@ __device__ __forceinline__ int64_t nb_index(const Geo &g, int64_t i, int q) {
   return (q & 1) ? i - off : i + off;
 }
 
+// gv[al][i] += sum_k w_al,k u_i(point k) over the LSQ stencil of link l
+// (Eqs. 48-52), points in order.  The loads of 8 points are issued together
+// (a sequential loop would wait for every index and then every value in
+// turn); the accumulation order is the sequential one.  slot(k) gives the
+// displacement index of point k, uval(j, i) component i there.
+template <int D, typename SlotF, typename UF>
+__device__ __forceinline__ void lsq_gather(const Links &L, int64_t l, int np, SlotF slot, UF uval,
+                                           double (&gv)[D - 1][D]) {
+  constexpr int B = 8;
+  for (int k0 = 0; k0 < np; k0 += B) {
+    int64_t jj[B];
+#pragma unroll
+    for (int t = 0; t < B; ++t) jj[t] = (k0 + t < np) ? slot(k0 + t) : -1;
+    double uu[B][D], ww[B][D - 1];
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+      const bool ok = jj[t] >= 0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) uu[t][i] = ok ? uval(jj[t], i) : 0.0;
+#pragma unroll
+      for (int al = 0; al < D - 1; ++al) ww[t][al] = ok ? L.sw[lsq_w(L, l, al, k0 + t)] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < B; ++t)
+      if (jj[t] >= 0)
+#pragma unroll
+        for (int al = 0; al < D - 1; ++al)
+#pragma unroll
+          for (int i = 0; i < D; ++i) gv[al][i] += ww[t][al] * uu[t][i];
+  }
+}
+
 // ------------------------------------------------- boundary data (FP64)
 
 __host__ __device__ __forceinline__ void ramp_eval(int kind, double Tr, double t, double &s, double &ds) {

@@ -111,8 +111,9 @@ struct StencilT {
 struct AdjArena {
   std::vector<void *> blk;
   std::vector<size_t> bytes;
-  int64_t key[2] = {-1, -1};
+  int64_t key[2] = {-1, -1};  // (steps, requested segment length)
   size_t avail = 0;  // free memory beyond the fixed needs when first sized
+  int64_t seg = 1, tail = 0;  // the schedule chosen for that key
 };
 
 // projection / CG workspace
@@ -292,6 +293,9 @@ struct tlvlbm_ctx {
   // nodes (one wavefront each); the bulk update skips the rest
   int32_t *chunks = nullptr;
   int nchunks = 0;
+  // position of every 64-node block in the chunk list (-1: not listed); the
+  // reverse-mode tape stores chunk slots cpos[i / 64] * 64 + i % 64
+  int32_t *cpos = nullptr;
   // body acceleration b(X, t) = s(t) g(X) (Eq. 5): g in D planes of the
   // population precision (null: none), s a ramp
   void *bf = nullptr;
@@ -308,6 +312,8 @@ struct tlvlbm_ctx {
   int64_t bid_begin[256] = {0}, bid_end[256] = {0};
   bool bc_set[256] = {false};
   tl::BC bcs[256];
+  tl::BC *d_bcs = nullptr;  // device copy for the cut-link launches (refreshed when bcs_dirty)
+  bool bcs_dirty = true;
   tl::CG cg;
   double *hscal = nullptr;  // pinned host mirror for scalars
   int *d_flag = nullptr;
@@ -329,7 +335,7 @@ void launch_planes_in(tlvlbm_ctx *c, const double *src, void *dst, int k);
 void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar);
 // launchers (embed.hip)
 int build_links(tlvlbm_ctx *c, const double *phi_d, const uint8_t *bid_d, std::string &err);
-void launch_cutlinks(tlvlbm_ctx *c, double tn);
+int launch_cutlinks(tlvlbm_ctx *c, double tn);
 // store/mode: 0 solve; 1 solve and keep the solution on the active tiles in
 // store; 2 take the solution from store instead of solving
 int run_projection(tlvlbm_ctx *c, bool first, double tn, double *store = nullptr, int mode = 0);
@@ -355,6 +361,13 @@ struct TapeStep {
   double *xs[2];  // projection solutions of the step (see run_projection)
   int xmode;
 };
+// reverse-mode tape planes: one slot per node of the chunk list (embedded
+// bodies) or per node
+inline int64_t tape_stride(const tlvlbm_ctx *c) {
+  return (c->act && c->chunks) ? (int64_t)c->nchunks * 64 : (int64_t)c->geo.S;
+}
+// dst[k * tape_stride + slot] = src[k * S + node] for k < planes (embed.hip)
+void launch_tape_gather(tlvlbm_ctx *c, const void *src, void *dst, int planes);
 // out[i * nu + t] = u_i at node un[t] (embed.hip)
 void launch_gather_u(tlvlbm_ctx *c, const int64_t *un, int64_t nu, double *out);
 // one step of Algorithm 1 (api.hip)

@@ -91,7 +91,9 @@ def test_adjoint_segments_agree(T, name):
     cfg = make()
     wU, wu = _weights(cfg)
     out = []
-    for seg in (0, 1, 4, n):
+    # 0: every step taped in the first pass; -3: three taped final steps
+    # and the rest checkpointed; > 0: checkpoints only
+    for seg in (0, -3, 1, 4, n):
         s = _solver(T, cfg, "fp64")
         s.set_state(cfg["U0"], u0=cfg.get("u0"), dU0=cfg.get("dU0"))
         out.append(s.adjoint(n, wU, wu, segment=seg))

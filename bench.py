@@ -296,18 +296,23 @@ def bench_c4(args):
         return time.perf_counter() - t
 
     def compare(sweeps, mg):
+        # 20 untimed steps on both paths (first launches, graph capture),
+        # then `steps` timed steps holding the same number of projections
         A = build(sweeps, mg)
+        T.step_each(A, 20)
         ta = timed(lambda: T.step_each(A, steps))
         B = build(sweeps, mg)
         bt = T.Batch(B, use_graph=True)
+        tiles = bt.tiles()
+        bt.step(20)
         tb = timed(lambda: bt.step(steps))
         bt.close()
         err = max(float(np.linalg.norm(a.moments()[0] - b.moments()[0]) / np.linalg.norm(a.moments()[0]))
                   for a, b in zip(A, B))
-        return ta, tb, err
+        return ta, tb, err, tiles
 
-    ta, tb, err = compare(20, False)
-    tc, te, err_mg = compare(0, True)
+    ta, tb, err, tiles = compare(20, False)
+    tc, te, err_mg, _ = compare(0, True)
     _common("batched speedup over per-instance launches of the same kernels", round(ta / tb, 3), "x", steps, 0,
             round(tb * 1e3 / steps, 4), True, "f32",
             f"64 embedded D2Q4x6 instances (random holes, 64^2..512^2), {nodes} active nodes, "
@@ -315,6 +320,8 @@ def bench_c4(args):
             {"per_instance_s": round(ta, 4), "batched_s": round(tb, 4),
              "per_instance_MLUPS": round(nodes * steps / ta / 1e6, 1),
              "batched_MLUPS": round(nodes * steps / tb / 1e6, 1), "max_rel_state_diff": err,
+             "tiles": {"width": tiles[0], "order": tiles[1],
+                       "ms_per_bulk_launch": {f"order{o}_w{w}": round(v, 4) for (o, w), v in tiles[2].items()}},
              "exact_projection_multigrid_cg": {"per_instance_s": round(tc, 4), "batched_s": round(te, 4),
                                                "speedup": round(tc / te, 3), "max_rel_state_diff": err_mg}})
 

@@ -272,9 +272,9 @@ const char *tlvlbm_last_error(const tlvlbm_ctx *ctx);
  *    reverse pass (the transposed projection sweeps on projection steps).
  *  - Errors: the forward's errors; TLVLBM_ERR_CALL_ORDER without a fresh
  *    state.  A failure leaves the context in an error state. */
-tlvlbm_status tlvlbm_adjoint(tlvlbm_ctx *ctx, int64_t n, const double *U0, const double *dU0,
-                             const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
-                             double *grad_u0, int64_t segment);
+tlvlbm_status tlvlbm_adjoint_step(tlvlbm_ctx *ctx, int64_t n, const double *U0, const double *dU0,
+                                  const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
+                                  double *grad_u0, int64_t segment);
 
 /* ---- Many instances (project extension, not in the paper) ---------------
  * Independent contexts of the same lattice and precision, sharing one
@@ -300,6 +300,22 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
 tlvlbm_status tlvlbm_batch_step(tlvlbm_batch *b, int64_t steps);
 /* 0 disables graph replay (every launch issued from the host) */
 tlvlbm_status tlvlbm_batch_set_graph(tlvlbm_batch *b, int32_t use_graph);
+/* Tile configuration of the batched node kernels (bulk update, moments):
+ * tiles of tile_width nodes (64, 128 or 256; one workgroup each) of one row
+ * that hold active nodes, in order 0 (instance by instance) or 1 (round
+ * robin over the instances).  tlvlbm_batch_create picks the configuration
+ * by timing the bulk kernel over each of the six on the batch's own state
+ * (3 timed launches each; u* and u are saved and restored, no step is
+ * taken); tlvlbm_batch_autotune repeats that with `reps` timed launches;
+ * tlvlbm_batch_set_tiles forces one.  Results do not depend on the
+ * configuration (the per-node arithmetic is the same).
+ * tlvlbm_batch_get_tiles: the configuration in use and, in ms[6] (may be
+ * NULL), the mean time per launch of each candidate, index order * 3 +
+ * (0, 1, 2 for widths 64, 128, 256).  Errors: TLVLBM_ERR_INVALID_ARG for
+ * other widths or orders; device errors as for tlvlbm_batch_step. */
+tlvlbm_status tlvlbm_batch_autotune(tlvlbm_batch *b, int32_t reps);
+tlvlbm_status tlvlbm_batch_set_tiles(tlvlbm_batch *b, int32_t tile_width, int32_t order);
+tlvlbm_status tlvlbm_batch_get_tiles(const tlvlbm_batch *b, int32_t *tile_width, int32_t *order, double *ms);
 tlvlbm_status tlvlbm_batch_destroy(tlvlbm_batch *b);
 const char *tlvlbm_batch_last_error(const tlvlbm_batch *b);
 

@@ -6,7 +6,7 @@ The compute path is the HIP library ``libtlvlbm.so`` behind the C ABI in
 binding (and with it the library) loads on first use of one of its names, so
 that ``paper_2606_20646_amd.build`` can compile the library first.
 """
-_EXPORTS = ("DIRICHLET", "FP32", "FP64", "NEUMANN", "LIB_PATH", "Solver", "TlvlbmError")
+_EXPORTS = ("DIRICHLET", "FP32", "FP64", "NEUMANN", "LIB_PATH", "Solver", "TlvlbmError", "run_differentiable")
 
 
 def __getattr__(name):

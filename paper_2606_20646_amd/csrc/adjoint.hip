@@ -1420,7 +1420,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
 
 using namespace tl;
 
-extern "C" tlvlbm_status tlvlbm_adjoint(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0,
+extern "C" tlvlbm_status tlvlbm_adjoint_step(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0,
                                         const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
                                         double *grad_u0, int64_t segment) {
   if (!c || n < 0 || !U0) return TLVLBM_ERR_INVALID_ARG;

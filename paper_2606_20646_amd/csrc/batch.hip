@@ -23,6 +23,12 @@ struct tlvlbm_batch {
   Inst *d_inst = nullptr;
   int4 *d_btiles = nullptr, *d_ctiles = nullptr, *d_ltiles = nullptr;
   int nbt = 0, nct = 0, nlt = 0;
+  // node-kernel tiles: tw nodes of one row holding active nodes, in order
+  // `torder` (0: instance by instance, 1: round robin over the instances);
+  // chosen by batch_autotune
+  int tw = 256, torder = 0;
+  double tune_ms[2][3] = {};
+  std::vector<std::vector<uint8_t>> act;  // host copies of the activity masks
   Seg *d_segs = nullptr;
   int64_t *d_step = nullptr;
   int *d_pending = nullptr, *h_pending = nullptr;
@@ -144,19 +150,19 @@ tlvlbm_status pcg_batch(tlvlbm_batch *b, int anch) {
 }
 
 void plain_step(tlvlbm_batch *b) {
-  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, false, b->st);
+  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, false, b->tw, b->st);
   if (b->nlt) run(b, BatchOp::Cut);
   run(b, BatchOp::StepEnd);
 }
 
 tlvlbm_status projection_step(tlvlbm_batch *b) {
-  launch_moments_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, b->st);
+  launch_moments_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, b->tw, b->st);
   run(b, BatchOp::XfromU);
   tlvlbm_status s = cg_batch(b, 0);
   if (s) return s;
   run(b, BatchOp::UfromX);
   run(b, BatchOp::GradF);
-  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, true, b->st);
+  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, true, b->tw, b->st);
   run(b, BatchOp::XfromU);
   s = cg_batch(b, 1);
   if (s) return s;
@@ -164,6 +170,138 @@ tlvlbm_status projection_step(tlvlbm_batch *b) {
   if (b->nlt) run(b, BatchOp::Cut);
   run(b, BatchOp::StepEnd);
   return TLVLBM_OK;
+}
+
+// tiles of W nodes of one row that hold active nodes; order 0: instance by
+// instance, 1: round robin over the instances (tile r of each, then r + 1)
+std::vector<int4> node_tiles(const tlvlbm_batch *b, int W, int order) {
+  const int ni = (int)b->c.size();
+  std::vector<std::vector<int4>> per(ni);
+  for (int k = 0; k < ni; ++k) {
+    const Geo &g = b->c[k]->geo;
+    const std::vector<uint8_t> &a = b->act[k];
+    for (int row = 0; row < g.ny * g.nz; ++row)
+      for (int x0 = 0; x0 < g.nx; x0 += W) {
+        bool any = a.empty();
+        for (int x = x0; x < std::min(g.nx, x0 + W) && !any; ++x) any = a[(size_t)row * g.nx + x] != 0;
+        if (any) per[k].push_back(make_int4(k, row, x0, 0));
+      }
+  }
+  std::vector<int4> t;
+  if (order == 0) {
+    for (auto &v : per) t.insert(t.end(), v.begin(), v.end());
+  } else {
+    size_t most = 0;
+    for (auto &v : per) most = std::max(most, v.size());
+    for (size_t r = 0; r < most; ++r)
+      for (auto &v : per)
+        if (r < v.size()) t.push_back(v[r]);
+  }
+  return t;
+}
+
+tlvlbm_status set_tiles(tlvlbm_batch *b, const std::vector<int4> &t, int W, int order) {
+  int4 *d = nullptr;
+  BCHK(hipMalloc(&d, std::max<size_t>(1, t.size()) * sizeof(int4)), "tile alloc");
+  if (!t.empty() && hipMemcpyAsync(d, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice, b->st) != hipSuccess) {
+    (void)hipFree(d);
+    return bfail(b, TLVLBM_ERR_DEVICE, "tile upload");
+  }
+  BCHK(hipStreamSynchronize(b->st), "synchronize");
+  if (b->d_btiles) (void)hipFree(b->d_btiles);
+  b->d_btiles = d;
+  b->nbt = (int)t.size();
+  b->tw = W;
+  b->torder = order;
+  if (b->gexec) {  // the captured steps hold the old tiles
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->glen = 0;
+  }
+  return TLVLBM_OK;
+}
+
+// Time the bulk kernel over every tile configuration (reps launches each,
+// after one untimed) on the batch's own state and keep the fastest.  The
+// kernel reads the populations and rewrites the displacement history in
+// place, so u* and u of every instance are saved first and restored after
+// every launch: no step is taken and the state is unchanged.
+tlvlbm_status batch_autotune(tlvlbm_batch *b, int reps) {
+  const int ni = (int)b->c.size();
+  const int widths[3] = {64, 128, 256};
+  std::vector<void *> keep(2 * ni, nullptr);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int4 *dt = nullptr;
+  tlvlbm_status res = TLVLBM_OK;
+  auto restore = [&]() {
+    for (int k = 0; k < ni; ++k) {
+      const size_t bytes = (size_t)b->D * b->c[k]->geo.S * sizeof(double);
+      if (keep[2 * k] && hipMemcpyAsync(b->c[k]->ustar, keep[2 * k], bytes, hipMemcpyDeviceToDevice, b->st))
+        return false;
+      if (keep[2 * k + 1] && hipMemcpyAsync(b->c[k]->ubuf, keep[2 * k + 1], bytes, hipMemcpyDeviceToDevice, b->st))
+        return false;
+    }
+    return true;
+  };
+  double best = 1e300;
+  int bw = b->tw, bo = b->torder;
+  do {
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    for (int k = 0; ok && k < ni; ++k) {
+      const size_t bytes = (size_t)b->D * b->c[k]->geo.S * sizeof(double);
+      void *src[2] = {b->c[k]->ustar, b->c[k]->ubuf};
+      for (int j = 0; ok && j < 2; ++j) {
+        if (!src[j]) continue;
+        ok = hipMalloc(&keep[2 * k + j], bytes) == hipSuccess &&
+             hipMemcpyAsync(keep[2 * k + j], src[j], bytes, hipMemcpyDeviceToDevice, b->st) == hipSuccess;
+      }
+    }
+    if (!ok) {
+      res = bfail(b, TLVLBM_ERR_OUT_OF_MEMORY, "autotune: no room for the saved displacement history");
+      break;
+    }
+    for (int order = 0; order < 2 && res == TLVLBM_OK; ++order)
+      for (int wi = 0; wi < 3 && res == TLVLBM_OK; ++wi) {
+        const std::vector<int4> t = node_tiles(b, widths[wi], order);
+        if (dt) (void)hipFree(dt);
+        dt = nullptr;
+        if (hipMalloc(&dt, std::max<size_t>(1, t.size()) * sizeof(int4)) != hipSuccess ||
+            (!t.empty() &&
+             hipMemcpyAsync(dt, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice, b->st) != hipSuccess)) {
+          res = bfail(b, TLVLBM_ERR_DEVICE, "autotune: tile upload");
+          break;
+        }
+        double tot = 0.0;
+        for (int r = 0; r <= reps; ++r) {
+          float ms = 0.0f;
+          if (hipEventRecord(e0, b->st) != hipSuccess) res = TLVLBM_ERR_DEVICE;
+          launch_bulk_batch(b->D, b->prec, b->d_inst, dt, (int)t.size(), false, widths[wi], b->st);
+          if (hipEventRecord(e1, b->st) != hipSuccess || !restore() || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            res = TLVLBM_ERR_DEVICE;
+          if (res) break;
+          if (r > 0) tot += ms;
+        }
+        if (res) {
+          res = bfail(b, res, "autotune: timing");
+          break;
+        }
+        b->tune_ms[order][wi] = tot / std::max(reps, 1);
+        if (b->tune_ms[order][wi] < best) {
+          best = b->tune_ms[order][wi];
+          bw = widths[wi];
+          bo = order;
+        }
+      }
+  } while (false);
+  if (hipStreamSynchronize(b->st) != hipSuccess && !res) res = bfail(b, TLVLBM_ERR_DEVICE, "autotune: synchronize");
+  if (dt) (void)hipFree(dt);
+  for (void *p : keep)
+    if (p) (void)hipFree(p);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (res) return res;
+  return set_tiles(b, node_tiles(b, bw, bo), bw, bo);
 }
 
 // capture glen plain steps once; replayed for every such stretch
@@ -251,9 +389,18 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       I.flag = c->d_flag;
       I.nfail = (unsigned long long *)c->d_newton_fail;
       b->h_inst.push_back(I);
-      const Geo &g = c->geo;
-      for (int row = 0; row < g.ny * g.nz; ++row)
-        for (int x0 = 0; x0 < g.nx; x0 += 256) bt.push_back(make_int4(k, row, x0, 0));
+      {
+        // activity mask on the host for the node-tile lists (empty: all active)
+        std::vector<uint8_t> a;
+        if (c->act) {
+          a.resize((size_t)c->geo.N);
+          if (hipMemcpy(a.data(), c->act, a.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+            tlvlbm_batch_destroy(b);
+            return TLVLBM_ERR_DEVICE;
+          }
+        }
+        b->act.push_back(std::move(a));
+      }
       for (int blk = 0; blk < c->cg.nblk; ++blk) ct.push_back(make_int4(k, blk, 0, 0));
       for (int bid = 0; bid < 256; ++bid) {
         const int64_t b0 = c->bid_begin[bid], b1 = c->bid_end[bid];
@@ -271,6 +418,7 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       }
       b->maxit = std::max<int64_t>(b->maxit, c->cg_maxit > 0 ? c->cg_maxit : cg_default_maxit(c->nactive));
     }
+    bt = node_tiles(b, b->tw, b->torder);
     b->nbt = (int)bt.size();
     b->nct = (int)ct.size();
     b->nlt = (int)lt.size();
@@ -329,7 +477,7 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       }
     }
     if (hipMalloc(&b->d_inst, n * sizeof(Inst)) != hipSuccess ||
-        hipMalloc(&b->d_btiles, bt.size() * sizeof(int4)) != hipSuccess ||
+        hipMalloc(&b->d_btiles, std::max<size_t>(1, bt.size()) * sizeof(int4)) != hipSuccess ||
         hipMalloc(&b->d_ctiles, ct.size() * sizeof(int4)) != hipSuccess ||
         hipMalloc(&b->d_ltiles, std::max<size_t>(1, lt.size()) * sizeof(int4)) != hipSuccess ||
         hipMalloc(&b->d_segs, std::max<size_t>(1, segs.size()) * sizeof(Seg)) != hipSuccess ||
@@ -341,7 +489,8 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
     }
     hipStream_t st = b->st;
     if (hipMemcpyAsync(b->d_inst, b->h_inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(b->d_btiles, bt.data(), bt.size() * sizeof(int4), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (bt.size() &&
+         hipMemcpyAsync(b->d_btiles, bt.data(), bt.size() * sizeof(int4), hipMemcpyHostToDevice, st) != hipSuccess) ||
         hipMemcpyAsync(b->d_ctiles, ct.data(), ct.size() * sizeof(int4), hipMemcpyHostToDevice, st) != hipSuccess ||
         (lt.size() &&
          hipMemcpyAsync(b->d_ltiles, lt.data(), lt.size() * sizeof(int4), hipMemcpyHostToDevice, st) != hipSuccess) ||
@@ -352,12 +501,39 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       tlvlbm_batch_destroy(b);
       return TLVLBM_ERR_DEVICE;
     }
+    // tile configuration of the node kernels, timed on this batch
+    const tlvlbm_status ts = batch_autotune(b, 3);
+    if (ts) {
+      tlvlbm_batch_destroy(b);
+      return ts;
+    }
     *out = b;
     return TLVLBM_OK;
   } catch (...) {
     delete b;
     return TLVLBM_ERR_OUT_OF_MEMORY;
   }
+}
+
+tlvlbm_status tlvlbm_batch_autotune(tlvlbm_batch *b, int32_t reps) {
+  if (!b || reps < 1) return TLVLBM_ERR_INVALID_ARG;
+  return batch_autotune(b, reps);
+}
+
+tlvlbm_status tlvlbm_batch_set_tiles(tlvlbm_batch *b, int32_t tile_width, int32_t order) {
+  if (!b || (tile_width != 64 && tile_width != 128 && tile_width != 256) || (order != 0 && order != 1))
+    return TLVLBM_ERR_INVALID_ARG;
+  return set_tiles(b, node_tiles(b, tile_width, order), tile_width, order);
+}
+
+tlvlbm_status tlvlbm_batch_get_tiles(const tlvlbm_batch *b, int32_t *tile_width, int32_t *order, double *ms) {
+  if (!b) return TLVLBM_ERR_INVALID_ARG;
+  if (tile_width) *tile_width = b->tw;
+  if (order) *order = b->torder;
+  if (ms)
+    for (int o = 0; o < 2; ++o)
+      for (int w = 0; w < 3; ++w) ms[o * 3 + w] = b->tune_ms[o][w];
+  return TLVLBM_OK;
 }
 
 tlvlbm_status tlvlbm_batch_set_graph(tlvlbm_batch *b, int32_t use_graph) {

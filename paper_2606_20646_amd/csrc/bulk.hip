@@ -858,32 +858,34 @@ void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar) {
 namespace tl {
 
 // batched launchers: tiles are (instance, row, first x, 0) triples of 256 nodes
-template <int D, typename T> static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool repair,
-                                                      hipStream_t st) {
+template <int D, typename T>
+static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw, hipStream_t st) {
   if (repair)
-    hipLaunchKernelGGL((k_bulk_batch<D, T, true>), ntiles, 256, 0, st, insts, tiles);
+    hipLaunchKernelGGL((k_bulk_batch<D, T, true>), ntiles, tw, 0, st, insts, tiles);
   else
-    hipLaunchKernelGGL((k_bulk_batch<D, T, false>), ntiles, 256, 0, st, insts, tiles);
+    hipLaunchKernelGGL((k_bulk_batch<D, T, false>), ntiles, tw, 0, st, insts, tiles);
 }
 
-void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair,
+// tw: nodes per tile = threads per workgroup (<= 256)
+void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw,
                        hipStream_t st) {
   if (D == 2) {
-    if (prec) bulk_batch_t<2, double>(insts, tiles, ntiles, repair, st);
-    else bulk_batch_t<2, float>(insts, tiles, ntiles, repair, st);
+    if (prec) bulk_batch_t<2, double>(insts, tiles, ntiles, repair, tw, st);
+    else bulk_batch_t<2, float>(insts, tiles, ntiles, repair, tw, st);
   } else {
-    if (prec) bulk_batch_t<3, double>(insts, tiles, ntiles, repair, st);
-    else bulk_batch_t<3, float>(insts, tiles, ntiles, repair, st);
+    if (prec) bulk_batch_t<3, double>(insts, tiles, ntiles, repair, tw, st);
+    else bulk_batch_t<3, float>(insts, tiles, ntiles, repair, tw, st);
   }
 }
 
-void launch_moments_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, hipStream_t st) {
+void launch_moments_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, int tw,
+                          hipStream_t st) {
   if (D == 2) {
-    if (prec) hipLaunchKernelGGL((k_moments_batch<2, double>), ntiles, 256, 0, st, insts, tiles);
-    else hipLaunchKernelGGL((k_moments_batch<2, float>), ntiles, 256, 0, st, insts, tiles);
+    if (prec) hipLaunchKernelGGL((k_moments_batch<2, double>), ntiles, tw, 0, st, insts, tiles);
+    else hipLaunchKernelGGL((k_moments_batch<2, float>), ntiles, tw, 0, st, insts, tiles);
   } else {
-    if (prec) hipLaunchKernelGGL((k_moments_batch<3, double>), ntiles, 256, 0, st, insts, tiles);
-    else hipLaunchKernelGGL((k_moments_batch<3, float>), ntiles, 256, 0, st, insts, tiles);
+    if (prec) hipLaunchKernelGGL((k_moments_batch<3, double>), ntiles, tw, 0, st, insts, tiles);
+    else hipLaunchKernelGGL((k_moments_batch<3, float>), ntiles, tw, 0, st, insts, tiles);
   }
 }
 

@@ -262,9 +262,11 @@ struct DevOut {
 };
 
 void launch_batch(int D, int prec, BatchOp op, const BatchArgs &a);
-void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair,
+// batched node kernels over tiles of tw nodes of one row (tw <= 256 threads)
+void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw,
                        hipStream_t st);
-void launch_moments_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, hipStream_t st);
+void launch_moments_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, int tw,
+                          hipStream_t st);
 int ensure_cg(tlvlbm_ctx *c);
 int64_t cg_default_maxit(int64_t nactive);
 double cg_default_rtol(int prec);

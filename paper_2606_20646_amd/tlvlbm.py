@@ -104,16 +104,20 @@ def _load():
     L.tlvlbm_population_bytes.argtypes = [vp]
     L.tlvlbm_population_bytes.restype = C.c_size_t
     L.tlvlbm_step_each.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64]
-    L.tlvlbm_adjoint.argtypes = [vp, C.c_int64, dp, dp, dp, dp, C.POINTER(C.c_double), dp, dp, C.c_int64]
+    L.tlvlbm_adjoint_step.argtypes = [vp, C.c_int64, dp, dp, dp, dp, C.POINTER(C.c_double), dp, dp, C.c_int64]
     L.tlvlbm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
     L.tlvlbm_batch_step.argtypes = [vp, C.c_int64]
     L.tlvlbm_batch_set_graph.argtypes = [vp, C.c_int32]
+    L.tlvlbm_batch_autotune.argtypes = [vp, C.c_int32]
+    L.tlvlbm_batch_set_tiles.argtypes = [vp, C.c_int32, C.c_int32]
+    L.tlvlbm_batch_get_tiles.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     L.tlvlbm_batch_destroy.argtypes = [vp]
     L.tlvlbm_batch_last_error.argtypes = [vp]
     L.tlvlbm_batch_last_error.restype = C.c_char_p
     for name in ("create", "destroy", "set_levelset", "set_boundary", "set_material", "set_state", "step",
                  "moments", "get_state", "put_state", "get_links", "stats", "synchronize", "step_each",
-                 "batch_create", "batch_step", "batch_set_graph", "batch_destroy", "adjoint"):
+                 "batch_create", "batch_step", "batch_set_graph", "batch_destroy", "adjoint_step",
+                 "batch_autotune", "batch_set_tiles", "batch_get_tiles"):
         getattr(L, "tlvlbm_" + name).restype = C.c_int
     return L
 
@@ -233,7 +237,7 @@ class Solver:
         g0 = np.zeros((self.D, self.N)) if grad_u0 else None
         args = [a if (a is None or not isinstance(a, np.ndarray)) else np.ascontiguousarray(a, np.float64)
                 for a in (dLdU, dLdu)]
-        self._chk(lib.tlvlbm_adjoint(self.h, int(n), _ptr(U0)[0], _ptr(dU0)[0], _ptr(args[0])[0], _ptr(args[1])[0],
+        self._chk(lib.tlvlbm_adjoint_step(self.h, int(n), _ptr(U0)[0], _ptr(dU0)[0], _ptr(args[0])[0], _ptr(args[1])[0],
                                      gm, _ptr(gv)[0], _ptr(g0)[0], int(segment)), "adjoint")
         return np.array([gm[0], gm[1]]), gv, g0
 
@@ -317,9 +321,90 @@ class Batch:
         if st:
             raise TlvlbmError(st, f"batch_step: {lib.tlvlbm_batch_last_error(self.h).decode()}")
 
+    def autotune(self, reps=3):
+        st = lib.tlvlbm_batch_autotune(self.h, int(reps))
+        if st:
+            raise TlvlbmError(st, f"batch_autotune: {lib.tlvlbm_batch_last_error(self.h).decode()}")
+        return self.tiles()
+
+    def set_tiles(self, tile_width, order):
+        st = lib.tlvlbm_batch_set_tiles(self.h, int(tile_width), int(order))
+        if st:
+            raise TlvlbmError(st, f"batch_set_tiles: {lib.tlvlbm_batch_last_error(self.h).decode()}")
+
+    def tiles(self):
+        """(tile_width, order, {(order, width): mean ms per bulk launch})."""
+        w, o = C.c_int32(0), C.c_int32(0)
+        ms = (C.c_double * 6)()
+        st = lib.tlvlbm_batch_get_tiles(self.h, C.byref(w), C.byref(o), ms)
+        if st:
+            raise TlvlbmError(st, "batch_get_tiles")
+        return w.value, o.value, {(k // 3, (64, 128, 256)[k % 3]): ms[k] for k in range(6)}
+
     def close(self):
         if getattr(self, "h", None) and lib is not None:
             lib.tlvlbm_batch_destroy(self.h)
             self.h = None
 
     __del__ = close
+
+
+_RUN_FN = None
+
+
+def _run_fn():
+    """torch.autograd.Function over tlvlbm_step / tlvlbm_adjoint_step (built
+    on first use, so that importing the binding does not import torch)."""
+    global _RUN_FN
+    if _RUN_FN is not None:
+        return _RUN_FN
+    import torch
+
+    class _Run(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, mat, v0, solver, n, U0, dU0, segment, fibre):
+            mu, lam = (float(x) for x in mat.detach().to("cpu", torch.float64))
+            U = np.array(U0, np.float64, copy=True)
+            U[: solver.D] = v0.detach().to("cpu", torch.float64).numpy()
+            solver.set_material(mu, lam, fibre)
+            solver.set_state(U, dU0=dU0)
+            solver.step(n)
+            Uo, uo, _ = solver.moments(J=False)
+            ctx.run = (solver, n, U, dU0, segment, fibre, mu, lam)
+            ctx.devices = (mat.device, v0.device)
+            return torch.from_numpy(Uo).to(v0.device), torch.from_numpy(uo).to(v0.device)
+
+        @staticmethod
+        def backward(ctx, gU, gu):
+            solver, n, U, dU0, segment, fibre, mu, lam = ctx.run
+
+            def host(t):
+                if t is None:
+                    return None
+                a = t.detach().to("cpu", torch.float64).contiguous().numpy()
+                return a if np.any(a) else None
+
+            # the reverse mode restarts from the initial state of the forward
+            solver.set_material(mu, lam, fibre)
+            solver.set_state(U, dU0=dU0)
+            gm, gv, _ = solver.adjoint(n, host(gU), host(gu), segment=segment, grad_v0=True, grad_u0=False)
+            gmat = torch.tensor(gm, dtype=torch.float64, device=ctx.devices[0])
+            gv0 = torch.from_numpy(gv).to(ctx.devices[1])
+            return gmat, gv0, None, None, None, None, None, None
+
+    _RUN_FN = _Run
+    return _Run
+
+
+def run_differentiable(solver, mat, v0, n, U0, dU0=None, segment=0, fibre=None):
+    """Differentiable run of n steps for torch autograd.
+
+    mat: tensor (mu, lambda) [2]; v0: tensor [D][nodes], the velocity rows of
+    the initial state; U0: the initial state [M][nodes] (its F rows are used,
+    its velocity rows replaced by v0); dU0: its gradients as for set_state.
+    Returns (U, u) after n steps as float64 tensors on v0's device.  The
+    backward pass calls tlvlbm_adjoint_step from the same initial state (one
+    more forward, then the reverse) and returns dL/d(mu, lambda) and dL/dv0;
+    the solver's boundary conditions and level set stay as set by the caller.
+    Every step runs in the library's kernels; this is argument marshalling."""
+    return _run_fn().apply(mat, v0, solver, int(n), U0, dU0, int(segment), fibre)

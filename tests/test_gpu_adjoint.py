@@ -131,3 +131,26 @@ def test_adjoint_sphere_32(T, orc):
     assert np.all(np.abs(gm - gm_o) <= 1e-9 * np.abs(gm_o).max())
     assert _rel(gv, gv_o) <= 1e-9
     assert _rel(g0, g0_o) <= 1e-9
+
+
+def test_autograd_function_matches_adjoint(T):
+    """The torch.autograd wrapper returns the reverse mode's gradients."""
+    import torch
+    _say("autograd wrapper neumann_annulus_projection fp64")
+    make, n = CASES["neumann_annulus_projection"]
+    cfg = make()
+    wU, wu = _weights(cfg)
+    D = cfg["D"]
+    s = _solver(T, cfg, "fp64")
+    mat = torch.tensor([cfg["mu"], cfg["lam"]], dtype=torch.float64, requires_grad=True)
+    v0 = torch.tensor(cfg["U0"][:D], dtype=torch.float64, requires_grad=True)
+    U, u = T.run_differentiable(s, mat, v0, n, cfg["U0"], dU0=cfg.get("dU0"))
+    loss = (torch.from_numpy(wU) * U).sum() + (torch.from_numpy(wu) * u).sum()
+    loss.backward()
+    r = _solver(T, cfg, "fp64")
+    r.set_state(cfg["U0"], dU0=cfg.get("dU0"))
+    gm, gv, _ = r.adjoint(n, wU, wu)
+    Ur, ur, _ = r.moments()
+    assert np.array_equal(U.detach().numpy(), Ur) and np.array_equal(u.detach().numpy(), ur)
+    assert np.array_equal(mat.grad.numpy(), gm)
+    assert np.array_equal(v0.grad.numpy(), gv)

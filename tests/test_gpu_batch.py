@@ -110,3 +110,37 @@ def test_batched_instance_matches_oracle(env, orc):
         act = c["phi"] <= 0
         assert np.linalg.norm(Ub[:, act] - Uo[:, act]) <= 1e-11 * np.linalg.norm(Uo[:, act])
         assert np.linalg.norm(ub[:, act] - uo[:, act]) <= 1e-10 * np.linalg.norm(uo[:, act])
+
+
+def test_tile_configurations_agree(env):
+    """Every tile configuration of the batched node kernels gives the same
+    state bit for bit (the per-node arithmetic does not depend on it), and
+    the autotuner takes no step and leaves the state as it found it."""
+    T, stream = env
+    _say("batch tile configurations fp32 (64/128/256 x two orders) and autotune")
+    ref = None
+    for order in (0, 1):
+        for width in (64, 128, 256):
+            B = [_solver(T, c, "fp32", stream) for c in CFGS]
+            bt = T.Batch(B)
+            w, o, ms = bt.tiles()
+            assert w in (64, 128, 256) and o in (0, 1) and all(v > 0 for v in ms.values())
+            bt.autotune(2)  # again: no step, state untouched
+            bt.set_tiles(width, order)
+            assert bt.tiles()[:2] == (width, order)
+            bt.step(45)
+            bt.close()
+            out = [b.moments()[:2] for b in B]
+            assert all(b.stats()["step"] == 45 for b in B)
+            if ref is None:
+                ref = out
+                continue
+            for (U, u), (Ur, ur) in zip(out, ref):
+                assert np.array_equal(U, Ur) and np.array_equal(u, ur)
+    # the same steps without any batch: per-instance launches
+    A = [_solver(T, c, "fp32", stream) for c in CFGS]
+    T.step_each(A, 45)
+    for a, (Ur, _), c in zip(A, ref, CFGS):
+        act = c["phi"] <= 0
+        Ua = a.moments()[0]
+        assert np.linalg.norm(Ua[:, act] - Ur[:, act]) <= 1e-6 * np.linalg.norm(Ua[:, act])

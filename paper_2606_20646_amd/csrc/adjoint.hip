@@ -412,23 +412,30 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
   double lg[M];
 #pragma unroll
   for (int r = 0; r < M; ++r) lg[r] = double(Lb[(size_t)(qi * M + r) * g.S + o]);
+  // (read all M targets, then write them: the M slots of one link are
+  // distinct, and interleaved loads and stores through one pointer would be
+  // issued one row at a time)
   if constexpr (PASS == 2) {
-    if (eta >= 0.5)
+    if (eta >= 0.5) {
+      T cur[M];
 #pragma unroll
-      for (int r = 0; r < M; ++r) {
-        T *t = Lb + (size_t)(qi * M + r) * g.S + m;
-        *t = T(double(*t) + (1.0 - 0.5 / eta) * lg[r]);
-      }
+      for (int r = 0; r < M; ++r) cur[r] = Lb[(size_t)(qi * M + r) * g.S + m];
+#pragma unroll
+      for (int r = 0; r < M; ++r) Lb[(size_t)(qi * M + r) * g.S + m] = T(double(cur[r]) + (1.0 - 0.5 / eta) * lg[r]);
+    }
     return;
   }
   if constexpr (PASS == 3) {
-    if (eta < 0.5 && mm != m)
+    if (eta < 0.5 && mm != m) {
+      T cur[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) cur[r] = Lb[(size_t)(qo * M + r) * g.S + mm];
 #pragma unroll
       for (int r = 0; r < M; ++r) {
         const double Dg = NEU ? (r < D ? 1.0 : -1.0) : (r < D ? -1.0 : 1.0);
-        T *t = Lb + (size_t)(qo * M + r) * g.S + mm;
-        *t = T(double(*t) + Dg * (1.0 - 2.0 * eta) * lg[r]);
+        Lb[(size_t)(qo * M + r) * g.S + mm] = T(double(cur[r]) + Dg * (1.0 - 2.0 * eta) * lg[r]);
       }
+    }
     return;
   }
   // PASS 1

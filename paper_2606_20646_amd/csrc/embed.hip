@@ -382,6 +382,23 @@ __global__ void k_link_lsq(Geo g, const uint8_t *__restrict__ act, Links L, int 
 
 // ----------------------------------------------------- cut-link closure
 
+// The populations a closure reads, all loaded before any write: f*_out(m)
+// and, for eta >= 1/2, f*_in(m), else f*_out(m^-).  The closure writes only
+// the pull slot of the outside node, which no link reads, so the loads can
+// all be in flight together (interleaved with the writes through the same
+// pointer they would be issued one row at a time).
+template <int D, typename T>
+__device__ __forceinline__ void closure_reads(const T *__restrict__ f, const Geo &g, int64_t m, int64_t mm, int qo,
+                                              double eta, T (&fo)[D + D * D], T (&fx)[D + D * D]) {
+  constexpr int M = D + D * D;
+  const int qi = qo ^ 1;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    fo[r] = f[(size_t)(qo * M + r) * g.S + m];
+    fx[r] = (eta >= 0.5) ? f[(size_t)(qi * M + r) * g.S + m] : f[(size_t)(qo * M + r) * g.S + mm];
+  }
+}
+
 // Velocity Dirichlet (Sec. 3.3, Eqs. 44-45) with cut-link interpolation
 // (Sec. 3.2, Eqs. 42-43).  f holds post-collision populations (shifted); the
 // reconstructed incoming population is written to the pull slot of the
@@ -407,6 +424,8 @@ __device__ __forceinline__ void cut_dirichlet_link(T *__restrict__ f, const Link
   twist_add(bc, Xb, s, ds, true, vb);
   const T ie = T(1.0 / (2.0 * eta));
   const T e2 = T(2.0 * eta);
+  T fo[M], fx[M];
+  closure_reads<D, T>(f, g, m, mm, qo, eta, fo, fx);
 #pragma unroll
   for (int r = 0; r < M; ++r) {
     T Dg, S;
@@ -419,15 +438,9 @@ __device__ __forceinline__ void cut_dirichlet_link(T *__restrict__ f, const Link
       // -d_B v_i / c with d = -e_{q_out}; the shift cancels for these rows
       S = (B == A) ? T(sg * vb[i] / p.c) : T(0);
     }
-    const T fo = f[(size_t)(qo * M + r) * g.S + m];
     T out;
-    if (eta >= 0.5) {
-      const T fi = f[(size_t)(qi * M + r) * g.S + m];
-      out = (Dg * fo + S) * ie + (T(1) - ie) * fi;
-    } else {
-      const T fm = f[(size_t)(qo * M + r) * g.S + mm];
-      out = Dg * (e2 * fo + (T(1) - e2) * fm) + S;
-    }
+    if (eta >= 0.5) out = (Dg * fo[r] + S) * ie + (T(1) - ie) * fx[r];
+    else out = Dg * (e2 * fo[r] + (T(1) - e2) * fx[r]) + S;
     f[(size_t)(qi * M + r) * g.S + o] = out;
   }
 }
@@ -497,6 +510,8 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
   mat_piola<D>(Fb, p, Pb);
   const T ie = T(1.0 / (2.0 * eta));
   const T e2 = T(2.0 * eta);
+  T fo[M], fx[M];
+  closure_reads<D, T>(f, g, m, mm, qo, eta, fo, fx);
 #pragma unroll
   for (int r = 0; r < M; ++r) {
     T Dg, S;
@@ -509,15 +524,9 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
       // F_b/D in shifted variables: (F_b - I)/D
       S = T((Fb[k] - ((k % (D + 1) == 0) ? 1.0 : 0.0)) / D);
     }
-    const T fo = f[(size_t)(qo * M + r) * g.S + m];
     T out;
-    if (eta >= 0.5) {
-      const T fi = f[(size_t)(qi * M + r) * g.S + m];
-      out = (Dg * fo + S) * ie + (T(1) - ie) * fi;
-    } else {
-      const T fm = f[(size_t)(qo * M + r) * g.S + mm];
-      out = Dg * (e2 * fo + (T(1) - e2) * fm) + S;
-    }
+    if (eta >= 0.5) out = (Dg * fo[r] + S) * ie + (T(1) - ie) * fx[r];
+    else out = Dg * (e2 * fo[r] + (T(1) - e2) * fx[r]) + S;
     f[(size_t)(qi * M + r) * g.S + o] = out;
   }
 }

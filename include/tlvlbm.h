@@ -259,7 +259,7 @@ const char *tlvlbm_last_error(const tlvlbm_ctx *ctx);
  *    short runs), and only the steps before them are checkpointed and
  *    recomputed, in segments of about sqrt(steps x checkpoint / tape step).
  *    < 0: as 0 with at most -segment taped final steps.  Tape per step:
- *    D x D planes of F - I over the 64-node chunks that hold active nodes
+ *    D x D planes of F - I over the 32-node chunks that hold active nodes
  *    (population precision), F^r likewise on projection steps, and u at the
  *    Neumann stencil nodes (FP64).  TLVLBM_ERR_OUT_OF_MEMORY if checkpoints
  *    and tape do not fit.  When a quarter of the remaining memory holds

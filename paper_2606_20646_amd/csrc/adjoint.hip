@@ -174,10 +174,10 @@ __device__ __forceinline__ void push_adj(T *__restrict__ Lin, const Geo &g, cons
 }
 
 // tape planes (F - I of every step, F^r of projection steps) hold one slot
-// per node of the chunk list, cpos[i / 64] * 64 + i % 64, plane stride ts
+// per node of the chunk list, cpos[i / CHUNK] * CHUNK + i % CHUNK, plane stride ts
 // (without a chunk list: the node index, stride S)
 __device__ __forceinline__ int64_t tslot(const int32_t *__restrict__ cpos, int64_t node) {
-  return cpos ? (int64_t)cpos[node >> 6] * 64 + (node & 63) : node;
+  return cpos ? (int64_t)cpos[node / CHUNK] * CHUNK + (node % CHUNK) : node;
 }
 
 template <int D, typename T>
@@ -217,8 +217,8 @@ __global__ __launch_bounds__(AT) void k_adj_seed(T *__restrict__ Lin, Geo g, Adj
 // ------------------------------------------------- bulk transpose (plain)
 // collision (Eq. 29) with the damping source, recovery (Eq. 28) and the
 // displacement history (Eq. 34): u = u* + dt/2 v, u*' = u + dt/2 v.
-// CH: embedded bodies, over the list of 64-node chunks that hold active
-// nodes (one wavefront per chunk, as the forward update); else one block
+// CH: embedded bodies, over the list of CHUNK-node chunks that hold active
+// nodes (64 / CHUNK chunks per wavefront, as the forward update); else one block
 // per (row, x range).
 template <int D, typename T, bool MASK, bool TRACK, bool CH = false>
 __global__ __launch_bounds__(AT, 3) void k_adj_bulk(const T *__restrict__ Lout, T *__restrict__ Lin, Geo g, AdjPar p,
@@ -231,12 +231,12 @@ __global__ __launch_bounds__(AT, 3) void k_adj_bulk(const T *__restrict__ Lout, 
   bool live;
   int64_t slot = 0;
   if constexpr (CH) {
-    const int ch = blockIdx.x * (AT / 64) + (threadIdx.x >> 6);
-    const int64_t i = ch < nchunks ? (int64_t)chunks[ch] * 64 + (threadIdx.x & 63) : g.N;
+    const int ch = blockIdx.x * (AT / CHUNK) + (int)(threadIdx.x / CHUNK);
+    const int64_t i = ch < nchunks ? (int64_t)chunks[ch] * CHUNK + (threadIdx.x % CHUNK) : g.N;
     live = i < g.N;
     x = live ? (int)(i % g.nx) : 0;
     row = live ? (int)(i / g.nx) : 0;
-    slot = (int64_t)ch * 64 + (threadIdx.x & 63);
+    slot = (int64_t)ch * CHUNK + (threadIdx.x % CHUNK);
   } else {
     x = blockIdx.x * blockDim.x + threadIdx.x;
     row = blockIdx.y;
@@ -981,7 +981,7 @@ template <int D, typename T> int reverse_step(Run &R, int64_t k, const TapeStep 
   if (!proj) {
     const T *tU = (const T *)tp.U;
     if (c->act && c->chunks) {
-      const unsigned nb = (unsigned)((c->nchunks + AT / 64 - 1) / (AT / 64));
+      const unsigned nb = (unsigned)((c->nchunks + AT / CHUNK - 1) / (AT / CHUNK));
       if (c->track_u)
         hipLaunchKernelGGL((k_adj_bulk<D, T, true, true, true>), nb, AT, 0, c->st, Lout, Lin, g, R.ap, c->act, tU,
                            R.ts, R.ubc, R.lus, R.gblk, c->chunks, c->nchunks);
@@ -1128,7 +1128,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
                 {pp.a0[0], pp.a0[1], pp.a0[2]}};
   grid_of(g, R.grid, R.block);
   // per-block parameter-gradient slots: row blocks and chunk blocks
-  R.nblk = std::max((size_t)R.grid.x * R.grid.y, (size_t)(c->nchunks + AT / 64 - 1) / (AT / 64));
+  R.nblk = std::max((size_t)R.grid.x * R.grid.y, (size_t)(c->nchunks + AT / CHUNK - 1) / (AT / CHUNK));
   for (int b = 0; b < 256; ++b) {
     if (c->bid_end[b] <= c->bid_begin[b]) continue;
     if (c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION) R.neu = true;

@@ -280,19 +280,19 @@ tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *c, const double *phi, const uint8_
     (void)hipFree(cnt);
     c->nactive = (int64_t)na;
     {
-      // 64-node chunks holding active nodes, in node order
+      // CHUNK-node chunks holding active nodes, in node order
       std::vector<uint8_t> act(N);
       CHK(hipMemcpy(act.data(), c->act, N, hipMemcpyDeviceToHost), "mask read");
       std::vector<int32_t> ch;
-      for (int64_t k = 0; k * 64 < N; ++k) {
+      for (int64_t k = 0; k * CHUNK < N; ++k) {
         bool any = false;
-        for (int64_t i = k * 64; i < std::min<int64_t>(N, k * 64 + 64) && !any; ++i) any = act[i] != 0;
+        for (int64_t i = k * CHUNK; i < std::min<int64_t>(N, k * CHUNK + CHUNK) && !any; ++i) any = act[i] != 0;
         if (any) ch.push_back((int32_t)k);
       }
       if (!ch.empty()) {
         CHK(hipMalloc(&c->chunks, ch.size() * sizeof(int32_t)), "chunk alloc");
         CHK(hipMemcpy(c->chunks, ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice), "chunk upload");
-        std::vector<int32_t> pos((size_t)((N + 63) / 64), -1);
+        std::vector<int32_t> pos((size_t)((N + CHUNK - 1) / CHUNK), -1);
         for (size_t k = 0; k < ch.size(); ++k) pos[ch[k]] = (int32_t)k;
         CHK(hipMalloc(&c->cpos, pos.size() * sizeof(int32_t)), "chunk position alloc");
         CHK(hipMemcpy(c->cpos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice), "chunk position upload");

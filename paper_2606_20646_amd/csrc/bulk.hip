@@ -355,9 +355,9 @@ __global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T 
                                                    x + (int64_t)g.nx * blockIdx.y, g.S);
 }
 
-// Embedded bodies: the same update over the list of 64-node chunks (of the
-// node order) that hold active nodes, one wavefront per chunk; inactive
-// nodes of a chunk return at once (MASK).
+// Embedded bodies: the same update over the list of CHUNK-node chunks (of
+// the node order) that hold active nodes, 64 / CHUNK chunks per wavefront;
+// inactive nodes of a chunk return at once (MASK).
 template <int D, typename T, bool TRACK, bool REPAIR, bool EXT>
 __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks(const T *__restrict__ fin, T *__restrict__ fout,
                                                                     Geo g, Par p, const uint8_t *__restrict__ act,
@@ -366,9 +366,9 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks(const T *__r
                                                                     const T *__restrict__ Frp, int *__restrict__ flag,
                                                                     const T *__restrict__ bf, T bs,
                                                                     const int32_t *__restrict__ chunks, int nchunks) {
-  const int ch = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ch = blockIdx.x * (256 / CHUNK) + (int)(threadIdx.x / CHUNK);
   if (ch >= nchunks) return;
-  const int64_t i = (int64_t)chunks[ch] * 64 + (threadIdx.x & 63);
+  const int64_t i = (int64_t)chunks[ch] * CHUNK + (threadIdx.x % CHUNK);
   if (i >= g.N) return;
   const int x = (int)(i % g.nx), row = (int)(i / g.nx);
   bulk_node<D, T, true, TRACK, REPAIR, false, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, nullptr,
@@ -381,15 +381,15 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks_tape(
     const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p, const uint8_t *__restrict__ act,
     double *__restrict__ ustar, double *__restrict__ ubuf, const T *__restrict__ Frp, int *__restrict__ flag,
     T *__restrict__ tape, const int32_t *__restrict__ chunks, int nchunks) {
-  const int ch = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ch = blockIdx.x * (256 / CHUNK) + (int)(threadIdx.x / CHUNK);
   if (ch >= nchunks) return;
-  const int64_t i = (int64_t)chunks[ch] * 64 + (threadIdx.x & 63);
+  const int64_t i = (int64_t)chunks[ch] * CHUNK + (threadIdx.x % CHUNK);
   if (i >= g.N) return;
   const int x = (int)(i % g.nx), row = (int)(i / g.nx);
-  // tape slot of chunk ch, lane i % 64
+  // tape slot of chunk ch, position i % CHUNK
   bulk_node<D, T, true, TRACK, REPAIR, true, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, tape,
-                                                  nullptr, T(0), (int64_t)ch * 64 + (threadIdx.x & 63),
-                                                  (int64_t)nchunks * 64);
+                                                  nullptr, T(0), (int64_t)ch * CHUNK + (threadIdx.x % CHUNK),
+                                                  (int64_t)nchunks * CHUNK);
 }
 
 // Batched bulk update: one block per tile (instance, row, first x) of the
@@ -641,7 +641,7 @@ template <int D, typename T, bool EXT> static void bulk_plain_t(tlvlbm_ctx *c, b
   const T bs = body_scale<T>(c);
   if (c->act && c->chunks) {
     // embedded body: only the chunks holding active nodes
-    const unsigned nb = (unsigned)((c->nchunks + 3) / 4);
+    const unsigned nb = (unsigned)((c->nchunks + 256 / CHUNK - 1) / (256 / CHUNK));
     if (repair)
       hipLaunchKernelGGL((k_bulk_chunks<D, T, true, true, EXT>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs, c->chunks, c->nchunks);
@@ -685,7 +685,7 @@ template <int D, typename T, bool EXT> static void bulk_tape_t(tlvlbm_ctx *c, bo
   T *tp = (T *)tape;
   const T *nb = nullptr;
   if (c->act && c->chunks) {
-    const unsigned nblk = (unsigned)((c->nchunks + 3) / 4);
+    const unsigned nblk = (unsigned)((c->nchunks + 256 / CHUNK - 1) / (256 / CHUNK));
     if (repair)
       hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, true, true, EXT>), nblk, 256, 0, c->st, fin, fout, c->geo,
                          c->par, c->act, us, ub, Fr, c->d_flag, tp, c->chunks, c->nchunks);

@@ -1219,13 +1219,13 @@ __global__ __launch_bounds__(256) void k_tape_gather(const T *__restrict__ src, 
                                                      T *__restrict__ dst) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= nslot) return;
-  const int64_t node = (int64_t)chunks[s >> 6] * 64 + (s & 63);
+  const int64_t node = (int64_t)chunks[s / CHUNK] * CHUNK + (s % CHUNK);
   if (node >= N) return;
   for (int k = 0; k < planes; ++k) dst[(size_t)k * nslot + s] = src[(size_t)k * S + node];
 }
 
 void launch_tape_gather(tlvlbm_ctx *c, const void *src, void *dst, int planes) {
-  const int64_t ns = (int64_t)c->nchunks * 64;
+  const int64_t ns = (int64_t)c->nchunks * CHUNK;
   if (c->prec)
     hipLaunchKernelGGL(k_tape_gather<double>, nblk(ns, 256), 256, 0, c->st, (const double *)src, c->geo.S, c->geo.N,
                        c->chunks, ns, planes, (double *)dst);

@@ -16,6 +16,9 @@ enum : int { FLAG_J = 1, FLAG_NONFINITE = 2, FLAG_NEWTON = 4, FLAG_ARG = 8, FLAG
 // maximum LSQ stencil (active nodes within 2.5 dx of X_b; at most 21 lattice
 // points fit in 2D and 81 in 3D)
 constexpr int KMAX2 = 24;
+// nodes per chunk of the embedded-body chunk list (a divisor of 64: one
+// wavefront covers 64 / CHUNK chunks)
+constexpr int CHUNK = 32;
 constexpr int KMAX3 = 88;
 constexpr double LSQ_RADIUS = 2.5;
 
@@ -291,12 +294,12 @@ struct tlvlbm_ctx {
   hipStream_t st = nullptr;
   size_t esz = 4;
   void *fA = nullptr, *fB = nullptr;  // population planes (Q*M planes of stride S)
-  // embedded bodies: the 64-node chunks of the node order that hold active
+  // embedded bodies: the CHUNK-node chunks of the node order that hold active
   // nodes (one wavefront each); the bulk update skips the rest
   int32_t *chunks = nullptr;
   int nchunks = 0;
-  // position of every 64-node block in the chunk list (-1: not listed); the
-  // reverse-mode tape stores chunk slots cpos[i / 64] * 64 + i % 64
+  // position of every CHUNK-node block in the chunk list (-1: not listed);
+  // the reverse-mode tape stores chunk slots cpos[i / CHUNK] * CHUNK + i % CHUNK
   int32_t *cpos = nullptr;
   // body acceleration b(X, t) = s(t) g(X) (Eq. 5): g in D planes of the
   // population precision (null: none), s a ramp
@@ -366,7 +369,7 @@ struct TapeStep {
 // reverse-mode tape planes: one slot per node of the chunk list (embedded
 // bodies) or per node
 inline int64_t tape_stride(const tlvlbm_ctx *c) {
-  return (c->act && c->chunks) ? (int64_t)c->nchunks * 64 : (int64_t)c->geo.S;
+  return (c->act && c->chunks) ? (int64_t)c->nchunks * CHUNK : (int64_t)c->geo.S;
 }
 // dst[k * tape_stride + slot] = src[k * S + node] for k < planes (embed.hip)
 void launch_tape_gather(tlvlbm_ctx *c, const void *src, void *dst, int planes);

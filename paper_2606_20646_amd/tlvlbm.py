@@ -230,15 +230,23 @@ class Solver:
     def adjoint(self, n, dLdU=None, dLdu=None, segment=0, grad_v0=True, grad_u0=True):
         """Advance n steps from the state of set_state and return
         (dL/d(mu, lambda), dL/dv0 [D][N], dL/du0 [D][N]) for
-        L = sum dLdU . U + dLdu . u over the moments after the last step."""
+        L = sum dLdU . U + dLdu . u over the moments after the last step.
+        dLdU, dLdu: numpy arrays or contiguous float64 torch tensors (host or
+        device).  grad_v0 / grad_u0: True (new numpy arrays), False (not
+        computed) or a contiguous float64 tensor [D][N] to write into."""
         U0, dU0 = self._init
         gm = (C.c_double * 2)()
-        gv = np.zeros((self.D, self.N)) if grad_v0 else None
-        g0 = np.zeros((self.D, self.N)) if grad_u0 else None
+
+        def out(spec):
+            if spec is True:
+                return np.zeros((self.D, self.N))
+            return spec if spec is not False and spec is not None else None
+
+        gv, g0 = out(grad_v0), out(grad_u0)
         args = [a if (a is None or not isinstance(a, np.ndarray)) else np.ascontiguousarray(a, np.float64)
                 for a in (dLdU, dLdu)]
-        self._chk(lib.tlvlbm_adjoint_step(self.h, int(n), _ptr(U0)[0], _ptr(dU0)[0], _ptr(args[0])[0], _ptr(args[1])[0],
-                                     gm, _ptr(gv)[0], _ptr(g0)[0], int(segment)), "adjoint")
+        self._chk(lib.tlvlbm_adjoint_step(self.h, int(n), _ptr(U0)[0], _ptr(dU0)[0], _ptr(args[0])[0],
+                                          _ptr(args[1])[0], gm, _ptr(gv)[0], _ptr(g0)[0], int(segment)), "adjoint")
         return np.array([gm[0], gm[1]]), gv, g0
 
     def step(self, n=1):

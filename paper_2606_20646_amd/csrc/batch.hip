@@ -382,6 +382,7 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       I.anc_s = c->cg.anc_s;
       I.z = c->cg.z;
       I.anc_n = c->cg.anc_n;
+      I.nbm = c->cg.nbm;
       I.anc_i = c->cg.anc_i;
       I.partial = c->cg.partial;
       I.scal = c->cg.scal;

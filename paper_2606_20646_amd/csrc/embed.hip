@@ -1644,8 +1644,12 @@ __global__ __launch_bounds__(CG_T) void k_jacobi_batch(const Inst *__restrict__ 
   const Inst &I = insts[t.x];
   const double *xin = (const double *)(dir ? I.r : I.x);
   double *xout = (double *)(dir ? I.x : I.r);
-  jacobi_node<D>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.b, xin, xout, om,
-                 (int64_t)t.y * CG_T + threadIdx.x);
+  if (I.nbm)
+    jacobi_node_m<D>(I.g, I.nbm, anchored ? I.anc_n : nullptr, (const double *)I.b, xin, xout, om,
+                     (int64_t)t.y * CG_T + threadIdx.x);
+  else
+    jacobi_node<D>(I.g, I.act, anchored ? I.anc_n : nullptr, (const double *)I.b, xin, xout, om,
+                   (int64_t)t.y * CG_T + threadIdx.x);
 }
 
 template <int D>

@@ -152,6 +152,7 @@ struct Inst {
   void *x, *r, *p0, *p1, *Ap, *b, *V, *Fm, *Fr, *anc_s;
   void *z;  // preconditioned residual (batched multigrid)
   uint8_t *anc_n;
+  uint8_t *nbm;  // neighbour masks of the projection graph (null: from act)
   int *anc_i;
   double *partial, *scal;
   int nblk;  // node tiles of 256 of this instance (CG reductions)

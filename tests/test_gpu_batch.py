@@ -109,7 +109,12 @@ def test_batched_instance_matches_oracle(env, orc):
         Uo, uo, _ = o.moments()
         act = c["phi"] <= 0
         assert np.linalg.norm(Ub[:, act] - Uo[:, act]) <= 1e-11 * np.linalg.norm(Uo[:, act])
-        assert np.linalg.norm(ub[:, act] - uo[:, act]) <= 1e-10 * np.linalg.norm(uo[:, act])
+        # u comes out of the projection's Jacobi relaxation, whose terms are
+        # of size dx |F - I|; where the ramped load has not arrived yet u is
+        # round-off of those terms, so the bound has an absolute floor at
+        # FP64 round-off of dx per node besides the relative part
+        floor = 1e-13 * c["dx"] * np.sqrt(act.sum())
+        assert np.linalg.norm(ub[:, act] - uo[:, act]) <= 1e-10 * np.linalg.norm(uo[:, act]) + floor
 
 
 def test_tile_configurations_agree(env):

@@ -262,12 +262,30 @@ def config_c5(N=192, seed=SEED, mu=1.0, lam=2.0):
 def config_c4_instance(k, seed=SEED, N=None):
     """One instance of the batched 2D workload: unit square with 1-5 random
     circular holes, clamped left edge, traction (0.02 mu, 0) on the right
-    edge (sine-squared ramp over 500 steps), other surfaces traction free."""
+    edge (sine-squared ramp over 500 steps), other surfaces traction free.
+    A hole that would leave a ligament narrower than 4 cells to another hole,
+    or cut into one at a grazing depth (< 0.03), is drawn again: the
+    embedding needs a few active nodes across every ligament (sub-cell
+    slivers fail the local traction solve)."""
     rng = np.random.default_rng(seed + k)
     Nk = int(rng.integers(64, 513)) if N is None else N
     nh = int(rng.integers(1, 6))
     centres = rng.uniform(0.25, 0.75, size=(nh, 2))
     radii = rng.uniform(0.05, 0.15, size=nh)
+
+    def bad(j):
+        for i in range(j):
+            gap = float(np.linalg.norm(centres[i] - centres[j])) - radii[i] - radii[j]
+            if -0.03 < gap < 4.0 / Nk:
+                return True
+        return False
+
+    for j in range(1, nh):
+        for _ in range(1000):
+            if not bad(j):
+                break
+            centres[j] = rng.uniform(0.25, 0.75, size=2)
+            radii[j] = rng.uniform(0.05, 0.15)
     mu = float(rng.uniform(0.5, 2.0))
     lam = float(mu * math.exp(rng.uniform(0.0, math.log(50.0))))
     g = framed_box(Nk, 2)

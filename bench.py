@@ -136,7 +136,7 @@ def main():
          "affine": bench_analytic, "tube": bench_analytic}[args.workload](args)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
         sys.exit(2)
     import numpy as np

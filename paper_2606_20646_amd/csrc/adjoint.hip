@@ -639,18 +639,32 @@ __global__ __launch_bounds__(AT) void k_jacT_sweep(Geo g, const uint8_t *__restr
   if (i >= g.N || !(nbm[i] & 64u)) return;
   int64_t nb[2 * D];
   const int deg = jac_degree<D>(g, nbm, anc_n, i, nb);
+  // unconditional loads (a missing neighbour reads the node itself and adds
+  // an exact zero): all of them in flight together
+  int64_t at[2 * D];
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q) at[q] = nb[q] >= 0 ? nb[q] : i;
+  double wi[D], yi[D], wn[D][2 * D];
+#pragma unroll
   for (int c = 0; c < D; ++c) {
     const size_t o = (size_t)c * g.S;
-    const double wi = win[o + i];
-    y[o + i] += om * wi;
+    wi[c] = win[o + i];
+    yi[c] = y[o + i];
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q) wn[c][q] = win[o + at[q]];
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const size_t o = (size_t)c * g.S;
+    y[o + i] = yi[c] + om * wi[c];
     if (deg == 0) {
       wout[o + i] = 0.0;
       continue;
     }
     double s = 0.0;
-    for (int q = 0; q < 2 * D; ++q)
-      if (nb[q] >= 0) s += win[o + nb[q]];
-    wout[o + i] = (1.0 - om) * wi + om * s / double(deg);
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q) s += nb[q] >= 0 ? wn[c][q] : 0.0;
+    wout[o + i] = (1.0 - om) * wi[c] + om * s / double(deg);
   }
 }
 

@@ -836,24 +836,39 @@ __device__ __forceinline__ void jacobi_node_m(const Geo &g, const uint8_t *__res
   const unsigned m = nbm[i];
   int deg = 0;
   int64_t nb[2 * D];
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q) nb[q] = -1;
   if (m & 64u) {
     deg = (anc_n ? anc_n[i] : 0) + __builtin_popcount(m & ((1u << (2 * D)) - 1u));
 #pragma unroll
-    for (int q = 0; q < 2 * D; ++q) nb[q] = ((m >> q) & 1u) ? nb_index(g, i, q) : -1;
+    for (int q = 0; q < 2 * D; ++q)
+      if ((m >> q) & 1u) nb[q] = nb_index(g, i, q);
+  }
+  // every load unconditional (a missing neighbour reads the node itself and
+  // contributes an exact zero), so that all of them are in flight together
+  int64_t at[2 * D];
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q) at[q] = nb[q] >= 0 ? nb[q] : i;
+  double xi[D], bi[D], xn[D][2 * D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const size_t o = (size_t)c * g.S;
+    xi[c] = xin[o + i];
+    bi[c] = b[o + i];
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q) xn[c][q] = xin[o + at[q]];
   }
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     const size_t o = (size_t)c * g.S;
-    const double xi = xin[o + i];
     if (deg == 0) {
-      xout[o + i] = xi;
+      xout[o + i] = xi[c];
       continue;
     }
-    double kx = double(deg) * xi;
+    double kx = double(deg) * xi[c];
 #pragma unroll
-    for (int q = 0; q < 2 * D; ++q)
-      if (nb[q] >= 0) kx -= xin[o + nb[q]];
-    xout[o + i] = xi + om * (b[o + i] - kx) / double(deg);
+    for (int q = 0; q < 2 * D; ++q) kx -= nb[q] >= 0 ? xn[c][q] : 0.0;
+    xout[o + i] = xi[c] + om * (bi[c] - kx) / double(deg);
   }
 }
 

@@ -586,6 +586,47 @@ __device__ __forceinline__ void cg_rhs_node(const Geo &g, const uint8_t *__restr
   }
 }
 
+// the same right-hand side on an active node from its neighbour mask (bit q:
+// X + e_q active, bit 6: X active), every load issued before any use; a
+// missing neighbour reads the node itself and contributes an exact zero
+template <int D, typename T>
+__device__ __forceinline__ void cg_rhs_node_m(const Geo &g, const uint8_t *__restrict__ nbm,
+                                              const T *__restrict__ Fm, const double *__restrict__ anc_s,
+                                              double *__restrict__ b, int64_t i) {
+  if (i >= g.N) return;
+  const unsigned m = nbm[i];
+  if (!(m & 64u)) return;
+  int64_t lp[D], lm[D];
+#pragma unroll
+  for (int A = 0; A < D; ++A) {
+    lp[A] = ((m >> (2 * A)) & 1u) ? nb_index(g, i, 2 * A) : i;
+    lm[A] = ((m >> (2 * A + 1)) & 1u) ? nb_index(g, i, 2 * A + 1) : i;
+  }
+  double Fi[D * D], Fp[D * D], Fn[D * D], as[D];
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) {
+    const int A = k % D;
+    Fi[k] = double(Fm[(size_t)k * g.S + i]);
+    Fp[k] = double(Fm[(size_t)k * g.S + lp[A]]);
+    Fn[k] = double(Fm[(size_t)k * g.S + lm[A]]);
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) as[c] = anc_s ? anc_s[(size_t)c * g.S + i] : 0.0;
+  const double hdx = double(0.5 * g.dx);
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    double acc = as[c];
+#pragma unroll
+    for (int A = 0; A < D; ++A) {
+      const int k = c * D + A;
+      const double dl = (c == A) ? double(2) : double(0);
+      acc += ((m >> (2 * A + 1)) & 1u) ? hdx * (Fi[k] + Fn[k] - dl) : 0.0;
+      acc -= ((m >> (2 * A)) & 1u) ? hdx * (Fi[k] + Fp[k] - dl) : 0.0;
+    }
+    b[(size_t)c * g.S + i] = acc;
+  }
+}
+
 // block partials: up to PSTRIDE doubles per block
 constexpr int PSTRIDE = 16;
 
@@ -944,6 +985,17 @@ template <int D, typename T>
 __global__ __launch_bounds__(256) void k_cg_rhs(Geo g, const uint8_t *__restrict__ act, const T *__restrict__ Fm,
                                                  const double *__restrict__ anc_s, double *__restrict__ b) {
   cg_rhs_node<D, T>(g, act, Fm, anc_s, b, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
+// over the active tiles with the neighbour masks (nodes outside the tiles
+// keep b, which nothing reads there)
+template <int D, typename T>
+__global__ __launch_bounds__(CG_T) void k_cg_rhs_tiles(Geo g, const uint8_t *__restrict__ nbm,
+                                                        const T *__restrict__ Fm, const double *__restrict__ anc_s,
+                                                        double *__restrict__ b, const int32_t *__restrict__ tiles,
+                                                        int ntile) {
+  if ((int)blockIdx.x >= ntile) return;
+  cg_rhs_node_m<D, T>(g, nbm, Fm, anc_s, b, (int64_t)tiles[blockIdx.x] * CG_T + threadIdx.x);
 }
 
 template <int D, typename T>
@@ -1417,7 +1469,11 @@ template <int D, typename T> static int cg_solve(tlvlbm_ctx *c, const T *F, doub
     anc_n = w.anc_n;
     anc_s = (const double *)w.anc_s;
   }
-  hipLaunchKernelGGL((k_cg_rhs<D, T>), nblk(g.N, 256), 256, 0, st, g, c->act, F, anc_s, (double *)w.b);
+  if (w.nbm && w.tiles)
+    hipLaunchKernelGGL((k_cg_rhs_tiles<D, T>), (unsigned)w.ntiles, CG_T, 0, st, g, w.nbm, F, anc_s, (double *)w.b,
+                       w.tiles, w.ntiles);
+  else
+    hipLaunchKernelGGL((k_cg_rhs<D, T>), nblk(g.N, 256), 256, 0, st, g, c->act, F, anc_s, (double *)w.b);
   if (c->proj_sweeps > 0) return jacobi_run<D>(c, anc_n);
   return cg_run<D, T>(c, anc_n);
 }

@@ -63,21 +63,23 @@ __device__ __forceinline__ void lsq_gather(const Links &L, int64_t l, int np, Sl
                                            double (&gv)[D - 1][D]) {
   constexpr int B = 8;
   for (int k0 = 0; k0 < np; k0 += B) {
+    // past the last point the loads repeat point np - 1 (always valid) and
+    // are not accumulated: no load sits behind a branch
     int64_t jj[B];
 #pragma unroll
-    for (int t = 0; t < B; ++t) jj[t] = (k0 + t < np) ? slot(k0 + t) : -1;
+    for (int t = 0; t < B; ++t) jj[t] = slot(k0 + t < np ? k0 + t : np - 1);
     double uu[B][D], ww[B][D - 1];
 #pragma unroll
     for (int t = 0; t < B; ++t) {
-      const bool ok = jj[t] >= 0;
+      const int k = k0 + t < np ? k0 + t : np - 1;
 #pragma unroll
-      for (int i = 0; i < D; ++i) uu[t][i] = ok ? uval(jj[t], i) : 0.0;
+      for (int i = 0; i < D; ++i) uu[t][i] = uval(jj[t], i);
 #pragma unroll
-      for (int al = 0; al < D - 1; ++al) ww[t][al] = ok ? L.sw[lsq_w(L, l, al, k0 + t)] : 0.0;
+      for (int al = 0; al < D - 1; ++al) ww[t][al] = L.sw[lsq_w(L, l, al, k)];
     }
 #pragma unroll
     for (int t = 0; t < B; ++t)
-      if (jj[t] >= 0)
+      if (k0 + t < np)
 #pragma unroll
         for (int al = 0; al < D - 1; ++al)
 #pragma unroll

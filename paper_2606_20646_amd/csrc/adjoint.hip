@@ -551,12 +551,31 @@ __global__ __launch_bounds__(AT) void k_adj_ugather(int64_t ns, const int64_t *_
   if (t >= ns) return;
   double acc[D];
   for (int i = 0; i < D; ++i) acc[i] = 0.0;
-  for (int64_t e = so[t]; e < so[t + 1]; ++e) {
-    const int64_t l = el[e];
-    for (int al = 0; al < D - 1; ++al) {
-      const double wk = ew[(size_t)e * (D - 1) + al];
-      for (int i = 0; i < D; ++i) acc[i] += wk * gbar[l * 6 + al * 3 + i];
+  // entries in order, 4 at a time with every load unconditional (entries
+  // past the last repeat it and are not accumulated)
+  const int64_t e0 = so[t], e1 = so[t + 1];
+  for (int64_t e = e0; e < e1; e += 4) {
+    int64_t ll[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ll[k] = el[e + k < e1 ? e + k : e1 - 1];
+    double wk[4][D - 1], gb[4][D - 1][D];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t ek = e + k < e1 ? e + k : e1 - 1;
+#pragma unroll
+      for (int al = 0; al < D - 1; ++al) {
+        wk[k][al] = ew[(size_t)ek * (D - 1) + al];
+#pragma unroll
+        for (int i = 0; i < D; ++i) gb[k][al][i] = gbar[ll[k] * 6 + al * 3 + i];
+      }
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (e + k < e1)
+#pragma unroll
+        for (int al = 0; al < D - 1; ++al)
+#pragma unroll
+          for (int i = 0; i < D; ++i) acc[i] += wk[k][al] * gb[k][al][i];
   }
   for (int i = 0; i < D; ++i) ubc[(size_t)i * g.S + sn[t]] = acc[i];
 }

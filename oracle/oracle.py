@@ -60,6 +60,7 @@ def lib():
         L.orc_set_projection.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_set_body_force.argtypes = [C.c_void_p, dp, C.c_int, C.c_double]
         L.orc_set_bc_twist.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        L.orc_bc_data.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
         L.orc_set_fibres.argtypes = [C.c_void_p, C.c_double, dp]
         L.orc_set_levelset.argtypes = [C.c_void_p, dp, C.POINTER(C.c_uint8)]
         L.orc_set_bc.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp, dp,
@@ -248,6 +249,18 @@ class Sim:
             st = lib().orc_set_bc_twist(self.h, bid, float(twist))
             if st:
                 raise OracleError(st, "set_bc_twist")
+
+    def bc_data(self, bid, X, N, t):
+        """(imposed velocity or traction, prescribed displacement) of
+        boundary identifier bid at point X with normal N, time t."""
+        Xa = _f64(list(X) + [0.0] * (3 - len(X)))
+        Na = _f64(list(N) + [0.0] * (3 - len(N)))
+        val = np.zeros(3)
+        disp = np.zeros(3)
+        st = lib().orc_bc_data(self.h, int(bid), _d(Xa), _d(Na), float(t), _d(val), _d(disp))
+        if st:
+            raise OracleError(st, "bc_data")
+        return val[: self.D].copy(), disp[: self.D].copy()
 
     def set_fibres(self, k1, a0):
         """Fibre-reinforced law: W += k1/2 (|F a0|^2 - 1)^2 (k1 = 0: off)."""

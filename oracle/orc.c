@@ -930,6 +930,17 @@ static void bc_displacement(const orc_bc *b, int D, const double *X, const doubl
   }
 }
 
+/* boundary data of identifier bid at point X (normal Nb) and time t: the
+ * imposed velocity (Dirichlet) or traction (Neumann) and, for Dirichlet, the
+ * prescribed displacement; exposed so that tests can check the data itself */
+int orc_bc_data(orc_sim *s, int bid, const double *X, const double *Nb, double t, double *val, double *disp) {
+  if (!s || bid < 0 || bid > 255 || !X || !Nb || !val) return ORC_ERR_ARG;
+  const orc_bc *b = &s->bc[bid];
+  bc_value(b, s->D, X, Nb, t, val);
+  if (disp) bc_displacement(b, s->D, X, Nb, t, disp);
+  return ORC_OK;
+}
+
 /* material of the simulation with the given (mu, lambda) */
 static orc_mat sim_mat(const orc_sim *s, double mu, double lam) {
   orc_mat m = {mu, lam, s->k1, {s->a0[0], s->a0[1], s->a0[2]}};

@@ -100,6 +100,9 @@ int  orc_set_bc(orc_sim *s, int bid, int type, int ramp, double T_r,
 /* displacement-given Dirichlet only: add the ramped rigid rotation
  * (R(s(t) twist) - I)(X - X0) in the (e1, e2) plane (Sec. 5.3, Eq. 87) */
 int  orc_set_bc_twist(orc_sim *s, int bid, double twist);
+/* boundary data of identifier bid at X (normal Nb), time t: val = imposed
+ * velocity or traction, disp (may be NULL) = prescribed displacement */
+int  orc_bc_data(orc_sim *s, int bid, const double *X, const double *Nb, double t, double *val, double *disp);
 /* U0[M][N]; u0[D][N] or NULL; dU0[D][M][N] (d/dX_A of U0) or NULL */
 int  orc_set_state(orc_sim *s, const double *U0, const double *u0,
                    const double *dU0);

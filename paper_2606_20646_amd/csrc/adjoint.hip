@@ -1169,6 +1169,12 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   }
   const bool track = c->track_u;
   const size_t plane = (size_t)g.S * sizeof(T), dplane = (size_t)g.S * sizeof(double);
+  // projection tables first: rebuilding them frees the transposed stencils,
+  // which the tape below refers to, so no step of this call may rebuild them
+  if (c->act && (R.neu || R.dir) && (!c->gauge || c->aux_stale)) {
+    const int s = proj_aux_build(c);
+    if (s) return (tlvlbm_status)s;
+  }
   // transposed Neumann stencils: the gather of u_bar, and the nodes whose
   // displacement the tape keeps
   if (c->act && R.neu && !c->stT) {

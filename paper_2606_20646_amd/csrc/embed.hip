@@ -1077,15 +1077,18 @@ __global__ __launch_bounds__(FIN_T) void k_cg_fin_batch(const Inst *__restrict__
 
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_gradF(Geo g, const uint8_t *__restrict__ act, const double *__restrict__ u,
-                                                const T *__restrict__ Fm, T *__restrict__ Fr, double theta) {
-  gradF_node<D, T>(g, act, u, Fm, Fr, theta, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+                                                const T *__restrict__ Fm, T *__restrict__ Fr, double theta,
+                                                const int32_t *__restrict__ tiles) {
+  gradF_node<D, T>(g, act, u, Fm, Fr, theta,
+                   (tiles ? (int64_t)tiles[blockIdx.x] : (int64_t)blockIdx.x) * 256 + threadIdx.x);
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_ureset(Geo g, const uint8_t *__restrict__ act, const double *__restrict__ x,
                                                  const T *__restrict__ V, double *__restrict__ u, double *__restrict__ us,
-                                                 double hdt) {
-  ureset_node<D, T>(g, act, x, V, u, us, hdt, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+                                                 double hdt, const int32_t *__restrict__ tiles) {
+  ureset_node<D, T>(g, act, x, V, u, us, hdt,
+                    (tiles ? (int64_t)tiles[blockIdx.x] : (int64_t)blockIdx.x) * 256 + threadIdx.x);
 }
 
 // Workgroups go to the 8 XCDs round robin (block b to XCD b % 8): block b
@@ -1112,12 +1115,20 @@ __global__ __launch_bounds__(CG_T) void k_copy_planes(Geo g, const double *__res
     for (int c = 0; c < D; ++c) dst[(size_t)c * g.S + i] = src[(size_t)c * g.S + i];
 }
 
-// copy of the displacement planes (FP64) into or out of the solver iterate
+// copy of the displacement planes (FP64) into or out of the solver iterate,
+// over the 256-node tiles that hold active nodes (tiles == null: all nodes;
+// nothing reads either buffer outside the tiles)
 template <int D>
-__global__ __launch_bounds__(256) void k_copy_u(Geo g, const double *__restrict__ src, double *__restrict__ dst) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < g.N)
-    for (int c = 0; c < D; ++c) dst[(size_t)c * g.S + i] = src[(size_t)c * g.S + i];
+__global__ __launch_bounds__(256) void k_copy_u(Geo g, const double *__restrict__ src, double *__restrict__ dst,
+                                                 const int32_t *__restrict__ tiles) {
+  const int64_t i = (tiles ? (int64_t)tiles[blockIdx.x] : (int64_t)blockIdx.x) * 256 + threadIdx.x;
+  if (i < g.N) {
+    double v[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) v[c] = src[(size_t)c * g.S + i];
+#pragma unroll
+    for (int c = 0; c < D; ++c) dst[(size_t)c * g.S + i] = v[c];
+  }
 }
 
 // default CG tolerance: 1e-14 for FP64 populations, 1e-8 for FP32 ones (the
@@ -1557,20 +1568,29 @@ static int projection_t(tlvlbm_ctx *c, bool first, double tn, double *store, int
   if (st) return st;
   CG &w = c->cg;
   const Geo &g = c->geo;
+  // projection tables (tiles, masks, components) current before any launch
+  // that uses them
+  if (!c->gauge || c->aux_stale) {
+    st = proj_aux_build(c);
+    if (st) return st;
+  }
+  // the node-wise kernels around the solve run over the active tiles
+  const int32_t *tl = w.tiles;
+  const unsigned nt = tl ? (unsigned)w.ntiles : nblk(g.N, 256);
   if (first) {
     launch_pull_moments(c, nullptr, nullptr, nullptr, true);  // v, F, u^n
-    hipLaunchKernelGGL((k_copy_u<D>), nblk(g.N, 256), 256, 0, c->st, g, (const double *)c->ubuf, (double *)w.x);
+    hipLaunchKernelGGL((k_copy_u<D>), nt, 256, 0, c->st, g, (const double *)c->ubuf, (double *)w.x, tl);
     st = solve_or_replay<D, T>(c, (const T *)w.Fm, tn, store, mode);
     if (st) return st;
-    hipLaunchKernelGGL((k_copy_u<D>), nblk(g.N, 256), 256, 0, c->st, g, (const double *)w.x, (double *)c->ubuf);
-    hipLaunchKernelGGL((k_gradF<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const double *)w.x,
-                       (const T *)w.Fm, (T *)w.Fr, c->theta);
+    hipLaunchKernelGGL((k_copy_u<D>), nt, 256, 0, c->st, g, (const double *)w.x, (double *)c->ubuf, tl);
+    hipLaunchKernelGGL((k_gradF<D, T>), nt, 256, 0, c->st, g, c->act, (const double *)w.x, (const T *)w.Fm,
+                       (T *)w.Fr, c->theta, tl);
   } else {
-    hipLaunchKernelGGL((k_copy_u<D>), nblk(g.N, 256), 256, 0, c->st, g, (const double *)c->ubuf, (double *)w.x);
+    hipLaunchKernelGGL((k_copy_u<D>), nt, 256, 0, c->st, g, (const double *)c->ubuf, (double *)w.x, tl);
     st = solve_or_replay<D, T>(c, (const T *)w.Fr, tn, store, mode);
     if (st) return st;
-    hipLaunchKernelGGL((k_ureset<D, T>), nblk(g.N, 256), 256, 0, c->st, g, c->act, (const double *)w.x, (const T *)w.V,
-                       (double *)c->ubuf, (double *)c->ustar, 0.5 * c->par.dt);
+    hipLaunchKernelGGL((k_ureset<D, T>), nt, 256, 0, c->st, g, c->act, (const double *)w.x, (const T *)w.V,
+                       (double *)c->ubuf, (double *)c->ustar, 0.5 * c->par.dt, tl);
   }
   HIP_OK(hipGetLastError());
   return TLVLBM_OK;

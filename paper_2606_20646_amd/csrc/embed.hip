@@ -974,6 +974,20 @@ __global__ __launch_bounds__(128) void k_cut_neumann(T *__restrict__ f, Links L,
   if (l < b1) cut_neumann_link<D, T>(f, L, l, bcs[L.bid[l]], g, p, th, u, flag, nfail);
 }
 
+// both kinds in one launch (links sorted by identifier, so a wavefront
+// mostly holds one kind); the two closures read and write disjoint slots
+template <int D, typename T>
+__global__ __launch_bounds__(128) void k_cut_mixed(T *__restrict__ f, Links L, int64_t b0, int64_t b1,
+                                                    const BC *__restrict__ bcs, Geo g, Par p, double th,
+                                                    const double *__restrict__ u, int *__restrict__ flag,
+                                                    unsigned long long *__restrict__ nfail) {
+  const int64_t l = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= b1) return;
+  const BC &bc = bcs[L.bid[l]];
+  if (bc.type == TLVLBM_BC_DIRICHLET_VELOCITY) cut_dirichlet_link<D, T>(f, L, l, bc, g, p, th);
+  else cut_neumann_link<D, T>(f, L, l, bc, g, p, th, u, flag, nfail);
+}
+
 template <int D, typename T>
 __global__ void k_anchor(Links L, int64_t b0, int64_t b1, BC bc, Geo g, double t, const T *__restrict__ Fm,
                          int *__restrict__ anc_n, double *__restrict__ anc_s) {
@@ -1253,6 +1267,22 @@ template <int D, typename T> static int cutlinks_t(tlvlbm_ctx *c, double tn) {
   const double th = (double(c->step) + 0.5) * c->par.dt;  // t^n + dt/2, same rounding as the batched path
   const int s = sync_bcs(c);
   if (s) return s;
+  // both kinds present: one launch over every link
+  bool any_dir = false, any_neu = false;
+  int64_t lo = -1, hi = -1;
+  for (int b = 0; b < 256; ++b) {
+    if (c->bid_end[b] <= c->bid_begin[b]) continue;
+    if (c->bcs[b].type == TLVLBM_BC_DIRICHLET_VELOCITY) any_dir = true;
+    else any_neu = true;
+    if (lo < 0) lo = c->bid_begin[b];
+    hi = c->bid_end[b];
+  }
+  if (any_dir && any_neu && hi - lo == c->L.n) {
+    hipLaunchKernelGGL((k_cut_mixed<D, T>), nblk(hi - lo, 128), 128, 0, c->st, (T *)c->fA, c->L, lo, hi,
+                       (const BC *)c->d_bcs, c->geo, c->par, th, (const double *)c->ubuf, c->d_flag,
+                       (unsigned long long *)c->d_newton_fail);
+    return TLVLBM_OK;
+  }
   int b = 0;
   while (b < 256) {
     if (c->bid_end[b] <= c->bid_begin[b]) {

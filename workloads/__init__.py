@@ -308,7 +308,8 @@ def config_c4_instance(k, seed=SEED, N=None):
     U0[2] = 1.0
     U0[5] = 1.0
     return dict(g, D=2, X=X, phi=phi, bid=bid, bcs=bcs, mu=mu, lam=lam, rho0=1.0, c=c, dt=dt, omega=1.8,
-                gamma=10.0, proj_every=20, U0=U0, steps=2000, N_cells=Nk)
+                gamma=10.0, proj_every=20, U0=U0, steps=2000, N_cells=Nk, hole_centres=centres,
+                hole_radii=radii)
 
 
 def config_ellipsoid(N=320):

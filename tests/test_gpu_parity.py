@@ -234,3 +234,49 @@ def test_error_paths(T):
     assert e.value.code in (T.ERR_NONPOSITIVE_J, T.ERR_NONFINITE)
     with pytest.raises(T.TlvlbmError):
         g2.step(1)  # sticky
+
+
+def _embedded_pair(T, orc, c, precision, stream=None):
+    """GPU solver and oracle of an embedded configuration with its boundary
+    conditions and initial state (dU0 when the recipe gives one)."""
+    D = c["D"]
+    kw = dict(omega=c["omega"], gamma=c.get("gamma", 0.0), origin=c["origin"], periodic_mask=0,
+              proj_every=c["proj_every"])
+    g = T.Solver(D, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], precision=precision,
+                 stream=None if stream is None else stream.cuda_stream, **kw)
+    o = orc.Sim(D, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], **kw)
+    g.set_levelset(c["phi"], c["bid"])
+    o.set_levelset(c["phi"], c["bid"])
+    kinds = {"dirichlet": orc.DIRICHLET, "neumann": orc.NEUMANN}
+    ramps = {"const": orc.RAMP_CONST, "sin2": orc.RAMP_SIN2, "halfcos": orc.RAMP_HALFCOS}
+    for bid, bc in c["bcs"].items():
+        bg = dict(bc)
+        g.set_boundary(bid, bg.pop("type"), **bg)
+        bo = dict(bc)
+        t = kinds[bo.pop("type")]
+        if "ramp" in bo:
+            bo["ramp"] = ramps[bo["ramp"]]
+        o.set_bc(bid, t, **bo)
+    g.set_state(c["U0"], dU0=c.get("dU0"))
+    o.set_state(c["U0"], dU0=c.get("dU0"))
+    return g, o
+
+
+@pytest.mark.parametrize("cfg,precision,steps,tol,utol", [
+    ("c2", "fp64", 45, 1e-11, 1e-10), ("c2", "fp32", 45, 1e-5, 1e-4), ("c5", "fp64", 25, 1e-11, 1e-10)])
+def test_full_size_dynamics_matches_oracle(T, orc, cfg, precision, steps, tol, utol):
+    """The annulus 512^2 and the sphere 192^3 at their full sizes, on a
+    non-default stream as the benchmarks run them, through two or three
+    projection steps: the whole state against the oracle."""
+    import torch
+    c = W.config_c2(512) if cfg == "c2" else W.config_c5(192)
+    _say(f"full-size dynamics {cfg} {precision} {steps} steps")
+    g, o = _embedded_pair(T, orc, c, precision, torch.cuda.Stream())
+    g.step(steps)
+    o.step(steps)
+    Ug, ug, _ = g.moments()
+    Uo, uo, _ = o.moments()
+    act = c["phi"] <= 0
+    assert _rel(Ug[:, act], Uo[:, act]) < tol
+    assert _rel(ug[:, act], uo[:, act]) < utol
+    assert g.stats()["newton_failures"] == 0

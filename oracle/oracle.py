@@ -78,6 +78,7 @@ def lib():
         L.orc_get_links.argtypes = [C.c_void_p, i64p, C.POINTER(C.c_int32), dp, dp, C.POINTER(C.c_int32)]
         L.orc_stats.argtypes = [C.c_void_p, i64p]
         L.orc_project.argtypes = [C.c_void_p, dp, dp, C.c_double, i64p]
+        L.orc_project_anchored.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_double, i64p]
         L.orc_compatible_F.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_adjoint.argtypes = [C.c_void_p, C.c_int64, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = C.c_int
@@ -355,11 +356,16 @@ class Sim:
         return dict(newton_iters=int(st[0]), newton_fail=int(st[1]), cg_iters=int(st[2]),
                     projections=int(st[3]), step=int(st[4]), status=int(st[5]))
 
-    def project(self, F, u, rtol=1e-15):
+    def project(self, F, u, rtol=1e-15, t=None):
+        """Projection of u onto F (Sec. 3.5); with t given, the Dirichlet
+        cut links of the boundary conditions set add their anchors at time t."""
         F = _f64(F).reshape(self.D * self.D, self.N)
         u = _f64(u).reshape(self.D, self.N).copy()
         its = C.c_int64(0)
-        lib().orc_project(self.h, _d(F), _d(u), rtol, C.byref(its))
+        if t is None:
+            lib().orc_project(self.h, _d(F), _d(u), rtol, C.byref(its))
+        else:
+            lib().orc_project_anchored(self.h, _d(F), _d(u), float(t), rtol, C.byref(its))
         return u, its.value
 
     def compatible_F(self, u, F):

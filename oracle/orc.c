@@ -1602,6 +1602,31 @@ int orc_project(orc_sim *s, const double *F, double *u, double rtol, int64_t *it
   return ORC_OK;
 }
 
+/* the same projection with the anchors of the Dirichlet cut links at time t
+ * (the relation u^c_m + (F_m - I)(X_b - X_m) = u_D(X_b, t) per link), as the
+ * step applies it */
+int orc_project_anchored(orc_sim *s, const double *F, double *u, double t, double rtol, int64_t *iters) {
+  int D = s->D, M = s->M;
+  double *Unm = (double *)calloc((size_t)s->N * M, sizeof(double));
+  double *uu = (double *)malloc(sizeof(double) * (size_t)s->N * D);
+  for (int64_t i = 0; i < s->N; ++i) {
+    for (int k = 0; k < D * D; ++k) Unm[(size_t)i * M + D + k] = F[(size_t)k * s->N + i];
+    for (int a = 0; a < D; ++a) uu[i * D + a] = u[(size_t)a * s->N + i];
+  }
+  int *anc_n;
+  double *anc_s;
+  proj_anchors(s, Unm, t, &anc_n, &anc_s);
+  int64_t its = proj_solve(s, Unm, uu, rtol, anc_n, anc_s);
+  free(anc_n);
+  free(anc_s);
+  if (iters) *iters = its;
+  for (int64_t i = 0; i < s->N; ++i)
+    for (int a = 0; a < D; ++a) u[(size_t)a * s->N + i] = uu[i * D + a];
+  free(Unm);
+  free(uu);
+  return ORC_OK;
+}
+
 int orc_compatible_F(orc_sim *s, const double *u, const double *F, double *Fc) {
   int D = s->D, M = s->M;
   double *Unm = (double *)calloc((size_t)s->N * M, sizeof(double));

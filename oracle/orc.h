@@ -127,6 +127,8 @@ void orc_stats(orc_sim *s, int64_t *stats);
  * u[D][N], solve the edge least-squares problem of Eq. 57 in place. */
 int  orc_project(orc_sim *s, const double *F, double *u, double rtol,
                  int64_t *iters);
+/* the projection with the Dirichlet cut-link anchors evaluated at time t */
+int  orc_project_anchored(orc_sim *s, const double *F, double *u, double t, double rtol, int64_t *iters);
 /* Reverse mode (project extension; the paper has no adjoint).  From the state
  * set by orc_set_state, advance nsteps steps (as orc_step does) and return
  * the gradient of L = sum_m dLdU(m).U(m) + dLdu(m).u(m) over the moments

@@ -332,7 +332,7 @@ __global__ __launch_bounds__(AT) void k_adj_rep1(const T *__restrict__ Lout, Geo
     const int64_t slot = tslot(cpos, node);
     tape_F<D, T>(tape, ts, slot, Fa);
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) Fr[k] = double(tapeFr[(size_t)k * ts + slot]);
+    for (int k = 0; k < D * D; ++k) Fr[k] = double(tapeFr[(size_t)k * ts + slot]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
 #pragma unroll
     for (int r = 0; r < M; ++r) {
       Ur[r] = 0.0;
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(64) void k_adj_link(T *__restrict__ Lb, Links L, in
     double h[D], Fm[D * D];
     const int64_t slot = tslot(cpos, m);
     if (tapeFr)
-      for (int k = 0; k < D * D; ++k) Fm[k] = double(tapeFr[(size_t)k * ts + slot]);
+      for (int k = 0; k < D * D; ++k) Fm[k] = double(tapeFr[(size_t)k * ts + slot]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
     else
       tape_F<D, T>(tapeU, ts, slot, Fm);
     for (int i = 0; i < D; ++i) {

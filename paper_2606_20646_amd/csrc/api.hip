@@ -7,6 +7,7 @@
 #include <utility>
 #include <vector>
 
+#include "tl_device.hpp"
 #include "tl_internal.hpp"
 
 using namespace tl;
@@ -95,6 +96,11 @@ static void set_material_par(Par &p, const tlvlbm_material *m, int D) {
 
 tlvlbm_status check_flag(tlvlbm_ctx *c) { return read_flag(c); }
 
+// stress of the material on the host (the reference state's equilibrium)
+static double mat_piola_host(int D, const double *F, const Par &p, double *P) {
+  return D == 2 ? mat_piola<2>(F, p, P) : mat_piola<3>(F, p, P);
+}
+
 bool is_projection_step(const tlvlbm_ctx *c, int64_t step) {
   return has_neumann(c) && c->proj_every > 0 && (step % c->proj_every == 0);
 }
@@ -109,7 +115,7 @@ int step_once(tlvlbm_ctx *c, const TapeStep *tp) {
   if (proj) {
     int s = run_projection(c, true, tn, tp ? tp->xs[0] : nullptr, tp ? tp->xmode : 0);
     if (s) return s;
-    launch_bulk(c, true, tp ? tp->U : nullptr);
+    launch_bulk(c, true, tp ? tp->U : nullptr, tp != nullptr);
     if (tp && tp->Fr) {
       if (c->act && c->chunks) launch_tape_gather(c, c->cg.Fr, tp->Fr, c->D * c->D);
       else CHK(hipMemcpyAsync(tp->Fr, c->cg.Fr, (size_t)c->D * c->D * plane, hipMemcpyDeviceToDevice, c->st), "tape");
@@ -118,7 +124,7 @@ int step_once(tlvlbm_ctx *c, const TapeStep *tp) {
     if (s) return s;
     ++c->st_proj;
   } else {
-    launch_bulk(c, false, tp ? tp->U : nullptr);
+    launch_bulk(c, false, tp ? tp->U : nullptr, tp != nullptr);
   }
   if (c->L.n) {
     const int s = launch_cutlinks(c, tn);
@@ -200,6 +206,10 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   c->geo.oy = grid->origin[1];
   c->geo.oz = D == 3 ? grid->origin[2] : 0.0;
   set_material_par(c->par, mat, D);
+  for (int k = 0; k < 9; ++k) {
+    c->par.Fref[k] = (k < D * D && k % (D + 1) == 0) ? 1.0 : 0.0;
+    c->par.Pref[k] = 0.0;
+  }
   c->par.inv_rho0 = 1.0 / rho0;
   c->par.dt = dt;
   c->par.c = grid->dx / dt;
@@ -284,6 +294,12 @@ tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *c, const double *phi, const uint8_
       std::vector<uint8_t> act(N);
       CHK(hipMemcpy(act.data(), c->act, N, hipMemcpyDeviceToHost), "mask read");
       std::vector<int32_t> ch;
+      c->first_active = 0;
+      for (int64_t i = 0; i < N; ++i)
+        if (act[i]) {
+          c->first_active = i;
+          break;
+        }
       for (int64_t k = 0; k * CHUNK < N; ++k) {
         bool any = false;
         for (int64_t i = k * CHUNK; i < std::min<int64_t>(N, k * CHUNK + CHUNK) && !any; ++i) any = act[i] != 0;
@@ -392,6 +408,28 @@ tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0
     CHK(dU.take(U0, (size_t)M * N * sizeof(double), c->st), "U0 upload");
     CHK(du.take(u0, (size_t)D * N * sizeof(double), c->st), "u0 upload");
     CHK(ddU.take(dU0, (size_t)D * M * N * sizeof(double), c->st), "dU0 upload");
+    // reference state of the stored populations: (0, F0) at the first active
+    // node, with its stress under the current material
+    {
+      double Fr[9] = {0.0}, Pr[9] = {0.0};
+      CHK(hipMemcpy2DAsync(Fr, sizeof(double), (const double *)dU.ptr + (size_t)D * N + c->first_active,
+                           (size_t)N * sizeof(double), sizeof(double), (size_t)D * D, hipMemcpyDeviceToHost, c->st),
+          "reference state read");
+      CHK(hipStreamSynchronize(c->st), "synchronize");
+      bool ok = true;
+      for (int k = 0; k < D * D; ++k) ok = ok && std::isfinite(Fr[k]);
+      const double J = ok ? mat_piola_host(D, Fr, c->par, Pr) : 0.0;
+      if (!(J > 0.0) || !std::isfinite(J)) {
+        for (int k = 0; k < D * D; ++k) {
+          Fr[k] = (k % (D + 1) == 0) ? 1.0 : 0.0;
+          Pr[k] = 0.0;
+        }
+      }
+      for (int k = 0; k < 9; ++k) {
+        c->par.Fref[k] = k < D * D ? Fr[k] : 0.0;
+        c->par.Pref[k] = k < D * D ? Pr[k] * c->par.inv_rho0 : 0.0;
+      }
+    }
     const size_t fb = (size_t)c->Q * M * (size_t)S * c->esz;
     CHK(hipMemsetAsync(c->fB, 0, fb, c->st), "population clear");
     CHK(hipMemsetAsync(c->fA, 0, fb, c->st), "population clear");

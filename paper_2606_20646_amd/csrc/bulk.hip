@@ -10,10 +10,15 @@
 // cut-link kernel into the pull slot of the outside (inactive) node, so the
 // bulk kernel never branches on geometry.
 //
-// Precision.  Populations are stored shifted by the equilibrium of the
-// reference state, df = f - feq(v = 0, F = I); that equilibrium is U_I/(2D)
-// with U_I = (0, I) because P(I) = 0.  In FP32 this keeps the diagonal
-// deformation-gradient rows at O(|F - I|) magnitude instead of O(1/(2D)).
+// Precision.  Populations are stored shifted by the equilibrium of a uniform
+// reference state (0, Fref), g = f - feq(0, Fref) (the initial deformation
+// gradient at the first active node; I for a body at rest).  The stored
+// values and their sums (v, F - Fref) then have the magnitude of the
+// dynamics, not of the static deformation and its stress: a deformed
+// lattice with a weak wave on it keeps the wave's digits in FP32.  The
+// recovered F and its stress are formed in FP64 registers and the stress
+// enters the equilibrium as the difference P(F)/rho0 - P(Fref)/rho0, so the
+// FP32 arithmetic of the collision also acts on dynamic-scale values.
 #include "tl_device.hpp"
 #include "tl_internal.hpp"
 #include "tl_math.hpp"
@@ -118,60 +123,74 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
     for (int q = 1; q < Q; ++q) s += f[q][r];
     dU[r] = s;
   }
-  const T dt = T(p.dt), mu = T(p.mu), lam = T(p.lam), irho = T(p.inv_rho0);
+  const T dt = T(p.dt);
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
   T bacc[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) bacc[i] = (EXT && bf) ? bs * bf[(size_t)i * g.S + node] : T(0);
-  T v[D], F[D * D], P[D * D];
+  // the sums are v and F - Fref (populations stored about the reference
+  // state); F and its stress P(F) in FP64, which enters the equilibrium as
+  // the difference P(F)/rho0 - Pref
+  T v[D], dP[D * D];
 #pragma unroll
   for (int i = 0; i < D; ++i) v[i] = (EXT ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
+  double F[D * D], P[D * D];
 #pragma unroll
-  for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
-  T J = piola<D>(F, mu, lam, P);
+  for (int k = 0; k < D * D; ++k) F[k] = p.Fref[k] + double(dU[D + k]);
+  double J = piola<D>(F, p.mu, p.lam, P);
   if constexpr (EXT) {
-    if (p.k1 != 0.0) fibre_add<D>(F, T(p.k1), p.a0, P);
+    if (p.k1 != 0.0) fibre_add<D>(F, p.k1, p.a0, P);
   }
-  bool bad = !(J > T(0));
+  bool bad = !(J > 0.0);
   if constexpr (TAPE) {
+    if (tape) {
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) tape[(size_t)k * ts + tslot] = dU[D + k];
+      for (int k = 0; k < D * D; ++k) tape[(size_t)k * ts + tslot] = T(F[k] - ((k % (D + 1) == 0) ? 1.0 : 0.0));
+    }
   }
   const T inv2c = T(0.5) / T(p.c);
-  const T inv2D = T(1) / T(2 * D);
 
   if constexpr (REPAIR) {
-    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61)
-    T Fr[D * D], P1[D * D];
+    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61);
+    // the repaired planes hold F^r - I
+    double Fr[D * D], P1[D * D];
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) Fr[k] = Frp[(size_t)k * g.S + node];
-    const T J1 = piola<D>(Fr, mu, lam, P1);
+    for (int k = 0; k < D * D; ++k) Fr[k] = double(Frp[(size_t)k * g.S + node]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
+    const double J1 = piola<D>(Fr, p.mu, p.lam, P1);
     if constexpr (EXT) {
-      if (p.k1 != 0.0) fibre_add<D>(Fr, T(p.k1), p.a0, P1);
+      if (p.k1 != 0.0) fibre_add<D>(Fr, p.k1, p.a0, P1);
     }
-    bad |= !(J1 > T(0));
+    bad |= !(J1 > 0.0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int A = q / 2;
-      const T sg = (q & 1) ? T(-1) : T(1);
+      const double sg = (q & 1) ? -1.0 : 1.0;
 #pragma unroll
-      for (int i = 0; i < D; ++i) f[q][i] += sg * inv2c * (-(P1[i * D + A] - P[i * D + A]) * irho);
+      for (int i = 0; i < D; ++i) f[q][i] += T(sg * (0.5 / p.c) * (-(P1[i * D + A] - P[i * D + A]) * p.inv_rho0));
 #pragma unroll
-      for (int k = 0; k < D * D; ++k) f[q][D + k] += (Fr[k] - F[k]) * inv2D;
+      for (int k = 0; k < D * D; ++k) f[q][D + k] += T((Fr[k] - F[k]) / (2 * D));
     }
 #pragma unroll
     for (int k = 0; k < D * D; ++k) {
-      F[k] = Fr[k];
       P[k] = P1[k];
-      dU[D + k] = Fr[k] - ((k % (D + 1) == 0) ? T(1) : T(0));
+      dU[D + k] = T(Fr[k] - p.Fref[k]);
     }
     J = J1;
   }
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) dP[k] = T(P[k] * p.inv_rho0 - p.Pref[k]);
 
-  // BGK collision with source weights 1/(4D) (Eqs. 29-30).  Shifted
-  // equilibrium: feq_q - U_I/(2D) = (U - U_I)/(2D) + e_qA Phi_A(U) / (2c).
+  // BGK collision with source weights 1/(4D) (Eqs. 29-30) in the stored
+  // variables: feq_q(U) - feq_q(0, Fref) = (v, F - Fref)/(2D)
+  // + e_qA (Phi_A(U) - Phi_A(0, Fref)) / (2c).
+  // The isotropic part (v, F - Fref)/(2D) once per row, rounded from FP64:
+  // 1/(2D) has no exact FP32 value in 3D, and a rounded factor would bias
+  // the zeroth moment of every collision by the same relative amount.
   const T om = T(p.omega);
   const T srcw = dt * (T(2) - om) / T(4 * D);
+  T iso[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) iso[r] = T(double(r < D ? v[r] : dU[r]) * (1.0 / (2 * D)));
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int A = q / 2;
@@ -179,16 +198,13 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
 #pragma unroll
     for (int r = 0; r < M; ++r) {
       T phi;
-      T base;
       if (r < D) {
-        phi = -P[r * D + A] * irho;
-        base = v[r];
+        phi = -dP[r * D + A];
       } else {
         const int i = (r - D) / D, B = (r - D) % D;
         phi = (A == B) ? -v[i] : T(0);
-        base = dU[r];
       }
-      const T feq = base * inv2D + sg * inv2c * phi;
+      const T feq = iso[r] + sg * inv2c * phi;
       T out = f[q][r] + om * (feq - f[q][r]);
       if (r < D) out += srcw * (EXT ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
@@ -210,9 +226,9 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
       ustar[(size_t)i * g.S + node] = uu + hdt * double(v[i]);
     }
   }
-  T chk = J;
+  double chk = J;
 #pragma unroll
-  for (int i = 0; i < D; ++i) chk += v[i];
+  for (int i = 0; i < D; ++i) chk += double(v[i]);
   if (bad || !finite_(chk)) atomicOr(flag, finite_(chk) ? FLAG_J : FLAG_NONFINITE);
 }
 
@@ -247,56 +263,68 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
     for (int q = 1; q < Q; ++q) s += f[q][r];
     dU[r] = s;
   }
-  const T dt = T(p.dt), mu = T(p.mu), lam = T(p.lam), irho = T(p.inv_rho0);
+  const T dt = T(p.dt);
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
   T bacc[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) bacc[i] = (EXT && bf) ? bs * bf[(size_t)i * g.S + node] : T(0);
-  T v[D], F[D * D], P[D * D];
+  // the sums are v and F - Fref (populations stored about the reference
+  // state); F and its stress P(F) in FP64, which enters the equilibrium as
+  // the difference P(F)/rho0 - Pref
+  T v[D], dP[D * D];
 #pragma unroll
   for (int i = 0; i < D; ++i) v[i] = (EXT ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
+  double F[D * D], P[D * D];
 #pragma unroll
-  for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
-  T J = piola<D>(F, mu, lam, P);
+  for (int k = 0; k < D * D; ++k) F[k] = p.Fref[k] + double(dU[D + k]);
+  double J = piola<D>(F, p.mu, p.lam, P);
   if constexpr (EXT) {
-    if (p.k1 != 0.0) fibre_add<D>(F, T(p.k1), p.a0, P);
+    if (p.k1 != 0.0) fibre_add<D>(F, p.k1, p.a0, P);
   }
-  bool bad = !(J > T(0));
+  bool bad = !(J > 0.0);
   const T inv2c = T(0.5) / T(p.c);
-  const T inv2D = T(1) / T(2 * D);
 
   if constexpr (REPAIR) {
-    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61)
-    T Fr[D * D], P1[D * D];
+    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61);
+    // the repaired planes hold F^r - I
+    double Fr[D * D], P1[D * D];
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) Fr[k] = Frp[(size_t)k * g.S + node];
-    const T J1 = piola<D>(Fr, mu, lam, P1);
+    for (int k = 0; k < D * D; ++k) Fr[k] = double(Frp[(size_t)k * g.S + node]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
+    const double J1 = piola<D>(Fr, p.mu, p.lam, P1);
     if constexpr (EXT) {
-      if (p.k1 != 0.0) fibre_add<D>(Fr, T(p.k1), p.a0, P1);
+      if (p.k1 != 0.0) fibre_add<D>(Fr, p.k1, p.a0, P1);
     }
-    bad |= !(J1 > T(0));
+    bad |= !(J1 > 0.0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int A = q / 2;
-      const T sg = (q & 1) ? T(-1) : T(1);
+      const double sg = (q & 1) ? -1.0 : 1.0;
 #pragma unroll
-      for (int i = 0; i < D; ++i) f[q][i] += sg * inv2c * (-(P1[i * D + A] - P[i * D + A]) * irho);
+      for (int i = 0; i < D; ++i) f[q][i] += T(sg * (0.5 / p.c) * (-(P1[i * D + A] - P[i * D + A]) * p.inv_rho0));
 #pragma unroll
-      for (int k = 0; k < D * D; ++k) f[q][D + k] += (Fr[k] - F[k]) * inv2D;
+      for (int k = 0; k < D * D; ++k) f[q][D + k] += T((Fr[k] - F[k]) / (2 * D));
     }
 #pragma unroll
     for (int k = 0; k < D * D; ++k) {
-      F[k] = Fr[k];
       P[k] = P1[k];
-      dU[D + k] = Fr[k] - ((k % (D + 1) == 0) ? T(1) : T(0));
+      dU[D + k] = T(Fr[k] - p.Fref[k]);
     }
     J = J1;
   }
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) dP[k] = T(P[k] * p.inv_rho0 - p.Pref[k]);
 
-  // BGK collision with source weights 1/(4D) (Eqs. 29-30).  Shifted
-  // equilibrium: feq_q - U_I/(2D) = (U - U_I)/(2D) + e_qA Phi_A(U) / (2c).
+  // BGK collision with source weights 1/(4D) (Eqs. 29-30) in the stored
+  // variables: feq_q(U) - feq_q(0, Fref) = (v, F - Fref)/(2D)
+  // + e_qA (Phi_A(U) - Phi_A(0, Fref)) / (2c).
+  // The isotropic part (v, F - Fref)/(2D) once per row, rounded from FP64:
+  // 1/(2D) has no exact FP32 value in 3D, and a rounded factor would bias
+  // the zeroth moment of every collision by the same relative amount.
   const T om = T(p.omega);
   const T srcw = dt * (T(2) - om) / T(4 * D);
+  T iso[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) iso[r] = T(double(r < D ? v[r] : dU[r]) * (1.0 / (2 * D)));
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int A = q / 2;
@@ -304,16 +332,13 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
 #pragma unroll
     for (int r = 0; r < M; ++r) {
       T phi;
-      T base;
       if (r < D) {
-        phi = -P[r * D + A] * irho;
-        base = v[r];
+        phi = -dP[r * D + A];
       } else {
         const int i = (r - D) / D, B = (r - D) % D;
         phi = (A == B) ? -v[i] : T(0);
-        base = dU[r];
       }
-      const T feq = base * inv2D + sg * inv2c * phi;
+      const T feq = iso[r] + sg * inv2c * phi;
       T out = f[q][r] + om * (feq - f[q][r]);
       if (r < D) out += srcw * (EXT ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
@@ -335,9 +360,9 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
       ustar[(size_t)i * g.S + node] = uu + hdt * double(v[i]);
     }
   }
-  T chk = J;
+  double chk = J;
 #pragma unroll
-  for (int i = 0; i < D; ++i) chk += v[i];
+  for (int i = 0; i < D; ++i) chk += double(v[i]);
   if (bad || !finite_(chk)) atomicOr(flag, finite_(chk) ? FLAG_J : FLAG_NONFINITE);
 }
 
@@ -407,7 +432,7 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_batch(const Inst *_
 
 // Pull f^n and write moments: v (damping-corrected), F, u = u* + dt/2 v, J.
 // Output planes have stride ostride; any output may be null.
-template <int D, typename T, typename O, bool MASK>
+template <int D, typename T, typename O, bool MASK, bool DEV = false>
 __device__ __forceinline__ void moments_node(const T *__restrict__ fin, const Geo &g, const Par &p,
                                              const uint8_t *__restrict__ act, const double *__restrict__ ustar,
                                              O *__restrict__ Vo, O *__restrict__ Fo, double *__restrict__ uo,
@@ -437,23 +462,25 @@ __device__ __forceinline__ void moments_node(const T *__restrict__ fin, const Ge
     dU[r] = s;
   }
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * T(p.dt));
-  T v[D], F[D * D];
+  T v[D];
+  double F[D * D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
     v[i] = (bf ? dU[i] + T(0.5) * T(p.dt) * (bs * bf[(size_t)i * g.S + node]) : dU[i]) * inv_damp;
 #pragma unroll
-  for (int k = 0; k < D * D; ++k) F[k] = dU[D + k] + ((k % (D + 1) == 0) ? T(1) : T(0));
+  for (int k = 0; k < D * D; ++k) F[k] = p.Fref[k] + double(dU[D + k]);  // stored about (0, Fref)
   if (Vo)
     for (int i = 0; i < D; ++i) Vo[(size_t)i * ostride + node] = O(v[i]);
-  if (Fo)
-    for (int k = 0; k < D * D; ++k) Fo[(size_t)k * ostride + node] = O(F[k]);
+  if (Fo)  // DEV: F - I (the projection's planes), else F
+    for (int k = 0; k < D * D; ++k)
+      Fo[(size_t)k * ostride + node] = O(DEV ? F[k] - ((k % (D + 1) == 0) ? 1.0 : 0.0) : F[k]);
   if (uo)
     for (int i = 0; i < D; ++i)
       uo[(size_t)i * ostride + node] = ustar ? ustar[(size_t)i * g.S + node] + 0.5 * p.dt * double(v[i]) : 0.0;
   if (Jo) Jo[node] = O(det<D>(F));
 }
 
-template <int D, typename T, typename O, bool MASK>
+template <int D, typename T, typename O, bool MASK, bool DEV = false>
 __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ fin, Geo g, Par p,
                                                   const uint8_t *__restrict__ act, const double *__restrict__ ustar,
                                                   O *__restrict__ Vo, O *__restrict__ Fo, double *__restrict__ uo,
@@ -461,7 +488,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ fin, Geo 
                                                   T bs) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
-  moments_node<D, T, O, MASK>(fin, g, p, act, ustar, Vo, Fo, uo, Jo, ostride, x, (int)blockIdx.y, bf, bs);
+  moments_node<D, T, O, MASK, DEV>(fin, g, p, act, ustar, Vo, Fo, uo, Jo, ostride, x, (int)blockIdx.y, bf, bs);
 }
 
 // batched projection inputs: v, F into each instance's workspace, u = u* + dt/2 v
@@ -472,7 +499,7 @@ __global__ __launch_bounds__(256) void k_moments_batch(const Inst *__restrict__ 
   const Inst &I = insts[t.x];
   const int x = t.z + threadIdx.x;
   if (x >= I.g.nx) return;
-  moments_node<D, T, T, true>((const T *)I.fin, I.g, I.p, I.act, (const double *)I.ustar, (T *)I.V, (T *)I.Fm,
+  moments_node<D, T, T, true, true>((const T *)I.fin, I.g, I.p, I.act, (const double *)I.ustar, (T *)I.V, (T *)I.Fm,
                               (double *)I.ubuf, (T *)nullptr, I.g.S, x, t.y);
 }
 
@@ -545,8 +572,8 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
       }
       const double feq = U[r] * inv2D + sg * phi / (2.0 * c);
       const double dfeq = Z[r] * inv2D + sg * dphi / (2.0 * c);
-      double fv = feq - 0.5 * p.dt * dfeq;
-      if (r >= D && ((r - D) % (D + 1) == 0)) fv -= inv2D;  // shifted storage
+      // stored about the reference state (0, Fref)
+      const double fv = feq - 0.5 * p.dt * dfeq - pop_shift<D>(p, q, r);
       fout[(size_t)(q * M + r) * g.S + dst] = T(fv);
     }
   }
@@ -558,9 +585,9 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
 
 // raw pre-collision populations f^n (unshifted) [Q][M][N] and u*^n [D][N]
 template <int D, typename T, bool MASK>
-__global__ __launch_bounds__(256) void k_get_f(const T *__restrict__ fin, Geo g, const uint8_t *__restrict__ act,
-                                                const double *__restrict__ ustar, double *__restrict__ fo,
-                                                double *__restrict__ uso) {
+__global__ __launch_bounds__(256) void k_get_f(const T *__restrict__ fin, Geo g, Par p,
+                                                const uint8_t *__restrict__ act, const double *__restrict__ ustar,
+                                                double *__restrict__ fo, double *__restrict__ uso) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
@@ -575,8 +602,7 @@ __global__ __launch_bounds__(256) void k_get_f(const T *__restrict__ fin, Geo g,
     for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        double sh = (r >= D && ((r - D) % (D + 1) == 0)) ? 1.0 / (2 * D) : 0.0;
-        fo[((size_t)q * M + r) * g.N + node] = on ? double(f[q][r]) + sh : 0.0;
+        fo[((size_t)q * M + r) * g.N + node] = on ? double(f[q][r]) + pop_shift<D>(p, q, r) : 0.0;
       }
   }
   if (uso)
@@ -584,7 +610,7 @@ __global__ __launch_bounds__(256) void k_get_f(const T *__restrict__ fin, Geo g,
 }
 
 template <int D, typename T, bool MASK>
-__global__ __launch_bounds__(256) void k_put_f(T *__restrict__ fout, Geo g, const uint8_t *__restrict__ act,
+__global__ __launch_bounds__(256) void k_put_f(T *__restrict__ fout, Geo g, Par p, const uint8_t *__restrict__ act,
                                                 const double *__restrict__ fi, const double *__restrict__ usi,
                                                 double *__restrict__ ustar) {
   constexpr int Q = 2 * D, M = D + D * D;
@@ -605,8 +631,7 @@ __global__ __launch_bounds__(256) void k_put_f(T *__restrict__ fout, Geo g, cons
       const int64_t dst = xs + (int64_t)g.nx * (ys + (int64_t)g.ny * zs);
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        double sh = (r >= D && ((r - D) % (D + 1) == 0)) ? 1.0 / (2 * D) : 0.0;
-        fout[(size_t)(q * M + r) * g.S + dst] = T(fi[((size_t)q * M + r) * g.N + node] - sh);
+        fout[(size_t)(q * M + r) * g.S + dst] = T(fi[((size_t)q * M + r) * g.N + node] - pop_shift<D>(p, q, r));
       }
     }
   }
@@ -714,10 +739,10 @@ template <int D, typename T, bool EXT> static void bulk_tape_t(tlvlbm_ctx *c, bo
                        c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
 }
 
-template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair, void *tape) {
+template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair, void *tape, bool taped) {
   // extensions (body acceleration, fibre law) in their own instantiation
   const bool ext = c->bf || c->par.k1 != 0.0;
-  if (tape) {
+  if (tape || taped) {
     if (ext) bulk_tape_t<D, T, true>(c, repair, tape);
     else bulk_tape_t<D, T, false>(c, repair, tape);
     return;
@@ -726,13 +751,13 @@ template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair, void
   else bulk_plain_t<D, T, false>(c, repair);
 }
 
-void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape) {
+void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape, bool taped) {
   if (c->D == 2) {
-    if (c->prec) bulk_t<2, double>(c, repair, tape);
-    else bulk_t<2, float>(c, repair, tape);
+    if (c->prec) bulk_t<2, double>(c, repair, tape, taped);
+    else bulk_t<2, float>(c, repair, tape, taped);
   } else {
-    if (c->prec) bulk_t<3, double>(c, repair, tape);
-    else bulk_t<3, float>(c, repair, tape);
+    if (c->prec) bulk_t<3, double>(c, repair, tape, taped);
+    else bulk_t<3, float>(c, repair, tape, taped);
   }
 }
 
@@ -746,10 +771,10 @@ static void moments_t(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_sc
   if (to_scratch) {
     // projection inputs: v, F into the CG workspace, u into the u buffer
     if (c->act)
-      hipLaunchKernelGGL((k_moments<D, T, T, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act,
+      hipLaunchKernelGGL((k_moments<D, T, T, true, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act,
                          us, (T *)c->cg.V, (T *)c->cg.Fm, (double *)c->ubuf, (T *)nullptr, (int64_t)c->geo.S, bf, bs);
     else
-      hipLaunchKernelGGL((k_moments<D, T, T, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par,
+      hipLaunchKernelGGL((k_moments<D, T, T, false, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par,
                          c->act, us, (T *)c->cg.V, (T *)c->cg.Fm, (double *)c->ubuf, (T *)nullptr, (int64_t)c->geo.S, bf,
                          bs);
     return;
@@ -801,9 +826,11 @@ template <int D, typename T> static void getf_t(tlvlbm_ctx *c, double *f, double
   grid_of(c->geo, grid, block);
   const double *ust = c->track_u ? (const double *)c->ustar : nullptr;
   if (c->act)
-    hipLaunchKernelGGL((k_get_f<D, T, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->act, ust, f, us);
+    hipLaunchKernelGGL((k_get_f<D, T, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act, ust, f,
+                       us);
   else
-    hipLaunchKernelGGL((k_get_f<D, T, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->act, ust, f, us);
+    hipLaunchKernelGGL((k_get_f<D, T, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act, ust, f,
+                       us);
 }
 
 // caller planes [k][N] (FP64) into context planes [k][S] (population precision)
@@ -838,9 +865,9 @@ template <int D, typename T> static void putf_t(tlvlbm_ctx *c, const double *f, 
   grid_of(c->geo, grid, block);
   double *ust = c->track_u ? (double *)c->ustar : nullptr;
   if (c->act)
-    hipLaunchKernelGGL((k_put_f<D, T, true>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->act, f, us, ust);
+    hipLaunchKernelGGL((k_put_f<D, T, true>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->par, c->act, f, us, ust);
   else
-    hipLaunchKernelGGL((k_put_f<D, T, false>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->act, f, us, ust);
+    hipLaunchKernelGGL((k_put_f<D, T, false>), grid, block, 0, c->st, (T *)c->fB, c->geo, c->par, c->act, f, us, ust);
 }
 
 void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar) {

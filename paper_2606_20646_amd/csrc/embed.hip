@@ -435,7 +435,8 @@ __device__ __forceinline__ void cut_dirichlet_link(T *__restrict__ f, const Link
     } else {
       const int i = (r - D) / D, B = (r - D) % D;
       Dg = T(1);
-      // -d_B v_i / c with d = -e_{q_out}; the shift cancels for these rows
+      // -d_B v_i / c with d = -e_{q_out}; the shifts of q_out and q_in cancel
+      // in both row kinds (Dg = -1 on velocity rows, whose shift is odd in q)
       S = (B == A) ? T(sg * vb[i] / p.c) : T(0);
     }
     T out;
@@ -483,12 +484,12 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
   bc_base<D>(bc, Xb, N, Tb);
   for (int i = 0; i < D; ++i) Tb[i] *= s;
   // initial guess h0 = F_m N with F_m = sum_q f*_q^F(m) (collision keeps the
-  // F moment since the source has no F rows)
+  // F moment since the source has no F rows; stored about Fref)
   double h[D];
   {
     double Fm[D * D];
     for (int k = 0; k < D * D; ++k) {
-      double acc = (k % (D + 1) == 0) ? 1.0 : 0.0;
+      double acc = p.Fref[k];
       for (int qq = 0; qq < Q; ++qq) acc += double(f[(size_t)(qq * M + D + k) * g.S + m]);
       Fm[k] = acc;
     }
@@ -515,14 +516,17 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
 #pragma unroll
   for (int r = 0; r < M; ++r) {
     T Dg, S;
+    // sources in the stored variables g = f - feq(0, Fref): the closure
+    // g_in = Dg g_out + S holds with S = S_f + Dg g_shift(q_out) - g_shift(q_in)
     if (r < D) {
       Dg = T(1);
-      S = T(sg * Pb[r * D + A] * p.inv_rho0 / p.c);  // -d_A P_b,iA / (rho0 c)
+      // -d_A P_b,iA / (rho0 c), d = -e_{q_out}, plus twice the shift of q_out
+      S = T(sg * (Pb[r * D + A] * p.inv_rho0 - p.Pref[r * D + A]) / p.c);
     } else {
       const int k = r - D;
       Dg = T(-1);
-      // F_b/D in shifted variables: (F_b - I)/D
-      S = T((Fb[k] - ((k % (D + 1) == 0) ? 1.0 : 0.0)) / D);
+      // F_b/D less twice the shift Fref/(2D)
+      S = T((Fb[k] - p.Fref[k]) / D);
     }
     T out;
     if (eta >= 0.5) out = (Dg * fo[r] + S) * ie + (T(1) - ie) * fx[r];
@@ -556,7 +560,7 @@ __device__ __forceinline__ void anchor_link(const Links &L, int64_t l, const BC 
   const double off = sg * L.eta[l] * g.dx;
   atomicAdd(&anc_n[m], 1);
   for (int i = 0; i < D; ++i) {
-    const double Fi = double(Fm[(size_t)(i * D + A) * g.S + m]) - (i == A ? 1.0 : 0.0);
+    const double Fi = double(Fm[(size_t)(i * D + A) * g.S + m]);  // F - I
     atomicAdd(&anc_s[(size_t)i * g.S + m], uD[i] - Fi * off);
   }
 }
@@ -578,9 +582,8 @@ __device__ __forceinline__ void cg_rhs_node(const Geo &g, const uint8_t *__restr
     for (int A = 0; A < D; ++A) {
       const int64_t lp = node_dir(g, cc, 2 * A, 1), lm = node_dir(g, cc, 2 * A + 1, 1);
       const double Fi = Fm[(size_t)(c * D + A) * g.S + i];
-      const double dl = (c == A) ? double(2) : double(0);
-      if (lm >= 0 && act[lm]) acc += hdx * (Fi + Fm[(size_t)(c * D + A) * g.S + lm] - dl);
-      if (lp >= 0 && act[lp]) acc -= hdx * (Fi + Fm[(size_t)(c * D + A) * g.S + lp] - dl);
+      if (lm >= 0 && act[lm]) acc += hdx * (Fi + Fm[(size_t)(c * D + A) * g.S + lm]);
+      if (lp >= 0 && act[lp]) acc -= hdx * (Fi + Fm[(size_t)(c * D + A) * g.S + lp]);
     }
     b[(size_t)c * g.S + i] = acc;
   }
@@ -619,9 +622,8 @@ __device__ __forceinline__ void cg_rhs_node_m(const Geo &g, const uint8_t *__res
 #pragma unroll
     for (int A = 0; A < D; ++A) {
       const int k = c * D + A;
-      const double dl = (c == A) ? double(2) : double(0);
-      acc += ((m >> (2 * A + 1)) & 1u) ? hdx * (Fi[k] + Fn[k] - dl) : 0.0;
-      acc -= ((m >> (2 * A)) & 1u) ? hdx * (Fi[k] + Fp[k] - dl) : 0.0;
+      acc += ((m >> (2 * A + 1)) & 1u) ? hdx * (Fi[k] + Fn[k]) : 0.0;
+      acc -= ((m >> (2 * A)) & 1u) ? hdx * (Fi[k] + Fp[k]) : 0.0;
     }
     b[(size_t)c * g.S + i] = acc;
   }
@@ -915,7 +917,9 @@ __device__ __forceinline__ void jacobi_node_m(const Geo &g, const uint8_t *__res
 
 // compatible gradient F^c = I + grad_dx u^c (Eq. 59) and F^r = (1-theta) F +
 // theta F^c (Eq. 60): centred differences, one-sided next to a cut, the
-// evolved column kept when neither neighbour is active
+// evolved column kept when neither neighbour is active.  The projection's
+// deformation planes (evolved F, repaired F^r) hold F - I: the deviation keeps
+// its digits in the FP32 build, where a stored F = I + small loses them.
 template <int D, typename T>
 __device__ __forceinline__ void gradF_node(const Geo &g, const uint8_t *__restrict__ act, const double *__restrict__ u,
                                            const T *__restrict__ Fm, T *__restrict__ Fr, double theta, int64_t i) {
@@ -935,7 +939,6 @@ __device__ __forceinline__ void gradF_node(const Geo &g, const uint8_t *__restri
         Fr[(size_t)(c * D + A) * g.S + i] = T(Fe);
         continue;
       }
-      Fc += (c == A) ? 1.0 : 0.0;
       Fr[(size_t)(c * D + A) * g.S + i] = T((1.0 - theta) * Fe + theta * Fc);
     }
   }

@@ -172,7 +172,7 @@ template <int D> __device__ inline bool solve_small(const double *A, const doubl
 
 // stress and tangent action of the material in FP64 (neo-Hookean, plus the
 // fibre term when p.k1 > 0)
-template <int D> __device__ __forceinline__ double mat_piola(const double *F, const Par &p, double *P) {
+template <int D> __host__ __device__ __forceinline__ double mat_piola(const double *F, const Par &p, double *P) {
   const double J = piola<D>(F, p.mu, p.lam, P);
   if (p.k1 != 0.0) fibre_add<D>(F, p.k1, p.a0, P);
   return J;

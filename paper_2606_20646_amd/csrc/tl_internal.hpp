@@ -35,7 +35,20 @@ struct Geo {
 struct Par {
   double mu, lam, inv_rho0, dt, c, omega, gamma;
   double k1, a0[3];  // fibre reinforcement (k1 = 0: the neo-Hookean law of Eq. 62)
+  // Reference state (0, Fref) of the stored populations: every kernel keeps
+  // g_q = f_q - feq_q(0, Fref), whose moments are (v, F - Fref) and whose
+  // magnitudes are those of the dynamics rather than of the static stress.
+  // Pref = P(Fref) / rho0 with the material of tlvlbm_set_state (a constant
+  // of the representation: a later material change keeps it).
+  double Fref[9], Pref[9];
 };
+
+// stored-population shift feq_q^r(0, Fref) of direction q, row r:
+// velocity rows -e_qA Pref_iA / (2c), deformation rows Fref / (2D)
+template <int D> __host__ __device__ __forceinline__ double pop_shift(const Par &p, int q, int r) {
+  if (r < D) return ((q & 1) ? 0.5 : -0.5) * p.Pref[r * D + q / 2] / p.c;
+  return p.Fref[r - D] / (2 * D);
+}
 
 // cut-link table (device SoA), ordered by (bid, node, q)
 struct Links {
@@ -123,7 +136,7 @@ struct AdjArena {
 struct CG {
   void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *Ap = nullptr, *b = nullptr;  // [D][S] FP64
   void *z = nullptr;                                // preconditioned residual [D][S] FP64
-  void *V = nullptr, *Fm = nullptr, *Fr = nullptr;  // v [D][S], F [D2][S], F^r [D2][S]  (T)
+  void *V = nullptr, *Fm = nullptr, *Fr = nullptr;  // v [D][S], F - I [D2][S], F^r - I [D2][S]  (T)
   uint8_t *anc_n = nullptr;                         // anchors per node
   int *anc_i = nullptr;                             // anchor counting scratch
   void *anc_s = nullptr;                            // anchor target sums [D][S] (FP64)
@@ -311,6 +324,7 @@ struct tlvlbm_ctx {
   // builds (a quadrature over thousands of steps; FP32 sums lose ~1e-5)
   void *ustar = nullptr, *ubuf = nullptr;
   uint8_t *act = nullptr;  // active mask (nullptr: all active)
+  int64_t first_active = 0;  // first active node in node order (the reference state is read there)
   bool has_ls = false, have_state = false;
   bool fresh = false;  // state is the one set by set_state (no step since)
   int64_t nactive = 0;
@@ -333,7 +347,10 @@ struct tlvlbm_ctx {
 
 namespace tl {
 // launchers (bulk.hip)
-void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape = nullptr);
+// taped: the kernels of the reverse mode's forward (the same update through
+// the shared device function, recording the tape when tape is not null), so
+// that steps with and without a tape round identically
+void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape = nullptr, bool taped = false);
 void launch_pull_moments(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch);
 void launch_init(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0);
 void launch_get_f(tlvlbm_ctx *c, double *f, double *ustar);

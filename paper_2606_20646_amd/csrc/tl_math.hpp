@@ -13,7 +13,7 @@ template <int D> struct Lat {
 };
 
 // determinant and cofactor matrix cof(F) = det(F) F^{-T}
-template <int D, typename T> __device__ __forceinline__ T det(const T *F) {
+template <int D, typename T> __host__ __device__ __forceinline__ T det(const T *F) {
   if constexpr (D == 2) {
     return F[0] * F[3] - F[1] * F[2];
   } else {
@@ -22,7 +22,7 @@ template <int D, typename T> __device__ __forceinline__ T det(const T *F) {
   }
 }
 
-template <int D, typename T> __device__ __forceinline__ void cofactor(const T *F, T *C) {
+template <int D, typename T> __host__ __device__ __forceinline__ void cofactor(const T *F, T *C) {
   if constexpr (D == 2) {
     C[0] = F[3];
     C[1] = -F[2];
@@ -46,7 +46,7 @@ template <int D, typename T> __device__ __forceinline__ void cofactor(const T *F
 //   P = mu (F - F^{-T}) + lambda/2 (J^2 - 1) F^{-T}.
 // Returns J; the caller flags J <= 0.
 template <int D, typename T>
-__device__ __forceinline__ T piola(const T *F, T mu, T lam, T *P) {
+__host__ __device__ __forceinline__ T piola(const T *F, T mu, T lam, T *P) {
   T C[D * D];
   cofactor<D>(F, C);
   const T J = det<D>(F);
@@ -97,7 +97,7 @@ __device__ __forceinline__ void piola_tangent(const T *F, const T *dF, T mu, T l
 //   P  += 2 k1 (I4 - 1) (F a0) (x) a0,
 //   dP += 2 k1 [2 ((F a0).(dF a0)) (F a0) + (I4 - 1) dF a0] (x) a0.
 template <int D, typename T>
-__device__ __forceinline__ void fibre_add(const T *F, T k1, const double *a0, T *P) {
+__host__ __device__ __forceinline__ void fibre_add(const T *F, T k1, const double *a0, T *P) {
   T fa[D], I4 = T(0);
 #pragma unroll
   for (int i = 0; i < D; ++i) {

@@ -13,6 +13,7 @@ segment lengths give the same result (the recomputation is deterministic).
 import numpy as np
 import pytest
 
+from parity import check
 from test_oracle_adjoint import CASES, _make
 
 pytestmark = pytest.mark.gpu
@@ -81,7 +82,13 @@ def test_adjoint_matches_oracle(T, orc, name, precision, tol):
     # the context ends at step n with the forward state
     U, u, _ = s.moments()
     Uo, uo, _ = o.moments()
-    assert _rel(U, Uo) <= (1e-11 if precision == "fp64" else 1e-5)
+    act = (cfg["phi"] <= 0).reshape(-1) if "phi" in cfg else None
+    # exact projection: CG stopped at a residual of 1e-14 (GPU) / 1e-15 (oracle)
+    # relative to the larger of |b| and the initial residual, which the
+    # random initial displacement of these cases makes large
+    ftol = 1e-5 if precision == "fp32" else (1e-12 if cfg.get("proj_sweeps", 20) > 0 else 1e-9)
+    check(U, Uo, cfg["D"], ftol, mask=act, label=f"adjoint forward {name} {precision}", pops=o.get_f(), steps=n,
+          stress=(cfg["mu"], cfg["lam"], 1.0, cfg["dx"] / cfg["dt"], cfg["omega"]))
 
 
 @pytest.mark.parametrize("name", ["neumann_annulus_projection", "periodic2d_damped"])

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -61,10 +62,24 @@ def _oracle(orc, cfg):
 CFGS = [W.config_c4_instance(k, N=n) for k, n in enumerate([40, 64, 48, 33])]
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+# Jacobi projection: the same per-node arithmetic in both paths (FMA
+# contraction may differ between the two kernels: FP32 1e-6).  Exact
+# projection: CG stopped at relative residual 1e-14 (FP64 build) or 1e-8
+# (FP32 build) at different iterations in the two paths; with cond(K) ~ 1e4 on
+# these graphs the displacement differs by up to ~1e-10 / 1e-4 of its scale,
+# and the repair carries that into v and F: 1e-10 / 1e-4.  The batched CG
+# also keeps iterating on converged instances until all have converged.
+def _batch_tol(precision, sweeps):
+    if sweeps > 0:
+        return 1e-12 if precision == "fp64" else 1e-6
+    return 1e-10 if precision == "fp64" else 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("graph,mg,sweeps", [(True, False, 20), (False, False, 20), (True, False, 0),
                                              (False, False, 0), (True, True, 0)])
-def test_batch_equals_per_instance(env, precision, tol, graph, mg, sweeps):
+def test_batch_equals_per_instance(env, precision, graph, mg, sweeps):
+    tol = _batch_tol(precision, sweeps)
     T, stream = env
     _say(f"batch vs per-instance {precision} graph={graph} multigrid={mg} projection sweeps={sweeps}")
     A = [_solver(T, c, precision, stream, cg_multigrid=mg, proj_sweeps=sweeps) for c in CFGS]
@@ -74,11 +89,12 @@ def test_batch_equals_per_instance(env, precision, tol, graph, mg, sweeps):
     bt.step(30)
     bt.step(35)
     bt.close()
-    for a, b, c in zip(A, B, CFGS):
+    for k, (a, b, c) in enumerate(zip(A, B, CFGS)):
         Ua, ua, _ = a.moments()
         Ub, ub, _ = b.moments()
         act = c["phi"] <= 0
-        assert np.linalg.norm(Ua[:, act] - Ub[:, act]) <= tol * np.linalg.norm(Ua[:, act])
+        check(Ub, Ua, 2, tol, mask=act, label=f"batch instance {k} vs per-instance", pops=a.get_state()[0],
+              steps=65, stress=(c["mu"], c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
         # the displacement comes out of the projection solver.  Jacobi sweeps:
         # the same per-node arithmetic in both paths.  Exact mode: a CG
         # stopped at relative residual 1e-14 / 1e-8; the two paths compile
@@ -108,7 +124,8 @@ def test_batched_instance_matches_oracle(env, orc):
         Ub, ub, _ = b.moments()
         Uo, uo, _ = o.moments()
         act = c["phi"] <= 0
-        assert np.linalg.norm(Ub[:, act] - Uo[:, act]) <= 1e-11 * np.linalg.norm(Uo[:, act])
+        check(Ub, Uo, 2, 1e-12, mask=act, label="batched instance vs oracle fp64", pops=o.get_f(), steps=45,
+              stress=(c["mu"], c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
         # u comes out of the projection's Jacobi relaxation, whose terms are
         # of size dx |F - I|; where the ramped load has not arrived yet u is
         # round-off of those terms, so the bound has an absolute floor at
@@ -148,4 +165,4 @@ def test_tile_configurations_agree(env):
     for a, (Ur, _), c in zip(A, ref, CFGS):
         act = c["phi"] <= 0
         Ua = a.moments()[0]
-        assert np.linalg.norm(Ua[:, act] - Ur[:, act]) <= 1e-6 * np.linalg.norm(Ua[:, act])
+        check(Ur, Ua, 2, 1e-6, mask=act, label="batched fp32 vs per-instance")

@@ -5,10 +5,12 @@ current torch stream, inputs resident on the device).
 The oracle cannot rerun 256^3 x 1000 steps inside a test, so its state at 256
 seeded nodes and its per-component sums over all nodes are stored in
 tests/golden/c3_256_1000_samples.txt (written by make_c3_golden.py from the
-oracle alone).  Gates: FP32 populations within 1e-5 of the FP64 oracle,
-FP64 populations within 1e-12 (relative L2 over the sampled states); the sums
-agree with the oracle's (conservation of the state over the periodic grid,
-Sec. 2.4 with B = 0).
+oracle alone).  Gates, per part of the state over the sampled nodes: the
+velocity against its own norm and the deformation gradient against its
+deviation from the grid mean F0 (the conserved mean, Sec. 2.4 with B = 0, is
+the large static part of F; what the dynamics did is F - F0), FP32 within
+1e-5 and FP64 within 1e-12, and the pointwise ratios of each part likewise.
+The sums of F over all nodes agree with the oracle's (conservation).
 """
 import os
 
@@ -16,6 +18,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -64,12 +67,13 @@ def test_c3_256_1000_steps(c3, precision, tol, stol):
     sums_g = Ud.sum(dim=1).cpu().numpy()
     g.close()
     del Ud
-    err = np.linalg.norm(Ug - Uo)
-    mean = (sums_o / 256 ** 3)[:, None]
-    dyn = np.linalg.norm(Uo - mean)
-    print(f"relative error {err / np.linalg.norm(Uo):.3e}, against the deviation from the mean "
-          f"{err / dyn:.3e}", flush=True)
-    assert err <= tol * np.linalg.norm(Uo)
-    # sums: v sums vanish (zero-mean modes), F sums are N^3 F0; compare on the
-    # scale of the F sums
-    assert np.max(np.abs(sums_g - sums_o)) <= stol * np.max(np.abs(sums_o))
+    # the F rows measured from the conserved grid mean F0 (U0's uniform F):
+    # check() compares them against F - I, so shift both sides by F0 - I
+    F0 = c3["U0"][3:, :1]
+    shift = np.zeros((12, 1))
+    shift[3:] = F0 - np.eye(3).reshape(-1)[:, None]
+    check(Ug - shift, Uo - shift, 3, tol, label=f"c3 256^3 1000 steps {precision} (F about its mean)")
+    check(Ug, Uo, 3, tol, label=f"c3 256^3 1000 steps {precision} (F about I)")
+    # sums of F over the grid are N^3 F0, conserved; rounding moves them by
+    # at most about one unit roundoff per step
+    assert np.max(np.abs(sums_g[3:] - sums_o[3:])) <= stol * np.max(np.abs(sums_o[3:]))

@@ -1,15 +1,21 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Tolerances (relative state error ||U_gpu - U_orc||_2 / ||U_orc||_2 over all
-active nodes and components): 1e-12 for the FP64 build, 1e-5 for FP32
-populations; populations f^n are compared element by element as well.
-Geometry (active mask, cut-link table) is compared exactly, cut fractions and
-normals to FP64 round-off.
+Tolerances, per part of the state over the active nodes (tests/parity.py:
+||dv||/||v||, ||dF||/||F - I||, ||du||/||u|| and the pointwise ratios):
+1e-12 for the FP64 build, 1e-5 for FP32 populations.  The exact projection
+mode (CG stopped at relative residual 1e-14 in the FP64 build) is held to
+1e-11: the two sides stop at different iterates, and the graph Laplacian's
+condition number (~1e3-1e4 on these lattices) turns a residual of 1e-14 into
+a displacement difference of up to ~1e-10 relative in the worst case.
+Populations f^n are compared element by element as well.  Geometry (active
+mask, cut-link table) is compared exactly, cut fractions and normals to FP64
+round-off.
 """
 import numpy as np
 import pytest
 
 import workloads as W
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -46,9 +52,10 @@ def test_c1_periodic_2d_1000_steps(T, orc, precision, tol):
         s.step(c["steps"])
     Ug, _, Jg = g.moments()
     Uo, _, Jo = o.moments()
-    assert _rel(Ug, Uo) < tol
-    fg, _, step = g.get_state()
     fo = o.get_f()
+    check(Ug, Uo, 2, tol, label=f"c1 {precision}", pops=fo, steps=c["steps"],
+          stress=(c["mu"], c["lam"], 1.0, 10.0, c["omega"]))
+    fg, _, step = g.get_state()
     assert step == c["steps"]
     assert np.abs(fg - fo).max() / np.abs(fo).max() < (10 * tol)
 
@@ -79,7 +86,8 @@ def test_periodic_3d_fp64(T, orc, n):
         s.step(40)
     Ug, _, _ = g.moments()
     Uo, _, _ = o.moments()
-    assert _rel(Ug, Uo) < 1e-12
+    check(Ug, Uo, 3, 1e-12, label=f"periodic 3D {n}", pops=o.get_f(), steps=40,
+          stress=(1.0, 2.0, 1.0, 10.0, 1.8))
     fg, _, _ = g.get_state()
     assert np.abs(fg - o.get_f()).max() < 1e-13
 
@@ -95,7 +103,7 @@ def test_c3_shape_fp32_small(T, orc):
         s.step(300)
     Ug, _, _ = g.moments()
     Uo, _, _ = o.moments()
-    assert _rel(Ug, Uo) < 1e-5
+    check(Ug, Uo, 3, 1e-5, label="c3-recipe 32^3 fp32")
 
 
 def _annulus_pair(T, orc, Nc, precision, proj_every=20, steps=60, proj_sweeps=20):
@@ -124,9 +132,16 @@ def test_cut_link_table_matches_oracle(T, orc):
     assert np.abs(Lg["N"] - Lo["N"]).max() < 1e-13
 
 
+def _tol(precision, sweeps):
+    """FP64: 1e-12, the exact projection mode 1e-11 (module docstring); FP32: 1e-5"""
+    if precision == "fp32":
+        return 1e-5
+    return 1e-12 if sweeps > 0 else 1e-11
+
+
 @pytest.mark.parametrize("sweeps", [20, 0])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
-def test_mixed_annulus_with_projection(T, orc, precision, tol, sweeps):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mixed_annulus_with_projection(T, orc, precision, sweeps):
     """Clamp + traction-free annulus (the C2 recipe at N = 48): Dirichlet and
     Neumann closures, LSQ, Newton, anchored projection every 20 steps (20
     Jacobi sweeps, or the exact solve)."""
@@ -138,8 +153,8 @@ def test_mixed_annulus_with_projection(T, orc, precision, tol, sweeps):
     Ug, ug, _ = g.moments()
     Uo, uo, _ = o.moments()
     act = c["phi"] <= 0
-    assert _rel(Ug[:, act], Uo[:, act]) < tol
-    assert _rel(ug[:, act], uo[:, act]) < max(tol, 1e-12) * 10
+    check(Ug, Uo, 2, _tol(precision, sweeps), ug, uo, mask=act, label=f"annulus 48 {precision} sweeps {sweeps}",
+          pops=o.get_f(), steps=90, stress=(c["mu"], c["lam"], 1.0, 10.0, c["omega"]))
     st = g.stats()
     assert st["projections"] == 5 and st["newton_failures"] == 0
 
@@ -194,8 +209,8 @@ def test_sphere_3d_neumann_fp64(T, orc, sweeps):
     Ug, ug, _ = g.moments()
     Uo, uo, _ = o.moments()
     act = c["phi"] <= 0
-    assert _rel(Ug[:, act], Uo[:, act]) < 1e-11
-    assert _rel(ug[:, act], uo[:, act]) < 1e-10
+    check(Ug, Uo, 3, _tol("fp64", sweeps), ug, uo, mask=act, label=f"sphere 24 sweeps {sweeps}", pops=o.get_f(),
+          steps=25, stress=(c["mu"], c["lam"], 1.0, 10.0, c["omega"]))
 
 
 @pytest.mark.parametrize("cfg", ["c2", "c5"])
@@ -262,9 +277,8 @@ def _embedded_pair(T, orc, c, precision, stream=None):
     return g, o
 
 
-@pytest.mark.parametrize("cfg,precision,steps,tol,utol", [
-    ("c2", "fp64", 45, 1e-11, 1e-10), ("c2", "fp32", 45, 1e-5, 1e-4), ("c5", "fp64", 25, 1e-11, 1e-10)])
-def test_full_size_dynamics_matches_oracle(T, orc, cfg, precision, steps, tol, utol):
+@pytest.mark.parametrize("cfg,precision,steps", [("c2", "fp64", 45), ("c2", "fp32", 45), ("c5", "fp64", 25)])
+def test_full_size_dynamics_matches_oracle(T, orc, cfg, precision, steps):
     """The annulus 512^2 and the sphere 192^3 at their full sizes, on a
     non-default stream as the benchmarks run them, through two or three
     projection steps: the whole state against the oracle."""
@@ -277,6 +291,6 @@ def test_full_size_dynamics_matches_oracle(T, orc, cfg, precision, steps, tol, u
     Ug, ug, _ = g.moments()
     Uo, uo, _ = o.moments()
     act = c["phi"] <= 0
-    assert _rel(Ug[:, act], Uo[:, act]) < tol
-    assert _rel(ug[:, act], uo[:, act]) < utol
+    check(Ug, Uo, c["D"], _tol(precision, 20), ug, uo, mask=act, label=f"full size {cfg} {precision}",
+          pops=o.get_f(), steps=steps, stress=(c["mu"], c["lam"], 1.0, 10.0, c["omega"]))
     assert g.stats()["newton_failures"] == 0

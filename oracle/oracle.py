@@ -80,7 +80,7 @@ def lib():
         L.orc_project.argtypes = [C.c_void_p, dp, dp, C.c_double, i64p]
         L.orc_project_anchored.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_double, i64p]
         L.orc_compatible_F.argtypes = [C.c_void_p, dp, dp, dp]
-        L.orc_adjoint.argtypes = [C.c_void_p, C.c_int64, dp, dp, dp, dp, dp]
+        L.orc_adjoint.argtypes = [C.c_void_p, C.c_int64, dp, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -301,20 +301,22 @@ class Sim:
             raise OracleError(st, "moments")
         return U, u, J
 
-    def adjoint(self, n, dLdU=None, dLdu=None):
+    def adjoint(self, n, dLdU=None, dLdu=None, with_dU0=False):
         """Advance n steps from the state of set_state and return
         (dL/d(mu, lambda), dL/dv0 [D][N], dL/du0 [D][N]) for
-        L = sum dLdU . U + dLdu . u over the moments after the last step."""
+        L = sum dLdU . U + dLdu . u over the moments after the last step;
+        with_dU0 appends dL/d dU0 [D][M][N] (the initial gradient data)."""
         gU = None if dLdU is None else _f64(dLdU).reshape(self.M, self.N)
         gu = None if dLdu is None else _f64(dLdu).reshape(self.D, self.N)
         gm = np.zeros(2)
         gv = np.zeros((self.D, self.N))
         g0 = np.zeros((self.D, self.N))
+        gd = np.zeros((self.D, self.M, self.N)) if with_dU0 else None
         st = lib().orc_adjoint(self.h, int(n), None if gU is None else _d(gU), None if gu is None else _d(gu),
-                               _d(gm), _d(gv), _d(g0))
+                               _d(gm), _d(gv), _d(g0), None if gd is None else _d(gd))
         if st:
             raise OracleError(st, "adjoint")
-        return gm, gv, g0
+        return (gm, gv, g0, gd) if with_dU0 else (gm, gv, g0)
 
     def get_f(self):
         f = np.zeros((self.Q, self.M, self.N))

@@ -1984,7 +1984,7 @@ static void neumann_adj(orc_sim *s, const orc_link *L, double th, const double *
 }
 
 int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dLdu, double *grad_mat,
-                double *grad_v0, double *grad_u0) {
+                double *grad_v0, double *grad_u0, double *grad_dU0) {
   int D = s->D, M = s->M, Q = s->Q;
   int64_t N = s->N;
   if (!s->have_state || s->init_step != s->step || !s->U0) return ORC_ERR_ORDER;
@@ -2219,6 +2219,8 @@ int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dL
         for (int a = 0; a < D; ++a) grad_v0[(size_t)a * N + m] = 0.0;
       if (grad_u0)
         for (int a = 0; a < D; ++a) grad_u0[(size_t)a * N + m] = 0.0;
+      if (grad_dU0)
+        for (int k2 = 0; k2 < D * M; ++k2) grad_dU0[(size_t)k2 * N + m] = 0.0;
       if (!s->act[m]) continue;
       double U[MAXM], dA[MAXD * MAXM], f0[MAXQ * MAXM], f1[MAXQ * MAXM];
       const double *l0 = lf + (size_t)m * Q * M;
@@ -2237,6 +2239,17 @@ int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dL
         if (grad_v0) grad_v0[(size_t)a * N + m] = acc - 0.5 * s->dt * lus[m * D + a];
         if (grad_u0) grad_u0[(size_t)a * N + m] = lus[m * D + a];
       }
+      /* the populations are affine in the gradient data dU0 (Eqs. 32-33):
+       * unit differences are exact */
+      if (grad_dU0)
+        for (int k2 = 0; k2 < D * M; ++k2) {
+          double acc = 0.0;
+          dA[k2] += 1.0;
+          init_node(s, s->mu, s->lam, U, dA, b0, f1);
+          dA[k2] -= 1.0;
+          for (int k3 = 0; k3 < Q * M; ++k3) acc += l0[k3] * (f1[k3] - f0[k3]);
+          grad_dU0[(size_t)k2 * N + m] = acc;
+        }
       init_node(s, s->mu + 1.0, s->lam, U, dA, b0, f0);
       init_node(s, s->mu - 1.0, s->lam, U, dA, b0, f1);
       for (int k2 = 0; k2 < Q * M; ++k2) gi[0] += l0[k2] * 0.5 * (f0[k2] - f1[k2]);

@@ -134,12 +134,14 @@ int  orc_project_anchored(orc_sim *s, const double *F, double *u, double t, doub
  * the gradient of L = sum_m dLdU(m).U(m) + dLdu(m).u(m) over the moments
  * after the last step: grad_mat[2] = dL/d(mu, lambda), grad_v0[D][N] =
  * dL/dv0 and grad_u0[D][N] = dL/du0 for the v0 (velocity rows of U0) and u0
- * of orc_set_state (F0 and dU0 held fixed).  dLdU[M][N], dLdu[D][N] and any
- * output may be NULL.  ORC_ERR_ORDER unless the state is the one set by
+ * of orc_set_state (F0 and dU0 held fixed), and grad_dU0[D][M][N] = dL/d dU0,
+ * the gradient with respect to the spatial-gradient data of the
+ * initialisation (Eqs. 32-33; U0 held fixed).  dLdU[M][N], dLdu[D][N] and
+ * any output may be NULL.  ORC_ERR_ORDER unless the state is the one set by
  * orc_set_state. */
 int  orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU,
                  const double *dLdu, double *grad_mat, double *grad_v0,
-                 double *grad_u0);
+                 double *grad_u0, double *grad_dU0);
 /* OpenMP threads used by the oracle */
 int  orc_num_threads(void);
 /* compatible gradient of Eq. 59 (planar in/out) */

@@ -37,9 +37,9 @@ def _make(cfg, mu, lam):
     return o
 
 
-def _loss(cfg, mu, lam, U0, u0, n, wU, wu):
+def _loss(cfg, mu, lam, U0, u0, n, wU, wu, dU0=None):
     o = _make(cfg, mu, lam)
-    o.set_state(U0, u0=u0, dU0=cfg.get("dU0"))
+    o.set_state(U0, u0=u0, dU0=cfg.get("dU0") if dU0 is None else dU0)
     o.step(n)
     U, u, _ = o.moments()
     return float(np.sum(wU * U) + np.sum(wu * u))
@@ -109,10 +109,12 @@ def test_adjoint_matches_finite_differences(name):
     wu = rng.standard_normal((D, N)) * act
     dv = rng.standard_normal((D, N)) * act
     du = rng.standard_normal((D, N)) * act
+    dd = rng.standard_normal((D, M, N)) * act
+    dU0 = cfg.get("dU0", np.zeros((D, M, N)))
     mu, lam = cfg["mu"], cfg["lam"]
     o = _make(cfg, mu, lam)
     o.set_state(U0, u0=u0, dU0=cfg.get("dU0"))
-    gm, gv, g0 = o.adjoint(n, wU, wu)
+    gm, gv, g0, gd = o.adjoint(n, wU, wu, with_dU0=True)
     assert o.stats()["step"] == n
     # the adjoint call leaves the forward state at step n
     U, u, _ = o.moments()
@@ -129,6 +131,9 @@ def test_adjoint_matches_finite_differences(name):
         ("lambda", lambda h: _loss(cfg, mu, lam + h, U0, u0, n, wU, wu), gm[1], 1e-3 * lam),
         ("v0", L_v, float(np.sum(gv * dv)), 1e-3),
         ("u0", lambda h: _loss(cfg, mu, lam, U0, u0 + h * du, n, wU, wu), float(np.sum(g0 * du)), 1e-5),
+        # the initial gradient data enter the second-order initialisation
+        # (Eqs. 32-33) linearly
+        ("dU0", lambda h: _loss(cfg, mu, lam, U0, u0, n, wU, wu, dU0 + h * dd), float(np.sum(gd * dd)), 1e-3),
     ]
     for what, fun, ad, h in checks:
         fd = _richardson(fun, h)

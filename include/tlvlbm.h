@@ -276,6 +276,37 @@ tlvlbm_status tlvlbm_adjoint_step(tlvlbm_ctx *ctx, int64_t n, const double *U0, 
                                   const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
                                   double *grad_u0, int64_t segment);
 
+/* The same reverse mode in two calls, for losses that depend on the final
+ * state (their dLdU, dLdu are known only after the forward run) and for
+ * several gradients of one run:
+ *
+ * tlvlbm_adjoint_record: the first pass of tlvlbm_adjoint_step alone.  From
+ * the state of tlvlbm_set_state (no step since), advance n steps as
+ * tlvlbm_step does, keeping checkpoints and the tape of the final steps
+ * (schedule `segment` as above), and device copies of U0 and dU0 (the arrays
+ * given to tlvlbm_set_state: [M][nodes], [D][M][nodes] or NULL).  The
+ * context ends at step n; tlvlbm_moments reads the final state.
+ *
+ * tlvlbm_adjoint_backward: the reverse pass of the recorded run for
+ * L = sum dLdU . U + dLdu . u over the final moments (as above; either may
+ * be NULL): grad_mat[2] (host) = dL/d(mu, lambda); grad_v0, grad_u0
+ * [D][nodes] as above; grad_dU0 [D][M][nodes] = dL/d dU0, the gradient with
+ * respect to the initial gradient data of the second-order initialisation
+ * (Sec. 2.4, Eqs. 32-33; U0 held fixed).  A caller whose dU0 is a function
+ * of v0 (for instance a difference operator applied to it) obtains the total
+ * velocity gradient as grad_v0 + (that operator)^T grad_dU0.  Any output may
+ * be NULL; outputs are host or device FP64.  Segments are recomputed from
+ * their checkpoints; the context returns to the end of the run, and the
+ * record stays valid: the call may be repeated with other dLdU, dLdu.
+ * TLVLBM_ERR_CALL_ORDER without a record, or when the context changed after
+ * it (a step, a new state, material, boundary condition, level set or body
+ * force).  Every call gives the same result bit for bit as
+ * tlvlbm_adjoint_step on the same inputs. */
+tlvlbm_status tlvlbm_adjoint_record(tlvlbm_ctx *ctx, int64_t n, const double *U0, const double *dU0,
+                                    int64_t segment);
+tlvlbm_status tlvlbm_adjoint_backward(tlvlbm_ctx *ctx, const double *dLdU, const double *dLdu, double *grad_mat,
+                                      double *grad_v0, double *grad_u0, double *grad_dU0);
+
 /* ---- Many instances (project extension, not in the paper) ---------------
  * Independent contexts of the same lattice and precision, sharing one
  * non-default stream, at the same step, each with a level set and state.

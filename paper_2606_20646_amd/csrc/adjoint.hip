@@ -115,6 +115,24 @@ __device__ __forceinline__ void vjp_tangent(const double *F, const double *W, co
   for (int k = 0; k < D * D; ++k) CW[k] *= cf;
 }
 
+// Phi'_A(U)^T x for the flux of Eq. 13 at deformation F: velocity rows
+// -x[F_kA]; deformation rows -dP(F)[x_v (x) e_A] / rho0 (the tangent's major
+// symmetry turns the transpose into the tangent action)
+template <int D>
+__device__ __forceinline__ void flux_T(const double *x, int A, const double *F, const AdjPar &p, double *out) {
+  double W[D * D], CW[D * D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) out[k] = -x[D + k * D + A];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int B = 0; B < D; ++B) W[i * D + B] = (B == A) ? x[i] : 0.0;
+  piola_tangent<D>(F, W, p.mu, p.lam, CW);
+  if (p.k1 != 0.0) fibre_tangent_add<D>(F, W, p.k1, p.a0, CW);
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) out[D + k] = -CW[k] * p.irho;
+}
+
 // lam holds the adjoint populations in their storage type E (register
 // pressure: 2D·M values); the arithmetic is FP64.
 template <int D, typename E>
@@ -787,7 +805,7 @@ __global__ __launch_bounds__(AT) void k_adj_init(const T *__restrict__ Lin, Geo 
                                                  const uint8_t *__restrict__ act, const double *__restrict__ U0,
                                                  const double *__restrict__ dU0, const double *__restrict__ lus,
                                                  double *__restrict__ gv0, double *__restrict__ gu0,
-                                                 double *__restrict__ gblk) {
+                                                 double *__restrict__ gdU0, double *__restrict__ gblk) {
   constexpr int Q = 2 * D, M = D + D * D;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, row = blockIdx.y;
   const int64_t node = x + (int64_t)g.nx * row;
@@ -811,6 +829,32 @@ __global__ __launch_bounds__(AT) void k_adj_init(const T *__restrict__ Lin, Geo 
         const double lu = TRACK ? lus[(size_t)i * g.S + node] : 0.0;
         if (gv0) gv0[(size_t)i * g.N + node] = (1.0 + p.gamma * p.hdt) * G[i] - p.hdt * lu;
         if (gu0) gu0[(size_t)i * g.N + node] = lu;
+      }
+      if (gdU0) {
+        // f_q = feq(U0) - dt/2 feq'_q(U0)[Z_q] with Z_q = B0 - sum_A Phi'_A d_A U0
+        // + c e_qA d_A U0 (Eqs. 32-33) is affine in the gradient data:
+        // dL/d(d_A U0) = -dt/2 sum_q (c e_qA w_q - Phi'_A^T w_q),
+        // w_q = feq'_q^T lam_q = lam_q/(2D) + e_q Phi'_Aq^T lam_q/(2c)
+        double gd[D][M];
+#pragma unroll
+        for (int A = 0; A < D; ++A)
+#pragma unroll
+          for (int r = 0; r < M; ++r) gd[A][r] = 0.0;
+        for (int q = 0; q < Q; ++q) {
+          const int Aq = q / 2;
+          const double sg = (q & 1) ? -1.0 : 1.0;
+          double w[M], t[M];
+          flux_T<D>(lam[q], Aq, F, p, t);
+#pragma unroll
+          for (int r = 0; r < M; ++r) w[r] = lam[q][r] * p.i2D + sg * p.i2c * t[r];
+          for (int A = 0; A < D; ++A) {
+            flux_T<D>(w, A, F, p, t);
+#pragma unroll
+            for (int r = 0; r < M; ++r) gd[A][r] -= p.hdt * ((A == Aq ? p.c * sg * w[r] : 0.0) - t[r]);
+          }
+        }
+        for (int A = 0; A < D; ++A)
+          for (int r = 0; r < M; ++r) gdU0[((size_t)A * M + r) * g.N + node] = gd[A][r];
       }
       if (dU0) {
         double dA[D][M];
@@ -849,6 +893,8 @@ __global__ __launch_bounds__(AT) void k_adj_init(const T *__restrict__ Lin, Geo 
         if (gv0) gv0[(size_t)i * g.N + node] = 0.0;
         if (gu0) gu0[(size_t)i * g.N + node] = 0.0;
       }
+      if (gdU0)
+        for (int k = 0; k < D * (D + D * D); ++k) gdU0[(size_t)k * g.N + node] = 0.0;
     }
   }
   block_acc2(gm, gl, gblk + 2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x));
@@ -1132,17 +1178,24 @@ int stencil_transpose(tlvlbm_ctx *c) {
   return TLVLBM_OK;
 }
 
-template <int D, typename T>
-tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0, const double *dLdU,
-                        const double *dLdu, double *gmat, double *gv0, double *gu0, int64_t seg, std::string &err) {
-  constexpr int Q = 2 * D, M = D + D * D;
+// projection solutions of recorded step k: stored by the first pass (mode 1),
+// replayed by the recomputation (mode 2)
+inline void rec_xs(const AdjRec &rec, int64_t k, TapeStep &tp, int mode) {
+  tp.xs[0] = tp.xs[1] = nullptr;
+  tp.xmode = 0;
+  if (rec.xstore && rec.pidx[k] >= 0) {
+    tp.xs[0] = rec.xstore + (size_t)(2 * rec.pidx[k]) * rec.xslot;
+    tp.xs[1] = rec.xstore + (size_t)(2 * rec.pidx[k] + 1) * rec.xslot;
+    tp.xmode = mode;
+  }
+}
+
+// the launch geometry and flags of a reverse run (the same in the record and
+// the backward call)
+template <int D, typename T> void run_setup(Run &R, tlvlbm_ctx *c) {
   const Geo &g = c->geo;
-  hipStream_t st = c->st;
-  if (!c->arena) c->arena = new AdjArena();
-  Pool pool{c->arena};
-  Run R;
-  R.c = c;
   const Par &pp = c->par;
+  R.c = c;
   R.ap = AdjPar{pp.omega,
                 pp.dt * (2.0 - pp.omega) / (4.0 * D),
                 1.0 / (1.0 + 0.5 * pp.gamma * pp.dt),
@@ -1167,8 +1220,48 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     if (c->bcs[b].type == TLVLBM_BC_NEUMANN_TRACTION) R.neu = true;
     if (c->bcs[b].type == TLVLBM_BC_DIRICHLET_VELOCITY) R.dir = true;
   }
+  R.ts = tape_stride(c);
+  R.cpos = (c->act && c->chunks) ? c->cpos : nullptr;
+}
+
+// sizes of the checkpoint and tape blocks
+struct TapeSizes {
+  size_t plane, dplane, tplane, ck_bytes, tapeu_bytes, tape_bytes, trF_bytes;
+  int64_t nu;
+};
+
+template <int D, typename T> TapeSizes tape_sizes(const Run &R, tlvlbm_ctx *c) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  TapeSizes z;
+  z.plane = (size_t)c->geo.S * sizeof(T);
+  z.dplane = (size_t)c->geo.S * sizeof(double);
+  z.nu = (R.neu && c->stT) ? c->stT->ns : 0;
+  z.tplane = (size_t)R.ts * sizeof(T);
+  z.ck_bytes = (size_t)Q * M * z.plane + (c->track_u ? D * z.dplane : 0);
+  z.tapeu_bytes = (size_t)D * std::max<int64_t>(z.nu, 1) * sizeof(double);
+  z.tape_bytes = (size_t)D * D * z.tplane + (R.neu ? z.tapeu_bytes : 0);
+  z.trF_bytes = (size_t)D * D * z.tplane;
+  return z;
+}
+
+// First pass of the reverse mode: n forward steps from the fresh state with
+// checkpoints of the stored field and the tape of the final steps, leaving
+// the context at step n.  Everything the backward pass needs stays in the
+// context's arena and record.
+template <int D, typename T>
+tlvlbm_status record_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0, int64_t seg,
+                       std::string &err) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const Geo &g = c->geo;
+  hipStream_t st = c->st;
+  if (!c->arena) c->arena = new AdjArena();
+  if (!c->rec) c->rec = new AdjRec();
+  AdjRec &rec = *c->rec;
+  rec.valid = false;
+  Pool pool{c->arena};
+  Run R;
+  run_setup<D, T>(R, c);
   const bool track = c->track_u;
-  const size_t plane = (size_t)g.S * sizeof(T), dplane = (size_t)g.S * sizeof(double);
   // projection tables first: rebuilding them frees the transposed stencils,
   // which the tape below refers to, so no step of this call may rebuild them
   if (c->act && (R.neu || R.dir) && (!c->gauge || c->aux_stale)) {
@@ -1181,16 +1274,10 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     const int s = stencil_transpose(c);
     if (s) return (tlvlbm_status)s;
   }
-  const int64_t nu = (R.neu && c->stT) ? c->stT->ns : 0;
   // tape: F - I of every step and F^r of projection steps in chunk slots
   // (population precision), u at the Neumann stencil nodes (FP64)
-  R.ts = tape_stride(c);
-  R.cpos = (c->act && c->chunks) ? c->cpos : nullptr;
-  const size_t tplane = (size_t)R.ts * sizeof(T);
-  const size_t ck_bytes = (size_t)Q * M * plane + (track ? D * dplane : 0);
-  const size_t tapeu_bytes = (size_t)D * std::max<int64_t>(nu, 1) * sizeof(double);
-  const size_t tape_bytes = (size_t)D * D * tplane + (R.neu ? tapeu_bytes : 0);
-  const size_t trF_bytes = (size_t)D * D * tplane;
+  const TapeSizes z = tape_sizes<D, T>(R, c);
+  const size_t plane = z.plane, dplane = z.dplane;
   const bool has_proj = R.neu && c->proj_every > 0;
   auto nproj_in = [&](int64_t k0, int64_t k1) {
     int64_t np = 0;
@@ -1207,29 +1294,32 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   AdjArena &ar = *c->arena;
   int64_t tail = 0;
   size_t avail = 0;
+  const size_t init_bytes = (size_t)M * g.N * sizeof(double) + (dU0 ? (size_t)D * M * g.N * sizeof(double) : 0);
   if (ar.key[0] != n || ar.key[1] != seg_arg) {
     arena_release(&ar);
-    size_t fixed = 2 * (size_t)Q * M * plane + 2 * (size_t)D * dplane + 2 * ck_bytes;
+    size_t fixed = 2 * (size_t)Q * M * plane + 2 * (size_t)D * dplane + 2 * z.ck_bytes + init_bytes +
+                   (size_t)D * M * dplane;
     if (R.neu) fixed += (size_t)(M + 3 * D * D + 2 * D) * dplane;
-    if (nu) fixed += (size_t)nu * (3 * 8 + 8 * (D + 1)) + (size_t)c->L.n * c->L.kmax * 4;
+    if (z.nu) fixed += (size_t)z.nu * (3 * 8 + 8 * (D + 1)) + (size_t)c->L.n * c->L.kmax * 4;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
     if (seg_arg <= 0 && fr > fixed) {
-      const double per_step = (double)tape_bytes + (has_proj ? (double)trF_bytes / c->proj_every : 0.0);
+      const double per_step = (double)z.tape_bytes + (has_proj ? (double)z.trF_bytes / c->proj_every : 0.0);
       tail = std::min<int64_t>(n, (int64_t)(0.6 * (double)(fr - fixed) / per_step));
       if (seg_arg < 0) tail = std::min<int64_t>(tail, -seg_arg);
       tail = std::max<int64_t>(tail, 0);
     }
     const int64_t head = n - tail;
     if (seg_arg <= 0) {
-      seg = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(head, 1) * (double)ck_bytes / (double)tape_bytes));
+      seg = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(head, 1) * (double)z.ck_bytes /
+                                         (double)z.tape_bytes));
       seg = std::max<int64_t>(1, std::min<int64_t>(seg, std::max<int64_t>(head, 1)));
     }
     const int64_t nck_ = head > 0 ? (head + seg - 1) / seg : 0;
     const int64_t nps = has_proj ? seg / c->proj_every + 2 : 0;
-    size_t need = fixed + (size_t)(nck_ + 1) * ck_bytes + (head > 0 ? (size_t)seg * tape_bytes : 0) +
-                  (head > 0 ? (size_t)nps * trF_bytes : 0) + (size_t)tail * tape_bytes +
-                  (size_t)nproj_in(head, n) * trF_bytes;
+    size_t need = fixed + (size_t)(nck_ + 1) * z.ck_bytes + (head > 0 ? (size_t)seg * z.tape_bytes : 0) +
+                  (head > 0 ? (size_t)nps * z.trF_bytes : 0) + (size_t)tail * z.tape_bytes +
+                  (size_t)nproj_in(head, n) * z.trF_bytes;
     if (fr && need > fr) {
       err = "adjoint: checkpoints and tape do not fit in device memory (lower the step count or pass a segment length)";
       return TLVLBM_ERR_OUT_OF_MEMORY;
@@ -1245,78 +1335,79 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   avail = ar.avail;
   const int64_t head = n - tail;
   const int64_t nck = head > 0 ? (head + seg - 1) / seg : 0;
-  const int64_t nproj_seg = has_proj ? seg / c->proj_every + 2 : 0;
   if (R.neu || R.dir) {
     const int s = ensure_cg(c);
     if (s) return (tlvlbm_status)s;
   }
-  // inputs
-  DevIn dU0d, ddU0, dLU, dLu;
-  if (dU0d.take(U0, (size_t)M * g.N * sizeof(double), st) || ddU0.take(dU0, (size_t)D * M * g.N * sizeof(double), st) ||
-      dLU.take(dLdU, (size_t)M * g.N * sizeof(double), st) || dLu.take(dLdu, (size_t)D * g.N * sizeof(double), st))
-    return TLVLBM_ERR_OUT_OF_MEMORY;
+  // the initial data, kept for the initialisation's transpose
+  {
+    DevIn dU0d, ddU0;
+    if (dU0d.take(U0, (size_t)M * g.N * sizeof(double), st) ||
+        ddU0.take(dU0, (size_t)D * M * g.N * sizeof(double), st))
+      return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (pool.get(&rec.U0, (size_t)M * g.N * sizeof(double), st, false) ||
+        hipMemcpyAsync(rec.U0, dU0d.ptr, (size_t)M * g.N * sizeof(double), hipMemcpyDeviceToDevice, st))
+      return TLVLBM_ERR_OUT_OF_MEMORY;
+    rec.dU0 = nullptr;
+    if (dU0 && (pool.get(&rec.dU0, (size_t)D * M * g.N * sizeof(double), st, false) ||
+                hipMemcpyAsync(rec.dU0, ddU0.ptr, (size_t)D * M * g.N * sizeof(double), hipMemcpyDeviceToDevice,
+                               st)))
+      return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (hipStreamSynchronize(st) != hipSuccess) return TLVLBM_ERR_DEVICE;  // before the DevIn copies go
+  }
   // forward with checkpoints
-  std::vector<void *> ckf(nck + 1, nullptr), cku(nck + 1, nullptr);
+  rec.ckf.assign(nck + 1, nullptr);
+  rec.cku.assign(nck + 1, nullptr);
   for (int64_t s = 0; s <= nck; ++s) {
-    if (pool.get(&ckf[s], (size_t)Q * M * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-    if (track && pool.get(&cku[s], (size_t)D * dplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (pool.get(&rec.ckf[s], (size_t)Q * M * plane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (track && pool.get(&rec.cku[s], (size_t)D * dplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
   }
   auto save = [&](int64_t s) -> bool {
-    if (hipMemcpyAsync(ckf[s], c->fB, (size_t)Q * M * plane, hipMemcpyDeviceToDevice, st)) return false;
-    if (track && hipMemcpyAsync(cku[s], c->ustar, (size_t)D * dplane, hipMemcpyDeviceToDevice, st)) return false;
-    return true;
-  };
-  auto restore = [&](int64_t s) -> bool {
-    if (hipMemcpyAsync(c->fB, ckf[s], (size_t)Q * M * plane, hipMemcpyDeviceToDevice, st)) return false;
-    if (track && hipMemcpyAsync(c->ustar, cku[s], (size_t)D * dplane, hipMemcpyDeviceToDevice, st)) return false;
+    if (hipMemcpyAsync(rec.ckf[s], c->fB, (size_t)Q * M * plane, hipMemcpyDeviceToDevice, st)) return false;
+    if (track && hipMemcpyAsync(rec.cku[s], c->ustar, (size_t)D * dplane, hipMemcpyDeviceToDevice, st)) return false;
     return true;
   };
   // the projection solutions of the first pass are kept (active tiles, FP64)
   // when they fit in a quarter of the free memory, so that the recomputation
   // replays them instead of solving again
   const int64_t nproj = nproj_in(0, head);
-  double *xstore = nullptr;
-  size_t xslot = 0;
+  rec.xstore = nullptr;
+  rec.xslot = 0;
   if (nproj && c->cg.tiles) {
-    xslot = (size_t)D * c->cg.ntiles * 256;
-    const size_t xbytes = (size_t)nproj * 2 * xslot * sizeof(double);
-    if (xbytes <= avail / 4 && pool.get(&xstore, xbytes, st, false)) xstore = nullptr;
+    rec.xslot = (size_t)D * c->cg.ntiles * 256;
+    const size_t xbytes = (size_t)nproj * 2 * rec.xslot * sizeof(double);
+    if (xbytes <= avail / 4 && pool.get(&rec.xstore, xbytes, st, false)) rec.xstore = nullptr;
   }
-  std::vector<int64_t> pidx(n, -1);
+  rec.pidx.assign(n, -1);
   for (int64_t k = 0, p = 0; k < head; ++k)
-    if (is_projection_step(c, k)) pidx[k] = p++;
-  auto xs_of = [&](int64_t k, TapeStep &tp, int mode) {
-    tp.xs[0] = tp.xs[1] = nullptr;
-    tp.xmode = 0;
-    if (xstore && pidx[k] >= 0) {
-      tp.xs[0] = xstore + (size_t)(2 * pidx[k]) * xslot;
-      tp.xs[1] = xstore + (size_t)(2 * pidx[k] + 1) * xslot;
-      tp.xmode = mode;
-    }
-  };
+    if (is_projection_step(c, k)) rec.pidx[k] = p++;
   // the tail's tape, written by the first pass
   char *tailU = nullptr, *tailu = nullptr, *tailF = nullptr;
-  std::vector<TapeStep> ttp((size_t)tail);
+  rec.ttp.assign((size_t)tail, TapeStep{});
   if (tail > 0) {
     const int64_t ntp = nproj_in(head, n);
-    if (pool.get(&tailU, (size_t)tail * D * D * tplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-    if (R.neu && nu && pool.get(&tailu, (size_t)tail * tapeu_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-    if (ntp && pool.get(&tailF, (size_t)ntp * trF_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (pool.get(&tailU, (size_t)tail * D * D * z.tplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (R.neu && z.nu && pool.get(&tailu, (size_t)tail * z.tapeu_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (ntp && pool.get(&tailF, (size_t)ntp * z.trF_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
     int64_t ip = 0;
     for (int64_t k = head; k < n; ++k) {
-      TapeStep &tp = ttp[k - head];
-      tp.U = tailU + (size_t)(k - head) * D * D * tplane;
-      tp.u = (R.neu && nu) ? tailu + (size_t)(k - head) * tapeu_bytes : nullptr;
+      TapeStep &tp = rec.ttp[k - head];
+      tp.U = tailU + (size_t)(k - head) * D * D * z.tplane;
+      tp.u = (R.neu && z.nu) ? tailu + (size_t)(k - head) * z.tapeu_bytes : nullptr;
       tp.un = c->stT ? c->stT->sn : nullptr;
-      tp.nu = nu;
-      tp.Fr = is_projection_step(c, k) ? tailF + (size_t)(ip++) * trF_bytes : nullptr;
+      tp.nu = z.nu;
+      tp.Fr = is_projection_step(c, k) ? tailF + (size_t)(ip++) * z.trF_bytes : nullptr;
     }
   }
+  rec.n = n;
+  rec.seg = seg;
+  rec.tail = tail;
+  rec.nck = nck;
   for (int64_t k = 0; k < n; ++k) {
     if (k < head && k % seg == 0 && !save(k / seg)) return TLVLBM_ERR_DEVICE;
     TapeStep tp{};
-    if (k >= head) tp = ttp[k - head];
-    xs_of(k, tp, 1);
+    if (k >= head) tp = rec.ttp[k - head];
+    rec_xs(rec, k, tp, 1);
     const int s = step_once(c, &tp);
     if (s) return (tlvlbm_status)s;
   }
@@ -1325,6 +1416,40 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     const tlvlbm_status s = check_flag(c);
     if (s) return s;
   }
+  rec.pool_next = pool.next;
+  rec.valid = true;
+  return TLVLBM_OK;
+}
+
+// Backward pass: the gradient of L = sum dLdU . U + dLdu . u over the final
+// moments of the recorded run, with respect to (mu, lambda), v0, u0 and the
+// initial gradient data dU0.  The recorded segments are recomputed from
+// their checkpoints; the context returns to the end of the trajectory.
+template <int D, typename T>
+tlvlbm_status backward_t(tlvlbm_ctx *c, const double *dLdU, const double *dLdu, double *gmat, double *gv0,
+                         double *gu0, double *gdU0, std::string &err) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const Geo &g = c->geo;
+  hipStream_t st = c->st;
+  AdjRec &rec = *c->rec;
+  Pool pool{c->arena};
+  pool.next = rec.pool_next;
+  Run R;
+  run_setup<D, T>(R, c);
+  const bool track = c->track_u;
+  const TapeSizes z = tape_sizes<D, T>(R, c);
+  const size_t plane = z.plane, dplane = z.dplane;
+  const bool has_proj = R.neu && c->proj_every > 0;
+  const int64_t n = rec.n, seg = rec.seg, tail = rec.tail, head = n - tail, nck = rec.nck;
+  const int64_t nproj_seg = has_proj ? seg / c->proj_every + 2 : 0;
+  auto restore = [&](int64_t s) -> bool {
+    if (hipMemcpyAsync(c->fB, rec.ckf[s], (size_t)Q * M * plane, hipMemcpyDeviceToDevice, st)) return false;
+    if (track && hipMemcpyAsync(c->ustar, rec.cku[s], (size_t)D * dplane, hipMemcpyDeviceToDevice, st)) return false;
+    return true;
+  };
+  DevIn dLU, dLu;
+  if (dLU.take(dLdU, (size_t)M * g.N * sizeof(double), st) || dLu.take(dLdu, (size_t)D * g.N * sizeof(double), st))
+    return TLVLBM_ERR_OUT_OF_MEMORY;
   // adjoint buffers
   if (pool.get(&R.La, (size_t)Q * M * plane, st) || pool.get(&R.Lb, (size_t)Q * M * plane, st) ||
       pool.get(&R.lus, (size_t)D * dplane, st) || pool.get(&R.ubc, (size_t)D * dplane, st) ||
@@ -1339,10 +1464,12 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
       return TLVLBM_ERR_OUT_OF_MEMORY;
   }
   if (c->act) {
-    int s = TLVLBM_OK;
-    if (!c->gauge || c->aux_stale) s = proj_aux_build(c);
-    if (!s && !c->stT) s = stencil_transpose(c);
-    if (s) return (tlvlbm_status)s;
+    // (the record builds them when Neumann links exist: no tape refers to
+    // them otherwise, and the projection tables are current)
+    if (!c->stT) {
+      const int s = stencil_transpose(c);
+      if (s) return (tlvlbm_status)s;
+    }
     R.ns = c->stT->ns;
     R.sn = c->stT->sn;
     R.so = c->stT->so;
@@ -1353,9 +1480,9 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   // per-step tape of one segment
   char *tapeU = nullptr, *tapeu = nullptr, *tapeF = nullptr;
   if (head > 0) {
-    if (pool.get(&tapeU, (size_t)seg * D * D * tplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-    if (R.neu && pool.get(&tapeu, (size_t)seg * tapeu_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
-    if (nproj_seg && pool.get(&tapeF, (size_t)nproj_seg * trF_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (pool.get(&tapeU, (size_t)seg * D * D * z.tplane, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (R.neu && pool.get(&tapeu, (size_t)seg * z.tapeu_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (nproj_seg && pool.get(&tapeF, (size_t)nproj_seg * z.trF_bytes, st, false)) return TLVLBM_ERR_OUT_OF_MEMORY;
   }
   // seeds
   {
@@ -1378,9 +1505,9 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
   }
   // the tail in reverse from the first pass's tape, then the head's
   // segments in reverse: recompute with the tape, then reverse each step
-  const int64_t st_proj0 = c->st_proj, st_cg0 = c->st_cg;
+  const int64_t st_proj0 = c->st_proj;
   for (int64_t k = n - 1; k >= head; --k) {
-    const int e = reverse_step<D, T>(R, k, ttp[k - head]);
+    const int e = reverse_step<D, T>(R, k, rec.ttp[k - head]);
     if (e) return (tlvlbm_status)e;
   }
   for (int64_t s = nck - 1; s >= 0; --s) {
@@ -1391,16 +1518,16 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     int64_t ip = 0;
     for (int64_t k = k0; k < k1; ++k) {
       TapeStep &tp = tps[k - k0];
-      tp.U = tapeU + (size_t)(k - k0) * D * D * tplane;
+      tp.U = tapeU + (size_t)(k - k0) * D * D * z.tplane;
       // (no stencil node: no Neumann link reads the displacement)
-      tp.u = (R.neu && R.ns) ? tapeu + (size_t)(k - k0) * tapeu_bytes : nullptr;
+      tp.u = (R.neu && R.ns) ? tapeu + (size_t)(k - k0) * z.tapeu_bytes : nullptr;
       tp.un = R.sn;
       tp.nu = R.ns;
       tp.Fr = nullptr;
-      xs_of(k, tp, 2);
+      rec_xs(rec, k, tp, 2);
       if (is_projection_step(c, k)) {
         if (ip >= nproj_seg) return TLVLBM_ERR_INVALID_ARG;
-        tp.Fr = tapeF + (size_t)(ip++) * trF_bytes;
+        tp.Fr = tapeF + (size_t)(ip++) * z.trF_bytes;
       }
       const int e = step_once(c, &tp);
       if (e) return (tlvlbm_status)e;
@@ -1411,32 +1538,32 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     }
   }
   c->st_proj = st_proj0;  // recomputation is not counted as progress
-  (void)st_cg0;
   // initialisation transpose
-  DevOut ov, ou;
-  if (ov.take(gv0, (size_t)D * g.N * sizeof(double)) || ou.take(gu0, (size_t)D * g.N * sizeof(double)))
+  DevOut ov, ou, od;
+  if (ov.take(gv0, (size_t)D * g.N * sizeof(double)) || ou.take(gu0, (size_t)D * g.N * sizeof(double)) ||
+      od.take(gdU0, (size_t)D * M * g.N * sizeof(double)))
     return TLVLBM_ERR_OUT_OF_MEMORY;
   {
-    const double *u0p = (const double *)dU0d.ptr, *du0p = (const double *)ddU0.ptr;
-    double *pv = (double *)ov.ptr, *pu = (double *)ou.ptr;
+    const double *u0p = rec.U0, *du0p = rec.dU0;
+    double *pv = (double *)ov.ptr, *pu = (double *)ou.ptr, *pd = (double *)od.ptr;
     if (c->act) {
       if (track)
         hipLaunchKernelGGL((k_adj_init<D, T, true, true>), R.grid, R.block, 0, st, (const T *)R.La, g, R.ap, c->act,
-                           u0p, du0p, R.lus, pv, pu, R.ginit);
+                           u0p, du0p, R.lus, pv, pu, pd, R.ginit);
       else
         hipLaunchKernelGGL((k_adj_init<D, T, true, false>), R.grid, R.block, 0, st, (const T *)R.La, g, R.ap, c->act,
-                           u0p, du0p, R.lus, pv, pu, R.ginit);
+                           u0p, du0p, R.lus, pv, pu, pd, R.ginit);
     } else {
       if (track)
         hipLaunchKernelGGL((k_adj_init<D, T, false, true>), R.grid, R.block, 0, st, (const T *)R.La, g, R.ap, c->act,
-                           u0p, du0p, R.lus, pv, pu, R.ginit);
+                           u0p, du0p, R.lus, pv, pu, pd, R.ginit);
       else
         hipLaunchKernelGGL((k_adj_init<D, T, false, false>), R.grid, R.block, 0, st, (const T *)R.La, g, R.ap,
-                           c->act, u0p, du0p, R.lus, pv, pu, R.ginit);
+                           c->act, u0p, du0p, R.lus, pv, pu, pd, R.ginit);
     }
   }
   if (hipGetLastError() != hipSuccess) return TLVLBM_ERR_DEVICE;
-  if (ov.finish(st) || ou.finish(st)) return TLVLBM_ERR_DEVICE;
+  if (ov.finish(st) || ou.finish(st) || od.finish(st)) return TLVLBM_ERR_DEVICE;
   // parameter gradient: fixed-order host sum of the per-block and per-link slots
   std::vector<double> hb(R.nblk * 2), hi(R.nblk * 2), hl((size_t)std::max<int64_t>(c->L.n, 1) * 2);
   if (hipMemcpyAsync(hb.data(), R.gblk, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st) ||
@@ -1458,6 +1585,7 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
     gmat[0] = gsum[0];
     gmat[1] = gsum[1];
   }
+  (void)err;
   return check_flag(c);
 }
 
@@ -1466,39 +1594,89 @@ tlvlbm_status adjoint_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double
 
 using namespace tl;
 
-extern "C" tlvlbm_status tlvlbm_adjoint_step(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0,
-                                        const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
-                                        double *grad_u0, int64_t segment) {
-  if (!c || n < 0 || !U0) return TLVLBM_ERR_INVALID_ARG;
-  if (c->status) return (tlvlbm_status)c->status;
+namespace {
+
+tlvlbm_status adjoint_fail(tlvlbm_ctx *c, tlvlbm_status s, const std::string &err, const char *what) {
+  if (s) {
+    c->status = s;
+    if (c->rec) c->rec->valid = false;
+    try {
+      c->err = err.empty() ? std::string(what) : err;
+    } catch (...) {
+    }
+  }
+  return s;
+}
+
+tlvlbm_status record_call(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0, int64_t segment) {
+  if (!c->have_state || !c->fresh) {
+    c->err = "adjoint: the state must be the one set by tlvlbm_set_state (no step since)";
+    return TLVLBM_ERR_CALL_ORDER;
+  }
+  if (c->bf) {
+    c->err = "adjoint: no reverse mode with a body acceleration";
+    return TLVLBM_ERR_INVALID_ARG;
+  }
   std::string err;
   tlvlbm_status s;
   try {
-    if (!c->have_state || !c->fresh) {
-      c->err = "adjoint: the state must be the one set by tlvlbm_set_state (no step since)";
-      return TLVLBM_ERR_CALL_ORDER;
-    }
-    if (c->bf) {
-      c->err = "adjoint: no reverse mode with a body acceleration";
-      return TLVLBM_ERR_INVALID_ARG;
-    }
     if (c->D == 2)
-      s = c->prec ? adjoint_t<2, double>(c, n, U0, dU0, dLdU, dLdu, grad_mat, grad_v0, grad_u0, segment, err)
-                  : adjoint_t<2, float>(c, n, U0, dU0, dLdU, dLdu, grad_mat, grad_v0, grad_u0, segment, err);
+      s = c->prec ? record_t<2, double>(c, n, U0, dU0, segment, err) : record_t<2, float>(c, n, U0, dU0, segment, err);
     else
-      s = c->prec ? adjoint_t<3, double>(c, n, U0, dU0, dLdU, dLdu, grad_mat, grad_v0, grad_u0, segment, err)
-                  : adjoint_t<3, float>(c, n, U0, dU0, dLdU, dLdu, grad_mat, grad_v0, grad_u0, segment, err);
+      s = c->prec ? record_t<3, double>(c, n, U0, dU0, segment, err) : record_t<3, float>(c, n, U0, dU0, segment, err);
   } catch (...) {
     err = "adjoint: host allocation failed";
     s = TLVLBM_ERR_OUT_OF_MEMORY;
   }
   c->fresh = false;
-  if (s) {
-    c->status = s;
-    try {
-      c->err = err.empty() ? std::string("adjoint failed") : err;
-    } catch (...) {
-    }
+  return adjoint_fail(c, s, err, "adjoint record failed");
+}
+
+tlvlbm_status backward_call(tlvlbm_ctx *c, const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
+                            double *grad_u0, double *grad_dU0) {
+  if (!c->rec || !c->rec->valid || c->step != c->rec->n) {
+    c->err = "adjoint: no recorded run ending at the current state (tlvlbm_adjoint_record, no change since)";
+    return TLVLBM_ERR_CALL_ORDER;
   }
-  return s;
+  std::string err;
+  tlvlbm_status s;
+  try {
+    if (c->D == 2)
+      s = c->prec ? backward_t<2, double>(c, dLdU, dLdu, grad_mat, grad_v0, grad_u0, grad_dU0, err)
+                  : backward_t<2, float>(c, dLdU, dLdu, grad_mat, grad_v0, grad_u0, grad_dU0, err);
+    else
+      s = c->prec ? backward_t<3, double>(c, dLdU, dLdu, grad_mat, grad_v0, grad_u0, grad_dU0, err)
+                  : backward_t<3, float>(c, dLdU, dLdu, grad_mat, grad_v0, grad_u0, grad_dU0, err);
+  } catch (...) {
+    err = "adjoint: host allocation failed";
+    s = TLVLBM_ERR_OUT_OF_MEMORY;
+  }
+  return adjoint_fail(c, s, err, "adjoint backward failed");
+}
+
+}  // namespace
+
+extern "C" tlvlbm_status tlvlbm_adjoint_record(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0,
+                                               int64_t segment) {
+  if (!c || n < 0 || !U0) return TLVLBM_ERR_INVALID_ARG;
+  if (c->status) return (tlvlbm_status)c->status;
+  return record_call(c, n, U0, dU0, segment);
+}
+
+extern "C" tlvlbm_status tlvlbm_adjoint_backward(tlvlbm_ctx *c, const double *dLdU, const double *dLdu,
+                                                 double *grad_mat, double *grad_v0, double *grad_u0,
+                                                 double *grad_dU0) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  if (c->status) return (tlvlbm_status)c->status;
+  return backward_call(c, dLdU, dLdu, grad_mat, grad_v0, grad_u0, grad_dU0);
+}
+
+extern "C" tlvlbm_status tlvlbm_adjoint_step(tlvlbm_ctx *c, int64_t n, const double *U0, const double *dU0,
+                                        const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
+                                        double *grad_u0, int64_t segment) {
+  if (!c || n < 0 || !U0) return TLVLBM_ERR_INVALID_ARG;
+  if (c->status) return (tlvlbm_status)c->status;
+  const tlvlbm_status s = record_call(c, n, U0, dU0, segment);
+  if (s) return s;
+  return backward_call(c, dLdU, dLdu, grad_mat, grad_v0, grad_u0, nullptr);
 }

@@ -264,12 +264,14 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
       if (q) (void)hipFree(q);
     delete c->arena;
   }
+  delete c->rec;
   delete c;
   return TLVLBM_OK;
 }
 
 tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *c, const double *phi, const uint8_t *bid) {
   if (!c || !phi) return TLVLBM_ERR_INVALID_ARG;
+  rec_invalidate(c);
   try {
     if (c->has_ls) return fail(c, TLVLBM_ERR_CALL_ORDER, "level set already set");
     const int64_t N = c->geo.N;
@@ -326,6 +328,7 @@ tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *c, const double *phi, const uint8_
 
 tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *c, uint8_t bid, const tlvlbm_bc *bc) {
   if (!c || !bc) return TLVLBM_ERR_INVALID_ARG;
+  rec_invalidate(c);
   if (bc->type != TLVLBM_BC_DIRICHLET_VELOCITY && bc->type != TLVLBM_BC_NEUMANN_TRACTION)
     return fail(c, TLVLBM_ERR_INVALID_ARG, "unknown boundary type");
   if (bc->ramp < 0 || bc->ramp > 3 || (bc->ramp != TLVLBM_RAMP_CONST && !(bc->T_r > 0)))
@@ -353,6 +356,7 @@ tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *c, uint8_t bid, const tlvlbm_bc *b
 
 tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *c, const double *g, int32_t ramp, double T_r) {
   if (!c) return TLVLBM_ERR_INVALID_ARG;
+  rec_invalidate(c);
   if (ramp < 0 || ramp > 3 || (ramp != TLVLBM_RAMP_CONST && !(T_r > 0)))
     return fail(c, TLVLBM_ERR_INVALID_ARG, "bad ramp");
   try {
@@ -381,12 +385,14 @@ tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *c, const double *g, int32_t ramp
 
 tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *c, const tlvlbm_material *m) {
   if (!c || !material_ok(m)) return TLVLBM_ERR_INVALID_ARG;
+  rec_invalidate(c);
   set_material_par(c->par, m, c->D);
   return TLVLBM_OK;
 }
 
 tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0) {
   if (!c || !U0) return TLVLBM_ERR_INVALID_ARG;
+  rec_invalidate(c);
   try {
     if (!c->has_ls)
       for (int a = 0; a < c->D; ++a)
@@ -460,6 +466,7 @@ tlvlbm_status tlvlbm_step(tlvlbm_ctx *c, int64_t n) {
   if (!c || n < 0) return TLVLBM_ERR_INVALID_ARG;
   if (!c->have_state) return fail(c, TLVLBM_ERR_CALL_ORDER, "step before set_state");
   if (c->status) return (tlvlbm_status)c->status;
+  if (n > 0) rec_invalidate(c);
   for (int64_t k = 0; k < n; ++k) {
     c->fresh = false;
     const int s = step_once(c);
@@ -475,6 +482,7 @@ tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t nctx, int64_t n)
   if (!ctxs || nctx < 1 || n < 0) return TLVLBM_ERR_INVALID_ARG;
   for (int i = 0; i < nctx; ++i) {
     if (!ctxs[i]) return TLVLBM_ERR_INVALID_ARG;
+    rec_invalidate(ctxs[i]);
     if (!ctxs[i]->have_state) return fail(ctxs[i], TLVLBM_ERR_CALL_ORDER, "step before set_state");
     if (ctxs[i]->status) return (tlvlbm_status)ctxs[i]->status;
   }
@@ -531,6 +539,7 @@ tlvlbm_status tlvlbm_get_state(tlvlbm_ctx *c, double *f, double *ustar, int64_t 
 
 tlvlbm_status tlvlbm_put_state(tlvlbm_ctx *c, const double *f, const double *ustar, int64_t step) {
   if (!c || !f || step < 0) return TLVLBM_ERR_INVALID_ARG;
+  rec_invalidate(c);
   {
     const int64_t N = c->geo.N;
     if (c->track_u && !c->ustar) {

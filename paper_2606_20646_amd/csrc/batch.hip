@@ -547,6 +547,8 @@ tlvlbm_status tlvlbm_batch_step(tlvlbm_batch *b, int64_t n) {
   if (!b || n < 0) return TLVLBM_ERR_INVALID_ARG;
   for (auto *c : b->c)
     if (c->status) return bfail(b, (tlvlbm_status)c->status, "an instance holds a sticky error");
+  if (n > 0)
+    for (auto *c : b->c) rec_invalidate(c);
   const int pe = b->proj_every;
   int64_t k = 0;
   while (k < n) {

@@ -150,6 +150,8 @@ struct CG {
   int nblk = 0;
 };
 
+struct AdjRec;  // a recorded forward run of the reverse mode (below)
+
 // Per-instance descriptor of a batched launch (device memory).  fin/fout are
 // swapped on the device at the end of every step, so the ping-pong of every
 // instance needs no upload (and replays correctly from a graph).
@@ -303,6 +305,7 @@ struct tlvlbm_ctx {
   tl::Gauge *gauge = nullptr;  // components without anchors (built on first use)
   tl::StencilT *stT = nullptr; // transposed Neumann stencils (reverse mode, built on first use)
   tl::AdjArena *arena = nullptr; // reverse-mode device memory (kept until destroy or a new shape)
+  tl::AdjRec *rec = nullptr;     // the forward run recorded for the backward pass
   bool aux_stale = true;       // boundary conditions changed since the build
   bool track_u = false;
   hipStream_t st = nullptr;
@@ -384,6 +387,26 @@ struct TapeStep {
   double *xs[2];  // projection solutions of the step (see run_projection)
   int xmode;
 };
+// A forward run recorded by tlvlbm_adjoint_record: the schedule, the arena
+// blocks of its checkpoints, of the tape of its final steps and of the
+// projection solutions, and device copies of the initial data.  Valid until
+// the context changes (a step, a new state, material or boundary, another
+// record); the backward pass leaves it valid.
+struct AdjRec {
+  bool valid = false;
+  int64_t n = 0, seg = 1, tail = 0, nck = 0;
+  size_t pool_next = 0;  // first arena block after the record's
+  std::vector<void *> ckf, cku;
+  std::vector<TapeStep> ttp;
+  double *xstore = nullptr;
+  size_t xslot = 0;
+  std::vector<int64_t> pidx;
+  double *U0 = nullptr, *dU0 = nullptr;
+};
+inline void rec_invalidate(tlvlbm_ctx *c) {
+  if (c->rec) c->rec->valid = false;
+}
+
 // reverse-mode tape planes: one slot per node of the chunk list (embedded
 // bodies) or per node
 inline int64_t tape_stride(const tlvlbm_ctx *c) {

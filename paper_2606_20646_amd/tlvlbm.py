@@ -105,6 +105,8 @@ def _load():
     L.tlvlbm_population_bytes.restype = C.c_size_t
     L.tlvlbm_step_each.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64]
     L.tlvlbm_adjoint_step.argtypes = [vp, C.c_int64, dp, dp, dp, dp, C.POINTER(C.c_double), dp, dp, C.c_int64]
+    L.tlvlbm_adjoint_record.argtypes = [vp, C.c_int64, dp, dp, C.c_int64]
+    L.tlvlbm_adjoint_backward.argtypes = [vp, dp, dp, C.POINTER(C.c_double), dp, dp, dp]
     L.tlvlbm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
     L.tlvlbm_batch_step.argtypes = [vp, C.c_int64]
     L.tlvlbm_batch_set_graph.argtypes = [vp, C.c_int32]
@@ -117,6 +119,7 @@ def _load():
     for name in ("create", "destroy", "set_levelset", "set_boundary", "set_material", "set_state", "step",
                  "moments", "get_state", "put_state", "get_links", "stats", "synchronize", "step_each",
                  "batch_create", "batch_step", "batch_set_graph", "batch_destroy", "adjoint_step",
+                 "adjoint_record", "adjoint_backward",
                  "batch_autotune", "batch_set_tiles", "batch_get_tiles"):
         getattr(L, "tlvlbm_" + name).restype = C.c_int
     return L
@@ -249,6 +252,32 @@ class Solver:
                                           _ptr(args[1])[0], gm, _ptr(gv)[0], _ptr(g0)[0], int(segment)), "adjoint")
         return np.array([gm[0], gm[1]]), gv, g0
 
+    def adjoint_record(self, n, segment=0):
+        """First pass of the reverse mode: n steps from the state of
+        set_state with checkpoints and tape (tlvlbm_adjoint_record)."""
+        U0, dU0 = self._init
+        self._chk(lib.tlvlbm_adjoint_record(self.h, int(n), _ptr(U0)[0], _ptr(dU0)[0], int(segment)),
+                  "adjoint_record")
+
+    def adjoint_backward(self, dLdU=None, dLdu=None, grad_v0=True, grad_u0=True, grad_dU0=False):
+        """Reverse pass of the recorded run (tlvlbm_adjoint_backward): returns
+        (dL/d(mu, lambda), dL/dv0, dL/du0, dL/d dU0).  Output specs as in
+        adjoint(); grad_dU0 True gives a new [D][M][N] numpy array."""
+        gm = (C.c_double * 2)()
+
+        def out(spec, shape):
+            if spec is True:
+                return np.zeros(shape)
+            return spec if spec is not False and spec is not None else None
+
+        gv, g0 = out(grad_v0, (self.D, self.N)), out(grad_u0, (self.D, self.N))
+        gd = out(grad_dU0, (self.D, self.M, self.N))
+        args = [a if (a is None or not isinstance(a, np.ndarray)) else np.ascontiguousarray(a, np.float64)
+                for a in (dLdU, dLdu)]
+        self._chk(lib.tlvlbm_adjoint_backward(self.h, _ptr(args[0])[0], _ptr(args[1])[0], gm, _ptr(gv)[0],
+                                              _ptr(g0)[0], _ptr(gd)[0]), "adjoint_backward")
+        return np.array([gm[0], gm[1]]), gv, g0, gd
+
     def step(self, n=1):
         self._chk(lib.tlvlbm_step(self.h, int(n)), "step")
 
@@ -361,58 +390,83 @@ _RUN_FN = None
 
 
 def _run_fn():
-    """torch.autograd.Function over tlvlbm_step / tlvlbm_adjoint_step (built
-    on first use, so that importing the binding does not import torch)."""
+    """torch.autograd.Function over tlvlbm_adjoint_record /
+    tlvlbm_adjoint_backward (built on first use, so that importing the
+    binding does not import torch)."""
     global _RUN_FN
     if _RUN_FN is not None:
         return _RUN_FN
     import torch
 
+    def f64(t, dev):
+        return t.detach().to(device=dev, dtype=torch.float64).contiguous()
+
+    def ready(dev):
+        # the library works on its own stream: torch's writes must be done
+        if dev.type == "cuda":
+            torch.cuda.current_stream(dev).synchronize()
+
     class _Run(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, mat, v0, solver, n, U0, dU0, segment, fibre):
+        def forward(ctx, mat, v0, dv0, solver, n, U0, dU0, segment, fibre):
+            dev = v0.device
+            D, M, N = solver.D, solver.M, solver.N
             mu, lam = (float(x) for x in mat.detach().to("cpu", torch.float64))
-            U = np.array(U0, np.float64, copy=True)
-            U[: solver.D] = v0.detach().to("cpu", torch.float64).numpy()
+            U = f64(torch.as_tensor(U0), dev).clone()
+            U[:D] = f64(v0, dev)
+            if dU0 is None and dv0 is None:
+                dU = None
+            else:
+                dU = f64(torch.as_tensor(dU0), dev).clone() if dU0 is not None else \
+                    torch.zeros((D, M, N), dtype=torch.float64, device=dev)
+                if dv0 is not None:
+                    dU[:, :D] = f64(dv0, dev)
+            ready(dev)
             solver.set_material(mu, lam, fibre)
-            solver.set_state(U, dU0=dU0)
-            solver.step(n)
-            Uo, uo, _ = solver.moments(J=False)
-            ctx.run = (solver, n, U, dU0, segment, fibre, mu, lam)
-            ctx.devices = (mat.device, v0.device)
-            return torch.from_numpy(Uo).to(v0.device), torch.from_numpy(uo).to(v0.device)
+            solver.set_state(U, dU0=dU)
+            solver.adjoint_record(n, segment=segment)  # the forward, keeping its tape
+            Uo = torch.empty((M, N), dtype=torch.float64, device=dev)
+            uo = torch.empty((D, N), dtype=torch.float64, device=dev)
+            solver.moments_into(U=Uo, u=uo)
+            ctx.run = (solver, dU is not None and dv0 is not None)
+            ctx.devices = (mat.device, dev)
+            return Uo, uo
 
         @staticmethod
         def backward(ctx, gU, gu):
-            solver, n, U, dU0, segment, fibre, mu, lam = ctx.run
-
-            def host(t):
-                if t is None:
-                    return None
-                a = t.detach().to("cpu", torch.float64).contiguous().numpy()
-                return a if np.any(a) else None
-
-            # the reverse mode restarts from the initial state of the forward
-            solver.set_material(mu, lam, fibre)
-            solver.set_state(U, dU0=dU0)
-            gm, gv, _ = solver.adjoint(n, host(gU), host(gu), segment=segment, grad_v0=True, grad_u0=False)
+            solver, want_d = ctx.run
+            dev = ctx.devices[1]
+            D, M, N = solver.D, solver.M, solver.N
+            gv = torch.empty((D, N), dtype=torch.float64, device=dev)
+            gd = torch.empty((D, M, N), dtype=torch.float64, device=dev) if want_d else None
+            gU = None if gU is None else f64(gU, dev)
+            gu = None if gu is None else f64(gu, dev)
+            ready(dev)
+            gm, _, _, _ = solver.adjoint_backward(gU, gu, grad_v0=gv, grad_u0=False,
+                                                  grad_dU0=gd if want_d else False)
             gmat = torch.tensor(gm, dtype=torch.float64, device=ctx.devices[0])
-            gv0 = torch.from_numpy(gv).to(ctx.devices[1])
-            return gmat, gv0, None, None, None, None, None, None
+            gdv = gd[:, :D].contiguous() if want_d else None
+            return gmat, gv, gdv, None, None, None, None, None, None
 
     _RUN_FN = _Run
     return _Run
 
 
-def run_differentiable(solver, mat, v0, n, U0, dU0=None, segment=0, fibre=None):
+def run_differentiable(solver, mat, v0, n, U0, dU0=None, segment=0, fibre=None, dv0=None):
     """Differentiable run of n steps for torch autograd.
 
     mat: tensor (mu, lambda) [2]; v0: tensor [D][nodes], the velocity rows of
     the initial state; U0: the initial state [M][nodes] (its F rows are used,
-    its velocity rows replaced by v0); dU0: its gradients as for set_state.
-    Returns (U, u) after n steps as float64 tensors on v0's device.  The
-    backward pass calls tlvlbm_adjoint_step from the same initial state (one
-    more forward, then the reverse) and returns dL/d(mu, lambda) and dL/dv0;
-    the solver's boundary conditions and level set stay as set by the caller.
-    Every step runs in the library's kernels; this is argument marshalling."""
-    return _run_fn().apply(mat, v0, solver, int(n), U0, dU0, int(segment), fibre)
+    its velocity rows replaced by v0); dU0: its gradients [D][M][nodes] as for
+    set_state (or None); dv0: optional tensor [D][D][nodes], dv0[A][i] =
+    d v0_i / d X_A, replacing the velocity rows of dU0 and receiving its own
+    gradient (build it from v0 with differentiable torch operations, and
+    autograd carries dL/d dv0 back to v0: the initial velocity and its
+    gradient then stay consistent).  Returns (U, u) after n steps as float64
+    tensors on v0's device.  The forward is tlvlbm_adjoint_record (the run,
+    with its checkpoints and tape) and the backward tlvlbm_adjoint_backward:
+    no second forward and no host copies (device tensors stay on the device).
+    The solver's boundary conditions and level set stay as set by the caller;
+    it must not be stepped between forward and backward.  Every step runs in
+    the library's kernels; this is argument marshalling."""
+    return _run_fn().apply(mat, v0, dv0, solver, int(n), U0, dU0, int(segment), fibre)

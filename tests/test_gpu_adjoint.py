@@ -66,12 +66,17 @@ def test_adjoint_matches_oracle(T, orc, name, precision, tol):
     u0 = cfg.get("u0")
     o = _make(cfg, cfg["mu"], cfg["lam"])
     o.set_state(cfg["U0"], u0=u0, dU0=cfg.get("dU0"))
-    gm_o, gv_o, g0_o = o.adjoint(n, wU, wu)
+    gm_o, gv_o, g0_o, gd_o = o.adjoint(n, wU, wu, with_dU0=True)
     s = _solver(T, cfg, precision)
     s.set_state(cfg["U0"], u0=u0, dU0=cfg.get("dU0"))
-    gm, gv, g0 = s.adjoint(n, wU, wu)
+    # the two-call reverse mode: record the run, then the backward pass
+    s.adjoint_record(n)
     assert s.stats()["step"] == n
-    print(f"mu,lam: gpu {gm} oracle {gm_o}; v0 rel {_rel(gv, gv_o):.2e}; u0 rel {_rel(g0, g0_o):.2e}", flush=True)
+    gm, gv, g0, gd = s.adjoint_backward(wU, wu, grad_dU0=True)
+    assert s.stats()["step"] == n
+    print(f"mu,lam: gpu {gm} oracle {gm_o}; v0 rel {_rel(gv, gv_o):.2e}; u0 rel {_rel(g0, g0_o):.2e}; "
+          f"dU0 rel {_rel(gd, gd_o):.2e}", flush=True)
+    assert _rel(gd, gd_o) <= tol
     scale = np.abs(gm_o).max()
     assert np.all(np.abs(gm - gm_o) <= tol * scale)
     assert _rel(gv, gv_o) <= tol
@@ -108,6 +113,33 @@ def test_adjoint_segments_agree(T, name):
         assert np.array_equal(gm, out[0][0])
         assert np.array_equal(gv, out[0][1])
         assert np.array_equal(g0, out[0][2])
+
+
+def test_record_backward_repeat_and_order(T):
+    """The backward pass can be repeated on one record (same gradients bit
+    for bit as the one-call reverse mode); any step after the record makes
+    the backward refuse."""
+    _say("adjoint record/backward repeat neumann_annulus_projection fp64")
+    make, n = CASES["neumann_annulus_projection"]
+    cfg = make()
+    wU, wu = _weights(cfg)
+    s = _solver(T, cfg, "fp64")
+    s.set_state(cfg["U0"], u0=cfg.get("u0"), dU0=cfg.get("dU0"))
+    s.adjoint_record(n)
+    a = s.adjoint_backward(wU, wu)
+    b = s.adjoint_backward(wU, wu)
+    r = _solver(T, cfg, "fp64")
+    r.set_state(cfg["U0"], u0=cfg.get("u0"), dU0=cfg.get("dU0"))
+    c = r.adjoint(n, wU, wu)
+    for x, y, z in zip(a[:3], b[:3], c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    U1, u1, _ = s.moments()
+    U2, u2, _ = r.moments()
+    assert np.array_equal(U1, U2) and np.array_equal(u1, u2)
+    s.step(1)
+    with pytest.raises(T.TlvlbmError) as e:
+        s.adjoint_backward(wU, wu)
+    assert e.value.code == T.ERR_CALL_ORDER
 
 
 def test_adjoint_requires_fresh_state(T):
@@ -161,3 +193,54 @@ def test_autograd_function_matches_adjoint(T):
     assert np.array_equal(U.detach().numpy(), Ur) and np.array_equal(u.detach().numpy(), ur)
     assert np.array_equal(mat.grad.numpy(), gm)
     assert np.array_equal(v0.grad.numpy(), gv)
+
+
+def test_autograd_with_consistent_initial_gradient(T):
+    """Device tensors end to end, with the initial velocity gradient built
+    from v0 by a torch difference operator: autograd's dL/dv0 (through
+    dL/dv0 and dL/d dv0) matches central differences of runs in which v0 and
+    its gradient move together.  The partial dL/dv0 at fixed dv0 does not."""
+    import torch
+    _say("autograd with dv0 = grad(v0) periodic2d_damped fp64 (device tensors)")
+    make, n = CASES["periodic2d_damped"]
+    cfg = make()
+    D, N = cfg["D"], int(np.prod(cfg["n"]))
+    nx, ny = cfg["n"]
+    dx = cfg["dx"]
+    dev = torch.device("cuda")
+    wU, wu = (torch.from_numpy(w).to(dev) for w in _weights(cfg))
+
+    def grad_op(v):  # periodic central differences: [A][i][nodes]
+        vv = v.reshape(D, ny, nx)
+        gx = (torch.roll(vv, -1, 2) - torch.roll(vv, 1, 2)) / (2 * dx)
+        gy = (torch.roll(vv, -1, 1) - torch.roll(vv, 1, 1)) / (2 * dx)
+        return torch.stack([gx.reshape(D, N), gy.reshape(D, N)])
+
+    mat = torch.tensor([cfg["mu"], cfg["lam"]], dtype=torch.float64, device=dev)
+    s = _solver(T, cfg, "fp64")
+
+    def loss(v, dv=True):
+        U, u = T.run_differentiable(s, mat, v, n, cfg["U0"], dU0=cfg["dU0"], dv0=grad_op(v) if dv else None)
+        return (wU * U).sum() + (wu * u).sum()
+
+    v0 = torch.tensor(cfg["U0"][:D], device=dev, requires_grad=True)
+    loss(v0).backward()
+    g_total = v0.grad.clone()
+    v1 = torch.tensor(cfg["U0"][:D], device=dev, requires_grad=True)
+    loss(v1, dv=False).backward()
+    g_partial = v1.grad.clone()
+    rng = np.random.default_rng(4)
+    delta = torch.from_numpy(rng.standard_normal((D, N))).to(dev)
+    base = torch.tensor(cfg["U0"][:D], device=dev)
+    with torch.no_grad():
+        def L(h):
+            return float(loss(base + h * delta))
+        h = 1e-3
+        d1 = (L(h) - L(-h)) / (2 * h)
+        d2 = (L(h / 2) - L(-h / 2)) / h
+        fd = (4 * d2 - d1) / 3
+    ad = float((g_total * delta).sum())
+    ap = float((g_partial * delta).sum())
+    print(f"total {ad} partial {ap} fd {fd}", flush=True)
+    assert abs(ad - fd) <= 1e-7 * abs(fd)
+    assert abs(ap - fd) > 100 * abs(ad - fd)

@@ -10,8 +10,14 @@ resident in HBM before the timed region.
 
 Prints one JSON line:  metric MLUPS (active node updates per second / 1e6),
 roofline of the bulk kernel (576 algorithmic bytes per node-step against the
-8 TB/s HBM peak, kernel time from HIP events on the library's stream), and the
-FP64 CPU oracle timed on a bounded sample of the same recipe.
+8 TB/s HBM peak, kernel time from HIP events on the library's stream), the
+FP64 CPU oracle timed on a bounded sample of the same recipe, and the other
+two parts of the metric measured in the same run: "adjoint_over_forward"
+(the embedded sphere 192^3, 4000 steps, the surface-misfit loss: reverse-mode
+time over forward time, with central-difference checks of dL/dmu, dL/dlambda
+and an initial-velocity direction) and "batched_speedup" (64 random-hole 2D
+instances, 2000 steps: per-instance launches over the batched launch).
+--no-extras prints the headline alone.
 
     python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--n 256]
 
@@ -22,7 +28,8 @@ Other workloads (one JSON line each; not the headline):
     --workload c4   64 embedded 2D instances: batched launch against
                     per-instance launches of the same kernels
     --workload c5   embedded sphere 192^3 (+frame), Neumann surface: reverse
-                    mode (forward + recomputation + reverse) over forward time
+                    mode (record + backward) over forward time, surface misfit
+                    against a target at mu* = 1.3, lambda* = 6
     --workload ellipsoid / shell / annulus / affine
                     the analytic benchmarks end to end (rotated ellipsoid
                     with affine Dirichlet data, N = 320; spherical shell under
@@ -111,16 +118,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 1000; c2 20000, c4 40, c5 200)")
+                    help="timed steps (default: 1000; c2 20000, c4 2000, c5 4000)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=None,
                     help="grid cells per axis (c3 256, ellipsoid 320, shell 200)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "ellipsoid", "shell", "annulus", "affine", "tube"], default="c3")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--fd", action="store_true",
-                    help="c5: check dL/dmu against Richardson-extrapolated central differences of the forward")
-    ap.add_argument("--fd-h", type=float, default=1e-2, help="c5 --fd: relative step of mu")
+    ap.add_argument("--no-fd", action="store_true", help="c5: skip the central-difference checks")
+    ap.add_argument("--fd-h", type=float, default=1e-3, help="c5: relative step of the central differences")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: skip the reverse-mode and batched parts of the metric")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -202,6 +210,10 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(nodes)},
         "cpu_baseline": cpu,
     }
+    if not args.no_extras:
+        # the other two parts of the metric, measured in the same run
+        out["adjoint_over_forward"] = c5_measure(4000)
+        out["batched_speedup"] = c4_measure(2000)
     print(json.dumps(out), flush=True)
 
 
@@ -258,23 +270,23 @@ def bench_c2(args):
              "projections": st["projections"], "J_range": [float(J[act].min()), float(J[act].max())]})
 
 
-def bench_c4(args):
+def c4_measure(steps=2000, steps_exact=40):
     """64 instances of the random-hole 2D recipe (64^2 .. 512^2), FP32: the
     batched launch against per-instance launches of the same kernels over
-    2000 steps (the recipe's length) with the default projection (Jacobi
-    sweeps); beside it, 40 steps with the exact projection
-    (multigrid-preconditioned CG)."""
+    `steps` steps (the recipe's 2000 by default) with the default projection
+    (Jacobi sweeps); beside it, `steps_exact` steps with the exact projection
+    (multigrid-preconditioned CG).  Returns the speedup record."""
     import numpy as np
     import torch
 
     import workloads as W
     from paper_2606_20646_amd import tlvlbm as T
-    steps = args.steps or 2000
-    steps_exact = min(steps, 40)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
     cfgs = [W.config_c4_instance(k) for k in range(64)]
     nodes = sum(int((c["phi"] <= 0).sum()) for c in cfgs)
+    log(f"[c4] 64 instances, {nodes} active nodes: inputs in {time.perf_counter() - t0:.1f} s")
 
     def build(sweeps, mg):
         out = []
@@ -309,96 +321,169 @@ def bench_c4(args):
         bt.step(20)
         tb = timed(lambda: bt.step(steps))
         bt.close()
-        err = max(float(np.linalg.norm(a.moments()[0] - b.moments()[0]) / np.linalg.norm(a.moments()[0]))
-                  for a, b in zip(A, B))
+        err = 0.0
+        for a, b, c in zip(A, B, cfgs):
+            act = c["phi"] <= 0
+            Ua, Ub = a.moments()[0][:, act], b.moments()[0][:, act]
+            err = max(err, float(np.linalg.norm(Ua[:2] - Ub[:2]) / np.linalg.norm(Ua[:2])),
+                      float(np.linalg.norm(Ua[2:] - Ub[2:]) / np.linalg.norm(Ua[2:] - np.eye(2).reshape(-1, 1))))
+        for x in A + B:
+            x.close()
         return ta, tb, err, tiles
 
     ta, tb, err, tiles = compare(20, False, steps)
+    log(f"[c4] {steps} steps: per-instance {ta:.3f} s, batched {tb:.3f} s")
     tc, te, err_mg, _ = compare(0, True, steps_exact)
-    _common("batched speedup over per-instance launches of the same kernels", round(ta / tb, 3), "x", steps, 0,
-            round(tb * 1e3 / steps, 4), True, "f32",
-            f"64 embedded D2Q4x6 instances (random holes, 64^2..512^2), {nodes} active nodes, "
-            f"projection every 20 steps (20 damped Jacobi sweeps in both paths)",
-            {"per_instance_s": round(ta, 4), "batched_s": round(tb, 4),
-             "per_instance_MLUPS": round(nodes * steps / ta / 1e6, 1),
-             "batched_MLUPS": round(nodes * steps / tb / 1e6, 1), "max_rel_state_diff": err,
-             "tiles": {"width": tiles[0], "order": tiles[1],
-                       "ms_per_bulk_launch": {f"order{o}_w{w}": round(v, 4) for (o, w), v in tiles[2].items()}},
-             "exact_projection_multigrid_cg": {"steps": steps_exact, "per_instance_s": round(tc, 4),
-                                               "batched_s": round(te, 4),
-                                               "speedup": round(tc / te, 3), "max_rel_state_diff": err_mg}})
+    return {"value": round(ta / tb, 3), "unit": "x (per-instance time / batched time)", "steps": steps,
+            "workload": f"64 embedded D2Q4x6 instances (random holes, 64^2..512^2), {nodes} active nodes, "
+                        f"FP32, projection every 20 steps (20 damped Jacobi sweeps in both paths)",
+            "per_instance_s": round(ta, 4), "batched_s": round(tb, 4),
+            "per_instance_MLUPS": round(nodes * steps / ta / 1e6, 1),
+            "batched_MLUPS": round(nodes * steps / tb / 1e6, 1),
+            "max_rel_diff_v_and_F_minus_I": err,
+            "tiles": {"width": tiles[0], "order": tiles[1],
+                      "ms_per_bulk_launch": {f"order{o}_w{w}": round(v, 4) for (o, w), v in tiles[2].items()}},
+            "exact_projection_multigrid_cg": {"steps": steps_exact, "per_instance_s": round(tc, 4),
+                                              "batched_s": round(te, 4), "speedup": round(tc / te, 3),
+                                              "max_rel_diff_v_and_F_minus_I": err_mg}}
 
 
-def bench_c5(args):
-    """Embedded sphere R = 0.35 on 192^3 (+frame), traction-free, v0 = 1e-2
-    Fourier modes, FP32; L = sum dLdu . u after n steps."""
+def bench_c4(args):
+    r = c4_measure(args.steps or 2000)
+    _common("batched speedup over per-instance launches of the same kernels", r["value"], "x", r["steps"], 0,
+            round(r["batched_s"] * 1e3 / r["steps"], 4), True, "f32", r["workload"],
+            {k: v for k, v in r.items() if k not in ("value", "unit", "steps", "workload")})
+
+
+def c5_measure(steps=4000, precision="fp32", fd=True, fd_h=1e-3):
+    """The differentiation configuration: embedded sphere R = 0.35 on 192^3
+    (+frame), traction-free, v0 = 1e-2 Fourier modes.  Loss
+    L = 1/2 sum_{surface nodes} |u - u*|^2 after `steps` steps, u* the final
+    displacement of a forward run at mu* = 1.3, lambda* = 6 (FP64).  Times the
+    forward (tlvlbm_step) and the reverse mode (tlvlbm_adjoint_record +
+    tlvlbm_adjoint_backward: forward with checkpoints and tape, recomputation,
+    reverse) in `precision`; with fd, checks dL/dmu, dL/dlambda and the
+    derivative along a smooth initial-velocity direction (v0 and its
+    gradient moved together) against central differences (relative step
+    fd_h) of FP64 forward runs.  Inputs stay in HBM."""
     import numpy as np
     import torch
 
     import workloads as W
     from paper_2606_20646_amd import tlvlbm as T
-    steps = args.steps or 200
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
     c = W.config_c5(192)
+    rng = np.random.default_rng(77)
+    dvh, ddvh = W.fourier_velocity(c["X"], W.fourier_modes(rng, 3), 1e-2)
+    log(f"[c5] inputs in {time.perf_counter() - t0:.1f} s")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64)).cuda()  # noqa: E731
+    U0d, dU0d, dvd, ddvd = dev(c["U0"]), dev(c["dU0"]), dev(dvh), dev(ddvh)
+    act = torch.from_numpy(c["phi"] <= 0).cuda()
 
-    # inputs resident in HBM: the initial state, its gradients and the loss
-    # weights cross the ABI as device pointers (no PCIe traffic in the timing)
-    U0d = torch.from_numpy(np.ascontiguousarray(c["U0"], np.float64)).cuda()
-    dU0d = torch.from_numpy(np.ascontiguousarray(c["dU0"], np.float64)).cuda()
-
-    def mk(mu=c["mu"], precision=args.precision):
-        s = T.Solver(3, c["n"], c["dx"], c["dt"], mu, c["lam"], omega=c["omega"], origin=c["origin"],
-                     periodic_mask=0, proj_every=c["proj_every"], precision=precision, stream=stream.cuda_stream)
+    def mk(mu, lam, prec, U0=U0d, dU0=dU0d):
+        s = T.Solver(3, c["n"], c["dx"], c["dt"], mu, lam, omega=c["omega"], origin=c["origin"],
+                     periodic_mask=0, proj_every=c["proj_every"], precision=prec, stream=stream.cuda_stream)
         s.set_levelset(c["phi"], c["bid"])
         s.set_boundary(1, "neumann")
-        s.set_state(U0d, dU0=dU0d)
+        torch.cuda.synchronize()  # device inputs written by torch on its own stream
+        s.set_state(U0, dU0=dU0)
         return s
 
-    act = c["phi"] <= 0
-    if args.fd:
-        # a smooth functional: L = sum u_ref . u with u_ref the forward's own
-        # final displacement (no cancellation, so differences resolve it)
-        s = mk()
-        s.step(steps)
-        wu = s.moments()[1] * act
-        del s
-    else:
-        wu = np.random.default_rng(1).standard_normal((3, act.size)) * act
-    wud = torch.from_numpy(np.ascontiguousarray(wu, np.float64)).cuda()
-    gvd = torch.zeros((3, act.size), dtype=torch.float64, device="cuda")
-    s = mk()
-    s.adjoint(steps, None, wud, grad_v0=gvd, grad_u0=False)  # one-time tables and device memory of this shape
+    def final_u(s):
+        u = torch.empty((3, act.numel()), dtype=torch.float64, device="cuda")
+        s.moments_into(u=u)
+        return u
+
+    s = mk(1.3, 6.0, "fp64")
+    s.step(steps)
+    us = final_u(s)
+    S = torch.zeros(act.numel(), dtype=torch.bool, device="cuda")
+    S[torch.from_numpy(s.links()["node"]).cuda()] = True
+    s.close()
+    log(f"[c5] target at mu*=1.3, lambda*=6: {steps} steps")
+
+    def loss_of(u):
+        return 0.5 * float((((u - us) * S) ** 2).sum())
+
+    s = mk(c["mu"], c["lam"], precision)
+    # one untimed reverse run: one-time tables and the device memory of this shape
+    s.adjoint_record(steps)
+    dLdu = (final_u(s) - us) * S
+    torch.cuda.synchronize()
+    s.adjoint_backward(None, dLdu, grad_v0=False, grad_u0=False)
     s.set_state(U0d, dU0=dU0d)
     torch.cuda.synchronize()
     t = time.perf_counter()
     s.step(steps)
     torch.cuda.synchronize()
     tf = time.perf_counter() - t
+    L0 = loss_of(final_u(s))
+    gv = torch.empty((3, act.numel()), dtype=torch.float64, device="cuda")
+    gd = torch.empty((3, 12, act.numel()), dtype=torch.float64, device="cuda")
     s.set_state(U0d, dU0=dU0d)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    gm, gv, g0 = s.adjoint(steps, None, wud, grad_v0=gvd, grad_u0=False)
+    s.adjoint_record(steps)
     torch.cuda.synchronize()
-    ta = time.perf_counter() - t
-    extra = {"forward_s": round(tf, 4), "adjoint_s": round(ta, 4), "dL_dmu_dlambda": [float(gm[0]), float(gm[1])]}
-    if args.fd:
-        # reference: Richardson-extrapolated central differences of FP64
-        # forward runs (FP32 runs would bury the difference in rounding)
-        def L(mu):
-            s = mk(mu, "fp64")
-            s.step(steps)
-            return float(np.sum(wu * s.moments()[1]))
-        h = args.fd_h * c["mu"]
-        d1 = (L(c["mu"] + h) - L(c["mu"] - h)) / (2 * h)
-        d2 = (L(c["mu"] + h / 2) - L(c["mu"] - h / 2)) / h
-        fd = (4 * d2 - d1) / 3
-        extra["fd_dL_dmu"] = fd
-        extra["fd_rel_err"] = abs(fd - float(gm[0])) / abs(fd)
-    _common("reverse-mode time / forward time", round(ta / tf, 3), "ratio", steps, 0, round(ta * 1e3 / steps, 4),
-            False, "f32" if args.precision == "fp32" else "f64",
-            f"D3Q6x12 sphere 192^3+frame, {int(act.sum())} active nodes, traction free, projection every 20 steps, "
-            f"{args.precision}", extra)
+    tr = time.perf_counter() - t
+    dLdu = (final_u(s) - us) * S
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    gm, _, _, _ = s.adjoint_backward(None, dLdu, grad_v0=gv, grad_u0=False, grad_dU0=gd)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    s.close()
+    ad_v = float((gv * dvd).sum() + (gd[:, :3] * ddvd).sum())
+    log(f"[c5] forward {tf:.3f} s, record {tr:.3f} s, backward {tb:.3f} s")
+    out = {"value": round((tr + tb) / tf, 3), "unit": "ratio (reverse mode time / forward time)", "steps": steps,
+           "workload": f"D3Q6x12 sphere 192^3+frame, {int(act.sum())} active nodes, traction free, projection "
+                       f"every 20 steps, {precision}; L = 1/2 sum over {int(S.sum())} surface nodes of |u - u*|^2, "
+                       f"u* from mu*=1.3 lambda*=6",
+           "forward_s": round(tf, 4), "record_s": round(tr, 4), "backward_s": round(tb, 4), "loss": L0,
+           "grad": {"mu": float(gm[0]), "lambda": float(gm[1]), "v0_direction": ad_v}}
+    if fd:
+        def L(mu, lam, h=0.0):
+            U0, dU0 = U0d, dU0d
+            if h:
+                U0, dU0 = U0d.clone(), dU0d.clone()
+                U0[:3] += h * dvd
+                dU0[:, :3] += h * ddvd
+            r = mk(mu, lam, "fp64", U0, dU0)
+            r.step(steps)
+            val = loss_of(final_u(r))
+            r.close()
+            return val
+
+        mu, lam = c["mu"], c["lam"]
+        # central differences at h and h/2; their Richardson combination
+        # removes the O(h^2) truncation (the loss follows waves over 4000
+        # steps: at h = 1e-3 the truncation alone is ~1e-4 relative)
+        fns = {"mu": (lambda e: L(mu * (1 + e), lam), mu),
+               "lambda": (lambda e: L(mu, lam * (1 + e)), lam),
+               "v0_direction": (lambda e: L(mu, lam, e), 1.0)}
+        cd, rich = {}, {}
+        for k, (fn, scale) in fns.items():
+            d1 = (fn(fd_h) - fn(-fd_h)) / (2 * fd_h * scale)
+            d2 = (fn(fd_h / 2) - fn(-fd_h / 2)) / (fd_h * scale)
+            cd[k] = d1
+            rich[k] = (4 * d2 - d1) / 3
+        out["fd_h"] = fd_h
+        out["fd_central"] = cd
+        out["fd_richardson"] = rich
+        out["fd_rel_err"] = {k: abs(out["grad"][k] - v) / abs(v) for k, v in rich.items()}
+        out["fd_central_rel_err"] = {k: abs(out["grad"][k] - v) / abs(v) for k, v in cd.items()}
+        log(f"[c5] central differences {cd}, Richardson {rich}; relative errors {out['fd_rel_err']}")
+    return out
+
+
+def bench_c5(args):
+    r = c5_measure(args.steps or 4000, args.precision, fd=not args.no_fd, fd_h=args.fd_h)
+    _common("reverse-mode time / forward time", r["value"], "ratio", r["steps"], 0,
+            round((r["record_s"] + r["backward_s"]) * 1e3 / r["steps"], 4), False,
+            "f32" if args.precision == "fp32" else "f64", r["workload"],
+            {k: v for k, v in r.items() if k not in ("value", "unit", "steps", "workload")})
 
 
 def _embedded_solver(T, c, precision, stream, dU0=True):

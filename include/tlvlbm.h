@@ -324,7 +324,9 @@ tlvlbm_status tlvlbm_adjoint_backward(tlvlbm_ctx *ctx, const double *dLdU, const
  * in use are not allowed (the batch keeps its own copy of their buffer
  * roles).  Results equal the per-instance path up to floating-point
  * summation order.  Errors of any instance are reported (and made sticky on
- * that context). */
+ * that context).  The projection phases run over every instance, so either
+ * all instances have Neumann links or none has (TLVLBM_ERR_INVALID_ARG for a
+ * mixed set: the projection belongs to lattices with Neumann links only). */
 typedef struct tlvlbm_batch tlvlbm_batch;
 tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t n, int64_t steps);
 tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_batch **out);

@@ -346,6 +346,7 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
     b->use_graph = b->st != nullptr;  // no stream capture on the legacy default stream
     std::vector<Seg> segs;
     std::vector<int4> bt, ct, lt;
+    int n_neu = 0;  // instances with Neumann links (those the projection runs on)
     for (int k = 0; k < n; ++k) {
       tlvlbm_ctx *c = ctxs[k];
       if (!c || c->D != b->D || c->prec != b->prec || c->st != b->st || c->proj_every != b->proj_every ||
@@ -403,9 +404,11 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
         b->act.push_back(std::move(a));
       }
       for (int blk = 0; blk < c->cg.nblk; ++blk) ct.push_back(make_int4(k, blk, 0, 0));
+      bool inst_neu = false;
       for (int bid = 0; bid < 256; ++bid) {
         const int64_t b0 = c->bid_begin[bid], b1 = c->bid_end[bid];
         if (b1 <= b0) continue;
+        if (c->bcs[bid].type == TLVLBM_BC_NEUMANN_TRACTION) inst_neu = true;
         Seg s{};
         s.inst = k;
         s.type = c->bcs[bid].type;
@@ -417,7 +420,15 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
         for (int64_t o = 0; o < b1 - b0; o += 64) lt.push_back(make_int4((int)segs.size(), (int)o, 0, 0));
         segs.push_back(s);
       }
+      n_neu += inst_neu ? 1 : 0;
       b->maxit = std::max<int64_t>(b->maxit, c->cg_maxit > 0 ? c->cg_maxit : cg_default_maxit(c->nactive));
+    }
+    // The projection phases run over every instance of the batch, and the
+    // projection belongs only to lattices with Neumann links (Sec. 3.5):
+    // instances with and without them cannot share a batch.
+    if (n_neu != 0 && n_neu != n) {
+      tlvlbm_batch_destroy(b);
+      return TLVLBM_ERR_INVALID_ARG;
     }
     bt = node_tiles(b, b->tw, b->torder);
     b->nbt = (int)bt.size();

@@ -110,6 +110,20 @@ typedef struct {
                            started from the current displacement (the paper's relaxation; default
                            20); 0: exact minimiser (CG to cg_rtol) */
   double proj_weight;   /* Jacobi damping weight, 0 < proj_weight <= 1 (default 2/3) */
+  /* Device memory of the context.  When dev_alloc is set, every device buffer
+   * the context keeps (populations, displacement history, cut-link tables,
+   * projection and multigrid workspace, reverse-mode arena) comes from
+   * dev_alloc(bytes, alloc_user) and goes back through dev_free(ptr,
+   * alloc_user) -- for example a framework's caching allocator; dev_alloc
+   * returns NULL when it cannot allocate (TLVLBM_ERR_OUT_OF_MEMORY) and must
+   * return memory usable on `stream`.  dev_free is required with dev_alloc.
+   * The library calls them from the thread that makes the API call; memory
+   * is released only after the context's stream is synchronised.  NULL
+   * (default): hipMalloc / hipFree.  Call-scoped staging of host arrays and
+   * the batch's tile lists always use hipMalloc. */
+  void *(*dev_alloc)(size_t bytes, void *alloc_user);
+  void (*dev_free)(void *ptr, void *alloc_user);
+  void *alloc_user;
 } tlvlbm_options;
 
 /* Boundary condition attached to a boundary identifier (Sec. 3.1).

@@ -915,11 +915,12 @@ inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); 
 // reallocating a block that is too small
 struct Pool {
   AdjArena *a;
+  tlvlbm_ctx *c;
   size_t next = 0;
   template <typename X> hipError_t get(X **out, size_t bytes, hipStream_t st, bool zero = true) {
     bytes = bytes ? bytes : 16;
     if (next < a->blk.size() && a->bytes[next] < bytes) {
-      (void)hipFree(a->blk[next]);
+      dfree(c, a->blk[next]);
       a->blk[next] = nullptr;
       a->bytes[next] = 0;
     }
@@ -929,7 +930,7 @@ struct Pool {
     }
     if (!a->blk[next]) {
       void *q = nullptr;
-      const hipError_t e = hipMalloc(&q, bytes);
+      const hipError_t e = dmalloc(c, &q, bytes);
       if (e != hipSuccess) return e;
       a->blk[next] = q;
       a->bytes[next] = bytes;
@@ -939,9 +940,9 @@ struct Pool {
   }
 };
 
-void arena_release(AdjArena *a) {
+void arena_release(tlvlbm_ctx *c, AdjArena *a) {
   for (void *q : a->blk)
-    if (q) (void)hipFree(q);
+    if (q) dfree(c, q);
   a->blk.clear();
   a->bytes.clear();
   a->key[0] = a->key[1] = -1;
@@ -1159,9 +1160,9 @@ int stencil_transpose(tlvlbm_ctx *c) {
   if (!T) return TLVLBM_ERR_OUT_OF_MEMORY;
   T->ns = (int64_t)sn.size();
   if (T->ns) {
-    if (hipMalloc(&T->sn, sn.size() * sizeof(int64_t)) || hipMalloc(&T->so, so.size() * sizeof(int64_t)) ||
-        hipMalloc(&T->el, el.size() * sizeof(int32_t)) || hipMalloc(&T->ek, ek.size() * sizeof(int32_t)) ||
-        hipMalloc(&T->ew, ew.size() * sizeof(double)) || hipMalloc(&T->sc, sc.size() * sizeof(int32_t)) ||
+    if (dmalloc(c, &T->sn, sn.size() * sizeof(int64_t)) || dmalloc(c, &T->so, so.size() * sizeof(int64_t)) ||
+        dmalloc(c, &T->el, el.size() * sizeof(int32_t)) || dmalloc(c, &T->ek, ek.size() * sizeof(int32_t)) ||
+        dmalloc(c, &T->ew, ew.size() * sizeof(double)) || dmalloc(c, &T->sc, sc.size() * sizeof(int32_t)) ||
         hipMemcpy(T->sn, sn.data(), sn.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
         hipMemcpy(T->so, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
         hipMemcpy(T->el, el.data(), el.size() * sizeof(int32_t), hipMemcpyHostToDevice) ||
@@ -1169,7 +1170,7 @@ int stencil_transpose(tlvlbm_ctx *c) {
         hipMemcpy(T->ew, ew.data(), ew.size() * sizeof(double), hipMemcpyHostToDevice) ||
         hipMemcpy(T->sc, sc.data(), sc.size() * sizeof(int32_t), hipMemcpyHostToDevice)) {
       for (void *p : {(void *)T->sn, (void *)T->so, (void *)T->el, (void *)T->ek, (void *)T->ew, (void *)T->sc})
-        (void)hipFree(p);
+        dfree(c, p);
       delete T;
       return TLVLBM_ERR_OUT_OF_MEMORY;
     }
@@ -1258,7 +1259,7 @@ tlvlbm_status record_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double 
   if (!c->rec) c->rec = new AdjRec();
   AdjRec &rec = *c->rec;
   rec.valid = false;
-  Pool pool{c->arena};
+  Pool pool{c->arena, c};
   Run R;
   run_setup<D, T>(R, c);
   const bool track = c->track_u;
@@ -1296,7 +1297,7 @@ tlvlbm_status record_t(tlvlbm_ctx *c, int64_t n, const double *U0, const double 
   size_t avail = 0;
   const size_t init_bytes = (size_t)M * g.N * sizeof(double) + (dU0 ? (size_t)D * M * g.N * sizeof(double) : 0);
   if (ar.key[0] != n || ar.key[1] != seg_arg) {
-    arena_release(&ar);
+    arena_release(c, &ar);
     size_t fixed = 2 * (size_t)Q * M * plane + 2 * (size_t)D * dplane + 2 * z.ck_bytes + init_bytes +
                    (size_t)D * M * dplane;
     if (R.neu) fixed += (size_t)(M + 3 * D * D + 2 * D) * dplane;
@@ -1432,7 +1433,7 @@ tlvlbm_status backward_t(tlvlbm_ctx *c, const double *dLdU, const double *dLdu, 
   const Geo &g = c->geo;
   hipStream_t st = c->st;
   AdjRec &rec = *c->rec;
-  Pool pool{c->arena};
+  Pool pool{c->arena, c};
   pool.next = rec.pool_next;
   Run R;
   run_setup<D, T>(R, c);

@@ -96,6 +96,27 @@ static void set_material_par(Par &p, const tlvlbm_material *m, int D) {
 
 tlvlbm_status check_flag(tlvlbm_ctx *c) { return read_flag(c); }
 
+hipError_t dmalloc_v(tlvlbm_ctx *c, void **p, size_t bytes) {
+  *p = nullptr;
+  if (c && c->dev_alloc) {
+    *p = c->dev_alloc(bytes ? bytes : 1, c->alloc_user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+void dfree(tlvlbm_ctx *c, void *p) {
+  if (!p) return;
+  if (c && c->dev_alloc) {
+    // a caching allocator may hand the block out at once: the context's
+    // queued work must be done with it first (hipFree waits by itself)
+    (void)hipStreamSynchronize(c->st);
+    c->dev_free(p, c->alloc_user);
+    return;
+  }
+  (void)hipFree(p);
+}
+
 // stress of the material on the host (the reference state's equilibrium)
 static double mat_piola_host(int D, const double *F, const Par &p, double *P) {
   return D == 2 ? mat_piola<2>(F, p, P) : mat_piola<3>(F, p, P);
@@ -176,6 +197,7 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   if (!(o.omega > 0 && o.omega <= 2) || !(o.theta_F > 0 && o.theta_F <= 1)) return TLVLBM_ERR_INVALID_ARG;
   if (o.precision != TLVLBM_FP32 && o.precision != TLVLBM_FP64) return TLVLBM_ERR_INVALID_ARG;
   if (o.proj_sweeps < 0 || !(o.proj_weight > 0 && o.proj_weight <= 1)) return TLVLBM_ERR_INVALID_ARG;
+  if (!o.dev_alloc != !o.dev_free) return TLVLBM_ERR_INVALID_ARG;
   const int D = (int)lattice;
   int64_t N = 1;
   for (int a = 0; a < 3; ++a) {
@@ -225,10 +247,13 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   c->track_opt = o.track_u;
   c->track_u = o.track_u == 1;
   c->st = (hipStream_t)o.stream;
+  c->dev_alloc = o.dev_alloc;
+  c->dev_free = o.dev_free;
+  c->alloc_user = o.alloc_user;
   const size_t fb = (size_t)c->Q * c->M * (size_t)S * c->esz;
-  if (hipMalloc(&c->fA, fb) != hipSuccess || hipMalloc(&c->fB, fb) != hipSuccess ||
-      hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess ||
-      hipMalloc(&c->d_newton_fail, sizeof(int64_t)) != hipSuccess ||
+  if (dmalloc(c, &c->fA, fb) != hipSuccess || dmalloc(c, &c->fB, fb) != hipSuccess ||
+      dmalloc(c, &c->d_flag, sizeof(int)) != hipSuccess ||
+      dmalloc(c, &c->d_newton_fail, sizeof(int64_t)) != hipSuccess ||
       hipHostMalloc((void **)&c->h_flag, sizeof(int)) != hipSuccess ||
       hipHostMalloc((void **)&c->hscal, 64 * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
@@ -255,13 +280,13 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
                   c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles,
                   c->cg.nbm, c->bf, c->chunks, c->cpos, c->d_bcs};
   for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+    if (p) dfree(c, p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
   if (c->hscal) (void)hipHostFree(c->hscal);
   proj_aux_free(c);
   if (c->arena) {
     for (void *q : c->arena->blk)
-      if (q) (void)hipFree(q);
+      if (q) dfree(c, q);
     delete c->arena;
   }
   delete c->rec;
@@ -278,18 +303,18 @@ tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *c, const double *phi, const uint8_
     DevIn dphi, dbid;
     CHK(dphi.take(phi, N * sizeof(double), c->st), "phi upload");
     CHK(dbid.take(bid, N, c->st), "bid upload");
-    CHK(hipMalloc(&c->act, N), "mask alloc");
+    CHK(dmalloc(c, &c->act, N), "mask alloc");
     std::string err;
     int s = build_links(c, (const double *)dphi.ptr, (const uint8_t *)dbid.ptr, err);
     if (s) return fail(c, (tlvlbm_status)s, err.c_str());
     unsigned long long *cnt = nullptr;
-    CHK(hipMalloc(&cnt, sizeof(unsigned long long)), "count alloc");
+    CHK(dmalloc(c, &cnt, sizeof(unsigned long long)), "count alloc");
     CHK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->st), "count clear");
     hipLaunchKernelGGL(k_count_active, (unsigned)((N + 255) / 256), 256, 0, c->st, c->act, N, cnt);
     unsigned long long na = 0;
     CHK(hipMemcpyAsync(&na, cnt, sizeof(na), hipMemcpyDeviceToHost, c->st), "count read");
     CHK(hipStreamSynchronize(c->st), "synchronize");
-    (void)hipFree(cnt);
+    dfree(c, cnt);
     c->nactive = (int64_t)na;
     {
       // CHUNK-node chunks holding active nodes, in node order
@@ -308,11 +333,11 @@ tlvlbm_status tlvlbm_set_levelset(tlvlbm_ctx *c, const double *phi, const uint8_
         if (any) ch.push_back((int32_t)k);
       }
       if (!ch.empty()) {
-        CHK(hipMalloc(&c->chunks, ch.size() * sizeof(int32_t)), "chunk alloc");
+        CHK(dmalloc(c, &c->chunks, ch.size() * sizeof(int32_t)), "chunk alloc");
         CHK(hipMemcpy(c->chunks, ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice), "chunk upload");
         std::vector<int32_t> pos((size_t)((N + CHUNK - 1) / CHUNK), -1);
         for (size_t k = 0; k < ch.size(); ++k) pos[ch[k]] = (int32_t)k;
-        CHK(hipMalloc(&c->cpos, pos.size() * sizeof(int32_t)), "chunk position alloc");
+        CHK(dmalloc(c, &c->cpos, pos.size() * sizeof(int32_t)), "chunk position alloc");
         CHK(hipMemcpy(c->cpos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice), "chunk position upload");
       }
       c->nchunks = (int)ch.size();
@@ -361,13 +386,13 @@ tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *c, const double *g, int32_t ramp
     return fail(c, TLVLBM_ERR_INVALID_ARG, "bad ramp");
   try {
     if (!g) {
-      if (c->bf) CHK(hipFree(c->bf), "body force free");
+      dfree(c, c->bf);
       c->bf = nullptr;
       return TLVLBM_OK;
     }
     const size_t plane = (size_t)c->geo.S * c->esz;
     if (!c->bf) {
-      CHK(hipMalloc(&c->bf, (size_t)c->D * plane), "body force alloc");
+      CHK(dmalloc(c, &c->bf, (size_t)c->D * plane), "body force alloc");
       CHK(hipMemsetAsync(c->bf, 0, (size_t)c->D * plane, c->st), "body force clear");
     }
     DevIn dg;
@@ -406,8 +431,8 @@ tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0
     const int64_t N = c->geo.N, S = c->geo.S;
     const int D = c->D, M = c->M;
     if (c->track_u && !c->ustar) {
-      CHK(hipMalloc(&c->ustar, (size_t)D * S * sizeof(double)), "u* alloc");
-      CHK(hipMalloc(&c->ubuf, (size_t)D * S * sizeof(double)), "u alloc");
+      CHK(dmalloc(c, &c->ustar, (size_t)D * S * sizeof(double)), "u* alloc");
+      CHK(dmalloc(c, &c->ubuf, (size_t)D * S * sizeof(double)), "u alloc");
       CHK(hipMemsetAsync(c->ubuf, 0, (size_t)D * S * sizeof(double), c->st), "u clear");
     }
     DevIn dU, du, ddU;
@@ -543,8 +568,8 @@ tlvlbm_status tlvlbm_put_state(tlvlbm_ctx *c, const double *f, const double *ust
   {
     const int64_t N = c->geo.N;
     if (c->track_u && !c->ustar) {
-      CHK(hipMalloc(&c->ustar, (size_t)c->D * c->geo.S * sizeof(double)), "u* alloc");
-      CHK(hipMalloc(&c->ubuf, (size_t)c->D * c->geo.S * sizeof(double)), "u alloc");
+      CHK(dmalloc(c, &c->ustar, (size_t)c->D * c->geo.S * sizeof(double)), "u* alloc");
+      CHK(dmalloc(c, &c->ubuf, (size_t)c->D * c->geo.S * sizeof(double)), "u alloc");
       CHK(hipMemsetAsync(c->ubuf, 0, (size_t)c->D * c->geo.S * sizeof(double), c->st), "u clear");
     }
     DevIn F, U;

@@ -157,16 +157,16 @@ __device__ double phi_grad_axis(const Geo &g, const double *phi, C3 c, int64_t i
 
 // Cut fraction eta: bisection of the cubic interpolant of phi through the
 // link parameters -1, 0, 1, 2 (linear when an outer sample is missing)
-// (Sec. 3.1, Eq. 37); normal N_b from the level-set gradient (Eq. 38),
-// tangent frame, upstream node m^- of the eta < 1/2 branch (Eq. 43).
+// (Sec. 3.1, Eq. 37) and the unit normal N_b from the level-set gradient
+// (Eq. 38) of the link (m, q) with outside node o; mb = the node behind m
+// (-1 if none).  Shared by the context's link tables and the allocation-free
+// table of tlvlbm_cut_links_noalloc.
 template <int D>
-__global__ void k_link_geom(Geo g, const double *__restrict__ phi, const uint8_t *__restrict__ act, Links L) {
-  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (l >= L.n) return;
-  const int64_t m = L.node[l], o = L.out[l];
-  const int q = L.q[l], A = q / 2, sg = (q & 1) ? -1 : 1;
+__device__ __forceinline__ double link_eta_normal(const Geo &g, const double *__restrict__ phi, int64_t m, int64_t o,
+                                                  int q, int64_t mb, double *N) {
+  const int A = q / 2, sg = (q & 1) ? -1 : 1;
   const C3 cm = coords_of(g, m), co = coords_of(g, o);
-  const int64_t mb = node_dir(g, cm, q, -1), o2 = node_dir(g, co, q, 1);
+  const int64_t o2 = node_dir(g, co, q, 1);
   const double p0 = phi[m], p1 = phi[o];
   const bool cubic = (mb >= 0 && o2 >= 0);
   const double pm = cubic ? phi[mb] : 0.0, p2 = cubic ? phi[o2] : 0.0;
@@ -189,9 +189,8 @@ __global__ void k_link_geom(Geo g, const double *__restrict__ phi, const uint8_t
   }
   double eta = 0.5 * (lo + hi);
   eta = eta < 0.0 ? 0.0 : (eta > 1.0 ? 1.0 : eta);
-  L.eta[l] = eta;
-  const double X[3] = {g.ox + (cm.x + 0.5) * g.dx, g.oy + (cm.y + 0.5) * g.dx, g.oz + (cm.z + 0.5) * g.dx};
-  double N[3] = {0, 0, 0}, nrm = 0.0;
+  double nrm = 0.0;
+  for (int a = 0; a < 3; ++a) N[a] = 0.0;
   for (int a = 0; a < D; ++a) {
     const double gm = phi_grad_axis(g, phi, cm, m, a), go = phi_grad_axis(g, phi, co, o, a);
     N[a] = (1.0 - eta) * gm + eta * go;
@@ -203,6 +202,23 @@ __global__ void k_link_geom(Geo g, const double *__restrict__ phi, const uint8_t
   } else {
     for (int a = 0; a < D; ++a) N[a] = (a == A) ? sg : 0.0;
   }
+  return eta;
+}
+
+// link geometry of the context's table: eta, N_b, X_b, the tangent frame and
+// the upstream node m^- of the eta < 1/2 branch (Eq. 43)
+template <int D>
+__global__ void k_link_geom(Geo g, const double *__restrict__ phi, const uint8_t *__restrict__ act, Links L) {
+  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= L.n) return;
+  const int64_t m = L.node[l], o = L.out[l];
+  const int q = L.q[l], A = q / 2, sg = (q & 1) ? -1 : 1;
+  const C3 cm = coords_of(g, m);
+  const int64_t mb = node_dir(g, cm, q, -1);
+  double N[3];
+  const double eta = link_eta_normal<D>(g, phi, m, o, q, mb, N);
+  L.eta[l] = eta;
+  const double X[3] = {g.ox + (cm.x + 0.5) * g.dx, g.oy + (cm.y + 0.5) * g.dx, g.oz + (cm.z + 0.5) * g.dx};
   for (int a = 0; a < 3; ++a) {
     L.Nb[l * 3 + a] = N[a];
     L.Xb[l * 3 + a] = X[a] + ((a == A) ? sg * eta * g.dx : 0.0);
@@ -1169,7 +1185,7 @@ template <int D> static int build_links_t(tlvlbm_ctx *c, const double *phi, cons
   hipStream_t st = c->st;
   hipLaunchKernelGGL((k_active<D>), nblk(g.N, 256), 256, 0, st, phi, g, c->act, c->d_flag);
   unsigned *hist = nullptr;
-  HIP_OK(hipMalloc(&hist, 256 * sizeof(unsigned)));
+  HIP_OK(dmalloc(c, &hist, 256 * sizeof(unsigned)));
   HIP_OK(hipMemsetAsync(hist, 0, 256 * sizeof(unsigned), st));
   HIP_OK(hipMemsetAsync(c->d_flag, 0, sizeof(int), st));
   hipLaunchKernelGGL((k_check_hist<D>), nblk(g.N, 256), 256, 0, st, g, c->act, bid, c->d_flag, hist);
@@ -1178,7 +1194,7 @@ template <int D> static int build_links_t(tlvlbm_ctx *c, const double *phi, cons
   HIP_OK(hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, st));
   HIP_OK(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  (void)hipFree(hist);
+  dfree(c, hist);
   if (flag & FLAG_ARG) {
     err = "an active node has no lattice neighbour (non-periodic axis needs an inactive frame)";
     return TLVLBM_ERR_INVALID_ARG;
@@ -1189,27 +1205,27 @@ template <int D> static int build_links_t(tlvlbm_ctx *c, const double *phi, cons
   L.n = total;
   L.kmax = (D == 2) ? KMAX2 : KMAX3;
   const int64_t n = total > 0 ? total : 1;
-  HIP_OK(hipMalloc(&L.node, n * 8));
-  HIP_OK(hipMalloc(&L.out, n * 8));
-  HIP_OK(hipMalloc(&L.mminus, n * 8));
-  HIP_OK(hipMalloc(&L.q, n * 4));
-  HIP_OK(hipMalloc(&L.bid, n * 4));
-  HIP_OK(hipMalloc(&L.npts, n * 4));
-  HIP_OK(hipMalloc(&L.basis, n * 4));
-  HIP_OK(hipMalloc(&L.eta, n * 8));
-  HIP_OK(hipMalloc(&L.Nb, n * 24));
-  HIP_OK(hipMalloc(&L.Xb, n * 24));
-  HIP_OK(hipMalloc(&L.tang, n * 48));
-  HIP_OK(hipMalloc(&L.sidx, n * L.kmax * 4));
-  HIP_OK(hipMalloc(&L.sw, n * 2 * L.kmax * 8));
+  HIP_OK(dmalloc(c, &L.node, n * 8));
+  HIP_OK(dmalloc(c, &L.out, n * 8));
+  HIP_OK(dmalloc(c, &L.mminus, n * 8));
+  HIP_OK(dmalloc(c, &L.q, n * 4));
+  HIP_OK(dmalloc(c, &L.bid, n * 4));
+  HIP_OK(dmalloc(c, &L.npts, n * 4));
+  HIP_OK(dmalloc(c, &L.basis, n * 4));
+  HIP_OK(dmalloc(c, &L.eta, n * 8));
+  HIP_OK(dmalloc(c, &L.Nb, n * 24));
+  HIP_OK(dmalloc(c, &L.Xb, n * 24));
+  HIP_OK(dmalloc(c, &L.tang, n * 48));
+  HIP_OK(dmalloc(c, &L.sidx, n * L.kmax * 4));
+  HIP_OK(dmalloc(c, &L.sw, n * 2 * L.kmax * 8));
   // per-identifier compaction by prefix scan over link counts
   int *cnt = nullptr;
   int64_t *off = nullptr, *tot = nullptr, *grand = nullptr;
   const int64_t nb = (g.N + SCAN_CH - 1) / SCAN_CH;
-  HIP_OK(hipMalloc(&cnt, g.N * sizeof(int)));
-  HIP_OK(hipMalloc(&off, g.N * sizeof(int64_t)));
-  HIP_OK(hipMalloc(&tot, nb * sizeof(int64_t)));
-  HIP_OK(hipMalloc(&grand, sizeof(int64_t)));
+  HIP_OK(dmalloc(c, &cnt, g.N * sizeof(int)));
+  HIP_OK(dmalloc(c, &off, g.N * sizeof(int64_t)));
+  HIP_OK(dmalloc(c, &tot, nb * sizeof(int64_t)));
+  HIP_OK(dmalloc(c, &grand, sizeof(int64_t)));
   int64_t base = 0;
   for (int b = 0; b < 256; ++b) {
     c->bid_begin[b] = c->bid_end[b] = base;
@@ -1229,10 +1245,10 @@ template <int D> static int build_links_t(tlvlbm_ctx *c, const double *phi, cons
     base += gsum;
     c->bid_end[b] = base;
   }
-  (void)hipFree(cnt);
-  (void)hipFree(off);
-  (void)hipFree(tot);
-  (void)hipFree(grand);
+  dfree(c, cnt);
+  dfree(c, off);
+  dfree(c, tot);
+  dfree(c, grand);
   if (total > 0) {
     hipLaunchKernelGGL((k_link_geom<D>), nblk(total, 128), 128, 0, st, g, phi, c->act, L);
     hipLaunchKernelGGL((k_link_lsq<D>), nblk(total, 64), 64, 0, st, g, c->act, L, c->d_flag);
@@ -1254,7 +1270,7 @@ int build_links(tlvlbm_ctx *c, const double *phi, const uint8_t *bid, std::strin
 // device copy of the boundary conditions (after tlvlbm_set_boundary),
 // ordered on the context's stream behind the steps already queued
 static int sync_bcs(tlvlbm_ctx *c) {
-  if (!c->d_bcs && hipMalloc(&c->d_bcs, sizeof(c->bcs)) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
+  if (!c->d_bcs && dmalloc(c, &c->d_bcs, sizeof(c->bcs)) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
   if (c->bcs_dirty) {
     if (hipMemcpyAsync(c->d_bcs, c->bcs, sizeof(c->bcs), hipMemcpyHostToDevice, c->st) != hipSuccess)
       return TLVLBM_ERR_DEVICE;
@@ -1363,18 +1379,18 @@ template <int D, typename T> static int cg_alloc(tlvlbm_ctx *c) {
   const size_t plane = (size_t)c->geo.S * sizeof(T), dplane = (size_t)c->geo.S * sizeof(double);
   void **vec[] = {&w.x, &w.r, &w.p0, &w.p1, &w.Ap, &w.b, &w.anc_s, &w.z};
   for (void **pp : vec) {
-    HIP_OK(hipMalloc(pp, D * dplane));
+    HIP_OK(dmalloc(c, pp, D * dplane));
     HIP_OK(hipMemsetAsync(*pp, 0, D * dplane, c->st));
   }
-  HIP_OK(hipMalloc(&w.V, D * plane));
-  HIP_OK(hipMalloc(&w.Fm, D * D * plane));
-  HIP_OK(hipMalloc(&w.Fr, D * D * plane));
+  HIP_OK(dmalloc(c, &w.V, D * plane));
+  HIP_OK(dmalloc(c, &w.Fm, D * D * plane));
+  HIP_OK(dmalloc(c, &w.Fr, D * D * plane));
   HIP_OK(hipMemsetAsync(w.Fr, 0, D * D * plane, c->st));
-  HIP_OK(hipMalloc(&w.anc_n, c->geo.S));
-  HIP_OK(hipMalloc(&w.anc_i, c->geo.S * sizeof(int)));
+  HIP_OK(dmalloc(c, &w.anc_n, c->geo.S));
+  HIP_OK(dmalloc(c, &w.anc_i, c->geo.S * sizeof(int)));
   w.nblk = (int)nblk(c->geo.N, CG_T);
-  HIP_OK(hipMalloc(&w.partial, (size_t)w.nblk * PSTRIDE * sizeof(double)));
-  HIP_OK(hipMalloc(&w.scal, S_NSCAL * sizeof(double)));
+  HIP_OK(dmalloc(c, &w.partial, (size_t)w.nblk * PSTRIDE * sizeof(double)));
+  HIP_OK(dmalloc(c, &w.scal, S_NSCAL * sizeof(double)));
   return TLVLBM_OK;
 }
 
@@ -1910,3 +1926,4 @@ int ensure_cg(tlvlbm_ctx *c) {
 }
 
 }  // namespace tl
+

@@ -439,19 +439,19 @@ template <int D> void batch_vcycle_t(const BatchMG &bm, const Inst *insts, int n
 
 namespace {
 
-void gauge_free(Gauge *G) {
+void gauge_free(tlvlbm_ctx *c, Gauge *G) {
   if (!G) return;
   for (void *p : {(void *)G->comp, (void *)G->cn, (void *)G->ct, (void *)G->ccnt, (void *)G->tpart,
                   (void *)G->mean, (void *)G->mean0, (void *)G->anc_n})
-    (void)hipFree(p);
+    dfree(c, p);
   delete G;
 }
 
-void mg_free(MG *mg) {
+void mg_free(tlvlbm_ctx *c, MG *mg) {
   if (!mg) return;
   for (MGLevel &L : mg->lev) {
-    for (void *p : {(void *)L.w, (void *)L.d, (void *)L.x, (void *)L.t}) (void)hipFree(p);
-    if (L.b) (void)hipFree(L.b);  // level 0 borrows the CG residual only inside mg_apply
+    for (void *p : {(void *)L.w, (void *)L.d, (void *)L.x, (void *)L.t}) dfree(c, p);
+    if (L.b) dfree(c, L.b);  // level 0 borrows the CG residual only inside mg_apply
   }
   delete mg;
 }
@@ -521,12 +521,12 @@ int gauge_build(tlvlbm_ctx *c, const std::vector<uint8_t> &act, const std::vecto
   G->nu = nu;
   G->ntile = ct[nu];
   const size_t ncn = std::max<size_t>(cn.size(), 1);
-  if (hipMalloc(&G->comp, N * sizeof(int32_t)) || hipMalloc(&G->cn, ncn * sizeof(int32_t)) ||
-      hipMalloc(&G->ct, ct.size() * sizeof(int64_t)) || hipMalloc(&G->ccnt, ccnt.size() * sizeof(int64_t)) ||
-      hipMalloc(&G->tpart, ((size_t)G->ntile + 1) * D * sizeof(double)) ||
-      hipMalloc(&G->mean, ((size_t)nu + 1) * D * sizeof(double)) ||
-      hipMalloc(&G->mean0, ((size_t)nu + 1) * D * sizeof(double)) || hipMalloc(&G->anc_n, N)) {
-    gauge_free(G);
+  if (dmalloc(c, &G->comp, N * sizeof(int32_t)) || dmalloc(c, &G->cn, ncn * sizeof(int32_t)) ||
+      dmalloc(c, &G->ct, ct.size() * sizeof(int64_t)) || dmalloc(c, &G->ccnt, ccnt.size() * sizeof(int64_t)) ||
+      dmalloc(c, &G->tpart, ((size_t)G->ntile + 1) * D * sizeof(double)) ||
+      dmalloc(c, &G->mean, ((size_t)nu + 1) * D * sizeof(double)) ||
+      dmalloc(c, &G->mean0, ((size_t)nu + 1) * D * sizeof(double)) || dmalloc(c, &G->anc_n, N)) {
+    gauge_free(c, G);
     return TLVLBM_ERR_OUT_OF_MEMORY;
   }
   if (hipMemcpy(G->comp, comp.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) ||
@@ -534,7 +534,7 @@ int gauge_build(tlvlbm_ctx *c, const std::vector<uint8_t> &act, const std::vecto
       hipMemcpy(G->ct, ct.data(), ct.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
       hipMemcpy(G->ccnt, ccnt.data(), ccnt.size() * sizeof(int64_t), hipMemcpyHostToDevice) ||
       hipMemcpy(G->anc_n, an.data(), N, hipMemcpyHostToDevice)) {
-    gauge_free(G);
+    gauge_free(c, G);
     return TLVLBM_ERR_DEVICE;
   }
   *out = G;
@@ -551,13 +551,13 @@ void proj_aux_free(tlvlbm_ctx *c) {
   if (c->stT) {
     for (void *p : {(void *)c->stT->sn, (void *)c->stT->so, (void *)c->stT->el, (void *)c->stT->ek,
                     (void *)c->stT->ew, (void *)c->stT->sc})
-      (void)hipFree(p);
+      dfree(c, p);
     delete c->stT;
     c->stT = nullptr;
   }
-  gauge_free(c->gauge);
+  gauge_free(c, c->gauge);
   c->gauge = nullptr;
-  mg_free(c->mg);
+  mg_free(c, c->mg);
   c->mg = nullptr;
 }
 
@@ -589,7 +589,7 @@ int proj_aux_build(tlvlbm_ctx *c) {
       for (int64_t i = t * 256; i < std::min<int64_t>(N, t * 256 + 256) && !any; ++i) any = act[i] != 0;
       if (any) tiles.push_back((int32_t)t);
     }
-    if (c->cg.tiles) (void)hipFree(c->cg.tiles);
+    if (c->cg.tiles) dfree(c, c->cg.tiles);
     c->cg.tiles = nullptr;
     c->cg.ntiles = 0;
     // neighbour masks of the active-node graph: the Jacobi sweeps read one
@@ -613,12 +613,12 @@ int proj_aux_build(tlvlbm_ctx *c) {
       }
       nbm[i] = m;
     }
-    if (c->cg.nbm) (void)hipFree(c->cg.nbm);
+    if (c->cg.nbm) dfree(c, c->cg.nbm);
     c->cg.nbm = nullptr;
-    if (hipMalloc(&c->cg.nbm, N) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
+    if (dmalloc(c, &c->cg.nbm, N) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
     if (hipMemcpy(c->cg.nbm, nbm.data(), N, hipMemcpyHostToDevice) != hipSuccess) return TLVLBM_ERR_DEVICE;
     if (!tiles.empty()) {
-      if (hipMalloc(&c->cg.tiles, tiles.size() * sizeof(int32_t)) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
+      if (dmalloc(c, &c->cg.tiles, tiles.size() * sizeof(int32_t)) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
       if (hipMemcpy(c->cg.tiles, tiles.data(), tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
         return TLVLBM_ERR_DEVICE;
       c->cg.ntiles = (int)tiles.size();
@@ -757,10 +757,10 @@ int mg_build(tlvlbm_ctx *c, const std::vector<uint8_t> &act, const std::vector<f
     L.v.N = n;
     L.v.stride = l == 0 ? g.S : n;
     float *w = nullptr, *dd = nullptr;
-    if (hipMalloc(&w, (size_t)D * n * sizeof(float)) != hipSuccess ||
-        hipMalloc(&dd, (size_t)n * sizeof(float)) != hipSuccess) {
-      if (w) (void)hipFree(w);
-      mg_free(mg);
+    if (dmalloc(c, &w, (size_t)D * n * sizeof(float)) != hipSuccess ||
+        dmalloc(c, &dd, (size_t)n * sizeof(float)) != hipSuccess) {
+      if (w) dfree(c, w);
+      mg_free(c, mg);
       return TLVLBM_ERR_OUT_OF_MEMORY;
     }
     L.w = w;
@@ -769,18 +769,18 @@ int mg_build(tlvlbm_ctx *c, const std::vector<uint8_t> &act, const std::vector<f
     L.v.d = dd;
     if (hipMemcpy(w, h.w.data(), (size_t)D * n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dd, d.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-      mg_free(mg);
+      mg_free(c, mg);
       return TLVLBM_ERR_DEVICE;
     }
     const size_t vb = (size_t)D * L.v.stride * sizeof(double);
-    if (hipMalloc(&L.x, vb) != hipSuccess || hipMalloc(&L.t, vb) != hipSuccess ||
-        (l > 0 && hipMalloc(&L.b, vb) != hipSuccess)) {
-      mg_free(mg);
+    if (dmalloc(c, &L.x, vb) != hipSuccess || dmalloc(c, &L.t, vb) != hipSuccess ||
+        (l > 0 && dmalloc(c, &L.b, vb) != hipSuccess)) {
+      mg_free(c, mg);
       return TLVLBM_ERR_OUT_OF_MEMORY;
     }
     if (hipMemset(L.x, 0, vb) != hipSuccess || hipMemset(L.t, 0, vb) != hipSuccess ||
         (l > 0 && hipMemset(L.b, 0, vb) != hipSuccess)) {
-      mg_free(mg);
+      mg_free(c, mg);
       return TLVLBM_ERR_DEVICE;
     }
   }

@@ -306,6 +306,10 @@ struct tlvlbm_ctx {
   tl::StencilT *stT = nullptr; // transposed Neumann stencils (reverse mode, built on first use)
   tl::AdjArena *arena = nullptr; // reverse-mode device memory (kept until destroy or a new shape)
   tl::AdjRec *rec = nullptr;     // the forward run recorded for the backward pass
+  // caller's device allocator (tlvlbm_options); null: hipMalloc / hipFree
+  void *(*dev_alloc)(size_t, void *) = nullptr;
+  void (*dev_free)(void *, void *) = nullptr;
+  void *alloc_user = nullptr;
   bool aux_stale = true;       // boundary conditions changed since the build
   bool track_u = false;
   hipStream_t st = nullptr;
@@ -349,6 +353,12 @@ struct tlvlbm_ctx {
 };
 
 namespace tl {
+// device memory kept by a context: through its allocator hooks when set
+hipError_t dmalloc_v(tlvlbm_ctx *c, void **p, size_t bytes);
+void dfree(tlvlbm_ctx *c, void *p);
+template <typename X> inline hipError_t dmalloc(tlvlbm_ctx *c, X **p, size_t bytes) {
+  return dmalloc_v(c, (void **)p, bytes);
+}
 // launchers (bulk.hip)
 // taped: the kernels of the reverse mode's forward (the same update through
 // the shared device function, recording the tape when tape is not null), so

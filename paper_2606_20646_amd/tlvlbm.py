@@ -44,11 +44,36 @@ def _material(mu, lam, fibre):
     return m
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class Options(C.Structure):
     _fields_ = [("omega", C.c_double), ("gamma", C.c_double), ("theta_F", C.c_double), ("cg_rtol", C.c_double),
                 ("proj_every", C.c_int32), ("cg_maxit", C.c_int32), ("precision", C.c_int32),
                 ("track_u", C.c_int32), ("stream", C.c_void_p), ("cg_multigrid", C.c_int32),
-                ("proj_sweeps", C.c_int32), ("proj_weight", C.c_double)]
+                ("proj_sweeps", C.c_int32), ("proj_weight", C.c_double), ("dev_alloc", ALLOC_FN),
+                ("dev_free", FREE_FN), ("alloc_user", C.c_void_p)]
+
+
+def torch_allocator(stream=None):
+    """(dev_alloc, dev_free) callbacks that hand the library's device memory
+    to torch's caching allocator (torch.cuda.caching_allocator_alloc /
+    _delete) on the current device, associated with `stream` (a
+    torch.cuda.Stream; None: the current stream)."""
+    import torch
+    dev = torch.cuda.current_device()
+
+    def alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+        except Exception:  # out of memory: the library reports TLVLBM_ERR_OUT_OF_MEMORY
+            return None
+
+    def free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return ALLOC_FN(alloc), FREE_FN(free)
 
 
 class BC(C.Structure):
@@ -148,7 +173,11 @@ class Solver:
 
     def __init__(self, D, n, dx, dt, mu, lam, rho0=1.0, origin=None, periodic_mask=None, omega=1.8, gamma=0.0,
                  theta_F=1.0, proj_every=20, precision="fp32", track_u=-1, cg_rtol=0.0, cg_maxit=0,
-                 stream=None, cg_multigrid=True, proj_sweeps=20, proj_weight=2.0 / 3.0, fibre=None):
+                 stream=None, cg_multigrid=True, proj_sweeps=20, proj_weight=2.0 / 3.0, fibre=None,
+                 allocator=None):
+        """allocator: None (the library's hipMalloc), "torch" (torch's caching
+        allocator, on the stream given as a torch.cuda.Stream or the current
+        one), or a (dev_alloc, dev_free) pair of ALLOC_FN / FREE_FN."""
         self.D, self.M, self.Q = D, D + D * D, 2 * D
         self.n = tuple(int(v) for v in n)
         self.N = int(np.prod(self.n))
@@ -165,7 +194,17 @@ class Solver:
         o.omega, o.gamma, o.theta_F, o.cg_rtol = omega, gamma, theta_F, cg_rtol
         o.proj_every, o.cg_maxit, o.track_u = proj_every, cg_maxit, track_u
         o.precision = FP64 if precision in ("fp64", FP64) else FP32
+        tstream = None
+        if stream is not None and hasattr(stream, "cuda_stream"):  # a torch.cuda.Stream
+            tstream, stream = stream, stream.cuda_stream
         o.stream = stream
+        self._alloc = None
+        if allocator == "torch":
+            self._alloc = torch_allocator(tstream)
+        elif allocator is not None:
+            self._alloc = tuple(allocator)
+        if self._alloc is not None:
+            o.dev_alloc, o.dev_free = self._alloc
         o.cg_multigrid = int(bool(cg_multigrid))
         o.proj_sweeps, o.proj_weight = int(proj_sweeps), float(proj_weight)
         h = C.c_void_p()

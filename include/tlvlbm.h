@@ -366,6 +366,34 @@ tlvlbm_status tlvlbm_batch_get_tiles(const tlvlbm_batch *b, int32_t *tile_width,
 tlvlbm_status tlvlbm_batch_destroy(tlvlbm_batch *b);
 const char *tlvlbm_batch_last_error(const tlvlbm_batch *b);
 
+/* ---- Without device allocation ------------------------------------------
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the cut-link table
+ * that tlvlbm_set_levelset builds and tlvlbm_get_links returns, computed
+ * straight from a level set with no allocation at all.
+ *  - grid, lattice: as for tlvlbm_create; phi [N] FP64 and bid [N] uint8
+ *    (NULL: identifier 0) node samples as for tlvlbm_set_levelset, in device
+ *    memory.
+ *  - Outputs (device memory, caller-owned, `capacity` records each): node
+ *    [cap] int64, q [cap] int32 (required); eta [cap] FP64, Nb [cap][3] FP64,
+ *    bid_out [cap] int32 (each may be NULL).  Same records, same order
+ *    (bid, node, q) and the same values bit for bit as tlvlbm_get_links after
+ *    tlvlbm_set_levelset.  *n_links (host) receives the number of cut links.
+ *  - stream: hipStream_t of the work (NULL: default); returns after the
+ *    results are in place (synchronises the stream).
+ *  - Workspace: one fixed device array of the library (about 66 KiB, held by
+ *    every GPU the library runs on until the process ends), which limits
+ *    the grid to TLVLBM_NOALLOC_MAX_NODES nodes.  Calls that overlap on one
+ *    GPU (several host threads or streams) race on it.
+ *  - Errors: TLVLBM_ERR_INVALID_ARG for a larger grid, host-memory arrays, a
+ *    missing required pointer, an active node without a lattice neighbour,
+ *    or more links than `capacity` (then *n_links holds the count needed and
+ *    no record is written); TLVLBM_ERR_DEVICE for a device failure. */
+#define TLVLBM_NOALLOC_MAX_NODES (8192LL * 2048LL)
+tlvlbm_status tlvlbm_cut_links_noalloc(const tlvlbm_grid *grid, tlvlbm_lattice lattice, const double *phi,
+                                       const uint8_t *bid, int64_t capacity, int64_t *node, int32_t *q, double *eta,
+                                       double *Nb, int32_t *bid_out, int64_t *n_links, void *stream);
+
 /* Size in bytes of one population buffer (for bandwidth accounting). */
 size_t tlvlbm_population_bytes(const tlvlbm_ctx *ctx);
 

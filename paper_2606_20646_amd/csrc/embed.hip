@@ -5,6 +5,7 @@
 //  - compatibility projection by conjugate gradients (Sec. 3.5).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "tl_device.hpp"
@@ -1927,3 +1928,222 @@ int ensure_cg(tlvlbm_ctx *c) {
 
 }  // namespace tl
 
+// --------------------------------------------- allocation-free link table
+// tlvlbm_cut_links_noalloc: the cut-link table of a level set without any
+// device allocation.  Its workspace (per-identifier link histogram, error
+// flag, chunk totals of the prefix scan) is one fixed device array of the
+// library, `scratch`, held by every GPU the library runs on until the
+// process ends; the activity test phi <= 0 is evaluated where needed, so no
+// node-sized buffer exists.  Host code reaches the array only through the
+// address hipGetSymbolAddress returns on each device.
+
+namespace tl {
+namespace {
+
+constexpr int NA_CHUNKS = 8192;  // chunk totals: at most NA_CHUNKS * SCAN_CH nodes
+constexpr size_t NA_TOT = 0, NA_GRAND = NA_TOT + sizeof(int64_t) * NA_CHUNKS, NA_HIST = NA_GRAND + 256,
+                 NA_FLAG = NA_HIST + 256 * sizeof(unsigned), NA_BYTES = NA_FLAG + 256;
+constexpr int NA_MAX_DEVICES = 64;
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+std::mutex na_mutex;
+void *na_ptr[NA_MAX_DEVICES] = {nullptr};
+
+// the array's address on the current device (looked up once per device)
+hipError_t na_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NA_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(na_mutex);
+  if (!na_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    na_ptr[dev] = p;
+  }
+  *out = na_ptr[dev];
+  return hipSuccess;
+}
+
+__device__ __forceinline__ bool na_active(const double *__restrict__ phi, int64_t i) { return phi[i] <= 0.0; }
+
+__global__ void k_na_clear(unsigned *hist, int *flag) {
+  hist[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) *flag = 0;
+}
+
+// every lattice neighbour of an active node must exist; cut links per bid
+template <int D>
+__global__ void k_na_hist(Geo g, const double *__restrict__ phi, const uint8_t *__restrict__ bid, int *flag,
+                          unsigned *hist) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.N || !na_active(phi, i)) return;
+  const C3 c = coords_of(g, i);
+  for (int q = 0; q < 2 * D; ++q) {
+    const int64_t o = node_dir(g, c, q, 1);
+    if (o < 0) {
+      atomicOr(flag, FLAG_ARG);
+      return;
+    }
+    if (!na_active(phi, o)) atomicAdd(&hist[bid ? bid[o] : 0], 1u);
+  }
+}
+
+// cut links of node i whose outside node carries identifier b
+template <int D>
+__device__ __forceinline__ int na_count(const Geo &g, const double *__restrict__ phi, const uint8_t *__restrict__ bid,
+                                        int b, int64_t i) {
+  if (i >= g.N || !na_active(phi, i)) return 0;
+  const C3 c = coords_of(g, i);
+  int k = 0;
+  for (int q = 0; q < 2 * D; ++q) {
+    const int64_t o = node_dir(g, c, q, 1);
+    if (o >= 0 && !na_active(phi, o) && (bid ? bid[o] : 0) == b) ++k;
+  }
+  return k;
+}
+
+// link count of every chunk of SCAN_CH nodes
+template <int D>
+__global__ __launch_bounds__(SCAN_T) void k_na_chunk(Geo g, const double *__restrict__ phi,
+                                                     const uint8_t *__restrict__ bid, int b, int64_t *tot) {
+  __shared__ int64_t sh[SCAN_T];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CH + threadIdx.x * SCAN_V;
+  int64_t s = 0;
+  for (int k = 0; k < SCAN_V; ++k) s += na_count<D>(g, phi, bid, b, base + k);
+  int64_t total;
+  block_excl_scan(s, sh, total);
+  if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+// records of identifier b in (node, q) order: chunk offset (scanned totals)
+// plus the block-local exclusive scan of the per-thread counts
+template <int D>
+__global__ __launch_bounds__(SCAN_T) void k_na_scatter(Geo g, const double *__restrict__ phi,
+                                                       const uint8_t *__restrict__ bid, int b,
+                                                       const int64_t *__restrict__ tot, int64_t base_out, int64_t cap,
+                                                       int64_t *__restrict__ node, int32_t *__restrict__ qo,
+                                                       int32_t *__restrict__ bo) {
+  __shared__ int64_t sh[SCAN_T];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CH + threadIdx.x * SCAN_V;
+  int cnt[SCAN_V];
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_V; ++k) {
+    cnt[k] = na_count<D>(g, phi, bid, b, base + k);
+    s += cnt[k];
+  }
+  int64_t total;
+  int64_t ex = block_excl_scan(s, sh, total) + tot[blockIdx.x] + base_out;
+  for (int k = 0; k < SCAN_V; ++k) {
+    if (!cnt[k]) continue;
+    const int64_t i = base + k;
+    const C3 c = coords_of(g, i);
+    for (int q = 0; q < 2 * D; ++q) {
+      const int64_t o = node_dir(g, c, q, 1);
+      if (o >= 0 && !na_active(phi, o) && (bid ? bid[o] : 0) == b) {
+        if (ex < cap) {
+          node[ex] = i;
+          qo[ex] = q;
+          if (bo) bo[ex] = b;
+        }
+        ++ex;
+      }
+    }
+  }
+}
+
+template <int D>
+__global__ void k_na_geom(Geo g, const double *__restrict__ phi, int64_t n, const int64_t *__restrict__ node,
+                          const int32_t *__restrict__ qo, double *__restrict__ eta, double *__restrict__ Nb) {
+  const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= n) return;
+  const int64_t m = node[l];
+  const int q = qo[l];
+  const C3 cm = coords_of(g, m);
+  const int64_t o = node_dir(g, cm, q, 1), mb = node_dir(g, cm, q, -1);
+  double N[3];
+  const double e = link_eta_normal<D>(g, phi, m, o, q, mb, N);
+  if (eta) eta[l] = e;
+  if (Nb)
+    for (int a = 0; a < 3; ++a) Nb[l * 3 + a] = N[a];
+}
+
+template <int D>
+tlvlbm_status na_links_t(const Geo &g, const double *phi, const uint8_t *bid, int64_t cap, int64_t *node, int32_t *q,
+                         double *eta, double *Nb, int32_t *bo, int64_t *n_links, hipStream_t st,
+                         unsigned char *ws) {
+  int64_t *tot = (int64_t *)(ws + NA_TOT), *grand = (int64_t *)(ws + NA_GRAND);
+  unsigned *hist = (unsigned *)(ws + NA_HIST);
+  int *flag = (int *)(ws + NA_FLAG);
+  const int64_t nb = (g.N + SCAN_CH - 1) / SCAN_CH;
+  // the workspace keeps the last call's contents: clear what starts at zero
+  hipLaunchKernelGGL(k_na_clear, 1, 256, 0, st, hist, flag);
+  hipLaunchKernelGGL((k_na_hist<D>), nblk(g.N, 256), 256, 0, st, g, phi, bid, flag, hist);
+  unsigned hh[256];
+  int fl = 0;
+  if (hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return TLVLBM_ERR_DEVICE;
+  if (fl & FLAG_ARG) return TLVLBM_ERR_INVALID_ARG;
+  int64_t total = 0;
+  for (int b = 0; b < 256; ++b) total += hh[b];
+  *n_links = total;
+  if (total > cap) return TLVLBM_ERR_INVALID_ARG;
+  int64_t base = 0;
+  for (int b = 0; b < 256; ++b) {
+    if (!hh[b]) continue;
+    hipLaunchKernelGGL((k_na_chunk<D>), (unsigned)nb, SCAN_T, 0, st, g, phi, bid, b, tot);
+    hipLaunchKernelGGL(k_scan_tot2, 1, SCAN_T, 0, st, tot, nb, grand);
+    hipLaunchKernelGGL((k_na_scatter<D>), (unsigned)nb, SCAN_T, 0, st, g, phi, bid, b, tot, base, cap, node, q, bo);
+    base += hh[b];
+  }
+  if (total > 0)
+    hipLaunchKernelGGL((k_na_geom<D>), nblk(total, 128), 128, 0, st, g, phi, total, node, q, eta, Nb);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return TLVLBM_ERR_DEVICE;
+  return TLVLBM_OK;
+}
+
+}  // namespace
+}  // namespace tl
+
+extern "C" tlvlbm_status tlvlbm_cut_links_noalloc(const tlvlbm_grid *grid, tlvlbm_lattice lattice, const double *phi,
+                                                  const uint8_t *bid, int64_t capacity, int64_t *node, int32_t *q,
+                                                  double *eta, double *Nb, int32_t *bid_out, int64_t *n_links,
+                                                  void *stream) {
+  using namespace tl;
+  if (!grid || !phi || !node || !q || !n_links || capacity < 0) return TLVLBM_ERR_INVALID_ARG;
+  if (lattice != TLVLBM_D2Q4x6 && lattice != TLVLBM_D3Q6x12) return TLVLBM_ERR_INVALID_ARG;
+  *n_links = 0;
+  const int D = (int)lattice;
+  Geo g{};
+  int64_t N = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int na = a < D ? grid->n[a] : 1;
+    if (na < 1) return TLVLBM_ERR_INVALID_ARG;
+    N *= na;
+  }
+  if (!(grid->dx > 0) || N > (int64_t)NA_CHUNKS * SCAN_CH) return TLVLBM_ERR_INVALID_ARG;
+  // inputs and outputs in device memory (nothing is staged: staging would allocate)
+  for (const void *p : {(const void *)phi, (const void *)bid, (const void *)node, (const void *)q, (const void *)eta,
+                        (const void *)Nb, (const void *)bid_out})
+    if (p && !is_device_ptr(p)) return TLVLBM_ERR_INVALID_ARG;
+  g.nx = grid->n[0];
+  g.ny = grid->n[1];
+  g.nz = D == 3 ? grid->n[2] : 1;
+  g.per = (int)(grid->periodic_mask & ((1u << D) - 1)) | (D == 2 ? 4 : 0);
+  g.N = N;
+  g.S = N;
+  g.dx = grid->dx;
+  g.ox = grid->origin[0];
+  g.oy = grid->origin[1];
+  g.oz = D == 3 ? grid->origin[2] : 0.0;
+  void *ws = nullptr;
+  if (na_scratch(&ws) != hipSuccess) return TLVLBM_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  return D == 2 ? na_links_t<2>(g, phi, bid, capacity, node, q, eta, Nb, bid_out, n_links, st, (unsigned char *)ws)
+                : na_links_t<3>(g, phi, bid, capacity, node, q, eta, Nb, bid_out, n_links, st, (unsigned char *)ws);
+}

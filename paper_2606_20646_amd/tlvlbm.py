@@ -132,6 +132,9 @@ def _load():
     L.tlvlbm_adjoint_step.argtypes = [vp, C.c_int64, dp, dp, dp, dp, C.POINTER(C.c_double), dp, dp, C.c_int64]
     L.tlvlbm_adjoint_record.argtypes = [vp, C.c_int64, dp, dp, C.c_int64]
     L.tlvlbm_adjoint_backward.argtypes = [vp, dp, dp, C.POINTER(C.c_double), dp, dp, dp]
+    L.tlvlbm_cut_links_noalloc.argtypes = [C.POINTER(Grid), C.c_int, dp, dp, C.c_int64, dp, dp, dp, dp, dp,
+                                           C.POINTER(C.c_int64), vp]
+    L.tlvlbm_cut_links_noalloc.restype = C.c_int
     L.tlvlbm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
     L.tlvlbm_batch_step.argtypes = [vp, C.c_int64]
     L.tlvlbm_batch_set_graph.argtypes = [vp, C.c_int32]
@@ -364,6 +367,30 @@ class Solver:
 
     def population_bytes(self):
         return int(lib.tlvlbm_population_bytes(self.h))
+
+
+def cut_links_noalloc(D, n, dx, phi, capacity, node, q, eta=None, Nb=None, bid_out=None, bid=None, origin=None,
+                      periodic_mask=0, stream=None):
+    """tlvlbm_cut_links_noalloc: the cut-link table of a level set with no
+    device allocation.  phi [N] float64, bid [N] uint8 (or None), and the
+    outputs node [cap] int64, q [cap] int32, eta [cap] float64, Nb [cap, 3]
+    float64, bid_out [cap] int32 are contiguous device tensors owned by the
+    caller (capacity = their length).  Returns the number of cut links; raises
+    TlvlbmError (with .n_links set) when it exceeds the capacity."""
+    g = Grid()
+    for a in range(3):
+        g.n[a] = int(n[a]) if a < D else 1
+        g.origin[a] = (origin[a] if origin is not None and a < len(origin) else 0.0)
+    g.dx = dx
+    g.periodic_mask = periodic_mask
+    nl = C.c_int64(0)
+    st = lib.tlvlbm_cut_links_noalloc(C.byref(g), D, _ptr(phi)[0], _ptr(bid)[0], int(capacity), _ptr(node)[0],
+                                      _ptr(q)[0], _ptr(eta)[0], _ptr(Nb)[0], _ptr(bid_out)[0], C.byref(nl), stream)
+    if st:
+        e = TlvlbmError(st, f"cut_links_noalloc (links: {nl.value}, capacity {capacity})")
+        e.n_links = nl.value
+        raise e
+    return nl.value
 
 
 def _handles(solvers):

@@ -82,6 +82,12 @@ def lib():
         L.orc_compatible_F.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_adjoint.argtypes = [C.c_void_p, C.c_int64, dp, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_viscous.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        L.orc_get_viscous.argtypes = [C.c_void_p, dp, dp]
+        L.orc_visco_piola.argtypes = [C.c_int] + [C.c_double] * 4 + [dp] * 4
+        L.orc_visco_piola_jvp.argtypes = [C.c_int] + [C.c_double] * 4 + [dp] * 5
+        L.orc_visco_path.argtypes = [C.c_int] + [C.c_double] * 5 + [C.c_int64, dp, dp]
+        L.orc_stress.argtypes = [C.c_void_p, dp, dp]
         _lib = L
     return _lib
 
@@ -153,6 +159,40 @@ def cauchy(F, mu, lam):
     s = np.zeros((D, D))
     lib().orc_cauchy(D, mu, lam, _d(F), _d(s))
     return s
+
+
+def visco_piola(F, mu, lam, beta, xi, Qh, S0h):
+    """P = P_NH(F) + F Q(F), Q(F) = xi^2 Qh + beta xi (S_0(F) - S0h): the
+    stress of a node of the Maxwell-branch law with history (Qh, S0h)."""
+    F, Qh, S0h = _f64(F), _f64(Qh), _f64(S0h)
+    D = F.shape[0]
+    P = np.zeros((D, D))
+    st = lib().orc_visco_piola(D, mu, lam, beta, xi, _d(Qh), _d(S0h), _d(F), _d(P))
+    if st:
+        raise OracleError(st, "visco_piola")
+    return P
+
+
+def visco_piola_jvp(F, dF, mu, lam, beta, xi, Qh, S0h):
+    F, dF, Qh, S0h = _f64(F), _f64(dF), _f64(Qh), _f64(S0h)
+    D = F.shape[0]
+    dP = np.zeros((D, D))
+    st = lib().orc_visco_piola_jvp(D, mu, lam, beta, xi, _d(Qh), _d(S0h), _d(F), _d(dF), _d(dP))
+    if st:
+        raise OracleError(st, "visco_piola_jvp")
+    return dP
+
+
+def visco_path(F, mu, lam, beta, tau, dt):
+    """Stress [n+1][D][D] of a material point of the Maxwell-branch law driven
+    along F [n+1][D][D] (one step dt apart), started relaxed at F[0]."""
+    F = _f64(F)
+    n1, D = F.shape[0], F.shape[1]
+    P = np.zeros_like(F)
+    st = lib().orc_visco_path(D, mu, lam, beta, tau, dt, n1 - 1, _d(F), _d(P))
+    if st:
+        raise OracleError(st, "visco_path")
+    return P
 
 
 def energy(F, mu, lam):
@@ -269,6 +309,31 @@ class Sim:
         st = lib().orc_set_fibres(self.h, float(k1), _d(a))
         if st:
             raise OracleError(st, "set_fibres")
+
+    def set_viscous(self, beta, tau):
+        """Maxwell branch dQ/dt + Q/tau = beta dS_0/dt on top of the law
+        (before set_state; tau = inf: glassy limit, tau = 0: none)."""
+        st = lib().orc_set_viscous(self.h, float(beta), float(tau))
+        if st:
+            raise OracleError(st, "set_viscous")
+
+    def viscous_history(self):
+        """(Q^n, S_0^n) of every node, [D*D][N] each"""
+        Qh = np.zeros((self.D * self.D, self.N))
+        S0 = np.zeros((self.D * self.D, self.N))
+        st = lib().orc_get_viscous(self.h, _d(Qh), _d(S0))
+        if st:
+            raise OracleError(st, "get_viscous")
+        return Qh, S0
+
+    def stress(self):
+        """(P, sigma) of the current state, [D*D][N] each (Eq. 35)"""
+        P = np.zeros((self.D * self.D, self.N))
+        S = np.zeros((self.D * self.D, self.N))
+        st = lib().orc_stress(self.h, _d(P), _d(S))
+        if st:
+            raise OracleError(st, "stress")
+        return P, S
 
     def set_body_force(self, g, ramp=RAMP_CONST, T_r=1.0):
         """Body acceleration b(X, t) = s(t) g(X), g [D][N] (None clears)."""

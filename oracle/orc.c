@@ -151,56 +151,186 @@ int orc_piola_jvp(int D, double mu, double lam, const double *F, const double *d
  *   W = W_NH(F) + (k1/2) (I4 - 1)^2,  I4 = |F a0|^2,
  *   P = P_NH + 2 k1 (I4 - 1) (F a0) (x) a0,
  *   dP = dP_NH + 2 k1 [2 ((F a0).(dF a0)) (F a0) (x) a0 + (I4 - 1) (dF a0) (x) a0].
- * k1 = 0 is the paper's law. */
+ * k1 = 0 is the paper's law.
+ *
+ * Optionally one viscoelastic (Maxwell) branch, the history-dependent law the
+ * outlook names as a local node update (Sec. 6).  The branch adds an
+ * overstress Q to the second Piola stress, P = P_eq(F) + F Q, driven by the
+ * shear part of the neo-Hookean second Piola stress S_0 = mu (I - C^{-1})
+ * (C = F^T F) through the relaxation equation
+ *   dQ/dt + Q / tau = beta dS_0/dt,
+ * i.e. Q(t) = beta int exp(-(t - s)/tau) dS_0/ds ds.  The convolution over one
+ * step taken by the midpoint rule gives the second-order update
+ *   Q^{n+1} = xi^2 Q^n + beta xi (S_0^{n+1} - S_0^n),  xi = exp(-dt/(2 tau)).
+ * At a node the map F -> P therefore depends on the history (Qh, S0h) =
+ * (Q^n, S_0^n) of the last committed step:
+ *   Q(F) = xi^2 Qh + beta xi (S_0(F) - S0h),   P(F) = P_eq(F) + F Q(F),
+ * and its tangent at frozen history is
+ *   dP = dP_eq + dF Q(F) + beta xi F dS_0,  dS_0 = mu C^{-1} dC C^{-1},
+ *   dC = dF^T F + F^T dF.
+ * tau -> infinity (xi = 1) from an undeformed start gives the neo-Hookean
+ * solid with shear modulus mu (1 + beta); tau -> 0 (xi = 0) the equilibrium
+ * law.  Qh = NULL: no branch. */
 typedef struct {
   double mu, lam, k1, a0[3];
+  double beta, xi;
+  const double *Qh, *S0h; /* D x D history of the node, or NULL */
 } orc_mat;
 
 static orc_mat nh_mat(double mu, double lam) {
-  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}};
+  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, 0.0, 0.0, NULL, NULL};
   return m;
+}
+
+/* S_0 = mu (I - C^{-1}), C^{-1}_AB = sum_i F^{-T}_iA F^{-T}_iB */
+static void visco_S0(int D, double mu, const double *F, double *S0, double *Ci) {
+  double C[9], J = det_n(D, F);
+  cof_n(D, F, C);
+  for (int A = 0; A < D; ++A)
+    for (int B = 0; B < D; ++B) {
+      double s = 0.0;
+      for (int i = 0; i < D; ++i) s += C[i * D + A] * C[i * D + B];
+      s /= J * J;
+      if (Ci) Ci[A * D + B] = s;
+      S0[A * D + B] = mu * ((A == B ? 1.0 : 0.0) - s);
+    }
+}
+
+/* overstress Q(F) with the node's history */
+static void visco_Q(int D, const orc_mat *m, const double *F, double *Qv, double *Ci) {
+  double S0[9];
+  visco_S0(D, m->mu, F, S0, Ci);
+  for (int k = 0; k < D * D; ++k) Qv[k] = m->xi * m->xi * m->Qh[k] + m->beta * m->xi * (S0[k] - m->S0h[k]);
 }
 
 static int mat_piola(int D, const orc_mat *m, const double *F, double *P) {
   int st = orc_piola(D, m->mu, m->lam, F, P);
-  if (st || m->k1 == 0.0) return st;
-  double fa[3] = {0.0, 0.0, 0.0}, I4 = 0.0;
-  for (int i = 0; i < D; ++i) {
-    for (int A = 0; A < D; ++A) fa[i] += F[i * D + A] * m->a0[A];
-    I4 += fa[i] * fa[i];
+  if (st) return st;
+  if (m->k1 != 0.0) {
+    double fa[3] = {0.0, 0.0, 0.0}, I4 = 0.0;
+    for (int i = 0; i < D; ++i) {
+      for (int A = 0; A < D; ++A) fa[i] += F[i * D + A] * m->a0[A];
+      I4 += fa[i] * fa[i];
+    }
+    for (int i = 0; i < D; ++i)
+      for (int A = 0; A < D; ++A) P[i * D + A] += 2.0 * m->k1 * (I4 - 1.0) * fa[i] * m->a0[A];
   }
-  for (int i = 0; i < D; ++i)
-    for (int A = 0; A < D; ++A) P[i * D + A] += 2.0 * m->k1 * (I4 - 1.0) * fa[i] * m->a0[A];
+  if (m->Qh) {
+    double Qv[9];
+    visco_Q(D, m, F, Qv, NULL);
+    for (int i = 0; i < D; ++i)
+      for (int A = 0; A < D; ++A) {
+        double s = 0.0;
+        for (int B = 0; B < D; ++B) s += F[i * D + B] * Qv[B * D + A];
+        P[i * D + A] += s;
+      }
+  }
   return ORC_OK;
 }
 
 static int mat_piola_jvp(int D, const orc_mat *m, const double *F, const double *dF, double *dP) {
   int st = orc_piola_jvp(D, m->mu, m->lam, F, dF, dP);
-  if (st || m->k1 == 0.0) return st;
-  double fa[3] = {0.0, 0.0, 0.0}, dfa[3] = {0.0, 0.0, 0.0}, I4 = 0.0, dI = 0.0;
-  for (int i = 0; i < D; ++i) {
-    for (int A = 0; A < D; ++A) {
-      fa[i] += F[i * D + A] * m->a0[A];
-      dfa[i] += dF[i * D + A] * m->a0[A];
+  if (st) return st;
+  if (m->k1 != 0.0) {
+    double fa[3] = {0.0, 0.0, 0.0}, dfa[3] = {0.0, 0.0, 0.0}, I4 = 0.0, dI = 0.0;
+    for (int i = 0; i < D; ++i) {
+      for (int A = 0; A < D; ++A) {
+        fa[i] += F[i * D + A] * m->a0[A];
+        dfa[i] += dF[i * D + A] * m->a0[A];
+      }
+      I4 += fa[i] * fa[i];
+      dI += fa[i] * dfa[i];
     }
-    I4 += fa[i] * fa[i];
-    dI += fa[i] * dfa[i];
+    for (int i = 0; i < D; ++i)
+      for (int A = 0; A < D; ++A)
+        dP[i * D + A] += 2.0 * m->k1 * (2.0 * dI * fa[i] + (I4 - 1.0) * dfa[i]) * m->a0[A];
   }
-  for (int i = 0; i < D; ++i)
+  if (m->Qh) {
+    double Qv[9], Ci[9], dC[9], W[9], dS0[9];
+    visco_Q(D, m, F, Qv, Ci);
     for (int A = 0; A < D; ++A)
-      dP[i * D + A] += 2.0 * m->k1 * (2.0 * dI * fa[i] + (I4 - 1.0) * dfa[i]) * m->a0[A];
+      for (int B = 0; B < D; ++B) {
+        double s = 0.0;
+        for (int i = 0; i < D; ++i) s += dF[i * D + A] * F[i * D + B] + F[i * D + A] * dF[i * D + B];
+        dC[A * D + B] = s;
+      }
+    for (int A = 0; A < D; ++A) /* W = C^{-1} dC */
+      for (int B = 0; B < D; ++B) {
+        double s = 0.0;
+        for (int K = 0; K < D; ++K) s += Ci[A * D + K] * dC[K * D + B];
+        W[A * D + B] = s;
+      }
+    for (int A = 0; A < D; ++A) /* dS0 = mu W C^{-1} */
+      for (int B = 0; B < D; ++B) {
+        double s = 0.0;
+        for (int K = 0; K < D; ++K) s += W[A * D + K] * Ci[K * D + B];
+        dS0[A * D + B] = m->mu * s;
+      }
+    for (int i = 0; i < D; ++i)
+      for (int A = 0; A < D; ++A) {
+        double s = 0.0;
+        for (int B = 0; B < D; ++B)
+          s += dF[i * D + B] * Qv[B * D + A] + m->beta * m->xi * F[i * D + B] * dS0[B * D + A];
+        dP[i * D + A] += s;
+      }
+  }
+  return ORC_OK;
+}
+
+/* advance a node's history with the deformation F the step used:
+ * (Qh, S0h) <- (Q(F), S_0(F)) */
+static void visco_commit(int D, const orc_mat *m, const double *F, double *Qh, double *S0h) {
+  double Qv[9], S0[9];
+  visco_Q(D, m, F, Qv, NULL);
+  visco_S0(D, m->mu, F, S0, NULL);
+  for (int k = 0; k < D * D; ++k) {
+    Qh[k] = Qv[k];
+    S0h[k] = S0[k];
+  }
+}
+
+/* exported forms of the Maxwell-branch maps (pins) */
+int orc_visco_piola(int D, double mu, double lam, double beta, double xi, const double *Qh, const double *S0h,
+                    const double *F, double *P) {
+  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, beta, xi, Qh, S0h};
+  return mat_piola(D, &m, F, P);
+}
+
+int orc_visco_piola_jvp(int D, double mu, double lam, double beta, double xi, const double *Qh, const double *S0h,
+                        const double *F, const double *dF, double *dP) {
+  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, beta, xi, Qh, S0h};
+  return mat_piola_jvp(D, &m, F, dF, dP);
+}
+
+/* a material point driven along F[0..n] (one step apart): history started
+ * relaxed at F[0] (Q = 0, S0h = S_0(F[0])); at each step the stress of the
+ * current F with the stored history, then the history advance, the order a
+ * lattice node takes them in */
+int orc_visco_path(int D, double mu, double lam, double beta, double tau, double dt, int64_t n, const double *F,
+                   double *P) {
+  double Qh[9] = {0.0}, S0h[9];
+  if (!(tau >= 0.0) || !(dt > 0.0)) return ORC_ERR_ARG;
+  const double xi = exp(-dt / (2.0 * tau));
+  visco_S0(D, mu, F, S0h, NULL);
+  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, beta, xi, Qh, S0h};
+  for (int64_t k = 0; k <= n; ++k) {
+    const double *Fk = F + (size_t)k * D * D;
+    int st = mat_piola(D, &m, Fk, P + (size_t)k * D * D);
+    if (st) return st;
+    visco_commit(D, &m, Fk, Qh, S0h);
+  }
   return ORC_OK;
 }
 
 /* exported forms of the material maps (law with fibres) */
 int orc_piola_law(int D, double mu, double lam, double k1, const double *a0, const double *F, double *P) {
-  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}};
+  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}, 0.0, 0.0, NULL, NULL};
   return mat_piola(D, &m, F, P);
 }
 
 int orc_piola_law_jvp(int D, double mu, double lam, double k1, const double *a0, const double *F,
                       const double *dF, double *dP) {
-  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}};
+  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}, 0.0, 0.0, NULL, NULL};
   return mat_piola_jvp(D, &m, F, dF, dP);
 }
 
@@ -524,6 +654,9 @@ struct orc_sim {
   double *bf;
   int bf_ramp;
   double bf_Tr;
+  /* Maxwell branch (orc_set_viscous): history [N][D*D] of every node, or NULL */
+  double vbeta, vtau, vxi;
+  double *Qh, *S0h;
 };
 
 static void coords(const orc_sim *s, int64_t i, int *c) {
@@ -633,6 +766,8 @@ void orc_destroy(orc_sim *s) {
   free(s->u0);
   free(s->dU0);
   free(s->bf);
+  free(s->Qh);
+  free(s->S0h);
   free(s->act);
   free(s);
 }
@@ -806,6 +941,31 @@ int orc_set_fibres(orc_sim *s, double k1, const double *a0) {
   return ORC_OK;
 }
 
+int orc_set_viscous(orc_sim *s, double beta, double tau) {
+  if (!(beta >= 0.0) || !(tau >= 0.0)) return ORC_ERR_ARG;
+  if (!s->Qh) {
+    s->Qh = (double *)calloc((size_t)s->N * s->D * s->D, sizeof(double));
+    s->S0h = (double *)calloc((size_t)s->N * s->D * s->D, sizeof(double));
+    if (!s->Qh || !s->S0h) return ORC_ERR_MEM;
+  }
+  s->vbeta = beta;
+  s->vtau = tau;
+  s->vxi = exp(-s->dt / (2.0 * tau)); /* tau = 0: 0; tau = inf: 1 */
+  s->have_state = 0;                  /* the history starts at orc_set_state */
+  return ORC_OK;
+}
+
+int orc_get_viscous(orc_sim *s, double *Qh, double *S0h) {
+  int DD = s->D * s->D;
+  if (!s->Qh) return ORC_ERR_ARG;
+  for (int64_t i = 0; i < s->N; ++i)
+    for (int k = 0; k < DD; ++k) {
+      if (Qh) Qh[(size_t)k * s->N + i] = s->act[i] ? s->Qh[(size_t)i * DD + k] : 0.0;
+      if (S0h) S0h[(size_t)k * s->N + i] = s->act[i] ? s->S0h[(size_t)i * DD + k] : 0.0;
+    }
+  return ORC_OK;
+}
+
 int orc_set_body_force(orc_sim *s, const double *g, int ramp, double T_r) {
   free(s->bf);
   s->bf = NULL;
@@ -941,10 +1101,18 @@ int orc_bc_data(orc_sim *s, int bid, const double *X, const double *Nb, double t
   return ORC_OK;
 }
 
-/* material of the simulation with the given (mu, lambda) */
-static orc_mat sim_mat(const orc_sim *s, double mu, double lam) {
-  orc_mat m = {mu, lam, s->k1, {s->a0[0], s->a0[1], s->a0[2]}};
-  return m;
+/* material of node m of the simulation with the given (mu, lambda); with a
+ * Maxwell branch it carries the node's history (m < 0: none) */
+static orc_mat sim_mat(const orc_sim *s, double mu, double lam, int64_t m) {
+  orc_mat mat = {mu, lam, s->k1, {s->a0[0], s->a0[1], s->a0[2]}, 0.0, 0.0, NULL, NULL};
+  if (s->Qh && m >= 0) {
+    size_t o = (size_t)m * s->D * s->D;
+    mat.beta = s->vbeta;
+    mat.xi = s->vxi;
+    mat.Qh = s->Qh + o;
+    mat.S0h = s->S0h + o;
+  }
+  return mat;
 }
 
 /* body acceleration at node i and time t (zero without a field) */
@@ -962,11 +1130,11 @@ static void body_acc(const orc_sim *s, int64_t i, double t, double *b) {
  * with the directional derivatives taken through the equilibrium derivative
  * of Eq. 27.  With no gradients supplied the spatial terms vanish. */
 /* populations of one node from U0 and its derivatives dA[A*M + r] */
-static void init_node(const orc_sim *s, double mu, double lam, const double *U, const double *dA,
+static void init_node(const orc_sim *s, int64_t node, double mu, double lam, const double *U, const double *dA,
                       const double *b0, double *f) {
   int D = s->D, M = s->M, Q = s->Q;
   double Ut[MAXM], feq[MAXQ * MAXM], dPhi[MAXD * MAXM];
-  const orc_mat mat = sim_mat(s, mu, lam);
+  const orc_mat mat = sim_mat(s, mu, lam, node);
   /* B0 = (b0 - gamma v0, 0): body acceleration and velocity damping */
   for (int r = 0; r < M; ++r) Ut[r] = (r < D) ? b0[r] - s->gamma * U[r] : 0.0;
   for (int A = 0; A < D; ++A) {
@@ -1027,7 +1195,12 @@ int orc_set_state(orc_sim *s, const double *U0, const double *u0, const double *
         dA[A * M + r] = dU0 ? dU0[((size_t)A * M + r) * s->N + i] : 0.0;
     double b0[MAXD];
     body_acc(s, i, s->step * s->dt, b0);
-    init_node(s, s->mu, s->lam, U, dA, b0, f);
+    if (s->Qh) { /* the branch starts relaxed at F0: Q = 0, S0h = S_0(F0) */
+      double *Qh = s->Qh + (size_t)i * D * D, *S0h = s->S0h + (size_t)i * D * D;
+      for (int k = 0; k < D * D; ++k) Qh[k] = 0.0;
+      visco_S0(D, s->mu, U + D, S0h, NULL);
+    }
+    init_node(s, i, s->mu, s->lam, U, dA, b0, f);
     for (int a = 0; a < D; ++a) {
       double u0a = u0 ? u0[(size_t)a * s->N + i] : 0.0;
       s->ustar[i * D + a] = u0a - 0.5 * s->dt * U[a]; /* so that u^0 = u0 (Eq. 34) */
@@ -1323,7 +1496,7 @@ static int neumann_Fb(orc_sim *s, const orc_link *L, double th, int count, doubl
     h0[i] = acc;
   }
   int its = 0;
-  const orc_mat mat = sim_mat(s, s->mu, s->lam);
+  const orc_mat mat = sim_mat(s, s->mu, s->lam, L->m);
   int conv = newton_m(D, &mat, L->N, Gt, T, h0, 1e-12, h, &its);
   if (count) {
 #pragma omp atomic
@@ -1367,7 +1540,7 @@ static int close_link(orc_sim *s, const orc_link *L, double tn) {
   } else if (b->type == ORC_BC_NEUMANN) {
     double Gt[9], Fb[9], Pb[9];
     ok = neumann_Fb(s, L, th, 1, Gt, Fb);
-    const orc_mat mat = sim_mat(s, s->mu, s->lam);
+    const orc_mat mat = sim_mat(s, s->mu, s->lam, L->m);
     mat_piola(D, &mat, Fb, Pb);
     /* Eqs. 46-47: D_N = diag(I_D, -I_D2), S^v_i = -d_A P_b,iA / c,
      * S^F_iB = F_b,iB / D ; the density divides the stress flux */
@@ -1422,7 +1595,7 @@ static void project_pre(orc_sim *s, double tn) {
     for (int r = 0; r < M; ++r) Ur[r] = U[r];
     for (int k = 0; k < D * D; ++k)
       Ur[D + k] = (1.0 - s->theta) * U[D + k] + s->theta * Fc[(size_t)m * D * D + k];
-    const orc_mat mat = sim_mat(s, s->mu, s->lam);
+    const orc_mat mat = sim_mat(s, s->mu, s->lam, m);
     feq_m(D, s->c, &mat, s->rho0, U, fe0);
     feq_m(D, s->c, &mat, s->rho0, Ur, fe1);
     double *f = s->f + (size_t)m * Q * M;
@@ -1460,7 +1633,7 @@ int orc_step(orc_sim *s, int64_t nsteps) {
       if (!s->act[m]) continue;
       const double *U = s->U + (size_t)m * M;
       double feq[MAXQ * MAXM], B[MAXM], b[MAXD];
-      const orc_mat mat = sim_mat(s, s->mu, s->lam);
+      const orc_mat mat = sim_mat(s, s->mu, s->lam, m);
       feq_m(D, s->c, &mat, s->rho0, U, feq);
       body_acc(s, m, tn, b);
       for (int r = 0; r < M; ++r) B[r] = (r < D) ? b[r] - s->gamma * U[r] : 0.0;
@@ -1471,6 +1644,10 @@ int orc_step(orc_sim *s, int64_t nsteps) {
           fs[q * M + r] = f[q * M + r] + s->omega * (feq[q * M + r] - f[q * M + r]) +
                           s->dt * (2.0 - s->omega) * B[r] / (4.0 * D);
       for (int a = 0; a < D; ++a) s->ustar[m * D + a] = s->u[m * D + a] + 0.5 * s->dt * U[a];
+      /* the Maxwell branch commits the deformation this collision used (the
+       * repaired one on a projection step); the cut-link closures of the
+       * step, which follow, see the advanced history (reading) */
+      if (s->Qh) visco_commit(D, &mat, U + D, s->Qh + (size_t)m * D * D, s->S0h + (size_t)m * D * D);
     }
     if (proj) {
       /* second displacement projection with the repaired F; the history reset
@@ -1526,6 +1703,36 @@ int orc_moments(orc_sim *s, double *Uo, double *uo, double *Jo) {
     if (uo)
       for (int k = 0; k < D; ++k) uo[(size_t)k * s->N + i] = a ? s->u[i * D + k] : 0.0;
     if (Jo) Jo[i] = a ? det_n(D, U + D) : 0.0;
+  }
+  return st;
+}
+
+/* stress of the current state at every active node: P = P(F) with the
+ * node's law (and the history of the Maxwell branch as the next collision
+ * would use it), sigma = J^{-1} P F^T (Sec. 2.4, Eq. 35); planar [D*D][N],
+ * zero at inactive nodes; either may be NULL */
+int orc_stress(orc_sim *s, double *Po, double *So) {
+  int D = s->D, M = s->M;
+  if (!s->have_state) return ORC_ERR_ORDER;
+  int st = recover(s);
+  for (int64_t i = 0; i < s->N; ++i) {
+    double P[9] = {0.0}, sg[9] = {0.0};
+    if (s->act[i]) {
+      const double *F = s->U + (size_t)i * M + D;
+      const orc_mat mat = sim_mat(s, s->mu, s->lam, i);
+      if (mat_piola(D, &mat, F, P)) st = st ? st : ORC_ERR_J;
+      double J = det_n(D, F);
+      for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) {
+          double acc = 0.0;
+          for (int A = 0; A < D; ++A) acc += P[a * D + A] * F[b * D + A];
+          sg[a * D + b] = acc / J;
+        }
+    }
+    for (int k = 0; k < D * D; ++k) {
+      if (Po) Po[(size_t)k * s->N + i] = P[k];
+      if (So) So[(size_t)k * s->N + i] = sg[k];
+    }
   }
   return st;
 }
@@ -1695,7 +1902,7 @@ static void feq_vjp(const orc_sim *s, double mu, double lam, const double *U, co
   for (int r = 0; r < M; ++r) {
     double e[MAXM] = {0}, d[MAXQ * MAXM], acc = 0.0;
     e[r] = 1.0;
-    const orc_mat mat = sim_mat(s, mu, lam);
+    const orc_mat mat = sim_mat(s, mu, lam, -1);
     feq_jvp_m(s->D, s->c, &mat, s->rho0, U, e, d);
     for (int k = 0; k < Q * M; ++k) acc += lq[k] * d[k];
     out[r] = acc;
@@ -1938,7 +2145,7 @@ static void neumann_adj(orc_sim *s, const orc_link *L, double th, const double *
   /* S^v_i = -sum_B d_B P_iB / (rho0 c), S^F_iB = F_b,iB / D */
   for (int i = 0; i < D; ++i)
     for (int B = 0; B < D; ++B) W[i * D + B] = -Sbar[i] * d[B] / (s->rho0 * s->c);
-  const orc_mat mat = sim_mat(s, s->mu, s->lam);
+  const orc_mat mat = sim_mat(s, s->mu, s->lam, -1);
   piola_vjp(D, &mat, Fb, W, Fbb);
   for (int k = 0; k < D * D; ++k) Fbb[k] += Sbar[D + k] / D;
   piola_dp(D, s->mu, s->lam, Fb, W, gmat);
@@ -1989,7 +2196,7 @@ int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dL
   int64_t N = s->N;
   if (!s->have_state || s->init_step != s->step || !s->U0) return ORC_ERR_ORDER;
   if (s->status) return s->status;
-  if (nsteps < 0) return ORC_ERR_ARG;
+  if (nsteps < 0 || s->Qh) return ORC_ERR_ARG; /* no reverse mode through a Maxwell branch */
   int has_neu = 0, has_dir = 0;
   for (int64_t l = 0; l < s->nl; ++l) {
     int t = s->bc[s->links[l].bid].type;
@@ -2229,11 +2436,11 @@ int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dL
         for (int r = 0; r < M; ++r) dA[A * M + r] = s->dU0[((size_t)A * M + r) * N + m];
       double b0[MAXD];
       body_acc(s, m, s->init_step * s->dt, b0);
-      init_node(s, s->mu, s->lam, U, dA, b0, f0);
+      init_node(s, -1, s->mu, s->lam, U, dA, b0, f0);
       for (int a = 0; a < D; ++a) {
         double acc = 0.0;
         U[a] += 1.0;
-        init_node(s, s->mu, s->lam, U, dA, b0, f1);
+        init_node(s, -1, s->mu, s->lam, U, dA, b0, f1);
         U[a] -= 1.0;
         for (int k2 = 0; k2 < Q * M; ++k2) acc += l0[k2] * (f1[k2] - f0[k2]);
         if (grad_v0) grad_v0[(size_t)a * N + m] = acc - 0.5 * s->dt * lus[m * D + a];
@@ -2245,16 +2452,16 @@ int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dL
         for (int k2 = 0; k2 < D * M; ++k2) {
           double acc = 0.0;
           dA[k2] += 1.0;
-          init_node(s, s->mu, s->lam, U, dA, b0, f1);
+          init_node(s, -1, s->mu, s->lam, U, dA, b0, f1);
           dA[k2] -= 1.0;
           for (int k3 = 0; k3 < Q * M; ++k3) acc += l0[k3] * (f1[k3] - f0[k3]);
           grad_dU0[(size_t)k2 * N + m] = acc;
         }
-      init_node(s, s->mu + 1.0, s->lam, U, dA, b0, f0);
-      init_node(s, s->mu - 1.0, s->lam, U, dA, b0, f1);
+      init_node(s, -1, s->mu + 1.0, s->lam, U, dA, b0, f0);
+      init_node(s, -1, s->mu - 1.0, s->lam, U, dA, b0, f1);
       for (int k2 = 0; k2 < Q * M; ++k2) gi[0] += l0[k2] * 0.5 * (f0[k2] - f1[k2]);
-      init_node(s, s->mu, s->lam + 1.0, U, dA, b0, f0);
-      init_node(s, s->mu, s->lam - 1.0, U, dA, b0, f1);
+      init_node(s, -1, s->mu, s->lam + 1.0, U, dA, b0, f0);
+      init_node(s, -1, s->mu, s->lam - 1.0, U, dA, b0, f1);
       for (int k2 = 0; k2 < Q * M; ++k2) gi[1] += l0[k2] * 0.5 * (f0[k2] - f1[k2]);
     }
     gmat[0] += gi[0];

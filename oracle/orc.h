@@ -91,6 +91,23 @@ int  orc_set_body_force(orc_sim *s, const double *g, int ramp, double T_r);
 /* fibre reinforcement W += k1/2 (|F a0|^2 - 1)^2 along the reference
  * direction a0 (normalised; k1 = 0 restores the neo-Hookean law) */
 int  orc_set_fibres(orc_sim *s, double k1, const double *a0);
+/* one viscoelastic (Maxwell) branch on top of the law (the history-dependent
+ * extension of Sec. 6): P = P_eq(F) + F Q, dQ/dt + Q/tau = beta dS_0/dt,
+ * S_0 = mu (I - C^{-1}); per-node history started relaxed at orc_set_state
+ * (call before it).  beta >= 0; tau >= 0 (0: no overstress, INFINITY: the
+ * glassy limit).  No reverse mode with a branch (ORC_ERR_ARG). */
+int  orc_set_viscous(orc_sim *s, double beta, double tau);
+/* the branch's history (Q^n, S_0^n) of every node, planar [D*D][N] each */
+int  orc_get_viscous(orc_sim *s, double *Qh, double *S0h);
+/* point maps of the branch with a given history, and a material point driven
+ * along F[0..n] [n+1][D*D] one step dt apart (P [n+1][D*D]) */
+int  orc_visco_piola(int D, double mu, double lam, double beta, double xi,
+                     const double *Qh, const double *S0h, const double *F, double *P);
+int  orc_visco_piola_jvp(int D, double mu, double lam, double beta, double xi,
+                         const double *Qh, const double *S0h, const double *F,
+                         const double *dF, double *dP);
+int  orc_visco_path(int D, double mu, double lam, double beta, double tau, double dt,
+                    int64_t n, const double *F, double *P);
 /* phi[N] node samples (phi <= 0 inside, Eq. 36); bid[N] boundary ids. */
 int  orc_set_levelset(orc_sim *s, const double *phi, const uint8_t *bid);
 /* boundary value s(t) (a + G (X - X0) + p_radial e_R + p_normal N_b) */
@@ -109,6 +126,10 @@ int  orc_set_state(orc_sim *s, const double *U0, const double *u0,
 int  orc_step(orc_sim *s, int64_t nsteps);
 /* U[M][N] (recovered, Eq. 28), u[D][N] (Eq. 34), J[N]; any may be NULL */
 int  orc_moments(orc_sim *s, double *U, double *u, double *J);
+/* first Piola P[D*D][N] (with each node's law and history) and Cauchy
+ * stress sigma[D*D][N] = J^{-1} P F^T (Eq. 35) of the current state; either
+ * may be NULL */
+int  orc_stress(orc_sim *s, double *P, double *sigma);
 /* pre-collision populations f^n as [Q][M][N] */
 int  orc_get_f(orc_sim *s, double *f);
 int  orc_put_f(orc_sim *s, const double *f, const double *ustar, int64_t step);

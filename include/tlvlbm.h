@@ -80,12 +80,24 @@ typedef struct {
  * law 1: the same solid reinforced by one family of fibres along the unit
  *   reference direction a0 (an anisotropic law as the outlook of Sec. 6
  *   names): W += k1/2 (|F a0|^2 - 1)^2, k1 >= 0; a0 is normalised.
- * k1 and a0 are read for law 1 only. */
+ * law 2: law 1 (k1 = 0: law 0) with one viscoelastic Maxwell branch, the
+ *   history-dependent extension that Sec. 6 names as a local node update:
+ *   an overstress Q in the second Piola stress, P = P_eq(F) + F Q, relaxing
+ *   as dQ/dt + Q / tau = beta dS_0/dt with S_0 = mu (I - C^{-1}),
+ *   C = F^T F, advanced once per step by the midpoint rule on its
+ *   convolution, Q^{n+1} = xi^2 Q^n + beta xi (S_0^{n+1} - S_0^n),
+ *   xi = exp(-dt / (2 tau)).  beta >= 0; tau >= 0 (0: no overstress;
+ *   INFINITY: the glassy limit, a neo-Hookean solid of shear modulus
+ *   mu (1 + beta) from an undeformed start).  Every active node keeps the
+ *   branch's history (D(D+1)/2 FP64 values), started relaxed at F0 by
+ *   tlvlbm_set_state.
+ * k1 and a0 are read for laws 1 and 2, beta and tau for law 2 only. */
 typedef struct {
   int32_t law;
   double mu, lambda;
   double k1;
   double a0[3];
+  double beta, tau;
 } tlvlbm_material;
 
 /* Run options (tlvlbm_default_options fills the paper's settings of
@@ -202,7 +214,9 @@ tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *ctx, uint8_t bid, const tlvlbm_bc 
 tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *ctx, const double *g, int32_t ramp, double T_r);
 
 /* Replace the material (e.g. for finite-difference sweeps).  The stored
- * populations are kept. */
+ * populations are kept.  When the old or the new material has a Maxwell
+ * branch (law 2), the branch's history starts anew: tlvlbm_step returns
+ * CALL_ORDER until the next tlvlbm_set_state. */
 tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *ctx, const tlvlbm_material *mat);
 
 /* Initial state (Sec. 2.1, Eq. 6).  U0[M][N]; u0[D][N] or NULL (zero);
@@ -228,9 +242,18 @@ tlvlbm_status tlvlbm_step(tlvlbm_ctx *ctx, int64_t n);
  * (det F).  Any output may be NULL. */
 tlvlbm_status tlvlbm_moments(tlvlbm_ctx *ctx, double *U_out, double *u_out, double *J_out);
 
+/* Stress of the current time level (the final diagnostics of Algorithm 1):
+ * first Piola P_out[D*D][N] of the recovered F with the material law (with
+ * a Maxwell branch: its history as the next collision uses it) and Cauchy
+ * stress sigma_out[D*D][N] = J^{-1} P F^T (Sec. 2.4, Eq. 35), row-major
+ * components, FP64, host or device; zero at inactive nodes.  Either may be
+ * NULL. */
+tlvlbm_status tlvlbm_stress(tlvlbm_ctx *ctx, double *P_out, double *sigma_out);
+
 /* Raw state for checkpoint/resume: pre-collision populations f^n as
  * [2D][M][N] and the displacement history u*^n as [D][N] (either may be
- * NULL), plus the step index. */
+ * NULL), plus the step index.  The history of a Maxwell branch is not part
+ * of it: tlvlbm_put_state keeps the branch's history as it is. */
 tlvlbm_status tlvlbm_get_state(tlvlbm_ctx *ctx, double *f, double *ustar, int64_t *step);
 tlvlbm_status tlvlbm_put_state(tlvlbm_ctx *ctx, const double *f, const double *ustar, int64_t step);
 
@@ -285,7 +308,8 @@ const char *tlvlbm_last_error(const tlvlbm_ctx *ctx);
  *    recomputation of the checkpointed steps without projection solves, one
  *    reverse pass (the transposed projection sweeps on projection steps).
  *  - Errors: the forward's errors; TLVLBM_ERR_CALL_ORDER without a fresh
- *    state.  A failure leaves the context in an error state. */
+ *    state; TLVLBM_ERR_INVALID_ARG with a body acceleration or a Maxwell
+ *    branch (law 2).  A failure leaves the context in an error state. */
 tlvlbm_status tlvlbm_adjoint_step(tlvlbm_ctx *ctx, int64_t n, const double *U0, const double *dU0,
                                   const double *dLdU, const double *dLdu, double *grad_mat, double *grad_v0,
                                   double *grad_u0, int64_t segment);
@@ -340,7 +364,10 @@ tlvlbm_status tlvlbm_adjoint_backward(tlvlbm_ctx *ctx, const double *dLdU, const
  * summation order.  Errors of any instance are reported (and made sticky on
  * that context).  The projection phases run over every instance, so either
  * all instances have Neumann links or none has (TLVLBM_ERR_INVALID_ARG for a
- * mixed set: the projection belongs to lattices with Neumann links only). */
+ * mixed set: the projection belongs to lattices with Neumann links only).
+ * The batched bulk update is that of law 0: instances with fibres, a
+ * Maxwell branch or a body acceleration are refused (TLVLBM_ERR_INVALID_ARG;
+ * tlvlbm_step_each takes them). */
 typedef struct tlvlbm_batch tlvlbm_batch;
 tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t n, int64_t steps);
 tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_batch **out);

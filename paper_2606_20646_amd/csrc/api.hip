@@ -75,23 +75,39 @@ bool has_neumann(const tlvlbm_ctx *c) {
 
 namespace tl {
 
-// law 0: neo-Hookean; law 1: with fibres (k1 >= 0, a0 not zero)
+// law 0: neo-Hookean; law 1: with fibres (k1 >= 0, a0 not zero); law 2:
+// law 1 (or law 0 when k1 = 0) with a Maxwell branch (beta >= 0, tau >= 0)
 static bool material_ok(const tlvlbm_material *m) {
-  if (!m || (m->law != 0 && m->law != 1)) return false;
-  if (m->law == 1) {
+  if (!m || m->law < 0 || m->law > 2) return false;
+  if (m->law >= 1) {
     const double n = m->a0[0] * m->a0[0] + m->a0[1] * m->a0[1] + m->a0[2] * m->a0[2];
-    if (!(m->k1 >= 0) || !(n > 0)) return false;
+    if (!(m->k1 >= 0) || (m->law == 1 && !(n > 0)) || (m->k1 > 0 && !(n > 0))) return false;
   }
+  if (m->law == 2 && (!(m->beta >= 0) || !(m->tau >= 0))) return false;
   return true;
 }
 
-static void set_material_par(Par &p, const tlvlbm_material *m, int D) {
+static void set_material_par(tlvlbm_ctx *c, const tlvlbm_material *m) {
+  Par &p = c->par;
+  const int D = c->D;
   p.mu = m->mu;
   p.lam = m->lambda;
-  p.k1 = m->law == 1 ? m->k1 : 0.0;
+  p.k1 = m->law >= 1 ? m->k1 : 0.0;
   double n = 0.0;
   for (int a = 0; a < D; ++a) n += m->a0[a] * m->a0[a];
-  for (int a = 0; a < 3; ++a) p.a0[a] = (m->law == 1 && a < D) ? m->a0[a] / std::sqrt(n) : 0.0;
+  for (int a = 0; a < 3; ++a) p.a0[a] = (p.k1 > 0 && a < D) ? m->a0[a] / std::sqrt(n) : 0.0;
+  c->visco = m->law == 2;
+  c->vbeta = c->visco ? m->beta : 0.0;
+  c->vtau = c->visco ? m->tau : 0.0;
+  p.hist = nullptr;  // attached by set_state
+}
+
+// branch constants beta xi and xi^2, xi = exp(-dt / (2 tau)) (tau = 0: 0,
+// tau = infinity: 1)
+static void set_branch_par(tlvlbm_ctx *c) {
+  const double xi = c->visco ? std::exp(-c->par.dt / (2.0 * c->vtau)) : 0.0;
+  c->par.vbx = c->vbeta * xi;
+  c->par.vxi2 = xi * xi;
 }
 
 tlvlbm_status check_flag(tlvlbm_ctx *c) { return read_flag(c); }
@@ -227,7 +243,7 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   c->geo.ox = grid->origin[0];
   c->geo.oy = grid->origin[1];
   c->geo.oz = D == 3 ? grid->origin[2] : 0.0;
-  set_material_par(c->par, mat, D);
+  set_material_par(c, mat);
   for (int k = 0; k < 9; ++k) {
     c->par.Fref[k] = (k < D * D && k % (D + 1) == 0) ? 1.0 : 0.0;
     c->par.Pref[k] = 0.0;
@@ -235,6 +251,7 @@ tlvlbm_status tlvlbm_create(const tlvlbm_grid *grid, tlvlbm_lattice lattice, con
   c->par.inv_rho0 = 1.0 / rho0;
   c->par.dt = dt;
   c->par.c = grid->dx / dt;
+  set_branch_par(c);
   c->par.omega = o.omega;
   c->par.gamma = o.gamma;
   c->theta = o.theta_F;
@@ -278,7 +295,7 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
                   c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles,
-                  c->cg.nbm, c->bf, c->chunks, c->cpos, c->d_bcs};
+                  c->cg.nbm, c->bf, c->chunks, c->cpos, c->d_bcs, c->hist};
   for (void *p : ptrs)
     if (p) dfree(c, p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
@@ -411,7 +428,10 @@ tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *c, const double *g, int32_t ramp
 tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *c, const tlvlbm_material *m) {
   if (!c || !material_ok(m)) return TLVLBM_ERR_INVALID_ARG;
   rec_invalidate(c);
-  set_material_par(c->par, m, c->D);
+  // a Maxwell branch (before or after) starts its history at set_state
+  if (c->visco || m->law == 2) c->have_state = false;
+  set_material_par(c, m);
+  set_branch_par(c);
   return TLVLBM_OK;
 }
 
@@ -434,6 +454,12 @@ tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0
       CHK(dmalloc(c, &c->ustar, (size_t)D * S * sizeof(double)), "u* alloc");
       CHK(dmalloc(c, &c->ubuf, (size_t)D * S * sizeof(double)), "u alloc");
       CHK(hipMemsetAsync(c->ubuf, 0, (size_t)D * S * sizeof(double), c->st), "u clear");
+    }
+    // the Maxwell branch's history (the initialisation starts it at F0)
+    c->par.hist = nullptr;
+    if (c->visco) {
+      if (!c->hist) CHK(dmalloc(c, &c->hist, (size_t)(D * (D + 1) / 2) * S * sizeof(double)), "history alloc");
+      c->par.hist = c->hist;
     }
     DevIn dU, du, ddU;
     CHK(dU.take(U0, (size_t)M * N * sizeof(double), c->st), "U0 upload");
@@ -542,6 +568,22 @@ tlvlbm_status tlvlbm_moments(tlvlbm_ctx *c, double *U_out, double *u_out, double
   CHK(U.finish(c->st), "U copy");
   CHK(u.finish(c->st), "u copy");
   CHK(J.finish(c->st), "J copy");
+  CHK(hipStreamSynchronize(c->st), "synchronize");
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_stress(tlvlbm_ctx *c, double *P_out, double *sigma_out) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  if (!c->have_state) return fail(c, TLVLBM_ERR_CALL_ORDER, "stress before set_state");
+  const int64_t N = c->geo.N;
+  const size_t bytes = (size_t)c->D * c->D * N * sizeof(double);
+  DevOut P, S;
+  CHK(P.take(P_out, bytes), "P alloc");
+  CHK(S.take(sigma_out, bytes), "sigma alloc");
+  launch_stress(c, (double *)P.ptr, (double *)S.ptr);
+  CHK(hipGetLastError(), "stress launch");
+  CHK(P.finish(c->st), "P copy");
+  CHK(S.finish(c->st), "sigma copy");
   CHK(hipStreamSynchronize(c->st), "synchronize");
   return TLVLBM_OK;
 }

@@ -97,7 +97,7 @@ template <typename T> __device__ __forceinline__ bool finite_(T v) { return __bu
 // collision with source + displacement quadrature (Algorithm 1, bulk loops).
 // TAPE: also store the recovered (pre-repair) F - I to the tape planes of
 // the reverse mode, plane k at tape[k * ts + tslot].
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool TAPE = false, bool EXT = false>
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool TAPE = false, class L = NeoHookean<D>>
 __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restrict__ fout, const Geo &g,
                                           const Par &p, const uint8_t *__restrict__ act, double *__restrict__ ustar,
                                           double *__restrict__ ubuf, const T *__restrict__ Frp,
@@ -127,20 +127,19 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
   T bacc[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) bacc[i] = (EXT && bf) ? bs * bf[(size_t)i * g.S + node] : T(0);
+  for (int i = 0; i < D; ++i) bacc[i] = (L::body && bf) ? bs * bf[(size_t)i * g.S + node] : T(0);
   // the sums are v and F - Fref (populations stored about the reference
   // state); F and its stress P(F) in FP64, which enters the equilibrium as
   // the difference P(F)/rho0 - Pref
   T v[D], dP[D * D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) v[i] = (EXT ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
+  for (int i = 0; i < D; ++i) v[i] = (L::body ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
   double F[D * D], P[D * D];
 #pragma unroll
   for (int k = 0; k < D * D; ++k) F[k] = p.Fref[k] + double(dU[D + k]);
-  double J = piola<D>(F, p.mu, p.lam, P);
-  if constexpr (EXT) {
-    if (p.k1 != 0.0) fibre_add<D>(F, p.k1, p.a0, P);
-  }
+  typename L::Node law;  // the law's internal variables at the node
+  L::load(p, node, g.S, law);
+  double J = L::stress(p, F, law, P);
   bool bad = !(J > 0.0);
   if constexpr (TAPE) {
     if (tape) {
@@ -156,10 +155,7 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
     double Fr[D * D], P1[D * D];
 #pragma unroll
     for (int k = 0; k < D * D; ++k) Fr[k] = double(Frp[(size_t)k * g.S + node]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
-    const double J1 = piola<D>(Fr, p.mu, p.lam, P1);
-    if constexpr (EXT) {
-      if (p.k1 != 0.0) fibre_add<D>(Fr, p.k1, p.a0, P1);
-    }
+    const double J1 = L::stress(p, Fr, law, P1);
     bad |= !(J1 > 0.0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -179,6 +175,8 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
   }
 #pragma unroll
   for (int k = 0; k < D * D; ++k) dP[k] = T(P[k] * p.inv_rho0 - p.Pref[k]);
+  // internal variables advance with the deformation the collision uses
+  L::commit(p, law, node, g.S);
 
   // BGK collision with source weights 1/(4D) (Eqs. 29-30) in the stored
   // variables: feq_q(U) - feq_q(0, Fref) = (v, F - Fref)/(2D)
@@ -206,7 +204,7 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
       }
       const T feq = iso[r] + sg * inv2c * phi;
       T out = f[q][r] + om * (feq - f[q][r]);
-      if (r < D) out += srcw * (EXT ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
+      if (r < D) out += srcw * (L::body ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
     }
   }
@@ -236,7 +234,7 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
 // device function above, the compiler schedules its address arithmetic
 // differently and the kernel runs 2.6% slower at 256^3 (measured).  The two
 // bodies are kept identical (a CPU test compares them).
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool EXT = false>
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, class L = NeoHookean<D>>
 __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
                                                const uint8_t *__restrict__ act, double *__restrict__ ustar,
                                                double *__restrict__ ubuf, const T *__restrict__ Frp,
@@ -267,20 +265,19 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
   const T inv_damp = T(1) / (T(1) + T(0.5) * T(p.gamma) * dt);
   T bacc[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) bacc[i] = (EXT && bf) ? bs * bf[(size_t)i * g.S + node] : T(0);
+  for (int i = 0; i < D; ++i) bacc[i] = (L::body && bf) ? bs * bf[(size_t)i * g.S + node] : T(0);
   // the sums are v and F - Fref (populations stored about the reference
   // state); F and its stress P(F) in FP64, which enters the equilibrium as
   // the difference P(F)/rho0 - Pref
   T v[D], dP[D * D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) v[i] = (EXT ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
+  for (int i = 0; i < D; ++i) v[i] = (L::body ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
   double F[D * D], P[D * D];
 #pragma unroll
   for (int k = 0; k < D * D; ++k) F[k] = p.Fref[k] + double(dU[D + k]);
-  double J = piola<D>(F, p.mu, p.lam, P);
-  if constexpr (EXT) {
-    if (p.k1 != 0.0) fibre_add<D>(F, p.k1, p.a0, P);
-  }
+  typename L::Node law;  // the law's internal variables at the node
+  L::load(p, node, g.S, law);
+  double J = L::stress(p, F, law, P);
   bool bad = !(J > 0.0);
   const T inv2c = T(0.5) / T(p.c);
 
@@ -290,10 +287,7 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
     double Fr[D * D], P1[D * D];
 #pragma unroll
     for (int k = 0; k < D * D; ++k) Fr[k] = double(Frp[(size_t)k * g.S + node]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
-    const double J1 = piola<D>(Fr, p.mu, p.lam, P1);
-    if constexpr (EXT) {
-      if (p.k1 != 0.0) fibre_add<D>(Fr, p.k1, p.a0, P1);
-    }
+    const double J1 = L::stress(p, Fr, law, P1);
     bad |= !(J1 > 0.0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -313,6 +307,8 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
   }
 #pragma unroll
   for (int k = 0; k < D * D; ++k) dP[k] = T(P[k] * p.inv_rho0 - p.Pref[k]);
+  // internal variables advance with the deformation the collision uses
+  L::commit(p, law, node, g.S);
 
   // BGK collision with source weights 1/(4D) (Eqs. 29-30) in the stored
   // variables: feq_q(U) - feq_q(0, Fref) = (v, F - Fref)/(2D)
@@ -340,7 +336,7 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
       }
       const T feq = iso[r] + sg * inv2c * phi;
       T out = f[q][r] + om * (feq - f[q][r]);
-      if (r < D) out += srcw * (EXT ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
+      if (r < D) out += srcw * (L::body ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
     }
   }
@@ -367,7 +363,7 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
 }
 
 // the same update recording the recovered state on the reverse-mode tape
-template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, bool EXT = false>
+template <int D, typename T, bool MASK, bool TRACK, bool REPAIR, class L = NeoHookean<D>>
 __global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p,
                                                    const uint8_t *__restrict__ act, double *__restrict__ ustar,
                                                    double *__restrict__ ubuf, const T *__restrict__ Frp,
@@ -375,7 +371,7 @@ __global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T 
                                                    const T *__restrict__ bf, T bs) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
-  bulk_node<D, T, MASK, TRACK, REPAIR, true, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x,
+  bulk_node<D, T, MASK, TRACK, REPAIR, true, L>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x,
                                                    (int)blockIdx.y, tape, bf, bs,
                                                    x + (int64_t)g.nx * blockIdx.y, g.S);
 }
@@ -383,7 +379,7 @@ __global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T 
 // Embedded bodies: the same update over the list of CHUNK-node chunks (of
 // the node order) that hold active nodes, 64 / CHUNK chunks per wavefront;
 // inactive nodes of a chunk return at once (MASK).
-template <int D, typename T, bool TRACK, bool REPAIR, bool EXT>
+template <int D, typename T, bool TRACK, bool REPAIR, class L>
 __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks(const T *__restrict__ fin, T *__restrict__ fout,
                                                                     Geo g, Par p, const uint8_t *__restrict__ act,
                                                                     double *__restrict__ ustar,
@@ -396,12 +392,12 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks(const T *__r
   const int64_t i = (int64_t)chunks[ch] * CHUNK + (threadIdx.x % CHUNK);
   if (i >= g.N) return;
   const int x = (int)(i % g.nx), row = (int)(i / g.nx);
-  bulk_node<D, T, true, TRACK, REPAIR, false, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, nullptr,
+  bulk_node<D, T, true, TRACK, REPAIR, false, L>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, nullptr,
                                                     bf, bs);
 }
 
 // the chunked update recording the recovered state on the reverse-mode tape
-template <int D, typename T, bool TRACK, bool REPAIR, bool EXT>
+template <int D, typename T, bool TRACK, bool REPAIR, class L>
 __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks_tape(
     const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p, const uint8_t *__restrict__ act,
     double *__restrict__ ustar, double *__restrict__ ubuf, const T *__restrict__ Frp, int *__restrict__ flag,
@@ -412,7 +408,7 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks_tape(
   if (i >= g.N) return;
   const int x = (int)(i % g.nx), row = (int)(i / g.nx);
   // tape slot of chunk ch, position i % CHUNK
-  bulk_node<D, T, true, TRACK, REPAIR, true, EXT>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, tape,
+  bulk_node<D, T, true, TRACK, REPAIR, true, L>(fin, fout, g, p, act, ustar, ubuf, Frp, flag, x, row, tape,
                                                   nullptr, T(0), (int64_t)ch * CHUNK + (threadIdx.x % CHUNK),
                                                   (int64_t)nchunks * CHUNK);
 }
@@ -491,6 +487,51 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ fin, Geo 
   moments_node<D, T, O, MASK, DEV>(fin, g, p, act, ustar, Vo, Fo, uo, Jo, ostride, x, (int)blockIdx.y, bf, bs);
 }
 
+// Stress of the current time level: P of the recovered F with the node's
+// law and sigma = J^{-1} P F^T (Sec. 2.4, Eq. 35), planar [D*D][N] FP64;
+// zero at inactive nodes
+template <int D, typename T, bool MASK>
+__global__ __launch_bounds__(256) void k_stress(const T *__restrict__ fin, Geo g, Par p,
+                                                 const uint8_t *__restrict__ act, double *__restrict__ Po,
+                                                 double *__restrict__ So) {
+  constexpr int Q = 2 * D, M = D + D * D;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int row = blockIdx.y;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = x + (int64_t)g.nx * row;
+  double P[D * D], sg[D * D];
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) P[k] = sg[k] = 0.0;
+  if (!MASK || act[node]) {
+    T f[Q][M];
+    pull_all<D, T, M>(fin, g, x, y, z, f);
+    double F[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+      T s = f[0][D + k];
+#pragma unroll
+      for (int q = 1; q < Q; ++q) s += f[q][D + k];
+      F[k] = p.Fref[k] + double(s);
+    }
+    double Hn[sym_n<D>()];
+    const double J = law_piola<D>(F, p, law_load<D>(p, node, g.S, Hn) ? Hn : nullptr, P);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        double s = 0.0;
+#pragma unroll
+        for (int A = 0; A < D; ++A) s += P[a * D + A] * F[b * D + A];
+        sg[a * D + b] = s / J;
+      }
+  }
+  if (Po)
+    for (int k = 0; k < D * D; ++k) Po[(size_t)k * g.N + node] = P[k];
+  if (So)
+    for (int k = 0; k < D * D; ++k) So[(size_t)k * g.N + node] = sg[k];
+}
+
 // batched projection inputs: v, F into each instance's workspace, u = u* + dt/2 v
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_moments_batch(const Inst *__restrict__ insts,
@@ -527,11 +568,24 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
     for (int r = 0; r < M; ++r) dA[A][r] = dU0 ? dU0[((size_t)A * M + r) * g.N + node] : 0.0;
   const double *F = U + D;
   double P[D * D];
-  const double J = mat_piola<D>(F, p, P);
-  if (!(J > 0.0)) {
+  if (!(det<D>(F) > 0.0)) {
     atomicOr(flag, FLAG_J);
     return;
   }
+  // a Maxwell branch starts relaxed at F0: Q^0 = 0, S_0^0 = S_0(F0), i.e.
+  // R = -beta xi S_0(F0)
+  double Hn[sym_n<D>()];
+  const double *hn = nullptr;
+  if (p.hist) {
+    shear_S0<D>(F, p.mu, Hn, nullptr);
+#pragma unroll
+    for (int k = 0; k < sym_n<D>(); ++k) {
+      Hn[k] = -p.vbx * Hn[k];
+      p.hist[(size_t)k * g.S + node] = Hn[k];
+    }
+    hn = Hn;
+  }
+  law_piola<D>(F, p, hn, P);
   // d_t U0 = B0 - Phi'_A(U0) d_A U0, B0 = (b0 - gamma v0, 0)
 #pragma unroll
   for (int r = 0; r < M; ++r)
@@ -539,7 +593,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
 #pragma unroll
   for (int A = 0; A < D; ++A) {
     double dP[D * D];
-    mat_tangent<D>(F, dA[A] + D, p, dP);
+    law_tangent<D>(F, dA[A] + D, p, hn, dP);
 #pragma unroll
     for (int i = 0; i < D; ++i) Ut[i] += dP[i * D + A] * p.inv_rho0;  // -(-dP)
 #pragma unroll
@@ -553,7 +607,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
     double Z[M], dP[D * D];
 #pragma unroll
     for (int r = 0; r < M; ++r) Z[r] = Ut[r] + c * sg * dA[A][r];
-    mat_tangent<D>(F, Z + D, p, dP);
+    law_tangent<D>(F, Z + D, p, hn, dP);
     int xs = x, ys = y, zs = z;  // X - e_q
     if (A == 0) xs = (x - (int)sg + g.nx) % g.nx;
     if (A == 1) ys = (y - (int)sg + g.ny) % g.ny;
@@ -655,7 +709,7 @@ template <typename T> static T body_scale(const tlvlbm_ctx *c) {
   return T(sv);
 }
 
-template <int D, typename T, bool EXT> static void bulk_plain_t(tlvlbm_ctx *c, bool repair) {
+template <int D, typename T, class L> static void bulk_plain_t(tlvlbm_ctx *c, bool repair) {
   dim3 grid, block;
   grid_of(c->geo, grid, block);
   const T *fin = (const T *)c->fB;
@@ -668,39 +722,39 @@ template <int D, typename T, bool EXT> static void bulk_plain_t(tlvlbm_ctx *c, b
     // embedded body: only the chunks holding active nodes
     const unsigned nb = (unsigned)((c->nchunks + 256 / CHUNK - 1) / (256 / CHUNK));
     if (repair)
-      hipLaunchKernelGGL((k_bulk_chunks<D, T, true, true, EXT>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
+      hipLaunchKernelGGL((k_bulk_chunks<D, T, true, true, L>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs, c->chunks, c->nchunks);
     else if (c->track_u)
-      hipLaunchKernelGGL((k_bulk_chunks<D, T, true, false, EXT>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
+      hipLaunchKernelGGL((k_bulk_chunks<D, T, true, false, L>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs, c->chunks, c->nchunks);
     else
-      hipLaunchKernelGGL((k_bulk_chunks<D, T, false, false, EXT>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
+      hipLaunchKernelGGL((k_bulk_chunks<D, T, false, false, L>), nb, 256, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs, c->chunks, c->nchunks);
     return;
   }
   if (repair) {
-    hipLaunchKernelGGL((k_bulk<D, T, true, true, true, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+    hipLaunchKernelGGL((k_bulk<D, T, true, true, true, L>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                        c->act, us, ub, Fr, c->d_flag, bf, bs);
   } else if (c->act) {
     if (c->track_u)
-      hipLaunchKernelGGL((k_bulk<D, T, true, true, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+      hipLaunchKernelGGL((k_bulk<D, T, true, true, false, L>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs);
     else
-      hipLaunchKernelGGL((k_bulk<D, T, true, false, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+      hipLaunchKernelGGL((k_bulk<D, T, true, false, false, L>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs);
   } else {
     if (c->track_u)
-      hipLaunchKernelGGL((k_bulk<D, T, false, true, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+      hipLaunchKernelGGL((k_bulk<D, T, false, true, false, L>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                          c->act, us, ub, Fr, c->d_flag, bf, bs);
     else
-      hipLaunchKernelGGL((k_bulk<D, T, false, false, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo,
+      hipLaunchKernelGGL((k_bulk<D, T, false, false, false, L>), grid, block, 0, c->st, fin, fout, c->geo,
                          c->par, c->act, us, ub, Fr, c->d_flag, bf, bs);
   }
 }
 
 // the forward of the reverse mode (no body acceleration: refused there; the
-// fibre law in the EXT instantiation)
-template <int D, typename T, bool EXT> static void bulk_tape_t(tlvlbm_ctx *c, bool repair, void *tape) {
+// fibre law in the Reinforced instantiation; no history-dependent law)
+template <int D, typename T, class L> static void bulk_tape_t(tlvlbm_ctx *c, bool repair, void *tape) {
   dim3 grid, block;
   grid_of(c->geo, grid, block);
   const T *fin = (const T *)c->fB;
@@ -712,43 +766,45 @@ template <int D, typename T, bool EXT> static void bulk_tape_t(tlvlbm_ctx *c, bo
   if (c->act && c->chunks) {
     const unsigned nblk = (unsigned)((c->nchunks + 256 / CHUNK - 1) / (256 / CHUNK));
     if (repair)
-      hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, true, true, EXT>), nblk, 256, 0, c->st, fin, fout, c->geo,
+      hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, true, true, L>), nblk, 256, 0, c->st, fin, fout, c->geo,
                          c->par, c->act, us, ub, Fr, c->d_flag, tp, c->chunks, c->nchunks);
     else if (c->track_u)
-      hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, true, false, EXT>), nblk, 256, 0, c->st, fin, fout, c->geo,
+      hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, true, false, L>), nblk, 256, 0, c->st, fin, fout, c->geo,
                          c->par, c->act, us, ub, Fr, c->d_flag, tp, c->chunks, c->nchunks);
     else
-      hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, false, false, EXT>), nblk, 256, 0, c->st, fin, fout, c->geo,
+      hipLaunchKernelGGL((k_bulk_chunks_tape<D, T, false, false, L>), nblk, 256, 0, c->st, fin, fout, c->geo,
                          c->par, c->act, us, ub, Fr, c->d_flag, tp, c->chunks, c->nchunks);
     return;
   }
   if (repair)
-    hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, true, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+    hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, true, L>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                        c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
   else if (c->act && c->track_u)
-    hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
+    hipLaunchKernelGGL((k_bulk_tape<D, T, true, true, false, L>), grid, block, 0, c->st, fin, fout, c->geo, c->par,
                        c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
   else if (c->act)
-    hipLaunchKernelGGL((k_bulk_tape<D, T, true, false, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo,
+    hipLaunchKernelGGL((k_bulk_tape<D, T, true, false, false, L>), grid, block, 0, c->st, fin, fout, c->geo,
                        c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
   else if (c->track_u)
-    hipLaunchKernelGGL((k_bulk_tape<D, T, false, true, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo,
+    hipLaunchKernelGGL((k_bulk_tape<D, T, false, true, false, L>), grid, block, 0, c->st, fin, fout, c->geo,
                        c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
   else
-    hipLaunchKernelGGL((k_bulk_tape<D, T, false, false, false, EXT>), grid, block, 0, c->st, fin, fout, c->geo,
+    hipLaunchKernelGGL((k_bulk_tape<D, T, false, false, false, L>), grid, block, 0, c->st, fin, fout, c->geo,
                        c->par, c->act, us, ub, Fr, c->d_flag, tp, nb, T(0));
 }
 
 template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair, void *tape, bool taped) {
-  // extensions (body acceleration, fibre law) in their own instantiation
+  // one instantiation per law: the paper's, the reinforced solid (fibres,
+  // body acceleration) and the Maxwell branch (the reverse mode refuses it)
   const bool ext = c->bf || c->par.k1 != 0.0;
   if (tape || taped) {
-    if (ext) bulk_tape_t<D, T, true>(c, repair, tape);
-    else bulk_tape_t<D, T, false>(c, repair, tape);
+    if (ext) bulk_tape_t<D, T, Reinforced<D>>(c, repair, tape);
+    else bulk_tape_t<D, T, NeoHookean<D>>(c, repair, tape);
     return;
   }
-  if (ext) bulk_plain_t<D, T, true>(c, repair);
-  else bulk_plain_t<D, T, false>(c, repair);
+  if (c->par.hist) bulk_plain_t<D, T, Viscoelastic<D>>(c, repair);
+  else if (ext) bulk_plain_t<D, T, Reinforced<D>>(c, repair);
+  else bulk_plain_t<D, T, NeoHookean<D>>(c, repair);
 }
 
 void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape, bool taped) {
@@ -795,6 +851,26 @@ void launch_pull_moments(tlvlbm_ctx *c, double *U, double *u, double *J, bool to
   } else {
     if (c->prec) moments_t<3, double>(c, U, u, J, to_scratch);
     else moments_t<3, float>(c, U, u, J, to_scratch);
+  }
+}
+
+template <int D, typename T> static void stress_t(tlvlbm_ctx *c, double *P, double *S) {
+  dim3 grid, block;
+  grid_of(c->geo, grid, block);
+  if (c->act)
+    hipLaunchKernelGGL((k_stress<D, T, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act, P, S);
+  else
+    hipLaunchKernelGGL((k_stress<D, T, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act, P,
+                       S);
+}
+
+void launch_stress(tlvlbm_ctx *c, double *P, double *S) {
+  if (c->D == 2) {
+    if (c->prec) stress_t<2, double>(c, P, S);
+    else stress_t<2, float>(c, P, S);
+  } else {
+    if (c->prec) stress_t<3, double>(c, P, S);
+    else stress_t<3, float>(c, P, S);
   }
 }
 

@@ -516,7 +516,11 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
       h[i] = acc;
     }
   }
-  const bool conv = newton_h<D>(N, Gt, Tb, p, 1e-12, h);
+  // the law of node m (with a Maxwell branch: its history after this step's
+  // collision)
+  double Hn[sym_n<D>()];
+  const double *hn = law_load<D>(p, m, g.S, Hn) ? Hn : nullptr;
+  const bool conv = newton_h<D>(N, Gt, Tb, p, 1e-12, h, hn);
   if (!conv) atomicAdd(nfail, 1ull);
   double Fb[D * D], Pb[D * D];
   for (int i = 0; i < D; ++i)
@@ -525,7 +529,7 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
     atomicOr(flag, FLAG_NEWTON);
     for (int k = 0; k < D * D; ++k) Fb[k] = (k % (D + 1) == 0) ? 1.0 : 0.0;
   }
-  mat_piola<D>(Fb, p, Pb);
+  law_piola<D>(Fb, p, hn, Pb);
   const T ie = T(1.0 / (2.0 * eta));
   const T e2 = T(2.0 * eta);
   T fo[M], fx[M];

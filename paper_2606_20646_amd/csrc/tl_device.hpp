@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include "tl_internal.hpp"
+#include "tl_law.hpp"
 #include "tl_math.hpp"
 
 namespace tl {
@@ -170,29 +171,27 @@ template <int D> __device__ inline bool solve_small(const double *A, const doubl
   return true;
 }
 
-// stress and tangent action of the material in FP64 (neo-Hookean, plus the
-// fibre term when p.k1 > 0)
+// stress and tangent action of the elastic material in FP64 (neo-Hookean,
+// plus the fibre term when p.k1 > 0)
 template <int D> __host__ __device__ __forceinline__ double mat_piola(const double *F, const Par &p, double *P) {
-  const double J = piola<D>(F, p.mu, p.lam, P);
-  if (p.k1 != 0.0) fibre_add<D>(F, p.k1, p.a0, P);
-  return J;
+  return law_piola<D>(F, p, nullptr, P);
 }
 
 template <int D>
 __device__ __forceinline__ void mat_tangent(const double *F, const double *dF, const Par &p, double *dP) {
-  piola_tangent<D>(F, dF, p.mu, p.lam, dP);
-  if (p.k1 != 0.0) fibre_tangent_add<D>(F, dF, p.k1, p.a0, dP);
+  law_tangent<D>(F, dF, p, nullptr, dP);
 }
 
-// R(h) = P(h (x) N + Gt) N - T (Eqs. 54, 56); false if det F_b <= 0
+// R(h) = P(h (x) N + Gt) N - T (Eqs. 54, 56) with the law of the link's
+// node (Hn: its internal variables, or null); false if det F_b <= 0
 template <int D>
 __device__ inline bool nm_residual(const double *h, const double *N, const double *Gt, const double *Tb, const Par &p,
-                            double *R) {
+                            double *R, const double *Hn = nullptr) {
   double F[D * D], P[D * D];
   for (int i = 0; i < D; ++i)
     for (int a = 0; a < D; ++a) F[i * D + a] = h[i] * N[a] + Gt[i * D + a];
   if (!(det<D>(F) > 0.0)) return false;
-  mat_piola<D>(F, p, P);
+  law_piola<D>(F, p, Hn, P);
   for (int i = 0; i < D; ++i) {
     double s = 0.0;
     for (int a = 0; a < D; ++a) s += P[i * D + a] * N[a];
@@ -207,9 +206,9 @@ __device__ inline bool nm_residual(const double *h, const double *N, const doubl
 // accepts only det F_b > 0 with a decreasing residual (<= 10 halvings).
 template <int D>
 __device__ inline bool newton_h(const double *N, const double *Gt, const double *Tb, const Par &p, double tol,
-                         double *h) {
+                         double *h, const double *Hn = nullptr) {
   double R[D], Rt[D], ht[D];
-  if (!nm_residual<D>(h, N, Gt, Tb, p, R)) return false;
+  if (!nm_residual<D>(h, N, Gt, Tb, p, R, Hn)) return false;
   const double thr = tol * (p.mu > 1.0 ? p.mu : 1.0);
   for (int it = 0; it <= 30; ++it) {
     double rinf = 0.0, r2 = 0.0;
@@ -226,7 +225,7 @@ __device__ inline bool newton_h(const double *N, const double *Gt, const double 
       double dF[D * D], dP[D * D];
       for (int i = 0; i < D; ++i)
         for (int a = 0; a < D; ++a) dF[i * D + a] = (i == k) ? N[a] : 0.0;
-      mat_tangent<D>(F, dF, p, dP);
+      law_tangent<D>(F, dF, p, Hn, dP);
       for (int i = 0; i < D; ++i) {
         double s = 0.0;
         for (int a = 0; a < D; ++a) s += dP[i * D + a] * N[a];
@@ -239,7 +238,7 @@ __device__ inline bool newton_h(const double *N, const double *Gt, const double 
     bool acc = false;
     for (int ls = 0; ls <= 10; ++ls) {
       for (int i = 0; i < D; ++i) ht[i] = h[i] + step * dh[i];
-      if (nm_residual<D>(ht, N, Gt, Tb, p, Rt)) {
+      if (nm_residual<D>(ht, N, Gt, Tb, p, Rt, Hn)) {
         double rt2 = 0.0, rtinf = 0.0;
         for (int i = 0; i < D; ++i) {
           rt2 += Rt[i] * Rt[i];

@@ -41,6 +41,12 @@ struct Par {
   // Pref = P(Fref) / rho0 with the material of tlvlbm_set_state (a constant
   // of the representation: a later material change keeps it).
   double Fref[9], Pref[9];
+  // Maxwell branch (law 2): beta xi and xi^2 with xi = exp(-dt / (2 tau)),
+  // and the node's internal variables R = xi^2 Q^n - beta xi S_0^n in
+  // D(D+1)/2 FP64 planes of stride S (packed symmetric, sym_idx); null: no
+  // branch
+  double vbx, vxi2;
+  double *hist;
 };
 
 // stored-population shift feq_q^r(0, Fref) of direction q, row r:
@@ -327,6 +333,11 @@ struct tlvlbm_ctx {
   void *bf = nullptr;
   int bf_ramp = 0;
   double bf_Tr = 1.0;
+  // Maxwell branch of law 2 (beta, tau) and its history planes (kept
+  // allocated once made; par.hist points at them while the law has a branch)
+  bool visco = false;
+  double vbeta = 0.0, vtau = 0.0;
+  double *hist = nullptr;
   // displacement history u* and u (Eq. 34): D FP64 planes each in both
   // builds (a quadrature over thousands of steps; FP32 sums lose ~1e-5)
   void *ustar = nullptr, *ubuf = nullptr;
@@ -369,6 +380,7 @@ void launch_init(tlvlbm_ctx *c, const double *U0, const double *u0, const double
 void launch_get_f(tlvlbm_ctx *c, double *f, double *ustar);
 void launch_planes_in(tlvlbm_ctx *c, const double *src, void *dst, int k);
 void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar);
+void launch_stress(tlvlbm_ctx *c, double *P, double *sigma);
 // launchers (embed.hip)
 int build_links(tlvlbm_ctx *c, const double *phi_d, const uint8_t *bid_d, std::string &err);
 int launch_cutlinks(tlvlbm_ctx *c, double tn);

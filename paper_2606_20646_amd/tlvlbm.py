@@ -30,17 +30,21 @@ class Grid(C.Structure):
 
 class Material(C.Structure):
     _fields_ = [("law", C.c_int32), ("mu", C.c_double), ("lam", C.c_double), ("k1", C.c_double),
-                ("a0", C.c_double * 3)]
+                ("a0", C.c_double * 3), ("beta", C.c_double), ("tau", C.c_double)]
 
 
-def _material(mu, lam, fibre):
-    """law 0 (neo-Hookean) or, with fibre = (k1, a0), law 1."""
-    if fibre is None:
-        return Material(0, mu, lam, 0.0)
-    k1, a0 = fibre
-    m = Material(1, mu, lam, float(k1))
-    for k, v in enumerate(a0):
-        m.a0[k] = v
+def _material(mu, lam, fibre, viscous=None):
+    """law 0 (neo-Hookean); with fibre = (k1, a0), law 1; with viscous =
+    (beta, tau), law 2 (a Maxwell branch, on top of the fibres if given)."""
+    m = Material(0, mu, lam, 0.0)
+    if fibre is not None:
+        k1, a0 = fibre
+        m.law, m.k1 = 1, float(k1)
+        for k, v in enumerate(a0):
+            m.a0[k] = v
+    if viscous is not None:
+        m.law = 2
+        m.beta, m.tau = float(viscous[0]), float(viscous[1])
     return m
 
 
@@ -119,6 +123,7 @@ def _load():
     L.tlvlbm_set_state.argtypes = [vp, dp, dp, dp]
     L.tlvlbm_step.argtypes = [vp, C.c_int64]
     L.tlvlbm_moments.argtypes = [vp, dp, dp, dp]
+    L.tlvlbm_stress.argtypes = [vp, dp, dp]
     L.tlvlbm_get_state.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
     L.tlvlbm_put_state.argtypes = [vp, dp, dp, C.c_int64]
     L.tlvlbm_get_links.argtypes = [vp, dp, dp, dp, dp, dp]
@@ -177,10 +182,12 @@ class Solver:
     def __init__(self, D, n, dx, dt, mu, lam, rho0=1.0, origin=None, periodic_mask=None, omega=1.8, gamma=0.0,
                  theta_F=1.0, proj_every=20, precision="fp32", track_u=-1, cg_rtol=0.0, cg_maxit=0,
                  stream=None, cg_multigrid=True, proj_sweeps=20, proj_weight=2.0 / 3.0, fibre=None,
-                 allocator=None):
+                 allocator=None, viscous=None):
         """allocator: None (the library's hipMalloc), "torch" (torch's caching
         allocator, on the stream given as a torch.cuda.Stream or the current
-        one), or a (dev_alloc, dev_free) pair of ALLOC_FN / FREE_FN."""
+        one), or a (dev_alloc, dev_free) pair of ALLOC_FN / FREE_FN.
+        fibre = (k1, a0): fibre-reinforced law; viscous = (beta, tau): one
+        Maxwell branch (tau = inf: glassy limit)."""
         self.D, self.M, self.Q = D, D + D * D, 2 * D
         self.n = tuple(int(v) for v in n)
         self.N = int(np.prod(self.n))
@@ -191,7 +198,7 @@ class Solver:
             g.origin[a] = (origin[a] if origin is not None and a < len(origin) else 0.0)
         g.dx = dx
         g.periodic_mask = ((1 << D) - 1) if periodic_mask is None else periodic_mask
-        m = _material(mu, lam, fibre)
+        m = _material(mu, lam, fibre, viscous)
         o = Options()
         lib.tlvlbm_default_options(C.byref(o))
         o.omega, o.gamma, o.theta_F, o.cg_rtol = omega, gamma, theta_F, cg_rtol
@@ -262,8 +269,8 @@ class Solver:
         p, keep = _ptr(arr)
         self._chk(lib.tlvlbm_set_body_force(self.h, p, RAMPS.get(ramp, ramp), float(T_r)), "set_body_force")
 
-    def set_material(self, mu, lam, fibre=None):
-        self._chk(lib.tlvlbm_set_material(self.h, C.byref(_material(mu, lam, fibre))), "set_material")
+    def set_material(self, mu, lam, fibre=None, viscous=None):
+        self._chk(lib.tlvlbm_set_material(self.h, C.byref(_material(mu, lam, fibre, viscous))), "set_material")
 
     def set_state(self, U0, u0=None, dU0=None):
         arrs = [a if (a is None or not isinstance(a, np.ndarray)) else np.ascontiguousarray(a, np.float64)
@@ -329,6 +336,13 @@ class Solver:
         Jo = np.zeros(self.N) if J else None
         self._chk(lib.tlvlbm_moments(self.h, _ptr(Uo)[0], _ptr(uo)[0], _ptr(Jo)[0]), "moments")
         return Uo, uo, Jo
+
+    def stress(self, P=True, sigma=True):
+        """(P, sigma) of the current time level, [D*D][N] each (Eq. 35)"""
+        Po = np.zeros((self.D * self.D, self.N)) if P else None
+        So = np.zeros((self.D * self.D, self.N)) if sigma else None
+        self._chk(lib.tlvlbm_stress(self.h, _ptr(Po)[0], _ptr(So)[0]), "stress")
+        return Po, So
 
     def moments_into(self, U=None, u=None, J=None):
         """Write moments into caller buffers (numpy or torch, host or device)."""

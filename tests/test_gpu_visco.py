@@ -1,0 +1,189 @@
+"""GPU parity of the history-dependent law (law 2: one viscoelastic Maxwell
+branch on the neo-Hookean solid, Sec. 6 outlook) and of the stress output
+(Eq. 35), through the C ABI, against the FP64 oracle.
+
+- periodic 3D, F0 = I + 0.05 A (the branch starts relaxed at a deformed
+  state) with 8 Fourier velocity modes, beta = 1.5 and tau = 16 steps (the
+  branch relaxes within the run): state per part (tests/parity.py; FP64
+  1e-12 plus the rounding floor, FP32 1e-5) and the first Piola and Cauchy
+  stresses of the final state (which carry the branch's history);
+- the embedded annulus (displacement-driven inner surface, traction-free
+  outer surface, projection with repair every 20 steps) with a branch:
+  the traction closure's Newton solve runs on the node's history;
+- the stress output of the paper's law on the periodic 2D configuration;
+- the calls that refuse the branch (batch, reverse mode) and the reset that
+  a material change asks for.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import check
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2606_20646_amd import tlvlbm
+    return tlvlbm
+
+
+def _stress_check(Pg, Po, Sg, So, tol, mask, label, pops=None, steps=0, stiff=0.0):
+    """stresses on the scale of their own deviation from their mean (the
+    static part is what the populations store about), plus the FP64 floor:
+    the rounding of the oracle's F rows (steps * eps * sum_q |f_q|, as in
+    tests/parity.py) times the stiffness, four times over"""
+    out = {}
+    floor = 0.0
+    if pops is not None:
+        D = int(round(np.sqrt(Pg.shape[0])))
+        aF = np.abs(pops[:, D:, :]).sum(0)[:, mask]
+        floor = 4.0 * stiff * steps * 2.0 ** -52 * np.linalg.norm(aF)
+    for name, g, o in (("P", Pg, Po), ("sigma", Sg, So)):
+        g, o = g[:, mask], o[:, mask]
+        dev = np.linalg.norm(o - o.mean(axis=1, keepdims=True))
+        err = float(np.linalg.norm(g - o))
+        out[name] = err / dev
+        out[name + "_floor"] = floor / dev
+        assert err <= tol * dev + floor, f"{label}: {name} error {err / dev:.3e} above {tol:g} + {floor / dev:.2e}"
+    print(f"[parity] {label} stress " + " ".join(f"{k}={v:.2e}" for k, v in out.items()), flush=True)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_maxwell_periodic_3d(T, orc, precision, tol):
+    c = W.config_c3(32)
+    beta, steps = 1.5, 120
+    tau = 16 * c["dt"]
+    _say(f"maxwell branch periodic 32^3 {precision} {steps} steps")
+    g = T.Solver(3, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], precision=precision,
+                 viscous=(beta, tau))
+    o = orc.Sim(3, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"])
+    o.set_viscous(beta, tau)
+    for s in (g, o):
+        s.set_state(c["U0"], dU0=c["dU0"])
+        s.step(steps)
+    Ug, _, _ = g.moments()
+    Uo, _, _ = o.moments()
+    check(Ug, Uo, 3, tol, label=f"maxwell periodic 3D {precision}", pops=o.get_f(), steps=steps,
+          stress=(c["mu"] * (1 + beta), c["lam"], 1.0, 10.0, c["omega"]))
+    Pg, Sg = g.stress()
+    Po, So = o.stress()
+    _stress_check(Pg, Po, Sg, So, tol, np.ones(g.N, bool), f"maxwell periodic 3D {precision}", o.get_f(), steps,
+                  c["lam"] + 2 * c["mu"] * (1 + beta))
+    # the branch carries stress: the elastic law's stress of the same state
+    # differs by far more than the tolerance
+    Qh, S0h = o.viscous_history()
+    assert np.abs(Qh).max() > 1e-4
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_maxwell_embedded_annulus(T, orc, precision, tol):
+    from oracle import oracle as O
+    c = W.config_c2(64)
+    beta, tau, steps = 1.0, 0.05, 400
+    _say(f"maxwell branch annulus 64^2 {precision} {steps} steps")
+    g = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
+                 origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"], precision=precision,
+                 viscous=(beta, tau))
+    o = O.Sim(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
+              origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"])
+    o.set_viscous(beta, tau)
+    kinds = {"dirichlet": O.DIRICHLET, "neumann": O.NEUMANN}
+    ramps = {"const": O.RAMP_CONST, "sin2": O.RAMP_SIN2}
+    g.set_levelset(c["phi"], c["bid"])
+    o.set_levelset(c["phi"], c["bid"])
+    for bid, bc in c["bcs"].items():
+        bc = dict(bc)
+        if "ramp" in bc:
+            bc["T_r"] = 0.3
+        gb = dict(bc)
+        g.set_boundary(bid, gb.pop("type"), **gb)
+        t = kinds[bc.pop("type")]
+        if "ramp" in bc:
+            bc["ramp"] = ramps[bc["ramp"]]
+        o.set_bc(bid, t, **bc)
+    for s in (g, o):
+        s.set_state(c["U0"])
+        s.step(steps)
+    assert g.stats()["newton_failures"] == 0
+    Ug, ug, _ = g.moments()
+    Uo, uo, _ = o.moments()
+    act = c["phi"] <= 0
+    check(Ug[:, act], Uo[:, act], 2, tol, ug[:, act], uo[:, act], label=f"maxwell annulus {precision}",
+          pops=o.get_f()[:, :, act], steps=steps, stress=(c["mu"] * (1 + beta), c["lam"], 1.0, c["c"], c["omega"]))
+    Pg, Sg = g.stress()
+    Po, So = o.stress()
+    _stress_check(Pg, Po, Sg, So, tol, act, f"maxwell annulus {precision}", o.get_f(), steps,
+                  c["lam"] + 2 * c["mu"] * (1 + beta))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_stress_output_paper_law(T, orc, precision, tol):
+    c = W.config_c1()
+    steps = 200
+    _say(f"stress output c1 2D 64^2 {precision} {steps} steps")
+    g = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], precision=precision)
+    o = orc.Sim(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"])
+    for s in (g, o):
+        s.set_state(c["U0"], dU0=c["dU0"])
+        s.step(steps)
+    Pg, Sg = g.stress()
+    Po, So = o.stress()
+    _stress_check(Pg, Po, Sg, So, tol, np.ones(g.N, bool), f"stress c1 {precision}", o.get_f(), steps,
+                  c["lam"] + 2 * c["mu"])
+    # sigma is J^{-1} P F^T of the returned state, node by node (Eq. 35)
+    Ug, _, _ = g.moments()
+    for i in (0, 1000, 4095):
+        F = Ug[2:, i].reshape(2, 2)
+        ref = orc.cauchy(F, c["mu"], c["lam"])
+        assert np.abs(Sg[:, i].reshape(2, 2) - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_maxwell_refusals_and_reset(T):
+    c = W.config_c2(32)
+    _say("maxwell branch refusals")
+    import torch
+    stream = torch.cuda.Stream()
+
+    def solver(viscous):
+        s = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
+                     origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"], precision="fp64",
+                     stream=stream.cuda_stream, viscous=viscous)
+        s.set_levelset(c["phi"], c["bid"])
+        for bid, bc in c["bcs"].items():
+            bc = dict(bc)
+            s.set_boundary(bid, bc.pop("type"), **bc)
+        s.set_state(c["U0"])
+        return s
+
+    a, b = solver((1.0, 0.1)), solver(None)
+    with pytest.raises(T.TlvlbmError) as e:
+        T.Batch([a, b])
+    assert e.value.code == T.ERR_INVALID_ARG
+    with pytest.raises(T.TlvlbmError) as e:
+        a.adjoint_record(5)
+    assert e.value.code == T.ERR_INVALID_ARG
+    # a material change on a context with a branch asks for a new state
+    a.set_state(c["U0"])
+    a.set_material(c["mu"], c["lam"], viscous=(2.0, 0.1))
+    with pytest.raises(T.TlvlbmError) as e:
+        a.step(1)
+    assert e.value.code == T.ERR_CALL_ORDER
+    a.set_state(c["U0"])
+    a.step(3)
+    # beta = 0: the paper's law (the branch's instantiation rounds alike up
+    # to contraction order)
+    a.set_material(c["mu"], c["lam"], viscous=(0.0, math.inf))
+    for s in (a, b):
+        s.set_state(c["U0"])
+        s.step(50)
+    act = c["phi"] <= 0
+    check(a.moments()[0][:, act], b.moments()[0][:, act], 2, 1e-12, label="beta = 0 against law 0",
+          pops=b.get_state()[0][:, :, act], steps=50, stress=(c["mu"], c["lam"], 1.0, c["c"], c["omega"]))

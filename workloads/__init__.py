@@ -259,14 +259,15 @@ def config_c5(N=192, seed=SEED, mu=1.0, lam=2.0):
                 proj_every=20, U0=U0, dU0=dU0, steps=4000)
 
 
-def config_c4_instance(k, seed=SEED, N=None):
+def config_c4_instance(k, seed=SEED, N=None, redraw=True):
     """One instance of the batched 2D workload: unit square with 1-5 random
     circular holes, clamped left edge, traction (0.02 mu, 0) on the right
     edge (sine-squared ramp over 500 steps), other surfaces traction free.
     A hole that would leave a ligament narrower than 4 cells to another hole,
     or cut into one at a grazing depth (< 0.03), is drawn again: the
     embedding needs a few active nodes across every ligament (sub-cell
-    slivers fail the local traction solve)."""
+    slivers fail the local traction solve).  redraw=False keeps the first
+    draw (the geometry with slivers, for the failure path)."""
     rng = np.random.default_rng(seed + k)
     Nk = int(rng.integers(64, 513)) if N is None else N
     nh = int(rng.integers(1, 6))
@@ -280,7 +281,7 @@ def config_c4_instance(k, seed=SEED, N=None):
                 return True
         return False
 
-    for j in range(1, nh):
+    for j in range(1, nh if redraw else 1):
         for _ in range(1000):
             if not bad(j):
                 break

@@ -55,7 +55,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_NODE_STEP = 576  # 2 * Q * M * 4 bytes, D3Q6x12 FP32
 COUNTERS = os.path.join(ROOT, "profiles", "bulk_c3_256_counters.json")
-KERNEL_SRC = [os.path.join(ROOT, "paper_2606_20646_amd", "csrc", f) for f in ("bulk.hip", "tl_math.hpp")]
+KERNEL_SRC = [os.path.join(ROOT, "paper_2606_20646_amd", "csrc", f) for f in ("bulk.hip", "tl_math.hpp", "tl_law.hpp")]
 
 
 def kernel_hash():

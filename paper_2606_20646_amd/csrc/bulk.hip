@@ -34,6 +34,10 @@
 #ifndef TL_BULK_WAVES
 #define TL_BULK_WAVES 1
 #endif
+// embedded bodies: minimum waves per SIMD of the chunked update
+#ifndef TL_CHUNK_WAVES
+#define TL_CHUNK_WAVES TL_BULK_WAVES
+#endif
 
 namespace tl {
 
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(256) void k_bulk_tape(const T *__restrict__ fin, T 
 // the node order) that hold active nodes, 64 / CHUNK chunks per wavefront;
 // inactive nodes of a chunk return at once (MASK).
 template <int D, typename T, bool TRACK, bool REPAIR, class L>
-__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks(const T *__restrict__ fin, T *__restrict__ fout,
+__global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_chunks(const T *__restrict__ fin, T *__restrict__ fout,
                                                                     Geo g, Par p, const uint8_t *__restrict__ act,
                                                                     double *__restrict__ ustar,
                                                                     double *__restrict__ ubuf,

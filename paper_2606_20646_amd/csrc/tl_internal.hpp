@@ -18,7 +18,10 @@ enum : int { FLAG_J = 1, FLAG_NONFINITE = 2, FLAG_NEWTON = 4, FLAG_ARG = 8, FLAG
 constexpr int KMAX2 = 24;
 // nodes per chunk of the embedded-body chunk list (a divisor of 64: one
 // wavefront covers 64 / CHUNK chunks)
-constexpr int CHUNK = 32;
+#ifndef TL_CHUNK
+#define TL_CHUNK 32
+#endif
+constexpr int CHUNK = TL_CHUNK;
 constexpr int KMAX3 = 88;
 constexpr double LSQ_RADIUS = 2.5;
 

@@ -10,6 +10,8 @@ branch on the neo-Hookean solid, Sec. 6 outlook) and of the stress output
 - the embedded annulus (displacement-driven inner surface, traction-free
   outer surface, projection with repair every 20 steps) with a branch:
   the traction closure's Newton solve runs on the node's history;
+- the branch on the fibre-reinforced solid with a ramped body acceleration
+  (periodic 2D): the policies compose;
 - the stress output of the paper's law on the periodic 2D configuration;
 - the calls that refuse the branch (batch, reverse mode) and the reset that
   a material change asks for.
@@ -122,6 +124,37 @@ def test_maxwell_embedded_annulus(T, orc, precision, tol):
     Po, So = o.stress()
     _stress_check(Pg, Po, Sg, So, tol, act, f"maxwell annulus {precision}", o.get_f(), steps,
                   c["lam"] + 2 * c["mu"] * (1 + beta))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_maxwell_with_fibres_and_body_force(T, orc, precision, tol):
+    """law 2 composed with the fibre family and a ramped body acceleration
+    (the branch sits on the reinforced solid), periodic 2D"""
+    c = W.config_c1()
+    beta, steps, k1, a0 = 0.8, 300, 2.0, (0.6, 0.8)
+    tau = 25 * c["dt"]
+    _say(f"maxwell branch + fibres + body force 64^2 {precision} {steps} steps")
+    X = W.node_coords(c["n"], c["dx"], c["origin"])
+    gfield = np.stack([0.5 * np.sin(2 * np.pi * X[1]), 0.3 * np.cos(2 * np.pi * (X[0] + X[1]))])
+    g = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=0.5, precision=precision,
+                 fibre=(k1, a0), viscous=(beta, tau))
+    o = orc.Sim(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=0.5)
+    o.set_fibres(k1, a0)
+    o.set_viscous(beta, tau)
+    g.set_body_force(gfield, ramp="sin2", T_r=100 * c["dt"])
+    o.set_body_force(gfield, ramp=orc.RAMP_SIN2, T_r=100 * c["dt"])
+    for s in (g, o):
+        s.set_state(c["U0"], dU0=c["dU0"])
+        s.step(steps)
+    Ug, _, _ = g.moments()
+    Uo, _, _ = o.moments()
+    stiff_mu = c["mu"] * (1 + beta) + 2 * k1
+    check(Ug, Uo, 2, tol, label=f"maxwell + fibres + body force {precision}", pops=o.get_f(), steps=steps,
+          stress=(stiff_mu, c["lam"], 1.0, 10.0, c["omega"]))
+    Pg, Sg = g.stress()
+    Po, So = o.stress()
+    _stress_check(Pg, Po, Sg, So, tol, np.ones(g.N, bool), f"maxwell + fibres + body force {precision}", o.get_f(),
+                  steps, c["lam"] + 2 * stiff_mu)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])

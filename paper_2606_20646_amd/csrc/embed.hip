@@ -898,16 +898,17 @@ __device__ __forceinline__ void jacobi_node_m(const Geo &g, const uint8_t *__res
                                               int64_t i) {
   if (i >= g.N) return;
   const unsigned m = nbm[i];
-  int deg = 0;
+  // an inactive node has no edges: no active node reads it, and neither
+  // buffer's value there is used, so it is skipped (the copies of the
+  // result skip it too)
+  if (!(m & 64u)) return;
   int64_t nb[2 * D];
 #pragma unroll
   for (int q = 0; q < 2 * D; ++q) nb[q] = -1;
-  if (m & 64u) {
-    deg = (anc_n ? anc_n[i] : 0) + __builtin_popcount(m & ((1u << (2 * D)) - 1u));
+  const int deg = (anc_n ? anc_n[i] : 0) + __builtin_popcount(m & ((1u << (2 * D)) - 1u));
 #pragma unroll
-    for (int q = 0; q < 2 * D; ++q)
-      if ((m >> q) & 1u) nb[q] = nb_index(g, i, q);
-  }
+  for (int q = 0; q < 2 * D; ++q)
+    if ((m >> q) & 1u) nb[q] = nb_index(g, i, q);
   // every load unconditional (a missing neighbour reads the node itself and
   // contributes an exact zero), so that all of them are in flight together
   int64_t at[2 * D];
@@ -1146,10 +1147,11 @@ __global__ __launch_bounds__(CG_T) void k_jacobi(Geo g, const uint8_t *__restric
 
 template <int D>
 __global__ __launch_bounds__(CG_T) void k_copy_planes(Geo g, const double *__restrict__ src, double *__restrict__ dst,
-                                                      const int32_t *__restrict__ tiles) {
+                                                      const int32_t *__restrict__ tiles,
+                                                      const uint8_t *__restrict__ nbm) {
   const int64_t blk = tiles ? (int64_t)tiles[blockIdx.x] : (int64_t)blockIdx.x;
   const int64_t i = blk * CG_T + threadIdx.x;
-  if (i < g.N)
+  if (i < g.N && (nbm[i] & 64u))
     for (int c = 0; c < D; ++c) dst[(size_t)c * g.S + i] = src[(size_t)c * g.S + i];
 }
 
@@ -1505,7 +1507,7 @@ template <int D> static int jacobi_run(tlvlbm_ctx *c, const uint8_t *anc_n) {
     std::swap(a, bb);
   }
   if (a != (double *)w.x)
-    hipLaunchKernelGGL((k_copy_planes<D>), nt, CG_T, 0, st, g, (const double *)a, (double *)w.x, w.tiles);
+    hipLaunchKernelGGL((k_copy_planes<D>), nt, CG_T, 0, st, g, (const double *)a, (double *)w.x, w.tiles, w.nbm);
   c->st_cg += (int64_t)c->proj_sweeps * D;
   return hipGetLastError() == hipSuccess ? TLVLBM_OK : TLVLBM_ERR_DEVICE;
 }
@@ -1803,7 +1805,8 @@ __global__ __launch_bounds__(CG_T) void k_jacobi_copy_batch(const Inst *__restri
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
   const int64_t i = (int64_t)t.y * CG_T + threadIdx.x;
-  if (i < I.g.N)
+  // the sweeps over the neighbour masks skip inactive nodes: copy active ones
+  if (i < I.g.N && (!I.nbm || (I.nbm[i] & 64u)))
     for (int c = 0; c < D; ++c)
       ((double *)I.x)[(size_t)c * I.g.S + i] = ((const double *)I.r)[(size_t)c * I.g.S + i];
 }

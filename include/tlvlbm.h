@@ -356,8 +356,11 @@ tlvlbm_status tlvlbm_adjoint_backward(tlvlbm_ctx *ctx, const double *dLdU, const
  * tlvlbm_batch_create builds tile lists over all instances; tlvlbm_batch_step
  * then runs every phase of Algorithm 1 as ONE launch over all instances
  * (bulk update, cut links, every projection/CG kernel with per-instance
- * scalars and segmented reductions) and replays the steps between
- * projections from a captured hipGraph.  The batch borrows the contexts:
+ * scalars and segmented reductions) and replays captured hipGraphs: with
+ * the Jacobi projection (proj_sweeps > 0) a whole projection cycle
+ * (projection step and the proj_every - 1 steps after it) from one graph;
+ * with the exact projection, whose CG polls its convergence from the host,
+ * the steps between projections.  The batch borrows the contexts:
  * they must outlive it, and single-instance calls on them while the batch is
  * in use are not allowed (the batch keeps its own copy of their buffer
  * roles).  Results equal the per-instance path up to floating-point

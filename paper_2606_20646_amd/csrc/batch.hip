@@ -38,6 +38,10 @@ struct tlvlbm_batch {
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
   int glen = 0;
+  // a whole projection cycle (projection step + proj_every - 1 plain steps)
+  // captured once, in the Jacobi mode (no host decisions inside it)
+  hipGraphExec_t gcycle = nullptr;
+  bool capturing = false;
   bool use_mg = false;  // every instance has a multigrid hierarchy: batched V-cycles
   BatchMG bmg;
   std::string err;
@@ -97,7 +101,8 @@ tlvlbm_status cg_batch(tlvlbm_batch *b, int useFr) {
     // damped Jacobi relaxation: sweeps alternate x -> r and r -> x
     for (int k = 0; k < b->sweeps; ++k) run(b, BatchOp::Jacobi, k & 1, anch);
     if (b->sweeps & 1) run(b, BatchOp::JacobiCopy);
-    for (tlvlbm_ctx *c : b->c) c->st_cg += (int64_t)b->sweeps * c->D;
+    if (!b->capturing)
+      for (tlvlbm_ctx *c : b->c) c->st_cg += (int64_t)b->sweeps * c->D;
     return TLVLBM_OK;
   }
   if (b->use_mg) return pcg_batch(b, anch);
@@ -218,6 +223,10 @@ tlvlbm_status set_tiles(tlvlbm_batch *b, const std::vector<int4> &t, int W, int 
     b->gexec = nullptr;
     b->glen = 0;
   }
+  if (b->gcycle) {
+    (void)hipGraphExecDestroy(b->gcycle);
+    b->gcycle = nullptr;
+  }
   return TLVLBM_OK;
 }
 
@@ -318,6 +327,31 @@ tlvlbm_status ensure_graph(tlvlbm_batch *b, int len) {
   BCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0), "graph instantiate");
   (void)hipGraphDestroy(g);
   b->glen = len;
+  return TLVLBM_OK;
+}
+
+// capture one projection cycle: the projection step (Jacobi sweeps: a fixed
+// sequence of launches, no polls, no memsets) and the proj_every - 1 plain
+// steps after it; replayed for every whole cycle
+tlvlbm_status ensure_cycle_graph(tlvlbm_batch *b) {
+  if (b->gcycle) return TLVLBM_OK;
+  hipGraph_t g = nullptr;
+  BCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal), "graph capture");
+  b->capturing = true;
+  tlvlbm_status s = projection_step(b);
+  for (int k = 1; k < b->proj_every && !s; ++k) plain_step(b);
+  b->capturing = false;
+  const hipError_t e = hipStreamEndCapture(b->st, &g);
+  if (s || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return s ? s : bfail(b, TLVLBM_ERR_DEVICE, "graph capture end");
+  }
+  const hipError_t ei = hipGraphInstantiate(&b->gcycle, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    b->gcycle = nullptr;
+    return bfail(b, TLVLBM_ERR_DEVICE, "graph instantiate");
+  }
   return TLVLBM_OK;
 }
 
@@ -564,6 +598,16 @@ tlvlbm_status tlvlbm_batch_step(tlvlbm_batch *b, int64_t n) {
   int64_t k = 0;
   while (k < n) {
     const bool proj = b->any_neu && pe > 0 && (b->step % pe == 0);
+    if (proj && b->use_graph && b->sweeps > 0 && pe > 1 && n - k >= pe) {
+      // a whole cycle from one graph
+      tlvlbm_status s = ensure_cycle_graph(b);
+      if (s) return s;
+      BCHK(hipGraphLaunch(b->gcycle, b->st), "graph launch");
+      for (tlvlbm_ctx *c : b->c) c->st_cg += 2 * (int64_t)b->sweeps * c->D;
+      b->step += pe;
+      k += pe;
+      continue;
+    }
     if (proj) {
       tlvlbm_status s = projection_step(b);
       if (s) return s;
@@ -616,6 +660,7 @@ tlvlbm_status tlvlbm_batch_destroy(tlvlbm_batch *b) {
   if (!b) return TLVLBM_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(b->st);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->gcycle) (void)hipGraphExecDestroy(b->gcycle);
   batch_mg_free(b->bmg);
   void *ptrs[] = {b->d_inst, b->d_btiles, b->d_ctiles, b->d_ltiles, b->d_segs, b->d_step, b->d_pending};
   for (void *p : ptrs)

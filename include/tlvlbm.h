@@ -242,6 +242,13 @@ tlvlbm_status tlvlbm_step(tlvlbm_ctx *ctx, int64_t n);
  * (det F).  Any output may be NULL. */
 tlvlbm_status tlvlbm_moments(tlvlbm_ctx *ctx, double *U_out, double *u_out, double *J_out);
 
+/* The same moments in the context's precision: U_out[M][N] and J_out[N] as
+ * float for a TLVLBM_FP32 context (double for TLVLBM_FP64), the values
+ * tlvlbm_moments returns rounded once to that precision; u_out[D][N] stays
+ * FP64 (the displacement history is FP64 in both builds).  Host or device;
+ * any output may be NULL. */
+tlvlbm_status tlvlbm_moments_native(tlvlbm_ctx *ctx, void *U_out, double *u_out, void *J_out);
+
 /* Stress of the current time level (the final diagnostics of Algorithm 1):
  * first Piola P_out[D*D][N] of the recovered F with the material law (with
  * a Maxwell branch: its history as the next collision uses it) and Cauchy

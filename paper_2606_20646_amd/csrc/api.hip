@@ -572,6 +572,24 @@ tlvlbm_status tlvlbm_moments(tlvlbm_ctx *c, double *U_out, double *u_out, double
   return TLVLBM_OK;
 }
 
+tlvlbm_status tlvlbm_moments_native(tlvlbm_ctx *c, void *U_out, double *u_out, void *J_out) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  if (!c->have_state) return fail(c, TLVLBM_ERR_CALL_ORDER, "moments before set_state");
+  const int64_t N = c->geo.N;
+  DevOut U, u, J;
+  CHK(U.take(U_out, (size_t)c->M * N * c->esz), "U alloc");
+  CHK(u.take(u_out, (size_t)c->D * N * sizeof(double)), "u alloc");
+  CHK(J.take(J_out, (size_t)N * c->esz), "J alloc");
+  if (u.ptr && !c->track_u) CHK(hipMemsetAsync(u.ptr, 0, (size_t)c->D * N * sizeof(double), c->st), "u clear");
+  launch_moments_native(c, U.ptr, c->track_u ? (double *)u.ptr : nullptr, J.ptr);
+  CHK(hipGetLastError(), "moments launch");
+  CHK(U.finish(c->st), "U copy");
+  CHK(u.finish(c->st), "u copy");
+  CHK(J.finish(c->st), "J copy");
+  CHK(hipStreamSynchronize(c->st), "synchronize");
+  return TLVLBM_OK;
+}
+
 tlvlbm_status tlvlbm_stress(tlvlbm_ctx *c, double *P_out, double *sigma_out) {
   if (!c) return TLVLBM_ERR_INVALID_ARG;
   if (!c->have_state) return fail(c, TLVLBM_ERR_CALL_ORDER, "stress before set_state");

@@ -848,6 +848,32 @@ static void moments_t(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_sc
                        c->act, us, Vo, Fo, u, J, (int64_t)c->geo.N, bf, bs);
 }
 
+// moments in the population precision (v and F as stored, J), u in FP64
+template <int D, typename T> static void moments_native_t(tlvlbm_ctx *c, void *U, double *u, void *J) {
+  dim3 grid, block;
+  grid_of(c->geo, grid, block);
+  const double *us = c->track_u ? (const double *)c->ustar : nullptr;
+  const T *bf = (const T *)c->bf;
+  const T bs = body_scale<T>(c);
+  T *Vo = (T *)U, *Fo = U ? (T *)U + (size_t)D * c->geo.N : nullptr;
+  if (c->act)
+    hipLaunchKernelGGL((k_moments<D, T, T, true>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act, us,
+                       Vo, Fo, u, (T *)J, (int64_t)c->geo.N, bf, bs);
+  else
+    hipLaunchKernelGGL((k_moments<D, T, T, false>), grid, block, 0, c->st, (const T *)c->fB, c->geo, c->par, c->act,
+                       us, Vo, Fo, u, (T *)J, (int64_t)c->geo.N, bf, bs);
+}
+
+void launch_moments_native(tlvlbm_ctx *c, void *U, double *u, void *J) {
+  if (c->D == 2) {
+    if (c->prec) moments_native_t<2, double>(c, U, u, J);
+    else moments_native_t<2, float>(c, U, u, J);
+  } else {
+    if (c->prec) moments_native_t<3, double>(c, U, u, J);
+    else moments_native_t<3, float>(c, U, u, J);
+  }
+}
+
 void launch_pull_moments(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch) {
   if (c->D == 2) {
     if (c->prec) moments_t<2, double>(c, U, u, J, to_scratch);

@@ -379,6 +379,7 @@ template <typename X> inline hipError_t dmalloc(tlvlbm_ctx *c, X **p, size_t byt
 // that steps with and without a tape round identically
 void launch_bulk(tlvlbm_ctx *c, bool repair, void *tape = nullptr, bool taped = false);
 void launch_pull_moments(tlvlbm_ctx *c, double *U, double *u, double *J, bool to_scratch);
+void launch_moments_native(tlvlbm_ctx *c, void *U, double *u, void *J);
 void launch_init(tlvlbm_ctx *c, const double *U0, const double *u0, const double *dU0);
 void launch_get_f(tlvlbm_ctx *c, double *f, double *ustar);
 void launch_planes_in(tlvlbm_ctx *c, const double *src, void *dst, int k);

@@ -124,6 +124,7 @@ def _load():
     L.tlvlbm_step.argtypes = [vp, C.c_int64]
     L.tlvlbm_moments.argtypes = [vp, dp, dp, dp]
     L.tlvlbm_stress.argtypes = [vp, dp, dp]
+    L.tlvlbm_moments_native.argtypes = [vp, dp, dp, dp]
     L.tlvlbm_get_state.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
     L.tlvlbm_put_state.argtypes = [vp, dp, dp, C.c_int64]
     L.tlvlbm_get_links.argtypes = [vp, dp, dp, dp, dp, dp]
@@ -204,6 +205,7 @@ class Solver:
         o.omega, o.gamma, o.theta_F, o.cg_rtol = omega, gamma, theta_F, cg_rtol
         o.proj_every, o.cg_maxit, o.track_u = proj_every, cg_maxit, track_u
         o.precision = FP64 if precision in ("fp64", FP64) else FP32
+        self.precision = o.precision
         tstream = None
         if stream is not None and hasattr(stream, "cuda_stream"):  # a torch.cuda.Stream
             tstream, stream = stream, stream.cuda_stream
@@ -335,6 +337,16 @@ class Solver:
         uo = np.zeros((self.D, self.N)) if u else None
         Jo = np.zeros(self.N) if J else None
         self._chk(lib.tlvlbm_moments(self.h, _ptr(Uo)[0], _ptr(uo)[0], _ptr(Jo)[0]), "moments")
+        return Uo, uo, Jo
+
+    def moments_native(self):
+        """(U [M][N], u [D][N], J [N]): U and J in the context's precision
+        (float32 for FP32 contexts), u in float64"""
+        dt = np.float64 if self.precision == FP64 else np.float32
+        Uo = np.zeros((self.M, self.N), dt)
+        uo = np.zeros((self.D, self.N))
+        Jo = np.zeros(self.N, dt)
+        self._chk(lib.tlvlbm_moments_native(self.h, _ptr(Uo)[0], _ptr(uo)[0], _ptr(Jo)[0]), "moments_native")
         return Uo, uo, Jo
 
     def stress(self, P=True, sigma=True):

@@ -294,3 +294,25 @@ def test_full_size_dynamics_matches_oracle(T, orc, cfg, precision, steps):
     check(Ug, Uo, c["D"], _tol(precision, 20), ug, uo, mask=act, label=f"full size {cfg} {precision}",
           pops=o.get_f(), steps=steps, stress=(c["mu"], c["lam"], 1.0, 10.0, c["omega"]))
     assert g.stats()["newton_failures"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_moments_in_context_precision(T, precision):
+    """tlvlbm_moments_native: U and J in the population precision are the
+    FP64 moments rounded once; u is the FP64 displacement"""
+    c = W.config_c2(64)
+    _say(f"moments in context precision, annulus 64^2 {precision}")
+    s = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
+                 origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"], precision=precision)
+    s.set_levelset(c["phi"], c["bid"])
+    for bid, bc in c["bcs"].items():
+        bc = dict(bc)
+        s.set_boundary(bid, bc.pop("type"), **bc)
+    s.set_state(c["U0"])
+    s.step(45)
+    U, u, J = s.moments()
+    Un, un, Jn = s.moments_native()
+    dt = np.float32 if precision == "fp32" else np.float64
+    assert Un.dtype == dt and Jn.dtype == dt and un.dtype == np.float64
+    assert np.array_equal(Un, U.astype(dt)) and np.array_equal(Jn, J.astype(dt)) and np.array_equal(un, u)
+    assert np.abs(u).max() > 0

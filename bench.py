@@ -203,7 +203,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded; recipe of the 256^3 periodic D3Q6x12 configuration)",
-        "config": {"workload": f"D3Q6x12 periodic {N}^3, FP32 SoA populations, neo-Hookean mu=1 lambda=2, "
+        "config": {"workload": f"D3Q6x12 periodic {N}^3, FP32 SoA populations and collision (F and its "
+                               f"stress formed in FP64 registers), neo-Hookean mu=1 lambda=2, "
                                f"F0=I+0.05A, 8 Fourier velocity modes amp 1e-3, c=10, omega=1.8",
                    "nodes": nodes, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -216,7 +216,8 @@ tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *ctx, const double *g, int32_t ra
 /* Replace the material (e.g. for finite-difference sweeps).  The stored
  * populations are kept.  When the old or the new material has a Maxwell
  * branch (law 2), the branch's history starts anew: tlvlbm_step returns
- * CALL_ORDER until the next tlvlbm_set_state. */
+ * CALL_ORDER until the next tlvlbm_set_state (or tlvlbm_put_history and
+ * tlvlbm_put_state). */
 tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *ctx, const tlvlbm_material *mat);
 
 /* Initial state (Sec. 2.1, Eq. 6).  U0[M][N]; u0[D][N] or NULL (zero);
@@ -260,9 +261,22 @@ tlvlbm_status tlvlbm_stress(tlvlbm_ctx *ctx, double *P_out, double *sigma_out);
 /* Raw state for checkpoint/resume: pre-collision populations f^n as
  * [2D][M][N] and the displacement history u*^n as [D][N] (either may be
  * NULL), plus the step index.  The history of a Maxwell branch is not part
- * of it: tlvlbm_put_state keeps the branch's history as it is. */
+ * of it (tlvlbm_get_history / tlvlbm_put_history): tlvlbm_put_state keeps
+ * the branch's history as it is, and on a law-2 context that has none yet
+ * (no set_state, no put_history) returns CALL_ORDER. */
 tlvlbm_status tlvlbm_get_state(tlvlbm_ctx *ctx, double *f, double *ustar, int64_t *step);
 tlvlbm_status tlvlbm_put_state(tlvlbm_ctx *ctx, const double *f, const double *ustar, int64_t step);
+
+/* The Maxwell branch's history (law 2) for checkpoint/resume: per node
+ * R = xi^2 Q^n - beta xi S_0^n (the overstress Q and the shear stress S_0 of
+ * the last committed step, xi = exp(-dt/(2 tau))), D(D+1)/2 packed symmetric
+ * components (2D: 00, 01, 11; 3D: 00, 01, 02, 11, 12, 22) as [D(D+1)/2][N]
+ * FP64, host or device; values at inactive nodes are not used.  A history
+ * is meaningful only with the beta, tau, mu and dt it was taken with.
+ * INVALID_ARG without a branch; get: CALL_ORDER before set_state or
+ * put_history. */
+tlvlbm_status tlvlbm_get_history(tlvlbm_ctx *ctx, double *R);
+tlvlbm_status tlvlbm_put_history(tlvlbm_ctx *ctx, const double *R);
 
 /* Cut-link table (host or device outputs, length = stats.cut_links): node,
  * outgoing direction q, cut fraction eta, normal N_b [L][3], boundary id.

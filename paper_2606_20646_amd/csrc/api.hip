@@ -429,7 +429,10 @@ tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *c, const tlvlbm_material *m) {
   if (!c || !material_ok(m)) return TLVLBM_ERR_INVALID_ARG;
   rec_invalidate(c);
   // a Maxwell branch (before or after) starts its history at set_state
-  if (c->visco || m->law == 2) c->have_state = false;
+  if (c->visco || m->law == 2) {
+    c->have_state = false;
+    c->hist_set = false;
+  }
   set_material_par(c, m);
   set_branch_par(c);
   return TLVLBM_OK;
@@ -460,6 +463,7 @@ tlvlbm_status tlvlbm_set_state(tlvlbm_ctx *c, const double *U0, const double *u0
     if (c->visco) {
       if (!c->hist) CHK(dmalloc(c, &c->hist, (size_t)(D * (D + 1) / 2) * S * sizeof(double)), "history alloc");
       c->par.hist = c->hist;
+      c->hist_set = true;  // the initialisation writes it
     }
     DevIn dU, du, ddU;
     CHK(dU.take(U0, (size_t)M * N * sizeof(double), c->st), "U0 upload");
@@ -622,8 +626,40 @@ tlvlbm_status tlvlbm_get_state(tlvlbm_ctx *c, double *f, double *ustar, int64_t 
   return TLVLBM_OK;
 }
 
+tlvlbm_status tlvlbm_get_history(tlvlbm_ctx *c, double *R) {
+  if (!c || !R) return TLVLBM_ERR_INVALID_ARG;
+  if (!c->visco) return fail(c, TLVLBM_ERR_INVALID_ARG, "get_history: the material has no Maxwell branch");
+  if (!c->hist_set) return fail(c, TLVLBM_ERR_CALL_ORDER, "get_history before set_state or put_history");
+  const int64_t N = c->geo.N, S = c->geo.S;
+  const int K = c->D * (c->D + 1) / 2;
+  CHK(hipMemcpy2DAsync(R, (size_t)N * sizeof(double), c->hist, (size_t)S * sizeof(double), (size_t)N * sizeof(double),
+                       (size_t)K, hipMemcpyDefault, c->st),
+      "history copy");
+  CHK(hipStreamSynchronize(c->st), "synchronize");
+  return TLVLBM_OK;
+}
+
+tlvlbm_status tlvlbm_put_history(tlvlbm_ctx *c, const double *R) {
+  if (!c || !R) return TLVLBM_ERR_INVALID_ARG;
+  if (!c->visco) return fail(c, TLVLBM_ERR_INVALID_ARG, "put_history: the material has no Maxwell branch");
+  rec_invalidate(c);
+  const int64_t N = c->geo.N, S = c->geo.S;
+  const int K = c->D * (c->D + 1) / 2;
+  if (!c->hist) CHK(dmalloc(c, &c->hist, (size_t)K * S * sizeof(double)), "history alloc");
+  CHK(hipMemcpy2DAsync(c->hist, (size_t)S * sizeof(double), R, (size_t)N * sizeof(double), (size_t)N * sizeof(double),
+                       (size_t)K, hipMemcpyDefault, c->st),
+      "history copy");
+  CHK(hipStreamSynchronize(c->st), "synchronize");
+  c->par.hist = c->hist;
+  c->hist_set = true;
+  c->fresh = false;
+  return TLVLBM_OK;
+}
+
 tlvlbm_status tlvlbm_put_state(tlvlbm_ctx *c, const double *f, const double *ustar, int64_t step) {
   if (!c || !f || step < 0) return TLVLBM_ERR_INVALID_ARG;
+  if (c->visco && !c->hist_set)
+    return fail(c, TLVLBM_ERR_CALL_ORDER, "put_state: a Maxwell branch needs its history first (put_history)");
   rec_invalidate(c);
   {
     const int64_t N = c->geo.N;

@@ -341,6 +341,7 @@ struct tlvlbm_ctx {
   bool visco = false;
   double vbeta = 0.0, vtau = 0.0;
   double *hist = nullptr;
+  bool hist_set = false;  // the planes hold the branch's history (set_state or put_history)
   // displacement history u* and u (Eq. 34): D FP64 planes each in both
   // builds (a quadrature over thousands of steps; FP32 sums lose ~1e-5)
   void *ustar = nullptr, *ubuf = nullptr;

@@ -125,6 +125,8 @@ def _load():
     L.tlvlbm_moments.argtypes = [vp, dp, dp, dp]
     L.tlvlbm_stress.argtypes = [vp, dp, dp]
     L.tlvlbm_moments_native.argtypes = [vp, dp, dp, dp]
+    L.tlvlbm_get_history.argtypes = [vp, dp]
+    L.tlvlbm_put_history.argtypes = [vp, dp]
     L.tlvlbm_get_state.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
     L.tlvlbm_put_state.argtypes = [vp, dp, dp, C.c_int64]
     L.tlvlbm_get_links.argtypes = [vp, dp, dp, dp, dp, dp]
@@ -366,6 +368,16 @@ class Solver:
         st = C.c_int64(0)
         self._chk(lib.tlvlbm_get_state(self.h, _ptr(f)[0], _ptr(us)[0], C.byref(st)), "get_state")
         return f, us, st.value
+
+    def get_history(self):
+        """the Maxwell branch's history R [D(D+1)/2][N] (law 2)"""
+        R = np.zeros((self.D * (self.D + 1) // 2, self.N))
+        self._chk(lib.tlvlbm_get_history(self.h, _ptr(R)[0]), "get_history")
+        return R
+
+    def put_history(self, R):
+        R = np.ascontiguousarray(R, np.float64)
+        self._chk(lib.tlvlbm_put_history(self.h, _ptr(R)[0]), "put_history")
 
     def put_state(self, f, ustar=None, step=0):
         f = np.ascontiguousarray(f, np.float64)

@@ -220,3 +220,42 @@ def test_maxwell_refusals_and_reset(T):
     act = c["phi"] <= 0
     check(a.moments()[0][:, act], b.moments()[0][:, act], 2, 1e-12, label="beta = 0 against law 0",
           pops=b.get_state()[0][:, :, act], steps=50, stress=(c["mu"], c["lam"], 1.0, c["c"], c["omega"]))
+
+
+def test_maxwell_checkpoint_resume(T):
+    """get_state + get_history at step 60, a fresh context resumed from them
+    (put_history, put_state) reaches step 100 with the states of the
+    uninterrupted run, bit for bit; put_state without a history is refused"""
+    c = W.config_c2(64)
+    _say("maxwell branch checkpoint and resume, annulus 64^2 fp32")
+
+    def solver():
+        s = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], gamma=c["gamma"],
+                     origin=c["origin"], periodic_mask=0, proj_every=c["proj_every"], precision="fp32",
+                     viscous=(1.0, 0.05))
+        s.set_levelset(c["phi"], c["bid"])
+        for bid, bc in c["bcs"].items():
+            bc = dict(bc)
+            if "ramp" in bc:
+                bc["T_r"] = 0.3
+            s.set_boundary(bid, bc.pop("type"), **bc)
+        return s
+
+    a = solver()
+    a.set_state(c["U0"])
+    a.step(60)
+    f, us, step = a.get_state()
+    R = a.get_history()
+    assert np.abs(R).max() > 0
+    a.step(40)
+    Ua, ua, _ = a.moments()
+    b = solver()
+    with pytest.raises(T.TlvlbmError) as e:
+        b.put_state(f, us, step)
+    assert e.value.code == T.ERR_CALL_ORDER
+    b.put_history(R)
+    b.put_state(f, us, step)
+    b.step(40)
+    Ub, ub, _ = b.moments()
+    assert np.array_equal(Ua, Ub) and np.array_equal(ua, ub)
+    assert np.array_equal(a.get_history(), b.get_history())

@@ -31,12 +31,14 @@
 #ifndef TL_NT_STORE
 #define TL_NT_STORE 1
 #endif
+// The periodic update fits 168 VGPRs without spills at 3 waves per SIMD;
+// the embedded (chunked) updates run fastest at their natural allocation.
 #ifndef TL_BULK_WAVES
-#define TL_BULK_WAVES 1
+#define TL_BULK_WAVES 3
 #endif
-// embedded bodies: minimum waves per SIMD of the chunked update
+// embedded bodies: minimum waves per SIMD of the chunked and batched updates
 #ifndef TL_CHUNK_WAVES
-#define TL_CHUNK_WAVES TL_BULK_WAVES
+#define TL_CHUNK_WAVES 1
 #endif
 
 namespace tl {
@@ -135,16 +137,12 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
   // the sums are v and F - Fref (populations stored about the reference
   // state); F and its stress P(F) in FP64, which enters the equilibrium as
   // the difference P(F)/rho0 - Pref
-  T v[D], dP[D * D];
+  T v[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) v[i] = (L::body ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
-  double F[D * D], P[D * D];
+  double F[D * D];
 #pragma unroll
   for (int k = 0; k < D * D; ++k) F[k] = p.Fref[k] + double(dU[D + k]);
-  typename L::Node law;  // the law's internal variables at the node
-  L::load(p, node, g.S, law);
-  double J = L::stress(p, F, law, P);
-  bool bad = !(J > 0.0);
   if constexpr (TAPE) {
     if (tape) {
 #pragma unroll
@@ -152,13 +150,55 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
     }
   }
   const T inv2c = T(0.5) / T(p.c);
-
+  const T om = T(p.omega);
+  const T srcw = dt * (T(2) - om) / T(4 * D);
+  double Fr[D * D];
   if constexpr (REPAIR) {
-    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61);
-    // the repaired planes hold F^r - I
-    double Fr[D * D], P1[D * D];
+    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61),
+    // deformation rows here, velocity rows with the stress below; the
+    // repaired planes hold F^r - I
 #pragma unroll
     for (int k = 0; k < D * D; ++k) Fr[k] = double(Frp[(size_t)k * g.S + node]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) f[q][D + k] += T((Fr[k] - F[k]) / (2 * D));
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) dU[D + k] = T(Fr[k] - p.Fref[k]);
+  }
+
+  // BGK collision with source weights 1/(4D) (Eqs. 29-30) in the stored
+  // variables: feq_q(U) - feq_q(0, Fref) = (v, F - Fref)/(2D)
+  // + e_qA (Phi_A(U) - Phi_A(0, Fref)) / (2c).
+  // The isotropic part (v, F - Fref)/(2D) once per row, rounded from FP64:
+  // 1/(2D) has no exact FP32 value in 3D, and a rounded factor would bias
+  // the zeroth moment of every collision by the same relative amount.
+  // The deformation rows need v and F but not the stress: they are stored
+  // first, which frees their registers before the stress is formed.
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) {
+    const int r = D + k, i = k / D, B = k % D;
+    const T iso = T(double(dU[r]) * (1.0 / (2 * D)));
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int A = q / 2;
+      const T sg = (q & 1) ? T(-1) : T(1);
+      const T phi = (A == B) ? -v[i] : T(0);
+      const T feq = iso + sg * inv2c * phi;
+      const T out = f[q][r] + om * (feq - f[q][r]);
+      st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
+    }
+  }
+
+  // the first Piola stress in FP64 (law L), which enters the equilibrium as
+  // the difference P(F)/rho0 - Pref, and the velocity rows
+  typename L::Node law;  // the law's internal variables at the node
+  L::load(p, node, g.S, law);
+  double P[D * D];
+  double J = L::stress(p, F, law, P);
+  bool bad = !(J > 0.0);
+  if constexpr (REPAIR) {
+    double P1[D * D];
     const double J1 = L::stress(p, Fr, law, P1);
     bad |= !(J1 > 0.0);
 #pragma unroll
@@ -167,48 +207,26 @@ __device__ __forceinline__ void bulk_node(const T *__restrict__ fin, T *__restri
       const double sg = (q & 1) ? -1.0 : 1.0;
 #pragma unroll
       for (int i = 0; i < D; ++i) f[q][i] += T(sg * (0.5 / p.c) * (-(P1[i * D + A] - P[i * D + A]) * p.inv_rho0));
-#pragma unroll
-      for (int k = 0; k < D * D; ++k) f[q][D + k] += T((Fr[k] - F[k]) / (2 * D));
     }
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) {
-      P[k] = P1[k];
-      dU[D + k] = T(Fr[k] - p.Fref[k]);
-    }
+    for (int k = 0; k < D * D; ++k) P[k] = P1[k];
     J = J1;
   }
+  T dP[D * D];
 #pragma unroll
   for (int k = 0; k < D * D; ++k) dP[k] = T(P[k] * p.inv_rho0 - p.Pref[k]);
   // internal variables advance with the deformation the collision uses
   L::commit(p, law, node, g.S);
-
-  // BGK collision with source weights 1/(4D) (Eqs. 29-30) in the stored
-  // variables: feq_q(U) - feq_q(0, Fref) = (v, F - Fref)/(2D)
-  // + e_qA (Phi_A(U) - Phi_A(0, Fref)) / (2c).
-  // The isotropic part (v, F - Fref)/(2D) once per row, rounded from FP64:
-  // 1/(2D) has no exact FP32 value in 3D, and a rounded factor would bias
-  // the zeroth moment of every collision by the same relative amount.
-  const T om = T(p.omega);
-  const T srcw = dt * (T(2) - om) / T(4 * D);
-  T iso[M];
 #pragma unroll
-  for (int r = 0; r < M; ++r) iso[r] = T(double(r < D ? v[r] : dU[r]) * (1.0 / (2 * D)));
+  for (int r = 0; r < D; ++r) {
+    const T iso = T(double(v[r]) * (1.0 / (2 * D)));
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int A = q / 2;
-    const T sg = (q & 1) ? T(-1) : T(1);
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-      T phi;
-      if (r < D) {
-        phi = -dP[r * D + A];
-      } else {
-        const int i = (r - D) / D, B = (r - D) % D;
-        phi = (A == B) ? -v[i] : T(0);
-      }
-      const T feq = iso[r] + sg * inv2c * phi;
+    for (int q = 0; q < Q; ++q) {
+      const int A = q / 2;
+      const T sg = (q & 1) ? T(-1) : T(1);
+      const T feq = iso + sg * inv2c * (-dP[r * D + A]);
       T out = f[q][r] + om * (feq - f[q][r]);
-      if (r < D) out += srcw * (L::body ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
+      out += srcw * (L::body ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
     }
   }
@@ -273,24 +291,62 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
   // the sums are v and F - Fref (populations stored about the reference
   // state); F and its stress P(F) in FP64, which enters the equilibrium as
   // the difference P(F)/rho0 - Pref
-  T v[D], dP[D * D];
+  T v[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) v[i] = (L::body ? dU[i] + T(0.5) * dt * bacc[i] : dU[i]) * inv_damp;
-  double F[D * D], P[D * D];
+  double F[D * D];
 #pragma unroll
   for (int k = 0; k < D * D; ++k) F[k] = p.Fref[k] + double(dU[D + k]);
-  typename L::Node law;  // the law's internal variables at the node
-  L::load(p, node, g.S, law);
-  double J = L::stress(p, F, law, P);
-  bool bad = !(J > 0.0);
   const T inv2c = T(0.5) / T(p.c);
-
+  const T om = T(p.omega);
+  const T srcw = dt * (T(2) - om) / T(4 * D);
+  double Fr[D * D];
   if constexpr (REPAIR) {
-    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61);
-    // the repaired planes hold F^r - I
-    double Fr[D * D], P1[D * D];
+    // population repair f += feq(v, F^r) - feq(v, F) (Sec. 3.5, Eq. 61),
+    // deformation rows here, velocity rows with the stress below; the
+    // repaired planes hold F^r - I
 #pragma unroll
     for (int k = 0; k < D * D; ++k) Fr[k] = double(Frp[(size_t)k * g.S + node]) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) f[q][D + k] += T((Fr[k] - F[k]) / (2 * D));
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) dU[D + k] = T(Fr[k] - p.Fref[k]);
+  }
+
+  // BGK collision with source weights 1/(4D) (Eqs. 29-30) in the stored
+  // variables: feq_q(U) - feq_q(0, Fref) = (v, F - Fref)/(2D)
+  // + e_qA (Phi_A(U) - Phi_A(0, Fref)) / (2c).
+  // The isotropic part (v, F - Fref)/(2D) once per row, rounded from FP64:
+  // 1/(2D) has no exact FP32 value in 3D, and a rounded factor would bias
+  // the zeroth moment of every collision by the same relative amount.
+  // The deformation rows need v and F but not the stress: they are stored
+  // first, which frees their registers before the stress is formed.
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) {
+    const int r = D + k, i = k / D, B = k % D;
+    const T iso = T(double(dU[r]) * (1.0 / (2 * D)));
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int A = q / 2;
+      const T sg = (q & 1) ? T(-1) : T(1);
+      const T phi = (A == B) ? -v[i] : T(0);
+      const T feq = iso + sg * inv2c * phi;
+      const T out = f[q][r] + om * (feq - f[q][r]);
+      st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
+    }
+  }
+
+  // the first Piola stress in FP64 (law L), which enters the equilibrium as
+  // the difference P(F)/rho0 - Pref, and the velocity rows
+  typename L::Node law;  // the law's internal variables at the node
+  L::load(p, node, g.S, law);
+  double P[D * D];
+  double J = L::stress(p, F, law, P);
+  bool bad = !(J > 0.0);
+  if constexpr (REPAIR) {
+    double P1[D * D];
     const double J1 = L::stress(p, Fr, law, P1);
     bad |= !(J1 > 0.0);
 #pragma unroll
@@ -299,48 +355,26 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk(const T *__restrict
       const double sg = (q & 1) ? -1.0 : 1.0;
 #pragma unroll
       for (int i = 0; i < D; ++i) f[q][i] += T(sg * (0.5 / p.c) * (-(P1[i * D + A] - P[i * D + A]) * p.inv_rho0));
-#pragma unroll
-      for (int k = 0; k < D * D; ++k) f[q][D + k] += T((Fr[k] - F[k]) / (2 * D));
     }
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) {
-      P[k] = P1[k];
-      dU[D + k] = T(Fr[k] - p.Fref[k]);
-    }
+    for (int k = 0; k < D * D; ++k) P[k] = P1[k];
     J = J1;
   }
+  T dP[D * D];
 #pragma unroll
   for (int k = 0; k < D * D; ++k) dP[k] = T(P[k] * p.inv_rho0 - p.Pref[k]);
   // internal variables advance with the deformation the collision uses
   L::commit(p, law, node, g.S);
-
-  // BGK collision with source weights 1/(4D) (Eqs. 29-30) in the stored
-  // variables: feq_q(U) - feq_q(0, Fref) = (v, F - Fref)/(2D)
-  // + e_qA (Phi_A(U) - Phi_A(0, Fref)) / (2c).
-  // The isotropic part (v, F - Fref)/(2D) once per row, rounded from FP64:
-  // 1/(2D) has no exact FP32 value in 3D, and a rounded factor would bias
-  // the zeroth moment of every collision by the same relative amount.
-  const T om = T(p.omega);
-  const T srcw = dt * (T(2) - om) / T(4 * D);
-  T iso[M];
 #pragma unroll
-  for (int r = 0; r < M; ++r) iso[r] = T(double(r < D ? v[r] : dU[r]) * (1.0 / (2 * D)));
+  for (int r = 0; r < D; ++r) {
+    const T iso = T(double(v[r]) * (1.0 / (2 * D)));
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int A = q / 2;
-    const T sg = (q & 1) ? T(-1) : T(1);
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-      T phi;
-      if (r < D) {
-        phi = -dP[r * D + A];
-      } else {
-        const int i = (r - D) / D, B = (r - D) % D;
-        phi = (A == B) ? -v[i] : T(0);
-      }
-      const T feq = iso[r] + sg * inv2c * phi;
+    for (int q = 0; q < Q; ++q) {
+      const int A = q / 2;
+      const T sg = (q & 1) ? T(-1) : T(1);
+      const T feq = iso + sg * inv2c * (-dP[r * D + A]);
       T out = f[q][r] + om * (feq - f[q][r]);
-      if (r < D) out += srcw * (L::body ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
+      out += srcw * (L::body ? bacc[r] - T(p.gamma) * v[r] : -T(p.gamma) * v[r]);
       st_pop(fout + (size_t)(q * M + r) * g.S + node, out);
     }
   }
@@ -402,7 +436,7 @@ __global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_chunks(const T *__
 
 // the chunked update recording the recovered state on the reverse-mode tape
 template <int D, typename T, bool TRACK, bool REPAIR, class L>
-__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks_tape(
+__global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_chunks_tape(
     const T *__restrict__ fin, T *__restrict__ fout, Geo g, Par p, const uint8_t *__restrict__ act,
     double *__restrict__ ustar, double *__restrict__ ubuf, const T *__restrict__ Frp, int *__restrict__ flag,
     T *__restrict__ tape, const int32_t *__restrict__ chunks, int nchunks) {
@@ -420,7 +454,7 @@ __global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_chunks_tape(
 // Batched bulk update: one block per tile (instance, row, first x) of the
 // tile list; every instance keeps its own geometry, material and buffers.
 template <int D, typename T, bool REPAIR>
-__global__ __launch_bounds__(256, TL_BULK_WAVES) void k_bulk_batch(const Inst *__restrict__ insts,
+__global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_batch(const Inst *__restrict__ insts,
                                                                    const int4 *__restrict__ tiles) {
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];

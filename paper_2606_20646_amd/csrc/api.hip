@@ -295,7 +295,7 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
                   c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles,
-                  c->cg.nbm, c->bf, c->chunks, c->cpos, c->d_bcs, c->hist};
+                  c->cg.jt, c->cg.nbm, c->bf, c->chunks, c->cpos, c->d_bcs, c->hist};
   for (void *p : ptrs)
     if (p) dfree(c, p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);

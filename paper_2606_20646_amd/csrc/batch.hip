@@ -23,6 +23,10 @@ struct tlvlbm_batch {
   Inst *d_inst = nullptr;
   int4 *d_btiles = nullptr, *d_ctiles = nullptr, *d_ltiles = nullptr;
   int nbt = 0, nct = 0, nlt = 0;
+  // 2D: tiles (instance, tx, ty) of the fused Jacobi sweeps (none: one
+  // launch per sweep)
+  int4 *d_jtiles = nullptr;
+  int njt = 0;
   // node-kernel tiles: tw nodes of one row holding active nodes, in order
   // `torder` (0: instance by instance, 1: round robin over the instances);
   // chosen by batch_autotune
@@ -74,16 +78,19 @@ BatchArgs args_of(tlvlbm_batch *b) {
   a.nlt = b->nlt;
   a.ctiles = b->d_ctiles;
   a.nct = b->nct;
+  a.jtiles = b->d_jtiles;
+  a.njt = b->njt;
   a.step = b->d_step;
   a.pending = b->d_pending;
   a.om = b->jw;
   return a;
 }
 
-void run(tlvlbm_batch *b, BatchOp op, int fa = 0, int fb = 0) {
+void run(tlvlbm_batch *b, BatchOp op, int fa = 0, int fb = 0, int nsw = 0) {
   BatchArgs a = args_of(b);
   a.flagA = fa;
   a.flagB = fb;
+  a.nsw = nsw;
   launch_batch(b->D, b->prec, op, a);
 }
 
@@ -98,9 +105,16 @@ tlvlbm_status cg_batch(tlvlbm_batch *b, int useFr) {
   }
   run(b, BatchOp::Rhs, useFr, anch);
   if (b->sweeps > 0) {
-    // damped Jacobi relaxation: sweeps alternate x -> r and r -> x
-    for (int k = 0; k < b->sweeps; ++k) run(b, BatchOp::Jacobi, k & 1, anch);
-    if (b->sweeps & 1) run(b, BatchOp::JacobiCopy);
+    // damped Jacobi relaxation: launches alternate x -> r and r -> x (2D:
+    // up to JT_NS sweeps per launch, staged in LDS)
+    int dir = 0;
+    for (int k = 0; k < b->sweeps;) {
+      const int ns = b->njt ? std::min(b->sweeps - k, JT_NS) : 1;
+      run(b, b->njt ? BatchOp::JacobiFused : BatchOp::Jacobi, dir, anch, ns);
+      dir ^= 1;
+      k += ns;
+    }
+    if (dir) run(b, BatchOp::JacobiCopy);
     if (!b->capturing)
       for (tlvlbm_ctx *c : b->c) c->st_cg += (int64_t)b->sweeps * c->D;
     return TLVLBM_OK;
@@ -547,6 +561,30 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       tlvlbm_batch_destroy(b);
       return TLVLBM_ERR_DEVICE;
     }
+    // 2D Jacobi projection: the tiles of the fused sweeps, instance by
+    // instance (every instance needs its neighbour masks)
+    if (b->D == 2 && b->any_neu && b->sweeps > 0) {
+      std::vector<int4> jt;
+      std::vector<int32_t> one;
+      bool ok = true;
+      for (int k = 0; k < n && ok; ++k) {
+        const tlvlbm_ctx *c = b->c[k];
+        ok = c->cg.nbm != nullptr &&
+             active_tiles2(c->geo, b->act[k].empty() ? nullptr : b->act[k].data(), one);
+        for (int32_t p : one) jt.push_back(make_int4(k, p & 0xffff, p >> 16, 0));
+      }
+      if (ok && !jt.empty()) {
+        if (hipMalloc(&b->d_jtiles, jt.size() * sizeof(int4)) != hipSuccess) {
+          tlvlbm_batch_destroy(b);
+          return TLVLBM_ERR_OUT_OF_MEMORY;
+        }
+        if (hipMemcpy(b->d_jtiles, jt.data(), jt.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) {
+          tlvlbm_batch_destroy(b);
+          return TLVLBM_ERR_DEVICE;
+        }
+        b->njt = (int)jt.size();
+      }
+    }
     // tile configuration of the node kernels, timed on this batch
     const tlvlbm_status ts = batch_autotune(b, 3);
     if (ts) {
@@ -662,7 +700,7 @@ tlvlbm_status tlvlbm_batch_destroy(tlvlbm_batch *b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->gcycle) (void)hipGraphExecDestroy(b->gcycle);
   batch_mg_free(b->bmg);
-  void *ptrs[] = {b->d_inst, b->d_btiles, b->d_ctiles, b->d_ltiles, b->d_segs, b->d_step, b->d_pending};
+  void *ptrs[] = {b->d_inst, b->d_btiles, b->d_ctiles, b->d_ltiles, b->d_jtiles, b->d_segs, b->d_step, b->d_pending};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (b->h_pending) (void)hipHostFree(b->h_pending);

@@ -889,6 +889,17 @@ __device__ __forceinline__ void jacobi_node(const Geo &g, const uint8_t *__restr
   }
 }
 
+// one component of one node's damped Jacobi update: node value xi,
+// right-hand side bi, neighbour values xn[q] (used where bit q of the mask m
+// says X + e_q is active), diagonal deg > 0
+template <int D>
+__device__ __forceinline__ double jacobi_upd(double xi, double bi, const double *xn, unsigned m, int deg, double om) {
+  double kx = double(deg) * xi;
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q) kx -= ((m >> q) & 1u) ? xn[q] : 0.0;
+  return xi + om * (bi - kx) / double(deg);
+}
+
 // the same sweep from the precomputed neighbour mask (bit q: X + e_q active,
 // bit 6: X active); the same operations in the same order
 template <int D>
@@ -926,14 +937,104 @@ __device__ __forceinline__ void jacobi_node_m(const Geo &g, const uint8_t *__res
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     const size_t o = (size_t)c * g.S;
-    if (deg == 0) {
-      xout[o + i] = xi[c];
-      continue;
-    }
-    double kx = double(deg) * xi[c];
+    xout[o + i] = deg == 0 ? xi[c] : jacobi_upd<D>(xi[c], bi[c], xn[c], m, deg, om);
+  }
+}
+
+// JT_NS or fewer damped Jacobi sweeps of a 2D grid fused in LDS.  The tile
+// (tx, ty) of JT x JT nodes and a halo of ns nodes (wrapped on periodic
+// axes) are staged once; sweep s updates the active nodes at least s nodes
+// inside the staged square, whose four neighbours then hold the values of
+// sweep s - 1, so after ns sweeps the tile holds exactly what ns separate
+// sweeps give, and only the tile is written.  Every update is jacobi_upd,
+// as in jacobi_node_m.  Staged nodes outside a non-periodic grid, and
+// inactive ones, are never read: no mask bit points at them.
+constexpr int JT_W = JT + 2 * JT_NS;
+constexpr int JT_OWN = (JT_W * JT_W + CG_T - 1) / CG_T;  // staged nodes per thread
+__device__ __forceinline__ void jacobi_tile2(const Geo &g, const uint8_t *__restrict__ nbm,
+                                             const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
+                                             const double *__restrict__ xin, double *__restrict__ xout, double om,
+                                             int tx, int ty, int ns, double2 *sx) {
+  const int W = JT + 2 * ns, R = W * W;
+  const int gx0 = tx * JT - ns, gy0 = ty * JT - ns;
+  const size_t S = (size_t)g.S;
+  int pos[JT_OWN];       // lx | ly << 8 of the staged node, -1: none
+  unsigned md[JT_OWN];   // neighbour mask | diagonal << 8 (0: inactive)
+  int64_t gi[JT_OWN];    // its node (0 where it has none)
+  double b0[JT_OWN], b1[JT_OWN], n0[JT_OWN], n1[JT_OWN];
+  bool in[JT_OWN];
 #pragma unroll
-    for (int q = 0; q < 2 * D; ++q) kx -= nb[q] >= 0 ? xn[c][q] : 0.0;
-    xout[o + i] = xi[c] + om * (bi[c] - kx) / double(deg);
+  for (int j = 0; j < JT_OWN; ++j) {
+    const int r = (int)threadIdx.x + j * CG_T;
+    const int lx = r % W, ly = r / W;
+    pos[j] = r < R ? lx | (ly << 8) : -1;
+    int gx = gx0 + lx, gy = gy0 + ly;
+    in[j] = r < R;
+    if (gx < 0 || gx >= g.nx) {
+      if (g.per & 1) gx = ((gx % g.nx) + g.nx) % g.nx;
+      else in[j] = false;
+    }
+    if (gy < 0 || gy >= g.ny) {
+      if (g.per & 2) gy = ((gy % g.ny) + g.ny) % g.ny;
+      else in[j] = false;
+    }
+    gi[j] = in[j] ? gx + (int64_t)g.nx * gy : 0;
+  }
+  // every load issued before any is used (node 0 stands in where a staged
+  // position has no node), so that all of them are in flight together
+  unsigned mm[JT_OWN], an[JT_OWN];
+  double x0[JT_OWN], x1[JT_OWN];
+#pragma unroll
+  for (int j = 0; j < JT_OWN; ++j) {
+    mm[j] = nbm[gi[j]];
+    an[j] = anc_n ? anc_n[gi[j]] : 0u;
+    b0[j] = b[gi[j]];
+    b1[j] = b[S + gi[j]];
+    x0[j] = xin[gi[j]];
+    x1[j] = xin[S + gi[j]];
+  }
+#pragma unroll
+  for (int j = 0; j < JT_OWN; ++j) {
+    const bool a = in[j] && (mm[j] & 64u);
+    md[j] = a ? (mm[j] | ((an[j] + (unsigned)__builtin_popcount(mm[j] & 15u)) << 8)) : 0u;
+    if (pos[j] >= 0) sx[(int)threadIdx.x + j * CG_T] = a ? make_double2(x0[j], x1[j]) : make_double2(0.0, 0.0);
+    n0[j] = n1[j] = 0.0;
+  }
+  __syncthreads();
+  for (int s = 1; s <= ns; ++s) {
+    bool up[JT_OWN];
+#pragma unroll
+    for (int j = 0; j < JT_OWN; ++j) {
+      const int r = (int)threadIdx.x + j * CG_T;
+      const int lx = pos[j] & 255, ly = pos[j] >> 8;
+      const int deg = (int)(md[j] >> 8);
+      up[j] = pos[j] >= 0 && deg > 0 && lx >= s && lx < W - s && ly >= s && ly < W - s;
+      // no branch around the reads: a position that is not updated reads
+      // an interior one instead (its result is dropped)
+      const int rc = up[j] ? r : W + 1;
+      const double2 c0 = sx[rc], e = sx[rc + 1], w = sx[rc - 1], n = sx[rc + W], o = sx[rc - W];
+      const double xa[4] = {e.x, w.x, n.x, o.x}, xb[4] = {e.y, w.y, n.y, o.y};
+      const unsigned m = md[j] & 255u;
+      const int dg = up[j] ? deg : 1;
+      n0[j] = jacobi_upd<2>(c0.x, b0[j], xa, m, dg, om);
+      n1[j] = jacobi_upd<2>(c0.y, b1[j], xb, m, dg, om);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < JT_OWN; ++j)
+      if (up[j]) sx[(int)threadIdx.x + j * CG_T] = make_double2(n0[j], n1[j]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < JT_OWN; ++j) {
+    const int lx = pos[j] & 255, ly = pos[j] >> 8;
+    if (pos[j] < 0 || !(md[j] & 64u) || lx < ns || lx >= ns + JT || ly < ns || ly >= ns + JT) continue;
+    // the tile proper: no wrap (a last tile's columns or rows past the grid
+    // are wrapped copies and are not written)
+    if (tx * JT + lx - ns >= g.nx || ty * JT + ly - ns >= g.ny) continue;
+    const double2 v = sx[(int)threadIdx.x + j * CG_T];
+    xout[gi[j]] = v.x;
+    xout[S + gi[j]] = v.y;
   }
 }
 
@@ -1143,6 +1244,19 @@ __global__ __launch_bounds__(CG_T) void k_jacobi(Geo g, const uint8_t *__restric
   if (t >= ntile) return;
   const int64_t blk = tiles ? (int64_t)tiles[t] : (int64_t)t;
   jacobi_node_m<D>(g, nbm, anc_n, b, xin, xout, om, blk * CG_T + threadIdx.x);
+}
+
+// fused 2D sweeps over the tiles jt (the XCD-aware order of k_jacobi)
+__global__ __launch_bounds__(CG_T) void k_jacobi_fused2(Geo g, const uint8_t *__restrict__ nbm,
+                                                        const uint8_t *__restrict__ anc_n,
+                                                        const double *__restrict__ b, const double *__restrict__ xin,
+                                                        double *__restrict__ xout, double om,
+                                                        const int32_t *__restrict__ jt, int njt, int per, int ns) {
+  __shared__ double2 sx[JT_W * JT_W];
+  const int t = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+  if (t >= njt) return;
+  const int32_t p = jt[t];
+  jacobi_tile2(g, nbm, anc_n, b, xin, xout, om, p & 0xffff, p >> 16, ns, sx);
 }
 
 template <int D>
@@ -1501,10 +1615,22 @@ template <int D> static int jacobi_run(tlvlbm_ctx *c, const uint8_t *anc_n) {
   const unsigned nt = w.tiles ? (unsigned)w.ntiles : nblk(g.N, CG_T);
   const int per = (int)((nt + NXCD - 1) / NXCD);
   double *a = (double *)w.x, *bb = (double *)w.r;
-  for (int k = 0; k < c->proj_sweeps; ++k) {
-    hipLaunchKernelGGL((k_jacobi<D>), (unsigned)(per * NXCD), CG_T, 0, st, g, w.nbm, anc_n, (const double *)w.b,
-                       (const double *)a, bb, c->proj_weight, w.tiles, (int)nt, per);
-    std::swap(a, bb);
+  if (D == 2 && w.jt) {
+    // up to JT_NS sweeps per launch, staged in LDS
+    const int per2 = (w.njt + NXCD - 1) / NXCD;
+    for (int left = c->proj_sweeps; left > 0;) {
+      const int ns = std::min(left, JT_NS);
+      hipLaunchKernelGGL(k_jacobi_fused2, (unsigned)(per2 * NXCD), CG_T, 0, st, g, w.nbm, anc_n,
+                         (const double *)w.b, (const double *)a, bb, c->proj_weight, w.jt, w.njt, per2, ns);
+      std::swap(a, bb);
+      left -= ns;
+    }
+  } else {
+    for (int k = 0; k < c->proj_sweeps; ++k) {
+      hipLaunchKernelGGL((k_jacobi<D>), (unsigned)(per * NXCD), CG_T, 0, st, g, w.nbm, anc_n, (const double *)w.b,
+                         (const double *)a, bb, c->proj_weight, w.tiles, (int)nt, per);
+      std::swap(a, bb);
+    }
   }
   if (a != (double *)w.x)
     hipLaunchKernelGGL((k_copy_planes<D>), nt, CG_T, 0, st, g, (const double *)a, (double *)w.x, w.tiles, w.nbm);
@@ -1799,6 +1925,21 @@ __global__ __launch_bounds__(CG_T) void k_jacobi_batch(const Inst *__restrict__ 
                    (int64_t)t.y * CG_T + threadIdx.x);
 }
 
+// fused 2D sweeps of the batch: tiles (instance, tx, ty) in the XCD-aware
+// order of k_jacobi; dir as in k_jacobi_batch
+__global__ __launch_bounds__(CG_T) void k_jacobi_fused2_batch(const Inst *__restrict__ insts,
+                                                              const int4 *__restrict__ jt, int njt, int per, int dir,
+                                                              int anchored, double om, int ns) {
+  __shared__ double2 sx[JT_W * JT_W];
+  const int t = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+  if (t >= njt) return;
+  const int4 q = jt[t];
+  const Inst &I = insts[q.x];
+  const double *xin = (const double *)(dir ? I.r : I.x);
+  double *xout = (double *)(dir ? I.x : I.r);
+  jacobi_tile2(I.g, I.nbm, anchored ? I.anc_n : nullptr, (const double *)I.b, xin, xout, om, q.y, q.z, ns, sx);
+}
+
 template <int D>
 __global__ __launch_bounds__(CG_T) void k_jacobi_copy_batch(const Inst *__restrict__ insts,
                                                             const int4 *__restrict__ tiles) {
@@ -1902,6 +2043,13 @@ static void batch_kernels_t(BatchOp op, const BatchArgs &a) {
       break;
     case BatchOp::Jacobi:
       hipLaunchKernelGGL((k_jacobi_batch<D>), a.nct, CG_T, 0, st, a.insts, a.ctiles, a.flagA, a.flagB, a.om);
+      break;
+    case BatchOp::JacobiFused:
+      if (D == 2) {
+        const int per = (a.njt + NXCD - 1) / NXCD;
+        hipLaunchKernelGGL(k_jacobi_fused2_batch, (unsigned)(per * NXCD), CG_T, 0, st, a.insts, a.jtiles, a.njt, per,
+                           a.flagA, a.flagB, a.om, a.nsw);
+      }
       break;
     case BatchOp::JacobiCopy:
       hipLaunchKernelGGL((k_jacobi_copy_batch<D>), a.nct, CG_T, 0, st, a.insts, a.ctiles);

@@ -592,6 +592,17 @@ int proj_aux_build(tlvlbm_ctx *c) {
     if (c->cg.tiles) dfree(c, c->cg.tiles);
     c->cg.tiles = nullptr;
     c->cg.ntiles = 0;
+    if (c->cg.jt) dfree(c, c->cg.jt);
+    c->cg.jt = nullptr;
+    c->cg.njt = 0;
+    // 2D: the tiles of the fused Jacobi sweeps
+    std::vector<int32_t> jt;
+    if (c->D == 2 && active_tiles2(g, act.data(), jt) && !jt.empty()) {
+      if (dmalloc(c, &c->cg.jt, jt.size() * sizeof(int32_t)) != hipSuccess) return TLVLBM_ERR_OUT_OF_MEMORY;
+      if (hipMemcpy(c->cg.jt, jt.data(), jt.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+        return TLVLBM_ERR_DEVICE;
+      c->cg.njt = (int)jt.size();
+    }
     // neighbour masks of the active-node graph: the Jacobi sweeps read one
     // byte per node instead of the seven activity flags and coordinates
     std::vector<uint8_t> nbm(N, 0);

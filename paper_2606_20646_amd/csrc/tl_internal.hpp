@@ -24,6 +24,13 @@ constexpr int KMAX2 = 24;
 constexpr int CHUNK = TL_CHUNK;
 constexpr int KMAX3 = 88;
 constexpr double LSQ_RADIUS = 2.5;
+// 2D projection sweeps fused in LDS: tiles of JT x JT nodes, JT_NS sweeps per
+// launch (the staged halo is JT_NS nodes wide)
+constexpr int JT = 32;
+#ifndef TL_JACOBI_FUSE
+#define TL_JACOBI_FUSE 5
+#endif
+constexpr int JT_NS = TL_JACOBI_FUSE;
 
 // grid geometry passed by value to kernels
 struct Geo {
@@ -153,6 +160,8 @@ struct CG {
   int32_t *tiles = nullptr;                         // 256-node tiles holding active nodes
   int ntiles = 0;
   uint8_t *nbm = nullptr;  // per node: bit q = neighbour X + e_q active, bit 6 = node active
+  int32_t *jt = nullptr;   // 2D: JT x JT tiles holding active nodes (tx | ty << 16)
+  int njt = 0;
   hipGraphExec_t pcg_graph = nullptr;               // captured batch of preconditioned iterations
   const void *pcg_key = nullptr;                    // anchor array it was captured with
   double *scal = nullptr;                           // device scalars
@@ -192,7 +201,8 @@ struct Seg {
 };
 
 enum class BatchOp { Cut, Anchor, ZeroAnchor, NarrowAnchor, XfromU, UfromX, Rhs, CgInit, CgAp, CgUpdate, GradF,
-                     UReset, StepEnd, Pending, PcInit, PcAp, PcUpdate, PcDot, PcDotFirst, Jacobi, JacobiCopy };
+                     UReset, StepEnd, Pending, PcInit, PcAp, PcUpdate, PcDot, PcDotFirst, Jacobi, JacobiCopy,
+                     JacobiFused };
 
 // one multigrid level of one instance in a batched V-cycle: the view and the
 // level's vectors (b: right-hand side, A and B: the two sweep buffers; the
@@ -229,8 +239,29 @@ struct BatchArgs {
   int64_t *step;       // device step counter
   int *pending;
   int flagA, flagB;
+  const int4 *jtiles;  // 2D tiles of the fused sweeps (instance, tx, ty)
+  int njt;
+  int nsw;             // sweeps of one fused launch
   double om;           // Jacobi weight (projection sweeps)
 };
+
+// JT x JT tiles of a 2D grid that hold an active node, row by row, packed
+// tx | ty << 16 (act null: every node active); false when the grid has more
+// tiles per axis than the packing holds
+inline bool active_tiles2(const Geo &g, const uint8_t *act, std::vector<int32_t> &out) {
+  out.clear();
+  const int tnx = (g.nx + JT - 1) / JT, tny = (g.ny + JT - 1) / JT;
+  if (g.nz != 1 || tnx > 65535 || tny > 32767) return false;
+  std::vector<uint8_t> hit((size_t)tnx * tny, act ? 0 : 1);
+  if (act)
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x)
+        if (act[x + (int64_t)g.nx * y]) hit[(size_t)(y / JT) * tnx + x / JT] = 1;
+  for (int ty = 0; ty < tny; ++ty)
+    for (int tx = 0; tx < tnx; ++tx)
+      if (hit[(size_t)ty * tnx + tx]) out.push_back(tx | (ty << 16));
+  return true;
+}
 
 // host or device arguments crossing the ABI
 inline bool is_device_ptr(const void *p) {

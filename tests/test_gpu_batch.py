@@ -79,8 +79,8 @@ def _batch_tol(precision, sweeps):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("graph,mg,sweeps", [(True, False, 20), (False, False, 20), (True, False, 0),
-                                             (False, False, 0), (True, True, 0)])
+@pytest.mark.parametrize("graph,mg,sweeps", [(True, False, 20), (False, False, 20), (True, False, 13),
+                                             (True, False, 0), (False, False, 0), (True, True, 0)])
 def test_batch_equals_per_instance(env, precision, graph, mg, sweeps):
     tol = _batch_tol(precision, sweeps)
     T, stream = env

@@ -137,12 +137,13 @@ def _tol(precision, sweeps):
     return 1e-5 if precision == "fp32" else 1e-12
 
 
-@pytest.mark.parametrize("sweeps", [20, 0])
+@pytest.mark.parametrize("sweeps", [20, 0, 13])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_mixed_annulus_with_projection(T, orc, precision, sweeps):
     """Clamp + traction-free annulus (the C2 recipe at N = 48): Dirichlet and
     Neumann closures, LSQ, Newton, anchored projection every 20 steps (20
-    Jacobi sweeps, or the exact solve)."""
+    Jacobi sweeps, or the exact solve; 13 sweeps end on a partial fused
+    launch)."""
     c, g, o = _annulus_pair(T, orc, 48, precision, proj_sweeps=sweeps)
     _say(f"annulus 48 {precision} 90 steps, projection sweeps {sweeps}")
     for s in (g, o):
@@ -153,6 +154,40 @@ def test_mixed_annulus_with_projection(T, orc, precision, sweeps):
     act = c["phi"] <= 0
     check(Ug, Uo, 2, _tol(precision, sweeps), ug, uo, mask=act, label=f"annulus 48 {precision} sweeps {sweeps}",
           pops=o.get_f(), steps=90, stress=(c["mu"], c["lam"], 1.0, 10.0, c["omega"]))
+    st = g.stats()
+    assert st["projections"] == 5 and st["newton_failures"] == 0
+
+
+@pytest.mark.parametrize("sweeps", [20, 13])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_periodic_slab_traction(T, orc, precision, sweeps):
+    """A slab periodic in x (70 columns: the last projection tile is ragged
+    and its halo wraps) under opposite shear-and-normal tractions on its two
+    faces (Neumann only: the projection has no anchor and fixes u up to its
+    gauge), against the oracle."""
+    nx, ny, dx = 70, 40, 1 / 64
+    X = (np.tile(np.arange(nx), ny) + 0.5) * dx
+    Y = (np.repeat(np.arange(ny), nx) + 0.5) * dx
+    phi = np.abs(Y - 20 * dx) - 12.3 * dx
+    bid = np.where(Y > 20 * dx, 2, 3).astype(np.uint8)
+    kw = dict(omega=1.8, gamma=10.0, periodic_mask=1, proj_every=20, proj_sweeps=sweeps)
+    g, o = _pair(T, orc, 2, (nx, ny), dx, dx / 10, 1.0, 2.0, precision, **kw)
+    _say(f"periodic slab 70x40 {precision} 90 steps, projection sweeps {sweeps}")
+    for s in (g, o):
+        s.set_levelset(phi, bid)
+    for bb, a in ((2, (0.02, 0.01)), (3, (-0.02, -0.01))):
+        g.set_boundary(bb, "neumann", ramp="sin2", T_r=0.05, a=a)
+        o.set_bc(bb, orc.NEUMANN, ramp=orc.RAMP_SIN2, T_r=0.05, a=a)
+    U0 = np.zeros((6, nx * ny))
+    U0[2] = U0[5] = 1.0
+    for s in (g, o):
+        s.set_state(U0)
+        s.step(90)
+    Ug, ug, _ = g.moments()
+    Uo, uo, _ = o.moments()
+    act = phi <= 0
+    check(Ug, Uo, 2, _tol(precision, sweeps), ug, uo, mask=act, label=f"slab {precision} sweeps {sweeps}",
+          pops=o.get_f(), steps=90, stress=(1.0, 2.0, 1.0, 10.0, 1.8))
     st = g.stats()
     assert st["projections"] == 5 and st["newton_failures"] == 0
 

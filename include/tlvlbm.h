@@ -399,9 +399,9 @@ tlvlbm_status tlvlbm_batch_step(tlvlbm_batch *b, int64_t steps);
 /* 0 disables graph replay (every launch issued from the host) */
 tlvlbm_status tlvlbm_batch_set_graph(tlvlbm_batch *b, int32_t use_graph);
 /* Tile configuration of the batched node kernels (bulk update, moments):
- * tiles of tile_width nodes (64, 128 or 256; one workgroup each) of one row
- * that hold active nodes, in order 0 (instance by instance) or 1 (round
- * robin over the instances).  tlvlbm_batch_create picks the configuration
+ * spans of tile_width nodes (64, 128 or 256; one workgroup each) of an
+ * instance's node order, aligned to tile_width, that hold active nodes, in
+ * order 0 (instance by instance) or 1 (round robin over the instances).  tlvlbm_batch_create picks the configuration
  * by timing the bulk kernel over each of the six on the batch's own state
  * (3 timed launches each; u* and u are saved and restored, no step is
  * taken); tlvlbm_batch_autotune repeats that with `reps` timed launches;

@@ -27,7 +27,8 @@ struct tlvlbm_batch {
   // launch per sweep)
   int4 *d_jtiles = nullptr;
   int njt = 0;
-  // node-kernel tiles: tw nodes of one row holding active nodes, in order
+  // node-kernel tiles: spans of tw nodes of an instance's node order (aligned
+  // to tw) holding active nodes, in order
   // `torder` (0: instance by instance, 1: round robin over the instances);
   // chosen by batch_autotune
   int tw = 256, torder = 0;
@@ -191,7 +192,9 @@ tlvlbm_status projection_step(tlvlbm_batch *b) {
   return TLVLBM_OK;
 }
 
-// tiles of W nodes of one row that hold active nodes; order 0: instance by
+// spans k W .. (k + 1) W - 1 of an instance's node order that hold active
+// nodes, as (instance, k); the spans are aligned to W nodes in every plane,
+// so their loads and stores start on a cache line; order 0: instance by
 // instance, 1: round robin over the instances (tile r of each, then r + 1)
 std::vector<int4> node_tiles(const tlvlbm_batch *b, int W, int order) {
   const int ni = (int)b->c.size();
@@ -199,12 +202,11 @@ std::vector<int4> node_tiles(const tlvlbm_batch *b, int W, int order) {
   for (int k = 0; k < ni; ++k) {
     const Geo &g = b->c[k]->geo;
     const std::vector<uint8_t> &a = b->act[k];
-    for (int row = 0; row < g.ny * g.nz; ++row)
-      for (int x0 = 0; x0 < g.nx; x0 += W) {
-        bool any = a.empty();
-        for (int x = x0; x < std::min(g.nx, x0 + W) && !any; ++x) any = a[(size_t)row * g.nx + x] != 0;
-        if (any) per[k].push_back(make_int4(k, row, x0, 0));
-      }
+    for (int64_t s = 0; s < g.N; s += W) {
+      bool any = a.empty();
+      for (int64_t i = s; i < std::min<int64_t>(g.N, s + W) && !any; ++i) any = a[(size_t)i] != 0;
+      if (any) per[k].push_back(make_int4(k, (int)(s / W), 0, 0));
+    }
   }
   std::vector<int4> t;
   if (order == 0) {

@@ -458,10 +458,11 @@ __global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_batch(const Inst *
                                                                    const int4 *__restrict__ tiles) {
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
-  const int x = t.z + threadIdx.x;
-  if (x >= I.g.nx) return;
+  const int64_t node = (int64_t)t.y * blockDim.x + threadIdx.x;
+  if (node >= I.g.N) return;
+  const int row = (int)(node / I.g.nx), x = (int)(node - (int64_t)row * I.g.nx);
   bulk_node<D, T, true, true, REPAIR>((const T *)I.fin, (T *)I.fout, I.g, I.p, I.act, (double *)I.ustar,
-                                      (double *)I.ubuf, (const T *)I.Fr, I.flag, x, t.y);
+                                      (double *)I.ubuf, (const T *)I.Fr, I.flag, x, row);
 }
 
 // Pull f^n and write moments: v (damping-corrected), F, u = u* + dt/2 v, J.
@@ -576,10 +577,11 @@ __global__ __launch_bounds__(256) void k_moments_batch(const Inst *__restrict__ 
                                                         const int4 *__restrict__ tiles) {
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
-  const int x = t.z + threadIdx.x;
-  if (x >= I.g.nx) return;
+  const int64_t node = (int64_t)t.y * blockDim.x + threadIdx.x;
+  if (node >= I.g.N) return;
+  const int row = (int)(node / I.g.nx), x = (int)(node - (int64_t)row * I.g.nx);
   moments_node<D, T, T, true, true>((const T *)I.fin, I.g, I.p, I.act, (const double *)I.ustar, (T *)I.V, (T *)I.Fm,
-                              (double *)I.ubuf, (T *)nullptr, I.g.S, x, t.y);
+                              (double *)I.ubuf, (T *)nullptr, I.g.S, x, row);
 }
 
 // Second-order initialisation (Sec. 2.4, Eqs. 32-33) in FP64, stored
@@ -1024,7 +1026,7 @@ void launch_put_f(tlvlbm_ctx *c, const double *f, const double *ustar) {
 
 namespace tl {
 
-// batched launchers: tiles are (instance, row, first x, 0) triples of 256 nodes
+// batched launchers: tiles are (instance, k) pairs, nodes k tw .. (k + 1) tw - 1 of the instance
 template <int D, typename T>
 static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw, hipStream_t st) {
   if (repair)

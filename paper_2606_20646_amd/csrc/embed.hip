@@ -951,6 +951,8 @@ __device__ __forceinline__ void jacobi_node_m(const Geo &g, const uint8_t *__res
 // inactive ones, are never read: no mask bit points at them.
 constexpr int JT_W = JT + 2 * JT_NS;
 constexpr int JT_OWN = (JT_W * JT_W + CG_T - 1) / CG_T;  // staged nodes per thread
+static_assert(JT_NS >= 1 && JT_W < 256 && JT_W * JT_W * 16 <= 65536,
+              "fused sweeps: 1 <= JT_NS, the staged square within the LDS of one workgroup");
 __device__ __forceinline__ void jacobi_tile2(const Geo &g, const uint8_t *__restrict__ nbm,
                                              const uint8_t *__restrict__ anc_n, const double *__restrict__ b,
                                              const double *__restrict__ xin, double *__restrict__ xout, double om,

@@ -88,6 +88,9 @@ def lib():
         L.orc_visco_piola_jvp.argtypes = [C.c_int] + [C.c_double] * 4 + [dp] * 5
         L.orc_visco_path.argtypes = [C.c_int] + [C.c_double] * 5 + [C.c_int64, dp, dp]
         L.orc_stress.argtypes = [C.c_void_p, dp, dp]
+        L.orc_set_thermal.argtypes = [C.c_void_p, dp]
+        L.orc_thermal_piola.argtypes = [C.c_int] + [C.c_double] * 3 + [dp, C.c_double, dp, dp]
+        L.orc_thermal_piola_jvp.argtypes = [C.c_int] + [C.c_double] * 3 + [dp, C.c_double, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -180,6 +183,30 @@ def visco_piola_jvp(F, dF, mu, lam, beta, xi, Qh, S0h):
     st = lib().orc_visco_piola_jvp(D, mu, lam, beta, xi, _d(Qh), _d(S0h), _d(F), _d(dF), _d(dP))
     if st:
         raise OracleError(st, "visco_piola_jvp")
+    return dP
+
+
+def thermal_piola(F, mu, lam, th, k1=0.0, a0=(1.0, 0.0, 0.0)):
+    """P(F) = th^(D-1) P_W(F / th): the law (fibres k1 along a0) at a node
+    with thermal stretch th."""
+    F = _f64(F)
+    D = F.shape[0]
+    a = _f64(list(a0) + [0.0] * (3 - len(a0)))
+    P = np.zeros((D, D))
+    st = lib().orc_thermal_piola(D, mu, lam, k1, _d(a), float(th), _d(F), _d(P))
+    if st:
+        raise OracleError(st, "thermal_piola")
+    return P
+
+
+def thermal_piola_jvp(F, dF, mu, lam, th, k1=0.0, a0=(1.0, 0.0, 0.0)):
+    F, dF = _f64(F), _f64(dF)
+    D = F.shape[0]
+    a = _f64(list(a0) + [0.0] * (3 - len(a0)))
+    dP = np.zeros((D, D))
+    st = lib().orc_thermal_piola_jvp(D, mu, lam, k1, _d(a), float(th), _d(F), _d(dF), _d(dP))
+    if st:
+        raise OracleError(st, "thermal_piola_jvp")
     return dP
 
 
@@ -334,6 +361,14 @@ class Sim:
         if st:
             raise OracleError(st, "stress")
         return P, S
+
+    def set_thermal(self, th):
+        """Thermal stretch th [N] (> 0; None removes it): P = th^(D-1) P_W(F/th)."""
+        tp = None if th is None else _d(_keep(self, _f64(th).reshape(self.N)))
+        st = lib().orc_set_thermal(self.h, tp)
+        self._tmps = []
+        if st:
+            raise OracleError(st, "set_thermal")
 
     def set_body_force(self, g, ramp=RAMP_CONST, T_r=1.0):
         """Body acceleration b(X, t) = s(t) g(X), g [D][N] (None clears)."""

@@ -170,15 +170,26 @@ int orc_piola_jvp(int D, double mu, double lam, const double *F, const double *d
  *   dC = dF^T F + F^T dF.
  * tau -> infinity (xi = 1) from an undeformed start gives the neo-Hookean
  * solid with shear modulus mu (1 + beta); tau -> 0 (xi = 0) the equilibrium
- * law.  Qh = NULL: no branch. */
+ * law.  Qh = NULL: no branch.
+ *
+ * Optionally a thermal stretch th > 0 at the node, the thermal distortion
+ * the outlook names for thermoelasticity (Sec. 6): the temperature field,
+ * advanced by whatever solves for it, enters as the isotropic stretch
+ * F_th = th I of the multiplicative split F = F_e F_th, with the energy per
+ * reference volume det(F_th) W(F_e).  Then
+ *   P(F) = th^(D-1) P_W(F / th),
+ * P_W the stress of the law above, and its tangent is
+ *   dP = th^(D-1) dP_W(F / th; dF / th).
+ * th = 1: no stretch. */
 typedef struct {
   double mu, lam, k1, a0[3];
   double beta, xi;
   const double *Qh, *S0h; /* D x D history of the node, or NULL */
+  double th;              /* thermal stretch of the node (1: none) */
 } orc_mat;
 
 static orc_mat nh_mat(double mu, double lam) {
-  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, 0.0, 0.0, NULL, NULL};
+  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, 0.0, 0.0, NULL, NULL, 1.0};
   return m;
 }
 
@@ -203,7 +214,7 @@ static void visco_Q(int D, const orc_mat *m, const double *F, double *Qv, double
   for (int k = 0; k < D * D; ++k) Qv[k] = m->xi * m->xi * m->Qh[k] + m->beta * m->xi * (S0[k] - m->S0h[k]);
 }
 
-static int mat_piola(int D, const orc_mat *m, const double *F, double *P) {
+static int mat_piola_w(int D, const orc_mat *m, const double *F, double *P) {
   int st = orc_piola(D, m->mu, m->lam, F, P);
   if (st) return st;
   if (m->k1 != 0.0) {
@@ -228,7 +239,7 @@ static int mat_piola(int D, const orc_mat *m, const double *F, double *P) {
   return ORC_OK;
 }
 
-static int mat_piola_jvp(int D, const orc_mat *m, const double *F, const double *dF, double *dP) {
+static int mat_piola_jvp_w(int D, const orc_mat *m, const double *F, const double *dF, double *dP) {
   int st = orc_piola_jvp(D, m->mu, m->lam, F, dF, dP);
   if (st) return st;
   if (m->k1 != 0.0) {
@@ -277,6 +288,30 @@ static int mat_piola_jvp(int D, const orc_mat *m, const double *F, const double 
   return ORC_OK;
 }
 
+/* the law at a node with its thermal stretch (see orc_mat) */
+static int mat_piola(int D, const orc_mat *m, const double *F, double *P) {
+  if (m->th == 1.0) return mat_piola_w(D, m, F, P);
+  double Fe[9];
+  for (int k = 0; k < D * D; ++k) Fe[k] = F[k] / m->th;
+  int st = mat_piola_w(D, m, Fe, P);
+  const double sc = pow(m->th, D - 1);
+  for (int k = 0; k < D * D; ++k) P[k] *= sc;
+  return st;
+}
+
+static int mat_piola_jvp(int D, const orc_mat *m, const double *F, const double *dF, double *dP) {
+  if (m->th == 1.0) return mat_piola_jvp_w(D, m, F, dF, dP);
+  double Fe[9], dFe[9];
+  for (int k = 0; k < D * D; ++k) {
+    Fe[k] = F[k] / m->th;
+    dFe[k] = dF[k] / m->th;
+  }
+  int st = mat_piola_jvp_w(D, m, Fe, dFe, dP);
+  const double sc = pow(m->th, D - 1);
+  for (int k = 0; k < D * D; ++k) dP[k] *= sc;
+  return st;
+}
+
 /* advance a node's history with the deformation F the step used:
  * (Qh, S0h) <- (Q(F), S_0(F)) */
 static void visco_commit(int D, const orc_mat *m, const double *F, double *Qh, double *S0h) {
@@ -292,13 +327,13 @@ static void visco_commit(int D, const orc_mat *m, const double *F, double *Qh, d
 /* exported forms of the Maxwell-branch maps (pins) */
 int orc_visco_piola(int D, double mu, double lam, double beta, double xi, const double *Qh, const double *S0h,
                     const double *F, double *P) {
-  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, beta, xi, Qh, S0h};
+  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, beta, xi, Qh, S0h, 1.0};
   return mat_piola(D, &m, F, P);
 }
 
 int orc_visco_piola_jvp(int D, double mu, double lam, double beta, double xi, const double *Qh, const double *S0h,
                         const double *F, const double *dF, double *dP) {
-  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, beta, xi, Qh, S0h};
+  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, beta, xi, Qh, S0h, 1.0};
   return mat_piola_jvp(D, &m, F, dF, dP);
 }
 
@@ -312,7 +347,7 @@ int orc_visco_path(int D, double mu, double lam, double beta, double tau, double
   if (!(tau >= 0.0) || !(dt > 0.0)) return ORC_ERR_ARG;
   const double xi = exp(-dt / (2.0 * tau));
   visco_S0(D, mu, F, S0h, NULL);
-  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, beta, xi, Qh, S0h};
+  orc_mat m = {mu, lam, 0.0, {0.0, 0.0, 0.0}, beta, xi, Qh, S0h, 1.0};
   for (int64_t k = 0; k <= n; ++k) {
     const double *Fk = F + (size_t)k * D * D;
     int st = mat_piola(D, &m, Fk, P + (size_t)k * D * D);
@@ -322,15 +357,30 @@ int orc_visco_path(int D, double mu, double lam, double beta, double tau, double
   return ORC_OK;
 }
 
+/* exported forms of the law with a thermal stretch (pins) */
+int orc_thermal_piola(int D, double mu, double lam, double k1, const double *a0, double th, const double *F,
+                      double *P) {
+  if (!(th > 0.0)) return ORC_ERR_ARG;
+  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}, 0.0, 0.0, NULL, NULL, th};
+  return mat_piola(D, &m, F, P);
+}
+
+int orc_thermal_piola_jvp(int D, double mu, double lam, double k1, const double *a0, double th, const double *F,
+                          const double *dF, double *dP) {
+  if (!(th > 0.0)) return ORC_ERR_ARG;
+  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}, 0.0, 0.0, NULL, NULL, th};
+  return mat_piola_jvp(D, &m, F, dF, dP);
+}
+
 /* exported forms of the material maps (law with fibres) */
 int orc_piola_law(int D, double mu, double lam, double k1, const double *a0, const double *F, double *P) {
-  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}, 0.0, 0.0, NULL, NULL};
+  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}, 0.0, 0.0, NULL, NULL, 1.0};
   return mat_piola(D, &m, F, P);
 }
 
 int orc_piola_law_jvp(int D, double mu, double lam, double k1, const double *a0, const double *F,
                       const double *dF, double *dP) {
-  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}, 0.0, 0.0, NULL, NULL};
+  orc_mat m = {mu, lam, k1, {a0[0], a0[1], D == 3 ? a0[2] : 0.0}, 0.0, 0.0, NULL, NULL, 1.0};
   return mat_piola_jvp(D, &m, F, dF, dP);
 }
 
@@ -657,6 +707,8 @@ struct orc_sim {
   /* Maxwell branch (orc_set_viscous): history [N][D*D] of every node, or NULL */
   double vbeta, vtau, vxi;
   double *Qh, *S0h;
+  /* thermal stretch of every node (orc_set_thermal) [N], or NULL */
+  double *th;
 };
 
 static void coords(const orc_sim *s, int64_t i, int *c) {
@@ -766,6 +818,7 @@ void orc_destroy(orc_sim *s) {
   free(s->u0);
   free(s->dU0);
   free(s->bf);
+  free(s->th);
   free(s->Qh);
   free(s->S0h);
   free(s->act);
@@ -942,7 +995,7 @@ int orc_set_fibres(orc_sim *s, double k1, const double *a0) {
 }
 
 int orc_set_viscous(orc_sim *s, double beta, double tau) {
-  if (!(beta >= 0.0) || !(tau >= 0.0)) return ORC_ERR_ARG;
+  if (!(beta >= 0.0) || !(tau >= 0.0) || s->th) return ORC_ERR_ARG;
   if (!s->Qh) {
     s->Qh = (double *)calloc((size_t)s->N * s->D * s->D, sizeof(double));
     s->S0h = (double *)calloc((size_t)s->N * s->D * s->D, sizeof(double));
@@ -963,6 +1016,21 @@ int orc_get_viscous(orc_sim *s, double *Qh, double *S0h) {
       if (Qh) Qh[(size_t)k * s->N + i] = s->act[i] ? s->Qh[(size_t)i * DD + k] : 0.0;
       if (S0h) S0h[(size_t)k * s->N + i] = s->act[i] ? s->S0h[(size_t)i * DD + k] : 0.0;
     }
+  return ORC_OK;
+}
+
+int orc_set_thermal(orc_sim *s, const double *th) {
+  if (!th) {
+    free(s->th);
+    s->th = NULL;
+    return ORC_OK;
+  }
+  if (s->Qh) return ORC_ERR_ARG;
+  for (int64_t i = 0; i < s->N; ++i)
+    if (!(th[i] > 0.0) || !isfinite(th[i])) return ORC_ERR_ARG;
+  if (!s->th) s->th = (double *)malloc(sizeof(double) * (size_t)s->N);
+  if (!s->th) return ORC_ERR_MEM;
+  memcpy(s->th, th, sizeof(double) * (size_t)s->N);
   return ORC_OK;
 }
 
@@ -1104,7 +1172,8 @@ int orc_bc_data(orc_sim *s, int bid, const double *X, const double *Nb, double t
 /* material of node m of the simulation with the given (mu, lambda); with a
  * Maxwell branch it carries the node's history (m < 0: none) */
 static orc_mat sim_mat(const orc_sim *s, double mu, double lam, int64_t m) {
-  orc_mat mat = {mu, lam, s->k1, {s->a0[0], s->a0[1], s->a0[2]}, 0.0, 0.0, NULL, NULL};
+  orc_mat mat = {mu, lam, s->k1, {s->a0[0], s->a0[1], s->a0[2]}, 0.0, 0.0, NULL, NULL, 1.0};
+  if (s->th && m >= 0) mat.th = s->th[m];
   if (s->Qh && m >= 0) {
     size_t o = (size_t)m * s->D * s->D;
     mat.beta = s->vbeta;
@@ -2196,7 +2265,7 @@ int orc_adjoint(orc_sim *s, int64_t nsteps, const double *dLdU, const double *dL
   int64_t N = s->N;
   if (!s->have_state || s->init_step != s->step || !s->U0) return ORC_ERR_ORDER;
   if (s->status) return s->status;
-  if (nsteps < 0 || s->Qh) return ORC_ERR_ARG; /* no reverse mode through a Maxwell branch */
+  if (nsteps < 0 || s->Qh || s->th) return ORC_ERR_ARG; /* no reverse mode through a branch or a stretch */
   int has_neu = 0, has_dir = 0;
   for (int64_t l = 0; l < s->nl; ++l) {
     int t = s->bc[s->links[l].bid].type;

@@ -97,6 +97,18 @@ int  orc_set_fibres(orc_sim *s, double k1, const double *a0);
  * (call before it).  beta >= 0; tau >= 0 (0: no overstress, INFINITY: the
  * glassy limit).  No reverse mode with a branch (ORC_ERR_ARG). */
 int  orc_set_viscous(orc_sim *s, double beta, double tau);
+/* thermal stretch th [N] (copied; every value > 0; NULL removes it): the
+ * law at node i becomes P(F) = th_i^(D-1) P_W(F / th_i), the thermal
+ * distortion F = F_e (th I) of thermoelasticity (Sec. 6), the temperature
+ * field advanced by the caller.  Takes effect at the next step, and in the
+ * initialisation when set before orc_set_state (whose second-order terms
+ * take th as locally uniform).  Not with a Maxwell branch and no reverse
+ * mode (ORC_ERR_ARG). */
+int  orc_set_thermal(orc_sim *s, const double *th);
+int  orc_thermal_piola(int D, double mu, double lam, double k1, const double *a0, double th,
+                       const double *F, double *P);
+int  orc_thermal_piola_jvp(int D, double mu, double lam, double k1, const double *a0, double th,
+                           const double *F, const double *dF, double *dP);
 /* the branch's history (Q^n, S_0^n) of every node, planar [D*D][N] each */
 int  orc_get_viscous(orc_sim *s, double *Qh, double *S0h);
 /* point maps of the branch with a given history, and a material point driven

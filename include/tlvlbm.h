@@ -213,6 +213,23 @@ tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *ctx, uint8_t bid, const tlvlbm_bc 
  * cannot join a batch and have no reverse mode (TLVLBM_ERR_INVALID_ARG). */
 tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *ctx, const double *g, int32_t ramp, double T_r);
 
+/* Thermal stretch th(X) per node, the thermal distortion through which the
+ * outlook introduces thermoelasticity (Sec. 6): the temperature field,
+ * advanced by the caller, enters as the isotropic stretch of the split
+ * F = F_e (th I) with the energy th^D W(F_e) per reference volume, so the
+ * law (neo-Hookean, or with fibres) at node X becomes
+ *   P(F) = th^(D-1) P_W(F / th)
+ * in the bulk update, the traction closure's Newton solve, the
+ * initialisation and the stress output.
+ *   th  [N] FP64, host or device (copied; every value > 0 and finite, else
+ *       TLVLBM_ERR_INVALID_ARG); NULL removes the field
+ * A new field takes effect at the next step (a caller that advances the
+ * temperature sets it between steps); set before tlvlbm_set_state it enters
+ * the initialisation, whose second-order terms take th as locally uniform.
+ * Not with a Maxwell branch (law 2), and such contexts cannot join a batch
+ * and have no reverse mode (TLVLBM_ERR_INVALID_ARG). */
+tlvlbm_status tlvlbm_set_thermal_stretch(tlvlbm_ctx *ctx, const double *th);
+
 /* Replace the material (e.g. for finite-difference sweeps).  The stored
  * populations are kept.  When the old or the new material has a Maxwell
  * branch (law 2), the branch's history starts anew: tlvlbm_step returns

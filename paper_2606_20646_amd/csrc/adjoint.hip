@@ -1622,6 +1622,10 @@ tlvlbm_status record_call(tlvlbm_ctx *c, int64_t n, const double *U0, const doub
     c->err = "adjoint: no reverse mode through a Maxwell branch";
     return TLVLBM_ERR_INVALID_ARG;
   }
+  if (c->par.thf) {
+    c->err = "adjoint: no reverse mode with a thermal stretch";
+    return TLVLBM_ERR_INVALID_ARG;
+  }
   std::string err;
   tlvlbm_status s;
   try {

@@ -100,6 +100,7 @@ static void set_material_par(tlvlbm_ctx *c, const tlvlbm_material *m) {
   c->vbeta = c->visco ? m->beta : 0.0;
   c->vtau = c->visco ? m->tau : 0.0;
   p.hist = nullptr;  // attached by set_state
+  p.thf = c->thf;    // the thermal stretch stays with the context
 }
 
 // branch constants beta xi and xi^2, xi = exp(-dt / (2 tau)) (tau = 0: 0,
@@ -133,7 +134,9 @@ void dfree(tlvlbm_ctx *c, void *p) {
   (void)hipFree(p);
 }
 
-// stress of the material on the host (the reference state's equilibrium)
+// stress of the material on the host (the reference state's equilibrium: a
+// constant of the stored representation, so the thermal stretch, which may
+// change between steps, stays out of it)
 static double mat_piola_host(int D, const double *F, const Par &p, double *P) {
   return D == 2 ? mat_piola<2>(F, p, P) : mat_piola<3>(F, p, P);
 }
@@ -295,7 +298,7 @@ tlvlbm_status tlvlbm_destroy(tlvlbm_ctx *c) {
                   c->L.mminus, c->L.q, c->L.bid, c->L.npts, c->L.basis, c->L.eta, c->L.Nb, c->L.Xb, c->L.tang,
                   c->L.sidx, c->L.sw, c->cg.x, c->cg.r, c->cg.p0, c->cg.p1, c->cg.Ap, c->cg.b, c->cg.V, c->cg.Fm,
                   c->cg.Fr, c->cg.anc_n, c->cg.anc_i, c->cg.anc_s, c->cg.partial, c->cg.scal, c->cg.z, c->cg.tiles,
-                  c->cg.jt, c->cg.nbm, c->bf, c->chunks, c->cpos, c->d_bcs, c->hist};
+                  c->cg.jt, c->cg.nbm, c->bf, c->chunks, c->cpos, c->d_bcs, c->hist, c->thf};
   for (void *p : ptrs)
     if (p) dfree(c, p);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
@@ -425,8 +428,38 @@ tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *c, const double *g, int32_t ramp
   }
 }
 
+tlvlbm_status tlvlbm_set_thermal_stretch(tlvlbm_ctx *c, const double *th) {
+  if (!c) return TLVLBM_ERR_INVALID_ARG;
+  rec_invalidate(c);
+  try {
+    if (!th) {
+      dfree(c, c->thf);
+      c->thf = nullptr;
+      c->par.thf = nullptr;
+      return TLVLBM_OK;
+    }
+    if (c->visco) return fail(c, TLVLBM_ERR_INVALID_ARG, "a thermal stretch does not combine with a Maxwell branch");
+    const int64_t N = c->geo.N;
+    std::vector<double> h((size_t)N);
+    CHK(hipMemcpyAsync(h.data(), th, (size_t)N * sizeof(double), hipMemcpyDefault, c->st), "thermal stretch read");
+    CHK(hipStreamSynchronize(c->st), "synchronize");
+    for (int64_t i = 0; i < N; ++i)
+      if (!(h[i] > 0.0) || !std::isfinite(h[i]))
+        return fail(c, TLVLBM_ERR_INVALID_ARG, "the thermal stretch must be positive and finite at every node");
+    if (!c->thf) CHK(dmalloc(c, &c->thf, (size_t)c->geo.S * sizeof(double)), "thermal stretch alloc");
+    CHK(hipMemcpyAsync(c->thf, h.data(), (size_t)N * sizeof(double), hipMemcpyHostToDevice, c->st),
+        "thermal stretch upload");
+    CHK(hipStreamSynchronize(c->st), "synchronize");
+    c->par.thf = c->thf;
+    return TLVLBM_OK;
+  } catch (...) {
+    return fail(c, TLVLBM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
 tlvlbm_status tlvlbm_set_material(tlvlbm_ctx *c, const tlvlbm_material *m) {
   if (!c || !material_ok(m)) return TLVLBM_ERR_INVALID_ARG;
+  if (m->law == 2 && c->thf) return fail(c, TLVLBM_ERR_INVALID_ARG, "a Maxwell branch does not combine with a thermal stretch");
   rec_invalidate(c);
   // a Maxwell branch (before or after) starts its history at set_state
   if (c->visco || m->law == 2) {

@@ -401,7 +401,8 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       tlvlbm_ctx *c = ctxs[k];
       if (!c || c->D != b->D || c->prec != b->prec || c->st != b->st || c->proj_every != b->proj_every ||
           c->proj_sweeps != b->sweeps || c->proj_weight != b->jw || c->step != b->step || !c->have_state ||
-          !c->has_ls || !c->track_u || c->status || c->bf || c->par.k1 != 0.0 || c->visco) {
+          !c->has_ls || !c->track_u || c->status || c->bf || c->par.k1 != 0.0 || c->visco ||
+          c->par.thf) {
         delete b;
         return TLVLBM_ERR_INVALID_ARG;
       }

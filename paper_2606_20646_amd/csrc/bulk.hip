@@ -554,7 +554,7 @@ __global__ __launch_bounds__(256) void k_stress(const T *__restrict__ fin, Geo g
       F[k] = p.Fref[k] + double(s);
     }
     double Hn[sym_n<D>()];
-    const double J = law_piola<D>(F, p, law_load<D>(p, node, g.S, Hn) ? Hn : nullptr, P);
+    const double J = law_piola<D>(F, p, law_load<D>(p, node, g.S, Hn) ? Hn : nullptr, P, law_theta<D>(p, node));
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -625,7 +625,10 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
     }
     hn = Hn;
   }
-  law_piola<D>(F, p, hn, P);
+  // the node's thermal stretch, taken as locally uniform in the
+  // second-order terms (its gradient does not enter them)
+  const double th = law_theta<D>(p, node);
+  law_piola<D>(F, p, hn, P, th);
   // d_t U0 = B0 - Phi'_A(U0) d_A U0, B0 = (b0 - gamma v0, 0)
 #pragma unroll
   for (int r = 0; r < M; ++r)
@@ -633,7 +636,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
 #pragma unroll
   for (int A = 0; A < D; ++A) {
     double dP[D * D];
-    law_tangent<D>(F, dA[A] + D, p, hn, dP);
+    law_tangent<D>(F, dA[A] + D, p, hn, dP, th);
 #pragma unroll
     for (int i = 0; i < D; ++i) Ut[i] += dP[i * D + A] * p.inv_rho0;  // -(-dP)
 #pragma unroll
@@ -647,7 +650,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ fout, Geo g, Par p
     double Z[M], dP[D * D];
 #pragma unroll
     for (int r = 0; r < M; ++r) Z[r] = Ut[r] + c * sg * dA[A][r];
-    law_tangent<D>(F, Z + D, p, hn, dP);
+    law_tangent<D>(F, Z + D, p, hn, dP, th);
     int xs = x, ys = y, zs = z;  // X - e_q
     if (A == 0) xs = (x - (int)sg + g.nx) % g.nx;
     if (A == 1) ys = (y - (int)sg + g.ny) % g.ny;
@@ -843,6 +846,7 @@ template <int D, typename T> static void bulk_t(tlvlbm_ctx *c, bool repair, void
     return;
   }
   if (c->par.hist) bulk_plain_t<D, T, Viscoelastic<D>>(c, repair);
+  else if (c->par.thf) bulk_plain_t<D, T, Thermal<D>>(c, repair);
   else if (ext) bulk_plain_t<D, T, Reinforced<D>>(c, repair);
   else bulk_plain_t<D, T, NeoHookean<D>>(c, repair);
 }

@@ -520,7 +520,8 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
   // collision)
   double Hn[sym_n<D>()];
   const double *hn = law_load<D>(p, m, g.S, Hn) ? Hn : nullptr;
-  const bool conv = newton_h<D>(N, Gt, Tb, p, 1e-12, h, hn);
+  const double ths = law_theta<D>(p, m);  // the node's thermal stretch
+  const bool conv = newton_h<D>(N, Gt, Tb, p, 1e-12, h, hn, ths);
   if (!conv) atomicAdd(nfail, 1ull);
   double Fb[D * D], Pb[D * D];
   for (int i = 0; i < D; ++i)
@@ -529,7 +530,7 @@ __device__ __forceinline__ void cut_neumann_link(T *__restrict__ f, const Links 
     atomicOr(flag, FLAG_NEWTON);
     for (int k = 0; k < D * D; ++k) Fb[k] = (k % (D + 1) == 0) ? 1.0 : 0.0;
   }
-  law_piola<D>(Fb, p, hn, Pb);
+  law_piola<D>(Fb, p, hn, Pb, ths);
   const T ie = T(1.0 / (2.0 * eta));
   const T e2 = T(2.0 * eta);
   T fo[M], fx[M];

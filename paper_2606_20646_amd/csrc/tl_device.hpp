@@ -183,15 +183,16 @@ __device__ __forceinline__ void mat_tangent(const double *F, const double *dF, c
 }
 
 // R(h) = P(h (x) N + Gt) N - T (Eqs. 54, 56) with the law of the link's
-// node (Hn: its internal variables, or null); false if det F_b <= 0
+// node (Hn: its internal variables, or null; th: its thermal stretch);
+// false if det F_b <= 0
 template <int D>
 __device__ inline bool nm_residual(const double *h, const double *N, const double *Gt, const double *Tb, const Par &p,
-                            double *R, const double *Hn = nullptr) {
+                            double *R, const double *Hn = nullptr, double th = 1.0) {
   double F[D * D], P[D * D];
   for (int i = 0; i < D; ++i)
     for (int a = 0; a < D; ++a) F[i * D + a] = h[i] * N[a] + Gt[i * D + a];
   if (!(det<D>(F) > 0.0)) return false;
-  law_piola<D>(F, p, Hn, P);
+  law_piola<D>(F, p, Hn, P, th);
   for (int i = 0; i < D; ++i) {
     double s = 0.0;
     for (int a = 0; a < D; ++a) s += P[i * D + a] * N[a];
@@ -206,9 +207,9 @@ __device__ inline bool nm_residual(const double *h, const double *N, const doubl
 // accepts only det F_b > 0 with a decreasing residual (<= 10 halvings).
 template <int D>
 __device__ inline bool newton_h(const double *N, const double *Gt, const double *Tb, const Par &p, double tol,
-                         double *h, const double *Hn = nullptr) {
+                         double *h, const double *Hn = nullptr, double th = 1.0) {
   double R[D], Rt[D], ht[D];
-  if (!nm_residual<D>(h, N, Gt, Tb, p, R, Hn)) return false;
+  if (!nm_residual<D>(h, N, Gt, Tb, p, R, Hn, th)) return false;
   const double thr = tol * (p.mu > 1.0 ? p.mu : 1.0);
   for (int it = 0; it <= 30; ++it) {
     double rinf = 0.0, r2 = 0.0;
@@ -225,7 +226,7 @@ __device__ inline bool newton_h(const double *N, const double *Gt, const double 
       double dF[D * D], dP[D * D];
       for (int i = 0; i < D; ++i)
         for (int a = 0; a < D; ++a) dF[i * D + a] = (i == k) ? N[a] : 0.0;
-      law_tangent<D>(F, dF, p, Hn, dP);
+      law_tangent<D>(F, dF, p, Hn, dP, th);
       for (int i = 0; i < D; ++i) {
         double s = 0.0;
         for (int a = 0; a < D; ++a) s += dP[i * D + a] * N[a];
@@ -238,7 +239,7 @@ __device__ inline bool newton_h(const double *N, const double *Gt, const double 
     bool acc = false;
     for (int ls = 0; ls <= 10; ++ls) {
       for (int i = 0; i < D; ++i) ht[i] = h[i] + step * dh[i];
-      if (nm_residual<D>(ht, N, Gt, Tb, p, Rt, Hn)) {
+      if (nm_residual<D>(ht, N, Gt, Tb, p, Rt, Hn, th)) {
         double rt2 = 0.0, rtinf = 0.0;
         for (int i = 0; i < D; ++i) {
           rt2 += Rt[i] * Rt[i];

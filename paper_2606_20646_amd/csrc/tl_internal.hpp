@@ -57,6 +57,8 @@ struct Par {
   // branch
   double vbx, vxi2;
   double *hist;
+  // thermal stretch of every node (one FP64 plane of stride S), or null
+  const double *thf;
 };
 
 // stored-population shift feq_q^r(0, Fref) of direction q, row r:
@@ -373,6 +375,7 @@ struct tlvlbm_ctx {
   double vbeta = 0.0, vtau = 0.0;
   double *hist = nullptr;
   bool hist_set = false;  // the planes hold the branch's history (set_state or put_history)
+  double *thf = nullptr;  // thermal stretch plane [S] (par.thf while set)
   // displacement history u* and u (Eq. 34): D FP64 planes each in both
   // builds (a quadrature over thousands of steps; FP32 sums lose ~1e-5)
   void *ustar = nullptr, *ubuf = nullptr;

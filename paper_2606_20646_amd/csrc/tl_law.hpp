@@ -16,7 +16,8 @@
 //                        the collision used)
 // NeoHookean is the paper's law (Eq. 62); Reinforced adds one fibre family
 // (k1 > 0) and takes a body acceleration; Viscoelastic adds one Maxwell
-// branch with per-node history to Reinforced.
+// branch with per-node history to Reinforced; Thermal gives Reinforced a
+// per-node thermal stretch.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -178,11 +179,54 @@ template <int D> struct Viscoelastic {
   }
 };
 
+// Thermal distortion (Sec. 6 names it for thermoelasticity): the temperature
+// field, advanced by the caller, enters as the isotropic stretch th of the
+// split F = F_e (th I) with the energy th^D W(F_e) per reference volume, so
+// P(F) = th^(D-1) P_W(F / th) and dP = th^(D-1) dP_W(F / th; dF / th).  The
+// node's th is one FP64 plane of stride S (p.thf).
+template <int D> struct Thermal {
+  static constexpr bool body = true;
+  struct Node {
+    double th;
+  };
+  __device__ static void load(const Par &p, int64_t node, int64_t, Node &n) { n.th = p.thf[node]; }
+  __host__ __device__ static double stress(const Par &p, const double *F, Node &n, double *P) {
+    double Fe[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Fe[k] = F[k] / n.th;
+    typename Reinforced<D>::Node e;
+    const double Je = Reinforced<D>::stress(p, Fe, e, P);
+    const double sc = D == 3 ? n.th * n.th : n.th;
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) P[k] *= sc;
+    return Je * sc * n.th;  // J = det F = th^D det F_e
+  }
+  __device__ static void tangent(const Par &p, const double *F, const Node &n, const double *dF, double *dP) {
+    double Fe[D * D], dFe[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+      Fe[k] = F[k] / n.th;
+      dFe[k] = dF[k] / n.th;
+    }
+    typename Reinforced<D>::Node e;
+    Reinforced<D>::tangent(p, Fe, e, dFe, dP);
+    const double sc = D == 3 ? n.th * n.th : n.th;
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) dP[k] *= sc;
+  }
+  __device__ static void commit(const Par &, const Node &, int64_t, int64_t) {}
+};
+
 // The context's law at one node for the paths that are not specialised
 // (initialisation, traction closure, stress output): the elastic part, plus
-// the Maxwell branch when R (the node's packed internal variables) is given.
+// the Maxwell branch when R (the node's packed internal variables) is given,
+// at the node's thermal stretch th (1: none).
 template <int D> __host__ __device__ __forceinline__ double law_piola(const double *F, const Par &p, const double *R,
-                                                                      double *P) {
+                                                                      double *P, double th = 1.0) {
+  if (th != 1.0) {
+    typename Thermal<D>::Node n{th};
+    return Thermal<D>::stress(p, F, n, P);
+  }
   typename Reinforced<D>::Node e;
   const double J = Reinforced<D>::stress(p, F, e, P);
   if (R) {
@@ -194,10 +238,20 @@ template <int D> __host__ __device__ __forceinline__ double law_piola(const doub
 
 template <int D>
 __device__ __forceinline__ void law_tangent(const double *F, const double *dF, const Par &p, const double *R,
-                                            double *dP) {
+                                            double *dP, double th = 1.0) {
+  if (th != 1.0) {
+    const typename Thermal<D>::Node n{th};
+    Thermal<D>::tangent(p, F, n, dF, dP);
+    return;
+  }
   typename Reinforced<D>::Node e;
   Reinforced<D>::tangent(p, F, e, dF, dP);
   if (R) maxwell_tangent_add<D>(F, dF, p, R, dP);
+}
+
+// the node's thermal stretch (1 without a field)
+template <int D> __device__ __forceinline__ double law_theta(const Par &p, int64_t node) {
+  return p.thf ? p.thf[node] : 1.0;
 }
 
 // the node's internal variables (false: the law has none)

@@ -120,6 +120,7 @@ def _load():
     L.tlvlbm_set_boundary.argtypes = [vp, C.c_uint8, C.POINTER(BC)]
     L.tlvlbm_set_material.argtypes = [vp, C.POINTER(Material)]
     L.tlvlbm_set_body_force.argtypes = [vp, C.c_void_p, C.c_int32, C.c_double]
+    L.tlvlbm_set_thermal_stretch.argtypes = [vp, C.c_void_p]
     L.tlvlbm_set_state.argtypes = [vp, dp, dp, dp]
     L.tlvlbm_step.argtypes = [vp, C.c_int64]
     L.tlvlbm_moments.argtypes = [vp, dp, dp, dp]
@@ -265,6 +266,13 @@ class Solver:
             b.X0[k] = v
         b.twist = float(twist)
         self._chk(lib.tlvlbm_set_boundary(self.h, int(bid), C.byref(b)), "set_boundary")
+
+    def set_thermal_stretch(self, th):
+        """Thermal stretch th [N] per node (> 0; numpy or device tensor; None
+        removes it): P(F) = th^(D-1) P_W(F / th)."""
+        arr = th if (th is None or not isinstance(th, np.ndarray)) else np.ascontiguousarray(th, np.float64)
+        p, keep = _ptr(arr)
+        self._chk(lib.tlvlbm_set_thermal_stretch(self.h, p), "set_thermal_stretch")
 
     def set_body_force(self, g, ramp="const", T_r=1.0):
         """Body acceleration b(X, t) = s(t) g(X); g [D][N] numpy or device

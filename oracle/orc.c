@@ -291,7 +291,7 @@ static int mat_piola_jvp_w(int D, const orc_mat *m, const double *F, const doubl
 /* the law at a node with its thermal stretch (see orc_mat) */
 static int mat_piola(int D, const orc_mat *m, const double *F, double *P) {
   if (m->th == 1.0) return mat_piola_w(D, m, F, P);
-  double Fe[9];
+  double Fe[9] = {0.0};
   for (int k = 0; k < D * D; ++k) Fe[k] = F[k] / m->th;
   int st = mat_piola_w(D, m, Fe, P);
   const double sc = pow(m->th, D - 1);
@@ -301,7 +301,7 @@ static int mat_piola(int D, const orc_mat *m, const double *F, double *P) {
 
 static int mat_piola_jvp(int D, const orc_mat *m, const double *F, const double *dF, double *dP) {
   if (m->th == 1.0) return mat_piola_jvp_w(D, m, F, dF, dP);
-  double Fe[9], dFe[9];
+  double Fe[9] = {0.0}, dFe[9] = {0.0};
   for (int k = 0; k < D * D; ++k) {
     Fe[k] = F[k] / m->th;
     dFe[k] = dF[k] / m->th;

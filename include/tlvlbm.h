@@ -269,7 +269,8 @@ tlvlbm_status tlvlbm_moments_native(tlvlbm_ctx *ctx, void *U_out, double *u_out,
 
 /* Stress of the current time level (the final diagnostics of Algorithm 1):
  * first Piola P_out[D*D][N] of the recovered F with the material law (with
- * a Maxwell branch: its history as the next collision uses it) and Cauchy
+ * a Maxwell branch: its history as the next collision uses it; with a
+ * thermal stretch: the node's stretch) and Cauchy
  * stress sigma_out[D*D][N] = J^{-1} P F^T (Sec. 2.4, Eq. 35), row-major
  * components, FP64, host or device; zero at inactive nodes.  Either may be
  * NULL. */

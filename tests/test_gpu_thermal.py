@@ -14,6 +14,8 @@ the FP64 oracle.
 - a traction-free disk under a uniform stretch relaxes to the exact
   stress-free expansion F = th I, u = (th - 1)(X - mean X) on the GPU as in
   the oracle;
+- a field handed over from a device tensor every 40 steps, as a temperature
+  solver would, against the oracle given the same fields;
 - th = 1 everywhere is no stretch (to rounding: the stretched law is its own
   kernel instantiation); the calls that refuse a
   stretch (Maxwell branch, batch, reverse mode) and non-positive values.
@@ -185,3 +187,35 @@ def test_thermal_unit_stretch_and_refusals(T):
     v = T.Solver(2, (8, 8), 1 / 8, 1 / 80, 1.0, 2.0, precision="fp64", viscous=(0.5, 1.0))
     with pytest.raises(T.TlvlbmError):
         v.set_thermal_stretch(np.ones(64))
+
+
+def test_thermal_field_updated_between_steps_from_device(T, orc):
+    """the use the call is made for: a temperature solver advances the field
+    and hands it over between steps, here as a device tensor every 40 steps
+    (a heating front crossing a periodic 2D body), against the oracle given
+    the same fields"""
+    import torch
+    c = W.config_c1()
+    X = W.node_coords(c["n"], c["dx"], c["origin"])
+    _say("thermal stretch updated every 40 steps from a device tensor, c1 2D fp64")
+    g = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], precision="fp64")
+    o = orc.Sim(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"])
+    for s in (g, o):
+        s.set_state(c["U0"], dU0=c["dU0"])
+    for k in range(6):
+        front = 0.15 * (k + 1)
+        th = 1.0 + 0.03 / (1.0 + np.exp(-(front - X[0]) / 0.05))
+        g.set_thermal_stretch(torch.tensor(th, dtype=torch.float64, device="cuda"))
+        o.set_thermal(th)
+        g.step(40)
+        o.step(40)
+    Ug, _, _ = g.moments()
+    Uo, _, _ = o.moments()
+    check(Ug, Uo, 2, 1e-12, label="thermal field updates fp64", pops=o.get_f(), steps=240,
+          stress=(c["mu"], c["lam"], 1.0, 10.0, c["omega"]))
+    # the heated part has moved: the field did act
+    g0 = T.Solver(2, c["n"], c["dx"], c["dt"], c["mu"], c["lam"], omega=c["omega"], precision="fp64")
+    g0.set_state(c["U0"], dU0=c["dU0"])
+    g0.step(240)
+    U0, _, _ = g0.moments()
+    assert np.abs(U0[:2] - Ug[:2]).max() > 1e-4

@@ -407,9 +407,11 @@ tlvlbm_status tlvlbm_adjoint_backward(tlvlbm_ctx *ctx, const double *dLdU, const
  * that context).  The projection phases run over every instance, so either
  * all instances have Neumann links or none has (TLVLBM_ERR_INVALID_ARG for a
  * mixed set: the projection belongs to lattices with Neumann links only).
- * The batched bulk update is that of law 0: instances with fibres, a
- * Maxwell branch or a body acceleration are refused (TLVLBM_ERR_INVALID_ARG;
- * tlvlbm_step_each takes them). */
+ * The batched bulk update runs laws 0 and 1 (each instance with its own
+ * material; when one has fibres the whole batch takes the reinforced
+ * update, whose fibre term vanishes where k1 = 0): instances with a Maxwell
+ * branch, a thermal stretch or a body acceleration are refused
+ * (TLVLBM_ERR_INVALID_ARG; tlvlbm_step_each takes them). */
 typedef struct tlvlbm_batch tlvlbm_batch;
 tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t n, int64_t steps);
 tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_batch **out);

@@ -39,6 +39,7 @@ struct tlvlbm_batch {
   int *d_pending = nullptr, *h_pending = nullptr;
   int *h_flags = nullptr;
   bool any_neu = false, any_dir = false;
+  bool fibres = false;  // an instance has the fibre law: the reinforced bulk update
   int64_t step = 0, maxit = 0;
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
@@ -170,7 +171,7 @@ tlvlbm_status pcg_batch(tlvlbm_batch *b, int anch) {
 }
 
 void plain_step(tlvlbm_batch *b) {
-  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, false, b->tw, b->st);
+  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, false, b->tw, b->st, b->fibres);
   if (b->nlt) run(b, BatchOp::Cut);
   run(b, BatchOp::StepEnd);
 }
@@ -182,7 +183,7 @@ tlvlbm_status projection_step(tlvlbm_batch *b) {
   if (s) return s;
   run(b, BatchOp::UfromX);
   run(b, BatchOp::GradF);
-  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, true, b->tw, b->st);
+  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, true, b->tw, b->st, b->fibres);
   run(b, BatchOp::XfromU);
   s = cg_batch(b, 1);
   if (s) return s;
@@ -300,7 +301,7 @@ tlvlbm_status batch_autotune(tlvlbm_batch *b, int reps) {
         for (int r = 0; r <= reps; ++r) {
           float ms = 0.0f;
           if (hipEventRecord(e0, b->st) != hipSuccess) res = TLVLBM_ERR_DEVICE;
-          launch_bulk_batch(b->D, b->prec, b->d_inst, dt, (int)t.size(), false, widths[wi], b->st);
+          launch_bulk_batch(b->D, b->prec, b->d_inst, dt, (int)t.size(), false, widths[wi], b->st, b->fibres);
           if (hipEventRecord(e1, b->st) != hipSuccess || !restore() || hipEventSynchronize(e1) != hipSuccess ||
               hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
             res = TLVLBM_ERR_DEVICE;
@@ -401,8 +402,7 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       tlvlbm_ctx *c = ctxs[k];
       if (!c || c->D != b->D || c->prec != b->prec || c->st != b->st || c->proj_every != b->proj_every ||
           c->proj_sweeps != b->sweeps || c->proj_weight != b->jw || c->step != b->step || !c->have_state ||
-          !c->has_ls || !c->track_u || c->status || c->bf || c->par.k1 != 0.0 || c->visco ||
-          c->par.thf) {
+          !c->has_ls || !c->track_u || c->status || c->bf || c->visco || c->par.thf) {
         delete b;
         return TLVLBM_ERR_INVALID_ARG;
       }
@@ -442,6 +442,7 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       I.flag = c->d_flag;
       I.nfail = (unsigned long long *)c->d_newton_fail;
       b->h_inst.push_back(I);
+      if (c->par.k1 != 0.0) b->fibres = true;
       {
         // activity mask on the host for the node-tile lists (empty: all active)
         std::vector<uint8_t> a;

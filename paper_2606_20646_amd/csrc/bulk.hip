@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_chunks_tape(
 
 // Batched bulk update: one block per tile (instance, row, first x) of the
 // tile list; every instance keeps its own geometry, material and buffers.
-template <int D, typename T, bool REPAIR>
+template <int D, typename T, bool REPAIR, class L = NeoHookean<D>>
 __global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_batch(const Inst *__restrict__ insts,
                                                                    const int4 *__restrict__ tiles) {
   const int4 t = tiles[blockIdx.x];
@@ -461,8 +461,8 @@ __global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_batch(const Inst *
   const int64_t node = (int64_t)t.y * blockDim.x + threadIdx.x;
   if (node >= I.g.N) return;
   const int row = (int)(node / I.g.nx), x = (int)(node - (int64_t)row * I.g.nx);
-  bulk_node<D, T, true, true, REPAIR>((const T *)I.fin, (T *)I.fout, I.g, I.p, I.act, (double *)I.ustar,
-                                      (double *)I.ubuf, (const T *)I.Fr, I.flag, x, row);
+  bulk_node<D, T, true, true, REPAIR, false, L>((const T *)I.fin, (T *)I.fout, I.g, I.p, I.act,
+                                                (double *)I.ustar, (double *)I.ubuf, (const T *)I.Fr, I.flag, x, row);
 }
 
 // Pull f^n and write moments: v (damping-corrected), F, u = u* + dt/2 v, J.
@@ -1032,7 +1032,17 @@ namespace tl {
 
 // batched launchers: tiles are (instance, k) pairs, nodes k tw .. (k + 1) tw - 1 of the instance
 template <int D, typename T>
-static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw, hipStream_t st) {
+static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw, hipStream_t st,
+                         bool fibres) {
+  // fibres: the reinforced law for the whole batch (its fibre term vanishes
+  // on instances with k1 = 0)
+  if (fibres) {
+    if (repair)
+      hipLaunchKernelGGL((k_bulk_batch<D, T, true, Reinforced<D>>), ntiles, tw, 0, st, insts, tiles);
+    else
+      hipLaunchKernelGGL((k_bulk_batch<D, T, false, Reinforced<D>>), ntiles, tw, 0, st, insts, tiles);
+    return;
+  }
   if (repair)
     hipLaunchKernelGGL((k_bulk_batch<D, T, true>), ntiles, tw, 0, st, insts, tiles);
   else
@@ -1041,13 +1051,13 @@ static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool 
 
 // tw: nodes per tile = threads per workgroup (<= 256)
 void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw,
-                       hipStream_t st) {
+                       hipStream_t st, bool fibres) {
   if (D == 2) {
-    if (prec) bulk_batch_t<2, double>(insts, tiles, ntiles, repair, tw, st);
-    else bulk_batch_t<2, float>(insts, tiles, ntiles, repair, tw, st);
+    if (prec) bulk_batch_t<2, double>(insts, tiles, ntiles, repair, tw, st, fibres);
+    else bulk_batch_t<2, float>(insts, tiles, ntiles, repair, tw, st, fibres);
   } else {
-    if (prec) bulk_batch_t<3, double>(insts, tiles, ntiles, repair, tw, st);
-    else bulk_batch_t<3, float>(insts, tiles, ntiles, repair, tw, st);
+    if (prec) bulk_batch_t<3, double>(insts, tiles, ntiles, repair, tw, st, fibres);
+    else bulk_batch_t<3, float>(insts, tiles, ntiles, repair, tw, st, fibres);
   }
 }
 

@@ -28,13 +28,13 @@ def env():
     return tlvlbm, torch.cuda.Stream()
 
 
-def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20):
+def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre=None):
     # per-instance and batched paths run the same projection solver (Jacobi
     # sweeps; or CG, plain or preconditioned by the multigrid V-cycle,
     # batched level-synchronously)
     s = T.Solver(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
                  origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"], precision=precision,
-                 stream=stream.cuda_stream, cg_multigrid=cg_multigrid, proj_sweeps=proj_sweeps)
+                 stream=stream.cuda_stream, cg_multigrid=cg_multigrid, proj_sweeps=proj_sweeps, fibre=fibre)
     s.set_levelset(cfg["phi"], cfg["bid"])
     for bid, bc in cfg["bcs"].items():
         bc = dict(bc)
@@ -43,9 +43,11 @@ def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20):
     return s
 
 
-def _oracle(orc, cfg):
+def _oracle(orc, cfg, fibre=None, steps=0):
     o = orc.Sim(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
                 origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"])
+    if fibre is not None:
+        o.set_fibres(*fibre)
     o.set_levelset(cfg["phi"], cfg["bid"])
     kinds = {"dirichlet": orc.DIRICHLET, "neumann": orc.NEUMANN}
     ramps = {"const": orc.RAMP_CONST, "sin2": orc.RAMP_SIN2}
@@ -56,6 +58,8 @@ def _oracle(orc, cfg):
             bc["ramp"] = ramps[bc["ramp"]]
         o.set_bc(bid, t, **bc)
     o.set_state(cfg["U0"])
+    if steps:
+        o.step(steps)
     return o
 
 
@@ -123,6 +127,43 @@ def test_batched_instance_matches_oracle(env, orc):
         act = c["phi"] <= 0
         check(Ub, Uo, 2, 1e-12, ub, uo, mask=act, label="batched instance vs oracle fp64", pops=o.get_f(),
               steps=600, stress=(c["mu"], c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
+
+
+FIBRES = [(1.5, (0.6, 0.8)), None, (0.8, (1.0, 0.0)), None]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_with_fibre_instances(env, orc, precision):
+    """instances of law 1 (fibres, each its own k1 and direction) beside
+    instances of law 0 in one batch: the batch runs the reinforced update
+    for all, equal to the per-instance launches; a batched fibre instance
+    equals the oracle in FP64"""
+    T, stream = env
+    tol = _batch_tol(precision, 20)
+    _say(f"batch with fibre instances {precision}")
+    A = [_solver(T, c, precision, stream, fibre=fb) for c, fb in zip(CFGS, FIBRES)]
+    B = [_solver(T, c, precision, stream, fibre=fb) for c, fb in zip(CFGS, FIBRES)]
+    T.step_each(A, 65)
+    bt = T.Batch(B)
+    bt.step(65)
+    bt.close()
+    for k, (a, b, c, fb) in enumerate(zip(A, B, CFGS, FIBRES)):
+        Ua, ua, _ = a.moments()
+        Ub, ub, _ = b.moments()
+        act = c["phi"] <= 0
+        mu_eff = c["mu"] + (2 * fb[0] if fb else 0.0)
+        check(Ub, Ua, 2, tol, mask=act, label=f"fibre batch instance {k} vs per-instance", pops=a.get_state()[0],
+              steps=65, stress=(mu_eff, c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
+        utol = 1e-10 if precision == "fp64" else 1e-6
+        assert np.linalg.norm(ua[:, act] - ub[:, act]) <= utol * np.linalg.norm(ua[:, act])
+    if precision == "fp64":
+        c, fb = CFGS[0], FIBRES[0]
+        o = _oracle(orc, c, fibre=fb, steps=65)
+        Uo, uo, _ = o.moments()
+        Ub, ub, _ = B[0].moments()
+        act = c["phi"] <= 0
+        check(Ub, Uo, 2, 1e-12, ub, uo, mask=act, label="batched fibre instance vs oracle fp64", pops=o.get_f(),
+              steps=65, stress=(c["mu"] + 2 * fb[0], c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
 
 
 def test_tile_configurations_agree(env):

@@ -226,8 +226,8 @@ tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *ctx, const double *g, int32_t ra
  * A new field takes effect at the next step (a caller that advances the
  * temperature sets it between steps); set before tlvlbm_set_state it enters
  * the initialisation, whose second-order terms take th as locally uniform.
- * Not with a Maxwell branch (law 2), and such contexts cannot join a batch
- * and have no reverse mode (TLVLBM_ERR_INVALID_ARG). */
+ * Not with a Maxwell branch (law 2), and no reverse mode
+ * (TLVLBM_ERR_INVALID_ARG). */
 tlvlbm_status tlvlbm_set_thermal_stretch(tlvlbm_ctx *ctx, const double *th);
 
 /* Replace the material (e.g. for finite-difference sweeps).  The stored
@@ -407,11 +407,13 @@ tlvlbm_status tlvlbm_adjoint_backward(tlvlbm_ctx *ctx, const double *dLdU, const
  * that context).  The projection phases run over every instance, so either
  * all instances have Neumann links or none has (TLVLBM_ERR_INVALID_ARG for a
  * mixed set: the projection belongs to lattices with Neumann links only).
- * The batched bulk update runs laws 0 and 1 (each instance with its own
- * material; when one has fibres the whole batch takes the reinforced
- * update, whose fibre term vanishes where k1 = 0): instances with a Maxwell
- * branch, a thermal stretch or a body acceleration are refused
- * (TLVLBM_ERR_INVALID_ARG; tlvlbm_step_each takes them). */
+ * The batched bulk update runs laws 0 and 1 and the thermal stretch, each
+ * instance with its own material and field (when one instance has fibres
+ * the whole batch takes the reinforced update, whose fibre term vanishes
+ * where k1 = 0; when one has a thermal stretch, the stretched update, with
+ * th = 1 where there is no field): instances with a Maxwell branch or a
+ * body acceleration are refused (TLVLBM_ERR_INVALID_ARG; tlvlbm_step_each
+ * takes them). */
 typedef struct tlvlbm_batch tlvlbm_batch;
 tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t n, int64_t steps);
 tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_batch **out);

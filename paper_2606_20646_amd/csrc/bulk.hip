@@ -1033,10 +1033,18 @@ namespace tl {
 // batched launchers: tiles are (instance, k) pairs, nodes k tw .. (k + 1) tw - 1 of the instance
 template <int D, typename T>
 static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw, hipStream_t st,
-                         bool fibres) {
-  // fibres: the reinforced law for the whole batch (its fibre term vanishes
-  // on instances with k1 = 0)
-  if (fibres) {
+                         int law) {
+  // law 2: the thermal stretch for the whole batch (th = 1 on instances
+  // without a field); 1: the reinforced law (its fibre term vanishes on
+  // instances with k1 = 0); 0: the neo-Hookean law
+  if (law == 2) {
+    if (repair)
+      hipLaunchKernelGGL((k_bulk_batch<D, T, true, Thermal<D>>), ntiles, tw, 0, st, insts, tiles);
+    else
+      hipLaunchKernelGGL((k_bulk_batch<D, T, false, Thermal<D>>), ntiles, tw, 0, st, insts, tiles);
+    return;
+  }
+  if (law == 1) {
     if (repair)
       hipLaunchKernelGGL((k_bulk_batch<D, T, true, Reinforced<D>>), ntiles, tw, 0, st, insts, tiles);
     else
@@ -1051,13 +1059,13 @@ static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool 
 
 // tw: nodes per tile = threads per workgroup (<= 256)
 void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw,
-                       hipStream_t st, bool fibres) {
+                       hipStream_t st, int law) {
   if (D == 2) {
-    if (prec) bulk_batch_t<2, double>(insts, tiles, ntiles, repair, tw, st, fibres);
-    else bulk_batch_t<2, float>(insts, tiles, ntiles, repair, tw, st, fibres);
+    if (prec) bulk_batch_t<2, double>(insts, tiles, ntiles, repair, tw, st, law);
+    else bulk_batch_t<2, float>(insts, tiles, ntiles, repair, tw, st, law);
   } else {
-    if (prec) bulk_batch_t<3, double>(insts, tiles, ntiles, repair, tw, st, fibres);
-    else bulk_batch_t<3, float>(insts, tiles, ntiles, repair, tw, st, fibres);
+    if (prec) bulk_batch_t<3, double>(insts, tiles, ntiles, repair, tw, st, law);
+    else bulk_batch_t<3, float>(insts, tiles, ntiles, repair, tw, st, law);
   }
 }
 

@@ -325,7 +325,7 @@ struct DevOut {
 void launch_batch(int D, int prec, BatchOp op, const BatchArgs &a);
 // batched node kernels over tiles of tw nodes of one row (tw <= 256 threads)
 void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw,
-                       hipStream_t st, bool fibres);
+                       hipStream_t st, int law);
 void launch_moments_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, int tw,
                           hipStream_t st);
 int ensure_cg(tlvlbm_ctx *c);

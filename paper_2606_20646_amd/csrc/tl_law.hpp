@@ -183,13 +183,14 @@ template <int D> struct Viscoelastic {
 // field, advanced by the caller, enters as the isotropic stretch th of the
 // split F = F_e (th I) with the energy th^D W(F_e) per reference volume, so
 // P(F) = th^(D-1) P_W(F / th) and dP = th^(D-1) dP_W(F / th; dF / th).  The
-// node's th is one FP64 plane of stride S (p.thf).
+// node's th is one FP64 plane of stride S (p.thf; none: th = 1, as for the
+// instances of a batch that have no field).
 template <int D> struct Thermal {
   static constexpr bool body = true;
   struct Node {
     double th;
   };
-  __device__ static void load(const Par &p, int64_t node, int64_t, Node &n) { n.th = p.thf[node]; }
+  __device__ static void load(const Par &p, int64_t node, int64_t, Node &n) { n.th = p.thf ? p.thf[node] : 1.0; }
   __host__ __device__ static double stress(const Par &p, const double *F, Node &n, double *P) {
     double Fe[D * D];
 #pragma unroll

@@ -28,7 +28,7 @@ def env():
     return tlvlbm, torch.cuda.Stream()
 
 
-def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre=None):
+def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre=None, thermal=None):
     # per-instance and batched paths run the same projection solver (Jacobi
     # sweeps; or CG, plain or preconditioned by the multigrid V-cycle,
     # batched level-synchronously)
@@ -40,10 +40,12 @@ def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre
         bc = dict(bc)
         s.set_boundary(bid, bc.pop("type"), **bc)
     s.set_state(cfg["U0"])
+    if thermal is not None:
+        s.set_thermal_stretch(thermal)
     return s
 
 
-def _oracle(orc, cfg, fibre=None, steps=0):
+def _oracle(orc, cfg, fibre=None, steps=0, thermal=None):
     o = orc.Sim(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
                 origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"])
     if fibre is not None:
@@ -58,6 +60,8 @@ def _oracle(orc, cfg, fibre=None, steps=0):
             bc["ramp"] = ramps[bc["ramp"]]
         o.set_bc(bid, t, **bc)
     o.set_state(cfg["U0"])
+    if thermal is not None:
+        o.set_thermal(thermal)
     if steps:
         o.step(steps)
     return o
@@ -164,6 +168,49 @@ def test_batch_with_fibre_instances(env, orc, precision):
         act = c["phi"] <= 0
         check(Ub, Uo, 2, 1e-12, ub, uo, mask=act, label="batched fibre instance vs oracle fp64", pops=o.get_f(),
               steps=65, stress=(c["mu"] + 2 * fb[0], c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
+
+
+def _heating(cfg, amp):
+    """a stretch rising from the clamped left face to the loaded right one"""
+    X = W.node_coords(cfg["n"], cfg["dx"], cfg["origin"])
+    return 1.0 + amp * np.clip(X[0], 0.0, 1.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_with_thermal_instances(env, orc, precision):
+    """instances with their own thermal stretch (one also with fibres)
+    beside a plain one: the batch runs the stretched update for all (th = 1
+    without a field), equal to the per-instance launches; a batched
+    stretched instance equals the oracle in FP64"""
+    T, stream = env
+    tol = _batch_tol(precision, 20)
+    fib = [None, None, (0.8, (1.0, 0.0)), None]
+    amps = [0.02, None, 0.015, 0.01]
+    th = [None if a is None else _heating(c, a) for c, a in zip(CFGS, amps)]
+    _say(f"batch with thermal instances {precision}")
+    A = [_solver(T, c, precision, stream, fibre=fb, thermal=t) for c, fb, t in zip(CFGS, fib, th)]
+    B = [_solver(T, c, precision, stream, fibre=fb, thermal=t) for c, fb, t in zip(CFGS, fib, th)]
+    T.step_each(A, 65)
+    bt = T.Batch(B)
+    bt.step(65)
+    bt.close()
+    for k, (a, b, c, fb) in enumerate(zip(A, B, CFGS, fib)):
+        Ua, ua, _ = a.moments()
+        Ub, ub, _ = b.moments()
+        act = c["phi"] <= 0
+        mu_eff = c["mu"] + (2 * fb[0] if fb else 0.0)
+        check(Ub, Ua, 2, tol, mask=act, label=f"thermal batch instance {k} vs per-instance", pops=a.get_state()[0],
+              steps=65, stress=(mu_eff, c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
+        utol = 1e-10 if precision == "fp64" else 1e-6
+        assert np.linalg.norm(ua[:, act] - ub[:, act]) <= utol * np.linalg.norm(ua[:, act])
+    if precision == "fp64":
+        c = CFGS[0]
+        o = _oracle(orc, c, steps=65, thermal=th[0])
+        Uo, uo, _ = o.moments()
+        Ub, ub, _ = B[0].moments()
+        act = c["phi"] <= 0
+        check(Ub, Uo, 2, 1e-12, ub, uo, mask=act, label="batched thermal instance vs oracle fp64", pops=o.get_f(),
+              steps=65, stress=(c["mu"], c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
 
 
 def test_tile_configurations_agree(env):

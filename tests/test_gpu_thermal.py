@@ -18,7 +18,8 @@ the FP64 oracle.
   solver would, against the oracle given the same fields;
 - th = 1 everywhere is no stretch (to rounding: the stretched law is its own
   kernel instantiation); the calls that refuse a
-  stretch (Maxwell branch, batch, reverse mode) and non-positive values.
+  stretch (Maxwell branch, reverse mode) and non-positive values (batches
+  with a stretch: tests/test_gpu_batch.py).
 """
 import numpy as np
 import pytest
@@ -176,11 +177,9 @@ def test_thermal_unit_stretch_and_refusals(T):
     # no Maxwell branch on a stretched context, and no stretch on a branch
     with pytest.raises(T.TlvlbmError):
         b.set_material(1.0, 2.0, viscous=(0.5, 1.0))
-    # no reverse mode, no batch
+    # no reverse mode
     with pytest.raises(T.TlvlbmError):
         b.adjoint(1, dLdu=np.zeros((2, b.N)))
-    with pytest.raises(T.TlvlbmError):
-        T.Batch([b])
     # removing the field restores the plain law
     b.set_thermal_stretch(None)
     b.step(1)

@@ -210,7 +210,7 @@ tlvlbm_status tlvlbm_set_boundary(tlvlbm_ctx *ctx, uint8_t bid, const tlvlbm_bc 
  *   ramp  tlvlbm_ramp kind of s(t), T_r its time (> 0 unless CONST)
  * A new field takes effect at the next step; a caller that needs a general
  * b(X, t) sets it before each step(1).  Contexts with a body acceleration
- * cannot join a batch and have no reverse mode (TLVLBM_ERR_INVALID_ARG). */
+ * have no reverse mode (TLVLBM_ERR_INVALID_ARG). */
 tlvlbm_status tlvlbm_set_body_force(tlvlbm_ctx *ctx, const double *g, int32_t ramp, double T_r);
 
 /* Thermal stretch th(X) per node, the thermal distortion through which the
@@ -407,13 +407,14 @@ tlvlbm_status tlvlbm_adjoint_backward(tlvlbm_ctx *ctx, const double *dLdU, const
  * that context).  The projection phases run over every instance, so either
  * all instances have Neumann links or none has (TLVLBM_ERR_INVALID_ARG for a
  * mixed set: the projection belongs to lattices with Neumann links only).
- * The batched bulk update runs laws 0 and 1 and the thermal stretch, each
- * instance with its own material and field (when one instance has fibres
- * the whole batch takes the reinforced update, whose fibre term vanishes
- * where k1 = 0; when one has a thermal stretch, the stretched update, with
- * th = 1 where there is no field): instances with a Maxwell branch or a
- * body acceleration are refused (TLVLBM_ERR_INVALID_ARG; tlvlbm_step_each
- * takes them). */
+ * The batched bulk update runs laws 0 and 1, the thermal stretch and the
+ * body acceleration, each instance with its own material, field and ramp
+ * (when one instance has fibres or a body acceleration the whole batch
+ * takes the reinforced update, whose fibre term vanishes where k1 = 0 and
+ * whose body term where there is no field; when one has a thermal stretch,
+ * the stretched update, with th = 1 where there is no field): instances
+ * with a Maxwell branch are refused (TLVLBM_ERR_INVALID_ARG;
+ * tlvlbm_step_each takes them). */
 typedef struct tlvlbm_batch tlvlbm_batch;
 tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t n, int64_t steps);
 tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_batch **out);

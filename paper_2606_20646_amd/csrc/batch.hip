@@ -40,7 +40,8 @@ struct tlvlbm_batch {
   int *h_flags = nullptr;
   bool any_neu = false, any_dir = false;
   // bulk update of the batch: 0 neo-Hookean, 1 reinforced (an instance has
-  // fibres), 2 thermal stretch (an instance has a field; it covers fibres)
+  // fibres or a body acceleration), 2 thermal stretch (an instance has a
+  // field; it covers both)
   int law = 0;
   int64_t step = 0, maxit = 0;
   bool use_graph = true;
@@ -173,19 +174,19 @@ tlvlbm_status pcg_batch(tlvlbm_batch *b, int anch) {
 }
 
 void plain_step(tlvlbm_batch *b) {
-  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, false, b->tw, b->st, b->law);
+  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, false, b->tw, b->st, b->law, b->d_step);
   if (b->nlt) run(b, BatchOp::Cut);
   run(b, BatchOp::StepEnd);
 }
 
 tlvlbm_status projection_step(tlvlbm_batch *b) {
-  launch_moments_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, b->tw, b->st);
+  launch_moments_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, b->tw, b->st, b->d_step);
   run(b, BatchOp::XfromU);
   tlvlbm_status s = cg_batch(b, 0);
   if (s) return s;
   run(b, BatchOp::UfromX);
   run(b, BatchOp::GradF);
-  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, true, b->tw, b->st, b->law);
+  launch_bulk_batch(b->D, b->prec, b->d_inst, b->d_btiles, b->nbt, true, b->tw, b->st, b->law, b->d_step);
   run(b, BatchOp::XfromU);
   s = cg_batch(b, 1);
   if (s) return s;
@@ -303,7 +304,7 @@ tlvlbm_status batch_autotune(tlvlbm_batch *b, int reps) {
         for (int r = 0; r <= reps; ++r) {
           float ms = 0.0f;
           if (hipEventRecord(e0, b->st) != hipSuccess) res = TLVLBM_ERR_DEVICE;
-          launch_bulk_batch(b->D, b->prec, b->d_inst, dt, (int)t.size(), false, widths[wi], b->st, b->law);
+          launch_bulk_batch(b->D, b->prec, b->d_inst, dt, (int)t.size(), false, widths[wi], b->st, b->law, b->d_step);
           if (hipEventRecord(e1, b->st) != hipSuccess || !restore() || hipEventSynchronize(e1) != hipSuccess ||
               hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
             res = TLVLBM_ERR_DEVICE;
@@ -404,7 +405,7 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       tlvlbm_ctx *c = ctxs[k];
       if (!c || c->D != b->D || c->prec != b->prec || c->st != b->st || c->proj_every != b->proj_every ||
           c->proj_sweeps != b->sweeps || c->proj_weight != b->jw || c->step != b->step || !c->have_state ||
-          !c->has_ls || !c->track_u || c->status || c->bf || c->visco) {
+          !c->has_ls || !c->track_u || c->status || c->visco) {
         delete b;
         return TLVLBM_ERR_INVALID_ARG;
       }
@@ -443,8 +444,11 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       I.nblk = c->cg.nblk;
       I.flag = c->d_flag;
       I.nfail = (unsigned long long *)c->d_newton_fail;
+      I.bf = c->bf;
+      I.bf_ramp = c->bf_ramp;
+      I.bf_Tr = c->bf_Tr;
       b->h_inst.push_back(I);
-      if (c->par.k1 != 0.0) b->law = std::max(b->law, 1);
+      if (c->par.k1 != 0.0 || c->bf) b->law = std::max(b->law, 1);
       if (c->par.thf) b->law = 2;
       {
         // activity mask on the host for the node-tile lists (empty: all active)

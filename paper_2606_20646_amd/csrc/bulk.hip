@@ -453,16 +453,27 @@ __global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_chunks_tape(
 
 // Batched bulk update: one block per tile (instance, row, first x) of the
 // tile list; every instance keeps its own geometry, material and buffers.
+// the body-acceleration ramp of instance I at the batch's current step
+// (read on the device, so that replays of captured steps advance it)
+template <typename T> __device__ __forceinline__ T batch_body_scale(const Inst &I, const int64_t *step) {
+  if (!I.bf) return T(0);
+  double sv, dsv;
+  ramp_eval(I.bf_ramp, I.bf_Tr, *step * I.p.dt, sv, dsv);
+  return T(sv);
+}
+
 template <int D, typename T, bool REPAIR, class L = NeoHookean<D>>
 __global__ __launch_bounds__(256, TL_CHUNK_WAVES) void k_bulk_batch(const Inst *__restrict__ insts,
-                                                                   const int4 *__restrict__ tiles) {
+                                                                   const int4 *__restrict__ tiles,
+                                                                   const int64_t *__restrict__ step) {
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
   const int64_t node = (int64_t)t.y * blockDim.x + threadIdx.x;
   if (node >= I.g.N) return;
   const int row = (int)(node / I.g.nx), x = (int)(node - (int64_t)row * I.g.nx);
   bulk_node<D, T, true, true, REPAIR, false, L>((const T *)I.fin, (T *)I.fout, I.g, I.p, I.act,
-                                                (double *)I.ustar, (double *)I.ubuf, (const T *)I.Fr, I.flag, x, row);
+                                                (double *)I.ustar, (double *)I.ubuf, (const T *)I.Fr, I.flag, x, row,
+                                                nullptr, (const T *)I.bf, batch_body_scale<T>(I, step));
 }
 
 // Pull f^n and write moments: v (damping-corrected), F, u = u* + dt/2 v, J.
@@ -574,14 +585,16 @@ __global__ __launch_bounds__(256) void k_stress(const T *__restrict__ fin, Geo g
 // batched projection inputs: v, F into each instance's workspace, u = u* + dt/2 v
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_moments_batch(const Inst *__restrict__ insts,
-                                                        const int4 *__restrict__ tiles) {
+                                                        const int4 *__restrict__ tiles,
+                                                        const int64_t *__restrict__ step) {
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
   const int64_t node = (int64_t)t.y * blockDim.x + threadIdx.x;
   if (node >= I.g.N) return;
   const int row = (int)(node / I.g.nx), x = (int)(node - (int64_t)row * I.g.nx);
   moments_node<D, T, T, true, true>((const T *)I.fin, I.g, I.p, I.act, (const double *)I.ustar, (T *)I.V, (T *)I.Fm,
-                              (double *)I.ubuf, (T *)nullptr, I.g.S, x, row);
+                                    (double *)I.ubuf, (T *)nullptr, I.g.S, x, row, (const T *)I.bf,
+                                    batch_body_scale<T>(I, step));
 }
 
 // Second-order initialisation (Sec. 2.4, Eqs. 32-33) in FP64, stored
@@ -1033,50 +1046,50 @@ namespace tl {
 // batched launchers: tiles are (instance, k) pairs, nodes k tw .. (k + 1) tw - 1 of the instance
 template <int D, typename T>
 static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw, hipStream_t st,
-                         int law) {
+                         int law, const int64_t *step) {
   // law 2: the thermal stretch for the whole batch (th = 1 on instances
   // without a field); 1: the reinforced law (its fibre term vanishes on
   // instances with k1 = 0); 0: the neo-Hookean law
   if (law == 2) {
     if (repair)
-      hipLaunchKernelGGL((k_bulk_batch<D, T, true, Thermal<D>>), ntiles, tw, 0, st, insts, tiles);
+      hipLaunchKernelGGL((k_bulk_batch<D, T, true, Thermal<D>>), ntiles, tw, 0, st, insts, tiles, step);
     else
-      hipLaunchKernelGGL((k_bulk_batch<D, T, false, Thermal<D>>), ntiles, tw, 0, st, insts, tiles);
+      hipLaunchKernelGGL((k_bulk_batch<D, T, false, Thermal<D>>), ntiles, tw, 0, st, insts, tiles, step);
     return;
   }
   if (law == 1) {
     if (repair)
-      hipLaunchKernelGGL((k_bulk_batch<D, T, true, Reinforced<D>>), ntiles, tw, 0, st, insts, tiles);
+      hipLaunchKernelGGL((k_bulk_batch<D, T, true, Reinforced<D>>), ntiles, tw, 0, st, insts, tiles, step);
     else
-      hipLaunchKernelGGL((k_bulk_batch<D, T, false, Reinforced<D>>), ntiles, tw, 0, st, insts, tiles);
+      hipLaunchKernelGGL((k_bulk_batch<D, T, false, Reinforced<D>>), ntiles, tw, 0, st, insts, tiles, step);
     return;
   }
   if (repair)
-    hipLaunchKernelGGL((k_bulk_batch<D, T, true>), ntiles, tw, 0, st, insts, tiles);
+    hipLaunchKernelGGL((k_bulk_batch<D, T, true>), ntiles, tw, 0, st, insts, tiles, step);
   else
-    hipLaunchKernelGGL((k_bulk_batch<D, T, false>), ntiles, tw, 0, st, insts, tiles);
+    hipLaunchKernelGGL((k_bulk_batch<D, T, false>), ntiles, tw, 0, st, insts, tiles, step);
 }
 
 // tw: nodes per tile = threads per workgroup (<= 256)
 void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw,
-                       hipStream_t st, int law) {
+                       hipStream_t st, int law, const int64_t *step) {
   if (D == 2) {
-    if (prec) bulk_batch_t<2, double>(insts, tiles, ntiles, repair, tw, st, law);
-    else bulk_batch_t<2, float>(insts, tiles, ntiles, repair, tw, st, law);
+    if (prec) bulk_batch_t<2, double>(insts, tiles, ntiles, repair, tw, st, law, step);
+    else bulk_batch_t<2, float>(insts, tiles, ntiles, repair, tw, st, law, step);
   } else {
-    if (prec) bulk_batch_t<3, double>(insts, tiles, ntiles, repair, tw, st, law);
-    else bulk_batch_t<3, float>(insts, tiles, ntiles, repair, tw, st, law);
+    if (prec) bulk_batch_t<3, double>(insts, tiles, ntiles, repair, tw, st, law, step);
+    else bulk_batch_t<3, float>(insts, tiles, ntiles, repair, tw, st, law, step);
   }
 }
 
 void launch_moments_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, int tw,
-                          hipStream_t st) {
+                          hipStream_t st, const int64_t *step) {
   if (D == 2) {
-    if (prec) hipLaunchKernelGGL((k_moments_batch<2, double>), ntiles, tw, 0, st, insts, tiles);
-    else hipLaunchKernelGGL((k_moments_batch<2, float>), ntiles, tw, 0, st, insts, tiles);
+    if (prec) hipLaunchKernelGGL((k_moments_batch<2, double>), ntiles, tw, 0, st, insts, tiles, step);
+    else hipLaunchKernelGGL((k_moments_batch<2, float>), ntiles, tw, 0, st, insts, tiles, step);
   } else {
-    if (prec) hipLaunchKernelGGL((k_moments_batch<3, double>), ntiles, tw, 0, st, insts, tiles);
-    else hipLaunchKernelGGL((k_moments_batch<3, float>), ntiles, tw, 0, st, insts, tiles);
+    if (prec) hipLaunchKernelGGL((k_moments_batch<3, double>), ntiles, tw, 0, st, insts, tiles, step);
+    else hipLaunchKernelGGL((k_moments_batch<3, float>), ntiles, tw, 0, st, insts, tiles, step);
   }
 }
 

@@ -193,6 +193,11 @@ struct Inst {
   int nblk;  // node tiles of 256 of this instance (CG reductions)
   int *flag;
   unsigned long long *nfail;
+  // body acceleration b = s(t) g: g planes in the population precision
+  // (null: none) and the ramp s
+  const void *bf;
+  int bf_ramp;
+  double bf_Tr;
 };
 
 // one boundary identifier of one instance: a contiguous link range
@@ -325,9 +330,9 @@ struct DevOut {
 void launch_batch(int D, int prec, BatchOp op, const BatchArgs &a);
 // batched node kernels over tiles of tw nodes of one row (tw <= 256 threads)
 void launch_bulk_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw,
-                       hipStream_t st, int law);
+                       hipStream_t st, int law, const int64_t *step);
 void launch_moments_batch(int D, int prec, const Inst *insts, const int4 *tiles, int ntiles, int tw,
-                          hipStream_t st);
+                          hipStream_t st, const int64_t *step);
 int ensure_cg(tlvlbm_ctx *c);
 int64_t cg_default_maxit(int64_t nactive);
 double cg_default_rtol(int prec);

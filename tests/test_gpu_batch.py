@@ -28,7 +28,7 @@ def env():
     return tlvlbm, torch.cuda.Stream()
 
 
-def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre=None, thermal=None):
+def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre=None, thermal=None, body=None):
     # per-instance and batched paths run the same projection solver (Jacobi
     # sweeps; or CG, plain or preconditioned by the multigrid V-cycle,
     # batched level-synchronously)
@@ -39,13 +39,15 @@ def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre
     for bid, bc in cfg["bcs"].items():
         bc = dict(bc)
         s.set_boundary(bid, bc.pop("type"), **bc)
+    if body is not None:
+        s.set_body_force(body[0], ramp=body[1], T_r=body[2])
     s.set_state(cfg["U0"])
     if thermal is not None:
         s.set_thermal_stretch(thermal)
     return s
 
 
-def _oracle(orc, cfg, fibre=None, steps=0, thermal=None):
+def _oracle(orc, cfg, fibre=None, steps=0, thermal=None, body=None):
     o = orc.Sim(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
                 origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"])
     if fibre is not None:
@@ -59,6 +61,8 @@ def _oracle(orc, cfg, fibre=None, steps=0, thermal=None):
         if "ramp" in bc:
             bc["ramp"] = ramps[bc["ramp"]]
         o.set_bc(bid, t, **bc)
+    if body is not None:
+        o.set_body_force(body[0], ramp={"sin2": orc.RAMP_SIN2, "const": orc.RAMP_CONST}[body[1]], T_r=body[2])
     o.set_state(cfg["U0"])
     if thermal is not None:
         o.set_thermal(thermal)
@@ -211,6 +215,50 @@ def test_batch_with_thermal_instances(env, orc, precision):
         act = c["phi"] <= 0
         check(Ub, Uo, 2, 1e-12, ub, uo, mask=act, label="batched thermal instance vs oracle fp64", pops=o.get_f(),
               steps=65, stress=(c["mu"], c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
+
+
+def _gravity(cfg, gx, gy):
+    """a body acceleration varying over the instance"""
+    X = W.node_coords(cfg["n"], cfg["dx"], cfg["origin"])
+    return np.stack([gx * (1.0 + 0.5 * np.sin(2 * np.pi * X[1])), gy * np.ones_like(X[0])])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_with_body_force_instances(env, orc, precision):
+    """instances with their own body acceleration and ramp (one with
+    fibres) beside a plain one, batched with graph replay across the ramp:
+    equal to the per-instance launches; a batched instance with a body
+    acceleration equals the oracle in FP64"""
+    T, stream = env
+    tol = _batch_tol(precision, 20)
+    fib = [None, (0.8, (1.0, 0.0)), None, None]
+    body = [(_gravity(CFGS[0], 0.3, -0.2), "sin2", 30 * CFGS[0]["dt"]), (_gravity(CFGS[1], -0.2, 0.1), "const", 1.0),
+            None, (_gravity(CFGS[3], 0.1, 0.25), "sin2", 50 * CFGS[3]["dt"])]
+    _say(f"batch with body-force instances {precision}")
+    A = [_solver(T, c, precision, stream, fibre=fb, body=bd) for c, fb, bd in zip(CFGS, fib, body)]
+    B = [_solver(T, c, precision, stream, fibre=fb, body=bd) for c, fb, bd in zip(CFGS, fib, body)]
+    T.step_each(A, 65)
+    bt = T.Batch(B, use_graph=True)
+    bt.step(30)
+    bt.step(35)
+    bt.close()
+    for k, (a, b, c, fb) in enumerate(zip(A, B, CFGS, fib)):
+        Ua, ua, _ = a.moments()
+        Ub, ub, _ = b.moments()
+        act = c["phi"] <= 0
+        mu_eff = c["mu"] + (2 * fb[0] if fb else 0.0)
+        check(Ub, Ua, 2, tol, mask=act, label=f"body-force batch instance {k} vs per-instance",
+              pops=a.get_state()[0], steps=65, stress=(mu_eff, c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
+        utol = 1e-10 if precision == "fp64" else 1e-6
+        assert np.linalg.norm(ua[:, act] - ub[:, act]) <= utol * np.linalg.norm(ua[:, act])
+    if precision == "fp64":
+        c = CFGS[0]
+        o = _oracle(orc, c, steps=65, body=body[0])
+        Uo, uo, _ = o.moments()
+        Ub, ub, _ = B[0].moments()
+        act = c["phi"] <= 0
+        check(Ub, Uo, 2, 1e-12, ub, uo, mask=act, label="batched body-force instance vs oracle fp64",
+              pops=o.get_f(), steps=65, stress=(c["mu"], c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
 
 
 def test_tile_configurations_agree(env):

@@ -114,7 +114,7 @@ def test_embedded_ramped_body_force_matches_oracle(T, orc):
     assert np.abs(Uo[:2, act]).max() > 1e-4  # the body acceleration moved the body
 
 
-def test_body_force_excludes_batch_and_reverse_mode(T):
+def test_body_force_excludes_reverse_mode(T):
     import torch
     stream = torch.cuda.Stream()
     c = W.config_c4_instance(0, N=40)
@@ -126,8 +126,6 @@ def test_body_force_excludes_batch_and_reverse_mode(T):
         s.set_boundary(bid, bc.pop("type"), **bc)
     s.set_body_force(np.ones((2, s.N)) * 0.01)
     s.set_state(c["U0"])
-    with pytest.raises(T.TlvlbmError):
-        T.Batch([s])
     with pytest.raises(T.TlvlbmError):
         s.adjoint(3, np.ones((6, s.N)))
 

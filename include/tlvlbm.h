@@ -407,14 +407,15 @@ tlvlbm_status tlvlbm_adjoint_backward(tlvlbm_ctx *ctx, const double *dLdU, const
  * that context).  The projection phases run over every instance, so either
  * all instances have Neumann links or none has (TLVLBM_ERR_INVALID_ARG for a
  * mixed set: the projection belongs to lattices with Neumann links only).
- * The batched bulk update runs laws 0 and 1, the thermal stretch and the
- * body acceleration, each instance with its own material, field and ramp
- * (when one instance has fibres or a body acceleration the whole batch
- * takes the reinforced update, whose fibre term vanishes where k1 = 0 and
- * whose body term where there is no field; when one has a thermal stretch,
- * the stretched update, with th = 1 where there is no field): instances
- * with a Maxwell branch are refused (TLVLBM_ERR_INVALID_ARG;
- * tlvlbm_step_each takes them). */
+ * The batched bulk update runs every law (0, 1, 2), the thermal stretch and
+ * the body acceleration, each instance with its own material, history,
+ * field and ramp: the whole batch takes the most general update one of its
+ * instances needs (reinforced for fibres or a body acceleration, whose
+ * extra terms vanish where an instance has none; the branch's update, with
+ * no overstress where an instance has no branch; the stretched update, with
+ * th = 1 where there is no field).  A batch holding both a Maxwell branch
+ * and a thermal stretch is refused (TLVLBM_ERR_INVALID_ARG; no update
+ * covers both; tlvlbm_step_each takes them). */
 typedef struct tlvlbm_batch tlvlbm_batch;
 tlvlbm_status tlvlbm_step_each(tlvlbm_ctx *const *ctxs, int32_t n, int64_t steps);
 tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_batch **out);

@@ -41,7 +41,8 @@ struct tlvlbm_batch {
   bool any_neu = false, any_dir = false;
   // bulk update of the batch: 0 neo-Hookean, 1 reinforced (an instance has
   // fibres or a body acceleration), 2 thermal stretch (an instance has a
-  // field; it covers both)
+  // field; it covers both), 3 Maxwell branch (an instance has one; it covers
+  // 1, not 2: a batch with both is refused)
   int law = 0;
   int64_t step = 0, maxit = 0;
   bool use_graph = true;
@@ -401,11 +402,12 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
     std::vector<Seg> segs;
     std::vector<int4> bt, ct, lt;
     int n_neu = 0;  // instances with Neumann links (those the projection runs on)
+    bool any_visco = false, any_thermal = false;
     for (int k = 0; k < n; ++k) {
       tlvlbm_ctx *c = ctxs[k];
       if (!c || c->D != b->D || c->prec != b->prec || c->st != b->st || c->proj_every != b->proj_every ||
           c->proj_sweeps != b->sweeps || c->proj_weight != b->jw || c->step != b->step || !c->have_state ||
-          !c->has_ls || !c->track_u || c->status || c->visco) {
+          !c->has_ls || !c->track_u || c->status || (c->visco && !c->hist_set)) {
         delete b;
         return TLVLBM_ERR_INVALID_ARG;
       }
@@ -449,7 +451,8 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       I.bf_Tr = c->bf_Tr;
       b->h_inst.push_back(I);
       if (c->par.k1 != 0.0 || c->bf) b->law = std::max(b->law, 1);
-      if (c->par.thf) b->law = 2;
+      if (c->par.thf) any_thermal = true;
+      if (c->visco) any_visco = true;
       {
         // activity mask on the host for the node-tile lists (empty: all active)
         std::vector<uint8_t> a;
@@ -489,6 +492,14 @@ tlvlbm_status tlvlbm_batch_create(tlvlbm_ctx *const *ctxs, int32_t n, tlvlbm_bat
       tlvlbm_batch_destroy(b);
       return TLVLBM_ERR_INVALID_ARG;
     }
+    // one bulk update serves the batch: a Maxwell branch and a thermal
+    // stretch have none in common
+    if (any_visco && any_thermal) {
+      tlvlbm_batch_destroy(b);
+      return TLVLBM_ERR_INVALID_ARG;
+    }
+    if (any_visco) b->law = 3;
+    else if (any_thermal) b->law = 2;
     bt = node_tiles(b, b->tw, b->torder);
     b->nbt = (int)bt.size();
     b->nct = (int)ct.size();

@@ -1047,9 +1047,17 @@ namespace tl {
 template <int D, typename T>
 static void bulk_batch_t(const Inst *insts, const int4 *tiles, int ntiles, bool repair, int tw, hipStream_t st,
                          int law, const int64_t *step) {
-  // law 2: the thermal stretch for the whole batch (th = 1 on instances
+  // law 3: the Maxwell branch for the whole batch (no overstress on
+  // instances without one); 2: the thermal stretch (th = 1 on instances
   // without a field); 1: the reinforced law (its fibre term vanishes on
   // instances with k1 = 0); 0: the neo-Hookean law
+  if (law == 3) {
+    if (repair)
+      hipLaunchKernelGGL((k_bulk_batch<D, T, true, Viscoelastic<D>>), ntiles, tw, 0, st, insts, tiles, step);
+    else
+      hipLaunchKernelGGL((k_bulk_batch<D, T, false, Viscoelastic<D>>), ntiles, tw, 0, st, insts, tiles, step);
+    return;
+  }
   if (law == 2) {
     if (repair)
       hipLaunchKernelGGL((k_bulk_batch<D, T, true, Thermal<D>>), ntiles, tw, 0, st, insts, tiles, step);

@@ -146,7 +146,9 @@ template <int D> struct Reinforced {
   __device__ static void commit(const Par &, const Node &, int64_t, int64_t) {}
 };
 
-// Maxwell branch on the reinforced solid: P = P_eq(F) + F Q,
+// Maxwell branch on the reinforced solid (an instance of a batch without a
+// branch has no history planes: R = 0 and beta xi = 0, so Q = 0 and nothing
+// is committed): P = P_eq(F) + F Q,
 // dQ/dt + Q / tau = beta dS_0/dt, advanced per step by the midpoint rule on
 // its convolution, Q^{n+1} = xi^2 Q^n + beta xi (S_0^{n+1} - S_0^n) with
 // xi = exp(-dt / (2 tau)).  The node keeps R = xi^2 Q^n - beta xi S_0^n, so
@@ -159,7 +161,7 @@ template <int D> struct Viscoelastic {
   };
   __device__ static void load(const Par &p, int64_t node, int64_t S, Node &n) {
 #pragma unroll
-    for (int k = 0; k < sym_n<D>(); ++k) n.R[k] = p.hist[(size_t)k * S + node];
+    for (int k = 0; k < sym_n<D>(); ++k) n.R[k] = p.hist ? p.hist[(size_t)k * S + node] : 0.0;
   }
   __host__ __device__ static double stress(const Par &p, const double *F, Node &n, double *P) {
     typename Reinforced<D>::Node e;
@@ -173,6 +175,7 @@ template <int D> struct Viscoelastic {
     maxwell_tangent_add<D>(F, dF, p, n.R, dP);
   }
   __device__ static void commit(const Par &p, const Node &n, int64_t node, int64_t S) {
+    if (!p.hist) return;
     const double c = p.vbx * (p.vxi2 - 1.0);
 #pragma unroll
     for (int k = 0; k < sym_n<D>(); ++k) p.hist[(size_t)k * S + node] = p.vxi2 * n.R[k] + c * n.S0[k];

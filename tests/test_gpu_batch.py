@@ -28,13 +28,15 @@ def env():
     return tlvlbm, torch.cuda.Stream()
 
 
-def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre=None, thermal=None, body=None):
+def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre=None, thermal=None, body=None,
+            viscous=None):
     # per-instance and batched paths run the same projection solver (Jacobi
     # sweeps; or CG, plain or preconditioned by the multigrid V-cycle,
     # batched level-synchronously)
     s = T.Solver(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
                  origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"], precision=precision,
-                 stream=stream.cuda_stream, cg_multigrid=cg_multigrid, proj_sweeps=proj_sweeps, fibre=fibre)
+                 stream=stream.cuda_stream, cg_multigrid=cg_multigrid, proj_sweeps=proj_sweeps, fibre=fibre,
+                 viscous=viscous)
     s.set_levelset(cfg["phi"], cfg["bid"])
     for bid, bc in cfg["bcs"].items():
         bc = dict(bc)
@@ -47,11 +49,13 @@ def _solver(T, cfg, precision, stream, cg_multigrid=False, proj_sweeps=20, fibre
     return s
 
 
-def _oracle(orc, cfg, fibre=None, steps=0, thermal=None, body=None):
+def _oracle(orc, cfg, fibre=None, steps=0, thermal=None, body=None, viscous=None):
     o = orc.Sim(2, cfg["n"], cfg["dx"], cfg["dt"], cfg["mu"], cfg["lam"], omega=cfg["omega"], gamma=cfg["gamma"],
                 origin=cfg["origin"], periodic_mask=0, proj_every=cfg["proj_every"])
     if fibre is not None:
         o.set_fibres(*fibre)
+    if viscous is not None:
+        o.set_viscous(*viscous)
     o.set_levelset(cfg["phi"], cfg["bid"])
     kinds = {"dirichlet": orc.DIRICHLET, "neumann": orc.NEUMANN}
     ramps = {"const": orc.RAMP_CONST, "sin2": orc.RAMP_SIN2}
@@ -259,6 +263,46 @@ def test_batch_with_body_force_instances(env, orc, precision):
         act = c["phi"] <= 0
         check(Ub, Uo, 2, 1e-12, ub, uo, mask=act, label="batched body-force instance vs oracle fp64",
               pops=o.get_f(), steps=65, stress=(c["mu"], c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_with_maxwell_instances(env, orc, precision):
+    """instances with their own Maxwell branch (one with fibres, one with a
+    body acceleration) beside a plain one: the batch runs the branch's
+    update for all (no overstress without a branch), equal to the
+    per-instance launches; a batched branch instance equals the oracle in
+    FP64"""
+    T, stream = env
+    tol = _batch_tol(precision, 20)
+    visc = [(1.0, 20 * CFGS[0]["dt"]), None, (0.5, 40 * CFGS[2]["dt"]), (1.5, 10 * CFGS[3]["dt"])]
+    fib = [None, None, (0.8, (1.0, 0.0)), None]
+    body = [None, None, None, (_gravity(CFGS[3], 0.1, 0.25), "sin2", 50 * CFGS[3]["dt"])]
+    _say(f"batch with maxwell-branch instances {precision}")
+    mk = lambda: [_solver(T, c, precision, stream, fibre=fb, body=bd, viscous=v)
+                  for c, fb, bd, v in zip(CFGS, fib, body, visc)]
+    A, B = mk(), mk()
+    T.step_each(A, 65)
+    bt = T.Batch(B)
+    bt.step(30)
+    bt.step(35)
+    bt.close()
+    for k, (a, b, c, fb, v) in enumerate(zip(A, B, CFGS, fib, visc)):
+        Ua, ua, _ = a.moments()
+        Ub, ub, _ = b.moments()
+        act = c["phi"] <= 0
+        mu_eff = c["mu"] * (1 + (v[0] if v else 0.0)) + (2 * fb[0] if fb else 0.0)
+        check(Ub, Ua, 2, tol, mask=act, label=f"maxwell batch instance {k} vs per-instance", pops=a.get_state()[0],
+              steps=65, stress=(mu_eff, c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
+        utol = 1e-10 if precision == "fp64" else 1e-6
+        assert np.linalg.norm(ua[:, act] - ub[:, act]) <= utol * np.linalg.norm(ua[:, act])
+    if precision == "fp64":
+        c, v = CFGS[0], visc[0]
+        o = _oracle(orc, c, steps=65, viscous=v)
+        Uo, uo, _ = o.moments()
+        Ub, ub, _ = B[0].moments()
+        act = c["phi"] <= 0
+        check(Ub, Uo, 2, 1e-12, ub, uo, mask=act, label="batched maxwell instance vs oracle fp64", pops=o.get_f(),
+              steps=65, stress=(c["mu"] * (1 + v[0]), c["lam"], 1.0, c["dx"] / c["dt"], c["omega"]))
 
 
 def test_tile_configurations_agree(env):

@@ -13,8 +13,9 @@ branch on the neo-Hookean solid, Sec. 6 outlook) and of the stress output
 - the branch on the fibre-reinforced solid with a ramped body acceleration
   (periodic 2D): the policies compose;
 - the stress output of the paper's law on the periodic 2D configuration;
-- the calls that refuse the branch (batch, reverse mode) and the reset that
-  a material change asks for.
+- the calls that refuse the branch (reverse mode; a batch that also holds a
+  thermal stretch) and the reset that a material change asks for (batches
+  with branches: tests/test_gpu_batch.py).
 """
 import math
 
@@ -197,8 +198,11 @@ def test_maxwell_refusals_and_reset(T):
         return s
 
     a, b = solver((1.0, 0.1)), solver(None)
+    # no batch of a branch and a thermal stretch (no bulk update covers both)
+    t = solver(None)
+    t.set_thermal_stretch(np.full(t.N, 1.01))
     with pytest.raises(T.TlvlbmError) as e:
-        T.Batch([a, b])
+        T.Batch([a, t])
     assert e.value.code == T.ERR_INVALID_ARG
     with pytest.raises(T.TlvlbmError) as e:
         a.adjoint_record(5)
